@@ -1,0 +1,216 @@
+"""Plain CPU oracle for the level-wise wavelet tree — TEST INFRASTRUCTURE ONLY.
+
+Only ``tests/``, ``__graft_entry__.smoke()`` and the ``cpu_baseline`` leg of
+``bench.py`` may import this package. The product path (``paper_2505_03372_amd``)
+never imports it and fails loudly when its HIP library is missing.
+
+The arithmetic lives in ``wt_oracle.c`` (plain C, definitions written out; see the
+header of that file for the passages of the thesis each function follows). This
+module only marshals numpy arrays and adds the pure-Python brute-force answers
+(``brute_*``) used on tiny inputs.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "wt_oracle.c")
+_LIB = os.path.join(_HERE, "libwtoracle.so")
+
+ACCESS_INVALID = 0xFFFFFFFF
+U64_MAX = (1 << 64) - 1
+
+_u64p = ctypes.POINTER(ctypes.c_uint64)
+_u32p = ctypes.POINTER(ctypes.c_uint32)
+_u16p = ctypes.POINTER(ctypes.c_uint16)
+
+
+def build_lib(force: bool = False) -> str:
+    """Compile wt_oracle.c into libwtoracle.so with gcc."""
+    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+        tmp = _LIB + ".tmp%d" % os.getpid()
+        subprocess.check_call(["gcc", "-O2", "-fPIC", "-shared", "-o", tmp, _SRC])
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        L = ctypes.CDLL(build_lib())
+        L.oracle_num_levels.restype = ctypes.c_int
+        L.oracle_num_levels.argtypes = [ctypes.c_uint64]
+        L.oracle_codes.argtypes = [ctypes.c_uint64, _u64p, _u32p]
+        L.oracle_hist.restype = ctypes.c_int
+        L.oracle_hist.argtypes = [ctypes.c_void_p, ctypes.c_uint64, ctypes.c_int, ctypes.c_uint64, _u64p]
+        L.oracle_level_bits.restype = ctypes.c_int
+        L.oracle_level_bits.argtypes = [ctypes.c_void_p, ctypes.c_uint64, ctypes.c_int, ctypes.c_uint64,
+                                        ctypes.c_uint64, _u64p, _u64p]
+        L.oracle_directory.argtypes = [_u64p, ctypes.c_uint64, ctypes.c_uint64, _u64p, _u16p]
+        L.oracle_samples.argtypes = [_u64p, ctypes.c_uint64, ctypes.c_uint64, _u64p, _u64p, _u64p, _u64p]
+        L.oracle_nodes.argtypes = [ctypes.c_void_p, ctypes.c_uint64, ctypes.c_int, ctypes.c_uint64, ctypes.c_int,
+                                   _u64p, _u64p, _u64p]
+        L.oracle_access.argtypes = [ctypes.c_void_p, ctypes.c_uint64, ctypes.c_int, _u64p, ctypes.c_uint64, _u32p]
+        L.oracle_rank.argtypes = [ctypes.c_void_p, ctypes.c_uint64, ctypes.c_int, ctypes.c_uint64, _u32p, _u64p,
+                                  ctypes.c_uint64, _u64p]
+        L.oracle_select.argtypes = [ctypes.c_void_p, ctypes.c_uint64, ctypes.c_int, ctypes.c_uint64, _u32p, _u64p,
+                                    ctypes.c_uint64, _u64p]
+        _lib = L
+    return _lib
+
+
+def _seq(S: np.ndarray) -> np.ndarray:
+    S = np.ascontiguousarray(S)
+    assert S.dtype in (np.uint8, np.uint16, np.uint32, np.uint64), S.dtype
+    return S
+
+
+def _p(a, t):
+    return a.ctypes.data_as(t)
+
+
+def num_levels(sigma: int) -> int:
+    return int(lib().oracle_num_levels(sigma))
+
+
+def codes(sigma: int):
+    """Reduced-tree codes (left-aligned to L bits) and code lengths of all symbols."""
+    code = np.zeros(max(sigma, 1), dtype=np.uint64)
+    ln = np.zeros(max(sigma, 1), dtype=np.uint32)
+    lib().oracle_codes(sigma, _p(code, _u64p), _p(ln, _u32p))
+    return code[:sigma], ln[:sigma]
+
+
+def hist(S: np.ndarray, sigma: int) -> np.ndarray:
+    S = _seq(S)
+    h = np.zeros(max(sigma, 1), dtype=np.uint64)
+    bad = lib().oracle_hist(ctypes.c_void_p(S.ctypes.data), S.size, S.dtype.itemsize, sigma, _p(h, _u64p))
+    if bad:
+        raise ValueError("symbol out of range")
+    return h[:sigma]
+
+
+class OracleTree:
+    """Every part of the tree, computed from its definition (see wt_oracle.c)."""
+
+    def __init__(self, S: np.ndarray, sigma: int, l2_bits: int = 512, sample_rate: int = 4096,
+                 with_nodes: bool = True):
+        S = _seq(S)
+        self.n = int(S.size)
+        self.sigma = int(sigma)
+        self.l2_bits = l2_bits
+        self.sample_rate = sample_rate
+        self.L = num_levels(sigma)
+        self.hist = hist(S, sigma)
+        self.cum_hist = np.zeros(sigma + 1, dtype=np.uint64)
+        self.cum_hist[1:] = np.cumsum(self.hist, dtype=np.uint64)
+        L = self.L
+        stride = max(1, (self.n + 63) // 64)
+        bits = np.zeros((max(L, 1), stride), dtype=np.uint64)
+        level_n = np.zeros(max(L, 1), dtype=np.uint64)
+        rc = lib().oracle_level_bits(ctypes.c_void_p(S.ctypes.data), self.n, S.dtype.itemsize, sigma, stride,
+                                     _p(bits, _u64p), _p(level_n, _u64p))
+        if rc != 0:
+            raise ValueError("symbol out of range")
+        self.level_n = [int(x) for x in level_n[:L]]
+        self.bits, self.L1, self.L2, self.samples1, self.samples0, self.ones = [], [], [], [], [], []
+        self.node_start, self.node_r0 = [], []
+        for l in range(L):
+            nl = self.level_n[l]
+            row = np.ascontiguousarray(bits[l, : (nl + 63) // 64])
+            self.bits.append(row)
+            rowp = np.ascontiguousarray(bits[l])
+            L1 = np.zeros((nl + 65535) // 65536 + 1, dtype=np.uint64)
+            L2 = np.zeros((nl + l2_bits - 1) // l2_bits + 1, dtype=np.uint16)
+            lib().oracle_directory(_p(rowp, _u64p), nl, l2_bits, _p(L1, _u64p), _p(L2, _u16p))
+            self.L1.append(L1)
+            self.L2.append(L2)
+            cap = nl // sample_rate + 1
+            s1 = np.zeros(cap, dtype=np.uint64)
+            s0 = np.zeros(cap, dtype=np.uint64)
+            n1 = ctypes.c_uint64(0)
+            n0 = ctypes.c_uint64(0)
+            lib().oracle_samples(_p(rowp, _u64p), nl, sample_rate, _p(s1, _u64p), ctypes.byref(n1),
+                                 _p(s0, _u64p), ctypes.byref(n0))
+            self.samples1.append(s1[: n1.value].copy())
+            self.samples0.append(s0[: n0.value].copy())
+            self.ones.append(int(L1[-1]))
+            if with_nodes:
+                st = np.zeros(1 << l, dtype=np.uint64)
+                r0 = np.zeros(1 << l, dtype=np.uint64)
+                lib().oracle_nodes(ctypes.c_void_p(S.ctypes.data), self.n, S.dtype.itemsize, sigma, l,
+                                   _p(rowp, _u64p), _p(st, _u64p), _p(r0, _u64p))
+                self.node_start.append(st)
+                self.node_r0.append(r0)
+
+    def bit(self, l: int, j: int) -> int:
+        return int((int(self.bits[l][j // 64]) >> (j % 64)) & 1)
+
+    def bit_string(self, l: int) -> str:
+        return "".join(str(self.bit(l, j)) for j in range(self.level_n[l]))
+
+
+def access(S: np.ndarray, pos: np.ndarray) -> np.ndarray:
+    S = _seq(S)
+    pos = np.ascontiguousarray(pos, dtype=np.uint64)
+    out = np.empty(pos.size, dtype=np.uint32)
+    lib().oracle_access(ctypes.c_void_p(S.ctypes.data), S.size, S.dtype.itemsize, _p(pos, _u64p), pos.size,
+                        _p(out, _u32p))
+    return out
+
+
+def rank(S: np.ndarray, sigma: int, c: np.ndarray, i: np.ndarray) -> np.ndarray:
+    S = _seq(S)
+    c = np.ascontiguousarray(c, dtype=np.uint32)
+    i = np.ascontiguousarray(i, dtype=np.uint64)
+    out = np.empty(c.size, dtype=np.uint64)
+    lib().oracle_rank(ctypes.c_void_p(S.ctypes.data), S.size, S.dtype.itemsize, sigma, _p(c, _u32p),
+                      _p(i, _u64p), c.size, _p(out, _u64p))
+    return out
+
+
+def select(S: np.ndarray, sigma: int, c: np.ndarray, k: np.ndarray) -> np.ndarray:
+    S = _seq(S)
+    c = np.ascontiguousarray(c, dtype=np.uint32)
+    k = np.ascontiguousarray(k, dtype=np.uint64)
+    out = np.empty(c.size, dtype=np.uint64)
+    lib().oracle_select(ctypes.c_void_p(S.ctypes.data), S.size, S.dtype.itemsize, sigma, _p(c, _u32p),
+                        _p(k, _u64p), c.size, _p(out, _u64p))
+    return out
+
+
+# ---- pure-Python brute force (tiny inputs only) ----
+
+def brute_access(S, i):
+    return int(S[i]) if 0 <= i < len(S) else ACCESS_INVALID
+
+
+def brute_rank(S, sigma, c, i):
+    n = len(S)
+    if i > n:
+        return U64_MAX
+    if c >= sigma:
+        return 0
+    return sum(1 for j in range(i) if int(S[j]) == c)
+
+
+def brute_select(S, sigma, c, k):
+    n = len(S)
+    if k == 0:
+        return U64_MAX
+    if c >= sigma:
+        return n
+    seen = 0
+    for j in range(n):
+        if int(S[j]) == c:
+            seen += 1
+            if seen == k:
+                return j
+    return n
