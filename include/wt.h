@@ -1,0 +1,166 @@
+/*
+ * wt.h — C ABI of the MI355X (gfx950) level-wise wavelet tree.
+ *
+ * The operations follow the thesis "GPU Implementation of the Wavelet Tree"
+ * (M. Franzreb Salgado, 2025):
+ *   access(i), rank_c(i), select_c(k) ............ Introduction (query definitions)
+ *   tree shape, reduced codes, level construction . Section 5.1 (Construction, Algorithms 3 and 4)
+ *   bit arrays, L1/L2 rank directory .............. Section 4, Section 4.1 (Algorithm 1)
+ *   select samples ................................ Section 4.2 (Algorithm 2)
+ *   precomputed node-start ranks .................. Sections 5.2-5.4
+ *   query traversals .............................. Section 5.2 (Algorithm 5), 5.3 (Algorithm 6),
+ *                                                   5.4 (Algorithms 7 and 8)
+ *
+ * Conventions (all calls):
+ *  - Positions are 0-based, k is 1-based, rank has an exclusive upper bound
+ *    (rank_c(i) counts c in S[0, i), i in [0, n]).
+ *  - Pointers named d_* are device pointers (HBM) owned by the caller; they must stay
+ *    valid until the work enqueued on `stream` completes. Pointers named h_* are host.
+ *  - `stream` is a hipStream_t passed as void* (NULL = the null stream). Query calls
+ *    enqueue one kernel and return without synchronising.
+ *  - A tree is owned by the library, immutable after wt_build returns, and may be
+ *    queried concurrently from several streams. Its memory comes from the allocator
+ *    installed with wt_set_allocator (default: hipMallocAsync / hipFreeAsync).
+ *  - Calls never throw; they return a wt_status and, on failure, set a thread-local
+ *    message readable with wt_last_error().
+ */
+#ifndef WT_H
+#define WT_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct wt_tree wt_tree;
+typedef void* wt_stream_t; /* hipStream_t */
+
+typedef enum {
+  WT_OK = 0,
+  WT_ERR_ARG = 1,          /* invalid argument (null pointer, unsupported width or alphabet, ...) */
+  WT_ERR_SYMBOL_RANGE = 2, /* a symbol >= sigma was found during the build; no tree is created */
+  WT_ERR_OOM = 3,          /* the allocator returned NULL */
+  WT_ERR_HIP = 4,          /* a HIP runtime call failed */
+  WT_ERR_STATE = 5         /* call not valid in the current state (e.g. no GPU) */
+} wt_status;
+
+/* Build options. Zero-initialised fields take the defaults. */
+typedef struct {
+  uint32_t l2_bits;     /* L2 block size |L2| in bits (Section 4.1): 256, 512 (default), 1024, 2048 */
+  uint32_t sample_rate; /* select sample interval s (Section 4.2): power of two in [512, 2^20]; default 4096 */
+  uint32_t flags;       /* WT_BUILD_PROFILE: time every build kernel with HIP events (wt_build_profile) */
+  uint32_t reserved;
+} wt_build_opts;
+
+#define WT_BUILD_PROFILE 1u
+
+/* Largest declared alphabet: the node tables are indexed by code prefix (2^L entries). */
+#define WT_MAX_SIGMA (1ull << 24)
+#define WT_MAX_LEVELS 24
+
+typedef void* (*wt_alloc_fn)(size_t bytes, wt_stream_t stream, void* ctx);
+typedef void (*wt_free_fn)(void* ptr, wt_stream_t stream, void* ctx);
+
+/* Install the device allocator used for tree memory and build scratch (NULL, NULL restores
+   the default). Returned pointers must be 256-byte aligned device memory. */
+wt_status wt_set_allocator(wt_alloc_fn alloc_fn, wt_free_fn free_fn, void* ctx);
+
+/*
+ * Build the level-wise wavelet tree of d_sym[0, n) (Section 5.1, Algorithm 4).
+ *   d_sym     device array of n symbols of sym_bytes bytes each (1, 2 or 4), little-endian.
+ *   sigma     declared alphabet size, 1 <= sigma <= min(2^(8 sym_bytes), WT_MAX_SIGMA); every
+ *             symbol must lie in [0, sigma). Absent symbols are allowed. Alphabets that are not
+ *             powers of two use the thesis's reduced codes (Algorithm 3).
+ *   opts      may be NULL (defaults).
+ *   out       receives the tree on WT_OK, NULL otherwise.
+ * The call enqueues the build on `stream` and waits for it to finish (it must read back the
+ * level sizes and the symbol-range flag). d_sym is not retained.
+ * Errors: WT_ERR_ARG (bad arguments), WT_ERR_SYMBOL_RANGE (a symbol >= sigma), WT_ERR_OOM,
+ * WT_ERR_HIP.
+ */
+wt_status wt_build(const void* d_sym, uint64_t n, uint32_t sym_bytes, uint64_t sigma, const wt_build_opts* opts,
+                   wt_stream_t stream, wt_tree** out);
+
+/* Release a tree (waits for the device to be idle first). NULL is accepted. */
+wt_status wt_free(wt_tree* t);
+
+/*
+ * Batched access (Section 5.2, Algorithm 5): d_out[j] = S[d_pos[j]] for j in [0, q).
+ * Positions >= n give 0xFFFFFFFF. One kernel on `stream`; q = 0 is a no-op.
+ */
+wt_status wt_access(const wt_tree* t, const uint64_t* d_pos, uint64_t q, uint32_t* d_out, wt_stream_t stream);
+
+/*
+ * Batched rank (Section 5.3, Algorithm 6): d_out[j] = number of d_sym[j] in S[0, d_pos[j]).
+ * Positions > n give UINT64_MAX; symbols >= sigma give 0.
+ */
+wt_status wt_rank(const wt_tree* t, const uint32_t* d_sym, const uint64_t* d_pos, uint64_t q, uint64_t* d_out,
+                  wt_stream_t stream);
+
+/*
+ * Batched select (Section 5.4, Algorithms 7 and 8 with the binary select of Algorithm 2):
+ * d_out[j] = 0-based position of the d_k[j]-th occurrence of d_sym[j].
+ * k = 0 gives UINT64_MAX; k > count(c) or c >= sigma gives n.
+ */
+wt_status wt_select(const wt_tree* t, const uint32_t* d_sym, const uint64_t* d_k, uint64_t q, uint64_t* d_out,
+                    wt_stream_t stream);
+
+/* Sizes and per-level counts of a built tree. */
+typedef struct {
+  uint64_t n, sigma;
+  uint32_t levels, sym_bytes, l2_bits, sample_rate;
+  uint64_t level_n[WT_MAX_LEVELS];    /* elements per level (n_l) */
+  uint64_t level_ones[WT_MAX_LEVELS]; /* ones per level */
+  uint64_t bytes_bits, bytes_l1, bytes_l2, bytes_samples, bytes_nodes, bytes_total; /* allocated */
+} wt_info_t;
+
+wt_status wt_info(const wt_tree* t, wt_info_t* out);
+
+/* Parts of a tree in canonical form (independent of the physical layout):
+ *   WT_PART_BITS       u64[ceil(n_l/64)]      level bits, LSB-first, zero padding
+ *   WT_PART_L1         u64[ceil(n_l/65536)+1] ones before each 65536-bit block; last = total
+ *   WT_PART_L2         u16[ceil(n_l/|L2|)+1]  ones from the enclosing L1 block start to each |L2| block
+ *   WT_PART_SAMPLES1   u64[floor(ones/s)]     position of the (k s)-th one, k = 1, 2, ...
+ *   WT_PART_SAMPLES0   u64[floor(zeros/s)]    position of the (k s)-th zero
+ *   WT_PART_NODE_START u64[2^l]               start of the node with code prefix p (UINT64_MAX: no node)
+ *   WT_PART_NODE_R0    u64[2^l]               rank0 of the level at that start (UINT64_MAX: no node)
+ *   WT_PART_CUM_HIST   u64[sigma+1]           exclusive prefix sums of the histogram (level ignored)
+ */
+enum {
+  WT_PART_BITS = 0,
+  WT_PART_L1 = 1,
+  WT_PART_L2 = 2,
+  WT_PART_SAMPLES1 = 3,
+  WT_PART_SAMPLES0 = 4,
+  WT_PART_NODE_START = 5,
+  WT_PART_NODE_R0 = 6,
+  WT_PART_CUM_HIST = 7
+};
+
+/* Copy one part to host memory h_dst of cap bytes; *needed receives the byte size of the part
+   (h_dst may be NULL to query it). Synchronous. WT_ERR_ARG if cap is too small. */
+wt_status wt_export(const wt_tree* t, int level, int part, void* h_dst, size_t cap, size_t* needed);
+
+/* Per-kernel durations of the last build of a tree made with WT_BUILD_PROFILE. */
+typedef struct {
+  char kernel[32]; /* "hist", "scan", "nodes", "tile_scan", "level", ... */
+  int32_t level;   /* tree level, or -1 */
+  float ms;        /* duration between HIP events recorded around the launch on the build stream */
+} wt_prof_entry;
+
+/* Copies up to cap entries; *count receives the number available. */
+wt_status wt_build_profile(const wt_tree* t, wt_prof_entry* out, uint32_t cap, uint32_t* count);
+
+/* Thread-local description of the last failure on this thread ("" if none). */
+const char* wt_last_error(void);
+
+/* Library version string. */
+const char* wt_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* WT_H */

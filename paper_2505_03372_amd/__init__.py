@@ -1,0 +1,245 @@
+"""MI355X (gfx950) level-wise wavelet tree: Python binding of the C ABI in include/wt.h.
+
+The binding only marshals arguments: every step of construction and of the queries runs in
+the HIP kernels of ``libwt.so``. PyTorch supplies device memory (input/output tensors) and the
+current HIP stream. There is no CPU fallback: importing works without the library, but every
+call that needs it raises ``WTLibraryMissing`` until ``python -m paper_2505_03372_amd.buildlib``
+has produced it.
+
+    import torch, paper_2505_03372_amd as wt
+    t = wt.build(sym_tensor_on_gpu, sigma=256)
+    t.access(pos)            # torch.uint32, 0xFFFFFFFF for positions >= n
+    t.rank(sym, pos)         # torch.uint64
+    t.select(sym, k)         # torch.uint64, n when k > count, 2^64-1 when k == 0
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libwt.so")
+
+WT_OK, WT_ERR_ARG, WT_ERR_SYMBOL_RANGE, WT_ERR_OOM, WT_ERR_HIP, WT_ERR_STATE = range(6)
+PART_BITS, PART_L1, PART_L2, PART_SAMPLES1, PART_SAMPLES0, PART_NODE_START, PART_NODE_R0, PART_CUM_HIST = range(8)
+BUILD_PROFILE = 1
+MAX_LEVELS = 24
+MAX_SIGMA = 1 << 24
+ACCESS_INVALID = 0xFFFFFFFF
+U64_MAX = (1 << 64) - 1
+
+# names declared by include/wt.h
+ABI_FUNCTIONS = ("wt_set_allocator", "wt_build", "wt_free", "wt_access", "wt_rank", "wt_select", "wt_info",
+                 "wt_export", "wt_build_profile", "wt_last_error", "wt_version")
+
+
+class WTLibraryMissing(RuntimeError):
+    pass
+
+
+class WTError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__("wt status %d: %s" % (status, msg))
+        self.status = status
+
+
+class BuildOpts(ctypes.Structure):
+    _fields_ = [("l2_bits", ctypes.c_uint32), ("sample_rate", ctypes.c_uint32), ("flags", ctypes.c_uint32),
+                ("reserved", ctypes.c_uint32)]
+
+
+class Info(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_uint64), ("sigma", ctypes.c_uint64), ("levels", ctypes.c_uint32),
+                ("sym_bytes", ctypes.c_uint32), ("l2_bits", ctypes.c_uint32), ("sample_rate", ctypes.c_uint32),
+                ("level_n", ctypes.c_uint64 * MAX_LEVELS), ("level_ones", ctypes.c_uint64 * MAX_LEVELS),
+                ("bytes_bits", ctypes.c_uint64), ("bytes_l1", ctypes.c_uint64), ("bytes_l2", ctypes.c_uint64),
+                ("bytes_samples", ctypes.c_uint64), ("bytes_nodes", ctypes.c_uint64), ("bytes_total", ctypes.c_uint64)]
+
+
+class ProfEntry(ctypes.Structure):
+    _fields_ = [("kernel", ctypes.c_char * 32), ("level", ctypes.c_int32), ("ms", ctypes.c_float)]
+
+
+_lib = None
+
+
+def lib():
+    """The loaded libwt.so; raises WTLibraryMissing when it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise WTLibraryMissing("%s is missing: build it with `python -m paper_2505_03372_amd.buildlib`" % LIB_PATH)
+    L = ctypes.CDLL(LIB_PATH)
+    vp, u64, u32 = ctypes.c_void_p, ctypes.c_uint64, ctypes.c_uint32
+    L.wt_build.restype = ctypes.c_int
+    L.wt_build.argtypes = [vp, u64, u32, u64, ctypes.POINTER(BuildOpts), vp, ctypes.POINTER(vp)]
+    L.wt_free.restype = ctypes.c_int
+    L.wt_free.argtypes = [vp]
+    L.wt_access.restype = ctypes.c_int
+    L.wt_access.argtypes = [vp, vp, u64, vp, vp]
+    L.wt_rank.restype = ctypes.c_int
+    L.wt_rank.argtypes = [vp, vp, vp, u64, vp, vp]
+    L.wt_select.restype = ctypes.c_int
+    L.wt_select.argtypes = [vp, vp, vp, u64, vp, vp]
+    L.wt_info.restype = ctypes.c_int
+    L.wt_info.argtypes = [vp, ctypes.POINTER(Info)]
+    L.wt_export.restype = ctypes.c_int
+    L.wt_export.argtypes = [vp, ctypes.c_int, ctypes.c_int, vp, ctypes.c_size_t, ctypes.POINTER(ctypes.c_size_t)]
+    L.wt_build_profile.restype = ctypes.c_int
+    L.wt_build_profile.argtypes = [vp, ctypes.POINTER(ProfEntry), u32, ctypes.POINTER(u32)]
+    L.wt_last_error.restype = ctypes.c_char_p
+    L.wt_last_error.argtypes = []
+    L.wt_version.restype = ctypes.c_char_p
+    L.wt_version.argtypes = []
+    L.wt_set_allocator.restype = ctypes.c_int
+    L.wt_set_allocator.argtypes = [vp, vp, vp]
+    _lib = L
+    return L
+
+
+def _check(status: int):
+    if status != WT_OK:
+        raise WTError(status, lib().wt_last_error().decode())
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _stream_handle(stream=None) -> int:
+    torch = _torch()
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return int(stream.cuda_stream) if hasattr(stream, "cuda_stream") else int(stream)
+
+
+def _dev_ptr(t, dtype, name):
+    torch = _torch()
+    if not t.is_cuda:
+        raise ValueError("%s must be a device tensor" % name)
+    if t.dtype != dtype:
+        raise TypeError("%s must be %s (got %s)" % (name, dtype, t.dtype))
+    if not t.is_contiguous():
+        raise ValueError("%s must be contiguous" % name)
+    return ctypes.c_void_p(t.data_ptr() if t.numel() else 0)
+
+
+_SYM_DTYPES = None
+
+
+def _sym_dtypes():
+    global _SYM_DTYPES
+    if _SYM_DTYPES is None:
+        torch = _torch()
+        _SYM_DTYPES = {torch.uint8: 1, torch.uint16: 2, torch.uint32: 4}
+    return _SYM_DTYPES
+
+
+class Tree:
+    """A wavelet tree resident in HBM (owned by libwt)."""
+
+    def __init__(self, handle: int, keepalive=None):
+        self._h = ctypes.c_void_p(handle)
+        self._keep = keepalive
+        self.info = self._info()
+
+    @property
+    def handle(self):
+        return self._h
+
+    def _info(self) -> dict:
+        inf = Info()
+        _check(lib().wt_info(self._h, ctypes.byref(inf)))
+        L = inf.levels
+        return dict(n=inf.n, sigma=inf.sigma, levels=L, sym_bytes=inf.sym_bytes, l2_bits=inf.l2_bits,
+                    sample_rate=inf.sample_rate, level_n=list(inf.level_n[:L]), level_ones=list(inf.level_ones[:L]),
+                    bytes_bits=inf.bytes_bits, bytes_l1=inf.bytes_l1, bytes_l2=inf.bytes_l2,
+                    bytes_samples=inf.bytes_samples, bytes_nodes=inf.bytes_nodes, bytes_total=inf.bytes_total)
+
+    @property
+    def n(self) -> int:
+        return self.info["n"]
+
+    @property
+    def sigma(self) -> int:
+        return self.info["sigma"]
+
+    def access(self, pos, out=None, stream=None):
+        torch = _torch()
+        q = pos.numel()
+        if out is None:
+            out = torch.empty(q, dtype=torch.uint32, device=pos.device)
+        _check(lib().wt_access(self._h, _dev_ptr(pos, torch.uint64, "pos"), q, _dev_ptr(out, torch.uint32, "out"),
+                               ctypes.c_void_p(_stream_handle(stream))))
+        return out
+
+    def rank(self, sym, pos, out=None, stream=None):
+        torch = _torch()
+        q = pos.numel()
+        if sym.numel() != q:
+            raise ValueError("sym and pos must have the same length")
+        if out is None:
+            out = torch.empty(q, dtype=torch.uint64, device=pos.device)
+        _check(lib().wt_rank(self._h, _dev_ptr(sym, torch.uint32, "sym"), _dev_ptr(pos, torch.uint64, "pos"), q,
+                             _dev_ptr(out, torch.uint64, "out"), ctypes.c_void_p(_stream_handle(stream))))
+        return out
+
+    def select(self, sym, k, out=None, stream=None):
+        torch = _torch()
+        q = k.numel()
+        if sym.numel() != q:
+            raise ValueError("sym and k must have the same length")
+        if out is None:
+            out = torch.empty(q, dtype=torch.uint64, device=k.device)
+        _check(lib().wt_select(self._h, _dev_ptr(sym, torch.uint32, "sym"), _dev_ptr(k, torch.uint64, "k"), q,
+                               _dev_ptr(out, torch.uint64, "out"), ctypes.c_void_p(_stream_handle(stream))))
+        return out
+
+    def export(self, part: int, level: int = 0) -> np.ndarray:
+        need = ctypes.c_size_t(0)
+        _check(lib().wt_export(self._h, level, part, None, 0, ctypes.byref(need)))
+        dt = np.uint16 if part == PART_L2 else np.uint64
+        buf = np.zeros(max(need.value // np.dtype(dt).itemsize, 1), dtype=dt)
+        _check(lib().wt_export(self._h, level, part, ctypes.c_void_p(buf.ctypes.data), buf.nbytes,
+                               ctypes.byref(need)))
+        return buf[: need.value // np.dtype(dt).itemsize]
+
+    def profile(self) -> list:
+        cnt = ctypes.c_uint32(0)
+        _check(lib().wt_build_profile(self._h, None, 0, ctypes.byref(cnt)))
+        arr = (ProfEntry * max(cnt.value, 1))()
+        _check(lib().wt_build_profile(self._h, arr, cnt.value, ctypes.byref(cnt)))
+        return [dict(kernel=arr[i].kernel.decode(), level=arr[i].level, ms=arr[i].ms) for i in range(cnt.value)]
+
+    def free(self):
+        if self._h is not None and self._h.value:
+            _check(lib().wt_free(self._h))
+            self._h = ctypes.c_void_p(0)
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
+
+
+def build(sym, sigma: int, l2_bits: int = 512, sample_rate: int = 4096, profile: bool = False, stream=None) -> Tree:
+    """Build the wavelet tree of a contiguous device tensor of uint8/uint16/uint32 symbols."""
+    dts = _sym_dtypes()
+    if sym.dtype not in dts:
+        raise TypeError("symbols must be uint8, uint16 or uint32 (got %s)" % sym.dtype)
+    if not sym.is_cuda or not sym.is_contiguous():
+        raise ValueError("symbols must be a contiguous device tensor")
+    opts = BuildOpts(l2_bits, sample_rate, BUILD_PROFILE if profile else 0, 0)
+    h = ctypes.c_void_p(0)
+    _check(lib().wt_build(ctypes.c_void_p(sym.data_ptr() if sym.numel() else 0), sym.numel(), dts[sym.dtype], sigma,
+                          ctypes.byref(opts), ctypes.c_void_p(_stream_handle(stream)), ctypes.byref(h)))
+    return Tree(h.value)
+
+
+def version() -> str:
+    return lib().wt_version().decode()

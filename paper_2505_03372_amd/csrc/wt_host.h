@@ -1,0 +1,55 @@
+// Host-side tree object and helpers shared by the C ABI translation units.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <string>
+#include <vector>
+
+#include "wt_internal.h"
+
+struct wt_tree {
+  uint64_t n = 0, sigma = 0;
+  uint32_t L = 0, w = 0, l2_bits = 512, srate = 4096, pow2 = 1;
+  int device = 0;
+  void* block = nullptr;  // one allocation holding every device part of the tree
+  size_t block_bytes = 0;
+  wt::TreeDev dev{};
+  wt::LevelMeta hmeta[WT_MAX_LEVELS]{};
+  size_t bytes_bits = 0, bytes_l1 = 0, bytes_l2 = 0, bytes_smp = 0, bytes_nodes = 0, bytes_cum = 0;
+  std::vector<wt_prof_entry> prof;
+};
+
+namespace wt {
+
+wt_status fail(wt_status s, const char* fmt, ...);
+void clear_error();
+void* dev_alloc(size_t bytes, hipStream_t s);
+void dev_free(void* p, hipStream_t s);
+
+// Checks a HIP call; on failure records the message and returns WT_ERR_HIP from the caller.
+#define WT_HIP(call)                                                                        \
+  do {                                                                                      \
+    hipError_t e_ = (call);                                                                 \
+    if (e_ != hipSuccess) return ::wt::fail(WT_ERR_HIP, "%s: %s", #call, hipGetErrorString(e_)); \
+  } while (0)
+
+inline uint64_t ceil_div(uint64_t a, uint64_t b) { return (a + b - 1) / b; }
+inline uint64_t round_up(uint64_t a, uint64_t b) { return ceil_div(a, b) * b; }
+
+// Byte sizes of the tree parts for n elements (every level gets the capacity of level 0).
+struct TreePlan {
+  uint64_t n, sigma;
+  uint32_t L, w, l2_bits, srate, tile;
+  uint64_t words_per_level;  // bit words per level (padded to whole tiles + one L2 block, 128 B aligned)
+  uint64_t l1_per_level, l2_per_level, smp_per_level;
+  uint64_t nheap;  // node table entries: 2^L - 1
+  size_t off_meta, off_cum, off_nodes, off_bits, off_l1, off_l2, off_smp, total;
+};
+
+TreePlan plan_tree(uint64_t n, uint32_t w, uint64_t sigma, uint32_t L, uint32_t l2_bits, uint32_t srate);
+
+// Tile (elements per level-kernel block) for a symbol width.
+inline uint32_t tile_elems(uint32_t w) { return 16384u / w; }
+
+}  // namespace wt
