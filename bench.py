@@ -1,0 +1,224 @@
+"""Benchmark of the wavelet-tree hot path on one MI355X.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload text_zipf]
+
+One step = one pass of the whole hot path over one batch of synthetic input already resident in
+HBM: build the level-wise wavelet tree of n symbols (histogram, node tables, every level's bits,
+rank directory, select samples and partition), then answer q access, q rank and q select queries,
+then free the tree. Default workload: n = 2^30 u8 symbols, alphabet 256, Zipf(1.0) frequencies over
+a seeded permutation, q = 2^26 queries of each kind.
+
+Prints one JSON line. `value` is (symbols built + queries answered) per second over the timed
+steps; the per-part rates are in `rates`. `roofline` covers the dominant kernel (the level pass),
+timed with HIP events recorded by the library around every level launch on the build stream.
+`cpu_baseline` times the plain CPU oracle on a bounded prefix of the same workload.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
+PMC_FILE = os.path.join(ROOT, "profiles", "level_kernel_text_zipf_pmc.json")
+LEVEL_SRC = os.path.join(ROOT, "paper_2505_03372_amd", "csrc", "wt_build.hip")
+
+
+def level_launch_bytes(info: dict, w: int) -> list:
+    """Algorithmic HBM bytes of each level-kernel launch: read the level (w B/symbol), write the
+    next level's sequence (w B/symbol, not at the last level), write the bits (1/8 B/symbol), the L1
+    and L2 entries and the select samples."""
+    L = info["levels"]
+    s = info["sample_rate"]
+    out = []
+    for l in range(L):
+        nl = info["level_n"][l]
+        ones = info["level_ones"][l]
+        b = nl * w                                      # read level l
+        if l + 1 < L:
+            b += info["level_n"][l + 1] * w             # write level l + 1
+        b += (nl + 63) // 64 * 8                        # bit words
+        b += ((nl + 65535) // 65536) * 8                # L1
+        b += ((nl + info["l2_bits"] - 1) // info["l2_bits"]) * 2  # L2
+        b += (ones // s + (nl - ones) // s) * 8         # samples
+        out.append(b)
+    return out
+
+
+def source_hash(path: str) -> str:
+    with open(path, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()[:16]
+
+
+def load_traffic(per_launch_alg: float):
+    """HBM traffic of the level kernel from the committed rocprofv3 counter summary, if it was taken
+    on the current kernel source."""
+    if not os.path.exists(PMC_FILE):
+        return None
+    with open(PMC_FILE) as f:
+        pmc = json.load(f)
+    if pmc.get("source_sha256_16") != source_hash(LEVEL_SRC):
+        return None
+    return pmc.get("traffic_bytes_per_launch")
+
+
+def cpu_baseline(name: str, n_sample: int, q_sample: int) -> dict:
+    import oracle
+    import workloads
+    S, sigma = workloads.make_text(name, n=n_sample)
+    qs = workloads.make_queries(name, S, sigma, q=q_sample)
+    t0 = time.perf_counter()
+    oracle.OracleTree(S, sigma)
+    t1 = time.perf_counter()
+    oracle.access(S, qs["acc_pos"])
+    oracle.rank(S, sigma, qs["rank_c"], qs["rank_i"])
+    oracle.select(S, sigma, qs["sel_c"], qs["sel_k"])
+    t2 = time.perf_counter()
+    items = n_sample + 3 * q_sample
+    return {"value": items / (t2 - t0), "unit": "(symbols+queries)/s", "cores": 1, "kind": "oracle",
+            "sample": "first 2^%d symbols of the same text (oracle build of every level, directory, samples and "
+                      "node tables: %.2f s) + 2^%d access, rank and select queries drawn with the same recipe "
+                      "(sweeps: %.2f s)" % (n_sample.bit_length() - 1, t1 - t0, q_sample.bit_length() - 1, t2 - t1)}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", default="text_zipf")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-sample-log2", type=int, default=25)
+    ap.add_argument("--cpu-queries-log2", type=int, default=20)
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="also run a plain 1 GiB device copy (reference kernel for HBM counter scaling)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU: the wavelet-tree build and queries here run on a single MI355X "
+              "(--gpus %d is not supported)" % args.gpus, file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import paper_2505_03372_amd as wt
+    import workloads
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    wt.lib()
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    idx, n, width, sigma, q = workloads.CONFIGS[args.workload]
+    print("# generating workload %s: n=%d width=%d sigma=%d q=%d" % (args.workload, n, width, sigma, q),
+          file=sys.stderr, flush=True)
+    wl = workloads.make(args.workload)
+    S = torch.from_numpy(wl.S).to(dev)
+    kinds = {}
+    if wl.acc_pos is not None:
+        kinds["access"] = (torch.from_numpy(wl.acc_pos).to(dev),)
+    if wl.rank_c is not None:
+        kinds["rank"] = (torch.from_numpy(wl.rank_c).to(dev), torch.from_numpy(wl.rank_i).to(dev))
+    if wl.sel_c is not None:
+        kinds["select"] = (torch.from_numpy(wl.sel_c).to(dev), torch.from_numpy(wl.sel_k).to(dev))
+    outs = {"access": torch.empty(q, dtype=torch.uint32, device=dev),
+            "rank": torch.empty(q, dtype=torch.uint64, device=dev),
+            "select": torch.empty(q, dtype=torch.uint64, device=dev)}
+    del wl
+    torch.cuda.synchronize()
+    print("# workload resident in HBM", file=sys.stderr, flush=True)
+
+    stream = torch.cuda.current_stream()
+
+    def step(record):
+        t = wt.build(S, sigma, profile=True)
+        evs = {}
+        for kind, a in kinds.items():
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            if kind == "access":
+                t.access(a[0], out=outs[kind])
+            elif kind == "rank":
+                t.rank(a[0], a[1], out=outs[kind])
+            else:
+                t.select(a[0], a[1], out=outs[kind])
+            e1.record(stream)
+            evs[kind] = (e0, e1)
+        if record is not None:
+            record.append((t.profile(), evs, t.info))
+        t.free()
+
+    for _ in range(args.warmup):
+        step(None)
+    torch.cuda.synchronize()
+    recs = []
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step(recs)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    ms_per_step = (t1 - t0) * 1e3 / args.steps
+
+    info = recs[0][2]
+    level_ms, build_ms, qms = [], [], {k: [] for k in kinds}
+    for prof, evs, _ in recs:
+        level_ms += [p["ms"] for p in prof if p["kernel"] == "level"]
+        build_ms.append(sum(p["ms"] for p in prof))
+        for k, (e0, e1) in evs.items():
+            qms[k].append(e0.elapsed_time(e1))
+    per_launch = level_launch_bytes(info, width)
+    avg_bytes = float(np.mean(per_launch))
+    avg_ms = float(np.mean(level_ms))
+    achieved = avg_bytes / (avg_ms * 1e-3) / 1e9
+    items = n + sum(q for _ in kinds)
+    rates = {"build_symbols_per_s": n / (np.median(build_ms) * 1e-3)}
+    for k in kinds:
+        rates[k + "_queries_per_s"] = q / (np.median(qms[k]) * 1e-3)
+    rates["build_ms_median"] = float(np.median(build_ms))
+    for k in kinds:
+        rates[k + "_ms_median"] = float(np.median(qms[k]))
+    roof = {"kernel": "k_level<uint8_t>" if width == 1 else ("k_level<uint16_t>" if width == 2 else
+                                                            "k_level<uint32_t>"),
+            "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBS, "traffic": load_traffic(avg_bytes),
+            "bytes_per_launch": avg_bytes, "avg_launch_ms": avg_ms, "launches": len(level_ms)}
+    line = {
+        "metric": "build symbols/s + access/rank/select queries/s; learned vs plain select",
+        "value": items / (ms_per_step * 1e-3),
+        "unit": "(symbols+queries)/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": {1: "u8", 2: "u16", 4: "u32"}[width],
+        "data": "synthetic",
+        "config": {"workload": args.workload, "n": n, "sym_bytes": width, "sigma": sigma, "queries_per_kind": q,
+                   "query_kinds": list(kinds), "l2_bits": 512, "sample_rate": 4096},
+        "rates": rates,
+        "roofline": roof,
+    }
+    if args.calibrate_copy:
+        src = torch.empty(1 << 30, dtype=torch.uint8, device=dev)
+        dst = torch.empty_like(src)
+        for _ in range(2):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        line["calibration_copy_bytes"] = 1 << 30
+        del src, dst
+    if not args.no_cpu_baseline:
+        print("# timing the CPU oracle on a bounded sample", file=sys.stderr, flush=True)
+        line["cpu_baseline"] = cpu_baseline(args.workload, 1 << args.cpu_sample_log2, 1 << args.cpu_queries_log2)
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

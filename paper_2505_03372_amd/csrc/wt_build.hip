@@ -34,13 +34,14 @@ constexpr int kHashSlots = 4096; // LDS count cache for large alphabets
 
 template <typename E>
 struct Tile {
-  static constexpr int EV = 16 / (int)sizeof(E);  // elements per 16-byte vector
-  static constexpr int NCH = 4;                   // vectors per thread
-  static constexpr int T = kBT * NCH * EV;        // elements per tile
-  static constexpr int W = T / 64;                // bit words per tile
-  static constexpr int G = 64 / EV;               // lanes whose vectors form one word
-  static constexpr int TSHIFT = sizeof(E) == 1 ? 14 : (sizeof(E) == 2 ? 13 : 12);
+  static constexpr int EV = 16 / (int)sizeof(E);         // elements per 16-byte vector
+  static constexpr int NCH = kTileBytes / (kBT * 16);     // vectors per thread
+  static constexpr int T = kBT * NCH * EV;               // elements per tile
+  static constexpr int W = T / 64;                       // bit words per tile
+  static constexpr int G = 64 / EV;                      // lanes whose vectors form one word
+  static constexpr int TSHIFT = sizeof(E) == 1 ? 13 : (sizeof(E) == 2 ? 12 : 11);
   static_assert((1 << TSHIFT) == T, "tile");
+  static_assert(T % 512 == 0 && kL1Bits % T == 0, "tiles cover whole L2 blocks and divide L1 blocks");
 };
 
 // ---------------------------------------------------------------- block scans
@@ -203,9 +204,15 @@ __device__ __forceinline__ void load16(const E* __restrict__ base, uint32_t q0, 
 
 // ---------------------------------------------------------------- histogram (Section 5.1.1)
 
+// Ones per tile are accumulated per chunk of kChunkTiles tiles as well, so a level's tile prefix
+// needs one launch: block b adds the chunk sums before it to the scan of its own chunk.
+constexpr int kChunkShift = 10;
+constexpr uint64_t kChunkTiles = 1ull << kChunkShift;
+
 // Persistent grid over whole tiles. Small alphabets count into LDS replicas (one per group of
-// threads, assigned round-robin); large alphabets use an LDS cache of claimed symbols with global
-// atomics for the rest. Also records, per level-0 tile, the number of ones (code bit L-1).
+// threads, assigned round-robin; replicas are padded by one counter so equal symbols of different
+// replicas fall into different banks); large alphabets use an LDS cache of claimed symbols with
+// global atomics for the rest. Also records, per level-0 tile, the number of ones (code bit L-1).
 template <typename E, bool kSmall>
 __global__ __launch_bounds__(kBT) void k_hist(const E* __restrict__ sym, uint64_t n, uint32_t sigma, uint32_t L,
                                               uint32_t pow2, uint32_t aligned, uint32_t nrep,
@@ -215,10 +222,11 @@ __global__ __launch_bounds__(kBT) void k_hist(const E* __restrict__ sym, uint64_
   extern __shared__ uint32_t s_h[];
   __shared__ uint32_t s_w[kBT / 64];
   const uint32_t tid = threadIdx.x;
-  const uint32_t hsize = kSmall ? nrep * sigma : 2u * kHashSlots;
+  const uint32_t stride = sigma + 1;
+  const uint32_t hsize = kSmall ? nrep * stride : 2u * kHashSlots;
   for (uint32_t i = tid; i < hsize; i += kBT) s_h[i] = 0;
   __syncthreads();
-  uint32_t* my_h = s_h + (kSmall ? (tid % nrep) * sigma : 0u);
+  uint32_t* my_h = s_h + (kSmall ? (tid % nrep) * stride : 0u);
   uint32_t* s_keys = s_h;
   uint32_t* s_cnts = s_h + kHashSlots;
   const uint64_t ntiles = (n + TL::T - 1) >> TL::TSHIFT;
@@ -227,7 +235,7 @@ __global__ __launch_bounds__(kBT) void k_hist(const E* __restrict__ sym, uint64_
     const uint64_t t0 = t << TL::TSHIFT;
     const uint32_t cnt = (uint32_t)min<uint64_t>(TL::T, n - t0);
     uint32_t ones = 0;
-#pragma unroll
+#pragma unroll 1
     for (int k = 0; k < TL::NCH; ++k) {
       const uint32_t q0 = (uint32_t)(k * kBT + tid) * TL::EV;
       E v[TL::EV];
@@ -263,7 +271,7 @@ __global__ __launch_bounds__(kBT) void k_hist(const E* __restrict__ sym, uint64_
   if (kSmall) {
     for (uint32_t s = tid; s < sigma; s += kBT) {
       uint64_t c = 0;
-      for (uint32_t r = 0; r < nrep; ++r) c += s_h[r * sigma + s];
+      for (uint32_t r = 0; r < nrep; ++r) c += s_h[r * stride + s];
       if (c) atomicAdd((unsigned long long*)&hist[s], (unsigned long long)c);
     }
   } else {
@@ -346,36 +354,66 @@ __global__ void k_node_final(uint64_t nheap, const uint64_t* __restrict__ zs, No
 
 // ---------------------------------------------------------------- per-level tile prefix
 
-// Single block: exclusive prefix of the ones per tile of level l (tile size 2^tshift), the level's
-// total ones, and the sentinel L1/L2 entries that make rank defined at i = n_l.
-__global__ __launch_bounds__(1024) void k_tile_scan(LevelMeta* __restrict__ meta, uint32_t l, uint32_t tshift,
-                                                    const uint64_t* __restrict__ cnt, uint64_t* __restrict__ pre,
-                                                    uint64_t* __restrict__ L1, uint16_t* __restrict__ L2,
-                                                    uint32_t l2shift) {
-  __shared__ uint64_t s_w[16];
+// Sum of the ones of every chunk of kChunkTiles tiles of level l.
+__global__ __launch_bounds__(kBT) void k_tile_reduce(const LevelMeta* __restrict__ meta, uint32_t l,
+                                                     uint32_t tshift, const uint64_t* __restrict__ cnt,
+                                                     uint64_t* __restrict__ chunk) {
+  __shared__ uint64_t s_w[kBT / 64];
+  const uint64_t nl = meta[l].n;
+  const uint64_t nt = (nl + (1ull << tshift) - 1) >> tshift;
+  const uint64_t b = blockIdx.x;
+  if ((b << kChunkShift) >= nt) return;
+  constexpr int kPer = (int)(kChunkTiles / kBT);
+  const uint64_t i0 = (b << kChunkShift) + (uint64_t)threadIdx.x * kPer;
+  uint64_t sum = 0;
+#pragma unroll
+  for (int i = 0; i < kPer; ++i) sum += (i0 + i < nt) ? cnt[i0 + i] : 0ull;
+  uint64_t tot;
+  block_excl_scan_u64(sum, s_w, tot);
+  if (threadIdx.x == 0) chunk[b] = tot;
+}
+
+// Exclusive prefix of the ones per tile of level l (tile size 2^tshift). Block b scans the tiles of
+// chunk b (4 per thread) after adding the sums of the chunks before it. Levels with no element get
+// their sentinel L1/L2 entries here; otherwise the block of the last tile writes them.
+__global__ __launch_bounds__(kBT) void k_tile_scan(LevelMeta* __restrict__ meta, uint32_t l, uint32_t tshift,
+                                                   const uint64_t* __restrict__ cnt,
+                                                   const uint64_t* __restrict__ chunk, uint64_t* __restrict__ pre,
+                                                   uint64_t* __restrict__ L1, uint16_t* __restrict__ L2) {
+  __shared__ uint64_t s_w[kBT / 64];
   const LevelMeta m = meta[l];
   const uint64_t nl = m.n;
   const uint64_t nt = (nl + (1ull << tshift) - 1) >> tshift;
-  const uint64_t per = (nt + 1023) / 1024;
-  const uint64_t i0 = (uint64_t)threadIdx.x * per;
-  const uint64_t i1 = min(i0 + per, nt);
-  uint64_t s = 0;
-  for (uint64_t i = i0; i < i1; ++i) s += cnt[i];
-  uint64_t total;
-  uint64_t run = block_excl_scan_u64(s, s_w, total);
-  for (uint64_t i = i0; i < i1; ++i) {
-    pre[i] = run;
-    run += cnt[i];
+  const uint64_t b = blockIdx.x;
+  if (nl == 0) {
+    if (b == 0 && threadIdx.x == 0) {
+      pre[0] = 0;
+      meta[l].ones = 0;
+      L1[m.l1] = 0;
+      L2[m.l2] = 0;
+    }
+    return;
   }
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    pre[nt] = total;
-    meta[l].ones = total;
-    L1[m.l1 + ((nl + kL1Bits - 1) >> kL1Shift)] = total;
-    const uint64_t j = (nl + (1ull << l2shift) - 1) >> l2shift;
-    const uint64_t blk = (j << l2shift) >> kL1Shift;
-    const uint64_t l1val = ((blk << kL1Shift) >= nl) ? total : pre[blk << (kL1Shift - tshift)];
-    L2[m.l2 + j] = (uint16_t)(total - l1val);
+  if ((b << kChunkShift) > nt) return;
+  uint64_t before = 0;
+  for (uint64_t c = threadIdx.x; c < b; c += kBT) before += chunk[c];
+  uint64_t tot;
+  block_excl_scan_u64(before, s_w, tot);
+  before = tot;
+  constexpr int kPer = (int)(kChunkTiles / kBT);
+  const uint64_t i0 = (b << kChunkShift) + (uint64_t)threadIdx.x * kPer;
+  uint64_t v[kPer];
+  uint64_t sum = 0;
+#pragma unroll
+  for (int i = 0; i < kPer; ++i) {
+    v[i] = (i0 + i < nt) ? cnt[i0 + i] : 0ull;
+    sum += v[i];
+  }
+  uint64_t run = before + block_excl_scan_u64(sum, s_w, tot);
+#pragma unroll
+  for (int i = 0; i < kPer; ++i) {
+    if (i0 + i <= nt) pre[i0 + i] = run;
+    run += v[i];
   }
 }
 
@@ -389,102 +427,190 @@ struct LevelArgs {
   uint16_t* L2;
   uint64_t* smp;
   LevelMeta* meta;
-  const uint64_t* pre;  // exclusive ones before each tile of this level
-  uint64_t* cnt_next;   // ones per tile of level l + 1 (accumulated)
-  const NodeB* ntb;     // node table of this level, indexed by code prefix
+  const uint64_t* pre;    // exclusive ones before each tile of this level
+  uint64_t* cnt_next;     // ones per tile of level l + 1 (accumulated)
+  const NodeB* ntb;       // node table of this level, indexed by code prefix
   uint32_t l, L, sigma, pow2;
   uint32_t l2shift, sshift;
-  uint32_t encode;  // level 0 of a reduced alphabet: turn symbols into codes
+  uint32_t encode;      // level 0 of a reduced alphabet: turn symbols into codes
   uint32_t in_vec;      // the input may be read with 16-byte vectors everywhere (padded and aligned)
   uint32_t in_aligned;  // the input base is 16-byte aligned (vectors only inside the sequence)
 };
 
+// Adds, for the lanes in `cls`, their next-level ones (the bit `nbit`, or `cnt_lane` when nbit is
+// unused) per destination tile to a running per-wave (tile, count) pair, flushing it to the global
+// tile counter when the tile changes. Destinations increase with the processing order, so each tile
+// is flushed about once per wave, and a tile counter sees few writers.
+__device__ __forceinline__ void count_next(uint64_t cls, uint64_t dt, uint32_t nbit, uint32_t lane,
+                                           uint64_t& cur_tile, uint32_t& cur_c, uint64_t* __restrict__ cnt,
+                                           uint32_t cnt_lane) {
+  const uint32_t mine = nbit + cnt_lane;
+  while (cls) {
+    const int leader = __ffsll((unsigned long long)cls) - 1;
+    const uint64_t ldt = __shfl(dt, leader, 64);
+    const bool in = ((cls >> lane) & 1ull) && dt == ldt;
+    const uint64_t same = __ballot(in);
+    uint32_t c1 = in ? mine : 0u;
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) c1 += __shfl_xor(c1, off, 64);
+    if (ldt == cur_tile) {
+      cur_c += c1;
+    } else {
+      if (cur_c && lane == 0) atomicAdd((unsigned long long*)&cnt[cur_tile], (unsigned long long)cur_c);
+      cur_tile = ldt;
+      cur_c = c1;
+    }
+    cls &= ~same;
+  }
+}
+
+// Tile-local rank1 at x in [0, T]: ones in the words before x / 64 plus the low bits of that word.
 __device__ __forceinline__ uint32_t r1loc(const uint64_t* __restrict__ sw, const uint32_t* __restrict__ sp,
                                           uint32_t x) {
   const uint32_t wi = x >> 6, bi = x & 63u;
   return sp[wi] + popc64(sw[wi] & ((1ull << bi) - 1ull));
 }
 
+struct Seg {
+  uint32_t a, z, zs, pad;  // tile-local segment [a, z) and its zeros
+  uint64_t d0, d1;         // level-(l+1) destinations of its first zero and first one
+};
+constexpr int kSegMax = 128;  // node segments per tile handled by the vector write-out
+static_assert(2 * kSegMax <= kBT, "one thread per run in the run prefix");
+
+// A lane meets the node of its element at tile position q: the node's segment [sa, sz) of the tile,
+// its zeros zs and the tile-local rank1 R1a at its start. The lane holding the segment's first
+// element records the segment's two runs.
+__device__ __forceinline__ void enter_node(const NodeB nb, uint32_t q, uint64_t t0, uint32_t cnt, uint64_t G0,
+                                           uint64_t G1, const uint64_t* s_words, const uint32_t* s_wpre,
+                                           Seg* s_seg, uint32_t* s_nseg, uint32_t& sa, uint32_t& zs,
+                                           uint32_t& R1a) {
+  sa = (uint32_t)(nb.start > t0 ? min(nb.start - t0, (uint64_t)cnt) : 0ull);
+  const uint32_t sz = (uint32_t)(nb.end > t0 ? min(nb.end - t0, (uint64_t)cnt) : 0ull);
+  R1a = r1loc(s_words, s_wpre, sa);
+  zs = (sz - r1loc(s_words, s_wpre, sz)) - (sa - R1a);
+  if (q == sa) {
+    const uint32_t idx = atomicAdd(s_nseg, 1u);
+    if (idx < (uint32_t)kSegMax) {
+      Seg g;
+      g.a = sa;
+      g.z = sz;
+      g.zs = zs;
+      g.pad = 0;
+      g.d0 = nb.off0 + G0 + (sa - R1a);
+      g.d1 = nb.off1 + G1 + R1a;
+      s_seg[idx] = g;
+    }
+  }
+}
+
+// Element e of a 16-byte vector of E (e a compile-time constant after unrolling).
+template <typename E>
+__device__ __forceinline__ uint32_t vec_elem(const uint4& x, uint32_t e) {
+  constexpr uint32_t per = 4 / sizeof(E);  // elements per dword
+  const uint32_t d = e / per;
+  const uint32_t dw = d < 2 ? (d == 0 ? x.x : x.y) : (d == 2 ? x.z : x.w);
+  if constexpr (sizeof(E) == 4) return dw;
+  else return (dw >> ((e % per) * 8 * sizeof(E))) & ((1u << (8 * sizeof(E))) - 1u);
+}
+
+// Element e of the 128-bit value (lo, hi) for a run-time e, by shifting (no indexed access, which
+// would put the vector in scratch memory).
+template <typename E>
+__device__ __forceinline__ uint32_t elem128(uint64_t lo, uint64_t hi, uint32_t e) {
+  const uint32_t sh = e * 8u * (uint32_t)sizeof(E);
+  const uint64_t v = sh < 64 ? (sh ? (lo >> sh) | (hi << (64 - sh)) : lo) : (hi >> (sh - 64));
+  return (uint32_t)v & (uint32_t)((1ull << (8 * sizeof(E))) - 1ull);
+}
+
 // One block per tile of T elements of level l:
-//  1. coalesced 16-byte loads (4 per thread); element q of the tile sits in vector q / EV;
-//  2. bit words: each vector gives EV bits, G neighbouring lanes OR them into one 64-bit word;
-//  3. block scan of the word popcounts -> tile-local rank1 at every word;
-//  4. bit words, L2 entries (ones since the enclosing L1 block start), the L1 entry when the tile
+//  1. coalesced 16-byte loads (NCH per thread, kept in registers); each vector gives EV bits and G
+//     neighbouring lanes OR them into one 64-bit word of the level;
+//  2. block scan of the word popcounts -> tile-local rank1 at every word;
+//  3. bit words, L2 entries (ones since the enclosing L1 block start), the L1 entry when the tile
 //     starts an L1 block, select samples where the global one/zero count crosses a multiple of s;
-//  5. stable partition staged in LDS: within the tile every node segment is reordered zeros-first
-//     (slot = segment start + tile-local rank of the element among its bit inside the segment), so
-//     the slot range of a segment equals its position range and slots are ordered by destination;
-//  6. write-out in slot order, 64 consecutive slots per wave instruction (contiguous destinations
-//     inside each run), and per-destination-tile counts of the next level's ones.
+//  4. stable partition into level l + 1: every element goes to off_b[node] + rank_b(position).
+//     a. staged in LDS in destination order: a node segment of the tile keeps its slot range and is
+//        reordered zeros first (each lane walks its own vectors with a running rank);
+//     b. runs (segment, bit) are contiguous in the destination: each lane writes one aligned
+//        16-byte chunk of a run (element stores only at run edges), and the next level's ones per
+//        destination tile are counted on the way.
 template <typename E>
 __global__ __launch_bounds__(kBT) void k_level(LevelArgs a) {
   using TL = Tile<E>;
   constexpr int T = TL::T, W = TL::W, EV = TL::EV, G = TL::G, NCH = TL::NCH;
-  __shared__ uint64_t s_words[W + 1];
-  __shared__ uint32_t s_wpre[W + 1];
-  __shared__ E s_stage[T];
+  __shared__ __align__(16) E s_stage[T + 16 / sizeof(E) + 4];  // + slack for the 20-byte chunk reads
+  __shared__ uint64_t s_words[W + 1];  // entry W: 0, so ranks are defined at x = T
+  __shared__ uint32_t s_wpre[W + 1];   // entry W: ones of the tile
   __shared__ uint32_t s_w[kBT / 64];
+  __shared__ Seg s_seg[kSegMax];
+  __shared__ uint32_t s_cp[2 * kSegMax + 1];
+  __shared__ uint32_t s_nseg;
 
-  const uint32_t tid = threadIdx.x, lane = tid & 63u, wv = tid >> 6;
+  const uint32_t tid = threadIdx.x, lane = tid & 63u;
   const uint32_t l = a.l, L = a.L;
   const LevelMeta m = a.meta[l];
   const uint64_t nl = m.n;
   const uint64_t t = blockIdx.x;
   const uint64_t t0 = t << TL::TSHIFT;
   if (t0 >= nl) return;
+  // independent scalars first, so their latency overlaps the tile loads
+  const bool last = l + 1 >= L;
+  const uint64_t G1 = a.pre[t];  // ones of the level before the tile
+  const uint64_t l1val = a.pre[t & ~(uint64_t)((kL1Bits / T) - 1)];
+  const uint64_t n_next = last ? 0ull : a.meta[l + 1].n;
   const uint32_t cnt = (uint32_t)min<uint64_t>((uint64_t)T, nl - t0);
   const uint32_t bsh = L - 1 - l;
-  const uint64_t pmask = (1ull << l) - 1ull;
+  if (tid == 0) s_nseg = 0;
 
-  // 1. load
-  E v[NCH][EV];
+  // 1. load, encode (level 0 of a reduced alphabet), bit words
   const E* in = reinterpret_cast<const E*>(a.in) + t0;
+  uint4 vx[NCH];
 #pragma unroll
   for (int k = 0; k < NCH; ++k) {
     const uint32_t q0 = (uint32_t)(k * kBT + tid) * EV;
-    load16<E>(in, q0, cnt, a.in_vec || (a.in_aligned && q0 + EV <= cnt), v[k]);
-  }
-  if (a.encode) {
-#pragma unroll
-    for (int k = 0; k < NCH; ++k)
+    E v[EV];
+    load16<E>(in, q0, cnt, a.in_vec || (a.in_aligned && q0 + EV <= cnt), v);
+    if (a.encode) {
 #pragma unroll
       for (int e = 0; e < EV; ++e) {
-        uint32_t s = (uint32_t)v[k][e];
+        uint32_t s = (uint32_t)v[e];
         if (s >= a.sigma) s = 0;  // out-of-range input: the build reports an error; keep indices valid
         uint32_t len;
-        v[k][e] = (E)encode_sym(s, a.sigma, L, a.pow2, &len);
+        v[e] = (E)encode_sym(s, a.sigma, L, a.pow2, &len);
       }
+    }
+    __builtin_memcpy(&vx[k], v, 16);
   }
-
-  // 2. bit words
 #pragma unroll
   for (int k = 0; k < NCH; ++k) {
     const uint32_t q0 = (uint32_t)(k * kBT + tid) * EV;
     uint32_t mask = 0;
 #pragma unroll
     for (int e = 0; e < EV; ++e)
-      if (q0 + e < cnt) mask |= (((uint32_t)v[k][e] >> bsh) & 1u) << e;
+      if (q0 + e < cnt) mask |= ((vec_elem<E>(vx[k], e) >> bsh) & 1u) << e;
     uint64_t word = (uint64_t)mask << ((tid % G) * EV);
 #pragma unroll
     for (int off = 1; off < G; off <<= 1) word |= __shfl_xor(word, off, 64);
     if (tid % G == 0) s_words[k * (kBT / G) + tid / G] = word;
   }
-  if (tid == 0) s_words[W] = 0;
   __syncthreads();
 
-  // 3. tile-local rank1 at every word
+  // 2. tile-local rank1 at every word
+  uint32_t tile_ones;
   {
     const uint32_t pc = (tid < (uint32_t)W) ? popc64(s_words[tid]) : 0u;
-    uint32_t tot;
-    const uint32_t ex = block_excl_scan_u32(pc, s_w, tot);
+    const uint32_t ex = block_excl_scan_u32(pc, s_w, tile_ones);
     if (tid < (uint32_t)W) s_wpre[tid] = ex;
-    if (tid == 0) s_wpre[W] = tot;
+    if (tid == 0) {
+      s_wpre[W] = tile_ones;
+      s_words[W] = 0;
+    }
   }
   __syncthreads();
 
-  // 4. bits and directory
-  const uint64_t G1 = a.pre[t];  // ones of the level before the tile
-  const uint64_t G0 = t0 - G1;   // zeros of the level before the tile
+  // 3. bits and directory
+  const uint64_t G0 = t0 - G1;  // zeros of the level before the tile
   if (tid < (uint32_t)W) {
     const uint64_t word = s_words[tid];
     const uint64_t gw = ((uint64_t)t * W) + tid;
@@ -493,10 +619,7 @@ __global__ __launch_bounds__(kBT) void k_level(LevelArgs a) {
     if (q < cnt) {
       const uint64_t ones_before = G1 + s_wpre[tid];
       const uint32_t l2w_shift = a.l2shift - 6;
-      if ((gw & ((1ull << l2w_shift) - 1)) == 0) {
-        const uint64_t l1val = a.pre[t & ~(uint64_t)((kL1Bits / T) - 1)];
-        a.L2[m.l2 + (gw >> l2w_shift)] = (uint16_t)(ones_before - l1val);
-      }
+      if ((gw & ((1ull << l2w_shift) - 1)) == 0) a.L2[m.l2 + (gw >> l2w_shift)] = (uint16_t)(ones_before - l1val);
       const uint32_t sh = a.sshift;
       const uint32_t pc = popc64(word);
       const uint64_t k1 = (ones_before + pc) >> sh;
@@ -514,106 +637,179 @@ __global__ __launch_bounds__(kBT) void k_level(LevelArgs a) {
       }
     }
   }
-  if (tid == 0 && (t0 & (kL1Bits - 1)) == 0) a.L1[m.l1 + (t0 >> kL1Shift)] = G1;
-  if (l + 1 >= L) return;
+  if (tid == 0) {
+    if ((t0 & (kL1Bits - 1)) == 0) a.L1[m.l1 + (t0 >> kL1Shift)] = G1;
+    if (t0 + cnt == nl) {
+      // last tile: total ones and the sentinel L1/L2 entries that make rank defined at i = n_l
+      const uint64_t total = G1 + tile_ones;
+      a.meta[l].ones = total;
+      a.L1[m.l1 + ((nl + kL1Bits - 1) >> kL1Shift)] = total;
+      const uint64_t j = (nl + (1ull << a.l2shift) - 1) >> a.l2shift;
+      const uint64_t blk = (j << a.l2shift) >> kL1Shift;
+      const uint64_t lv = ((blk << kL1Shift) >= nl) ? total : a.pre[blk << (kL1Shift - TL::TSHIFT)];
+      a.L2[m.l2 + j] = (uint16_t)(total - lv);
+    }
+  }
+  if (last) return;
 
-  // 5. stable partition of each node segment of the tile into LDS
+  // 4a. staging
+  const uint32_t nbsh = L - 2 - l;
+  const uint64_t pmask = (1ull << l) - 1ull;
   {
     uint64_t curN = ~0ull;
-    uint32_t base0 = 0, base1 = 0;
+    uint32_t sa = 0, zs = 0, R1a = 0;
 #pragma unroll
     for (int k = 0; k < NCH; ++k) {
       const uint32_t q0 = (uint32_t)(k * kBT + tid) * EV;
-      uint32_t r1 = r1loc(s_words, s_wpre, min(q0, cnt));
+      if (q0 < cnt) {
+        uint32_t r1 = r1loc(s_words, s_wpre, q0);
+        const uint32_t nv = min((uint32_t)EV, cnt - q0);
+        const uint64_t lo = ((uint64_t)vx[k].y << 32) | vx[k].x, hi = ((uint64_t)vx[k].w << 32) | vx[k].z;
+        const uint32_t cf = vec_elem<E>(vx[k], 0), cl = elem128<E>(lo, hi, nv - 1);
+        const uint64_t Nf = l ? ((uint64_t)cf >> (L - l)) & pmask : 0ull;
+        const uint64_t Nl = l ? ((uint64_t)cl >> (L - l)) & pmask : 0ull;
+        if (Nf == Nl) {
+          // the whole vector lies in one node
+          if (Nf != curN) enter_node(a.ntb[Nf], q0, t0, cnt, G0, G1, s_words, s_wpre, s_seg, &s_nseg, sa, zs, R1a), curN = Nf;
+          const uint32_t b0 = R1a, b1 = sa + zs - R1a;  // slot = b0 + rank0 or b1 + rank1 (tile-local)
 #pragma unroll
-      for (int e = 0; e < EV; ++e) {
-        const uint32_t q = q0 + e;
-        if (q >= cnt) continue;
-        const uint32_t code = (uint32_t)v[k][e];
-        const uint32_t b = (code >> bsh) & 1u;
-        const uint64_t N = l ? ((uint64_t)code >> (L - l)) & pmask : 0ull;
-        if (N != curN) {
-          const NodeB nb = a.ntb[N];
-          const uint64_t sa = nb.start > t0 ? min(nb.start - t0, (uint64_t)cnt) : 0ull;
-          const uint64_t sz = nb.end > t0 ? min(nb.end - t0, (uint64_t)cnt) : 0ull;
-          const uint32_t R1a = r1loc(s_words, s_wpre, (uint32_t)sa);
-          const uint32_t R1z = r1loc(s_words, s_wpre, (uint32_t)sz);
-          const uint32_t R0a = (uint32_t)sa - R1a;
-          const uint32_t zs = ((uint32_t)sz - R1z) - R0a;
-          base0 = R1a;
-          base1 = zs + R0a;
-          curN = N;
+          for (int e = 0; e < EV; ++e) {
+            if ((uint32_t)e < nv) {
+              const uint32_t code = vec_elem<E>(vx[k], e);
+              const uint32_t b = (code >> bsh) & 1u;
+              const uint32_t q = q0 + e;
+              const uint32_t slot = b ? b1 + r1 : b0 + (q - r1);
+              s_stage[min(slot, (uint32_t)T - 1u)] = (E)code;
+              r1 += b;
+            }
+          }
+        } else {
+          for (uint32_t e = 0; e < nv; ++e) {
+            const uint32_t code = elem128<E>(lo, hi, e);
+            const uint32_t b = (code >> bsh) & 1u;
+            const uint32_t q = q0 + e;
+            const uint64_t N = l ? ((uint64_t)code >> (L - l)) & pmask : 0ull;
+            if (N != curN) enter_node(a.ntb[N], q, t0, cnt, G0, G1, s_words, s_wpre, s_seg, &s_nseg, sa, zs, R1a), curN = N;
+            const uint32_t slot = b ? sa + zs + (r1 - R1a) : sa + ((q - r1) - (sa - R1a));
+            s_stage[min(slot, (uint32_t)T - 1u)] = (E)code;
+            r1 += b;
+          }
         }
-        uint32_t slot = b ? base1 + r1 : base0 + (q - r1);
-        slot = min(slot, (uint32_t)T - 1u);
-        s_stage[slot] = (E)code;
-        r1 += b;
       }
     }
   }
   __syncthreads();
+  const uint32_t nseg = s_nseg;
+  uint64_t cur_tile = ~0ull;
+  uint32_t cur_c = 0;
+  char* outb = reinterpret_cast<char*>(a.out);
 
-  // 6. write-out in slot order
-  {
-    const uint64_t n_next = a.meta[l + 1].n;
-    const uint32_t nbsh = L - 2 - l;
-    E* out = reinterpret_cast<E*>(a.out);
-    uint64_t curN = ~0ull, D0 = 0, D1 = 0;
-    uint64_t cur_tile = ~0ull;
-    uint32_t cur_c = 0;
+  if (nseg <= (uint32_t)kSegMax) {
+    // 4b. runs (segment, bit) -> their 16-byte destination chunks, prefix over runs
+    {
+      const uint32_t r = tid;
+      uint32_t nch = 0;
+      if (r < 2 * nseg) {
+        const Seg g = s_seg[r >> 1];
+        const uint32_t bb = r & 1u;
+        const uint64_t d = bb ? g.d1 : g.d0;
+        const uint32_t len = d < n_next ? (uint32_t)min<uint64_t>(bb ? g.z - g.a - g.zs : g.zs, n_next - d) : 0u;
+        if (len) nch = (uint32_t)(((d + len - 1) * sizeof(E) >> 4) - ((d * sizeof(E)) >> 4) + 1);
+      }
+      uint32_t total;
+      const uint32_t ex = block_excl_scan_u32(nch, s_w, total);
+      if (r < 2 * nseg) s_cp[r] = ex;
+      if (tid == 0) s_cp[2 * nseg] = total;
+    }
+    __syncthreads();
+    const uint32_t nrun = 2 * nseg;
+    const uint32_t C = s_cp[nrun];
+    const uint32_t* st32 = reinterpret_cast<const uint32_t*>(s_stage);
+    // 4c. write-out: one 16-byte destination chunk per lane
+    for (uint32_t c0 = 0; c0 < C; c0 += kBT) {
+      const uint32_t c = c0 + tid;
+      const bool active = c < C;
+      uint32_t nb1 = 0;
+      uint64_t chunk = 0;
+      if (active) {
+        uint32_t lo = 0, hi = nrun - 1;  // largest run with cp <= c
+        while (lo < hi) {
+          const uint32_t mid = (lo + hi + 1) >> 1;
+          if (s_cp[mid] <= c) lo = mid;
+          else hi = mid - 1;
+        }
+        const Seg g = s_seg[lo >> 1];
+        const uint32_t bb = lo & 1u;
+        const uint64_t d = bb ? g.d1 : g.d0;
+        const uint32_t len = (uint32_t)min<uint64_t>(bb ? g.z - g.a - g.zs : g.zs, n_next - d);
+        const uint32_t slot0 = bb ? g.a + g.zs : g.a;
+        const uint64_t db = d * sizeof(E), de = (d + len) * sizeof(E);
+        chunk = (db >> 4) + (c - s_cp[lo]);
+        const uint64_t cb = chunk << 4;
+        const uint64_t blo = max(db, cb), bhi = min(de, cb + 16);
+        const uint32_t src = slot0 * (uint32_t)sizeof(E) + (uint32_t)(blo - db);  // LDS byte of blo
+        if (blo == cb && bhi == cb + 16) {
+          const uint32_t dw = src >> 2, sh = src & 3u;
+          const uint32_t x0 = st32[dw], x1 = st32[dw + 1], x2 = st32[dw + 2], x3 = st32[dw + 3],
+                         x4 = st32[dw + 4];
+          uint4 y;
+          y.x = __builtin_amdgcn_alignbyte(x1, x0, sh);
+          y.y = __builtin_amdgcn_alignbyte(x2, x1, sh);
+          y.z = __builtin_amdgcn_alignbyte(x3, x2, sh);
+          y.w = __builtin_amdgcn_alignbyte(x4, x3, sh);
+          *reinterpret_cast<uint4*>(outb + cb) = y;
+#pragma unroll
+          for (int e = 0; e < EV; ++e) nb1 += (vec_elem<E>(y, e) >> nbsh) & 1u;
+        } else {
+          const uint32_t s0 = src / (uint32_t)sizeof(E);
+          E* oe = reinterpret_cast<E*>(outb);
+          const uint64_t e0 = blo / sizeof(E), e1 = bhi / sizeof(E);
+          for (uint64_t e = e0; e < e1; ++e) {
+            const E v = s_stage[s0 + (uint32_t)(e - e0)];
+            oe[e] = v;
+            nb1 += ((uint32_t)v >> nbsh) & 1u;
+          }
+        }
+      }
+      const uint64_t dt = (chunk << 4) / ((uint64_t)T * sizeof(E));
+      count_next(__ballot(active), dt, 0u, lane, cur_tile, cur_c, a.cnt_next, nb1);
+    }
+  } else {
+    // 4b'. many small nodes in this tile: element stores in slot order, destination per slot
+    const uint32_t wv = tid >> 6;
     constexpr uint32_t kPerWave = T / (kBT / 64);
-    for (uint32_t j0 = wv * kPerWave; j0 < (wv + 1) * kPerWave; j0 += 64) {
-      if (j0 >= cnt) break;
-      const uint32_t j = j0 + lane;
+    uint64_t curN = ~0ull, D0 = 0, D1 = 0;
+    uint32_t sa = 0, zs = 0;
+    for (uint32_t base = wv * kPerWave; base < (wv + 1) * kPerWave; base += 64) {
+      if (base >= cnt) break;
+      const uint32_t j = base + lane;
       bool cont = false;
       uint64_t dest = 0;
       uint32_t nbit = 0;
       if (j < cnt) {
         const uint32_t code = (uint32_t)s_stage[j];
-        const uint32_t b = (code >> bsh) & 1u;
         const uint64_t N = l ? ((uint64_t)code >> (L - l)) & pmask : 0ull;
         if (N != curN) {
           const NodeB nb = a.ntb[N];
-          const uint64_t sa = nb.start > t0 ? min(nb.start - t0, (uint64_t)cnt) : 0ull;
-          const uint64_t sz = nb.end > t0 ? min(nb.end - t0, (uint64_t)cnt) : 0ull;
-          const uint32_t R1a = r1loc(s_words, s_wpre, (uint32_t)sa);
-          const uint32_t R1z = r1loc(s_words, s_wpre, (uint32_t)sz);
-          const uint32_t R0a = (uint32_t)sa - R1a;
-          const uint32_t zs = ((uint32_t)sz - R1z) - R0a;
-          D0 = nb.off0 + G0 - R1a;
-          D1 = nb.off1 + G1 - (zs + R0a);
+          sa = (uint32_t)(nb.start > t0 ? min(nb.start - t0, (uint64_t)cnt) : 0ull);
+          const uint32_t sz = (uint32_t)(nb.end > t0 ? min(nb.end - t0, (uint64_t)cnt) : 0ull);
+          const uint32_t R1a = r1loc(s_words, s_wpre, sa);
+          zs = (sz - r1loc(s_words, s_wpre, sz)) - (sa - R1a);
+          D0 = nb.off0 + G0 + (sa - R1a);
+          D1 = nb.off1 + G1 + R1a;
           curN = N;
         }
-        dest = (uint64_t)j + (b ? D1 : D0);
+        dest = (j < sa + zs) ? D0 + (j - sa) : D1 + (j - sa - zs);
         cont = dest < n_next;
         if (cont) {
-          out[dest] = (E)code;
+          reinterpret_cast<E*>(outb)[dest] = (E)code;
           nbit = (code >> nbsh) & 1u;
         }
       }
-      // ones of the next level per destination tile; destinations increase with the slot
-      const uint64_t dt = dest >> TL::TSHIFT;
-      uint64_t pend = __ballot(cont);
-      while (pend) {
-        const int leader = __ffsll((unsigned long long)pend) - 1;
-        const uint64_t ldt = __shfl(dt, leader, 64);
-        const bool same = cont && dt == ldt;
-        const uint64_t sm = __ballot(same);
-        const uint32_t c1 = (uint32_t)__popcll(__ballot(same && nbit));
-        if (ldt == cur_tile) {
-          cur_c += c1;
-        } else {
-          if (cur_tile != ~0ull && cur_c && lane == 0)
-            atomicAdd((unsigned long long*)&a.cnt_next[cur_tile], (unsigned long long)cur_c);
-          cur_tile = ldt;
-          cur_c = c1;
-        }
-        pend &= ~sm;
-      }
+      count_next(__ballot(cont), dest >> TL::TSHIFT, nbit, lane, cur_tile, cur_c, a.cnt_next, 0u);
     }
-    if (cur_tile != ~0ull && cur_c && lane == 0)
-      atomicAdd((unsigned long long*)&a.cnt_next[cur_tile], (unsigned long long)cur_c);
   }
+  if (lane == 0 && cur_c) atomicAdd((unsigned long long*)&a.cnt_next[cur_tile], (unsigned long long)cur_c);
 }
 
 // ---------------------------------------------------------------- host orchestration
@@ -673,8 +869,8 @@ hipError_t launch_hist(const void* d_sym, uint64_t n, uint32_t sigma, uint32_t L
   const uint32_t grid = (uint32_t)std::min<uint64_t>(ntiles, 2048);
   const uint32_t aligned = ((uintptr_t)d_sym & 15u) == 0;
   if (sigma <= 16384) {
-    const uint32_t nrep = std::max<uint32_t>(1u, std::min<uint32_t>(32u, 16384u / sigma));
-    const size_t lds = (size_t)nrep * sigma * sizeof(uint32_t);
+    const uint32_t nrep = std::max<uint32_t>(1u, std::min<uint32_t>(32u, 16383u / (sigma + 1)));
+    const size_t lds = (size_t)nrep * (sigma + 1) * sizeof(uint32_t);
     hipLaunchKernelGGL((k_hist<E, true>), dim3(grid), dim3(kBT), lds, st, (const E*)d_sym, n, sigma, L, pow2,
                        aligned, nrep, hist, cnt0, err);
   } else {
@@ -820,7 +1016,9 @@ extern "C" wt_status wt_build(const void* d_sym, uint64_t n, uint32_t sym_bytes,
   const size_t o_seq0 = take(L > 1 ? seq_elems * sym_bytes : 0);
   const size_t o_seq1 = take(L > 2 ? seq_elems * sym_bytes : 0);
   const size_t o_hist = take(hist_n * 8);
-  const size_t o_cnt = take((size_t)std::max<uint32_t>(L, 1) * (ntiles + 1) * 8);
+  const uint64_t nchunks = ceil_div(ntiles, kChunkTiles);
+  const uint64_t cstride = (ntiles + 1) + (nchunks + 1);  // per level: tile counts, then chunk counts
+  const size_t o_cnt = take((size_t)std::max<uint32_t>(L, 1) * cstride * 8);
   const size_t o_pre = take((size_t)std::max<uint32_t>(L, 1) * (ntiles + 1) * 8);
   const size_t o_ntb = take(std::max<uint64_t>(P.nheap, 1) * sizeof(NodeB));
   const size_t o_z = take((P.nheap + 1) * 8);
@@ -870,7 +1068,7 @@ extern "C" wt_status wt_build(const void* d_sym, uint64_t n, uint32_t sym_bytes,
   WT_STEP(prof.begin("init", -1));
   hipLaunchKernelGGL(k_init_meta, dim3(1), dim3(64), 0, st, ia, t->dev.meta);
   hipLaunchKernelGGL(k_fill_u64, dim3(64), dim3(kBT), 0, st, hist, hist_n, 0ull);
-  hipLaunchKernelGGL(k_fill_u64, dim3(256), dim3(kBT), 0, st, tcnt, (uint64_t)std::max<uint32_t>(L, 1) * (ntiles + 1),
+  hipLaunchKernelGGL(k_fill_u64, dim3(256), dim3(kBT), 0, st, tcnt, (uint64_t)std::max<uint32_t>(L, 1) * cstride,
                      0ull);
   hipLaunchKernelGGL(k_fill_u64, dim3(1), dim3(64), 0, st, (uint64_t*)err, 8ull, 0ull);
   WT_STEP(hipGetLastError());
@@ -907,11 +1105,14 @@ extern "C" wt_status wt_build(const void* d_sym, uint64_t n, uint32_t sym_bytes,
   while ((1u << tshift) < T) ++tshift;
 
   for (uint32_t l = 0; l < L; ++l) {
-    uint64_t* cnt_l = tcnt + (size_t)l * (ntiles + 1);
+    uint64_t* cnt_l = tcnt + (size_t)l * cstride;
+    uint64_t* chunk_l = cnt_l + ntiles + 1;
     uint64_t* pre_l = tpre + (size_t)l * (ntiles + 1);
     WT_STEP(prof.begin("tile_scan", (int)l));
-    hipLaunchKernelGGL(k_tile_scan, dim3(1), dim3(1024), 0, st, t->dev.meta, l, tshift, (const uint64_t*)cnt_l, pre_l,
-                       t->dev.L1, t->dev.L2, l2shift);
+    hipLaunchKernelGGL(k_tile_reduce, dim3((uint32_t)nchunks), dim3(kBT), 0, st, (const LevelMeta*)t->dev.meta, l,
+                       tshift, (const uint64_t*)cnt_l, chunk_l);
+    hipLaunchKernelGGL(k_tile_scan, dim3((uint32_t)(nchunks + 1)), dim3(kBT), 0, st, t->dev.meta, l, tshift,
+                       (const uint64_t*)cnt_l, (const uint64_t*)chunk_l, pre_l, t->dev.L1, t->dev.L2);
     WT_STEP(hipGetLastError());
     WT_STEP(prof.end());
     LevelArgs a{};
@@ -923,7 +1124,7 @@ extern "C" wt_status wt_build(const void* d_sym, uint64_t n, uint32_t sym_bytes,
     a.smp = t->dev.smp;
     a.meta = t->dev.meta;
     a.pre = pre_l;
-    a.cnt_next = (l + 1 < L) ? tcnt + (size_t)(l + 1) * (ntiles + 1) : nullptr;
+    a.cnt_next = (l + 1 < L) ? tcnt + (size_t)(l + 1) * cstride : nullptr;
     a.ntb = ntb + ((1ull << l) - 1);
     a.l = l;
     a.L = L;

@@ -49,7 +49,8 @@ struct TreePlan {
 
 TreePlan plan_tree(uint64_t n, uint32_t w, uint64_t sigma, uint32_t L, uint32_t l2_bits, uint32_t srate);
 
-// Tile (elements per level-kernel block) for a symbol width.
-inline uint32_t tile_elems(uint32_t w) { return 16384u / w; }
+// Bytes of the level sequence one level-kernel block handles; a tile holds kTileBytes / w elements.
+constexpr uint32_t kTileBytes = 8192;
+inline uint32_t tile_elems(uint32_t w) { return kTileBytes / w; }
 
 }  // namespace wt
