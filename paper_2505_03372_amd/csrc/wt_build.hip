@@ -39,7 +39,7 @@ struct Tile {
   static constexpr int T = kBT * NCH * EV;               // elements per tile
   static constexpr int W = T / 64;                       // bit words per tile
   static constexpr int G = 64 / EV;                      // lanes whose vectors form one word
-  static constexpr int TSHIFT = sizeof(E) == 1 ? 13 : (sizeof(E) == 2 ? 12 : 11);
+  static constexpr int TSHIFT = __builtin_ctz((unsigned)T);
   static_assert((1 << TSHIFT) == T, "tile");
   static_assert(T % 512 == 0 && kL1Bits % T == 0, "tiles cover whole L2 blocks and divide L1 blocks");
 };
@@ -546,6 +546,9 @@ __global__ __launch_bounds__(kBT) void k_level(LevelArgs a) {
   __shared__ Seg s_seg[kSegMax];
   __shared__ uint32_t s_cp[2 * kSegMax + 1];
   __shared__ uint32_t s_nseg;
+  __shared__ uint64_t s_node[2];  // node of the tile's first and last element
+  __shared__ uint64_t s_dst[2];   // single-node tile: destinations of its first zero and first one
+  __shared__ uint32_t s_nc[4];    // single-node tile: next-level ones per (run, destination tile)
 
   const uint32_t tid = threadIdx.x, lane = tid & 63u;
   const uint32_t l = a.l, L = a.L;
@@ -593,8 +596,22 @@ __global__ __launch_bounds__(kBT) void k_level(LevelArgs a) {
 #pragma unroll
     for (int off = 1; off < G; off <<= 1) word |= __shfl_xor(word, off, 64);
     if (tid % G == 0) s_words[k * (kBT / G) + tid / G] = word;
+    if (q0 < cnt && q0 + EV > cnt - 1) {
+      const uint32_t cx = elem128<E>(((uint64_t)vx[k].y << 32) | vx[k].x, ((uint64_t)vx[k].w << 32) | vx[k].z,
+                                     cnt - 1 - q0);
+      s_node[1] = l ? ((uint64_t)cx >> (L - l)) & ((1ull << l) - 1ull) : 0ull;
+    }
+    if (q0 == 0) s_node[0] = l ? ((uint64_t)vec_elem<E>(vx[k], 0) >> (L - l)) & ((1ull << l) - 1ull) : 0ull;
   }
+  if (tid < 4) s_nc[tid] = 0;
   __syncthreads();
+  // a tile inside one node (the rule at shallow levels) takes the fast path: two runs, no segments
+  const bool single = s_node[0] == s_node[1];
+  if (single && !last && tid == 0) {
+    const NodeB nb = a.ntb[s_node[0]];
+    s_dst[0] = nb.off0 + (t0 - G1);
+    s_dst[1] = nb.off1 + G1;
+  }
 
   // 2. tile-local rank1 at every word
   uint32_t tile_ones;
@@ -655,6 +672,97 @@ __global__ __launch_bounds__(kBT) void k_level(LevelArgs a) {
   // 4a. staging
   const uint32_t nbsh = L - 2 - l;
   const uint64_t pmask = (1ull << l) - 1ull;
+  if (single) {
+    // zeros fill slots [0, Z), ones [Z, cnt)
+    const uint32_t Z = cnt - tile_ones;
+#pragma unroll 1
+    for (int k = 0; k < NCH; ++k) {
+      const uint32_t q0 = (uint32_t)(k * kBT + tid) * EV;
+      if (q0 < cnt) {
+        // vector k without indexed access (an indexed register array would go to scratch)
+        uint4 x = vx[0];
+#pragma unroll
+        for (int kk = 1; kk < NCH; ++kk)
+          if (k == kk) x = vx[kk];
+        uint32_t r1 = r1loc(s_words, s_wpre, q0);
+        uint32_t r0 = q0 - r1;
+        const uint32_t nv = min((uint32_t)EV, cnt - q0);
+#pragma unroll
+        for (int e = 0; e < EV; ++e) {
+          if ((uint32_t)e < nv) {
+            const uint32_t code = vec_elem<E>(x, e);
+            const uint32_t b = (code >> bsh) & 1u;
+            s_stage[b ? Z + r1 : r0] = (E)code;
+            r1 += b;
+            r0 += 1u - b;
+          }
+        }
+      }
+    }
+    __syncthreads();
+    // 4b. write-out of the two runs, one 16-byte destination chunk per lane; the next level's ones
+    //     are counted per (run, destination tile): a run of at most T elements touches two tiles
+    const uint64_t d0 = s_dst[0], d1 = s_dst[1];
+    char* outb = reinterpret_cast<char*>(a.out);
+    const uint32_t* st32 = reinterpret_cast<const uint32_t*>(s_stage);
+    const uint32_t len0 = d0 < n_next ? (uint32_t)min<uint64_t>(Z, n_next - d0) : 0u;
+    const uint32_t len1 = d1 < n_next ? (uint32_t)min<uint64_t>(cnt - Z, n_next - d1) : 0u;
+    const uint32_t C0 = len0 ? (uint32_t)(((d0 + len0 - 1) * sizeof(E) >> 4) - ((d0 * sizeof(E)) >> 4) + 1) : 0u;
+    const uint32_t C1 = len1 ? (uint32_t)(((d1 + len1 - 1) * sizeof(E) >> 4) - ((d1 * sizeof(E)) >> 4) + 1) : 0u;
+    constexpr uint32_t kTileB = (uint32_t)T * (uint32_t)sizeof(E);  // bytes of a destination tile
+    uint32_t cnt4[4] = {0u, 0u, 0u, 0u};                          // (run, first / second tile)
+    for (uint32_t c = tid; c < C0 + C1; c += kBT) {
+      const bool bb = c >= C0;
+      const uint64_t d = bb ? d1 : d0;
+      const uint32_t len = bb ? len1 : len0;
+      const uint32_t slot0 = bb ? Z : 0u;
+      const uint64_t db = d * sizeof(E), de = (d + len) * sizeof(E);
+      const uint64_t cb = ((db >> 4) + (bb ? c - C0 : c)) << 4;
+      const uint64_t blo = max(db, cb), bhi = min(de, cb + 16);
+      const uint32_t src = slot0 * (uint32_t)sizeof(E) + (uint32_t)(blo - db);
+      uint32_t nb = 0;
+      if (blo == cb && bhi == cb + 16) {
+        const uint32_t dw = src >> 2, sh = src & 3u;
+        const uint32_t x0 = st32[dw], x1 = st32[dw + 1], x2 = st32[dw + 2], x3 = st32[dw + 3], x4 = st32[dw + 4];
+        uint4 y;
+        y.x = __builtin_amdgcn_alignbyte(x1, x0, sh);
+        y.y = __builtin_amdgcn_alignbyte(x2, x1, sh);
+        y.z = __builtin_amdgcn_alignbyte(x3, x2, sh);
+        y.w = __builtin_amdgcn_alignbyte(x4, x3, sh);
+        *reinterpret_cast<uint4*>(outb + cb) = y;
+        // next-level bits of the 16/w elements: one bit per element, popcount per dword
+        constexpr uint32_t kLow = sizeof(E) == 1 ? 0x01010101u : (sizeof(E) == 2 ? 0x00010001u : 1u);
+        nb = __popc((y.x >> nbsh) & kLow) + __popc((y.y >> nbsh) & kLow) + __popc((y.z >> nbsh) & kLow) +
+             __popc((y.w >> nbsh) & kLow);
+      } else {
+        const uint32_t s0 = src / (uint32_t)sizeof(E);
+        E* oe = reinterpret_cast<E*>(outb);
+        const uint64_t e0 = blo / sizeof(E), e1 = bhi / sizeof(E);
+        for (uint64_t e = e0; e < e1; ++e) {
+          const E v = s_stage[s0 + (uint32_t)(e - e0)];
+          oe[e] = v;
+          nb += ((uint32_t)v >> nbsh) & 1u;
+        }
+      }
+      const uint32_t sub = (uint32_t)(cb / kTileB - db / kTileB);  // 0 or 1
+      cnt4[(bb ? 2 : 0) + sub] += nb;
+    }
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      uint32_t v = cnt4[r];
+#pragma unroll
+      for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+      if (lane == 0 && v) atomicAdd(&s_nc[r], v);
+    }
+    __syncthreads();
+    if (tid < 4) {
+      const uint32_t c = s_nc[tid];
+      const uint64_t d = (tid < 2) ? d0 : d1;
+      if (c && d < n_next)
+        atomicAdd((unsigned long long*)&a.cnt_next[(d >> TL::TSHIFT) + (tid & 1u)], (unsigned long long)c);
+    }
+    return;
+  }
   {
     uint64_t curN = ~0ull;
     uint32_t sa = 0, zs = 0, R1a = 0;

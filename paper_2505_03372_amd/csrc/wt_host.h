@@ -50,7 +50,7 @@ struct TreePlan {
 TreePlan plan_tree(uint64_t n, uint32_t w, uint64_t sigma, uint32_t L, uint32_t l2_bits, uint32_t srate);
 
 // Bytes of the level sequence one level-kernel block handles; a tile holds kTileBytes / w elements.
-constexpr uint32_t kTileBytes = 8192;
+constexpr uint32_t kTileBytes = 16384;
 inline uint32_t tile_elems(uint32_t w) { return kTileBytes / w; }
 
 }  // namespace wt
