@@ -4,13 +4,14 @@
 
 One step = one pass of the whole hot path over one batch of synthetic input already resident in
 HBM: build the level-wise wavelet tree of n symbols (histogram, node tables, every level's bits,
-rank directory, select samples and partition), then answer q access, q rank and q select queries,
-then free the tree. Default workload: n = 2^30 u8 symbols, alphabet 256, Zipf(1.0) frequencies over
+rank directory, select samples and partition), train its learned select index, answer q access,
+q rank, q select and q learned-select queries, then free the tree. Default workload: n = 2^30 u8 symbols, alphabet 256, Zipf(1.0) frequencies over
 a seeded permutation, q = 2^26 queries of each kind.
 
 Prints one JSON line. `value` is (symbols built + queries answered) per second over the timed
-steps; the per-part rates are in `rates`. `roofline` covers the dominant kernel (the level pass),
-timed with HIP events recorded by the library around every level launch on the build stream.
+steps; the per-part rates are in `rates`. `roofline` covers the kernel with the most time in a
+step; `roofline_build` the build's level pass, timed with HIP events recorded by the library
+around every level launch on the build stream.
 `cpu_baseline` times the plain CPU oracle on a bounded prefix of the same workload.
 """
 from __future__ import annotations
@@ -96,6 +97,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="text_zipf")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-learned", action="store_true", help="skip the learned select index (training + queries)")
     ap.add_argument("--cpu-sample-log2", type=int, default=25)
     ap.add_argument("--cpu-queries-log2", type=int, default=20)
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -128,7 +130,8 @@ def main():
         kinds["select"] = (torch.from_numpy(wl.sel_c).to(dev), torch.from_numpy(wl.sel_k).to(dev))
     outs = {"access": torch.empty(q, dtype=torch.uint32, device=dev),
             "rank": torch.empty(q, dtype=torch.uint64, device=dev),
-            "select": torch.empty(q, dtype=torch.uint64, device=dev)}
+            "select": torch.empty(q, dtype=torch.uint64, device=dev),
+            "select_learned": torch.empty(q, dtype=torch.uint64, device=dev)}
     del wl
     torch.cuda.synchronize()
     print("# workload resident in HBM", file=sys.stderr, flush=True)
@@ -138,20 +141,26 @@ def main():
     def step(record):
         t = wt.build(S, sigma, profile=True)
         evs = {}
+        linfo = None
+        if "select" in kinds and not args.no_learned:
+            linfo = t.learn_select()
         for kind, a in kinds.items():
-            e0 = torch.cuda.Event(enable_timing=True)
-            e1 = torch.cuda.Event(enable_timing=True)
-            e0.record(stream)
-            if kind == "access":
-                t.access(a[0], out=outs[kind])
-            elif kind == "rank":
-                t.rank(a[0], a[1], out=outs[kind])
-            else:
-                t.select(a[0], a[1], out=outs[kind])
-            e1.record(stream)
-            evs[kind] = (e0, e1)
+            for variant in (("plain", "learned") if kind == "select" and linfo is not None else ("plain",)):
+                e0 = torch.cuda.Event(enable_timing=True)
+                e1 = torch.cuda.Event(enable_timing=True)
+                e0.record(stream)
+                if kind == "access":
+                    t.access(a[0], out=outs[kind])
+                elif kind == "rank":
+                    t.rank(a[0], a[1], out=outs[kind])
+                elif variant == "plain":
+                    t.select(a[0], a[1], out=outs[kind])
+                else:
+                    t.select_learned(a[0], a[1], out=outs["select_learned"])
+                e1.record(stream)
+                evs[kind if variant == "plain" else "select_learned"] = (e0, e1)
         if record is not None:
-            record.append((t.profile(), evs, t.info))
+            record.append((t.profile(), evs, t.info, linfo))
         t.free()
 
     for _ in range(args.warmup):
@@ -166,28 +175,52 @@ def main():
     ms_per_step = (t1 - t0) * 1e3 / args.steps
 
     info = recs[0][2]
-    level_ms, build_ms, qms = [], [], {k: [] for k in kinds}
-    for prof, evs, _ in recs:
+    level_ms, build_ms, learn_ms = [], [], []
+    qms = {}
+    for prof, evs, _, linfo in recs:
         level_ms += [p["ms"] for p in prof if p["kernel"] == "level"]
         build_ms.append(sum(p["ms"] for p in prof))
+        if linfo is not None:
+            learn_ms.append(linfo["train_ms"])
         for k, (e0, e1) in evs.items():
-            qms[k].append(e0.elapsed_time(e1))
+            qms.setdefault(k, []).append(e0.elapsed_time(e1))
     per_launch = level_launch_bytes(info, width)
     avg_bytes = float(np.mean(per_launch))
     avg_ms = float(np.mean(level_ms))
     achieved = avg_bytes / (avg_ms * 1e-3) / 1e9
-    items = n + sum(q for _ in kinds)
+    items = n + q * len(qms)
     rates = {"build_symbols_per_s": n / (np.median(build_ms) * 1e-3)}
-    for k in kinds:
+    for k in qms:
         rates[k + "_queries_per_s"] = q / (np.median(qms[k]) * 1e-3)
     rates["build_ms_median"] = float(np.median(build_ms))
-    for k in kinds:
+    if learn_ms:
+        rates["learn_train_ms_median"] = float(np.median(learn_ms))
+        li = recs[0][3]
+        rates["learned_models"] = li["models"]
+        rates["learned_mean_err_blocks"] = li["mean_err_blocks"]
+        rates["untrained_mean_err_blocks"] = li["mean_err_init_blocks"]
+        rates["learned_vs_plain_select_speedup"] = float(np.median(qms["select"]) / np.median(qms["select_learned"]))
+    for k in qms:
         rates[k + "_ms_median"] = float(np.median(qms[k]))
-    roof = {"kernel": "k_level<uint8_t>" if width == 1 else ("k_level<uint16_t>" if width == 2 else
-                                                            "k_level<uint32_t>"),
-            "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": achieved / HBM_PEAK_GBS, "traffic": load_traffic(avg_bytes),
-            "bytes_per_launch": avg_bytes, "avg_launch_ms": avg_ms, "launches": len(level_ms)}
+    kname = {1: "k_level<uint8_t>", 2: "k_level<uint16_t>", 4: "k_level<uint32_t>"}[width]
+    build_roof = {"kernel": kname, "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                  "frac": achieved / HBM_PEAK_GBS, "traffic": load_traffic(avg_bytes),
+                  "bytes_per_launch": avg_bytes, "avg_launch_ms": avg_ms, "launches": len(level_ms)}
+    # the kernel with the most time in a step: queries touch at least one 64-byte L2 block of bits per
+    # level (random HBM lines), the level pass streams its level
+    per_step = {k: float(np.median(v)) for k, v in qms.items()}
+    per_step["level"] = avg_ms * info["levels"]
+    dom = max(per_step, key=per_step.get)
+    if dom == "level":
+        roof = build_roof
+    else:
+        qbytes = 64.0 * info["levels"] * q
+        qa = qbytes / (per_step[dom] * 1e-3) / 1e9
+        roof = {"kernel": {"access": "k_access", "rank": "k_rank", "select": "k_select",
+                           "select_learned": "k_select_learned"}[dom] + "<9>",
+                "bound": "hbm", "achieved": qa, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": qa / HBM_PEAK_GBS,
+                "traffic": None, "bytes_per_launch": qbytes, "avg_launch_ms": per_step[dom], "launches": len(qms[dom]),
+                "note": "random access: 64 B (one L2 block of bits) per level per query"}
     line = {
         "metric": "build symbols/s + access/rank/select queries/s; learned vs plain select",
         "value": items / (ms_per_step * 1e-3),
@@ -205,6 +238,7 @@ def main():
                    "query_kinds": list(kinds), "l2_bits": 512, "sample_rate": 4096},
         "rates": rates,
         "roofline": roof,
+        "roofline_build": build_roof,
     }
     if args.calibrate_copy:
         src = torch.empty(1 << 30, dtype=torch.uint8, device=dev)

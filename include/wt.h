@@ -153,6 +153,54 @@ typedef struct {
 /* Copies up to cap entries; *count receives the number available. */
 wt_status wt_build_profile(const wt_tree* t, wt_prof_entry* out, uint32_t cap, uint32_t* count);
 
+/* ---- learned select index (spec extension of Section 5.4; not in the thesis) ----
+ *
+ * For every child node of the tree (a node's zeros side or ones side at some level) a small FP32
+ * network u -> 1 -> 16 -> 1 (ReLU) -> v maps the node-local occurrence rank of a bit (u in [0, 1],
+ * normalised by the child's size) to its position inside the node (v in [0, 1]). It is trained on
+ * the GPU, by full-batch Adam on the build's own rank directory (the node-local rank at the start of
+ * every |L2| block inside the node, subsampled), with the library's own forward and backward kernels.
+ * A learned select then predicts the L2 block of each level's target, corrects the prediction
+ * exactly by galloping over the L2 counts within a budget derived from the model's measured error,
+ * and falls back to the plain sampled binary search (Algorithm 2) when the budget is exhausted.
+ * Answers are identical to wt_select.
+ */
+typedef struct {
+  uint32_t epochs;     /* Adam steps (full batch); 0 = 500 */
+  uint32_t max_points; /* training points per model, <= 2048; 0 = 2048 */
+  float lr;            /* initial learning rate (linear decay to lr/10); 0 = 3e-3 */
+  uint32_t flags;      /* reserved */
+} wt_learn_opts;
+
+typedef struct {
+  uint32_t models;             /* child nodes with a trained model */
+  uint32_t params_per_model;   /* 49 */
+  double mean_err_blocks;      /* mean |predicted - true| L2 block over every L2 boundary of every node */
+  double max_err_blocks;
+  double mean_err_init_blocks; /* same for the untrained starting point (the linear map v = u) */
+  double max_err_init_blocks;
+  double final_loss_mean;      /* mean over models of the final training loss */
+  float train_ms;              /* duration of the training kernels (HIP events) */
+  uint32_t reserved;
+} wt_learned_info_t;
+
+/* Trains (or retrains) the models of a tree; enqueued on `stream`, waits for completion. */
+wt_status wt_learn_select(wt_tree* t, const wt_learn_opts* opts, wt_stream_t stream);
+
+/* Batched select through the learned index (same arguments and results as wt_select).
+   WT_ERR_STATE if wt_learn_select has not been called on the tree. */
+wt_status wt_select_learned(const wt_tree* t, const uint32_t* d_sym, const uint64_t* d_k, uint64_t q,
+                            uint64_t* d_out, wt_stream_t stream);
+
+wt_status wt_learned_info(const wt_tree* t, wt_learned_info_t* out);
+
+/* One evaluation of the training objective on the device, with the same device code the training
+   kernel uses: d_out[0] = mean squared error of the network d_params (49 floats: w1[16], b1[16],
+   w2[16], b2) over the P points (d_u[i], d_v[i]); d_out[1 + j] = its derivative by parameter j.
+   For gradient checks against a reference. */
+wt_status wt_mlp_loss_grad(const float* d_params, const float* d_u, const float* d_v, uint32_t P, float* d_out,
+                           wt_stream_t stream);
+
 /* Thread-local description of the last failure on this thread ("" if none). */
 const char* wt_last_error(void);
 

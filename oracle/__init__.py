@@ -62,6 +62,11 @@ def lib():
                                   ctypes.c_uint64, _u64p]
         L.oracle_select.argtypes = [ctypes.c_void_p, ctypes.c_uint64, ctypes.c_int, ctypes.c_uint64, _u32p, _u64p,
                                     ctypes.c_uint64, _u64p]
+        _f64p = ctypes.POINTER(ctypes.c_double)
+        L.oracle_mlp_forward.restype = ctypes.c_double
+        L.oracle_mlp_forward.argtypes = [_f64p, ctypes.c_double]
+        L.oracle_mlp_loss_grad.restype = ctypes.c_double
+        L.oracle_mlp_loss_grad.argtypes = [_f64p, _f64p, _f64p, ctypes.c_int, _f64p]
         _lib = L
     return _lib
 
@@ -184,6 +189,37 @@ def select(S: np.ndarray, sigma: int, c: np.ndarray, k: np.ndarray) -> np.ndarra
     lib().oracle_select(ctypes.c_void_p(S.ctypes.data), S.size, S.dtype.itemsize, sigma, _p(c, _u32p),
                         _p(k, _u64p), c.size, _p(out, _u64p))
     return out
+
+
+# ---- learned select predictor (FP64 reference of the 1 -> 16 -> 1 ReLU network) ----
+
+MLP_PARAMS = 49
+
+
+def mlp_init() -> np.ndarray:
+    """The starting point of training: y = relu(u) = u on [0, 1] (w1 = 1, b1_k = -k/16, w2 = e_0, b2 = 0)."""
+    th = np.zeros(MLP_PARAMS, dtype=np.float64)
+    th[0:16] = 1.0
+    th[16:32] = -np.arange(16) / 16.0
+    th[32] = 1.0
+    return th
+
+
+def mlp_forward(theta, u) -> np.ndarray:
+    th = np.ascontiguousarray(theta, dtype=np.float64)
+    p = th.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+    return np.array([lib().oracle_mlp_forward(p, float(x)) for x in np.atleast_1d(u)])
+
+
+def mlp_loss_grad(theta, u, v):
+    th = np.ascontiguousarray(theta, dtype=np.float64)
+    u = np.ascontiguousarray(u, dtype=np.float64)
+    v = np.ascontiguousarray(v, dtype=np.float64)
+    g = np.zeros(MLP_PARAMS, dtype=np.float64)
+    f = ctypes.POINTER(ctypes.c_double)
+    loss = lib().oracle_mlp_loss_grad(th.ctypes.data_as(f), u.ctypes.data_as(f), v.ctypes.data_as(f), u.size,
+                                      g.ctypes.data_as(f))
+    return loss, g
 
 
 # ---- pure-Python brute force (tiny inputs only) ----

@@ -278,3 +278,42 @@ void oracle_select(const void* S, uint64_t n, int w, uint64_t sigma, const uint3
   }
   free(head); free(endq); free(cnt); free(e);
 }
+
+/* ---- learned select predictor: 1 -> 16 -> 1 ReLU network, FP64 reference ----
+ * Parameters theta[49]: w1[16], b1[16], w2[16], b2.
+ *   h_k = w1_k u + b1_k,  a_k = max(h_k, 0),  y = sum_k w2_k a_k + b2.
+ * Loss over P points: L = (1/P) sum_i (y_i - v_i)^2. The ReLU derivative at 0 is taken as 0.
+ */
+#define MLP_H 16
+
+double oracle_mlp_forward(const double* th, double u) {
+  double y = th[48];
+  for (int k = 0; k < MLP_H; ++k) {
+    double h = th[k] * u + th[16 + k];
+    if (h > 0) y += th[32 + k] * h;
+  }
+  return y;
+}
+
+/* Loss and its gradient with respect to the 49 parameters (grad may be NULL). */
+double oracle_mlp_loss_grad(const double* th, const double* u, const double* v, int P, double* grad) {
+  double loss = 0;
+  if (grad) memset(grad, 0, 49 * sizeof(double));
+  for (int i = 0; i < P; ++i) {
+    double y = oracle_mlp_forward(th, u[i]);
+    double r = y - v[i];
+    loss += r * r;
+    if (!grad) continue;
+    double g = 2.0 * r / P;
+    grad[48] += g;
+    for (int k = 0; k < MLP_H; ++k) {
+      double h = th[k] * u[i] + th[16 + k];
+      if (h > 0) {
+        grad[32 + k] += g * h;
+        grad[k] += g * th[32 + k] * u[i];
+        grad[16 + k] += g * th[32 + k];
+      }
+    }
+  }
+  return loss / P;
+}

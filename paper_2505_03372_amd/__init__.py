@@ -32,7 +32,9 @@ U64_MAX = (1 << 64) - 1
 
 # names declared by include/wt.h
 ABI_FUNCTIONS = ("wt_set_allocator", "wt_build", "wt_free", "wt_access", "wt_rank", "wt_select", "wt_info",
-                 "wt_export", "wt_build_profile", "wt_last_error", "wt_version")
+                 "wt_export", "wt_build_profile", "wt_last_error", "wt_version", "wt_learn_select",
+                 "wt_select_learned", "wt_learned_info", "wt_mlp_loss_grad")
+MLP_PARAMS = 49
 
 
 class WTLibraryMissing(RuntimeError):
@@ -56,6 +58,18 @@ class Info(ctypes.Structure):
                 ("level_n", ctypes.c_uint64 * MAX_LEVELS), ("level_ones", ctypes.c_uint64 * MAX_LEVELS),
                 ("bytes_bits", ctypes.c_uint64), ("bytes_l1", ctypes.c_uint64), ("bytes_l2", ctypes.c_uint64),
                 ("bytes_samples", ctypes.c_uint64), ("bytes_nodes", ctypes.c_uint64), ("bytes_total", ctypes.c_uint64)]
+
+
+class LearnOpts(ctypes.Structure):
+    _fields_ = [("epochs", ctypes.c_uint32), ("max_points", ctypes.c_uint32), ("lr", ctypes.c_float),
+                ("flags", ctypes.c_uint32)]
+
+
+class LearnedInfo(ctypes.Structure):
+    _fields_ = [("models", ctypes.c_uint32), ("params_per_model", ctypes.c_uint32),
+                ("mean_err_blocks", ctypes.c_double), ("max_err_blocks", ctypes.c_double),
+                ("mean_err_init_blocks", ctypes.c_double), ("max_err_init_blocks", ctypes.c_double),
+                ("final_loss_mean", ctypes.c_double), ("train_ms", ctypes.c_float), ("reserved", ctypes.c_uint32)]
 
 
 class ProfEntry(ctypes.Structure):
@@ -96,6 +110,14 @@ def lib():
     L.wt_version.argtypes = []
     L.wt_set_allocator.restype = ctypes.c_int
     L.wt_set_allocator.argtypes = [vp, vp, vp]
+    L.wt_learn_select.restype = ctypes.c_int
+    L.wt_learn_select.argtypes = [vp, ctypes.POINTER(LearnOpts), vp]
+    L.wt_select_learned.restype = ctypes.c_int
+    L.wt_select_learned.argtypes = [vp, vp, vp, u64, vp, vp]
+    L.wt_learned_info.restype = ctypes.c_int
+    L.wt_learned_info.argtypes = [vp, ctypes.POINTER(LearnedInfo)]
+    L.wt_mlp_loss_grad.restype = ctypes.c_int
+    L.wt_mlp_loss_grad.argtypes = [vp, vp, vp, u32, vp, vp]
     _lib = L
     return L
 
@@ -199,6 +221,28 @@ class Tree:
                                _dev_ptr(out, torch.uint64, "out"), ctypes.c_void_p(_stream_handle(stream))))
         return out
 
+    def learn_select(self, epochs: int = 0, max_points: int = 0, lr: float = 0.0, stream=None) -> dict:
+        """Train the learned select index of this tree on the GPU; returns its statistics."""
+        opts = LearnOpts(epochs, max_points, lr, 0)
+        _check(lib().wt_learn_select(self._h, ctypes.byref(opts), ctypes.c_void_p(_stream_handle(stream))))
+        return self.learned_info()
+
+    def learned_info(self) -> dict:
+        inf = LearnedInfo()
+        _check(lib().wt_learned_info(self._h, ctypes.byref(inf)))
+        return {f: getattr(inf, f) for f, _ in LearnedInfo._fields_ if f != "reserved"}
+
+    def select_learned(self, sym, k, out=None, stream=None):
+        torch = _torch()
+        q = k.numel()
+        if sym.numel() != q:
+            raise ValueError("sym and k must have the same length")
+        if out is None:
+            out = torch.empty(q, dtype=torch.uint64, device=k.device)
+        _check(lib().wt_select_learned(self._h, _dev_ptr(sym, torch.uint32, "sym"), _dev_ptr(k, torch.uint64, "k"), q,
+                                       _dev_ptr(out, torch.uint64, "out"), ctypes.c_void_p(_stream_handle(stream))))
+        return out
+
     def export(self, part: int, level: int = 0) -> np.ndarray:
         need = ctypes.c_size_t(0)
         _check(lib().wt_export(self._h, level, part, None, 0, ctypes.byref(need)))
@@ -239,6 +283,18 @@ def build(sym, sigma: int, l2_bits: int = 512, sample_rate: int = 4096, profile:
     _check(lib().wt_build(ctypes.c_void_p(sym.data_ptr() if sym.numel() else 0), sym.numel(), dts[sym.dtype], sigma,
                           ctypes.byref(opts), ctypes.c_void_p(_stream_handle(stream)), ctypes.byref(h)))
     return Tree(h.value)
+
+
+def mlp_loss_grad(params, u, v, stream=None):
+    """Loss and gradient of the learned-select network on the device (the training kernel's code):
+    returns a float32 tensor [loss, d loss / d param_0 .. param_48]."""
+    torch = _torch()
+    P = u.numel()
+    out = torch.empty(1 + MLP_PARAMS, dtype=torch.float32, device=u.device)
+    _check(lib().wt_mlp_loss_grad(_dev_ptr(params, torch.float32, "params"), _dev_ptr(u, torch.float32, "u"),
+                                  _dev_ptr(v, torch.float32, "v"), P, _dev_ptr(out, torch.float32, "out"),
+                                  ctypes.c_void_p(_stream_handle(stream))))
+    return out
 
 
 def version() -> str:

@@ -81,6 +81,7 @@ extern "C" wt_status wt_free(wt_tree* t) {
   clear_error();
   if (!t) return WT_OK;
   WT_HIP(hipDeviceSynchronize());
+  if (t->learn) dev_free(t->learn, nullptr);
   dev_free(t->block, nullptr);
   WT_HIP(hipDeviceSynchronize());
   delete t;

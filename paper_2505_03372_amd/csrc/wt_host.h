@@ -18,6 +18,9 @@ struct wt_tree {
   wt::LevelMeta hmeta[WT_MAX_LEVELS]{};
   size_t bytes_bits = 0, bytes_l1 = 0, bytes_l2 = 0, bytes_smp = 0, bytes_nodes = 0, bytes_cum = 0;
   std::vector<wt_prof_entry> prof;
+  void* learn = nullptr;  // learned select models (device), one per child node
+  uint32_t nmodels = 0;
+  wt_learned_info_t linfo{};
 };
 
 namespace wt {

@@ -10,105 +10,9 @@
 
 #include "wt_host.h"
 #include "wt_internal.h"
+#include "wt_query_dev.h"
 
 namespace wt {
-
-constexpr int kQT = 256;
-
-struct QArgs {
-  TreeDev d;
-  uint64_t n;
-  uint32_t sigma, L, pow2, sshift;
-};
-
-// rank1 of the level at position i (0 <= i <= n_l) and the bit at i (meaningful for i < n_l).
-template <int L2S>
-__device__ __forceinline__ uint64_t rank1_at(const TreeDev& d, const LevelMeta& m, uint64_t i, uint32_t& bit) {
-  constexpr int L2W = (1 << L2S) / 64;
-  const uint64_t j = i >> L2S;
-  uint64_t r = d.L1[m.l1 + (i >> kL1Shift)] + d.L2[m.l2 + j];
-  const uint64_t* blk = d.bits + m.bits + (j << (L2S - 6));
-  const uint32_t wi = (uint32_t)(i >> 6) & (L2W - 1), bi = (uint32_t)i & 63u;
-  uint64_t cur = 0;
-  if constexpr (L2W <= 8) {
-    uint64_t w[L2W];
-#pragma unroll
-    for (int k = 0; k < L2W / 2; ++k) {
-      const uint4 x = reinterpret_cast<const uint4*>(blk)[k];
-      w[2 * k] = (uint64_t)x.x | ((uint64_t)x.y << 32);
-      w[2 * k + 1] = (uint64_t)x.z | ((uint64_t)x.w << 32);
-    }
-#pragma unroll
-    for (int k = 0; k < L2W; ++k) {
-      r += ((uint32_t)k < wi) ? popc64(w[k]) : 0u;
-      cur = ((uint32_t)k == wi) ? w[k] : cur;
-    }
-  } else {
-    for (uint32_t k = 0; k < wi; ++k) r += popc64(blk[k]);
-    cur = blk[wi];
-  }
-  r += popc64(cur & ((1ull << bi) - 1ull));
-  bit = (uint32_t)(cur >> bi) & 1u;
-  return r;
-}
-
-// Position of the k-th bit equal to b (1 <= k <= count of b) of the level (Algorithm 2).
-template <int L2S>
-__device__ __forceinline__ uint64_t select_at(const TreeDev& d, const LevelMeta& m, uint32_t b, uint64_t k,
-                                              uint32_t sshift) {
-  constexpr int L2W = (1 << L2S) / 64;
-  constexpr uint64_t kPer = kL1Bits >> L2S;  // L2 blocks per L1 block
-  const uint64_t nl = m.n;
-  const uint64_t cntb = b ? m.ones : nl - m.ones;
-  // samples bound the position: the (si s)-th and ((si+1) s)-th bit equal to b
-  const uint64_t si = k >> sshift;
-  uint64_t lo_pos = 0, hi_pos = nl;
-  if (si) lo_pos = b ? d.smp[m.smp + si - 1] : d.smp[m.smp + m.smp_cap - si];
-  if (((si + 1) << sshift) <= cntb) hi_pos = b ? d.smp[m.smp + si] : d.smp[m.smp + m.smp_cap - si - 1];
-  const uint64_t nL1 = (nl + kL1Bits - 1) >> kL1Shift;
-  const uint64_t* L1 = d.L1 + m.l1;
-  const uint16_t* L2 = d.L2 + m.l2;
-  // largest L1 block whose count of b before it is < k
-  uint64_t blo = lo_pos >> kL1Shift, bhi = min(hi_pos >> kL1Shift, nL1 - 1);
-  while (blo < bhi) {
-    const uint64_t mid = (blo + bhi + 1) >> 1;
-    const uint64_t cb = b ? L1[mid] : (mid << kL1Shift) - L1[mid];
-    if (cb < k) blo = mid;
-    else bhi = mid - 1;
-  }
-  const uint64_t blk = blo;
-  k -= b ? L1[blk] : (blk << kL1Shift) - L1[blk];
-  // largest L2 block of that L1 block whose count of b since the L1 start is < k; the samples
-  // also bound the L2 range
-  const uint64_t nL2 = (nl + (1ull << L2S) - 1) >> L2S;
-  const uint64_t jb = blk * kPer;
-  uint64_t jlo = max(jb, lo_pos >> L2S);
-  uint64_t jhi = min(min(jb + kPer, nL2) - 1, hi_pos >> L2S);
-  while (jlo < jhi) {
-    const uint64_t mid = (jlo + jhi + 1) >> 1;
-    const uint64_t cb = b ? (uint64_t)L2[mid] : ((mid - jb) << L2S) - L2[mid];
-    if (cb < k) jlo = mid;
-    else jhi = mid - 1;
-  }
-  k -= b ? (uint64_t)L2[jlo] : ((jlo - jb) << L2S) - L2[jlo];
-  // word scan inside the L2 block, then the in-word select
-  const uint64_t* wp = d.bits + m.bits + (jlo << (L2S - 6));
-  uint32_t kk = (uint32_t)k;
-#pragma unroll
-  for (int w = 0; w < L2W; ++w) {
-    uint64_t word = wp[w];
-    if (!b) word = ~word;
-    const uint32_t pc = popc64(word);
-    if (kk <= pc) return (jlo << L2S) + 64u * (uint32_t)w + select_in_word(word, kk);
-    kk -= pc;
-  }
-  return nl;  // not reached for valid k
-}
-
-__device__ __forceinline__ void load_meta(const QArgs& a, LevelMeta* s_meta) {
-  if (threadIdx.x < a.L) s_meta[threadIdx.x] = a.d.meta[threadIdx.x];
-  __syncthreads();
-}
 
 // Algorithm 5 (top-down): the bit of the element picks the child; its position in the child is its
 // rank among the equal bits of the node. Stops once the node covers at most two symbols.
@@ -231,29 +135,6 @@ __global__ __launch_bounds__(kQT) void k_select(QArgs a, const uint32_t* __restr
     out[j] = res;
   }
 }
-
-static QArgs make_args(const wt_tree* t) {
-  QArgs a;
-  a.d = t->dev;
-  a.n = t->n;
-  a.sigma = (uint32_t)t->sigma;
-  a.L = t->L;
-  a.pow2 = t->pow2;
-  uint32_t sh = 0;
-  while ((1u << sh) < t->srate) ++sh;
-  a.sshift = sh;
-  return a;
-}
-
-static uint32_t query_grid(uint64_t q) { return (uint32_t)std::min<uint64_t>(ceil_div(q, kQT), 4096); }
-
-#define WT_DISPATCH_L2(bits, KERNEL, ...)                                                          \
-  switch (bits) {                                                                                 \
-    case 256: hipLaunchKernelGGL(KERNEL<8>, dim3(grid), dim3(kQT), 0, st, __VA_ARGS__); break;   \
-    case 512: hipLaunchKernelGGL(KERNEL<9>, dim3(grid), dim3(kQT), 0, st, __VA_ARGS__); break;   \
-    case 1024: hipLaunchKernelGGL(KERNEL<10>, dim3(grid), dim3(kQT), 0, st, __VA_ARGS__); break; \
-    default: hipLaunchKernelGGL(KERNEL<11>, dim3(grid), dim3(kQT), 0, st, __VA_ARGS__); break;   \
-  }
 
 }  // namespace wt
 

@@ -1,0 +1,105 @@
+"""GPU tests of the learned select index.
+
+* the device loss and gradient (the training kernel's own code) against the FP64 oracle of the
+  network, within a relative 1e-4 (FP32 accumulation);
+* learned select answers equal to the oracle's and to the plain select's on many trees
+  (exactness does not depend on the FP32 model: the prediction is corrected exactly);
+* what training gains: the trained networks' mean prediction error (in L2 blocks, over every L2
+  boundary of every node) is below that of the untrained starting point (the linear map).
+"""
+import numpy as np
+import pytest
+
+import oracle
+import workloads
+from tests import gpu_cases as G
+from tests.test_gpu_parity import make_seq
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _need_gpu():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    import paper_2505_03372_amd as wt
+    wt.lib()
+
+
+@pytest.mark.parametrize("P,seed", [(1, 1), (7, 2), (300, 3), (2048, 4)])
+def test_device_gradient_matches_fp64_reference(P, seed):
+    import paper_2505_03372_amd as wt
+    r = workloads.raw(0xD00 + seed, 0, P * 2 + 49).astype(np.float64) / 2.0**64
+    u = r[:P]
+    v = np.sqrt(u) + 0.05 * (r[P:2 * P] - 0.5)
+    th = oracle.mlp_init() + 0.2 * (r[2 * P:] - 0.5)
+    th32, u32, v32 = th.astype(np.float32), u.astype(np.float32), v.astype(np.float32)
+    G.log("mlp grad P=%d" % P)
+    out = G.host(wt.mlp_loss_grad(G.dev(th32), G.dev(u32), G.dev(v32)))
+    # reference on the same FP32-rounded inputs, in FP64
+    loss, grad = oracle.mlp_loss_grad(th32.astype(np.float64), u32.astype(np.float64), v32.astype(np.float64))
+    assert abs(out[0] - loss) <= 1e-4 * abs(loss) + 1e-9
+    scale = max(1e-6, float(np.abs(grad).max()))
+    np.testing.assert_allclose(out[1:], grad, rtol=1e-4, atol=1e-4 * scale)
+
+
+LEARN_CASES = [
+    (1, 256, 1 << 20, "zipf"),
+    (1, 256, 1 << 20, "uniform"),
+    (1, 77, 300001, "zipf"),
+    (1, 5, 100000, "alternate"),
+    (1, 2, 70001, "uniform"),
+    (1, 7, 131073, "runs"),
+    (2, 25, 500000, "zipf"),
+    (2, 40000, 300000, "uniform"),
+    (4, 1 << 20, 1 << 21, "zipf12"),
+    (4, 3, 100001, "uniform"),
+    (1, 1, 1000, "equal"),
+    (1, 11, 65, "uniform"),
+]
+
+
+@pytest.mark.parametrize("width,sigma,n,kind", LEARN_CASES, ids=["w%d-s%d-n%d-%s" % c for c in LEARN_CASES])
+def test_learned_select_is_exact(width, sigma, n, kind):
+    seed = 0xBEEF + n + sigma
+    S = make_seq(kind, n, sigma, width, seed)
+    G.log("learned case w=%d sigma=%d n=%d kind=%s" % (width, sigma, n, kind))
+    t = G.gpu_build(S, sigma)
+    info = t.learn_select()
+    assert info["params_per_model"] == 49
+    _, _, _, sc, sk = G.random_queries(S, sigma, 8192, seed)
+    got = G.host(t.select_learned(G.dev(sc), G.dev(sk)))
+    plain = G.host(t.select(G.dev(sc), G.dev(sk)))
+    exp = oracle.select(S, sigma, sc, sk)
+    G._assert_eq("learned select vs oracle", got, exp, np.stack([sc.astype(np.uint64), sk], 1))
+    G._assert_eq("learned select vs plain", got, plain, np.stack([sc.astype(np.uint64), sk], 1))
+    _, _, _, ec, ek = G.edge_queries(S, sigma)
+    got = G.host(t.select_learned(G.dev(ec), G.dev(ek)))
+    G._assert_eq("learned select edges", got, oracle.select(S, sigma, ec, ek), np.stack([ec.astype(np.uint64), ek], 1))
+    t.free()
+
+
+def test_training_reduces_prediction_error():
+    S, sigma = workloads.make_text("text_zipf", n=1 << 24)
+    G.log("training gain on text_zipf prefix 2^24")
+    t = G.gpu_build(S, sigma)
+    info = t.learn_select()
+    G.log("  %s" % info)
+    assert info["models"] > 0
+    assert info["mean_err_blocks"] < 0.8 * info["mean_err_init_blocks"]
+    assert info["max_err_blocks"] <= info["max_err_init_blocks"] + 2
+    t.free()
+
+
+def test_learned_select_full_size_text_zipf():
+    """n = 2^30 u8 Zipf(1.0): 2^26 learned selects, sampled check against the oracle."""
+    G.log("text_zipf learned: generating")
+    wl = workloads.make("text_zipf", kinds=("select",))
+    t = G.gpu_build(wl.S, wl.sigma)
+    G.log("text_zipf learned: training")
+    t.learn_select()
+    G.log("text_zipf learned: 2^26 selects")
+    got = G.host(t.select_learned(G.dev(wl.sel_c), G.dev(wl.sel_k)))
+    idx = np.arange(0, got.size, 1024)
+    G._assert_eq("learned select", got[idx], oracle.select(wl.S, wl.sigma, wl.sel_c[idx], wl.sel_k[idx]), wl.sel_k[idx])
+    t.free()

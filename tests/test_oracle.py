@@ -268,3 +268,24 @@ def test_node_ranks_match_histogram_formula(sigma, n):
             exp = sum(int(hist[c]) for c in range(s0)
                       if ln[c] > l and ((int(code[c]) >> (L - 1 - l)) & 1) == 0)
             assert int(t.node_r0[l][p]) == exp
+
+
+def test_mlp_reference_gradients_match_finite_differences():
+    rng = workloads.raw(0xABC, 0, 2000).astype(np.float64) / 2.0**64
+    u = rng[:500]
+    v = np.sqrt(u) + 0.01 * (rng[500:1000] - 0.5)  # a monotone target with noise
+    th = oracle.mlp_init() + 0.1 * (rng[1000:1049] - 0.5)
+    loss, g = oracle.mlp_loss_grad(th, u, v)
+    # the loss is the mean squared error of the forward pass
+    assert abs(loss - np.mean((oracle.mlp_forward(th, u) - v) ** 2)) < 1e-12
+    h = 1e-6
+    for j in range(oracle.MLP_PARAMS):
+        tp = th.copy(); tp[j] += h
+        tm = th.copy(); tm[j] -= h
+        fd = (oracle.mlp_loss_grad(tp, u, v)[0] - oracle.mlp_loss_grad(tm, u, v)[0]) / (2 * h)
+        assert abs(fd - g[j]) <= 1e-6 * max(1.0, abs(g[j])), (j, fd, g[j])
+
+
+def test_mlp_init_is_identity_on_unit_interval():
+    u = np.linspace(0, 1, 101)
+    assert np.allclose(oracle.mlp_forward(oracle.mlp_init(), u), u, atol=1e-15)
