@@ -312,8 +312,18 @@ __device__ __forceinline__ uint64_t select_learned_at(const TreeDev& d, const Le
   const uint64_t T = M.rank0 + j;  // global target among the side-b bits of the level
   if (M.eps < 0) return select_at<L2S>(d, m, b, T, sshift);
   float p[kNP];
+  {
+    const float4* mp = reinterpret_cast<const float4*>(M.p);
 #pragma unroll
-  for (int k = 0; k < kNP; ++k) p[k] = M.p[k];
+    for (int k = 0; k < kNP / 4; ++k) {
+      const float4 x = mp[k];
+      p[4 * k] = x.x;
+      p[4 * k + 1] = x.y;
+      p[4 * k + 2] = x.z;
+      p[4 * k + 3] = x.w;
+    }
+    p[kNP - 1] = M.p[kNP - 1];
+  }
   const float u = ((float)j - 0.5f) / (float)M.cnt;
   const float v = fminf(fmaxf(mlp_eval(p, u), 0.f), 1.f);
   const uint64_t start = M.start, end = M.start + M.len;
@@ -322,27 +332,42 @@ __device__ __forceinline__ uint64_t select_learned_at(const TreeDev& d, const Le
   const uint64_t Blo = start >> L2S, Bhi = (end - 1) >> L2S;
   const uint64_t B0 = guess >> L2S;
   const uint64_t budget = (uint64_t)M.eps;
-  // largest B in [Blo, Bhi] with count_before(B) < T; count_before(Blo) <= rank0 < T always
+  // largest B in [Blo, Bhi] with count_before(B) < T; count_before(Blo) <= rank0 < T always.
+  // First look at the aligned group of L2 counts holding B0 (one 128-byte line, inside one L1
+  // block): the counts are non-decreasing, so the blocks below the target form a prefix of it.
+  constexpr int GS = L2S <= 10 ? 6 : 5;
+  constexpr uint32_t GN = 1u << GS;
+  const uint64_t gbase = B0 & ~(uint64_t)(GN - 1);
+  const uint64_t glo = max(gbase, Blo), ghi = min(gbase + GN - 1, Bhi);
+  const uint64_t l1v = d.L1[m.l1 + ((gbase << L2S) >> kL1Shift)];
+  const uint4* gp = reinterpret_cast<const uint4*>(d.L2 + m.l2 + gbase);
+  uint4 g[GN / 8];
+#pragma unroll
+  for (uint32_t i = 0; i < GN / 8; ++i) g[i] = gp[i];
+  // below(e) <=> count_before(gbase + e) < T, in 32-bit arithmetic with saturation
+  int64_t D;
+  if (b) D = (int64_t)min<uint64_t>(T - min(T, l1v), 1ull << 20);  // l2 < D
+  else {
+    const uint64_t base0 = (gbase << L2S) - l1v;  // zeros before the group
+    D = T > base0 ? (int64_t)min<uint64_t>(T - base0, 1ull << 20) : -(int64_t)min<uint64_t>(base0 - T, 1ull << 20);
+  }
+  const int32_t Di = (int32_t)D;
+  const uint32_t elo = (uint32_t)(glo - gbase), ehi = (uint32_t)(ghi - gbase);
+  uint32_t below = 0;
+#pragma unroll
+  for (uint32_t e = 0; e < GN; ++e) {
+    const uint32_t dw = (e & 7) < 4 ? ((e & 7) < 2 ? g[e >> 3].x : g[e >> 3].y) : ((e & 7) < 6 ? g[e >> 3].z : g[e >> 3].w);
+    const int32_t l2v = (int32_t)((dw >> ((e & 1) * 16)) & 0xFFFFu);
+    const bool lt = b ? (l2v < Di) : ((int32_t)(e << L2S) - l2v < Di);
+    below += (lt && e >= elo && e <= ehi) ? 1u : 0u;
+  }
   uint64_t lo, hi;  // invariant: count_before(lo) < T, and hi = Bhi + 1 or count_before(hi) >= T
-  if (count_before<L2S>(d, m, b, B0 << L2S) < T) {
-    lo = B0;
-    uint64_t step = 1;
-    for (;;) {
-      const uint64_t nb = lo + step;
-      if (nb > Bhi) {
-        hi = Bhi + 1;
-        break;
-      }
-      if (count_before<L2S>(d, m, b, nb << L2S) >= T) {
-        hi = nb;
-        break;
-      }
-      lo = nb;
-      step <<= 1;
-      if (nb - B0 > budget) return select_at<L2S>(d, m, b, T, sshift);
-    }
-  } else {
-    hi = B0;
+  if (below > 0 && (glo + below - 1 < ghi || ghi == Bhi)) {
+    lo = glo + below - 1;
+    hi = lo + 1;
+  } else if (below == 0) {
+    // target left of the group (glo > Blo here): gallop left from glo
+    hi = glo;
     uint64_t step = 1;
     for (;;) {
       if (hi - Blo <= step) {
@@ -356,7 +381,25 @@ __device__ __forceinline__ uint64_t select_learned_at(const TreeDev& d, const Le
       }
       hi = nb;
       step <<= 1;
-      if (B0 - nb > budget) return select_at<L2S>(d, m, b, T, sshift);
+      if (glo - nb > budget) return select_at<L2S>(d, m, b, T, sshift);
+    }
+  } else {
+    // every block of the group is below the target: gallop right from ghi
+    lo = ghi;
+    uint64_t step = 1;
+    for (;;) {
+      const uint64_t nb = lo + step;
+      if (nb > Bhi) {
+        hi = Bhi + 1;
+        break;
+      }
+      if (count_before<L2S>(d, m, b, nb << L2S) >= T) {
+        hi = nb;
+        break;
+      }
+      lo = nb;
+      step <<= 1;
+      if (nb - ghi > budget) return select_at<L2S>(d, m, b, T, sshift);
     }
   }
   while (hi - lo > 1) {

@@ -74,11 +74,43 @@ __device__ __forceinline__ uint64_t select_at(const TreeDev& d, const LevelMeta&
   const uint64_t blk = blo;
   k -= b ? L1[blk] : (blk << kL1Shift) - L1[blk];
   // largest L2 block of that L1 block whose count of b since the L1 start is < k; the samples
-  // also bound the L2 range
+  // also bound the L2 range. The search starts on the aligned line of L2 counts holding jlo (64
+  // entries, inside the L1 block), read at once: the counts are non-decreasing, so the blocks below
+  // k form a prefix of the range and are counted in registers; only a range that leaves the line
+  // continues with the binary search over the remaining entries.
   const uint64_t nL2 = (nl + (1ull << L2S) - 1) >> L2S;
   const uint64_t jb = blk * kPer;
   uint64_t jlo = max(jb, lo_pos >> L2S);
   uint64_t jhi = min(min(jb + kPer, nL2) - 1, hi_pos >> L2S);
+  {
+    constexpr uint32_t GN = L2S <= 10 ? 64u : 32u;
+    const uint64_t gbase = jlo & ~(uint64_t)(GN - 1);
+    const uint64_t ghi = min(gbase + GN - 1, jhi);
+    const uint4* gp = reinterpret_cast<const uint4*>(L2 + gbase);
+    uint4 g[GN / 8];
+#pragma unroll
+    for (uint32_t i = 0; i < GN / 8; ++i) g[i] = gp[i];
+    const int32_t Ki = (int32_t)min<uint64_t>(k, 1ull << 20);
+    const int32_t rb = (int32_t)((gbase - jb) << L2S);  // bits from the L1 start to the group
+    const uint32_t elo = (uint32_t)(jlo - gbase), ehi = (uint32_t)(ghi - gbase);
+    uint32_t below = 0;
+#pragma unroll
+    for (uint32_t e = 0; e < GN; ++e) {
+      const uint32_t dw =
+          (e & 7) < 4 ? ((e & 7) < 2 ? g[e >> 3].x : g[e >> 3].y) : ((e & 7) < 6 ? g[e >> 3].z : g[e >> 3].w);
+      const int32_t l2v = (int32_t)((dw >> ((e & 1) * 16)) & 0xFFFFu);
+      const bool lt = b ? (l2v < Ki) : (rb + (int32_t)(e << L2S) - l2v < Ki);
+      below += (lt && e >= elo && e <= ehi) ? 1u : 0u;
+    }
+    // blocks jlo .. jlo + below - 1 are below k; jlo itself always is
+    if (below == 0) below = 1;
+    if (jlo + below - 1 < ghi || ghi == jhi) {
+      jlo = jlo + below - 1;
+      jhi = jlo;
+    } else {
+      jlo = ghi;
+    }
+  }
   while (jlo < jhi) {
     const uint64_t mid = (jlo + jhi + 1) >> 1;
     const uint64_t cb = b ? (uint64_t)L2[mid] : ((mid - jb) << L2S) - L2[mid];
