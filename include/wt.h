@@ -194,12 +194,142 @@ wt_status wt_select_learned(const wt_tree* t, const uint32_t* d_sym, const uint6
 
 wt_status wt_learned_info(const wt_tree* t, wt_learned_info_t* out);
 
+/* One model of the learned index, read back for inspection. Slots are numbered by child node: the
+   child on side b of node (level l, code prefix p) has slot 2^(l+1) - 2 + 2p + b, for 2^(L+1) - 2
+   slots in all (L = levels); slots of empty children or of leaves carry eps = -1 and no model.
+   For queries the trained network is compiled into its exact piecewise-linear form on [0, 1]:
+   v(u) = slope[s] u + intercept[s], where s is the number of knots <= u (the knots are the inputs
+   where a hidden unit switches, inside (0, 1), ascending; unused knots are 2). Synchronous.
+   WT_ERR_STATE before wt_learn_select, WT_ERR_ARG for a slot out of range. */
+typedef struct {
+  int32_t level;    /* level l of the parent node (the child's bits are those of level l) */
+  uint32_t side;    /* b */
+  int32_t eps;      /* correction budget in L2 blocks; -1: no model */
+  uint32_t points;  /* training points */
+  uint64_t start, len; /* node range in level l */
+  uint64_t count;   /* bits equal to b inside the node */
+  uint64_t rank0;   /* bits equal to b in level l before start */
+  float params[49]; /* w1[16], b1[16], w2[16], b2 */
+  uint32_t pieces;  /* number of linear pieces (knots inside (0, 1) plus one) */
+  float knots[16];
+  float slope[17], intercept[17];
+  float err_mean, err_max, err_init_mean, err_init_max; /* in L2 blocks, over every L2 boundary */
+  float loss;       /* final training loss */
+} wt_learned_model_t;
+
+wt_status wt_learned_model(const wt_tree* t, uint32_t slot, wt_learned_model_t* out);
+
 /* One evaluation of the training objective on the device, with the same device code the training
    kernel uses: d_out[0] = mean squared error of the network d_params (49 floats: w1[16], b1[16],
    w2[16], b2) over the P points (d_u[i], d_v[i]); d_out[1 + j] = its derivative by parameter j.
    For gradient checks against a reference. */
 wt_status wt_mlp_loss_grad(const float* d_params, const float* d_u, const float* d_v, uint32_t P, float* d_out,
                            wt_stream_t stream);
+
+/* ---- batched forest build (spec extension; the thesis builds one tree at a time) ----
+ *
+ * Many independent sequences of uneven length and alphabet are built into a forest of wavelet trees
+ * by one launch of a captured HIP graph. Every construction phase of Section 5.1 (histogram,
+ * cumulative histogram, node tables, and per level the tile prefix and the level pass) runs as one
+ * kernel over the blocks of every tree that has work in it; the blocks of a launch are mapped to
+ * trees by a table uploaded once, so small trees cost a few blocks instead of a launch sequence each.
+ * Each tree is identical to the tree wt_build makes from the same sequence and options.
+ */
+typedef struct wt_forest wt_forest;
+
+typedef struct {
+  const void* d_sym;    /* device symbols of the sequence (sym_bytes each; see wt_build_forest) */
+  uint64_t n;           /* length (0 allowed) */
+  uint64_t sigma;       /* declared alphabet size, as for wt_build */
+  uint32_t l2_bits;     /* 0: chosen by the tuning table of the options, else the default 512 */
+  uint32_t sample_rate; /* 0: chosen by the tuning table of the options, else the default 4096 */
+} wt_seq_desc;
+
+/* Tuning table: per shape bucket (floor(log2 n) / 2, floor(log2 sigma) / 4), the |L2| and s the
+   autotuner picked (0 = not tuned: defaults). Written by wt_autotune. */
+#define WT_TUNE_NB 21
+#define WT_TUNE_SB 7
+typedef struct {
+  uint32_t l2_bits[WT_TUNE_NB][WT_TUNE_SB];
+  uint32_t sample_rate[WT_TUNE_NB][WT_TUNE_SB];
+} wt_tune_table;
+
+typedef struct {
+  uint64_t max_probe_n;      /* symbols of the probe sequence of a bucket (a prefix); 0 = 2^22 */
+  uint32_t queries;          /* queries per kind and probe; 0 = 2^16 */
+  uint32_t reserved;
+  double queries_per_symbol; /* expected queries per symbol weighing query time against build time; 0 = 1/64 */
+  double space_cap;          /* largest (L2 + L1 + samples) / bits allowed; 0 = 0.10 */
+} wt_tune_opts;
+
+typedef struct {
+  uint32_t buckets, probes;  /* buckets tuned, builds probed */
+  float total_ms;
+  uint32_t reserved;
+  float cost_ns_per_symbol[WT_TUNE_NB][WT_TUNE_SB]; /* winning cost of every tuned bucket */
+} wt_tune_report;
+
+/*
+ * Autotuner of |L2| in {256, 512, 1024} and s in {1024, 4096, 16384} (the two parameters Sections 4.1
+ * and 4.2 leave open) per shape bucket of the given sequences. For every bucket with a sequence of
+ * length >= 1 and sigma >= 2, its longest sequence (a prefix of at most max_probe_n symbols) is built
+ * with every pair whose directory and samples fit the space cap, and a batch of each query kind is
+ * timed (HIP events) on it; the pair with the least build time per symbol plus queries_per_symbol
+ * times the mean query time wins. Buckets without a sequence stay 0 (defaults). Synchronous; the
+ * answers of trees built with any pair are the same. report may be NULL.
+ */
+wt_status wt_autotune(const wt_seq_desc* h_descs, uint32_t count, uint32_t sym_bytes, const wt_tune_opts* opts,
+                      wt_stream_t stream, wt_tune_table* out, wt_tune_report* report);
+
+typedef struct {
+  const wt_tune_table* tune; /* may be NULL */
+  uint32_t flags;            /* reserved */
+  uint32_t reserved;
+} wt_forest_opts;
+
+typedef struct {
+  uint32_t trees, levels_max;
+  uint64_t symbols;          /* total length */
+  uint64_t bytes_trees;      /* device bytes of every tree's parts (one allocation) */
+  uint64_t bytes_scratch;    /* build scratch (freed when wt_build_forest returns) */
+  uint32_t graph_kernels;    /* kernel nodes of the captured build graph */
+  uint32_t reserved;
+  float plan_ms;             /* host planning and the upload of the block tables */
+  float capture_ms;          /* graph capture and instantiation */
+  float graph_ms;            /* the graph launch (HIP events around it on the stream) */
+  float total_ms;            /* the whole call, host clock */
+} wt_forest_info_t;
+
+/*
+ * Build a forest (one tree per descriptor). All sequences use sym_bytes-byte symbols (1, 2 or 4).
+ * Same argument rules and errors as wt_build for every tree; WT_ERR_SYMBOL_RANGE names the first
+ * offending tree in wt_last_error. Enqueued on `stream` (a private stream when NULL) and waited for.
+ */
+wt_status wt_build_forest(const wt_seq_desc* h_descs, uint32_t count, uint32_t sym_bytes, const wt_forest_opts* opts,
+                          wt_stream_t stream, wt_forest** out);
+
+/* Borrowed handle of tree j (valid until wt_forest_free): usable with every query, info, export and
+   learned-index call; wt_free refuses it (WT_ERR_STATE). */
+wt_status wt_forest_tree(const wt_forest* f, uint32_t j, wt_tree** out);
+
+wt_status wt_forest_info(const wt_forest* f, wt_forest_info_t* out);
+
+/* Release a forest and its trees (waits for the device to be idle first). NULL is accepted. */
+wt_status wt_forest_free(wt_forest* f);
+
+/*
+ * Mixed batched queries over the trees of a forest: query j asks tree d_tree[j] for
+ *   d_op[j] = WT_OP_ACCESS: access(d_arg[j])            (d_sym ignored; 0xFFFFFFFF if out of range)
+ *             WT_OP_RANK:   rank_{d_sym[j]}(d_arg[j])
+ *             WT_OP_SELECT: select_{d_sym[j]}(d_arg[j])
+ * with the results and sentinels of wt_access / wt_rank / wt_select, widened to 64 bits in d_out[j].
+ * An unknown tree or op gives UINT64_MAX. The queries are grouped by (op, |L2| of the tree) on the
+ * device so that each wavefront runs one traversal; d_out is in the order of the queries.
+ */
+enum { WT_OP_ACCESS = 0, WT_OP_RANK = 1, WT_OP_SELECT = 2 };
+
+wt_status wt_query_mixed(const wt_forest* f, const uint32_t* d_tree, const uint8_t* d_op, const uint32_t* d_sym,
+                         const uint64_t* d_arg, uint64_t q, uint64_t* d_out, wt_stream_t stream);
 
 /* Thread-local description of the last failure on this thread ("" if none). */
 const char* wt_last_error(void);

@@ -33,7 +33,11 @@ U64_MAX = (1 << 64) - 1
 # names declared by include/wt.h
 ABI_FUNCTIONS = ("wt_set_allocator", "wt_build", "wt_free", "wt_access", "wt_rank", "wt_select", "wt_info",
                  "wt_export", "wt_build_profile", "wt_last_error", "wt_version", "wt_learn_select",
-                 "wt_select_learned", "wt_learned_info", "wt_mlp_loss_grad")
+                 "wt_select_learned", "wt_learned_info", "wt_learned_model", "wt_mlp_loss_grad",
+                 "wt_build_forest", "wt_forest_tree", "wt_forest_info", "wt_forest_free", "wt_query_mixed",
+                 "wt_autotune")
+OP_ACCESS, OP_RANK, OP_SELECT = 0, 1, 2
+TUNE_NB, TUNE_SB = 21, 7
 MLP_PARAMS = 49
 
 
@@ -70,6 +74,45 @@ class LearnedInfo(ctypes.Structure):
                 ("mean_err_blocks", ctypes.c_double), ("max_err_blocks", ctypes.c_double),
                 ("mean_err_init_blocks", ctypes.c_double), ("max_err_init_blocks", ctypes.c_double),
                 ("final_loss_mean", ctypes.c_double), ("train_ms", ctypes.c_float), ("reserved", ctypes.c_uint32)]
+
+
+class LearnedModel(ctypes.Structure):
+    _fields_ = [("level", ctypes.c_int32), ("side", ctypes.c_uint32), ("eps", ctypes.c_int32),
+                ("points", ctypes.c_uint32), ("start", ctypes.c_uint64), ("len", ctypes.c_uint64),
+                ("count", ctypes.c_uint64), ("rank0", ctypes.c_uint64), ("params", ctypes.c_float * 49),
+                ("pieces", ctypes.c_uint32), ("knots", ctypes.c_float * 16), ("slope", ctypes.c_float * 17),
+                ("intercept", ctypes.c_float * 17), ("err_mean", ctypes.c_float), ("err_max", ctypes.c_float),
+                ("err_init_mean", ctypes.c_float), ("err_init_max", ctypes.c_float), ("loss", ctypes.c_float)]
+
+
+class SeqDesc(ctypes.Structure):
+    _fields_ = [("d_sym", ctypes.c_void_p), ("n", ctypes.c_uint64), ("sigma", ctypes.c_uint64),
+                ("l2_bits", ctypes.c_uint32), ("sample_rate", ctypes.c_uint32)]
+
+
+class TuneTable(ctypes.Structure):
+    _fields_ = [("l2_bits", (ctypes.c_uint32 * 7) * 21), ("sample_rate", (ctypes.c_uint32 * 7) * 21)]
+
+
+class TuneOpts(ctypes.Structure):
+    _fields_ = [("max_probe_n", ctypes.c_uint64), ("queries", ctypes.c_uint32), ("reserved", ctypes.c_uint32),
+                ("queries_per_symbol", ctypes.c_double), ("space_cap", ctypes.c_double)]
+
+
+class TuneReport(ctypes.Structure):
+    _fields_ = [("buckets", ctypes.c_uint32), ("probes", ctypes.c_uint32), ("total_ms", ctypes.c_float),
+                ("reserved", ctypes.c_uint32), ("cost_ns_per_symbol", (ctypes.c_float * 7) * 21)]
+
+
+class ForestOpts(ctypes.Structure):
+    _fields_ = [("tune", ctypes.POINTER(TuneTable)), ("flags", ctypes.c_uint32), ("reserved", ctypes.c_uint32)]
+
+
+class ForestInfo(ctypes.Structure):
+    _fields_ = [("trees", ctypes.c_uint32), ("levels_max", ctypes.c_uint32), ("symbols", ctypes.c_uint64),
+                ("bytes_trees", ctypes.c_uint64), ("bytes_scratch", ctypes.c_uint64),
+                ("graph_kernels", ctypes.c_uint32), ("reserved", ctypes.c_uint32), ("plan_ms", ctypes.c_float),
+                ("capture_ms", ctypes.c_float), ("graph_ms", ctypes.c_float), ("total_ms", ctypes.c_float)]
 
 
 class ProfEntry(ctypes.Structure):
@@ -116,6 +159,22 @@ def lib():
     L.wt_select_learned.argtypes = [vp, vp, vp, u64, vp, vp]
     L.wt_learned_info.restype = ctypes.c_int
     L.wt_learned_info.argtypes = [vp, ctypes.POINTER(LearnedInfo)]
+    L.wt_build_forest.restype = ctypes.c_int
+    L.wt_build_forest.argtypes = [ctypes.POINTER(SeqDesc), u32, u32, ctypes.POINTER(ForestOpts), vp,
+                                  ctypes.POINTER(vp)]
+    L.wt_forest_tree.restype = ctypes.c_int
+    L.wt_forest_tree.argtypes = [vp, u32, ctypes.POINTER(vp)]
+    L.wt_forest_info.restype = ctypes.c_int
+    L.wt_forest_info.argtypes = [vp, ctypes.POINTER(ForestInfo)]
+    L.wt_forest_free.restype = ctypes.c_int
+    L.wt_forest_free.argtypes = [vp]
+    L.wt_query_mixed.restype = ctypes.c_int
+    L.wt_query_mixed.argtypes = [vp, vp, vp, vp, vp, u64, vp, vp]
+    L.wt_autotune.restype = ctypes.c_int
+    L.wt_autotune.argtypes = [ctypes.POINTER(SeqDesc), u32, u32, ctypes.POINTER(TuneOpts), vp,
+                              ctypes.POINTER(TuneTable), ctypes.POINTER(TuneReport)]
+    L.wt_learned_model.restype = ctypes.c_int
+    L.wt_learned_model.argtypes = [vp, u32, ctypes.POINTER(LearnedModel)]
     L.wt_mlp_loss_grad.restype = ctypes.c_int
     L.wt_mlp_loss_grad.argtypes = [vp, vp, vp, u32, vp, vp]
     _lib = L
@@ -164,9 +223,10 @@ def _sym_dtypes():
 class Tree:
     """A wavelet tree resident in HBM (owned by libwt)."""
 
-    def __init__(self, handle: int, keepalive=None):
+    def __init__(self, handle: int, keepalive=None, borrowed: bool = False):
         self._h = ctypes.c_void_p(handle)
         self._keep = keepalive
+        self._borrowed = borrowed
         self.info = self._info()
 
     @property
@@ -232,6 +292,16 @@ class Tree:
         _check(lib().wt_learned_info(self._h, ctypes.byref(inf)))
         return {f: getattr(inf, f) for f, _ in LearnedInfo._fields_ if f != "reserved"}
 
+    def learned_model(self, slot: int) -> dict:
+        """One model of the learned index (training record and its compiled piecewise-linear form)."""
+        m = LearnedModel()
+        _check(lib().wt_learned_model(self._h, slot, ctypes.byref(m)))
+        d = {}
+        for f, _ in LearnedModel._fields_:
+            v = getattr(m, f)
+            d[f] = np.array(v[:], dtype=np.float32) if isinstance(v, ctypes.Array) else v
+        return d
+
     def select_learned(self, sym, k, out=None, stream=None):
         torch = _torch()
         q = k.numel()
@@ -261,7 +331,8 @@ class Tree:
 
     def free(self):
         if self._h is not None and self._h.value:
-            _check(lib().wt_free(self._h))
+            if not self._borrowed:
+                _check(lib().wt_free(self._h))
             self._h = ctypes.c_void_p(0)
 
     def __del__(self):
@@ -283,6 +354,134 @@ def build(sym, sigma: int, l2_bits: int = 512, sample_rate: int = 4096, profile:
     _check(lib().wt_build(ctypes.c_void_p(sym.data_ptr() if sym.numel() else 0), sym.numel(), dts[sym.dtype], sigma,
                           ctypes.byref(opts), ctypes.c_void_p(_stream_handle(stream)), ctypes.byref(h)))
     return Tree(h.value)
+
+
+class Forest:
+    """Trees built together by wt_build_forest (owned by libwt; trees are borrowed handles)."""
+
+    def __init__(self, handle: int, keepalive=None):
+        self._h = ctypes.c_void_p(handle)
+        self._keep = keepalive
+        inf = ForestInfo()
+        _check(lib().wt_forest_info(self._h, ctypes.byref(inf)))
+        self.info = {f: getattr(inf, f) for f, _ in ForestInfo._fields_ if f != "reserved"}
+        self.trees = []
+        for j in range(inf.trees):
+            t = ctypes.c_void_p(0)
+            _check(lib().wt_forest_tree(self._h, j, ctypes.byref(t)))
+            self.trees.append(Tree(t.value, keepalive=self, borrowed=True))
+
+    def __len__(self):
+        return len(self.trees)
+
+    def __getitem__(self, j) -> Tree:
+        return self.trees[j]
+
+    def query_mixed(self, tree, op, sym, arg, out=None, stream=None):
+        """Mixed access/rank/select: tree (uint32), op (uint8: OP_ACCESS/OP_RANK/OP_SELECT), sym (uint32),
+        arg (uint64: position or k); returns uint64 results in query order."""
+        torch = _torch()
+        q = arg.numel()
+        if tree.numel() != q or op.numel() != q or sym.numel() != q:
+            raise ValueError("tree, op, sym and arg must have the same length")
+        if out is None:
+            out = torch.empty(q, dtype=torch.uint64, device=arg.device)
+        _check(lib().wt_query_mixed(self._h, _dev_ptr(tree, torch.uint32, "tree"), _dev_ptr(op, torch.uint8, "op"),
+                                    _dev_ptr(sym, torch.uint32, "sym"), _dev_ptr(arg, torch.uint64, "arg"), q,
+                                    _dev_ptr(out, torch.uint64, "out"), ctypes.c_void_p(_stream_handle(stream))))
+        return out
+
+    def free(self):
+        if self._h is not None and self._h.value:
+            for t in self.trees:
+                t._h = ctypes.c_void_p(0)
+            _check(lib().wt_forest_free(self._h))
+            self._h = ctypes.c_void_p(0)
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
+
+
+def make_tune_table(entries: dict) -> TuneTable:
+    """{(n_bucket, sigma_bucket): (l2_bits, sample_rate)} -> TuneTable."""
+    tt = TuneTable()
+    for (nb, sb), (l2, s) in entries.items():
+        tt.l2_bits[nb][sb] = l2
+        tt.sample_rate[nb][sb] = s
+    return tt
+
+
+def tune_bucket(n: int, sigma: int):
+    """Shape bucket of the tuning table: (floor(log2 n) // 2, floor(log2 sigma) // 4), clamped."""
+    nb = min((max(n, 1).bit_length() - 1) // 2, TUNE_NB - 1)
+    sb = min((max(sigma, 1).bit_length() - 1) // 4, TUNE_SB - 1)
+    return nb, sb
+
+
+def _descs(seqs, sigmas, l2_bits=None, sample_rates=None):
+    if len(seqs) == 0 or len(seqs) != len(sigmas):
+        raise ValueError("need one sigma per sequence")
+    dts = _sym_dtypes()
+    dt = seqs[0].dtype
+    if dt not in dts:
+        raise TypeError("symbols must be uint8, uint16 or uint32 (got %s)" % dt)
+    descs = (SeqDesc * len(seqs))()
+    for j, x in enumerate(seqs):
+        if x.dtype != dt or not x.is_cuda or not x.is_contiguous():
+            raise ValueError("sequence %d: contiguous device tensor of %s expected" % (j, dt))
+        descs[j].d_sym = x.data_ptr() if x.numel() else 0
+        descs[j].n = x.numel()
+        descs[j].sigma = int(sigmas[j])
+        descs[j].l2_bits = int(l2_bits[j]) if l2_bits is not None else 0
+        descs[j].sample_rate = int(sample_rates[j]) if sample_rates is not None else 0
+    return descs, dts[dt]
+
+
+def autotune(seqs, sigmas, max_probe_n: int = 0, queries: int = 0, queries_per_symbol: float = 0.0,
+             space_cap: float = 0.0, stream=None):
+    """Pick |L2| and s per shape bucket by timing probe builds and queries on the device.
+    Returns (TuneTable, report dict)."""
+    descs, w = _descs(seqs, sigmas)
+    opts = TuneOpts(max_probe_n, queries, 0, queries_per_symbol, space_cap)
+    tt, rep = TuneTable(), TuneReport()
+    _check(lib().wt_autotune(descs, len(seqs), w, ctypes.byref(opts), ctypes.c_void_p(_stream_handle(stream)),
+                             ctypes.byref(tt), ctypes.byref(rep)))
+    report = dict(buckets=rep.buckets, probes=rep.probes, total_ms=rep.total_ms,
+                  choice={(nb, sb): (tt.l2_bits[nb][sb], tt.sample_rate[nb][sb])
+                          for nb in range(TUNE_NB) for sb in range(TUNE_SB) if tt.l2_bits[nb][sb]},
+                  cost_ns_per_symbol={(nb, sb): rep.cost_ns_per_symbol[nb][sb]
+                                      for nb in range(TUNE_NB) for sb in range(TUNE_SB) if tt.l2_bits[nb][sb]})
+    return tt, report
+
+
+def save_tune(tt: TuneTable, path: str):
+    """Tuning table as JSON: {"n_bucket,sigma_bucket": [l2_bits, sample_rate]} (tuned buckets only)."""
+    import json
+    d = {"%d,%d" % (nb, sb): [tt.l2_bits[nb][sb], tt.sample_rate[nb][sb]]
+         for nb in range(TUNE_NB) for sb in range(TUNE_SB) if tt.l2_bits[nb][sb]}
+    with open(path, "w") as fh:
+        json.dump(d, fh, indent=1, sort_keys=True)
+
+
+def load_tune(path: str) -> TuneTable:
+    import json
+    with open(path) as fh:
+        d = json.load(fh)
+    return make_tune_table({tuple(int(x) for x in k.split(",")): tuple(v) for k, v in d.items()})
+
+
+def build_forest(seqs, sigmas, l2_bits=None, sample_rates=None, tune: TuneTable = None, stream=None) -> Forest:
+    """Build one tree per device tensor of `seqs` (all uint8, all uint16 or all uint32; views of one buffer
+    are fine) in one captured graph launch. l2_bits / sample_rates: per-sequence lists (0 = tuned/default)."""
+    descs, w = _descs(seqs, sigmas, l2_bits, sample_rates)
+    opts = ForestOpts(ctypes.pointer(tune) if tune is not None else None, 0, 0)
+    h = ctypes.c_void_p(0)
+    _check(lib().wt_build_forest(descs, len(seqs), w, ctypes.byref(opts), ctypes.c_void_p(_stream_handle(stream)),
+                                 ctypes.byref(h)))
+    return Forest(h.value)
 
 
 def mlp_loss_grad(params, u, v, stream=None):

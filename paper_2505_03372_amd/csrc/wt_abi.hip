@@ -80,6 +80,7 @@ extern "C" wt_status wt_set_allocator(wt_alloc_fn alloc_fn, wt_free_fn free_fn, 
 extern "C" wt_status wt_free(wt_tree* t) {
   clear_error();
   if (!t) return WT_OK;
+  if (t->borrowed) return fail(WT_ERR_STATE, "wt_free: the tree belongs to a forest (use wt_forest_free)");
   WT_HIP(hipDeviceSynchronize());
   if (t->learn) dev_free(t->learn, nullptr);
   dev_free(t->block, nullptr);

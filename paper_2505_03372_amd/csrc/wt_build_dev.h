@@ -1,0 +1,1047 @@
+// Device code of the level-wise construction (Section 5.1, Algorithm 4), shared by the single-tree
+// build and the batched forest build: every phase is a device body over a block index, called by a
+// kernel of one tree (block index = blockIdx.x) or by a forest kernel that maps its blocks to trees.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "wt_host.h"
+#include "wt_internal.h"
+
+namespace wt {
+
+// Device memory. The compiler infers it for pointers passed as kernel arguments, not for pointers
+// read from device memory (per-tree state of a forest build), whose accesses would otherwise all be
+// flat accesses: the level pass and the histogram take their pointers in this address space.
+#define WT_GLOBAL __attribute__((address_space(1)))
+
+template <typename T, typename U>
+__device__ __forceinline__ T* pcast(U* p) {
+  return (T*)p;
+}
+template <typename T, typename U>
+__device__ __forceinline__ WT_GLOBAL T* pcast(WT_GLOBAL U* p) {
+  return (WT_GLOBAL T*)p;
+}
+
+// 16-byte and struct accesses that keep the pointer's address space (HIP's uint4 and the tree
+// structs are classes whose copies take generic references).
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+
+template <typename P>
+__device__ __forceinline__ void st16(P p, const uint4& y) {
+  u32x4 x;
+  __builtin_memcpy(&x, &y, 16);
+  *pcast<u32x4>(p) = x;
+}
+
+template <typename P>
+__device__ __forceinline__ LevelMeta ld_meta(P p) {
+  LevelMeta m;
+  m.n = p->n;
+  m.ones = p->ones;
+  m.bits = p->bits;
+  m.l1 = p->l1;
+  m.l2 = p->l2;
+  m.smp = p->smp;
+  m.smp_cap = p->smp_cap;
+  m.pad = p->pad;
+  return m;
+}
+
+template <typename P>
+__device__ __forceinline__ NodeB ld_node(P p) {
+  NodeB b;
+  b.start = p->start;
+  b.end = p->end;
+  b.off0 = p->off0;
+  b.off1 = p->off1;
+  return b;
+}
+
+template <typename P>
+__device__ __forceinline__ void atomic_add_u64(P p, uint64_t v) {
+  (void)__hip_atomic_fetch_add(pcast<unsigned long long>(p), (unsigned long long)v, __ATOMIC_RELAXED,
+                               __HIP_MEMORY_SCOPE_AGENT);
+}
+
+constexpr int kBT = 256;         // threads per block (4 waves)
+constexpr int kHashSlots = 4096; // LDS count cache for large alphabets
+
+template <typename E>
+struct Tile {
+  static constexpr int EV = 16 / (int)sizeof(E);         // elements per 16-byte vector
+  static constexpr int NCH = kTileBytes / (kBT * 16);     // vectors per thread
+  static constexpr int T = kBT * NCH * EV;               // elements per tile
+  static constexpr int W = T / 64;                       // bit words per tile
+  static constexpr int G = 64 / EV;                      // lanes whose vectors form one word
+  static constexpr int TSHIFT = __builtin_ctz((unsigned)T);
+  static_assert((1 << TSHIFT) == T, "tile");
+  static_assert(T % 512 == 0 && kL1Bits % T == 0, "tiles cover whole L2 blocks and divide L1 blocks");
+};
+
+// ---------------------------------------------------------------- block scans
+
+__device__ __forceinline__ uint32_t wave_incl_scan_u32(uint32_t x) {
+  const int lane = threadIdx.x & 63;
+#pragma unroll
+  for (int off = 1; off < 64; off <<= 1) {
+    uint32_t y = __shfl_up(x, off, 64);
+    if (lane >= off) x += y;
+  }
+  return x;
+}
+
+__device__ __forceinline__ uint64_t wave_incl_scan_u64(uint64_t x) {
+  const int lane = threadIdx.x & 63;
+#pragma unroll
+  for (int off = 1; off < 64; off <<= 1) {
+    uint64_t y = __shfl_up(x, off, 64);
+    if (lane >= off) x += y;
+  }
+  return x;
+}
+
+// Exclusive scan over the block (blockDim.x threads, multiple of 64, at most 1024); s_w holds one
+// entry per wave. Returns the exclusive prefix and the block total.
+__device__ __forceinline__ uint32_t block_excl_scan_u32(uint32_t x, uint32_t* s_w, uint32_t& total) {
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  const uint32_t inc = wave_incl_scan_u32(x);
+  if (lane == 63) s_w[wv] = inc;
+  __syncthreads();
+  uint32_t pre = 0, tot = 0;
+  for (int i = 0; i < nw; ++i) {
+    const uint32_t v = s_w[i];
+    pre += (i < wv) ? v : 0u;
+    tot += v;
+  }
+  __syncthreads();
+  total = tot;
+  return pre + inc - x;
+}
+
+__device__ __forceinline__ uint64_t block_excl_scan_u64(uint64_t x, uint64_t* s_w, uint64_t& total) {
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  const uint64_t inc = wave_incl_scan_u64(x);
+  if (lane == 63) s_w[wv] = inc;
+  __syncthreads();
+  uint64_t pre = 0, tot = 0;
+  for (int i = 0; i < nw; ++i) {
+    const uint64_t v = s_w[i];
+    pre += (i < wv) ? v : 0ull;
+    tot += v;
+  }
+  __syncthreads();
+  total = tot;
+  return pre + inc - x;
+}
+
+// ---------------------------------------------------------------- generic u64 exclusive scan
+
+constexpr int kScanPer = 16;
+constexpr int kScanChunk = kBT * kScanPer;  // elements per block
+
+__device__ __forceinline__ void scan_reduce_body(const uint64_t* __restrict__ in, uint64_t n,
+                                                 uint64_t* __restrict__ part, uint64_t bid) {
+  __shared__ uint64_t s_w[kBT / 64];
+  const uint64_t b0 = bid * kScanChunk + (uint64_t)threadIdx.x * kScanPer;
+  uint64_t s = 0;
+#pragma unroll
+  for (int i = 0; i < kScanPer; ++i)
+    if (b0 + i < n) s += in[b0 + i];
+  uint64_t tot;
+  block_excl_scan_u64(s, s_w, tot);
+  if (threadIdx.x == 0) part[bid] = tot;
+}
+
+// Single block: exclusive scan of np partial sums in place.
+__device__ __forceinline__ void scan_partials_body(uint64_t* __restrict__ part, uint64_t np) {
+  __shared__ uint64_t s_w[16];
+  uint64_t carry = 0;
+  for (uint64_t base = 0; base < np; base += 1024) {
+    const uint64_t i = base + threadIdx.x;
+    const uint64_t x = i < np ? part[i] : 0;
+    uint64_t tot;
+    const uint64_t ex = block_excl_scan_u64(x, s_w, tot);
+    if (i < np) part[i] = carry + ex;
+    carry += tot;
+  }
+}
+
+__device__ __forceinline__ void scan_down_body(const uint64_t* __restrict__ in, uint64_t n,
+                                               const uint64_t* __restrict__ part, uint64_t* __restrict__ out,
+                                               uint64_t bid) {
+  __shared__ uint64_t s_w[kBT / 64];
+  const uint64_t b0 = bid * kScanChunk + (uint64_t)threadIdx.x * kScanPer;
+  uint64_t v[kScanPer];
+  uint64_t s = 0;
+#pragma unroll
+  for (int i = 0; i < kScanPer; ++i) {
+    v[i] = (b0 + i < n) ? in[b0 + i] : 0;
+    s += v[i];
+  }
+  uint64_t tot;
+  uint64_t run = block_excl_scan_u64(s, s_w, tot) + part[bid];
+#pragma unroll
+  for (int i = 0; i < kScanPer; ++i) {
+    if (b0 + i < n) out[b0 + i] = run;
+    run += v[i];
+  }
+}
+
+// ---------------------------------------------------------------- fill
+
+__device__ __forceinline__ void fill_body(uint64_t* __restrict__ p, uint64_t n, uint64_t v, uint64_t bid,
+                                          uint64_t nblk) {
+  for (uint64_t i = bid * blockDim.x + threadIdx.x; i < n; i += nblk * blockDim.x) p[i] = v;
+}
+
+// ---------------------------------------------------------------- loads
+
+// Loads elements [q0, q0 + EV) of a tile into v; elements at or beyond cnt read as 0. `vec` says the
+// 16 bytes starting at q0 may be read as one vector (aligned and inside the buffer).
+template <typename E, typename P>
+__device__ __forceinline__ void load16(P base, uint32_t q0, uint32_t cnt, bool vec, E (&v)[16 / sizeof(E)]) {
+  constexpr int EV = 16 / (int)sizeof(E);
+  if (vec) {
+    const u32x4 x = *pcast<const u32x4>(base + q0);
+    __builtin_memcpy(v, &x, 16);
+    if (q0 + EV > cnt) {
+#pragma unroll
+      for (int e = 0; e < EV; ++e)
+        if (q0 + e >= cnt) v[e] = 0;
+    }
+  } else {
+#pragma unroll
+    for (int e = 0; e < EV; ++e) v[e] = (q0 + e < cnt) ? base[q0 + e] : (E)0;
+  }
+}
+
+// ---------------------------------------------------------------- histogram (Section 5.1.1)
+
+// Ones per tile are accumulated per chunk of kChunkTiles tiles as well, so a level's tile prefix
+// needs one launch: block b adds the chunk sums before it to the scan of its own chunk.
+constexpr int kChunkShift = 10;
+constexpr uint64_t kChunkTiles = 1ull << kChunkShift;
+
+// Persistent grid over whole tiles. Small alphabets count into LDS replicas (one per group of
+// threads, assigned round-robin; replicas are padded by one counter so equal symbols of different
+// replicas fall into different banks); large alphabets use an LDS cache of claimed symbols with
+// global atomics for the rest. Also records, per level-0 tile, the number of ones (code bit L-1).
+template <typename E, bool kSmall, typename PS, typename PH, typename PE>
+__device__ __forceinline__ void hist_body(PS sym, uint64_t n, uint32_t sigma, uint32_t L, uint32_t pow2,
+                                          uint32_t aligned, uint32_t nrep, PH hist, PH tile_cnt0, PE err,
+                                          uint64_t bid, uint64_t nblk) {
+  using TL = Tile<E>;
+  extern __shared__ uint32_t s_h[];
+  __shared__ uint32_t s_w[kBT / 64];
+  const uint32_t tid = threadIdx.x;
+  const uint32_t stride = sigma + 1;
+  const uint32_t hsize = kSmall ? nrep * stride : 2u * kHashSlots;
+  for (uint32_t i = tid; i < hsize; i += kBT) s_h[i] = 0;
+  __syncthreads();
+  uint32_t* my_h = s_h + (kSmall ? (tid % nrep) * stride : 0u);
+  uint32_t* s_keys = s_h;
+  uint32_t* s_cnts = s_h + kHashSlots;
+  const uint64_t ntiles = (n + TL::T - 1) >> TL::TSHIFT;
+  uint32_t bad = 0;
+  for (uint64_t t = bid; t < ntiles; t += nblk) {
+    const uint64_t t0 = t << TL::TSHIFT;
+    const uint32_t cnt = (uint32_t)min<uint64_t>(TL::T, n - t0);
+    uint32_t ones = 0;
+#pragma unroll 1
+    for (int k = 0; k < TL::NCH; ++k) {
+      const uint32_t q0 = (uint32_t)(k * kBT + tid) * TL::EV;
+      E v[TL::EV];
+      load16<E>(sym + t0, q0, cnt, aligned && (q0 + TL::EV <= cnt), v);
+#pragma unroll
+      for (int e = 0; e < TL::EV; ++e) {
+        const uint32_t s = (uint32_t)v[e];
+        const bool in = q0 + e < cnt;
+        if (in && s >= sigma) bad = 1;
+        if (in && s < sigma) {
+          if (L) {
+            uint32_t len;
+            const uint32_t code = encode_sym(s, sigma, L, pow2, &len);
+            ones += (code >> (L - 1)) & 1u;
+          }
+          if (kSmall) {
+            atomicAdd(&my_h[s], 1u);
+          } else {
+            const uint32_t h = (s * 2654435761u) >> (32 - 12);
+            const uint32_t old = atomicCAS(&s_keys[h], 0u, s + 1u);
+            if (old == 0u || old == s + 1u) atomicAdd(&s_cnts[h], 1u);
+            else atomic_add_u64(hist + s, 1ull);
+          }
+        }
+      }
+    }
+    uint32_t tot;
+    block_excl_scan_u32(ones, s_w, tot);
+    if (tid == 0) tile_cnt0[t] = tot;
+  }
+  if (bad) (void)__hip_atomic_fetch_or(err, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  __syncthreads();
+  if (kSmall) {
+    for (uint32_t s = tid; s < sigma; s += kBT) {
+      uint64_t c = 0;
+      for (uint32_t r = 0; r < nrep; ++r) c += s_h[r * stride + s];
+      if (c) atomic_add_u64(hist + s, c);
+    }
+  } else {
+    for (uint32_t h = tid; h < (uint32_t)kHashSlots; h += kBT) {
+      const uint32_t key = s_keys[h];
+      if (key) atomic_add_u64(hist + (key - 1u), s_cnts[h]);
+    }
+  }
+}
+
+// ---------------------------------------------------------------- node tables
+
+// Heap entry h (level l = floor(lg(h+1)), code prefix p = h + 1 - 2^l): follow p from the root with
+// the split rule of the reduced tree (left child = the largest power of two strictly below the
+// width). A prefix that reaches a leaf before level l names no node at level l.
+__device__ __forceinline__ void node_walk_body(uint32_t sigma, uint64_t nheap, const uint64_t* __restrict__ cum,
+                                               NodeB* __restrict__ ntb, uint64_t* __restrict__ zeros, uint64_t h) {
+  if (h >= nheap) return;
+  const uint32_t l = 63u - (uint32_t)__clzll(h + 1);
+  const uint64_t p = h + 1 - (1ull << l);
+  uint64_t s = 0, e = sigma;
+  bool exists = true;
+  for (int i = (int)l - 1; i >= 0; --i) {
+    if (e - s <= 1) {
+      exists = false;
+      break;
+    }
+    const uint64_t half = pow2_below(e - s);
+    if ((p >> i) & 1) s += half;
+    else e = s + half;
+  }
+  if (exists && e - s <= 1) exists = false;
+  if (exists) {
+    const uint64_t m = s + pow2_below(e - s);
+    NodeB b;
+    b.start = cum[s];
+    b.end = cum[e];
+    b.off0 = cum[m];  // left-child end, turned into off0/off1 by k_node_final
+    b.off1 = 0;
+    ntb[h] = b;
+    zeros[h] = cum[m] - cum[s];
+  } else {
+    NodeB b;
+    b.start = kNoNode;
+    b.end = 0;
+    b.off0 = 0;
+    b.off1 = 0;
+    ntb[h] = b;
+    zeros[h] = 0;
+  }
+}
+
+// zs = exclusive prefix sums of the left-child sizes in heap order, so the rank0 at a node start is
+// zs[h] - zs[first entry of the level].
+__device__ __forceinline__ void node_final_body(uint64_t nheap, const uint64_t* __restrict__ zs,
+                                                NodeB* __restrict__ ntb, NodeQ* __restrict__ ntq,
+                                                LevelMeta* __restrict__ meta, uint64_t h) {
+  if (h >= nheap) return;
+  const uint32_t l = 63u - (uint32_t)__clzll(h + 1);
+  const uint64_t base = (1ull << l) - 1;
+  NodeB b = ntb[h];
+  NodeQ q;
+  if (b.start == kNoNode) {
+    q.start = kNoNode;
+    q.r0 = kNoNode;
+    ntq[h] = q;
+    return;
+  }
+  const uint64_t r0 = zs[h] - zs[base];
+  const uint64_t mid = b.off0;
+  q.start = b.start;
+  q.r0 = r0;
+  ntq[h] = q;
+  b.off0 = b.start - r0;
+  b.off1 = mid - b.start + r0;
+  ntb[h] = b;
+  atomicMax((unsigned long long*)&meta[l].n, (unsigned long long)b.end);
+}
+
+// ---------------------------------------------------------------- per-level tile prefix
+
+// Sum of the ones of every chunk of kChunkTiles tiles of level l.
+__device__ __forceinline__ void tile_reduce_body(const LevelMeta* __restrict__ meta, uint32_t l, uint32_t tshift,
+                                                 const uint64_t* __restrict__ cnt, uint64_t* __restrict__ chunk,
+                                                 uint64_t b) {
+  __shared__ uint64_t s_w[kBT / 64];
+  const uint64_t nl = meta[l].n;
+  const uint64_t nt = (nl + (1ull << tshift) - 1) >> tshift;
+  if ((b << kChunkShift) >= nt) return;
+  constexpr int kPer = (int)(kChunkTiles / kBT);
+  const uint64_t i0 = (b << kChunkShift) + (uint64_t)threadIdx.x * kPer;
+  uint64_t sum = 0;
+#pragma unroll
+  for (int i = 0; i < kPer; ++i) sum += (i0 + i < nt) ? cnt[i0 + i] : 0ull;
+  uint64_t tot;
+  block_excl_scan_u64(sum, s_w, tot);
+  if (threadIdx.x == 0) chunk[b] = tot;
+}
+
+// Exclusive prefix of the ones per tile of level l (tile size 2^tshift). Block b scans the tiles of
+// chunk b (4 per thread) after adding the sums of the chunks before it. Levels with no element get
+// their sentinel L1/L2 entries here; otherwise the block of the last tile writes them.
+__device__ __forceinline__ void tile_scan_body(LevelMeta* __restrict__ meta, uint32_t l, uint32_t tshift,
+                                               const uint64_t* __restrict__ cnt, const uint64_t* __restrict__ chunk,
+                                               uint64_t* __restrict__ pre, uint64_t* __restrict__ L1,
+                                               uint16_t* __restrict__ L2, uint64_t b) {
+  __shared__ uint64_t s_w[kBT / 64];
+  const LevelMeta m = meta[l];
+  const uint64_t nl = m.n;
+  const uint64_t nt = (nl + (1ull << tshift) - 1) >> tshift;
+  if (nl == 0) {
+    if (b == 0 && threadIdx.x == 0) {
+      pre[0] = 0;
+      meta[l].ones = 0;
+      L1[m.l1] = 0;
+      L2[m.l2] = 0;
+    }
+    return;
+  }
+  if ((b << kChunkShift) > nt) return;
+  uint64_t before = 0;
+  for (uint64_t c = threadIdx.x; c < b; c += kBT) before += chunk[c];
+  uint64_t tot;
+  block_excl_scan_u64(before, s_w, tot);
+  before = tot;
+  constexpr int kPer = (int)(kChunkTiles / kBT);
+  const uint64_t i0 = (b << kChunkShift) + (uint64_t)threadIdx.x * kPer;
+  uint64_t v[kPer];
+  uint64_t sum = 0;
+#pragma unroll
+  for (int i = 0; i < kPer; ++i) {
+    v[i] = (i0 + i < nt) ? cnt[i0 + i] : 0ull;
+    sum += v[i];
+  }
+  uint64_t run = before + block_excl_scan_u64(sum, s_w, tot);
+#pragma unroll
+  for (int i = 0; i < kPer; ++i) {
+    if (i0 + i <= nt) pre[i0 + i] = run;
+    run += v[i];
+  }
+}
+
+// ---------------------------------------------------------------- level pass
+
+struct LevelArgs {
+  const void* in;  // level-l sequence (codes; symbols at level 0)
+  void* out;       // level-(l+1) sequence
+  uint64_t* bits;
+  uint64_t* L1;
+  uint16_t* L2;
+  uint64_t* smp;
+  LevelMeta* meta;
+  const uint64_t* pre;    // exclusive ones before each tile of this level
+  uint64_t* cnt_next;     // ones per tile of level l + 1 (accumulated)
+  const NodeB* ntb;       // node table of this level, indexed by code prefix
+  uint32_t l, L, sigma, pow2;
+  uint32_t l2shift, sshift;
+  uint32_t encode;      // level 0 of a reduced alphabet: turn symbols into codes
+  uint32_t in_vec;      // the input may be read with 16-byte vectors everywhere (padded and aligned)
+  uint32_t in_aligned;  // the input base is 16-byte aligned (vectors only inside the sequence)
+};
+
+// The level pass's view of LevelArgs, with its pointers in the global address space.
+struct LevelArgsG {
+  const WT_GLOBAL char* in;
+  WT_GLOBAL char* out;
+  WT_GLOBAL uint64_t* bits;
+  WT_GLOBAL uint64_t* L1;
+  WT_GLOBAL uint16_t* L2;
+  WT_GLOBAL uint64_t* smp;
+  WT_GLOBAL LevelMeta* meta;
+  const WT_GLOBAL uint64_t* pre;
+  WT_GLOBAL uint64_t* cnt_next;
+  const WT_GLOBAL NodeB* ntb;
+  uint32_t l, L, sigma, pow2;
+  uint32_t l2shift, sshift;
+  uint32_t encode, in_vec, in_aligned;
+};
+
+__device__ __forceinline__ LevelArgsG to_global(const LevelArgs& a) {
+  LevelArgsG g;
+  g.in = (const WT_GLOBAL char*)a.in;
+  g.out = (WT_GLOBAL char*)a.out;
+  g.bits = (WT_GLOBAL uint64_t*)a.bits;
+  g.L1 = (WT_GLOBAL uint64_t*)a.L1;
+  g.L2 = (WT_GLOBAL uint16_t*)a.L2;
+  g.smp = (WT_GLOBAL uint64_t*)a.smp;
+  g.meta = (WT_GLOBAL LevelMeta*)a.meta;
+  g.pre = (const WT_GLOBAL uint64_t*)a.pre;
+  g.cnt_next = (WT_GLOBAL uint64_t*)a.cnt_next;
+  g.ntb = (const WT_GLOBAL NodeB*)a.ntb;
+  g.l = a.l;
+  g.L = a.L;
+  g.sigma = a.sigma;
+  g.pow2 = a.pow2;
+  g.l2shift = a.l2shift;
+  g.sshift = a.sshift;
+  g.encode = a.encode;
+  g.in_vec = a.in_vec;
+  g.in_aligned = a.in_aligned;
+  return g;
+}
+
+// Adds, for the lanes in `cls`, their next-level ones (the bit `nbit`, or `cnt_lane` when nbit is
+// unused) per destination tile to a running per-wave (tile, count) pair, flushing it to the global
+// tile counter when the tile changes. Destinations increase with the processing order, so each tile
+// is flushed about once per wave, and a tile counter sees few writers.
+template <typename P>
+__device__ __forceinline__ void count_next(uint64_t cls, uint64_t dt, uint32_t nbit, uint32_t lane,
+                                           uint64_t& cur_tile, uint32_t& cur_c, P cnt, uint32_t cnt_lane) {
+  const uint32_t mine = nbit + cnt_lane;
+  while (cls) {
+    const int leader = __ffsll((unsigned long long)cls) - 1;
+    const uint64_t ldt = __shfl(dt, leader, 64);
+    const bool in = ((cls >> lane) & 1ull) && dt == ldt;
+    const uint64_t same = __ballot(in);
+    uint32_t c1 = in ? mine : 0u;
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) c1 += __shfl_xor(c1, off, 64);
+    if (ldt == cur_tile) {
+      cur_c += c1;
+    } else {
+      if (cur_c && lane == 0) atomic_add_u64(cnt + cur_tile, cur_c);
+      cur_tile = ldt;
+      cur_c = c1;
+    }
+    cls &= ~same;
+  }
+}
+
+// Tile-local rank1 at x in [0, T]: ones in the words before x / 64 plus the low bits of that word.
+__device__ __forceinline__ uint32_t r1loc(const uint64_t* __restrict__ sw, const uint32_t* __restrict__ sp,
+                                          uint32_t x) {
+  const uint32_t wi = x >> 6, bi = x & 63u;
+  return sp[wi] + popc64(sw[wi] & ((1ull << bi) - 1ull));
+}
+
+struct Seg {
+  uint32_t a, z, zs, pad;  // tile-local segment [a, z) and its zeros
+  uint64_t d0, d1;         // level-(l+1) destinations of its first zero and first one
+};
+constexpr int kSegMax = 128;  // node segments per tile handled by the vector write-out
+static_assert(2 * kSegMax <= kBT, "one thread per run in the run prefix");
+
+// A lane meets the node of its element at tile position q: the node's segment [sa, sz) of the tile,
+// its zeros zs and the tile-local rank1 R1a at its start. The lane holding the segment's first
+// element records the segment's two runs.
+__device__ __forceinline__ void enter_node(const NodeB nb, uint32_t q, uint64_t t0, uint32_t cnt, uint64_t G0,
+                                           uint64_t G1, const uint64_t* s_words, const uint32_t* s_wpre,
+                                           Seg* s_seg, uint32_t* s_nseg, uint32_t& sa, uint32_t& zs,
+                                           uint32_t& R1a) {
+  sa = (uint32_t)(nb.start > t0 ? min(nb.start - t0, (uint64_t)cnt) : 0ull);
+  const uint32_t sz = (uint32_t)(nb.end > t0 ? min(nb.end - t0, (uint64_t)cnt) : 0ull);
+  R1a = r1loc(s_words, s_wpre, sa);
+  zs = (sz - r1loc(s_words, s_wpre, sz)) - (sa - R1a);
+  if (q == sa) {
+    const uint32_t idx = atomicAdd(s_nseg, 1u);
+    if (idx < (uint32_t)kSegMax) {
+      Seg g;
+      g.a = sa;
+      g.z = sz;
+      g.zs = zs;
+      g.pad = 0;
+      g.d0 = nb.off0 + G0 + (sa - R1a);
+      g.d1 = nb.off1 + G1 + R1a;
+      s_seg[idx] = g;
+    }
+  }
+}
+
+// Element e of a 16-byte vector of E (e a compile-time constant after unrolling).
+template <typename E>
+__device__ __forceinline__ uint32_t vec_elem(const uint4& x, uint32_t e) {
+  constexpr uint32_t per = 4 / sizeof(E);  // elements per dword
+  const uint32_t d = e / per;
+  const uint32_t dw = d < 2 ? (d == 0 ? x.x : x.y) : (d == 2 ? x.z : x.w);
+  if constexpr (sizeof(E) == 4) return dw;
+  else return (dw >> ((e % per) * 8 * sizeof(E))) & ((1u << (8 * sizeof(E))) - 1u);
+}
+
+// Element e of the 128-bit value (lo, hi) for a run-time e, by shifting (no indexed access, which
+// would put the vector in scratch memory).
+template <typename E>
+__device__ __forceinline__ uint32_t elem128(uint64_t lo, uint64_t hi, uint32_t e) {
+  const uint32_t sh = e * 8u * (uint32_t)sizeof(E);
+  const uint64_t v = sh < 64 ? (sh ? (lo >> sh) | (hi << (64 - sh)) : lo) : (hi >> (sh - 64));
+  return (uint32_t)v & (uint32_t)((1ull << (8 * sizeof(E))) - 1ull);
+}
+
+// One block per tile of T elements of level l:
+//  1. coalesced 16-byte loads (NCH per thread, kept in registers); each vector gives EV bits and G
+//     neighbouring lanes OR them into one 64-bit word of the level;
+//  2. block scan of the word popcounts -> tile-local rank1 at every word;
+//  3. bit words, L2 entries (ones since the enclosing L1 block start), the L1 entry when the tile
+//     starts an L1 block, select samples where the global one/zero count crosses a multiple of s;
+//  4. stable partition into level l + 1: every element goes to off_b[node] + rank_b(position).
+//     a. staged in LDS in destination order: a node segment of the tile keeps its slot range and is
+//        reordered zeros first (each lane walks its own vectors with a running rank);
+//     b. runs (segment, bit) are contiguous in the destination: each lane writes one aligned
+//        16-byte chunk of a run (element stores only at run edges), and the next level's ones per
+//        destination tile are counted on the way.
+// Per-tree build state of a batched (forest) build: the tree's parts and scratch, as the single-tree
+// build keeps them, for device-side derivation of every phase's arguments.
+struct TreeB {
+  const void* sym;
+  uint64_t n;
+  uint32_t sigma, L, pow2, aligned;
+  uint32_t l2shift, sshift, nrep, tshift;
+  LevelMeta* meta;
+  uint64_t* cum;
+  NodeQ* nodes;
+  uint64_t* bits;
+  uint64_t* L1;
+  uint16_t* L2;
+  uint64_t* smp;
+  uint64_t words_per_level, l1_per_level, l2_per_level, smp_per_level;
+  void* seq[2];
+  uint64_t* clear;  // [hist | tile counts | err], cleared at the start
+  uint64_t clear_n;
+  uint64_t* hist;
+  uint64_t* tcnt;
+  uint64_t* tpre;
+  NodeB* ntb;
+  uint64_t* z;
+  uint64_t* zs;
+  uint64_t* part;
+  uint32_t* err;
+  uint64_t ntiles, nchunks, cstride, nheap;
+};
+
+// Blocks of a forest launch: block g belongs to tree bmap[g] and is block g - boff[tree] of it.
+struct ForestGrid {
+  const TreeB* tb;
+  const uint32_t* bmap;
+  const uint32_t* boff;
+  uint32_t l;
+  uint32_t pad;
+};
+
+// Arguments of the level-l pass of a tree of a forest build (as the single-tree build sets them).
+__device__ __forceinline__ LevelArgs forest_level_args(const TreeB& b, uint32_t l) {
+  LevelArgs a;
+  a.in = (l == 0 ? b.sym : b.seq[(l - 1) & 1]);
+  a.out = (l + 1 < b.L) ? (b.seq[l & 1]) : nullptr;
+  a.bits = (b.bits);
+  a.L1 = (b.L1);
+  a.L2 = (b.L2);
+  a.smp = (b.smp);
+  a.meta = (b.meta);
+  a.pre = (b.tpre + (uint64_t)l * (b.ntiles + 1));
+  a.cnt_next = (l + 1 < b.L) ? (b.tcnt + (uint64_t)(l + 1) * b.cstride) : nullptr;
+  a.ntb = (b.ntb + ((1ull << l) - 1));
+  a.l = l;
+  a.L = b.L;
+  a.sigma = b.sigma;
+  a.pow2 = b.pow2;
+  a.l2shift = b.l2shift;
+  a.sshift = b.sshift;
+  a.encode = (l == 0 && !b.pow2) ? 1u : 0u;
+  a.in_vec = l == 0 ? 0u : 1u;
+  a.in_aligned = l == 0 ? b.aligned : 1u;
+  return a;
+}
+
+// The body stays in the kernel (as a device function it needs far more registers).
+template <typename E, bool kForest>
+__global__ __launch_bounds__(kBT) void k_level(LevelArgs a_one, ForestGrid fg) {
+  LevelArgsG a;
+  uint64_t t;
+  if constexpr (kForest) {
+    const uint32_t j = fg.bmap[blockIdx.x];
+    t = blockIdx.x - fg.boff[j];
+    a = to_global(forest_level_args(fg.tb[j], fg.l));
+  } else {
+    a = to_global(a_one);
+    t = blockIdx.x;
+  }
+  using TL = Tile<E>;
+  constexpr int T = TL::T, W = TL::W, EV = TL::EV, G = TL::G, NCH = TL::NCH;
+  __shared__ __align__(16) E s_stage[T + 16 / sizeof(E) + 4];  // + slack for the 20-byte chunk reads
+  __shared__ uint64_t s_words[W + 1];  // entry W: 0, so ranks are defined at x = T
+  __shared__ uint32_t s_wpre[W + 1];   // entry W: ones of the tile
+  __shared__ uint32_t s_w[kBT / 64];
+  __shared__ Seg s_seg[kSegMax];
+  __shared__ uint32_t s_cp[2 * kSegMax + 1];
+  __shared__ uint32_t s_nseg;
+  __shared__ uint64_t s_node[2];  // node of the tile's first and last element
+  __shared__ uint64_t s_dst[2];   // single-node tile: destinations of its first zero and first one
+  __shared__ uint32_t s_nc[4];    // single-node tile: next-level ones per (run, destination tile)
+
+  const uint32_t tid = threadIdx.x, lane = tid & 63u;
+  const uint32_t l = a.l, L = a.L;
+  const LevelMeta m = ld_meta(a.meta + l);
+  const uint64_t nl = m.n;
+  const uint64_t t0 = t << TL::TSHIFT;
+  if (t0 >= nl) return;
+  // independent scalars first, so their latency overlaps the tile loads
+  const bool last = l + 1 >= L;
+  const uint64_t G1 = a.pre[t];  // ones of the level before the tile
+  const uint64_t l1val = a.pre[t & ~(uint64_t)((kL1Bits / T) - 1)];
+  const uint64_t n_next = last ? 0ull : a.meta[l + 1].n;
+  const uint32_t cnt = (uint32_t)min<uint64_t>((uint64_t)T, nl - t0);
+  const uint32_t bsh = L - 1 - l;
+  if (tid == 0) s_nseg = 0;
+
+  // 1. load, encode (level 0 of a reduced alphabet), bit words
+  const WT_GLOBAL E* in = pcast<const E>(a.in) + t0;
+  uint4 vx[NCH];
+#pragma unroll
+  for (int k = 0; k < NCH; ++k) {
+    const uint32_t q0 = (uint32_t)(k * kBT + tid) * EV;
+    E v[EV];
+    load16<E>(in, q0, cnt, a.in_vec || (a.in_aligned && q0 + EV <= cnt), v);
+    if (a.encode) {
+#pragma unroll
+      for (int e = 0; e < EV; ++e) {
+        uint32_t s = (uint32_t)v[e];
+        if (s >= a.sigma) s = 0;  // out-of-range input: the build reports an error; keep indices valid
+        uint32_t len;
+        v[e] = (E)encode_sym(s, a.sigma, L, a.pow2, &len);
+      }
+    }
+    __builtin_memcpy(&vx[k], v, 16);
+  }
+#pragma unroll
+  for (int k = 0; k < NCH; ++k) {
+    const uint32_t q0 = (uint32_t)(k * kBT + tid) * EV;
+    uint32_t mask = 0;
+#pragma unroll
+    for (int e = 0; e < EV; ++e)
+      if (q0 + e < cnt) mask |= ((vec_elem<E>(vx[k], e) >> bsh) & 1u) << e;
+    uint64_t word = (uint64_t)mask << ((tid % G) * EV);
+#pragma unroll
+    for (int off = 1; off < G; off <<= 1) word |= __shfl_xor(word, off, 64);
+    if (tid % G == 0) s_words[k * (kBT / G) + tid / G] = word;
+    if (q0 < cnt && q0 + EV > cnt - 1) {
+      const uint32_t cx = elem128<E>(((uint64_t)vx[k].y << 32) | vx[k].x, ((uint64_t)vx[k].w << 32) | vx[k].z,
+                                     cnt - 1 - q0);
+      s_node[1] = l ? ((uint64_t)cx >> (L - l)) & ((1ull << l) - 1ull) : 0ull;
+    }
+    if (q0 == 0) s_node[0] = l ? ((uint64_t)vec_elem<E>(vx[k], 0) >> (L - l)) & ((1ull << l) - 1ull) : 0ull;
+  }
+  if (tid < 4) s_nc[tid] = 0;
+  __syncthreads();
+  // a tile inside one node (the rule at shallow levels) takes the fast path: two runs, no segments
+  const bool single = s_node[0] == s_node[1];
+  if (single && !last && tid == 0) {
+    const NodeB nb = ld_node(a.ntb + s_node[0]);
+    s_dst[0] = nb.off0 + (t0 - G1);
+    s_dst[1] = nb.off1 + G1;
+  }
+
+  // 2. tile-local rank1 at every word
+  uint32_t tile_ones;
+  {
+    const uint32_t pc = (tid < (uint32_t)W) ? popc64(s_words[tid]) : 0u;
+    const uint32_t ex = block_excl_scan_u32(pc, s_w, tile_ones);
+    if (tid < (uint32_t)W) s_wpre[tid] = ex;
+    if (tid == 0) {
+      s_wpre[W] = tile_ones;
+      s_words[W] = 0;
+    }
+  }
+  __syncthreads();
+
+  // 3. bits and directory
+  const uint64_t G0 = t0 - G1;  // zeros of the level before the tile
+  if (tid < (uint32_t)W) {
+    const uint64_t word = s_words[tid];
+    const uint64_t gw = ((uint64_t)t * W) + tid;
+    a.bits[m.bits + gw] = word;
+    const uint32_t q = tid * 64u;
+    if (q < cnt) {
+      const uint64_t ones_before = G1 + s_wpre[tid];
+      const uint32_t l2w_shift = a.l2shift - 6;
+      if ((gw & ((1ull << l2w_shift) - 1)) == 0) a.L2[m.l2 + (gw >> l2w_shift)] = (uint16_t)(ones_before - l1val);
+      const uint32_t sh = a.sshift;
+      const uint32_t pc = popc64(word);
+      const uint64_t k1 = (ones_before + pc) >> sh;
+      if (k1 > (ones_before >> sh)) {
+        const uint32_t r = (uint32_t)((k1 << sh) - ones_before);
+        a.smp[m.smp + k1 - 1] = t0 + q + select_in_word(word, r);
+      }
+      const uint32_t vb = min(64u, cnt - q);
+      const uint64_t zw = ~word & (vb == 64u ? ~0ull : ((1ull << vb) - 1ull));
+      const uint64_t zeros_before = t0 + q - ones_before;
+      const uint64_t k0 = (zeros_before + popc64(zw)) >> sh;
+      if (k0 > (zeros_before >> sh)) {
+        const uint32_t r = (uint32_t)((k0 << sh) - zeros_before);
+        a.smp[m.smp + m.smp_cap - k0] = t0 + q + select_in_word(zw, r);
+      }
+    }
+  }
+  if (tid == 0) {
+    if ((t0 & (kL1Bits - 1)) == 0) a.L1[m.l1 + (t0 >> kL1Shift)] = G1;
+    if (t0 + cnt == nl) {
+      // last tile: total ones and the sentinel L1/L2 entries that make rank defined at i = n_l
+      const uint64_t total = G1 + tile_ones;
+      a.meta[l].ones = total;
+      a.L1[m.l1 + ((nl + kL1Bits - 1) >> kL1Shift)] = total;
+      const uint64_t j = (nl + (1ull << a.l2shift) - 1) >> a.l2shift;
+      const uint64_t blk = (j << a.l2shift) >> kL1Shift;
+      const uint64_t lv = ((blk << kL1Shift) >= nl) ? total : a.pre[blk << (kL1Shift - TL::TSHIFT)];
+      a.L2[m.l2 + j] = (uint16_t)(total - lv);
+    }
+  }
+  if (last) return;
+
+  // 4a. staging
+  const uint32_t nbsh = L - 2 - l;
+  const uint64_t pmask = (1ull << l) - 1ull;
+  if (single) {
+    // zeros fill slots [0, Z), ones [Z, cnt)
+    const uint32_t Z = cnt - tile_ones;
+#pragma unroll 1
+    for (int k = 0; k < NCH; ++k) {
+      const uint32_t q0 = (uint32_t)(k * kBT + tid) * EV;
+      if (q0 < cnt) {
+        // vector k without indexed access (an indexed register array would go to scratch)
+        uint4 x = vx[0];
+#pragma unroll
+        for (int kk = 1; kk < NCH; ++kk)
+          if (k == kk) x = vx[kk];
+        uint32_t r1 = r1loc(s_words, s_wpre, q0);
+        uint32_t r0 = q0 - r1;
+        const uint32_t nv = min((uint32_t)EV, cnt - q0);
+#pragma unroll
+        for (int e = 0; e < EV; ++e) {
+          if ((uint32_t)e < nv) {
+            const uint32_t code = vec_elem<E>(x, e);
+            const uint32_t b = (code >> bsh) & 1u;
+            s_stage[b ? Z + r1 : r0] = (E)code;
+            r1 += b;
+            r0 += 1u - b;
+          }
+        }
+      }
+    }
+    __syncthreads();
+    // 4b. write-out of the two runs, one 16-byte destination chunk per lane; the next level's ones
+    //     are counted per (run, destination tile): a run of at most T elements touches two tiles
+    const uint64_t d0 = s_dst[0], d1 = s_dst[1];
+    WT_GLOBAL char* outb = a.out;
+    const uint32_t* st32 = reinterpret_cast<const uint32_t*>(s_stage);
+    const uint32_t len0 = d0 < n_next ? (uint32_t)min<uint64_t>(Z, n_next - d0) : 0u;
+    const uint32_t len1 = d1 < n_next ? (uint32_t)min<uint64_t>(cnt - Z, n_next - d1) : 0u;
+    const uint32_t C0 = len0 ? (uint32_t)(((d0 + len0 - 1) * sizeof(E) >> 4) - ((d0 * sizeof(E)) >> 4) + 1) : 0u;
+    const uint32_t C1 = len1 ? (uint32_t)(((d1 + len1 - 1) * sizeof(E) >> 4) - ((d1 * sizeof(E)) >> 4) + 1) : 0u;
+    constexpr uint32_t kTileB = (uint32_t)T * (uint32_t)sizeof(E);  // bytes of a destination tile
+    uint32_t cnt4[4] = {0u, 0u, 0u, 0u};                          // (run, first / second tile)
+    for (uint32_t c = tid; c < C0 + C1; c += kBT) {
+      const bool bb = c >= C0;
+      const uint64_t d = bb ? d1 : d0;
+      const uint32_t len = bb ? len1 : len0;
+      const uint32_t slot0 = bb ? Z : 0u;
+      const uint64_t db = d * sizeof(E), de = (d + len) * sizeof(E);
+      const uint64_t cb = ((db >> 4) + (bb ? c - C0 : c)) << 4;
+      const uint64_t blo = max(db, cb), bhi = min(de, cb + 16);
+      const uint32_t src = slot0 * (uint32_t)sizeof(E) + (uint32_t)(blo - db);
+      uint32_t nb = 0;
+      if (blo == cb && bhi == cb + 16) {
+        const uint32_t dw = src >> 2, sh = src & 3u;
+        const uint32_t x0 = st32[dw], x1 = st32[dw + 1], x2 = st32[dw + 2], x3 = st32[dw + 3], x4 = st32[dw + 4];
+        uint4 y;
+        y.x = __builtin_amdgcn_alignbyte(x1, x0, sh);
+        y.y = __builtin_amdgcn_alignbyte(x2, x1, sh);
+        y.z = __builtin_amdgcn_alignbyte(x3, x2, sh);
+        y.w = __builtin_amdgcn_alignbyte(x4, x3, sh);
+        st16(outb + cb, y);
+        // next-level bits of the 16/w elements: one bit per element, popcount per dword
+        constexpr uint32_t kLow = sizeof(E) == 1 ? 0x01010101u : (sizeof(E) == 2 ? 0x00010001u : 1u);
+        nb = __popc((y.x >> nbsh) & kLow) + __popc((y.y >> nbsh) & kLow) + __popc((y.z >> nbsh) & kLow) +
+             __popc((y.w >> nbsh) & kLow);
+      } else {
+        const uint32_t s0 = src / (uint32_t)sizeof(E);
+        WT_GLOBAL E* oe = pcast<E>(outb);
+        const uint64_t e0 = blo / sizeof(E), e1 = bhi / sizeof(E);
+        for (uint64_t e = e0; e < e1; ++e) {
+          const E v = s_stage[s0 + (uint32_t)(e - e0)];
+          oe[e] = v;
+          nb += ((uint32_t)v >> nbsh) & 1u;
+        }
+      }
+      const uint32_t sub = (uint32_t)(cb / kTileB - db / kTileB);  // 0 or 1
+      cnt4[(bb ? 2 : 0) + sub] += nb;
+    }
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      uint32_t v = cnt4[r];
+#pragma unroll
+      for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+      if (lane == 0 && v) atomicAdd(&s_nc[r], v);
+    }
+    __syncthreads();
+    if (tid < 4) {
+      const uint32_t c = s_nc[tid];
+      const uint64_t d = (tid < 2) ? d0 : d1;
+      if (c && d < n_next)
+        atomic_add_u64(a.cnt_next + (d >> TL::TSHIFT) + (tid & 1u), c);
+    }
+    return;
+  }
+  {
+    uint64_t curN = ~0ull;
+    uint32_t sa = 0, zs = 0, R1a = 0;
+#pragma unroll
+    for (int k = 0; k < NCH; ++k) {
+      const uint32_t q0 = (uint32_t)(k * kBT + tid) * EV;
+      if (q0 < cnt) {
+        uint32_t r1 = r1loc(s_words, s_wpre, q0);
+        const uint32_t nv = min((uint32_t)EV, cnt - q0);
+        const uint64_t lo = ((uint64_t)vx[k].y << 32) | vx[k].x, hi = ((uint64_t)vx[k].w << 32) | vx[k].z;
+        const uint32_t cf = vec_elem<E>(vx[k], 0), cl = elem128<E>(lo, hi, nv - 1);
+        const uint64_t Nf = l ? ((uint64_t)cf >> (L - l)) & pmask : 0ull;
+        const uint64_t Nl = l ? ((uint64_t)cl >> (L - l)) & pmask : 0ull;
+        if (Nf == Nl) {
+          // the whole vector lies in one node
+          if (Nf != curN) enter_node(ld_node(a.ntb + Nf), q0, t0, cnt, G0, G1, s_words, s_wpre, s_seg, &s_nseg, sa, zs, R1a), curN = Nf;
+          const uint32_t b0 = R1a, b1 = sa + zs - R1a;  // slot = b0 + rank0 or b1 + rank1 (tile-local)
+#pragma unroll
+          for (int e = 0; e < EV; ++e) {
+            if ((uint32_t)e < nv) {
+              const uint32_t code = vec_elem<E>(vx[k], e);
+              const uint32_t b = (code >> bsh) & 1u;
+              const uint32_t q = q0 + e;
+              const uint32_t slot = b ? b1 + r1 : b0 + (q - r1);
+              s_stage[min(slot, (uint32_t)T - 1u)] = (E)code;
+              r1 += b;
+            }
+          }
+        } else {
+          for (uint32_t e = 0; e < nv; ++e) {
+            const uint32_t code = elem128<E>(lo, hi, e);
+            const uint32_t b = (code >> bsh) & 1u;
+            const uint32_t q = q0 + e;
+            const uint64_t N = l ? ((uint64_t)code >> (L - l)) & pmask : 0ull;
+            if (N != curN) enter_node(ld_node(a.ntb + N), q, t0, cnt, G0, G1, s_words, s_wpre, s_seg, &s_nseg, sa, zs, R1a), curN = N;
+            const uint32_t slot = b ? sa + zs + (r1 - R1a) : sa + ((q - r1) - (sa - R1a));
+            s_stage[min(slot, (uint32_t)T - 1u)] = (E)code;
+            r1 += b;
+          }
+        }
+      }
+    }
+  }
+  __syncthreads();
+  const uint32_t nseg = s_nseg;
+  uint64_t cur_tile = ~0ull;
+  uint32_t cur_c = 0;
+  WT_GLOBAL char* outb = a.out;
+
+  if (nseg <= (uint32_t)kSegMax) {
+    // 4b. runs (segment, bit) -> their 16-byte destination chunks, prefix over runs
+    {
+      const uint32_t r = tid;
+      uint32_t nch = 0;
+      if (r < 2 * nseg) {
+        const Seg g = s_seg[r >> 1];
+        const uint32_t bb = r & 1u;
+        const uint64_t d = bb ? g.d1 : g.d0;
+        const uint32_t len = d < n_next ? (uint32_t)min<uint64_t>(bb ? g.z - g.a - g.zs : g.zs, n_next - d) : 0u;
+        if (len) nch = (uint32_t)(((d + len - 1) * sizeof(E) >> 4) - ((d * sizeof(E)) >> 4) + 1);
+      }
+      uint32_t total;
+      const uint32_t ex = block_excl_scan_u32(nch, s_w, total);
+      if (r < 2 * nseg) s_cp[r] = ex;
+      if (tid == 0) s_cp[2 * nseg] = total;
+    }
+    __syncthreads();
+    const uint32_t nrun = 2 * nseg;
+    const uint32_t C = s_cp[nrun];
+    const uint32_t* st32 = reinterpret_cast<const uint32_t*>(s_stage);
+    // 4c. write-out: one 16-byte destination chunk per lane
+    for (uint32_t c0 = 0; c0 < C; c0 += kBT) {
+      const uint32_t c = c0 + tid;
+      const bool active = c < C;
+      uint32_t nb1 = 0;
+      uint64_t chunk = 0;
+      if (active) {
+        uint32_t lo = 0, hi = nrun - 1;  // largest run with cp <= c
+        while (lo < hi) {
+          const uint32_t mid = (lo + hi + 1) >> 1;
+          if (s_cp[mid] <= c) lo = mid;
+          else hi = mid - 1;
+        }
+        const Seg g = s_seg[lo >> 1];
+        const uint32_t bb = lo & 1u;
+        const uint64_t d = bb ? g.d1 : g.d0;
+        const uint32_t len = (uint32_t)min<uint64_t>(bb ? g.z - g.a - g.zs : g.zs, n_next - d);
+        const uint32_t slot0 = bb ? g.a + g.zs : g.a;
+        const uint64_t db = d * sizeof(E), de = (d + len) * sizeof(E);
+        chunk = (db >> 4) + (c - s_cp[lo]);
+        const uint64_t cb = chunk << 4;
+        const uint64_t blo = max(db, cb), bhi = min(de, cb + 16);
+        const uint32_t src = slot0 * (uint32_t)sizeof(E) + (uint32_t)(blo - db);  // LDS byte of blo
+        if (blo == cb && bhi == cb + 16) {
+          const uint32_t dw = src >> 2, sh = src & 3u;
+          const uint32_t x0 = st32[dw], x1 = st32[dw + 1], x2 = st32[dw + 2], x3 = st32[dw + 3],
+                         x4 = st32[dw + 4];
+          uint4 y;
+          y.x = __builtin_amdgcn_alignbyte(x1, x0, sh);
+          y.y = __builtin_amdgcn_alignbyte(x2, x1, sh);
+          y.z = __builtin_amdgcn_alignbyte(x3, x2, sh);
+          y.w = __builtin_amdgcn_alignbyte(x4, x3, sh);
+          st16(outb + cb, y);
+#pragma unroll
+          for (int e = 0; e < EV; ++e) nb1 += (vec_elem<E>(y, e) >> nbsh) & 1u;
+        } else {
+          const uint32_t s0 = src / (uint32_t)sizeof(E);
+          WT_GLOBAL E* oe = pcast<E>(outb);
+          const uint64_t e0 = blo / sizeof(E), e1 = bhi / sizeof(E);
+          for (uint64_t e = e0; e < e1; ++e) {
+            const E v = s_stage[s0 + (uint32_t)(e - e0)];
+            oe[e] = v;
+            nb1 += ((uint32_t)v >> nbsh) & 1u;
+          }
+        }
+      }
+      const uint64_t dt = (chunk << 4) / ((uint64_t)T * sizeof(E));
+      count_next(__ballot(active), dt, 0u, lane, cur_tile, cur_c, a.cnt_next, nb1);
+    }
+  } else {
+    // 4b'. many small nodes in this tile: element stores in slot order, destination per slot
+    const uint32_t wv = tid >> 6;
+    constexpr uint32_t kPerWave = T / (kBT / 64);
+    uint64_t curN = ~0ull, D0 = 0, D1 = 0;
+    uint32_t sa = 0, zs = 0;
+    for (uint32_t base = wv * kPerWave; base < (wv + 1) * kPerWave; base += 64) {
+      if (base >= cnt) break;
+      const uint32_t j = base + lane;
+      bool cont = false;
+      uint64_t dest = 0;
+      uint32_t nbit = 0;
+      if (j < cnt) {
+        const uint32_t code = (uint32_t)s_stage[j];
+        const uint64_t N = l ? ((uint64_t)code >> (L - l)) & pmask : 0ull;
+        if (N != curN) {
+          const NodeB nb = ld_node(a.ntb + N);
+          sa = (uint32_t)(nb.start > t0 ? min(nb.start - t0, (uint64_t)cnt) : 0ull);
+          const uint32_t sz = (uint32_t)(nb.end > t0 ? min(nb.end - t0, (uint64_t)cnt) : 0ull);
+          const uint32_t R1a = r1loc(s_words, s_wpre, sa);
+          zs = (sz - r1loc(s_words, s_wpre, sz)) - (sa - R1a);
+          D0 = nb.off0 + G0 + (sa - R1a);
+          D1 = nb.off1 + G1 + R1a;
+          curN = N;
+        }
+        dest = (j < sa + zs) ? D0 + (j - sa) : D1 + (j - sa - zs);
+        cont = dest < n_next;
+        if (cont) {
+          pcast<E>(outb)[dest] = (E)code;
+          nbit = (code >> nbsh) & 1u;
+        }
+      }
+      count_next(__ballot(cont), dest >> TL::TSHIFT, nbit, lane, cur_tile, cur_c, a.cnt_next, 0u);
+    }
+  }
+  if (lane == 0 && cur_c) atomic_add_u64(a.cnt_next + cur_tile, cur_c);
+}
+}  // namespace wt

@@ -13,6 +13,7 @@ struct wt_tree {
   uint32_t L = 0, w = 0, l2_bits = 512, srate = 4096, pow2 = 1;
   int device = 0;
   void* block = nullptr;  // one allocation holding every device part of the tree
+  bool borrowed = false;  // the parts live in a forest's allocation (freed with the forest)
   size_t block_bytes = 0;
   wt::TreeDev dev{};
   wt::LevelMeta hmeta[WT_MAX_LEVELS]{};

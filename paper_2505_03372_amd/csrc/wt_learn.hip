@@ -10,17 +10,17 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstddef>
 #include <cstring>
 #include <vector>
 
 #include "wt_host.h"
 #include "wt_internal.h"
+#include "wt_learn_dev.h"
 #include "wt_query_dev.h"
 
 namespace wt {
 
-constexpr int kH = 16;           // hidden units
-constexpr int kNP = 3 * kH + 1;  // parameters: w1[16], b1[16], w2[16], b2
 constexpr int kPMax = 2048;      // training points per model
 constexpr int kLT = 256;         // threads of the training block
 
@@ -40,6 +40,7 @@ struct LearnModel {  // 320 bytes; the fields a query reads sit in the first 240
   float pad1[13];
 };
 static_assert(sizeof(LearnModel) == 320, "model size");
+
 
 __device__ __forceinline__ float mlp_eval(const float* __restrict__ p, float u) {
   float y = p[3 * kH];
@@ -156,12 +157,6 @@ __global__ void k_learn_setup(uint32_t sigma, uint32_t L, const uint64_t* __rest
   models[slot] = M;
 }
 
-// Count of side-b bits of a level before position x (x a multiple of the L2 block, x <= n_l).
-template <int L2S>
-__device__ __forceinline__ uint64_t count_before(const TreeDev& d, const LevelMeta& m, uint32_t b, uint64_t x) {
-  const uint64_t r1 = d.L1[m.l1 + (x >> kL1Shift)] + d.L2[m.l2 + (x >> L2S)];
-  return b ? r1 : x - r1;
-}
 
 // Training points of one model: the node-local side-b rank at every L2 boundary inside the node
 // (evenly subsampled to at most kPMax - 2) plus the two ends (0, 0) and (1, 1).
@@ -244,18 +239,68 @@ __global__ __launch_bounds__(kLT) void k_learn_train(LearnModel* __restrict__ mo
   if (threadIdx.x == 0) M.loss = loss;
 }
 
-// Prediction error in L2 blocks at every L2 boundary inside the node, for the trained model and for
-// the starting point; sets the correction budget eps = ceil(max error) + 2.
+// Piecewise-linear form of every trained network (one thread per model), computed in FP64: the
+// switch points inside (0, 1), sorted, and on each piece the sum of the active units' slopes and
+// intercepts (a unit is active on a piece when it is positive at the piece's midpoint).
+__global__ void k_learn_compile(const LearnModel* __restrict__ models, LearnQ* __restrict__ qm, uint64_t nmodels) {
+  const uint64_t slot = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (slot >= nmodels) return;
+  const LearnModel& M = models[slot];
+  LearnQ Q;
+  Q.start = M.start;
+  Q.len = M.len;
+  Q.rank0 = M.rank0;
+  Q.eps = M.eps < 0 ? -1 : 0;
+  Q.side = M.side;
+  Q.cntf = (float)M.cnt;
+  Q.pad0 = 0;
+  Q.pad1 = 0;
+  double t[kH];
+  uint32_t m = 0;
+  for (int k = 0; k < kH; ++k) {
+    const double w = M.p[k], c = M.p[kH + k];
+    if (w != 0.0) {
+      const double x = -c / w;
+      if (x > 0.0 && x < 1.0) t[m++] = x;
+    }
+  }
+  for (uint32_t i = 1; i < m; ++i) {  // insertion sort (at most 16)
+    const double x = t[i];
+    uint32_t k = i;
+    for (; k > 0 && t[k - 1] > x; --k) t[k] = t[k - 1];
+    t[k] = x;
+  }
+  for (uint32_t s = 0; s <= m; ++s) {
+    const double lo = s ? t[s - 1] : 0.0, hi = s < m ? t[s] : 1.0;
+    const double mid = 0.5 * (lo + hi);
+    double A = 0.0, C = M.p[3 * kH];
+    for (int k = 0; k < kH; ++k) {
+      const double w = M.p[k], c = M.p[kH + k], o = M.p[2 * kH + k];
+      if (w * mid + c > 0.0) {
+        A += o * w;
+        C += o * c;
+      }
+    }
+    Q.piece[s] = make_float2((float)A, (float)C);
+  }
+  for (uint32_t s = m + 1; s <= (uint32_t)kH; ++s) Q.piece[s] = Q.piece[m];
+  for (uint32_t s = 0; s < (uint32_t)kH; ++s) Q.knot[s] = s < m ? (float)t[s] : 2.f;
+  Q.npieces = m + 1;
+  qm[slot] = Q;
+}
+
+// Prediction error in L2 blocks at every L2 boundary inside the node, for the compiled trained model
+// (the evaluation queries use) and for the starting point; sets the correction budget
+// eps = ceil(max error) + 2.
 template <int L2S>
-__global__ __launch_bounds__(kLT) void k_learn_eval(TreeDev d, LearnModel* __restrict__ models) {
+__global__ __launch_bounds__(kLT) void k_learn_eval(TreeDev d, LearnModel* __restrict__ models,
+                                                    LearnQ* __restrict__ qm) {
   __shared__ float s_r[4][4];
   const uint64_t slot = blockIdx.x;
   LearnModel& M = models[slot];
   if (M.eps < 0) return;
   const LevelMeta m = d.meta[M.level];
-  float p[kNP];
-#pragma unroll
-  for (int j = 0; j < kNP; ++j) p[j] = M.p[j];
+  const LearnQ& Q = qm[slot];
   const uint64_t start = M.start, len = M.len, cnt = M.cnt;
   const uint64_t blo = (start + (1ull << L2S) - 1) >> L2S, bhi = (start + len - 1) >> L2S;
   const double bl = (double)(1u << L2S);
@@ -264,7 +309,7 @@ __global__ __launch_bounds__(kLT) void k_learn_eval(TreeDev d, LearnModel* __res
     const uint64_t x = B << L2S;
     const double u = (double)(count_before<L2S>(d, m, M.side, x) - M.rank0) / (double)cnt;
     const double tv = (double)(x - start);
-    const float e = (float)(fabs((double)mlp_eval(p, (float)u) * (double)len - tv) / bl);
+    const float e = (float)(fabs((double)pla_eval(Q, (float)u) * (double)len - tv) / bl);
     const float ei = (float)(fabs(u * (double)len - tv) / bl);
     smax = fmaxf(smax, e);
     ssum += e;
@@ -300,163 +345,25 @@ __global__ __launch_bounds__(kLT) void k_learn_eval(TreeDev d, LearnModel* __res
     M.err_init_max = c;
     M.err_init_mean = dsum / nb;
     M.eps = (int32_t)ceilf(a) + 2;
+    qm[slot].eps = M.eps;
   }
 }
 
 // ---------------------------------------------------------------- learned select
 
-// Position of the j-th (1-based, node-local) side-b bit of the node of model M at level m.
-template <int L2S>
-__device__ __forceinline__ uint64_t select_learned_at(const TreeDev& d, const LevelMeta& m, const LearnModel& M,
-                                                      uint32_t b, uint64_t j, uint32_t sshift) {
-  const uint64_t T = M.rank0 + j;  // global target among the side-b bits of the level
-  if (M.eps < 0) return select_at<L2S>(d, m, b, T, sshift);
-  float p[kNP];
-  {
-    const float4* mp = reinterpret_cast<const float4*>(M.p);
-#pragma unroll
-    for (int k = 0; k < kNP / 4; ++k) {
-      const float4 x = mp[k];
-      p[4 * k] = x.x;
-      p[4 * k + 1] = x.y;
-      p[4 * k + 2] = x.z;
-      p[4 * k + 3] = x.w;
-    }
-    p[kNP - 1] = M.p[kNP - 1];
-  }
-  const float u = ((float)j - 0.5f) / (float)M.cnt;
-  const float v = fminf(fmaxf(mlp_eval(p, u), 0.f), 1.f);
-  const uint64_t start = M.start, end = M.start + M.len;
-  uint64_t guess = start + (uint64_t)((double)v * (double)M.len);
-  guess = min(guess, end - 1);
-  const uint64_t Blo = start >> L2S, Bhi = (end - 1) >> L2S;
-  const uint64_t B0 = guess >> L2S;
-  const uint64_t budget = (uint64_t)M.eps;
-  // largest B in [Blo, Bhi] with count_before(B) < T; count_before(Blo) <= rank0 < T always.
-  // First look at the aligned group of L2 counts holding B0 (one 128-byte line, inside one L1
-  // block): the counts are non-decreasing, so the blocks below the target form a prefix of it.
-  constexpr int GS = L2S <= 10 ? 6 : 5;
-  constexpr uint32_t GN = 1u << GS;
-  const uint64_t gbase = B0 & ~(uint64_t)(GN - 1);
-  const uint64_t glo = max(gbase, Blo), ghi = min(gbase + GN - 1, Bhi);
-  const uint64_t l1v = d.L1[m.l1 + ((gbase << L2S) >> kL1Shift)];
-  const uint4* gp = reinterpret_cast<const uint4*>(d.L2 + m.l2 + gbase);
-  uint4 g[GN / 8];
-#pragma unroll
-  for (uint32_t i = 0; i < GN / 8; ++i) g[i] = gp[i];
-  // below(e) <=> count_before(gbase + e) < T, in 32-bit arithmetic with saturation
-  int64_t D;
-  if (b) D = (int64_t)min<uint64_t>(T - min(T, l1v), 1ull << 20);  // l2 < D
-  else {
-    const uint64_t base0 = (gbase << L2S) - l1v;  // zeros before the group
-    D = T > base0 ? (int64_t)min<uint64_t>(T - base0, 1ull << 20) : -(int64_t)min<uint64_t>(base0 - T, 1ull << 20);
-  }
-  const int32_t Di = (int32_t)D;
-  const uint32_t elo = (uint32_t)(glo - gbase), ehi = (uint32_t)(ghi - gbase);
-  uint32_t below = 0;
-#pragma unroll
-  for (uint32_t e = 0; e < GN; ++e) {
-    const uint32_t dw = (e & 7) < 4 ? ((e & 7) < 2 ? g[e >> 3].x : g[e >> 3].y) : ((e & 7) < 6 ? g[e >> 3].z : g[e >> 3].w);
-    const int32_t l2v = (int32_t)((dw >> ((e & 1) * 16)) & 0xFFFFu);
-    const bool lt = b ? (l2v < Di) : ((int32_t)(e << L2S) - l2v < Di);
-    below += (lt && e >= elo && e <= ehi) ? 1u : 0u;
-  }
-  uint64_t lo, hi;  // invariant: count_before(lo) < T, and hi = Bhi + 1 or count_before(hi) >= T
-  if (below > 0 && (glo + below - 1 < ghi || ghi == Bhi)) {
-    lo = glo + below - 1;
-    hi = lo + 1;
-  } else if (below == 0) {
-    // target left of the group (glo > Blo here): gallop left from glo
-    hi = glo;
-    uint64_t step = 1;
-    for (;;) {
-      if (hi - Blo <= step) {
-        lo = Blo;
-        break;
-      }
-      const uint64_t nb = hi - step;
-      if (count_before<L2S>(d, m, b, nb << L2S) < T) {
-        lo = nb;
-        break;
-      }
-      hi = nb;
-      step <<= 1;
-      if (glo - nb > budget) return select_at<L2S>(d, m, b, T, sshift);
-    }
-  } else {
-    // every block of the group is below the target: gallop right from ghi
-    lo = ghi;
-    uint64_t step = 1;
-    for (;;) {
-      const uint64_t nb = lo + step;
-      if (nb > Bhi) {
-        hi = Bhi + 1;
-        break;
-      }
-      if (count_before<L2S>(d, m, b, nb << L2S) >= T) {
-        hi = nb;
-        break;
-      }
-      lo = nb;
-      step <<= 1;
-      if (nb - ghi > budget) return select_at<L2S>(d, m, b, T, sshift);
-    }
-  }
-  while (hi - lo > 1) {
-    const uint64_t mid = lo + ((hi - lo) >> 1);
-    if (count_before<L2S>(d, m, b, mid << L2S) < T) lo = mid;
-    else hi = mid;
-  }
-  // word scan inside the block, then the in-word select
-  constexpr int L2W = (1 << L2S) / 64;
-  uint32_t kk = (uint32_t)(T - count_before<L2S>(d, m, b, lo << L2S));
-  const uint64_t* wp = d.bits + m.bits + (lo << (L2S - 6));
-#pragma unroll
-  for (int w = 0; w < L2W; ++w) {
-    uint64_t word = wp[w];
-    if (!b) word = ~word;
-    const uint32_t pc = popc64(word);
-    if (kk <= pc) return (lo << L2S) + 64u * (uint32_t)w + select_in_word(word, kk);
-    kk -= pc;
-  }
-  return select_at<L2S>(d, m, b, T, sshift);  // not reached for valid targets
-}
 
 template <int L2S>
-__global__ __launch_bounds__(kQT) void k_select_learned(QArgs a, const LearnModel* __restrict__ models,
+__global__ __launch_bounds__(kQT, 8) void k_select_learned(QArgs a, const LearnQ* __restrict__ qm,
                                                         const uint32_t* __restrict__ sym,
                                                         const uint64_t* __restrict__ kin, uint64_t q,
                                                         uint64_t* __restrict__ out) {
+  constexpr int GS = learn_gs<L2S>();
   __shared__ LevelMeta s_meta[WT_MAX_LEVELS];
   load_meta(a, s_meta);
   for (uint64_t j = (uint64_t)blockIdx.x * kQT + threadIdx.x; j < q; j += (uint64_t)gridDim.x * kQT) {
-    const uint32_t c = sym[j];
-    const uint64_t k = kin[j];
-    uint64_t res;
-    if (k == 0) {
-      res = ~0ull;
-    } else if (c >= a.sigma) {
-      res = a.n;
-    } else if (k > a.d.cum[c + 1] - a.d.cum[c]) {
-      res = a.n;
-    } else if (a.L == 0) {
-      res = k - 1;
-    } else {
-      uint32_t len;
-      const uint32_t code = encode_sym(c, a.sigma, a.L, a.pow2, &len);
-      uint64_t r = k;
-      for (int l = (int)len - 1; l >= 0; --l) {
-        const uint64_t pc = (uint64_t)(code >> (a.L - 1 - l));  // child prefix at level l + 1
-        const LearnModel& M = models[(1ull << (l + 1)) - 2 + pc];
-        const uint64_t at = select_learned_at<L2S>(a.d, s_meta[l], M, M.side, r, a.sshift);
-        r = at - M.start + 1;
-      }
-      res = r - 1;
-    }
-    out[j] = res;
+    out[j] = select_learned_one<L2S, GS>(a, s_meta, qm, sym[j], kin[j]);
   }
 }
-
 // One evaluation of the training objective (same device code as k_learn_train).
 __global__ __launch_bounds__(kLT) void k_mlp_loss_grad(const float* __restrict__ params, const float* __restrict__ u,
                                                        const float* __restrict__ v, uint32_t P,
@@ -511,11 +418,12 @@ extern "C" wt_status wt_learn_select(wt_tree* t, const wt_learn_opts* opts, wt_s
     return WT_OK;
   }
   const size_t mbytes = nmodels * sizeof(LearnModel);
-  t->learn = dev_alloc(mbytes, st);
+  t->learn = dev_alloc(mbytes + nmodels * sizeof(LearnQ), st);  // training records, then query forms
   if (!t->learn) return fail(WT_ERR_OOM, "wt_learn_select: model allocation failed");
   float2* pts = (float2*)dev_alloc(nmodels * pmax * sizeof(float2), st);
   if (!pts) return fail(WT_ERR_OOM, "wt_learn_select: training data allocation failed");
   LearnModel* models = (LearnModel*)t->learn;
+  LearnQ* qm = (LearnQ*)((char*)t->learn + mbytes);
   hipEvent_t e0, e1;
   WT_HIP(hipEventCreate(&e0));
   WT_HIP(hipEventCreate(&e1));
@@ -531,12 +439,13 @@ extern "C" wt_status wt_learn_select(wt_tree* t, const wt_learn_opts* opts, wt_s
   }
   hipLaunchKernelGGL(k_learn_train, dim3((uint32_t)nmodels), dim3(kLT), 0, st, models, (const float2*)pts, pmax,
                      epochs, lr);
+  hipLaunchKernelGGL(k_learn_compile, dim3(grid), dim3(256), 0, st, (const LearnModel*)models, qm, nmodels);
   WT_HIP(hipEventRecord(e1, st));
   switch (t->l2_bits) {
-    case 256: hipLaunchKernelGGL(k_learn_eval<8>, dim3((uint32_t)nmodels), dim3(kLT), 0, st, t->dev, models); break;
-    case 512: hipLaunchKernelGGL(k_learn_eval<9>, dim3((uint32_t)nmodels), dim3(kLT), 0, st, t->dev, models); break;
-    case 1024: hipLaunchKernelGGL(k_learn_eval<10>, dim3((uint32_t)nmodels), dim3(kLT), 0, st, t->dev, models); break;
-    default: hipLaunchKernelGGL(k_learn_eval<11>, dim3((uint32_t)nmodels), dim3(kLT), 0, st, t->dev, models); break;
+    case 256: hipLaunchKernelGGL(k_learn_eval<8>, dim3((uint32_t)nmodels), dim3(kLT), 0, st, t->dev, models, qm); break;
+    case 512: hipLaunchKernelGGL(k_learn_eval<9>, dim3((uint32_t)nmodels), dim3(kLT), 0, st, t->dev, models, qm); break;
+    case 1024: hipLaunchKernelGGL(k_learn_eval<10>, dim3((uint32_t)nmodels), dim3(kLT), 0, st, t->dev, models, qm); break;
+    default: hipLaunchKernelGGL(k_learn_eval<11>, dim3((uint32_t)nmodels), dim3(kLT), 0, st, t->dev, models, qm); break;
   }
   WT_HIP(hipGetLastError());
   std::vector<LearnModel> hm(nmodels);
@@ -581,8 +490,8 @@ extern "C" wt_status wt_select_learned(const wt_tree* t, const uint32_t* d_sym, 
   hipStream_t st = (hipStream_t)stream;
   const QArgs a = make_args(t);
   const uint32_t grid = query_grid(q);
-  const LearnModel* models = (const LearnModel*)t->learn;
-  WT_DISPATCH_L2(t->l2_bits, k_select_learned, a, models, d_sym, d_k, q, d_out);
+  const LearnQ* qm = (const LearnQ*)((const char*)t->learn + (size_t)t->nmodels * sizeof(LearnModel));
+  WT_DISPATCH_L2(t->l2_bits, k_select_learned, a, qm, d_sym, d_k, q, d_out);
   WT_HIP(hipGetLastError());
   return WT_OK;
 }
@@ -592,6 +501,41 @@ extern "C" wt_status wt_learned_info(const wt_tree* t, wt_learned_info_t* out) {
   if (!t || !out) return fail(WT_ERR_ARG, "wt_learned_info: NULL argument");
   if (!t->learn) return fail(WT_ERR_STATE, "wt_learned_info: no learned index");
   *out = t->linfo;
+  return WT_OK;
+}
+
+extern "C" wt_status wt_learned_model(const wt_tree* t, uint32_t slot, wt_learned_model_t* out) {
+  clear_error();
+  if (!t || !out) return fail(WT_ERR_ARG, "wt_learned_model: NULL argument");
+  if (!t->learn) return fail(WT_ERR_STATE, "wt_learned_model: no learned index");
+  if (slot >= t->nmodels) return fail(WT_ERR_ARG, "wt_learned_model: slot %u >= %u", slot, t->nmodels);
+  LearnModel M;
+  LearnQ Q;
+  WT_HIP(hipDeviceSynchronize());
+  WT_HIP(hipMemcpy(&M, (const LearnModel*)t->learn + slot, sizeof(M), hipMemcpyDeviceToHost));
+  WT_HIP(hipMemcpy(&Q, (const char*)t->learn + (size_t)t->nmodels * sizeof(LearnModel) + (size_t)slot * sizeof(LearnQ),
+                   sizeof(Q), hipMemcpyDeviceToHost));
+  std::memset(out, 0, sizeof(*out));
+  out->level = (int32_t)M.level;
+  out->side = M.side;
+  out->eps = Q.eps;
+  out->points = M.npts;
+  out->start = M.start;
+  out->len = M.len;
+  out->count = M.cnt;
+  out->rank0 = M.rank0;
+  for (int k = 0; k < kNP; ++k) out->params[k] = M.p[k];
+  out->pieces = Q.npieces;
+  for (int k = 0; k < kH; ++k) out->knots[k] = Q.knot[k];
+  for (int k = 0; k <= kH; ++k) {
+    out->slope[k] = Q.piece[k].x;
+    out->intercept[k] = Q.piece[k].y;
+  }
+  out->err_mean = M.err_mean;
+  out->err_max = M.err_max;
+  out->err_init_mean = M.err_init_mean;
+  out->err_init_max = M.err_init_max;
+  out->loss = M.loss;
   return WT_OK;
 }
 

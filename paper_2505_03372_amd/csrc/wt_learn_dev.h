@@ -1,0 +1,193 @@
+// Query side of the learned select index: the compiled (piecewise-linear) form of a trained network
+// and the select that corrects its prediction exactly, shared by the learned select kernel and the
+// mixed-query kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+
+#include "wt_internal.h"
+#include "wt_query_dev.h"
+
+namespace wt {
+
+constexpr int kH = 16;           // hidden units
+constexpr int kNP = 3 * kH + 1;  // parameters: w1[16], b1[16], w2[16], b2
+
+// Query form of a trained model. With one input, the network is linear between the points where a
+// hidden unit switches on or off (u = -b1_k / w1_k), so on [0, 1] it is exactly a piecewise-linear
+// function with at most 16 switch points: they are stored ascending (unused: 2, above every input)
+// with one (slope, intercept) pair per piece. A query loads the header and the switch points (the
+// first 128-byte line) and one piece, instead of the 49 parameters. 256 bytes.
+struct LearnQ {
+  uint64_t start;  // node range [start, start + len) in level l
+  uint64_t len;
+  uint64_t rank0;  // count of side-b bits of level l before `start`
+  int32_t eps;     // error budget in L2 blocks (max error + 2); -1: no model
+  uint32_t side;   // b
+  float cntf;      // bits equal to b inside the node, as float (the input scale)
+  uint32_t npieces;
+  uint64_t pad0;
+  float knot[kH];
+  float2 piece[kH + 1];  // (slope, intercept) of v(u) on [knot[s-1], knot[s])
+  uint64_t pad1;
+};
+static_assert(sizeof(LearnQ) == 256, "query model size");
+static_assert(offsetof(LearnQ, knot) % 16 == 0 && offsetof(LearnQ, knot) + sizeof(float) * kH <= 128,
+              "header and switch points share the first line");
+
+// v(u) of a compiled model, clamped to [0, 1]: the piece is the number of switch points <= u.
+__device__ __forceinline__ float pla_eval(const LearnQ& Q, float u) {
+  const float4* kp = reinterpret_cast<const float4*>(Q.knot);
+  uint32_t s = 0;
+#pragma unroll
+  for (int i = 0; i < kH / 4; ++i) {
+    const float4 x = kp[i];
+    s += (uint32_t)(x.x <= u) + (uint32_t)(x.y <= u) + (uint32_t)(x.z <= u) + (uint32_t)(x.w <= u);
+  }
+  const float2 pc = Q.piece[s];
+  return fminf(fmaxf(fmaf(pc.x, u, pc.y), 0.f), 1.f);
+}
+
+// Count of side-b bits of a level before position x (x a multiple of the L2 block, x <= n_l).
+template <int L2S>
+__device__ __forceinline__ uint64_t count_before(const TreeDev& d, const LevelMeta& m, uint32_t b, uint64_t x) {
+  const uint64_t r1 = d.L1[m.l1 + (x >> kL1Shift)] + d.L2[m.l2 + (x >> L2S)];
+  return b ? r1 : x - r1;
+}
+
+// Position of the j-th (1-based, node-local) side-b bit of the node of model Q at level m.
+// GS: log2 of the L2 counts read at once around the prediction (one aligned group).
+template <int L2S, int GS>
+__device__ __forceinline__ uint64_t select_learned_at(const TreeDev& d, const LevelMeta& m, const LearnQ& Q,
+                                                      uint64_t j, uint32_t sshift) {
+  const uint32_t b = Q.side;
+  const uint64_t T = Q.rank0 + j;  // global target among the side-b bits of the level
+  if (Q.eps < 0) return select_at<L2S, false>(d, m, b, T, sshift);
+  const float v = pla_eval(Q, ((float)j - 0.5f) / Q.cntf);
+  const uint64_t start = Q.start, end = Q.start + Q.len;
+  const uint64_t guess = min(start + (uint64_t)((double)v * (double)Q.len), end - 1);
+  const uint64_t Blo = start >> L2S, Bhi = (end - 1) >> L2S;
+  const uint64_t B0 = guess >> L2S;
+  const uint64_t budget = (uint64_t)Q.eps;
+  // largest B in [Blo, Bhi] with count_before(B) < T; count_before(Blo) <= rank0 < T always.
+  // First look at the aligned group of L2 counts holding B0 (inside one L1 block): the counts are
+  // non-decreasing, so the blocks below the target form a prefix of it.
+  constexpr uint32_t GN = 1u << GS;
+  const uint64_t gbase = B0 & ~(uint64_t)(GN - 1);
+  const uint64_t glo = max(gbase, Blo), ghi = min(gbase + GN - 1, Bhi);
+  const uint64_t l1v = d.L1[m.l1 + ((gbase << L2S) >> kL1Shift)];
+  const uint4* gp = reinterpret_cast<const uint4*>(d.L2 + m.l2 + gbase);
+  uint4 g[GN / 8];
+#pragma unroll
+  for (uint32_t i = 0; i < GN / 8; ++i) g[i] = gp[i];
+  // below(e) <=> count_before(gbase + e) < T, in 32-bit arithmetic with saturation
+  int64_t D;
+  if (b) D = (int64_t)min<uint64_t>(T - min(T, l1v), 1ull << 20);  // l2 < D
+  else {
+    const uint64_t base0 = (gbase << L2S) - l1v;  // zeros before the group
+    D = T > base0 ? (int64_t)min<uint64_t>(T - base0, 1ull << 20) : -(int64_t)min<uint64_t>(base0 - T, 1ull << 20);
+  }
+  const int32_t Di = (int32_t)D;
+  const uint32_t elo = (uint32_t)(glo - gbase), ehi = (uint32_t)(ghi - gbase);
+  uint32_t below = 0;
+#pragma unroll
+  for (uint32_t e = 0; e < GN; ++e) {
+    const uint32_t dw = (e & 7) < 4 ? ((e & 7) < 2 ? g[e >> 3].x : g[e >> 3].y) : ((e & 7) < 6 ? g[e >> 3].z : g[e >> 3].w);
+    const int32_t l2v = (int32_t)((dw >> ((e & 1) * 16)) & 0xFFFFu);
+    const bool lt = b ? (l2v < Di) : ((int32_t)(e << L2S) - l2v < Di);
+    below += (lt && e >= elo && e <= ehi) ? 1u : 0u;
+  }
+  uint64_t lo, hi;  // invariant: count_before(lo) < T, and hi = Bhi + 1 or count_before(hi) >= T
+  if (below > 0 && (glo + below - 1 < ghi || ghi == Bhi)) {
+    lo = glo + below - 1;
+    hi = lo + 1;
+  } else if (below == 0) {
+    // target left of the group (glo > Blo here): gallop left from glo
+    hi = glo;
+    uint64_t step = 1;
+    for (;;) {
+      if (hi - Blo <= step) {
+        lo = Blo;
+        break;
+      }
+      const uint64_t nb = hi - step;
+      if (count_before<L2S>(d, m, b, nb << L2S) < T) {
+        lo = nb;
+        break;
+      }
+      hi = nb;
+      step <<= 1;
+      if (glo - nb > budget) return select_at<L2S, false>(d, m, b, T, sshift);
+    }
+  } else {
+    // every block of the group is below the target: gallop right from ghi
+    lo = ghi;
+    uint64_t step = 1;
+    for (;;) {
+      const uint64_t nb = lo + step;
+      if (nb > Bhi) {
+        hi = Bhi + 1;
+        break;
+      }
+      if (count_before<L2S>(d, m, b, nb << L2S) >= T) {
+        hi = nb;
+        break;
+      }
+      lo = nb;
+      step <<= 1;
+      if (nb - ghi > budget) return select_at<L2S, false>(d, m, b, T, sshift);
+    }
+  }
+  while (hi - lo > 1) {
+    const uint64_t mid = lo + ((hi - lo) >> 1);
+    if (count_before<L2S>(d, m, b, mid << L2S) < T) lo = mid;
+    else hi = mid;
+  }
+  // word scan inside the block, then the in-word select
+  constexpr int L2W = (1 << L2S) / 64;
+  uint32_t kk = (uint32_t)(T - count_before<L2S>(d, m, b, lo << L2S));
+  const uint64_t* wp = d.bits + m.bits + (lo << (L2S - 6));
+#pragma unroll
+  for (int w = 0; w < L2W; ++w) {
+    uint64_t word = wp[w];
+    if (!b) word = ~word;
+    const uint32_t pc = popc64(word);
+    if (kk <= pc) return (lo << L2S) + 64u * (uint32_t)w + select_in_word(word, kk);
+    kk -= pc;
+  }
+  return select_at<L2S, false>(d, m, b, T, sshift);  // not reached for valid targets
+}
+
+// select_c(k) through the learned index (same results and sentinels as select_one).
+template <int L2S, int GS>
+__device__ __forceinline__ uint64_t select_learned_one(const QArgs& a, const LevelMeta* meta, const LearnQ* qm,
+                                                       uint32_t c, uint64_t k) {
+  if (k == 0) return ~0ull;
+  if (c >= a.sigma) return a.n;
+  if (k > a.d.cum[c + 1] - a.d.cum[c]) return a.n;
+  if (a.L == 0) return k - 1;
+  uint32_t len;
+  const uint32_t code = encode_sym(c, a.sigma, a.L, a.pow2, &len);
+  uint64_t r = k;
+  for (int l = (int)len - 1; l >= 0; --l) {
+    const uint64_t pc = (uint64_t)(code >> (a.L - 1 - l));  // child prefix at level l + 1
+    const LearnQ& Q = qm[(1ull << (l + 1)) - 2 + pc];
+    const uint64_t at = select_learned_at<L2S, GS>(a.d, meta[l], Q, r, a.sshift);
+    r = at - Q.start + 1;
+  }
+  return r - 1;
+}
+
+// Aligned group of L2 counts the learned correction reads at once: 2^WT_LEARN_GS entries (one fewer
+// power for 2048-bit blocks).
+#ifndef WT_LEARN_GS
+#define WT_LEARN_GS 5
+#endif
+template <int L2S>
+constexpr int learn_gs() {
+  return L2S <= 10 ? WT_LEARN_GS : WT_LEARN_GS - 1;
+}
+
+}  // namespace wt

@@ -48,7 +48,9 @@ __device__ __forceinline__ uint64_t rank1_at(const TreeDev& d, const LevelMeta& 
 }
 
 // Position of the k-th bit equal to b (1 <= k <= count of b) of the level (Algorithm 2).
-template <int L2S>
+// kLine: resolve the L2 search on the first line of L2 counts in registers before the binary search
+// (faster; the form without it needs fewer registers).
+template <int L2S, bool kLine = true>
 __device__ __forceinline__ uint64_t select_at(const TreeDev& d, const LevelMeta& m, uint32_t b, uint64_t k,
                                               uint32_t sshift) {
   constexpr int L2W = (1 << L2S) / 64;
@@ -82,7 +84,7 @@ __device__ __forceinline__ uint64_t select_at(const TreeDev& d, const LevelMeta&
   const uint64_t jb = blk * kPer;
   uint64_t jlo = max(jb, lo_pos >> L2S);
   uint64_t jhi = min(min(jb + kPer, nL2) - 1, hi_pos >> L2S);
-  {
+  if constexpr (kLine) {
     constexpr uint32_t GN = L2S <= 10 ? 64u : 32u;
     const uint64_t gbase = jlo & ~(uint64_t)(GN - 1);
     const uint64_t ghi = min(gbase + GN - 1, jhi);
@@ -130,6 +132,90 @@ __device__ __forceinline__ uint64_t select_at(const TreeDev& d, const LevelMeta&
     kk -= pc;
   }
   return nl;  // not reached for valid k
+}
+
+// Algorithm 5 (top-down): the bit of the element picks the child; its position in the child is its
+// rank among the equal bits of the node. Stops once the node covers at most two symbols.
+// Positions >= n give 0xFFFFFFFF.
+template <int L2S>
+__device__ __forceinline__ uint32_t access_one(const QArgs& a, const LevelMeta* meta, uint64_t i) {
+  if (i >= a.n) return 0xFFFFFFFFu;
+  uint32_t s = 0, e = a.sigma;
+  uint64_t p = 0, x = i;
+  for (uint32_t l = 0; l < a.L; ++l) {
+    const uint32_t width = e - s;
+    const NodeQ nd = a.d.nodes[(1ull << l) - 1 + p];
+    const LevelMeta& m = meta[l];
+    const uint64_t y = nd.start + x;
+    if (width <= 2) {
+      if (width == 2) s += (uint32_t)(a.d.bits[m.bits + (y >> 6)] >> (y & 63)) & 1u;
+      break;
+    }
+    uint32_t bit;
+    const uint64_t r0 = y - rank1_at<L2S>(a.d, m, y, bit);
+    const uint32_t half = (uint32_t)pow2_below(width);
+    if (!bit) {
+      x = r0 - nd.r0;
+      e = s + half;
+      p = 2 * p;
+    } else {
+      x = x - (r0 - nd.r0);
+      s += half;
+      p = 2 * p + 1;
+    }
+  }
+  return s;
+}
+
+// Algorithm 6 (top-down along the symbol's path): the count of the symbol's side before the position.
+// Positions > n give UINT64_MAX; symbols >= sigma give 0.
+template <int L2S>
+__device__ __forceinline__ uint64_t rank_one(const QArgs& a, const LevelMeta* meta, uint32_t c, uint64_t i) {
+  if (i > a.n) return ~0ull;
+  if (c >= a.sigma) return 0;
+  uint32_t s = 0, e = a.sigma;
+  uint64_t p = 0, x = i;
+  for (uint32_t l = 0; l < a.L; ++l) {
+    if (e - s <= 1 || x == 0) break;
+    const NodeQ nd = a.d.nodes[(1ull << l) - 1 + p];
+    const uint64_t y = nd.start + x;
+    uint32_t bit;
+    const uint64_t r0 = y - rank1_at<L2S>(a.d, meta[l], y, bit);
+    const uint32_t split = s + (uint32_t)pow2_below(e - s);
+    if (c < split) {
+      x = r0 - nd.r0;
+      e = split;
+      p = 2 * p;
+    } else {
+      x = x - (r0 - nd.r0);
+      s = split;
+      p = 2 * p + 1;
+    }
+  }
+  return x;
+}
+
+// Algorithms 7 and 8 (bottom-up from the symbol's leaf): the k-th occurrence inside the current node
+// is the (rank-at-node-start + k)-th bit equal to the node's side in the parent level.
+// k = 0 gives UINT64_MAX; k > count(c) or c >= sigma gives n.
+template <int L2S>
+__device__ __forceinline__ uint64_t select_one(const QArgs& a, const LevelMeta* meta, uint32_t c, uint64_t k) {
+  if (k == 0) return ~0ull;
+  if (c >= a.sigma) return a.n;
+  if (k > a.d.cum[c + 1] - a.d.cum[c]) return a.n;
+  if (a.L == 0) return k - 1;
+  uint32_t len;
+  const uint32_t code = encode_sym(c, a.sigma, a.L, a.pow2, &len);
+  uint64_t r = k;
+  for (int l = (int)len - 1; l >= 0; --l) {
+    const uint64_t p = l ? (uint64_t)(code >> (a.L - l)) : 0ull;
+    const uint32_t b = (code >> (a.L - 1 - l)) & 1u;
+    const NodeQ nd = a.d.nodes[(1ull << l) - 1 + p];
+    const uint64_t target = b ? (nd.start - nd.r0) + r : nd.r0 + r;
+    const uint64_t at = select_at<L2S>(a.d, meta[l], b, target, a.sshift);
+    r = at - nd.start + 1;
+  }
+  return r - 1;
 }
 
 __device__ __forceinline__ void load_meta(const QArgs& a, LevelMeta* s_meta) {

@@ -89,3 +89,24 @@ def test_product_package_never_imports_the_oracle():
                     text = f.read()
                 assert "import oracle" not in text and "from oracle" not in text, fn
                 assert "wt_oracle" not in text, fn
+
+
+def test_tune_table_json_roundtrip(tmp_path):
+    import paper_2505_03372_amd as wt
+    entries = {(5, 0): (256, 4096), (12, 3): (1024, 16384), (20, 6): (512, 1024)}
+    tt = wt.make_tune_table(entries)
+    path = str(tmp_path / "t.json")
+    wt.save_tune(tt, path)
+    tt2 = wt.load_tune(path)
+    assert bytes(tt2) == bytes(tt)
+    for (nb, sb), (l2, s) in entries.items():
+        assert (tt2.l2_bits[nb][sb], tt2.sample_rate[nb][sb]) == (l2, s)
+
+
+def test_tune_bucket():
+    import paper_2505_03372_amd as wt
+    assert wt.tune_bucket(1, 1) == (0, 0)
+    assert wt.tune_bucket(1 << 10, 4) == (5, 0)
+    assert wt.tune_bucket((1 << 24) - 1, 1 << 16) == (11, 4)
+    assert wt.tune_bucket(1 << 24, (1 << 16) - 1) == (12, 3)
+    assert wt.tune_bucket(1 << 60, 1 << 40) == (wt.TUNE_NB - 1, wt.TUNE_SB - 1)

@@ -5,7 +5,9 @@
 * learned select answers equal to the oracle's and to the plain select's on many trees
   (exactness does not depend on the FP32 model: the prediction is corrected exactly);
 * what training gains: the trained networks' mean prediction error (in L2 blocks, over every L2
-  boundary of every node) is below that of the untrained starting point (the linear map).
+  boundary of every node) is below that of the untrained starting point (the linear map);
+* the piecewise-linear form queries evaluate equals the trained network (FP64 forward pass of the
+  exported parameters), and every model sits in the slot of its child node.
 """
 import numpy as np
 import pytest
@@ -88,6 +90,48 @@ def test_training_reduces_prediction_error():
     assert info["models"] > 0
     assert info["mean_err_blocks"] < 0.8 * info["mean_err_init_blocks"]
     assert info["max_err_blocks"] <= info["max_err_init_blocks"] + 2
+    t.free()
+
+
+def test_compiled_models_equal_networks_and_slots():
+    sigma, n = 77, 300001
+    S = make_seq("zipf", n, sigma, 1, 0xC0DE)
+    G.log("compiled models sigma=%d n=%d" % (sigma, n))
+    t = G.gpu_build(S, sigma)
+    t.learn_select()
+    ref = oracle.OracleTree(S, sigma)
+    L = ref.L
+    u = np.concatenate([(np.arange(1, 200) - 0.5) / 199.0, [1e-6, 1 - 1e-6]])
+    trained = 0
+    for l in range(L):
+        bits = np.unpackbits(np.asarray(ref.bits[l]).view(np.uint8), bitorder="little")[: ref.level_n[l]]
+        for p in range(1 << l):
+            for b in (0, 1):
+                slot = (1 << (l + 1)) - 2 + 2 * p + b
+                M = t.learned_model(slot)
+                st = int(ref.node_start[l][p])
+                if M["eps"] < 0:
+                    continue
+                trained += 1
+                assert (M["level"], M["side"]) == (l, b), slot
+                assert M["start"] == st, slot
+                seg = bits[st: st + M["len"]]
+                assert M["count"] == int((seg == b).sum()), slot
+                r0 = int(ref.node_r0[l][p])
+                assert M["rank0"] == (st - r0 if b else r0), slot
+                kn = M["knots"]
+                m = M["pieces"] - 1
+                assert 0 <= m <= 16 and np.all(np.diff(kn[:m]) >= 0) and np.all(kn[m:] == 2.0), slot
+                th = M["params"].astype(np.float64)
+                w1, b1 = th[:16], th[16:32]
+                inside = [x for x in (-b1[w1 != 0] / w1[w1 != 0]) if 0 < x < 1]
+                assert len(inside) == m, slot
+                s_idx = np.searchsorted(kn[:m].astype(np.float64), u, side="right")
+                got = M["slope"][s_idx].astype(np.float64) * u + M["intercept"][s_idx].astype(np.float64)
+                exp = oracle.mlp_forward(th, u)
+                scale = 1.0 + np.abs(th[32:48]).sum() * (np.abs(w1).max() + np.abs(b1).max())
+                np.testing.assert_allclose(got, exp, rtol=0, atol=2e-6 * scale, err_msg="slot %d" % slot)
+    assert trained > 50
     t.free()
 
 

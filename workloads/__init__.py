@@ -29,6 +29,8 @@ _SRC = os.path.join(_HERE, "gen.c")
 _LIB = os.path.join(_HERE, "libwtgen.so")
 
 TAG_TEXT, TAG_PERM, TAG_ACC, TAG_RANK_C, TAG_RANK_I, TAG_SEL_C, TAG_SEL_K, TAG_TEXT2 = range(1, 9)
+TAG_TREE_N, TAG_TREE_SIGMA, TAG_MIX_TREE, TAG_MIX_OP, TAG_MIX_U1, TAG_MIX_U2 = range(9, 15)
+TAG_TREE_BASE = 0x1000  # sub-seed of tree j: subseed(base, TAG_TREE_BASE + j)
 
 _u64p = ctypes.POINTER(ctypes.c_uint64)
 _u32p = ctypes.POINTER(ctypes.c_uint32)
@@ -218,3 +220,93 @@ def make(name: str, n: int | None = None, q: int | None = None, kinds=("access",
     S, sigma = make_text(name, n)
     qs = make_queries(name, S, sigma, q, kinds)
     return Workload(name=name, S=S, sigma=sigma, **qs)
+
+
+# ---- batched forest: many sequences of uneven length and alphabet ----
+
+FOREST = dict(index=3, trees=1024, width=2, n_range=(1 << 10, 1 << 24), sigma_range=(4, 1 << 16), zipf_s=1.0,
+              queries=1 << 24)
+
+
+@dataclass
+class ForestWorkload:
+    S: np.ndarray          # every sequence, concatenated
+    offsets: np.ndarray    # u64[trees + 1]: sequence j is S[offsets[j]:offsets[j + 1]]
+    sigmas: np.ndarray     # u64[trees]
+    tree: np.ndarray | None = None  # mixed queries: u32 tree, u8 op, u32 symbol, u64 argument
+    op: np.ndarray | None = None
+    sym: np.ndarray | None = None
+    arg: np.ndarray | None = None
+
+    @property
+    def trees(self) -> int:
+        return int(self.sigmas.size)
+
+    def seq(self, j: int) -> np.ndarray:
+        return self.S[int(self.offsets[j]):int(self.offsets[j + 1])]
+
+
+def _unit(seed: int, n: int) -> np.ndarray:
+    """Elements [0, n) of the stream as doubles in [0, 1): (out >> 11) * 2^-53."""
+    return (raw(seed, 0, n) >> np.uint64(11)).astype(np.float64) * (1.0 / (1 << 53))
+
+
+def _scaled(u: np.ndarray, m: np.ndarray) -> np.ndarray:
+    """floor(u * m) clamped to [0, m - 1] (m >= 1), per element."""
+    m = m.astype(np.float64)
+    return np.minimum(np.floor(u * m), np.maximum(m - 1, 0)).astype(np.uint64)
+
+
+def make_forest(trees: int | None = None, n_range=None, sigma_range=None, queries: int | None = None,
+                width: int | None = None, zipf_s: float | None = None) -> ForestWorkload:
+    """Sequence j: length log-uniform in n_range, alphabet log-uniform in sigma_range, Zipf(s) symbol
+    frequencies over a per-tree seeded permutation. Mixed queries: tree uniform, op uniform over
+    {access, rank, select}, position uniform in the tree, symbol drawn from the tree's sequence, k
+    uniform in [1, count]."""
+    cfg = dict(FOREST)
+    for k, v in dict(trees=trees, n_range=n_range, sigma_range=sigma_range, queries=queries, width=width,
+                     zipf_s=zipf_s).items():
+        if v is not None:
+            cfg[k] = v
+    base = base_seed(cfg["index"])
+    T = cfg["trees"]
+    ns = loguniform(subseed(base, TAG_TREE_N), T, *cfg["n_range"])
+    sig = loguniform(subseed(base, TAG_TREE_SIGMA), T, *cfg["sigma_range"])
+    offsets = np.zeros(T + 1, dtype=np.uint64)
+    offsets[1:] = np.cumsum(ns, dtype=np.uint64)
+    S = np.empty(int(offsets[-1]), dtype=dtype_for(cfg["width"]))
+    for j in range(T):
+        tj = subseed(base, TAG_TREE_BASE + j)
+        perm = permutation(subseed(tj, TAG_PERM), int(sig[j]))
+        zipf(subseed(tj, TAG_TEXT), int(ns[j]), int(sig[j]), cfg["zipf_s"], cfg["width"], perm,
+             out=S[int(offsets[j]):int(offsets[j + 1])])
+    fw = ForestWorkload(S=S, offsets=offsets, sigmas=sig)
+    q = cfg["queries"]
+    if q:
+        tree = uniform(subseed(base, TAG_MIX_TREE), q, T, 4).astype(np.uint32)
+        op = uniform(subseed(base, TAG_MIX_OP), q, 3, 1).astype(np.uint8)
+        u1 = _unit(subseed(base, TAG_MIX_U1), q)
+        u2 = _unit(subseed(base, TAG_MIX_U2), q)
+        n_t = ns[tree]
+        pos = _scaled(u1, n_t)                       # access / rank position, index of the drawn symbol
+        sym = np.zeros(q, dtype=np.uint32)
+        arg = np.zeros(q, dtype=np.uint64)
+        has = n_t > 0
+        sym[has] = S[(offsets[tree[has]] + pos[has]).astype(np.int64)]
+        arg[op == 0] = pos[op == 0]
+        rk = op == 1
+        arg[rk] = _scaled(u2[rk], n_t[rk])
+        sel = np.nonzero(op == 2)[0]
+        if sel.size:
+            order = sel[np.argsort(tree[sel], kind="stable")]
+            tt = tree[order]
+            bounds = np.searchsorted(tt, np.arange(T + 1))
+            for j in range(T):
+                a, b = bounds[j], bounds[j + 1]
+                if a == b:
+                    continue
+                idx = order[a:b]
+                cnt = np.bincount(fw.seq(j), minlength=int(sig[j])).astype(np.uint64)
+                arg[idx] = 1 + _scaled(u2[idx], np.maximum(cnt[sym[idx]], 1))
+        fw.tree, fw.op, fw.sym, fw.arg = tree, op, sym, arg
+    return fw
