@@ -1,6 +1,6 @@
 """Benchmark of the wavelet-tree hot path on one MI355X.
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload text_zipf]
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload text_zipf|forest|serve]
 
 One step = one pass of the whole hot path over one batch of synthetic input already resident in
 HBM: build the level-wise wavelet tree of n symbols (histogram, node tables, every level's bits,
@@ -13,6 +13,15 @@ steps; the per-part rates are in `rates`. `roofline` covers the kernel with the 
 step; `roofline_build` the build's level pass, timed with HIP events recorded by the library
 around every level launch on the build stream.
 `cpu_baseline` times the plain CPU oracle on a bounded prefix of the same workload.
+
+--workload forest: 1024 u16 sequences (lengths log-uniform in [2^10, 2^24], alphabets log-uniform in
+[4, 2^16], Zipf 1.0) built as one forest (one captured graph launch, |L2| and s from the autotuner)
+plus 2^24 mixed access/rank/select queries across the trees; also timed the plain way (one wt_build
+and three query calls per tree) for the comparison.
+--workload serve: 64 resident trees of 2^26 u8 Zipf(1.0) symbols with learned select indexes; query
+batches of log-uniform size in [1, 2^20] (70 % select, 20 % rank, 10 % access) from page-locked host
+memory, replayed at saturation and at Poisson arrivals of 0.5, 0.8 and 0.95 of the saturation rate,
+with plain and with learned selects; p50/p99 latency and queries/s.
 """
 from __future__ import annotations
 
@@ -30,7 +39,7 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
 PMC_FILE = os.path.join(ROOT, "profiles", "level_kernel_text_zipf_pmc.json")
-LEVEL_SRC = os.path.join(ROOT, "paper_2505_03372_amd", "csrc", "wt_build.hip")
+LEVEL_SRCS = [os.path.join(ROOT, "paper_2505_03372_amd", "csrc", f) for f in ("wt_build_dev.h", "wt_build.hip")]
 
 
 def level_launch_bytes(info: dict, w: int) -> list:
@@ -54,9 +63,12 @@ def level_launch_bytes(info: dict, w: int) -> list:
     return out
 
 
-def source_hash(path: str) -> str:
-    with open(path, "rb") as f:
-        return hashlib.sha256(f.read()).hexdigest()[:16]
+def source_hash(paths) -> str:
+    h = hashlib.sha256()
+    for p in paths:
+        with open(p, "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
 
 
 def load_traffic(per_launch_alg: float):
@@ -66,7 +78,7 @@ def load_traffic(per_launch_alg: float):
         return None
     with open(PMC_FILE) as f:
         pmc = json.load(f)
-    if pmc.get("source_sha256_16") != source_hash(LEVEL_SRC):
+    if pmc.get("source_sha256_16") != source_hash(LEVEL_SRCS):
         return None
     return pmc.get("traffic_bytes_per_launch")
 
@@ -88,6 +100,198 @@ def cpu_baseline(name: str, n_sample: int, q_sample: int) -> dict:
             "sample": "first 2^%d symbols of the same text (oracle build of every level, directory, samples and "
                       "node tables: %.2f s) + 2^%d access, rank and select queries drawn with the same recipe "
                       "(sweeps: %.2f s)" % (n_sample.bit_length() - 1, t1 - t0, q_sample.bit_length() - 1, t2 - t1)}
+
+
+def forest_level_bytes(f, w: int) -> float:
+    """Algorithmic bytes of every level pass of every tree of a forest (as level_launch_bytes)."""
+    return float(sum(sum(level_launch_bytes(t.info, w)) for t in f.trees))
+
+
+def main_forest(args, torch, wt, workloads, dev):
+    cfg = workloads.FOREST
+    print("# generating the batched workload (%d u16 sequences, %d mixed queries)" % (cfg["trees"], cfg["queries"]),
+          file=sys.stderr, flush=True)
+    fw = workloads.make_forest()
+    n_total = int(fw.S.size)
+    dS = torch.from_numpy(fw.S).to(dev)
+    views = [dS[int(fw.offsets[j]):int(fw.offsets[j + 1])] for j in range(fw.trees)]
+    sig = [int(x) for x in fw.sigmas]
+    q = int(fw.arg.size)
+    d_tree, d_op = torch.from_numpy(fw.tree).to(dev), torch.from_numpy(fw.op).to(dev)
+    d_sym, d_arg = torch.from_numpy(fw.sym).to(dev), torch.from_numpy(fw.arg).to(dev)
+    out = torch.empty(q, dtype=torch.uint64, device=dev)
+    # the plain way: per tree and op, the query indexes (built once, outside the timed region)
+    groups = []
+    order = np.lexsort((fw.op, fw.tree))
+    keys = fw.tree[order].astype(np.int64) * 4 + fw.op[order]
+    bounds = np.searchsorted(keys, np.arange(fw.trees * 4 + 1))
+    for j in range(fw.trees):
+        g = []
+        for o in range(3):
+            idx = order[bounds[4 * j + o]:bounds[4 * j + o + 1]]
+            g.append(None if idx.size == 0 else (torch.from_numpy(fw.sym[idx]).to(dev),
+                                                  torch.from_numpy(fw.arg[idx]).to(dev),
+                                                  torch.empty(idx.size, dtype=torch.uint64 if o else torch.uint32,
+                                                              device=dev)))
+        groups.append(g)
+    del fw
+    torch.cuda.synchronize()
+    print("# autotuning |L2| and s per shape bucket", file=sys.stderr, flush=True)
+    tune, trep = wt.autotune(views, sig)
+    print("# tuned %d buckets in %.0f ms" % (trep["buckets"], trep["total_ms"]), file=sys.stderr, flush=True)
+
+    def forest_step(record):
+        e0, e1, e2 = (torch.cuda.Event(enable_timing=True) for _ in range(3))
+        t0 = time.perf_counter()
+        f = wt.build_forest(views, sig, tune=tune)
+        t1 = time.perf_counter()
+        e0.record()
+        f.query_mixed(d_tree, d_op, d_sym, d_arg, out=out)
+        e1.record()
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        if record is not None:
+            record.append(dict(build_s=t1 - t0, query_ms=e0.elapsed_time(e1), total_s=t2 - t0, info=dict(f.info),
+                               level_bytes=forest_level_bytes(f, 2)))
+        f.free()
+
+    def plain_step():
+        t0 = time.perf_counter()
+        trees = [wt.build(v, s) for v, s in zip(views, sig)]
+        t1 = time.perf_counter()
+        for t, g in zip(trees, groups):
+            if g[0] is not None:
+                t.access(g[0][1], out=g[0][2])
+            if g[1] is not None:
+                t.rank(g[1][0], g[1][1], out=g[1][2])
+            if g[2] is not None:
+                t.select(g[2][0], g[2][1], out=g[2][2])
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        for t in trees:
+            t.free()
+        return t1 - t0, t2 - t1, t2 - t0
+
+    for _ in range(args.warmup):
+        forest_step(None)
+    recs = []
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        forest_step(recs)
+    t1 = time.perf_counter()
+    ms_per_step = (t1 - t0) * 1e3 / args.steps
+    plain = [plain_step() for _ in range(max(1, min(args.steps, 3)))]
+    pb, pq, pt = (float(np.median([p[i] for p in plain])) for i in range(3))
+    fb = float(np.median([r["build_s"] for r in recs]))
+    fq = float(np.median([r["query_ms"] for r in recs])) * 1e-3
+    gms = float(np.median([r["info"]["graph_ms"] for r in recs]))
+    lb = recs[0]["level_bytes"]
+    ach = lb / (gms * 1e-3) / 1e9
+    line = {
+        "metric": "batched build symbols/s + mixed queries/s (forest vs one tree at a time)",
+        "value": (n_total + q) / (ms_per_step * 1e-3), "unit": "(symbols+queries)/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_per_step, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "u16", "data": "synthetic",
+        "config": {"workload": "forest", "trees": len(views), "symbols": n_total, "sym_bytes": 2,
+                   "mixed_queries": q, "tuned_buckets": trep["buckets"]},
+        "rates": {"forest_build_symbols_per_s": n_total / fb, "forest_build_ms": fb * 1e3,
+                  "forest_graph_ms": gms, "forest_plan_ms": float(np.median([r["info"]["plan_ms"] for r in recs])),
+                  "forest_capture_ms": float(np.median([r["info"]["capture_ms"] for r in recs])),
+                  "forest_graph_kernels": recs[0]["info"]["graph_kernels"],
+                  "mixed_queries_per_s": q / fq, "mixed_ms": fq * 1e3,
+                  "plain_build_symbols_per_s": n_total / pb, "plain_build_ms": pb * 1e3,
+                  "plain_queries_per_s": q / pq, "plain_queries_ms": pq * 1e3,
+                  "forest_vs_plain_build_speedup": pb / fb, "forest_vs_plain_query_speedup": pq / fq,
+                  "forest_vs_plain_total_speedup": pt / (fb + fq)},
+        "roofline": {"kernel": "forest build graph (every level pass of every tree)", "bound": "hbm",
+                     "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": ach / HBM_PEAK_GBS,
+                     "traffic": None, "bytes_per_launch": lb, "avg_launch_ms": gms, "launches": len(recs),
+                     "note": "level-pass algorithmic bytes of all trees / graph duration (includes histograms, "
+                             "scans and node tables)"},
+    }
+    print(json.dumps(line), flush=True)
+
+
+def main_serve(args, torch, wt, workloads, dev):
+    T, N, QPOOL = 64, 1 << 26, 1 << 24
+    print("# generating %d trees of 2^26 u8 Zipf(1.0)" % T, file=sys.stderr, flush=True)
+    fw = workloads.make_forest(trees=T, n_range=(N, N), sigma_range=(256, 256), queries=0, width=1, index=4)
+    dS = torch.from_numpy(fw.S).to(dev)
+    views = [dS[int(fw.offsets[j]):int(fw.offsets[j + 1])] for j in range(T)]
+    f = wt.build_forest(views, [256] * T)
+    for t in f.trees:
+        t.learn_select()
+    torch.cuda.synchronize()
+    print("# query pool", file=sys.stderr, flush=True)
+    base = workloads.subseed(workloads.base_seed(4), 1)
+    r = [workloads.raw(workloads.subseed(base, k), 0, QPOOL) for k in range(4)]
+    tree = (r[0] % np.uint64(T)).astype(np.uint32)
+    pick = r[1] % np.uint64(10)
+    op = np.where(pick < 7, 2, np.where(pick < 9, 1, 0)).astype(np.uint8)
+    pos = r[2] % np.uint64(N)
+    sym = fw.S[(fw.offsets[tree] + pos).astype(np.int64)].astype(np.uint32)
+    arg = pos.copy()
+    cnt = np.stack([np.bincount(fw.seq(j), minlength=256) for j in range(T)]).astype(np.uint64)
+    sel = op == 2
+    arg[sel] = 1 + r[3][sel] % cnt[tree[sel], sym[sel]]
+    del fw, dS, views
+
+    def pinned(a):
+        t = torch.empty(a.size, dtype=getattr(torch, str(a.dtype)), pin_memory=True)
+        t.numpy()[:] = a
+        return t
+
+    p_tree, p_op, p_sym, p_arg = pinned(tree), pinned(op), pinned(sym), pinned(arg)
+    op_l = op.copy()
+    op_l[op_l == 2] = 3
+    p_op_l = pinned(op_l)
+    p_out = torch.empty(QPOOL, dtype=torch.uint64, pin_memory=True)
+    nreq = 2000
+    sizes = workloads.loguniform(workloads.subseed(base, 5), nreq, 1, 1 << 20).astype(np.int64)
+    offs = (workloads.raw(workloads.subseed(base, 6), 0, nreq) % np.uint64(QPOOL - (1 << 20))).astype(np.int64)
+    u = workloads.raw(workloads.subseed(base, 7), 0, nreq).astype(np.float64) / 2.0 ** 64
+    gaps = -np.log1p(-u)  # unit-mean exponential
+
+    def requests(arrivals, learned):
+        ops = p_op_l if learned else p_op
+        rq = []
+        for i in range(nreq):
+            a, b = int(offs[i]), int(offs[i] + sizes[i])
+            rq.append(dict(tree=p_tree[a:b], op=ops[a:b], sym=p_sym[a:b], arg=p_arg[a:b], out=p_out[a:b],
+                           arrival_s=float(arrivals[i])))
+        return rq
+
+    srv = wt.Server(f, slots=8, mem_budget=4 << 30)
+    res = {}
+    for learned in (False, True):
+        key = "learned" if learned else "plain"
+        srv.run(requests(np.zeros(nreq), learned)[:50])  # warm-up
+        _, sat = srv.run(requests(np.zeros(nreq), learned))
+        res[key] = {"saturation_qps": sat["qps"], "saturation_p50_ms": sat["lat_p50_s"] * 1e3,
+                    "saturation_p99_ms": sat["lat_p99_s"] * 1e3}
+        mean_q = float(sizes.mean())
+        for rho in (0.5, 0.8, 0.95):
+            lam = rho * res["plain"]["saturation_qps"] / mean_q  # batches/s, offered against the plain path
+            arr = np.cumsum(gaps / lam)
+            _, st = srv.run(requests(arr, learned))
+            res[key]["rho%.2f" % rho] = {"qps": st["qps"], "p50_ms": st["lat_p50_s"] * 1e3,
+                                         "p99_ms": st["lat_p99_s"] * 1e3, "peak_in_flight": st["peak_in_flight"],
+                                         "peak_bytes": st["peak_bytes"]}
+        print("# %s: %s" % (key, json.dumps(res[key])), file=sys.stderr, flush=True)
+    srv.close()
+    f.free()
+    line = {
+        "metric": "serving queries/s with p50/p99 latency; learned vs plain select",
+        "value": res["learned"]["saturation_qps"], "unit": "queries/s", "n_gpus": 1, "steps": nreq, "warmup": 50,
+        "ms_per_step": None, "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "u8",
+        "data": "synthetic",
+        "config": {"workload": "serve", "trees": T, "n_per_tree": N, "batches": nreq,
+                   "batch_sizes": "log-uniform int [1, 2^20]", "mix": "70% select / 20% rank / 10% access",
+                   "slots": 8, "mem_budget_bytes": 4 << 30, "host_buffers": "page-locked"},
+        "rates": res,
+        "learned_vs_plain_saturation": res["learned"]["saturation_qps"] / res["plain"]["saturation_qps"],
+    }
+    print(json.dumps(line), flush=True)
 
 
 def main():
@@ -116,6 +320,10 @@ def main():
     wt.lib()
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
+    if args.workload == "forest":
+        return main_forest(args, torch, wt, workloads, dev)
+    if args.workload == "serve":
+        return main_serve(args, torch, wt, workloads, dev)
     idx, n, width, sigma, q = workloads.CONFIGS[args.workload]
     print("# generating workload %s: n=%d width=%d sigma=%d q=%d" % (args.workload, n, width, sigma, q),
           file=sys.stderr, flush=True)

@@ -322,14 +322,72 @@ wt_status wt_forest_free(wt_forest* f);
  *   d_op[j] = WT_OP_ACCESS: access(d_arg[j])            (d_sym ignored; 0xFFFFFFFF if out of range)
  *             WT_OP_RANK:   rank_{d_sym[j]}(d_arg[j])
  *             WT_OP_SELECT: select_{d_sym[j]}(d_arg[j])
+ *             WT_OP_SELECT_LEARNED: the same select through the tree's learned index
+ *                           (wt_learn_select; a plain select on a tree without one)
  * with the results and sentinels of wt_access / wt_rank / wt_select, widened to 64 bits in d_out[j].
- * An unknown tree or op gives UINT64_MAX. The queries are grouped by (op, |L2| of the tree) on the
- * device so that each wavefront runs one traversal; d_out is in the order of the queries.
+ * An unknown tree or op gives UINT64_MAX. Batches above 2048 queries are grouped by (op, |L2| of the
+ * tree) on the device so that each wavefront runs one traversal; d_out is in the order of the
+ * queries. d_sym may be NULL when every op is an access. At most 2^32 - 1 queries per call.
  */
-enum { WT_OP_ACCESS = 0, WT_OP_RANK = 1, WT_OP_SELECT = 2 };
+enum { WT_OP_ACCESS = 0, WT_OP_RANK = 1, WT_OP_SELECT = 2, WT_OP_SELECT_LEARNED = 3 };
 
 wt_status wt_query_mixed(const wt_forest* f, const uint32_t* d_tree, const uint8_t* d_op, const uint32_t* d_sym,
                          const uint64_t* d_arg, uint64_t q, uint64_t* d_out, wt_stream_t stream);
+
+/* ---- serving (spec extension): continuous batching over a resident forest ----
+ *
+ * A server keeps a forest resident and replays a trace of query batches (requests) on its own clock:
+ * a request becomes visible at its arrival time and is admitted in arrival order as soon as one of
+ * the server's slots (a stream each) is free and the request's device buffers fit in what the memory
+ * budget has left (the budget is carved once from device memory at creation). An admitted request
+ * copies its queries to the device, runs wt_query_mixed's kernels and copies the answers back, all on
+ * its slot's stream, so requests that arrive while others are on the GPU overlap with them.
+ * Latency = completion (observed by the server) - arrival. A request's answers do not depend on what
+ * else is in flight. A request larger than the whole budget is rejected (status WT_ERR_OOM).
+ */
+typedef struct wt_server wt_server;
+
+typedef struct {
+  uint32_t slots;          /* requests in flight at once; 0 = 8, at most 64 */
+  uint32_t reserved;
+  uint64_t mem_budget;     /* device bytes for in-flight requests; 0 = 4 GiB */
+  double sim_ns_per_query; /* > 0: no GPU; a request occupies its slot for q * this many ns (scheduler tests) */
+} wt_server_opts;
+
+typedef struct {
+  const uint32_t* h_tree;  /* host arrays of q entries (page-locked memory gives asynchronous copies) */
+  const uint8_t* h_op;     /* ops as in wt_query_mixed */
+  const uint32_t* h_sym;   /* may be NULL when every op is an access */
+  const uint64_t* h_arg;
+  uint64_t* h_out;         /* answers as in wt_query_mixed */
+  uint64_t q;
+  double arrival_s;        /* arrival on the server clock (seconds from the start of wt_server_run) */
+} wt_request;
+
+typedef struct {
+  double arrival_s, admit_s, done_s;
+  uint32_t slot;           /* slot that ran it (UINT32_MAX: rejected) */
+  wt_status status;        /* WT_OK, or WT_ERR_OOM when larger than the budget */
+} wt_completion;
+
+typedef struct {
+  uint32_t requests, rejected, peak_in_flight, reserved;
+  uint64_t queries;        /* answered */
+  uint64_t peak_bytes;     /* most device bytes held by admitted requests at once */
+  double makespan_s;       /* first arrival to last completion */
+  double qps;              /* answered queries / makespan */
+  double lat_p50_s, lat_p99_s, lat_mean_s, lat_max_s;
+} wt_serve_stats;
+
+/* f may be NULL only with sim_ns_per_query > 0. */
+wt_status wt_server_create(const wt_forest* f, const wt_server_opts* opts, wt_server** out);
+
+/* Replays `count` requests sorted by arrival; returns when all are answered or rejected. comps[i]
+   describes reqs[i]; stats may be NULL. */
+wt_status wt_server_run(wt_server* s, const wt_request* reqs, uint32_t count, wt_completion* comps,
+                        wt_serve_stats* stats);
+
+wt_status wt_server_destroy(wt_server* s);
 
 /* Thread-local description of the last failure on this thread ("" if none). */
 const char* wt_last_error(void);

@@ -35,8 +35,8 @@ ABI_FUNCTIONS = ("wt_set_allocator", "wt_build", "wt_free", "wt_access", "wt_ran
                  "wt_export", "wt_build_profile", "wt_last_error", "wt_version", "wt_learn_select",
                  "wt_select_learned", "wt_learned_info", "wt_learned_model", "wt_mlp_loss_grad",
                  "wt_build_forest", "wt_forest_tree", "wt_forest_info", "wt_forest_free", "wt_query_mixed",
-                 "wt_autotune")
-OP_ACCESS, OP_RANK, OP_SELECT = 0, 1, 2
+                 "wt_autotune", "wt_server_create", "wt_server_run", "wt_server_destroy")
+OP_ACCESS, OP_RANK, OP_SELECT, OP_SELECT_LEARNED = 0, 1, 2, 3
 TUNE_NB, TUNE_SB = 21, 7
 MLP_PARAMS = 49
 
@@ -115,6 +115,29 @@ class ForestInfo(ctypes.Structure):
                 ("capture_ms", ctypes.c_float), ("graph_ms", ctypes.c_float), ("total_ms", ctypes.c_float)]
 
 
+class ServerOpts(ctypes.Structure):
+    _fields_ = [("slots", ctypes.c_uint32), ("reserved", ctypes.c_uint32), ("mem_budget", ctypes.c_uint64),
+                ("sim_ns_per_query", ctypes.c_double)]
+
+
+class Request(ctypes.Structure):
+    _fields_ = [("h_tree", ctypes.c_void_p), ("h_op", ctypes.c_void_p), ("h_sym", ctypes.c_void_p),
+                ("h_arg", ctypes.c_void_p), ("h_out", ctypes.c_void_p), ("q", ctypes.c_uint64),
+                ("arrival_s", ctypes.c_double)]
+
+
+class Completion(ctypes.Structure):
+    _fields_ = [("arrival_s", ctypes.c_double), ("admit_s", ctypes.c_double), ("done_s", ctypes.c_double),
+                ("slot", ctypes.c_uint32), ("status", ctypes.c_int32)]
+
+
+class ServeStats(ctypes.Structure):
+    _fields_ = [("requests", ctypes.c_uint32), ("rejected", ctypes.c_uint32), ("peak_in_flight", ctypes.c_uint32),
+                ("reserved", ctypes.c_uint32), ("queries", ctypes.c_uint64), ("peak_bytes", ctypes.c_uint64),
+                ("makespan_s", ctypes.c_double), ("qps", ctypes.c_double), ("lat_p50_s", ctypes.c_double),
+                ("lat_p99_s", ctypes.c_double), ("lat_mean_s", ctypes.c_double), ("lat_max_s", ctypes.c_double)]
+
+
 class ProfEntry(ctypes.Structure):
     _fields_ = [("kernel", ctypes.c_char * 32), ("level", ctypes.c_int32), ("ms", ctypes.c_float)]
 
@@ -173,6 +196,13 @@ def lib():
     L.wt_autotune.restype = ctypes.c_int
     L.wt_autotune.argtypes = [ctypes.POINTER(SeqDesc), u32, u32, ctypes.POINTER(TuneOpts), vp,
                               ctypes.POINTER(TuneTable), ctypes.POINTER(TuneReport)]
+    L.wt_server_create.restype = ctypes.c_int
+    L.wt_server_create.argtypes = [vp, ctypes.POINTER(ServerOpts), ctypes.POINTER(vp)]
+    L.wt_server_run.restype = ctypes.c_int
+    L.wt_server_run.argtypes = [vp, ctypes.POINTER(Request), u32, ctypes.POINTER(Completion),
+                                ctypes.POINTER(ServeStats)]
+    L.wt_server_destroy.restype = ctypes.c_int
+    L.wt_server_destroy.argtypes = [vp]
     L.wt_learned_model.restype = ctypes.c_int
     L.wt_learned_model.argtypes = [vp, u32, ctypes.POINTER(LearnedModel)]
     L.wt_mlp_loss_grad.restype = ctypes.c_int
@@ -482,6 +512,58 @@ def build_forest(seqs, sigmas, l2_bits=None, sample_rates=None, tune: TuneTable 
     _check(lib().wt_build_forest(descs, len(seqs), w, ctypes.byref(opts), ctypes.c_void_p(_stream_handle(stream)),
                                  ctypes.byref(h)))
     return Forest(h.value)
+
+
+def _host_ptr(a) -> int:
+    """Address of a host array: numpy array or CPU torch tensor (page-locked ones copy asynchronously)."""
+    if a is None:
+        return 0
+    if isinstance(a, np.ndarray):
+        if not a.flags.c_contiguous:
+            raise ValueError("host arrays must be contiguous")
+        return a.ctypes.data
+    if getattr(a, "is_cuda", False):
+        raise ValueError("server requests take host arrays")
+    return a.data_ptr()
+
+
+class Server:
+    """Continuous-batching server over a resident forest (or a simulated executor when sim_ns_per_query > 0)."""
+
+    def __init__(self, forest=None, slots: int = 8, mem_budget: int = 0, sim_ns_per_query: float = 0.0):
+        opts = ServerOpts(slots, 0, mem_budget, sim_ns_per_query)
+        h = ctypes.c_void_p(0)
+        _check(lib().wt_server_create(forest._h if forest is not None else None, ctypes.byref(opts), ctypes.byref(h)))
+        self._h = h
+        self._forest = forest
+
+    def run(self, requests):
+        """requests: sorted by arrival, each a dict with tree, op, sym, arg, out (host arrays of q entries: u32, u8,
+        u32, u64, u64) and arrival_s; or, for a simulated server, just q and arrival_s.
+        Returns (list of completion dicts, stats dict)."""
+        R = (Request * max(len(requests), 1))()
+        for i, r in enumerate(requests):
+            q = int(r["q"]) if "q" in r else len(r["arg"])
+            R[i] = Request(_host_ptr(r.get("tree")), _host_ptr(r.get("op")), _host_ptr(r.get("sym")),
+                           _host_ptr(r.get("arg")), _host_ptr(r.get("out")), q, float(r["arrival_s"]))
+        C = (Completion * max(len(requests), 1))()
+        st = ServeStats()
+        _check(lib().wt_server_run(self._h, R, len(requests), C, ctypes.byref(st)))
+        comps = [dict(arrival_s=C[i].arrival_s, admit_s=C[i].admit_s, done_s=C[i].done_s, slot=C[i].slot,
+                      status=C[i].status) for i in range(len(requests))]
+        stats = {f: getattr(st, f) for f, _ in ServeStats._fields_ if f != "reserved"}
+        return comps, stats
+
+    def close(self):
+        if self._h is not None and self._h.value:
+            _check(lib().wt_server_destroy(self._h))
+            self._h = ctypes.c_void_p(0)
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def mlp_loss_grad(params, u, v, stream=None):

@@ -18,6 +18,7 @@
 #include "wt_build_dev.h"
 #include "wt_host.h"
 #include "wt_internal.h"
+#include "wt_learn_dev.h"
 #include "wt_query_dev.h"
 
 namespace wt {
@@ -159,13 +160,16 @@ __global__ void kf_gather(const TreeB* __restrict__ tb, const uint32_t* __restri
 // Query state of one tree of a forest.
 struct QTree {
   QArgs a;
-  uint32_t l2s;  // log2 |L2|
+  const LearnQ* lq;  // compiled learned-select models, or NULL
+  uint32_t l2s;      // log2 |L2|
   uint32_t pad;
 };
 
-// Class of a query: op * 4 + (log2 |L2| - 8) for the three ops; kMixInvalid for an unknown tree or op.
-constexpr uint32_t kMixInvalid = 12;
-constexpr uint32_t kMixClasses = 13;
+// Class of a query: op * 4 + (log2 |L2| - 8) for the four ops (a learned select on a tree without a
+// learned index is a plain select); kMixInvalid for an unknown tree or op.
+constexpr uint32_t kMixInvalid = 16;
+constexpr uint32_t kMixClasses = 17;
+constexpr uint64_t kMixDirectMax = 2048;  // batches up to this size skip the binning
 constexpr uint32_t kMixChunk = kQT * 16;  // queries per binning block
 
 struct MixRec {
@@ -175,8 +179,10 @@ struct MixRec {
 
 __device__ __forceinline__ uint32_t mix_class(const QTree* __restrict__ qt, uint32_t ntrees, uint32_t tree,
                                               uint32_t op) {
-  if (tree >= ntrees || op > 2) return kMixInvalid;
-  return op * 4 + (qt[tree].l2s - 8);
+  if (tree >= ntrees || op > WT_OP_SELECT_LEARNED) return kMixInvalid;
+  const QTree& t = qt[tree];
+  if (op == WT_OP_SELECT_LEARNED && !t.lq) op = WT_OP_SELECT;
+  return op * 4 + (t.l2s - 8);
 }
 
 // Adds the lanes of every class present in the wave to the LDS counter of that class.
@@ -197,8 +203,8 @@ __global__ __launch_bounds__(kQT) void k_mix_count(const QTree* __restrict__ qt,
                                                    const uint32_t* __restrict__ tree, const uint8_t* __restrict__ op,
                                                    uint64_t q, uint8_t* __restrict__ cls,
                                                    uint32_t* __restrict__ counts) {
-  __shared__ uint32_t s_cnt[16];
-  if (threadIdx.x < 16) s_cnt[threadIdx.x] = 0;
+  __shared__ uint32_t s_cnt[32];
+  if (threadIdx.x < 32) s_cnt[threadIdx.x] = 0;
   __syncthreads();
   const uint64_t c0 = (uint64_t)blockIdx.x * kMixChunk;
   for (uint32_t i = threadIdx.x; i < kMixChunk; i += kQT) {
@@ -223,9 +229,9 @@ __global__ __launch_bounds__(kQT) void k_mix_scatter(uint64_t q, const uint8_t* 
                                                      const uint64_t* __restrict__ arg,
                                                      const uint32_t* __restrict__ counts, uint32_t* __restrict__ cursor,
                                                      uint32_t* __restrict__ perm, MixRec* __restrict__ rec) {
-  __shared__ uint32_t s_cnt[16];
-  __shared__ uint32_t s_off[16];
-  if (threadIdx.x < 16) s_cnt[threadIdx.x] = 0;
+  __shared__ uint32_t s_cnt[32];
+  __shared__ uint32_t s_off[32];
+  if (threadIdx.x < 32) s_cnt[threadIdx.x] = 0;
   __syncthreads();
   const uint64_t c0 = (uint64_t)blockIdx.x * kMixChunk;
   for (uint32_t i = threadIdx.x; i < kMixChunk; i += kQT) {
@@ -292,8 +298,64 @@ __global__ __launch_bounds__(kQT) void k_mix_run(const QTree* __restrict__ qt, c
     uint64_t res;
     if constexpr (OP == WT_OP_ACCESS) res = access_one<L2S>(a, a.d.meta, r.arg);
     else if constexpr (OP == WT_OP_RANK) res = rank_one<L2S>(a, a.d.meta, r.sym, r.arg);
-    else res = select_one<L2S>(a, a.d.meta, r.sym, r.arg);
+    else if constexpr (OP == WT_OP_SELECT) res = select_one<L2S>(a, a.d.meta, r.sym, r.arg);
+    else res = select_learned_one<L2S, learn_gs<L2S>()>(a, a.d.meta, qt[r.tree].lq, r.sym, r.arg);
     out[perm[s]] = res;
+  }
+}
+
+// Small batches: every query in one kernel, no binning (a wave may run several traversals).
+__global__ __launch_bounds__(kQT) void k_mix_direct(const QTree* __restrict__ qt, uint32_t ntrees,
+                                                    const uint32_t* __restrict__ tree, const uint8_t* __restrict__ op,
+                                                    const uint32_t* __restrict__ sym,
+                                                    const uint64_t* __restrict__ arg, uint64_t q,
+                                                    uint64_t* __restrict__ out) {
+  for (uint64_t j = (uint64_t)blockIdx.x * kQT + threadIdx.x; j < q; j += (uint64_t)gridDim.x * kQT) {
+    const uint32_t tj = tree[j];
+    const uint32_t c = mix_class(qt, ntrees, tj, op[j]);
+    uint64_t res = ~0ull;
+    if (c != kMixInvalid) {
+      const QArgs& a = qt[tj].a;
+      const LevelMeta* meta = a.d.meta;
+      const uint32_t sj = sym ? sym[j] : 0u;
+      const uint64_t x = arg[j];
+      switch (c >> 2) {
+        case WT_OP_ACCESS:
+          switch (c & 3) {
+            case 0: res = access_one<8>(a, meta, x); break;
+            case 1: res = access_one<9>(a, meta, x); break;
+            case 2: res = access_one<10>(a, meta, x); break;
+            default: res = access_one<11>(a, meta, x); break;
+          }
+          break;
+        case WT_OP_RANK:
+          switch (c & 3) {
+            case 0: res = rank_one<8>(a, meta, sj, x); break;
+            case 1: res = rank_one<9>(a, meta, sj, x); break;
+            case 2: res = rank_one<10>(a, meta, sj, x); break;
+            default: res = rank_one<11>(a, meta, sj, x); break;
+          }
+          break;
+        case WT_OP_SELECT:
+          switch (c & 3) {
+            case 0: res = select_one<8>(a, meta, sj, x); break;
+            case 1: res = select_one<9>(a, meta, sj, x); break;
+            case 2: res = select_one<10>(a, meta, sj, x); break;
+            default: res = select_one<11>(a, meta, sj, x); break;
+          }
+          break;
+        default: {
+          const LearnQ* lq = qt[tj].lq;
+          switch (c & 3) {
+            case 0: res = select_learned_one<8, learn_gs<8>()>(a, meta, lq, sj, x); break;
+            case 1: res = select_learned_one<9, learn_gs<9>()>(a, meta, lq, sj, x); break;
+            case 2: res = select_learned_one<10, learn_gs<10>()>(a, meta, lq, sj, x); break;
+            default: res = select_learned_one<11, learn_gs<11>()>(a, meta, lq, sj, x); break;
+          }
+        }
+      }
+    }
+    out[j] = res;
   }
 }
 
@@ -320,7 +382,8 @@ struct wt_forest {
   std::vector<wt_tree*> trees;  // caller order
   void* block = nullptr;        // every tree's parts
   size_t block_bytes = 0;
-  void* qtab = nullptr;         // per-tree query state for wt_query_mixed
+  void* qtab = nullptr;         // per-tree query state for wt_query_mixed (made on first use)
+  uint64_t qversion = 0;        // sum of the trees' learned-index versions when qtab was made
   wt_forest_info_t info{};
 };
 
@@ -702,24 +765,6 @@ extern "C" wt_status wt_build_forest(const wt_seq_desc* h_descs, uint32_t count,
     f->trees.push_back(t);
     symbols += t->n;
   }
-  // query state of every tree for wt_query_mixed
-  {
-    std::vector<QTree> hq(count);
-    for (uint32_t j = 0; j < count; ++j) {
-      std::memset(&hq[j], 0, sizeof(QTree));
-      hq[j].a = make_args(f->trees[j]);
-      hq[j].l2s = log2_floor(f->trees[j]->l2_bits);
-    }
-    f->qtab = dev_alloc(count * sizeof(QTree), st);
-    if (!f->qtab) return bail(fail(WT_ERR_OOM, "wt_build_forest: query table allocation failed"));
-    he = hipMemcpyAsync(f->qtab, hq.data(), count * sizeof(QTree), hipMemcpyHostToDevice, st);
-    if (he == hipSuccess) he = hipStreamSynchronize(st);
-    if (he != hipSuccess) {
-      dev_free(f->qtab, st);
-      f->qtab = nullptr;
-      return bail(fail(WT_ERR_HIP, "wt_build_forest: query table upload: %s", hipGetErrorString(he)));
-    }
-  }
   const auto t_end = std::chrono::steady_clock::now();
   auto ms = [](auto a, auto b) { return (float)std::chrono::duration<double, std::milli>(b - a).count(); };
   f->info.trees = count;
@@ -766,26 +811,31 @@ extern "C" wt_status wt_forest_free(wt_forest* f) {
   return WT_OK;
 }
 
-extern "C" wt_status wt_query_mixed(const wt_forest* f, const uint32_t* d_tree, const uint8_t* d_op,
-                                    const uint32_t* d_sym, const uint64_t* d_arg, uint64_t q, uint64_t* d_out,
-                                    wt_stream_t stream) {
-  clear_error();
-  if (!f) return fail(WT_ERR_ARG, "wt_query_mixed: forest is NULL");
-  if (q == 0) return WT_OK;
-  if (!d_tree || !d_op || !d_arg || !d_out) return fail(WT_ERR_ARG, "wt_query_mixed: NULL buffer");
-  if (q >= (1ull << 32)) return fail(WT_ERR_ARG, "wt_query_mixed: at most 2^32 - 1 queries per call");
-  hipStream_t st = (hipStream_t)stream;
-  // scratch: counts and cursors, classes, slots, records
-  const size_t o_cnt = 0, o_cls = 256, o_perm = round_up(o_cls + q, 256), o_rec = round_up(o_perm + 4 * q, 256);
-  const size_t bytes = o_rec + 16 * q;
-  char* sb = (char*)dev_alloc(bytes, st);
-  if (!sb) return fail(WT_ERR_OOM, "wt_query_mixed: scratch allocation of %zu bytes failed", bytes);
-  uint32_t* counts = (uint32_t*)(sb + o_cnt);
-  uint32_t* cursor = counts + 16;
-  const QTree* qt = (const QTree*)f->qtab;
+namespace wt {
+
+// Scratch of one mixed batch: class counts and cursors, classes, slots, records (none for the
+// unbinned path).
+size_t mixed_scratch_bytes(uint64_t q) {
+  if (q <= kMixDirectMax) return 0;
+  const size_t o_perm = round_up(256 + q, 256), o_rec = round_up(o_perm + 4 * q, 256);
+  return o_rec + 16 * q;
+}
+
+// Enqueues one mixed batch on st (scratch: mixed_scratch_bytes(q) bytes of device memory).
+hipError_t mixed_enqueue(const QTree* qt, uint32_t ntrees, const uint32_t* d_tree, const uint8_t* d_op,
+                         const uint32_t* d_sym, const uint64_t* d_arg, uint64_t q, uint64_t* d_out, char* sb,
+                         hipStream_t st) {
+  if (q <= kMixDirectMax) {
+    hipLaunchKernelGGL(k_mix_direct, dim3((uint32_t)ceil_div(q, kQT)), dim3(kQT), 0, st, qt, ntrees, d_tree, d_op,
+                       d_sym, d_arg, q, d_out);
+    return hipGetLastError();
+  }
+  const size_t o_cls = 256, o_perm = round_up(o_cls + q, 256), o_rec = round_up(o_perm + 4 * q, 256);
+  uint32_t* counts = (uint32_t*)sb;
+  uint32_t* cursor = counts + 32;
   const uint32_t nchunk = (uint32_t)ceil_div(q, kMixChunk);
-  hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(64), 0, st, counts, 32u);
-  hipLaunchKernelGGL(k_mix_count, dim3(nchunk), dim3(kQT), 0, st, qt, f->count, d_tree, d_op, q, (uint8_t*)(sb + o_cls),
+  hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(64), 0, st, counts, 64u);
+  hipLaunchKernelGGL(k_mix_count, dim3(nchunk), dim3(kQT), 0, st, qt, ntrees, d_tree, d_op, q, (uint8_t*)(sb + o_cls),
                      counts);
   hipLaunchKernelGGL(k_mix_scatter, dim3(nchunk), dim3(kQT), 0, st, q, (const uint8_t*)(sb + o_cls), d_tree, d_sym,
                      d_arg, (const uint32_t*)counts, cursor, (uint32_t*)(sb + o_perm), (MixRec*)(sb + o_rec));
@@ -797,11 +847,64 @@ extern "C" wt_status wt_query_mixed(const wt_forest* f, const uint32_t* d_tree, 
   WT_MIX(0, 8); WT_MIX(0, 9); WT_MIX(0, 10); WT_MIX(0, 11);
   WT_MIX(1, 8); WT_MIX(1, 9); WT_MIX(1, 10); WT_MIX(1, 11);
   WT_MIX(2, 8); WT_MIX(2, 9); WT_MIX(2, 10); WT_MIX(2, 11);
+  WT_MIX(3, 8); WT_MIX(3, 9); WT_MIX(3, 10); WT_MIX(3, 11);
 #undef WT_MIX
   hipLaunchKernelGGL(k_mix_invalid, dim3(std::min<uint32_t>(grid, 64)), dim3(kQT), 0, st, (const uint32_t*)counts, pm,
                      d_out);
-  const hipError_t he = hipGetLastError();
-  dev_free(sb, st);
+  return hipGetLastError();
+}
+
+uint32_t forest_count(const wt_forest* f) { return f->count; }
+
+// Query table of a forest, rebuilt when a tree's learned index changed since it was made.
+wt_status forest_qtab(const wt_forest* fc, hipStream_t st, const QTree** out) {
+  wt_forest* f = const_cast<wt_forest*>(fc);
+  uint64_t ver = 0;
+  for (const wt_tree* t : f->trees) ver += t->learn_version;
+  if (!f->qtab || ver != f->qversion) {
+    std::vector<QTree> hq(f->count);
+    for (uint32_t j = 0; j < f->count; ++j) {
+      const wt_tree* t = f->trees[j];
+      std::memset(&hq[j], 0, sizeof(QTree));
+      hq[j].a = make_args(t);
+      hq[j].lq = t->learn && t->nmodels ? (const LearnQ*)((const char*)t->learn + (size_t)t->nmodels * learn_model_bytes())
+                                        : nullptr;
+      hq[j].l2s = log2_floor(t->l2_bits);
+    }
+    if (!f->qtab) {
+      f->qtab = dev_alloc(f->count * sizeof(QTree), st);
+      if (!f->qtab) return fail(WT_ERR_OOM, "query table allocation failed");
+    }
+    WT_HIP(hipMemcpyAsync(f->qtab, hq.data(), f->count * sizeof(QTree), hipMemcpyHostToDevice, st));
+    WT_HIP(hipStreamSynchronize(st));
+    f->qversion = ver;
+  }
+  *out = (const QTree*)f->qtab;
+  return WT_OK;
+}
+
+}  // namespace wt
+
+extern "C" wt_status wt_query_mixed(const wt_forest* f, const uint32_t* d_tree, const uint8_t* d_op,
+                                    const uint32_t* d_sym, const uint64_t* d_arg, uint64_t q, uint64_t* d_out,
+                                    wt_stream_t stream) {
+  clear_error();
+  if (!f) return fail(WT_ERR_ARG, "wt_query_mixed: forest is NULL");
+  if (q == 0) return WT_OK;
+  if (!d_tree || !d_op || !d_arg || !d_out) return fail(WT_ERR_ARG, "wt_query_mixed: NULL buffer");
+  if (q >= (1ull << 32)) return fail(WT_ERR_ARG, "wt_query_mixed: at most 2^32 - 1 queries per call");
+  hipStream_t st = (hipStream_t)stream;
+  const QTree* qt = nullptr;
+  const wt_status rc = forest_qtab(f, st, &qt);
+  if (rc != WT_OK) return rc;
+  const size_t bytes = mixed_scratch_bytes(q);
+  char* sb = nullptr;
+  if (bytes) {
+    sb = (char*)dev_alloc(bytes, st);
+    if (!sb) return fail(WT_ERR_OOM, "wt_query_mixed: scratch allocation of %zu bytes failed", bytes);
+  }
+  const hipError_t he = mixed_enqueue(qt, f->count, d_tree, d_op, d_sym, d_arg, q, d_out, sb, st);
+  if (sb) dev_free(sb, st);
   if (he != hipSuccess) return fail(WT_ERR_HIP, "wt_query_mixed: %s", hipGetErrorString(he));
   return WT_OK;
 }

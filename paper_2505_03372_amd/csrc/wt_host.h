@@ -21,6 +21,7 @@ struct wt_tree {
   std::vector<wt_prof_entry> prof;
   void* learn = nullptr;  // learned select models (device), one per child node
   uint32_t nmodels = 0;
+  uint32_t learn_version = 0;  // incremented by every training of the learned index
   wt_learned_info_t linfo{};
 };
 
@@ -50,6 +51,9 @@ struct TreePlan {
   uint64_t nheap;  // node table entries: 2^L - 1
   size_t off_meta, off_cum, off_nodes, off_bits, off_l1, off_l2, off_smp, total;
 };
+
+// Bytes of one training record of the learned index (the query forms follow the records).
+size_t learn_model_bytes();
 
 TreePlan plan_tree(uint64_t n, uint32_t w, uint64_t sigma, uint32_t L, uint32_t l2_bits, uint32_t srate);
 

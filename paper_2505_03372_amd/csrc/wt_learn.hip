@@ -392,6 +392,10 @@ __global__ __launch_bounds__(kLT) void k_mlp_loss_grad(const float* __restrict__
 
 using namespace wt;
 
+namespace wt {
+size_t learn_model_bytes() { return sizeof(LearnModel); }
+}  // namespace wt
+
 extern "C" wt_status wt_learn_select(wt_tree* t, const wt_learn_opts* opts, wt_stream_t stream) {
   clear_error();
   if (!t) return fail(WT_ERR_ARG, "wt_learn_select: tree is NULL");
@@ -410,6 +414,7 @@ extern "C" wt_status wt_learn_select(wt_tree* t, const wt_learn_opts* opts, wt_s
     t->learn = nullptr;
   }
   t->nmodels = (uint32_t)nmodels;
+  ++t->learn_version;
   std::memset(&t->linfo, 0, sizeof(t->linfo));
   t->linfo.params_per_model = kNP;
   if (nmodels == 0) {

@@ -1,0 +1,127 @@
+"""GPU tests of the serving loop (continuous batching over a resident forest).
+
+* every request's answers are the same alone (one slot, one request at a time) and in the mix (eight
+  slots, overlapping requests), equal to one wt_query_mixed call per request, and equal to the oracle
+  on a sample; the same with selects through the learned index;
+* the in-flight device memory never exceeds the budget, and requests still complete exactly.
+"""
+import numpy as np
+import pytest
+
+import oracle
+import workloads
+from tests import gpu_cases as G
+
+pytestmark = pytest.mark.gpu
+
+TREES, N = 8, 1 << 20
+
+
+@pytest.fixture(scope="module")
+def served():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    import paper_2505_03372_amd as wt
+    seqs = []
+    for j in range(TREES):
+        sj = workloads.subseed(0x5E4E, j)
+        seqs.append(workloads.zipf(sj, N, 256, 1.0, 1, workloads.permutation(sj + 1, 256)))
+    G.log("serving: forest of %d x 2^20 u8" % TREES)
+    f = wt.build_forest([G.dev(S) for S in seqs], [256] * TREES)
+    for t in f.trees:
+        t.learn_select()
+    yield f, seqs
+    f.free()
+
+
+def _trace(seqs, nreq, qmax, seed, gap_s):
+    """Poisson arrivals, sizes log-uniform in [1, qmax], 70 % select / 20 % rank / 10 % access."""
+    sizes = workloads.loguniform(workloads.subseed(seed, 1), nreq, 1, qmax).astype(np.int64)
+    u = workloads.raw(workloads.subseed(seed, 2), 0, nreq).astype(np.float64) / 2.0 ** 64
+    arr = np.cumsum(-np.log1p(-u) * gap_s)
+    reqs = []
+    off = 0
+    base = workloads.subseed(seed, 3)
+    for i in range(nreq):
+        q = int(sizes[i])
+        r = workloads.raw(base, off, off + 4 * q)
+        off += 4 * q
+        tree = (r[:q] % np.uint64(TREES)).astype(np.uint32)
+        pick = r[q:2 * q] % np.uint64(10)
+        op = np.where(pick < 7, 2, np.where(pick < 9, 1, 0)).astype(np.uint8)
+        pos = (r[2 * q:3 * q] % np.uint64(N)).astype(np.uint64)
+        sym = np.array([seqs[t][p] for t, p in zip(tree, pos)], dtype=np.uint32)
+        arg = pos.copy()
+        sel = op == 2
+        for t in range(TREES):
+            m = sel & (tree == t)
+            if m.any():
+                cnt = np.bincount(seqs[t], minlength=256).astype(np.uint64)
+                arg[m] = 1 + r[3 * q:4 * q][m] % cnt[sym[m]]
+        reqs.append(dict(tree=tree, op=op, sym=sym, arg=arg, out=np.zeros(q, np.uint64), arrival_s=float(arr[i])))
+    return reqs
+
+
+def _run(f, reqs, slots, budget=0, learned=False):
+    import paper_2505_03372_amd as wt
+    rq = []
+    for r in reqs:
+        op = r["op"].copy()
+        if learned:
+            op[op == 2] = 3
+        rq.append(dict(r, op=op, out=np.zeros_like(r["out"])))
+    s = wt.Server(f, slots=slots, mem_budget=budget)
+    comps, st = s.run(rq)
+    s.close()
+    assert all(c["status"] == wt.WT_OK for c in comps)
+    return [r["out"] for r in rq], comps, st
+
+
+def test_results_alone_equal_results_in_the_mix(served):
+    f, seqs = served
+    reqs = _trace(seqs, 120, 1 << 15, 0x77, 20e-6)
+    G.log("serving: mix (8 slots)")
+    mix, _, st_mix = _run(f, reqs, 8)
+    G.log("  %s" % st_mix)
+    assert st_mix["peak_in_flight"] > 1
+    G.log("serving: alone (1 slot, spaced arrivals)")
+    alone_reqs = [dict(r, arrival_s=0.0) for r in reqs]
+    alone, _, st_alone = _run(f, alone_reqs, 1)
+    assert st_alone["peak_in_flight"] == 1
+    G.log("serving: learned selects in the mix")
+    lmix, _, _ = _run(f, reqs, 8, learned=True)
+    for i, r in enumerate(reqs):
+        ref = G.host(f.query_mixed(G.dev(r["tree"]), G.dev(r["op"]), G.dev(r["sym"]), G.dev(r["arg"])))
+        np.testing.assert_array_equal(mix[i], ref, err_msg="request %d in the mix" % i)
+        np.testing.assert_array_equal(alone[i], ref, err_msg="request %d alone" % i)
+        np.testing.assert_array_equal(lmix[i], ref, err_msg="request %d learned" % i)
+    # oracle on a sample of every request
+    for i in range(0, len(reqs), 7):
+        r = reqs[i]
+        for t in range(TREES):
+            for o in range(3):
+                m = np.nonzero((r["tree"] == t) & (r["op"] == o))[0][:50]
+                if m.size == 0:
+                    continue
+                S = seqs[t]
+                if o == 0:
+                    e = oracle.access(S, r["arg"][m]).astype(np.uint64)
+                elif o == 1:
+                    e = oracle.rank(S, 256, r["sym"][m], r["arg"][m])
+                else:
+                    e = oracle.select(S, 256, r["sym"][m], r["arg"][m])
+                np.testing.assert_array_equal(mix[i][m], e)
+
+
+def test_memory_budget_bounds_in_flight_bytes(served):
+    f, seqs = served
+    reqs = _trace(seqs, 60, 1 << 16, 0x99, 5e-6)
+    biggest = max(len(r["arg"]) for r in reqs)
+    budget = 3 * (60 * biggest + (1 << 16))
+    G.log("serving: budget %d bytes" % budget)
+    out, comps, st = _run(f, reqs, 8, budget=budget)
+    G.log("  %s" % st)
+    assert 0 < st["peak_bytes"] <= budget
+    for i, r in enumerate(reqs):
+        ref = G.host(f.query_mixed(G.dev(r["tree"]), G.dev(r["op"]), G.dev(r["sym"]), G.dev(r["arg"])))
+        np.testing.assert_array_equal(out[i], ref)

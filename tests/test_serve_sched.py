@@ -1,0 +1,98 @@
+"""CPU tests of the serving scheduler (simulated executor: a request holds its slot for q * cost ns).
+
+Admission is in arrival order, only into a free slot, and only when the request's device buffers fit
+in what the memory budget has left; a request larger than the whole budget is rejected; latencies are
+completion - arrival; the statistics agree with the completions.
+"""
+import numpy as np
+import pytest
+
+import paper_2505_03372_amd as wt
+
+
+def _reqs(sizes, arrivals):
+    return [dict(q=int(q), arrival_s=float(a)) for q, a in zip(sizes, arrivals)]
+
+
+def _request_bytes(q):
+    r = lambda x: (x + 255) // 256 * 256  # noqa: E731
+    scratch = 0 if q <= 2048 else r(r(256 + q) + 4 * q) + 16 * q
+    return r(4 * q) + r(q) + r(4 * q) + r(8 * q) + r(8 * q) + r(scratch)
+
+
+def test_fifo_single_slot():
+    s = wt.Server(None, slots=1, sim_ns_per_query=200.0)
+    sizes = [1000, 10, 5000, 1, 3000]
+    comps, st = s.run(_reqs(sizes, [0.0] * len(sizes)))
+    admits = [c["admit_s"] for c in comps]
+    assert admits == sorted(admits)
+    for a, b in zip(comps, comps[1:]):
+        assert b["admit_s"] >= a["done_s"] - 1e-9
+    for q, c in zip(sizes, comps):
+        assert c["status"] == wt.WT_OK and c["slot"] == 0
+        assert c["done_s"] - c["admit_s"] >= q * 200e-9 * 0.999
+    assert st["peak_in_flight"] == 1 and st["queries"] == sum(sizes) and st["rejected"] == 0
+    s.close()
+
+
+def test_slots_bound_concurrency():
+    s = wt.Server(None, slots=4, sim_ns_per_query=1000.0)
+    comps, st = s.run(_reqs([2000] * 12, [0.0] * 12))
+    assert st["peak_in_flight"] == 4
+    slots = [c["slot"] for c in comps]
+    assert set(slots) == {0, 1, 2, 3}
+    # never more than 4 requests overlap
+    ev = sorted([(c["admit_s"], 1) for c in comps] + [(c["done_s"], -1) for c in comps], key=lambda x: (x[0], x[1]))
+    live = peak = 0
+    for _, d in ev:
+        live += d
+        peak = max(peak, live)
+    assert peak <= 4
+    s.close()
+
+
+def test_memory_budget_admission_and_rejection():
+    q = 100000
+    budget = 2 * _request_bytes(q) + 1000  # room for two such requests at once
+    s = wt.Server(None, slots=8, mem_budget=budget, sim_ns_per_query=20.0)
+    sizes = [q] * 6 + [10 * q] + [q]  # the 10q request exceeds the whole budget
+    comps, st = s.run(_reqs(sizes, [0.0] * len(sizes)))
+    assert st["peak_bytes"] <= budget
+    assert st["peak_in_flight"] == 2
+    assert comps[6]["status"] == wt.WT_ERR_OOM and comps[6]["slot"] == 0xFFFFFFFF
+    assert st["rejected"] == 1 and st["queries"] == 7 * q
+    assert all(c["status"] == wt.WT_OK for i, c in enumerate(comps) if i != 6)
+    s.close()
+
+
+def test_arrivals_and_latency_stats():
+    rng = np.random.default_rng(5)
+    n = 300
+    arr = np.cumsum(rng.exponential(200e-6, n))
+    sizes = rng.integers(1, 2000, n)
+    s = wt.Server(None, slots=3, sim_ns_per_query=100.0)
+    comps, st = s.run(_reqs(sizes, arr))
+    lat = np.array([c["done_s"] - c["arrival_s"] for c in comps])
+    assert np.all(np.array([c["admit_s"] for c in comps]) >= arr - 1e-9)
+    assert np.all(lat >= sizes * 100e-9 * 0.999)
+    srt = np.sort(lat)
+    assert abs(st["lat_p50_s"] - srt[int(0.5 * (n - 1) + 0.5)]) < 1e-12
+    assert abs(st["lat_p99_s"] - srt[int(0.99 * (n - 1) + 0.5)]) < 1e-12
+    assert st["lat_max_s"] == pytest.approx(srt[-1])
+    assert st["queries"] == int(sizes.sum())
+    assert st["qps"] == pytest.approx(st["queries"] / st["makespan_s"])
+    s.close()
+
+
+def test_unsorted_arrivals_rejected():
+    s = wt.Server(None, slots=2, sim_ns_per_query=10.0)
+    with pytest.raises(wt.WTError) as ei:
+        s.run(_reqs([1, 1], [0.5, 0.1]))
+    assert ei.value.status == wt.WT_ERR_ARG
+    s.close()
+
+
+def test_server_needs_forest_without_simulation():
+    with pytest.raises(wt.WTError) as ei:
+        wt.Server(None, slots=2)
+    assert ei.value.status == wt.WT_ERR_ARG

@@ -258,14 +258,14 @@ def _scaled(u: np.ndarray, m: np.ndarray) -> np.ndarray:
 
 
 def make_forest(trees: int | None = None, n_range=None, sigma_range=None, queries: int | None = None,
-                width: int | None = None, zipf_s: float | None = None) -> ForestWorkload:
+                width: int | None = None, zipf_s: float | None = None, index: int | None = None) -> ForestWorkload:
     """Sequence j: length log-uniform in n_range, alphabet log-uniform in sigma_range, Zipf(s) symbol
     frequencies over a per-tree seeded permutation. Mixed queries: tree uniform, op uniform over
     {access, rank, select}, position uniform in the tree, symbol drawn from the tree's sequence, k
     uniform in [1, count]."""
     cfg = dict(FOREST)
     for k, v in dict(trees=trees, n_range=n_range, sigma_range=sigma_range, queries=queries, width=width,
-                     zipf_s=zipf_s).items():
+                     zipf_s=zipf_s, index=index).items():
         if v is not None:
             cfg[k] = v
     base = base_seed(cfg["index"])
