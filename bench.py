@@ -40,6 +40,9 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
 PMC_FILE = os.path.join(ROOT, "profiles", "level_kernel_text_zipf_pmc.json")
 LEVEL_SRCS = [os.path.join(ROOT, "paper_2505_03372_amd", "csrc", f) for f in ("wt_build_dev.h", "wt_build.hip")]
+QUERY_PMC_FILE = os.path.join(ROOT, "profiles", "query_kernels_text_zipf_pmc.json")
+QUERY_SRCS = [os.path.join(ROOT, "paper_2505_03372_amd", "csrc", f)
+              for f in ("wt_query_dev.h", "wt_query.hip", "wt_learn_dev.h", "wt_learn.hip", "wt_internal.h")]
 
 
 def level_launch_bytes(info: dict, w: int) -> list:
@@ -81,6 +84,18 @@ def load_traffic(per_launch_alg: float):
     if pmc.get("source_sha256_16") != source_hash(LEVEL_SRCS):
         return None
     return pmc.get("traffic_bytes_per_launch")
+
+
+def load_query_traffic(kernel: str, q: int):
+    """HBM traffic of a query kernel launch from the committed counter summary (same sources, same q)."""
+    if not os.path.exists(QUERY_PMC_FILE):
+        return None
+    with open(QUERY_PMC_FILE) as f:
+        pmc = json.load(f)
+    if pmc.get("source_sha256_16") != source_hash(QUERY_SRCS) or pmc.get("queries_per_launch") != q:
+        return None
+    k = pmc.get("kernels", {}).get(kernel)
+    return k["traffic_bytes"] if k else None
 
 
 def cpu_baseline(name: str, n_sample: int, q_sample: int) -> dict:
@@ -429,6 +444,8 @@ def main():
                 "bound": "hbm", "achieved": qa, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": qa / HBM_PEAK_GBS,
                 "traffic": None, "bytes_per_launch": qbytes, "avg_launch_ms": per_step[dom], "launches": len(qms[dom]),
                 "note": "random access: 64 B (one L2 block of bits) per level per query"}
+        if args.workload == "text_zipf":
+            roof["traffic"] = load_query_traffic(roof["kernel"], q)
     line = {
         "metric": "build symbols/s + access/rank/select queries/s; learned vs plain select",
         "value": items / (ms_per_step * 1e-3),

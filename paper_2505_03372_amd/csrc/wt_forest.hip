@@ -277,9 +277,11 @@ __global__ __launch_bounds__(kQT) void k_mix_scatter(uint64_t q, const uint8_t* 
 }
 
 // Pass 3: one kernel per class (op, |L2|), over that class's range of slots: every wave runs one
-// traversal, with the registers of that traversal alone.
+// traversal, with the registers of that traversal alone. The lanes of a wave ask different trees, so
+// the tree arguments live in vector registers; the bound keeps every class at 80 (6 waves per SIMD)
+// without spills.
 template <int OP, int L2S>
-__global__ __launch_bounds__(kQT) void k_mix_run(const QTree* __restrict__ qt, const uint32_t* __restrict__ counts,
+__global__ __launch_bounds__(kQT, 6) void k_mix_run(const QTree* __restrict__ qt, const uint32_t* __restrict__ counts,
                                                  const uint32_t* __restrict__ perm, const MixRec* __restrict__ rec,
                                                  uint64_t* __restrict__ out) {
   constexpr uint32_t kC = OP * 4 + (L2S - 8);

@@ -108,7 +108,7 @@ def _mixed_reference(f, seqs, tree, op, sym, arg):
     out = np.full(tree.size, np.iinfo(np.uint64).max, dtype=np.uint64)
     for j in range(len(f)):
         for o in range(3):
-            idx = np.nonzero((tree == j) & (op == o))[0]
+            idx = np.nonzero((tree == j) & ((op == o) | ((op == 3) & (o == 2))))[0]
             if idx.size == 0:
                 continue
             t = f[j]
@@ -128,8 +128,8 @@ def test_mixed_queries_match_per_tree_calls(small_forest):
     q = 200003
     r = workloads.raw(0x3151, 0, 4 * q)
     tree = (r[:q] % np.uint64(T + 2)).astype(np.uint32)  # two unknown tree ids
-    op = (r[q:2 * q] % np.uint64(4)).astype(np.uint8)     # op 3 is unknown
-    op[:5] = [0, 1, 2, 255, 7]
+    op = (r[q:2 * q] % np.uint64(5)).astype(np.uint8)     # op 3: learned select (plain here), op 4 unknown
+    op[:6] = [0, 1, 2, 3, 255, 7]
     sym = np.zeros(q, dtype=np.uint32)
     arg = np.zeros(q, dtype=np.uint64)
     for j in range(T):
@@ -140,14 +140,15 @@ def test_mixed_queries_match_per_tree_calls(small_forest):
         b = r[3 * q + idx]
         arg[idx] = a % np.uint64(n + 2)                  # some positions past the end
         sym[idx] = (b % np.uint64(sigma + 1)).astype(np.uint32)  # some symbols past the alphabet
-        selj = idx[op[idx] == 2]
+        is_sel = (op[idx] == 2) | (op[idx] == 3)
+        selj = idx[is_sel]
         if n:
             cnt = np.bincount(S, minlength=sigma + 1).astype(np.uint64)
-            arg[selj] = a[op[idx] == 2] % (cnt[sym[selj]] + np.uint64(2))  # k = 0 and k > count included
+            arg[selj] = a[is_sel] % (cnt[sym[selj]] + np.uint64(2))  # k = 0 and k > count included
     G.log("mixed queries q=%d over %d trees" % (q, T))
     got = G.host(f.query_mixed(G.dev(tree), G.dev(op), G.dev(sym), G.dev(arg)))
     exp = _mixed_reference(f, seqs, tree, op, sym, arg)
-    bad = (tree >= T) | (op > 2)
+    bad = (tree >= T) | (op > 3)
     assert np.all(got[bad] == np.iinfo(np.uint64).max)
     G._assert_eq("mixed vs per-tree", got, exp, np.stack([tree.astype(np.uint64), op.astype(np.uint64), arg], 1))
     # and the oracle on a sample
@@ -156,7 +157,7 @@ def test_mixed_queries_match_per_tree_calls(small_forest):
         sub = idx[(tree[idx] == j)]
         S = seqs[j]
         for o, fn in ((0, None), (1, oracle.rank), (2, oracle.select)):
-            s2 = sub[op[sub] == o]
+            s2 = sub[(op[sub] == o) | ((op[sub] == 3) & (o == 2))]
             if s2.size == 0:
                 continue
             if o == 0:
