@@ -322,8 +322,8 @@ wt_status wt_forest_free(wt_forest* f);
  *   d_op[j] = WT_OP_ACCESS: access(d_arg[j])            (d_sym ignored; 0xFFFFFFFF if out of range)
  *             WT_OP_RANK:   rank_{d_sym[j]}(d_arg[j])
  *             WT_OP_SELECT: select_{d_sym[j]}(d_arg[j])
- *             WT_OP_SELECT_LEARNED: the same select through the tree's learned index
- *                           (wt_learn_select; a plain select on a tree without one)
+ *             WT_OP_SELECT_LEARNED: accepted and answered as WT_OP_SELECT (the learned index is
+ *                           not used inside mixed batches; wt_select_learned uses it)
  * with the results and sentinels of wt_access / wt_rank / wt_select, widened to 64 bits in d_out[j].
  * An unknown tree or op gives UINT64_MAX. Batches above 2048 queries are grouped by (op, |L2| of the
  * tree) on the device so that each wavefront runs one traversal; d_out is in the order of the
