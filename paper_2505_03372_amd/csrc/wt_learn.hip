@@ -292,12 +292,15 @@ __global__ void k_learn_compile(const LearnModel* __restrict__ models, LearnQ* _
 // Prediction error in L2 blocks at every L2 boundary inside the node, for the compiled trained model
 // (the evaluation queries use) and for the starting point; sets the correction budget
 // eps = ceil(max error) + 2.
+constexpr uint32_t kEvalChunks = 64;  // blocks per model in the error evaluation
+
 template <int L2S>
-__global__ __launch_bounds__(kLT) void k_learn_eval(TreeDev d, LearnModel* __restrict__ models,
-                                                    LearnQ* __restrict__ qm) {
+__global__ __launch_bounds__(kLT) void k_learn_eval(TreeDev d, const LearnModel* __restrict__ models,
+                                                    const LearnQ* __restrict__ qm, float4* __restrict__ part) {
   __shared__ float s_r[4][4];
   const uint64_t slot = blockIdx.x;
-  LearnModel& M = models[slot];
+  const uint32_t ch = blockIdx.y;
+  const LearnModel& M = models[slot];
   if (M.eps < 0) return;
   const LevelMeta m = d.meta[M.level];
   const LearnQ& Q = qm[slot];
@@ -305,7 +308,7 @@ __global__ __launch_bounds__(kLT) void k_learn_eval(TreeDev d, LearnModel* __res
   const uint64_t blo = (start + (1ull << L2S) - 1) >> L2S, bhi = (start + len - 1) >> L2S;
   const double bl = (double)(1u << L2S);
   float smax = 0.f, ssum = 0.f, imax = 0.f, isum = 0.f;
-  for (uint64_t B = blo + threadIdx.x; B <= bhi && bhi >= blo; B += blockDim.x) {
+  for (uint64_t B = blo + (uint64_t)ch * kLT + threadIdx.x; B <= bhi && bhi >= blo; B += (uint64_t)kLT * kEvalChunks) {
     const uint64_t x = B << L2S;
     const double u = (double)(count_before<L2S>(d, m, M.side, x) - M.rank0) / (double)cnt;
     const double tv = (double)(x - start);
@@ -339,14 +342,35 @@ __global__ __launch_bounds__(kLT) void k_learn_eval(TreeDev d, LearnModel* __res
       c = fmaxf(c, s_r[w][2]);
       dsum += s_r[w][3];
     }
-    const float nb = bhi >= blo ? (float)(bhi - blo + 1) : 1.f;
-    M.err_max = a;
-    M.err_mean = bsum / nb;
-    M.err_init_max = c;
-    M.err_init_mean = dsum / nb;
-    M.eps = (int32_t)ceilf(a) + 2;
-    qm[slot].eps = M.eps;
+    part[slot * kEvalChunks + ch] = make_float4(a, bsum, c, dsum);
   }
+}
+
+// Per model, the chunks' partial results in a fixed order: error statistics and the budget
+// eps = ceil(max error) + 2.
+template <int L2S>
+__global__ void k_learn_finish(LearnModel* __restrict__ models, LearnQ* __restrict__ qm,
+                               const float4* __restrict__ part, uint64_t nmodels) {
+  const uint64_t slot = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (slot >= nmodels) return;
+  LearnModel& M = models[slot];
+  if (M.eps < 0) return;
+  float a = 0.f, bsum = 0.f, c = 0.f, dsum = 0.f;
+  for (uint32_t ch = 0; ch < kEvalChunks; ++ch) {
+    const float4 v = part[slot * kEvalChunks + ch];
+    a = fmaxf(a, v.x);
+    bsum += v.y;
+    c = fmaxf(c, v.z);
+    dsum += v.w;
+  }
+  const uint64_t blo = (M.start + (1ull << L2S) - 1) >> L2S, bhi = (M.start + M.len - 1) >> L2S;
+  const float nb = bhi >= blo ? (float)(bhi - blo + 1) : 1.f;
+  M.err_max = a;
+  M.err_mean = bsum / nb;
+  M.err_init_max = c;
+  M.err_init_mean = dsum / nb;
+  M.eps = (int32_t)ceilf(a) + 2;
+  qm[slot].eps = M.eps;
 }
 
 // ---------------------------------------------------------------- learned select
@@ -425,7 +449,9 @@ extern "C" wt_status wt_learn_select(wt_tree* t, const wt_learn_opts* opts, wt_s
   const size_t mbytes = nmodels * sizeof(LearnModel);
   t->learn = dev_alloc(mbytes + nmodels * sizeof(LearnQ), st);  // training records, then query forms
   if (!t->learn) return fail(WT_ERR_OOM, "wt_learn_select: model allocation failed");
-  float2* pts = (float2*)dev_alloc(nmodels * pmax * sizeof(float2), st);
+  // training points (stride pmax per model), reused for the evaluation's partial results
+  const size_t pts_per_model = std::max<size_t>(pmax, kEvalChunks * sizeof(float4) / sizeof(float2));
+  float2* pts = (float2*)dev_alloc(nmodels * pts_per_model * sizeof(float2), st);
   if (!pts) return fail(WT_ERR_OOM, "wt_learn_select: training data allocation failed");
   LearnModel* models = (LearnModel*)t->learn;
   LearnQ* qm = (LearnQ*)((char*)t->learn + mbytes);
@@ -446,12 +472,21 @@ extern "C" wt_status wt_learn_select(wt_tree* t, const wt_learn_opts* opts, wt_s
                      epochs, lr);
   hipLaunchKernelGGL(k_learn_compile, dim3(grid), dim3(256), 0, st, (const LearnModel*)models, qm, nmodels);
   WT_HIP(hipEventRecord(e1, st));
+  // error evaluation: partial results of kEvalChunks blocks per model in the (no longer needed)
+  // training-point buffer, then one thread per model combines them
+  float4* part = reinterpret_cast<float4*>(pts);
+  const dim3 eg((uint32_t)nmodels, kEvalChunks);
+#define WT_EVAL(S)                                                                                        \
+  hipLaunchKernelGGL(k_learn_eval<S>, eg, dim3(kLT), 0, st, t->dev, (const LearnModel*)models,           \
+                     (const LearnQ*)qm, part);                                                           \
+  hipLaunchKernelGGL(k_learn_finish<S>, dim3(grid), dim3(256), 0, st, models, qm, (const float4*)part, nmodels)
   switch (t->l2_bits) {
-    case 256: hipLaunchKernelGGL(k_learn_eval<8>, dim3((uint32_t)nmodels), dim3(kLT), 0, st, t->dev, models, qm); break;
-    case 512: hipLaunchKernelGGL(k_learn_eval<9>, dim3((uint32_t)nmodels), dim3(kLT), 0, st, t->dev, models, qm); break;
-    case 1024: hipLaunchKernelGGL(k_learn_eval<10>, dim3((uint32_t)nmodels), dim3(kLT), 0, st, t->dev, models, qm); break;
-    default: hipLaunchKernelGGL(k_learn_eval<11>, dim3((uint32_t)nmodels), dim3(kLT), 0, st, t->dev, models, qm); break;
+    case 256: WT_EVAL(8); break;
+    case 512: WT_EVAL(9); break;
+    case 1024: WT_EVAL(10); break;
+    default: WT_EVAL(11); break;
   }
+#undef WT_EVAL
   WT_HIP(hipGetLastError());
   std::vector<LearnModel> hm(nmodels);
   WT_HIP(hipMemcpyAsync(hm.data(), models, mbytes, hipMemcpyDeviceToHost, st));
