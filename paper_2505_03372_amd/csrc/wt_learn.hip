@@ -380,12 +380,13 @@ template <int L2S>
 __global__ __launch_bounds__(kQT, 8) void k_select_learned(QArgs a, const LearnQ* __restrict__ qm,
                                                         const uint32_t* __restrict__ sym,
                                                         const uint64_t* __restrict__ kin, uint64_t q,
-                                                        uint64_t* __restrict__ out) {
+                                                        uint64_t* __restrict__ out,
+                                                        const uint32_t* __restrict__ perm) {
   constexpr int GS = learn_gs<L2S>();
   __shared__ LevelMeta s_meta[WT_MAX_LEVELS];
   load_meta(a, s_meta);
   for (uint64_t j = (uint64_t)blockIdx.x * kQT + threadIdx.x; j < q; j += (uint64_t)gridDim.x * kQT) {
-    out[j] = select_learned_one<L2S, GS>(a, s_meta, qm, sym[j], kin[j]);
+    out[perm ? perm[j] : j] = select_learned_one<L2S, GS>(a, s_meta, qm, sym[j], kin[j]);
   }
 }
 // One evaluation of the training objective (same device code as k_learn_train).
@@ -531,7 +532,17 @@ extern "C" wt_status wt_select_learned(const wt_tree* t, const uint32_t* d_sym, 
   const QArgs a = make_args(t);
   const uint32_t grid = query_grid(q);
   const LearnQ* qm = (const LearnQ*)((const char*)t->learn + (size_t)t->nmodels * sizeof(LearnModel));
-  WT_DISPATCH_L2(t->l2_bits, k_select_learned, a, qm, d_sym, d_k, q, d_out);
+  SortBufs sb;
+  bool binned;
+  const wt_status rc = sort_batch(t, a, 2, d_sym, d_k, q, st, sb, binned);
+  if (rc != WT_OK) return rc;
+  if (binned) {
+    WT_DISPATCH_L2(t->l2_bits, k_select_learned, a, qm, (const uint32_t*)sb.ssym, (const uint64_t*)sb.sarg, q, d_out,
+                   (const uint32_t*)sb.perm);
+    dev_free(sb.block, st);
+  } else {
+    WT_DISPATCH_L2(t->l2_bits, k_select_learned, a, qm, d_sym, d_k, q, d_out, (const uint32_t*)nullptr);
+  }
   WT_HIP(hipGetLastError());
   return WT_OK;
 }

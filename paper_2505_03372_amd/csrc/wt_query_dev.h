@@ -236,6 +236,20 @@ inline QArgs make_args(const wt_tree* t) {
   return a;
 }
 
+// Locality binning of a query batch (wt_query.hip): on success with `binned`, the batch's symbols and
+// arguments in bucket order are in ssym / sarg and the query index of every slot in perm; the caller
+// frees `block` (stream-ordered) after its traversal.
+struct SortBufs {
+  char* block = nullptr;
+  uint32_t* cnt;
+  uint32_t* bucket;
+  uint32_t* perm;
+  uint32_t* ssym;
+  uint64_t* sarg;
+};
+wt_status sort_batch(const wt_tree* t, const QArgs& a, int kind, const uint32_t* sym, const uint64_t* arg, uint64_t q,
+                     hipStream_t st, SortBufs& sb, bool& binned);
+
 inline uint32_t query_grid(uint64_t q) { return (uint32_t)std::min<uint64_t>(ceil_div(q, kQT), 4096); }
 
 #define WT_DISPATCH_L2(bits, KERNEL, ...)                                                          \
