@@ -358,6 +358,7 @@ def main():
     print("# workload resident in HBM", file=sys.stderr, flush=True)
 
     stream = torch.cuda.current_stream()
+    wt.query_profiling(True)
 
     def step(record):
         t = wt.build(S, sigma, profile=True)
@@ -380,8 +381,9 @@ def main():
                     t.select_learned(a[0], a[1], out=outs["select_learned"])
                 e1.record(stream)
                 evs[kind if variant == "plain" else "select_learned"] = (e0, e1)
+        qprof = wt.query_profile()  # per-kernel durations of this step's query calls (waits for them)
         if record is not None:
-            record.append((t.profile(), evs, t.info, linfo))
+            record.append((t.profile(), evs, t.info, linfo, qprof))
         t.free()
 
     for _ in range(args.warmup):
@@ -398,7 +400,10 @@ def main():
     info = recs[0][2]
     level_ms, build_ms, learn_ms = [], [], []
     qms = {}
-    for prof, evs, _, linfo in recs:
+    kms = {}
+    for prof, evs, _, linfo, qprof in recs:
+        for e in qprof:
+            kms.setdefault(e["kernel"], []).append(e["ms"])
         level_ms += [p["ms"] for p in prof if p["kernel"] == "level"]
         build_ms.append(sum(p["ms"] for p in prof))
         if linfo is not None:
@@ -423,13 +428,18 @@ def main():
         rates["learned_vs_plain_select_speedup"] = float(np.median(qms["select"]) / np.median(qms["select_learned"]))
     for k in qms:
         rates[k + "_ms_median"] = float(np.median(qms[k]))
+    # kernels of the query calls: traversal kernels and the binning passes (per call, summed over kinds)
+    for k, v in kms.items():
+        per_call = float(np.sum(v)) / max(1, len(recs))
+        rates["kernel_%s_ms_per_step" % k] = per_call
     kname = {1: "k_level<uint8_t>", 2: "k_level<uint16_t>", 4: "k_level<uint32_t>"}[width]
     build_roof = {"kernel": kname, "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                   "frac": achieved / HBM_PEAK_GBS, "traffic": load_traffic(avg_bytes),
                   "bytes_per_launch": avg_bytes, "avg_launch_ms": avg_ms, "launches": len(level_ms)}
     # the kernel with the most time in a step: queries touch at least one 64-byte L2 block of bits per
     # level (random HBM lines), the level pass streams its level
-    per_step = {k: float(np.median(v)) for k, v in qms.items()}
+    # the traversal kernel of each query kind, timed alone (events around the kernel on its stream)
+    per_step = {k: float(np.median(kms[k])) for k in qms if k in kms}
     per_step["level"] = avg_ms * info["levels"]
     dom = max(per_step, key=per_step.get)
     if dom == "level":
@@ -440,7 +450,7 @@ def main():
         roof = {"kernel": {"access": "k_access", "rank": "k_rank", "select": "k_select",
                            "select_learned": "k_select_learned"}[dom] + "<9>",
                 "bound": "hbm", "achieved": qa, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": qa / HBM_PEAK_GBS,
-                "traffic": None, "bytes_per_launch": qbytes, "avg_launch_ms": per_step[dom], "launches": len(qms[dom]),
+                "traffic": None, "bytes_per_launch": qbytes, "avg_launch_ms": per_step[dom], "launches": len(kms[dom]),
                 "note": "random access: 64 B (one L2 block of bits) per level per query"}
         if args.workload == "text_zipf":
             roof["traffic"] = load_query_traffic(roof["kernel"], q)

@@ -153,6 +153,14 @@ typedef struct {
 /* Copies up to cap entries; *count receives the number available. */
 wt_status wt_build_profile(const wt_tree* t, wt_prof_entry* out, uint32_t cap, uint32_t* count);
 
+/* Per-kernel timing of the query calls of this thread (off by default): while on, every query call
+   records HIP events around each of its kernels on its stream. wt_query_profile waits for them, copies
+   up to cap entries ({"sort_count" | "sort_scan" | "sort_scatter" | "access" | "rank" | "select" |
+   "select_learned", -1, ms} in call order; the sort entries belong to the binning of batches of at
+   least 2^16 queries) and clears the list; *count receives the number recorded. */
+wt_status wt_query_profiling(int on);
+wt_status wt_query_profile(wt_prof_entry* out, uint32_t cap, uint32_t* count);
+
 /* ---- learned select index (spec extension of Section 5.4; not in the thesis) ----
  *
  * For every child node of the tree (a node's zeros side or ones side at some level) a small FP32

@@ -35,7 +35,8 @@ ABI_FUNCTIONS = ("wt_set_allocator", "wt_build", "wt_free", "wt_access", "wt_ran
                  "wt_export", "wt_build_profile", "wt_last_error", "wt_version", "wt_learn_select",
                  "wt_select_learned", "wt_learned_info", "wt_learned_model", "wt_mlp_loss_grad",
                  "wt_build_forest", "wt_forest_tree", "wt_forest_info", "wt_forest_free", "wt_query_mixed",
-                 "wt_autotune", "wt_server_create", "wt_server_run", "wt_server_destroy")
+                 "wt_autotune", "wt_server_create", "wt_server_run", "wt_server_destroy", "wt_query_profiling",
+                 "wt_query_profile")
 OP_ACCESS, OP_RANK, OP_SELECT, OP_SELECT_LEARNED = 0, 1, 2, 3
 TUNE_NB, TUNE_SB = 21, 7
 MLP_PARAMS = 49
@@ -196,6 +197,10 @@ def lib():
     L.wt_autotune.restype = ctypes.c_int
     L.wt_autotune.argtypes = [ctypes.POINTER(SeqDesc), u32, u32, ctypes.POINTER(TuneOpts), vp,
                               ctypes.POINTER(TuneTable), ctypes.POINTER(TuneReport)]
+    L.wt_query_profiling.restype = ctypes.c_int
+    L.wt_query_profiling.argtypes = [ctypes.c_int]
+    L.wt_query_profile.restype = ctypes.c_int
+    L.wt_query_profile.argtypes = [ctypes.POINTER(ProfEntry), u32, ctypes.POINTER(u32)]
     L.wt_server_create.restype = ctypes.c_int
     L.wt_server_create.argtypes = [vp, ctypes.POINTER(ServerOpts), ctypes.POINTER(vp)]
     L.wt_server_run.restype = ctypes.c_int
@@ -564,6 +569,19 @@ class Server:
             self.close()
         except Exception:
             pass
+
+
+def query_profiling(on: bool = True):
+    """Record per-kernel durations of this thread's query calls (read with query_profile)."""
+    _check(lib().wt_query_profiling(1 if on else 0))
+
+
+def query_profile() -> list:
+    """Durations of the kernels of this thread's query calls since the last read (waits for them)."""
+    cnt = ctypes.c_uint32(0)
+    arr = (ProfEntry * 4096)()
+    _check(lib().wt_query_profile(arr, 4096, ctypes.byref(cnt)))
+    return [dict(kernel=arr[i].kernel.decode(), ms=arr[i].ms) for i in range(min(cnt.value, 4096))]
 
 
 def mlp_loss_grad(params, u, v, stream=None):

@@ -386,7 +386,8 @@ __global__ __launch_bounds__(kQT, 8) void k_select_learned(QArgs a, const LearnQ
   __shared__ LevelMeta s_meta[WT_MAX_LEVELS];
   load_meta(a, s_meta);
   for (uint64_t j = (uint64_t)blockIdx.x * kQT + threadIdx.x; j < q; j += (uint64_t)gridDim.x * kQT) {
-    out[perm ? perm[j] : j] = select_learned_one<L2S, GS>(a, s_meta, qm, sym[j], kin[j]);
+    const uint64_t jj = perm ? perm[j] : j;
+    out[jj] = select_learned_one<L2S, GS>(a, s_meta, qm, sym[jj], kin[jj]);
   }
 }
 // One evaluation of the training objective (same device code as k_learn_train).
@@ -536,13 +537,14 @@ extern "C" wt_status wt_select_learned(const wt_tree* t, const uint32_t* d_sym, 
   bool binned;
   const wt_status rc = sort_batch(t, a, 2, d_sym, d_k, q, st, sb, binned);
   if (rc != WT_OK) return rc;
+  qprof_begin("select_learned", st);
   if (binned) {
-    WT_DISPATCH_L2(t->l2_bits, k_select_learned, a, qm, (const uint32_t*)sb.ssym, (const uint64_t*)sb.sarg, q, d_out,
-                   (const uint32_t*)sb.perm);
+    WT_DISPATCH_L2(t->l2_bits, k_select_learned, a, qm, d_sym, d_k, q, d_out, (const uint32_t*)sb.perm);
     dev_free(sb.block, st);
   } else {
     WT_DISPATCH_L2(t->l2_bits, k_select_learned, a, qm, d_sym, d_k, q, d_out, (const uint32_t*)nullptr);
   }
+  qprof_end(st);
   WT_HIP(hipGetLastError());
   return WT_OK;
 }

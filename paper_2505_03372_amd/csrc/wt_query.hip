@@ -14,6 +14,8 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cstring>
+#include <vector>
 
 #include "wt_host.h"
 #include "wt_internal.h"
@@ -21,14 +23,17 @@
 
 namespace wt {
 
-// perm: NULL, or the query index of every (binned) slot j; the answer of slot j goes to out[perm[j]].
+// perm: NULL, or the queries in binned order: slot j runs query perm[j] (its arguments are read and its
+// answer written at that index).
 template <int L2S>
 __global__ __launch_bounds__(kQT) void k_access(QArgs a, const uint64_t* __restrict__ pos, uint64_t q,
                                                 uint32_t* __restrict__ out, const uint32_t* __restrict__ perm) {
   __shared__ LevelMeta s_meta[WT_MAX_LEVELS];
   load_meta(a, s_meta);
-  for (uint64_t j = (uint64_t)blockIdx.x * kQT + threadIdx.x; j < q; j += (uint64_t)gridDim.x * kQT)
-    out[perm ? perm[j] : j] = access_one<L2S>(a, s_meta, pos[j]);
+  for (uint64_t j = (uint64_t)blockIdx.x * kQT + threadIdx.x; j < q; j += (uint64_t)gridDim.x * kQT) {
+    const uint64_t jj = perm ? perm[j] : j;
+    out[jj] = access_one<L2S>(a, s_meta, pos[jj]);
+  }
 }
 
 template <int L2S>
@@ -37,8 +42,10 @@ __global__ __launch_bounds__(kQT) void k_rank(QArgs a, const uint32_t* __restric
                                               uint64_t* __restrict__ out, const uint32_t* __restrict__ perm) {
   __shared__ LevelMeta s_meta[WT_MAX_LEVELS];
   load_meta(a, s_meta);
-  for (uint64_t j = (uint64_t)blockIdx.x * kQT + threadIdx.x; j < q; j += (uint64_t)gridDim.x * kQT)
-    out[perm ? perm[j] : j] = rank_one<L2S>(a, s_meta, sym[j], pos[j]);
+  for (uint64_t j = (uint64_t)blockIdx.x * kQT + threadIdx.x; j < q; j += (uint64_t)gridDim.x * kQT) {
+    const uint64_t jj = perm ? perm[j] : j;
+    out[jj] = rank_one<L2S>(a, s_meta, sym[jj], pos[jj]);
+  }
 }
 
 template <int L2S>
@@ -47,17 +54,51 @@ __global__ __launch_bounds__(kQT, 8) void k_select(QArgs a, const uint32_t* __re
                                                 uint64_t* __restrict__ out, const uint32_t* __restrict__ perm) {
   __shared__ LevelMeta s_meta[WT_MAX_LEVELS];
   load_meta(a, s_meta);
-  for (uint64_t j = (uint64_t)blockIdx.x * kQT + threadIdx.x; j < q; j += (uint64_t)gridDim.x * kQT)
-    out[perm ? perm[j] : j] = select_one<L2S>(a, s_meta, sym[j], kin[j]);
+  for (uint64_t j = (uint64_t)blockIdx.x * kQT + threadIdx.x; j < q; j += (uint64_t)gridDim.x * kQT) {
+    const uint64_t jj = perm ? perm[j] : j;
+    out[jj] = select_one<L2S>(a, s_meta, sym[jj], kin[jj]);
+  }
+}
+
+// ---------------------------------------------------------------- per-kernel timing
+
+namespace {
+struct QProfRec {
+  char name[32];
+  hipEvent_t a, b;
+};
+thread_local bool t_qprof_on = false;
+thread_local std::vector<QProfRec> t_qprof;
+}  // namespace
+
+void qprof_begin(const char* name, hipStream_t st) {
+  if (!t_qprof_on) return;
+  QProfRec r{};
+  std::strncpy(r.name, name, sizeof(r.name) - 1);
+  if (hipEventCreate(&r.a) != hipSuccess) return;
+  if (hipEventCreate(&r.b) != hipSuccess) {
+    (void)hipEventDestroy(r.a);
+    return;
+  }
+  (void)hipEventRecord(r.a, st);
+  t_qprof.push_back(r);
+}
+
+void qprof_end(hipStream_t st) {
+  if (!t_qprof_on || t_qprof.empty()) return;
+  (void)hipEventRecord(t_qprof.back().b, st);
 }
 
 // ---------------------------------------------------------------- locality binning
 
-constexpr uint32_t kSortBuckets = 1u << 16;
-
-__global__ void k_sort_zero(uint32_t* __restrict__ p, uint32_t n) {
-  for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) p[i] = 0u;
-}
+// Counting sort of the queries by bucket = key >> shift (kBins buckets), block-local: every block
+// counts its chunk in an LDS histogram (128 KB: one 1024-thread block per CU), a pass gives every
+// (bucket, block) its offset, and the scatter places the chunk with LDS cursors (all atomics in LDS).
+// The buckets are fine enough that the 64 queries of a wave fall within a few lines of every array.
+constexpr uint32_t kBins = 32768;
+constexpr uint32_t kBinT = 1024;                // threads of the counting and scatter blocks
+constexpr uint32_t kBinChunk = kBinT * 256;     // queries per block
+constexpr uint64_t kSortMinQ = 1ull << 16;
 
 __device__ __forceinline__ uint64_t sort_key(const QArgs& a, int kind, uint32_t c, uint64_t x) {
   if (kind != 2) return min(x, a.n);  // access, rank: the position
@@ -66,136 +107,129 @@ __device__ __forceinline__ uint64_t sort_key(const QArgs& a, int kind, uint32_t 
   return x > cnt ? a.n : lo + x - 1;  // select: rank of the occurrence in symbol order
 }
 
-// Lanes of a wave with the same bucket as their left neighbour form a run; the run's first lane acts
-// for it (one atomic per run: already-ordered batches do not serialise on a bucket counter).
-struct WaveRun {
-  uint32_t head;  // lane of the run's first lane
-  uint32_t len;   // run length (meaningful in the head lane)
-};
-
-__device__ __forceinline__ WaveRun wave_run(uint32_t b, bool in) {
-  const uint32_t lane = threadIdx.x & 63u;
-  const uint32_t prev = __shfl_up(b, 1, 64);
-  const bool prev_in = __shfl_up((uint32_t)in, 1, 64) != 0u;
-  const bool head = in && (lane == 0 || !prev_in || prev != b);
-  const uint64_t heads = __ballot(head);
-  const uint64_t act = __ballot(in);
-  WaveRun r;
-  const uint64_t upto = heads & (lane == 63 ? ~0ull : ((2ull << lane) - 1ull));
-  r.head = upto ? 63u - (uint32_t)__clzll(upto) : lane;
-  const uint64_t after = heads & ~((2ull << lane) - 1ull) & (lane == 63 ? 0ull : ~0ull);
-  const uint32_t next = after ? (uint32_t)__ffsll((unsigned long long)after) - 1u : 64u;
-  const uint32_t last_in = act ? 64u - (uint32_t)__clzll(act) : 0u;  // one past the last active lane
-  r.len = min(next, last_in) - lane;
-  return r;
+template <int KIND>
+__device__ __forceinline__ uint32_t sort_bin(const QArgs& a, const uint32_t* __restrict__ sym,
+                                             const uint64_t* __restrict__ arg, uint64_t j, uint32_t shift) {
+  return (uint32_t)min<uint64_t>(sort_key(a, KIND, KIND ? sym[j] : 0u, arg[j]) >> shift, kBins - 1);
 }
 
 template <int KIND>
-__global__ __launch_bounds__(kQT) void k_sort_count(QArgs a, const uint32_t* __restrict__ sym,
-                                                    const uint64_t* __restrict__ arg, uint64_t q, uint32_t shift,
-                                                    uint32_t* __restrict__ bucket, uint32_t* __restrict__ cnt) {
-  const uint64_t stride = (uint64_t)gridDim.x * kQT;
-  for (uint64_t j0 = (uint64_t)blockIdx.x * kQT; j0 < q; j0 += stride) {
-    const uint64_t j = j0 + threadIdx.x;
-    const bool in = j < q;
-    uint32_t b = 0;
-    if (in) {
-      b = (uint32_t)min<uint64_t>(sort_key(a, KIND, KIND ? sym[j] : 0u, arg[j]) >> shift, kSortBuckets - 1);
-      bucket[j] = b;
-    }
-    const WaveRun r = wave_run(b, in);
-    if (in && r.head == (threadIdx.x & 63u)) atomicAdd(&cnt[b], r.len);
+__global__ __launch_bounds__(kBinT) void k_bin_count(QArgs a, const uint32_t* __restrict__ sym,
+                                                   const uint64_t* __restrict__ arg, uint64_t q, uint32_t shift,
+                                                   uint32_t* __restrict__ bhist) {
+  __shared__ uint32_t h[kBins];
+  for (uint32_t b = threadIdx.x; b < kBins; b += kBinT) h[b] = 0;
+  __syncthreads();
+  const uint64_t c0 = (uint64_t)blockIdx.x * kBinChunk;
+  for (uint32_t i = threadIdx.x; i < kBinChunk; i += kBinT) {
+    const uint64_t j = c0 + i;
+    if (j < q) atomicAdd(&h[sort_bin<KIND>(a, sym, arg, j, shift)], 1u);
   }
+  __syncthreads();
+  for (uint32_t b = threadIdx.x; b < kBins; b += kBinT) bhist[(uint64_t)blockIdx.x * kBins + b] = h[b];
 }
 
-// In place exclusive scan of the bucket counts (one block).
-__global__ __launch_bounds__(1024) void k_sort_scan(uint32_t* __restrict__ cnt) {
+// Per bucket: exclusive prefix over the blocks (in place) and the bucket total.
+__global__ __launch_bounds__(kQT) void k_bin_offsets(uint32_t* __restrict__ bhist, uint32_t nblk,
+                                                     uint32_t* __restrict__ tot) {
+  const uint32_t b = blockIdx.x * kQT + threadIdx.x;
+  if (b >= kBins) return;
+  uint32_t run = 0;
+  for (uint32_t k = 0; k < nblk; ++k) {
+    const uint32_t v = bhist[(uint64_t)k * kBins + b];
+    bhist[(uint64_t)k * kBins + b] = run;
+    run += v;
+  }
+  tot[b] = run;
+}
+
+// In place exclusive scan of the bucket totals (one block of 1024 threads, kBins / 1024 per thread).
+__global__ __launch_bounds__(1024) void k_bin_scan(uint32_t* __restrict__ tot) {
   __shared__ uint32_t s_w[16];
-  uint32_t carry = 0;
-  for (uint32_t base = 0; base < kSortBuckets; base += 1024) {
-    const uint32_t i = base + threadIdx.x;
-    const uint32_t x = cnt[i];
-    const uint32_t lane = threadIdx.x & 63u, wv = threadIdx.x >> 6;
-    uint32_t inc = x;
+  constexpr uint32_t kPer = kBins / 1024;
+  uint32_t v[kPer], sum = 0;
 #pragma unroll
-    for (int off = 1; off < 64; off <<= 1) {
-      const uint32_t y = __shfl_up(inc, off, 64);
-      if ((int)lane >= off) inc += y;
-    }
-    if (lane == 63) s_w[wv] = inc;
-    __syncthreads();
-    uint32_t pre = 0, tot = 0;
-    for (uint32_t w = 0; w < 16; ++w) {
-      pre += w < wv ? s_w[w] : 0u;
-      tot += s_w[w];
-    }
-    cnt[i] = carry + pre + inc - x;
-    carry += tot;
-    __syncthreads();
+  for (uint32_t i = 0; i < kPer; ++i) {
+    v[i] = tot[threadIdx.x * kPer + i];
+    sum += v[i];
+  }
+  const uint32_t lane = threadIdx.x & 63u, wv = threadIdx.x >> 6;
+  uint32_t inc = sum;
+#pragma unroll
+  for (int off = 1; off < 64; off <<= 1) {
+    const uint32_t y = __shfl_up(inc, off, 64);
+    if ((int)lane >= off) inc += y;
+  }
+  if (lane == 63) s_w[wv] = inc;
+  __syncthreads();
+  uint32_t pre = 0;
+  for (uint32_t w = 0; w < wv; ++w) pre += s_w[w];
+  uint32_t run = pre + inc - sum;
+#pragma unroll
+  for (uint32_t i = 0; i < kPer; ++i) {
+    tot[threadIdx.x * kPer + i] = run;
+    run += v[i];
   }
 }
 
 template <int KIND>
-__global__ __launch_bounds__(kQT) void k_sort_scatter(uint64_t q, const uint32_t* __restrict__ bucket,
-                                                      const uint32_t* __restrict__ sym,
-                                                      const uint64_t* __restrict__ arg, uint32_t* __restrict__ cursor,
-                                                      uint32_t* __restrict__ perm, uint32_t* __restrict__ ssym,
-                                                      uint64_t* __restrict__ sarg) {
-  const uint64_t stride = (uint64_t)gridDim.x * kQT;
-  const uint32_t lane = threadIdx.x & 63u;
-  for (uint64_t j0 = (uint64_t)blockIdx.x * kQT; j0 < q; j0 += stride) {
-    const uint64_t j = j0 + threadIdx.x;
-    const bool in = j < q;
-    const uint32_t b = in ? bucket[j] : 0u;
-    const WaveRun r = wave_run(b, in);
-    uint32_t base = 0;
-    if (in && r.head == lane) base = atomicAdd(&cursor[b], r.len);
-    base = __shfl(base, (int)r.head, 64);
-    if (in) {
-      const uint32_t s = base + (lane - r.head);
-      perm[s] = (uint32_t)j;
-      if (KIND) ssym[s] = sym[j];
-      sarg[s] = arg[j];
-    }
+__global__ __launch_bounds__(kBinT) void k_bin_scatter(QArgs a, const uint32_t* __restrict__ sym,
+                                                     const uint64_t* __restrict__ arg, uint64_t q, uint32_t shift,
+                                                     const uint32_t* __restrict__ bhist,
+                                                     const uint32_t* __restrict__ base, uint32_t* __restrict__ perm) {
+  __shared__ uint32_t cur[kBins];
+  for (uint32_t b = threadIdx.x; b < kBins; b += kBinT) cur[b] = base[b] + bhist[(uint64_t)blockIdx.x * kBins + b];
+  __syncthreads();
+  const uint64_t c0 = (uint64_t)blockIdx.x * kBinChunk;
+  for (uint32_t i = threadIdx.x; i < kBinChunk; i += kBinT) {
+    const uint64_t j = c0 + i;
+    if (j >= q) continue;
+    const uint32_t s = atomicAdd(&cur[sort_bin<KIND>(a, sym, arg, j, shift)], 1u);
+    perm[s] = (uint32_t)j;
   }
 }
 
-constexpr uint64_t kSortMinQ = 1ull << 16;
-
-// Bins the batch on st (kind 0 access, 1 rank, 2 select); false when the batch is too small to pay.
+// Bins the batch on st (kind 0 access, 1 rank, 2 select); binned = false when the batch is too small
+// to pay (or too large for 32-bit slots).
 wt_status sort_batch(const wt_tree* t, const QArgs& a, int kind, const uint32_t* sym, const uint64_t* arg,
-                            uint64_t q, hipStream_t st, SortBufs& sb, bool& binned) {
+                     uint64_t q, hipStream_t st, SortBufs& sb, bool& binned) {
   binned = false;
   if (q < kSortMinQ || q >= (1ull << 32)) return WT_OK;
-  const size_t o_b = round_up(4ull * kSortBuckets, 256), o_p = o_b + round_up(4 * q, 256),
-               o_s = o_p + round_up(4 * q, 256), o_a = o_s + round_up(4 * q, 256), bytes = o_a + 8 * q;
+  const uint32_t nblk = (uint32_t)ceil_div(q, kBinChunk);
+  const size_t o_t = round_up((size_t)nblk * kBins * 4, 256), o_p = o_t + round_up(4 * kBins, 256),
+               bytes = o_p + 4 * q;
   sb.block = (char*)dev_alloc(bytes, st);
   if (!sb.block) return fail(WT_ERR_OOM, "query binning: scratch allocation of %zu bytes failed", bytes);
-  sb.cnt = (uint32_t*)sb.block;
-  sb.bucket = (uint32_t*)(sb.block + o_b);
+  uint32_t* bhist = (uint32_t*)sb.block;
+  uint32_t* tot = (uint32_t*)(sb.block + o_t);
+  sb.cnt = tot;
+  sb.bucket = nullptr;
   sb.perm = (uint32_t*)(sb.block + o_p);
-  sb.ssym = (uint32_t*)(sb.block + o_s);
-  sb.sarg = (uint64_t*)(sb.block + o_a);
+  sb.ssym = nullptr;
+  sb.sarg = nullptr;
   uint32_t bits = 0;
   while ((1ull << bits) < a.n + 1) ++bits;
-  const uint32_t shift = bits > 16 ? bits - 16 : 0;
-  const uint32_t grid = query_grid(q);
-  hipLaunchKernelGGL(k_sort_zero, dim3(kSortBuckets / 256), dim3(256), 0, st, sb.cnt, kSortBuckets);
-  if (kind == 0) {
-    hipLaunchKernelGGL(k_sort_count<0>, dim3(grid), dim3(kQT), 0, st, a, sym, arg, q, shift, sb.bucket, sb.cnt);
-  } else if (kind == 1) {
-    hipLaunchKernelGGL(k_sort_count<1>, dim3(grid), dim3(kQT), 0, st, a, sym, arg, q, shift, sb.bucket, sb.cnt);
-  } else {
-    hipLaunchKernelGGL(k_sort_count<2>, dim3(grid), dim3(kQT), 0, st, a, sym, arg, q, shift, sb.bucket, sb.cnt);
-  }
-  hipLaunchKernelGGL(k_sort_scan, dim3(1), dim3(1024), 0, st, sb.cnt);
-  if (kind == 0) {
-    hipLaunchKernelGGL(k_sort_scatter<0>, dim3(grid), dim3(kQT), 0, st, q, (const uint32_t*)sb.bucket, sym, arg,
-                       sb.cnt, sb.perm, sb.ssym, sb.sarg);
-  } else {
-    hipLaunchKernelGGL(k_sort_scatter<1>, dim3(grid), dim3(kQT), 0, st, q, (const uint32_t*)sb.bucket, sym, arg,
-                       sb.cnt, sb.perm, sb.ssym, sb.sarg);
-  }
+  const uint32_t shift = bits > 15 ? bits - 15 : 0;
+  qprof_begin("sort_count", st);
+  if (kind == 0) hipLaunchKernelGGL(k_bin_count<0>, dim3(nblk), dim3(kBinT), 0, st, a, sym, arg, q, shift, bhist);
+  else if (kind == 1) hipLaunchKernelGGL(k_bin_count<1>, dim3(nblk), dim3(kBinT), 0, st, a, sym, arg, q, shift, bhist);
+  else hipLaunchKernelGGL(k_bin_count<2>, dim3(nblk), dim3(kBinT), 0, st, a, sym, arg, q, shift, bhist);
+  qprof_end(st);
+  qprof_begin("sort_scan", st);
+  hipLaunchKernelGGL(k_bin_offsets, dim3(kBins / kQT), dim3(kQT), 0, st, bhist, nblk, tot);
+  hipLaunchKernelGGL(k_bin_scan, dim3(1), dim3(1024), 0, st, tot);
+  qprof_end(st);
+  qprof_begin("sort_scatter", st);
+  if (kind == 0)
+    hipLaunchKernelGGL(k_bin_scatter<0>, dim3(nblk), dim3(kBinT), 0, st, a, sym, arg, q, shift, (const uint32_t*)bhist,
+                       (const uint32_t*)tot, sb.perm);
+  else if (kind == 1)
+    hipLaunchKernelGGL(k_bin_scatter<1>, dim3(nblk), dim3(kBinT), 0, st, a, sym, arg, q, shift, (const uint32_t*)bhist,
+                       (const uint32_t*)tot, sb.perm);
+  else
+    hipLaunchKernelGGL(k_bin_scatter<2>, dim3(nblk), dim3(kBinT), 0, st, a, sym, arg, q, shift, (const uint32_t*)bhist,
+                       (const uint32_t*)tot, sb.perm);
+  qprof_end(st);
   WT_HIP(hipGetLastError());
   binned = true;
   (void)t;
@@ -219,12 +253,14 @@ extern "C" wt_status wt_access(const wt_tree* t, const uint64_t* d_pos, uint64_t
   bool binned;
   const wt_status rc = sort_batch(t, a, 0, nullptr, d_pos, q, st, sb, binned);
   if (rc != WT_OK) return rc;
+  qprof_begin("access", st);
   if (binned) {
-    WT_DISPATCH_L2(t->l2_bits, k_access, a, (const uint64_t*)sb.sarg, q, d_out, (const uint32_t*)sb.perm);
+    WT_DISPATCH_L2(t->l2_bits, k_access, a, d_pos, q, d_out, (const uint32_t*)sb.perm);
     dev_free(sb.block, st);
   } else {
     WT_DISPATCH_L2(t->l2_bits, k_access, a, d_pos, q, d_out, (const uint32_t*)nullptr);
   }
+  qprof_end(st);
   WT_HIP(hipGetLastError());
   return WT_OK;
 }
@@ -242,13 +278,14 @@ extern "C" wt_status wt_rank(const wt_tree* t, const uint32_t* d_sym, const uint
   bool binned;
   const wt_status rc = sort_batch(t, a, 1, d_sym, d_pos, q, st, sb, binned);
   if (rc != WT_OK) return rc;
+  qprof_begin("rank", st);
   if (binned) {
-    WT_DISPATCH_L2(t->l2_bits, k_rank, a, (const uint32_t*)sb.ssym, (const uint64_t*)sb.sarg, q, d_out,
-                   (const uint32_t*)sb.perm);
+    WT_DISPATCH_L2(t->l2_bits, k_rank, a, d_sym, d_pos, q, d_out, (const uint32_t*)sb.perm);
     dev_free(sb.block, st);
   } else {
     WT_DISPATCH_L2(t->l2_bits, k_rank, a, d_sym, d_pos, q, d_out, (const uint32_t*)nullptr);
   }
+  qprof_end(st);
   WT_HIP(hipGetLastError());
   return WT_OK;
 }
@@ -266,13 +303,43 @@ extern "C" wt_status wt_select(const wt_tree* t, const uint32_t* d_sym, const ui
   bool binned;
   const wt_status rc = sort_batch(t, a, 2, d_sym, d_k, q, st, sb, binned);
   if (rc != WT_OK) return rc;
+  qprof_begin("select", st);
   if (binned) {
-    WT_DISPATCH_L2(t->l2_bits, k_select, a, (const uint32_t*)sb.ssym, (const uint64_t*)sb.sarg, q, d_out,
-                   (const uint32_t*)sb.perm);
+    WT_DISPATCH_L2(t->l2_bits, k_select, a, d_sym, d_k, q, d_out, (const uint32_t*)sb.perm);
     dev_free(sb.block, st);
   } else {
     WT_DISPATCH_L2(t->l2_bits, k_select, a, d_sym, d_k, q, d_out, (const uint32_t*)nullptr);
   }
+  qprof_end(st);
   WT_HIP(hipGetLastError());
+  return WT_OK;
+}
+
+extern "C" wt_status wt_query_profiling(int on) {
+  clear_error();
+  t_qprof_on = on != 0;
+  return WT_OK;
+}
+
+extern "C" wt_status wt_query_profile(wt_prof_entry* out, uint32_t cap, uint32_t* count) {
+  clear_error();
+  if (count) *count = (uint32_t)t_qprof.size();
+  uint32_t i = 0;
+  wt_status rc = WT_OK;
+  for (QProfRec& r : t_qprof) {
+    float ms = 0.f;
+    if (hipEventSynchronize(r.b) != hipSuccess || hipEventElapsedTime(&ms, r.a, r.b) != hipSuccess) rc = WT_ERR_HIP;
+    if (out && i < cap) {
+      std::memset(&out[i], 0, sizeof(out[i]));
+      std::memcpy(out[i].kernel, r.name, sizeof(out[i].kernel));
+      out[i].level = -1;
+      out[i].ms = ms;
+    }
+    ++i;
+    (void)hipEventDestroy(r.a);
+    (void)hipEventDestroy(r.b);
+  }
+  t_qprof.clear();
+  if (rc != WT_OK) return fail(rc, "wt_query_profile: event query failed");
   return WT_OK;
 }

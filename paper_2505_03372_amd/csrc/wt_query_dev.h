@@ -236,9 +236,14 @@ inline QArgs make_args(const wt_tree* t) {
   return a;
 }
 
-// Locality binning of a query batch (wt_query.hip): on success with `binned`, the batch's symbols and
-// arguments in bucket order are in ssym / sarg and the query index of every slot in perm; the caller
-// frees `block` (stream-ordered) after its traversal.
+// Per-kernel timing of query calls (wt_query_profiling): HIP events recorded around every kernel of a
+// call on its stream, kept per thread until wt_query_profile reads them.
+void qprof_begin(const char* name, hipStream_t st);
+void qprof_end(hipStream_t st);
+
+// Locality binning of a query batch (wt_query.hip): on success with `binned`, perm holds the queries in
+// bucket order (slot j runs query perm[j]); the caller frees `block` (stream-ordered) after its
+// traversal.
 struct SortBufs {
   char* block = nullptr;
   uint32_t* cnt;
