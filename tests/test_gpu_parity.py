@@ -194,3 +194,41 @@ def test_full_size_large_alphabet():
     _level_properties(t, wl.S, wl.sigma)
     _sampled_check(t, wl.S, wl.sigma, None, wl.rank_c, wl.rank_i, wl.sel_c, wl.sel_k, stride=256)
     t.free()
+
+
+@pytest.mark.parametrize("order", ["random", "sorted", "reversed", "one_position"])
+def test_binned_batches_equal_unbinned(order):
+    """Batches of at least 2^16 queries are binned by where their answers lie before the traversal;
+    their answers must equal those of the same queries asked in batches below the binning size."""
+    import paper_2505_03372_amd as wt
+    n, sigma = 3_000_017, 300
+    S = make_seq("zipf", n, sigma, 2, 0x5151)
+    t = G.gpu_build(S, sigma)
+    q = (1 << 17) + 33
+    pos, rc, ri, sc, sk = G.random_queries(S, sigma, q, 0x77)
+    if order == "sorted":
+        o = np.argsort(pos, kind="stable"); pos = pos[o]; o = np.lexsort((ri, rc)); rc, ri = rc[o], ri[o]
+        o = np.lexsort((sk, sc)); sc, sk = sc[o], sk[o]
+    elif order == "reversed":
+        pos, rc, ri, sc, sk = pos[::-1].copy(), rc[::-1].copy(), ri[::-1].copy(), sc[::-1].copy(), sk[::-1].copy()
+    elif order == "one_position":
+        pos[:] = n // 2; ri[:] = n // 2; sc[:] = sc[0]; sk[:] = 1
+    # out-of-domain arguments mixed in
+    pos[::97] = n + 5; ri[::89] = n + 1; rc[::83] = sigma + 3; sk[::79] = 0; sc[::73] = sigma
+    G.log("binned vs unbinned, order %s, q=%d" % (order, q))
+    def pieces(fn, *arrs):
+        step = (1 << 16) - 1
+        return np.concatenate([G.host(fn(*[G.dev(np.ascontiguousarray(a[i:i + step])) for a in arrs]))
+                               for i in range(0, q, step)])
+    got = G.host(t.access(G.dev(pos)))
+    G._assert_eq("access binned", got, pieces(t.access, pos), pos)
+    got = G.host(t.rank(G.dev(rc), G.dev(ri)))
+    G._assert_eq("rank binned", got, pieces(t.rank, rc, ri), ri)
+    got = G.host(t.select(G.dev(sc), G.dev(sk)))
+    G._assert_eq("select binned", got, pieces(t.select, sc, sk), sk)
+    t.learn_select()
+    got = G.host(t.select_learned(G.dev(sc), G.dev(sk)))
+    G._assert_eq("learned select binned", got, pieces(t.select, sc, sk), sk)
+    idx = np.arange(0, q, 61)
+    G._assert_eq("select vs oracle", got[idx], oracle.select(S, sigma, sc[idx], sk[idx]), sk[idx])
+    t.free()
