@@ -74,12 +74,18 @@ __global__ void k_fill_u64(uint64_t* __restrict__ p, uint64_t n, uint64_t v) {
   fill_body(p, n, v, blockIdx.x, gridDim.x);
 }
 
-template <typename E, bool kSmall>
-__global__ __launch_bounds__(kBT) void k_hist(const E* __restrict__ sym, uint64_t n, uint32_t sigma, uint32_t L,
-                                              uint32_t pow2, uint32_t aligned, uint32_t nrep,
-                                              uint64_t* __restrict__ hist, uint64_t* __restrict__ tile_cnt0,
-                                              uint32_t* __restrict__ err) {
-  hist_body<E, kSmall>(sym, n, sigma, L, pow2, aligned, nrep, hist, tile_cnt0, err, blockIdx.x, gridDim.x);
+template <typename E, uint32_t kWords>
+__global__ __launch_bounds__(kHT) void k_hist_dense(const E* __restrict__ sym, uint64_t n, uint32_t sigma, uint32_t L,
+                                                    uint32_t aligned, uint64_t* __restrict__ hist,
+                                                    uint64_t* __restrict__ tile_cnt0, uint32_t* __restrict__ err) {
+  hist_dense_body<E, kWords>(sym, n, sigma, L, aligned, hist, tile_cnt0, err, blockIdx.x, gridDim.x);
+}
+
+template <typename E>
+__global__ __launch_bounds__(kBT) void k_hist_hash(const E* __restrict__ sym, uint64_t n, uint32_t sigma, uint32_t L,
+                                                   uint32_t aligned, uint64_t* __restrict__ hist,
+                                                   uint64_t* __restrict__ tile_cnt0, uint32_t* __restrict__ err) {
+  hist_hash_body<E>(sym, n, sigma, L, aligned, hist, tile_cnt0, err, blockIdx.x, gridDim.x);
 }
 
 __global__ void k_node_walk(uint32_t sigma, uint64_t nheap, const uint64_t* __restrict__ cum,
@@ -156,22 +162,24 @@ struct Scratch {
 };
 
 template <typename E>
-hipError_t launch_hist(const void* d_sym, uint64_t n, uint32_t sigma, uint32_t L, uint32_t pow2, uint64_t* hist,
-                       uint64_t* cnt0, uint32_t* err, hipStream_t st) {
+hipError_t launch_hist(const void* d_sym, uint64_t n, uint32_t sigma, uint32_t L, uint64_t* hist, uint64_t* cnt0,
+                       uint32_t* err, hipStream_t st) {
   using TL = Tile<E>;
   const uint64_t ntiles = ceil_div(n, TL::T);
   if (ntiles == 0) return hipSuccess;
-  const uint32_t grid = (uint32_t)std::min<uint64_t>(ntiles, 2048);
   const uint32_t aligned = ((uintptr_t)d_sym & 15u) == 0;
-  if (sigma <= 16384) {
-    const uint32_t nrep = std::max<uint32_t>(1u, std::min<uint32_t>(32u, 16383u / (sigma + 1)));
-    const size_t lds = (size_t)nrep * (sigma + 1) * sizeof(uint32_t);
-    hipLaunchKernelGGL((k_hist<E, true>), dim3(grid), dim3(kBT), lds, st, (const E*)d_sym, n, sigma, L, pow2,
-                       aligned, nrep, hist, cnt0, err);
+  if (sigma <= kHDenseMax) {
+    const uint32_t grid = (uint32_t)hist_dense_blocks(ntiles, hist_tiles_per_block(ntiles));
+    if (sigma + 1 <= kHSmallWords)
+      hipLaunchKernelGGL((k_hist_dense<E, kHSmallWords>), dim3(grid), dim3(kHT), 0, st, (const E*)d_sym, n, sigma,
+                         L, aligned, hist, cnt0, err);
+    else
+      hipLaunchKernelGGL((k_hist_dense<E, kHBigWords>), dim3(grid), dim3(kHT), 0, st, (const E*)d_sym, n, sigma, L,
+                         aligned, hist, cnt0, err);
   } else {
-    const size_t lds = 2ull * kHashSlots * sizeof(uint32_t);
-    hipLaunchKernelGGL((k_hist<E, false>), dim3(grid), dim3(kBT), lds, st, (const E*)d_sym, n, sigma, L, pow2,
-                       aligned, 1u, hist, cnt0, err);
+    const uint32_t grid = (uint32_t)std::min<uint64_t>(ntiles, 2048);
+    hipLaunchKernelGGL((k_hist_hash<E>), dim3(grid), dim3(kBT), 0, st, (const E*)d_sym, n, sigma, L, aligned, hist,
+                       cnt0, err);
   }
   return hipGetLastError();
 }
@@ -370,9 +378,9 @@ extern "C" wt_status wt_build(const void* d_sym, uint64_t n, uint32_t sym_bytes,
   WT_STEP(prof.end());
 
   WT_STEP(prof.begin("hist", -1));
-  if (sym_bytes == 1) WT_STEP(launch_hist<uint8_t>(d_sym, n, (uint32_t)sigma, L, pow2, hist, tcnt, err, st));
-  else if (sym_bytes == 2) WT_STEP(launch_hist<uint16_t>(d_sym, n, (uint32_t)sigma, L, pow2, hist, tcnt, err, st));
-  else WT_STEP(launch_hist<uint32_t>(d_sym, n, (uint32_t)sigma, L, pow2, hist, tcnt, err, st));
+  if (sym_bytes == 1) WT_STEP(launch_hist<uint8_t>(d_sym, n, (uint32_t)sigma, L, hist, tcnt, err, st));
+  else if (sym_bytes == 2) WT_STEP(launch_hist<uint16_t>(d_sym, n, (uint32_t)sigma, L, hist, tcnt, err, st));
+  else WT_STEP(launch_hist<uint32_t>(d_sym, n, (uint32_t)sigma, L, hist, tcnt, err, st));
   WT_STEP(prof.end());
 
   WT_STEP(prof.begin("cum_hist", -1));

@@ -217,6 +217,71 @@ __device__ __forceinline__ void load16(P base, uint32_t q0, uint32_t cnt, bool v
   }
 }
 
+// Element e of a 16-byte vector of E (e a compile-time constant after unrolling).
+template <typename E>
+__device__ __forceinline__ uint32_t vec_elem(const uint4& x, uint32_t e) {
+  constexpr uint32_t per = 4 / sizeof(E);  // elements per dword
+  const uint32_t d = e / per;
+  const uint32_t dw = d < 2 ? (d == 0 ? x.x : x.y) : (d == 2 ? x.z : x.w);
+  if constexpr (sizeof(E) == 4) return dw;
+  else return (dw >> ((e % per) * 8 * sizeof(E))) & ((1u << (8 * sizeof(E))) - 1u);
+}
+
+typedef unsigned short u16x2 __attribute__((ext_vector_type(2)));
+
+__device__ __forceinline__ uint32_t udot2_u16(uint32_t a, uint32_t w, uint32_t c) {
+  u16x2 x, y;
+  __builtin_memcpy(&x, &a, 4);
+  __builtin_memcpy(&y, &w, 4);
+  return __builtin_amdgcn_udot2(x, y, c, false);
+}
+
+// Bit `bsh` of every element of a 16-byte vector of E, as a mask (element e -> bit e). For bytes
+// and halfwords the selected bits, still at offset bsh inside their lanes, are weighted by powers of
+// two in a dot product, which sums to the mask shifted left by bsh.
+template <typename E>
+__device__ __forceinline__ uint32_t vec_bits(const uint4& x, uint32_t bsh) {
+  if constexpr (sizeof(E) == 1) {
+    const uint32_t M = 0x01010101u << bsh;
+    const uint32_t lo = __builtin_amdgcn_udot4(x.x & M, 0x08040201u,
+                                               __builtin_amdgcn_udot4(x.y & M, 0x80402010u, 0u, false), false);
+    const uint32_t hi = __builtin_amdgcn_udot4(x.z & M, 0x08040201u,
+                                               __builtin_amdgcn_udot4(x.w & M, 0x80402010u, 0u, false), false);
+    return ((hi << 8) | lo) >> bsh;
+  } else if constexpr (sizeof(E) == 2) {
+    const uint32_t M = 0x00010001u << bsh;
+    uint32_t d = udot2_u16(x.w & M, 0x00800040u, 0u);
+    d = udot2_u16(x.z & M, 0x00200010u, d);
+    d = udot2_u16(x.y & M, 0x00080004u, d);
+    d = udot2_u16(x.x & M, 0x00020001u, d);
+    return d >> bsh;
+  } else {
+    return ((x.x >> bsh) & 1u) | (((x.y >> bsh) & 1u) << 1) | (((x.z >> bsh) & 1u) << 2) | (((x.w >> bsh) & 1u) << 3);
+  }
+}
+
+// Number of elements of a 16-byte vector of E whose bit `bsh` is set.
+template <typename E>
+__device__ __forceinline__ uint32_t vec_count_bit(const uint4& x, uint32_t bsh) {
+  if constexpr (sizeof(E) == 1) {
+    const uint32_t M = 0x01010101u << bsh;
+    uint32_t d = __builtin_amdgcn_udot4(x.x & M, 0x01010101u, 0u, false);
+    d = __builtin_amdgcn_udot4(x.y & M, 0x01010101u, d, false);
+    d = __builtin_amdgcn_udot4(x.z & M, 0x01010101u, d, false);
+    d = __builtin_amdgcn_udot4(x.w & M, 0x01010101u, d, false);
+    return d >> bsh;
+  } else if constexpr (sizeof(E) == 2) {
+    const uint32_t M = 0x00010001u << bsh;
+    uint32_t d = udot2_u16(x.x & M, 0x00010001u, 0u);
+    d = udot2_u16(x.y & M, 0x00010001u, d);
+    d = udot2_u16(x.z & M, 0x00010001u, d);
+    d = udot2_u16(x.w & M, 0x00010001u, d);
+    return d >> bsh;
+  } else {
+    return ((x.x >> bsh) & 1u) + ((x.y >> bsh) & 1u) + ((x.z >> bsh) & 1u) + ((x.w >> bsh) & 1u);
+  }
+}
+
 // ---------------------------------------------------------------- histogram (Section 5.1.1)
 
 // Ones per tile are accumulated per chunk of kChunkTiles tiles as well, so a level's tile prefix
@@ -224,25 +289,43 @@ __device__ __forceinline__ void load16(P base, uint32_t q0, uint32_t cnt, bool v
 constexpr int kChunkShift = 10;
 constexpr uint64_t kChunkTiles = 1ull << kChunkShift;
 
-// Persistent grid over whole tiles. Small alphabets count into LDS replicas (one per group of
-// threads, assigned round-robin; replicas are padded by one counter so equal symbols of different
-// replicas fall into different banks); large alphabets use an LDS cache of claimed symbols with
-// global atomics for the rest. Also records, per level-0 tile, the number of ones (code bit L-1).
-template <typename E, bool kSmall, typename PS, typename PH, typename PE>
-__device__ __forceinline__ void hist_body(PS sym, uint64_t n, uint32_t sigma, uint32_t L, uint32_t pow2,
-                                          uint32_t aligned, uint32_t nrep, PH hist, PH tile_cnt0, PE err,
-                                          uint64_t bid, uint64_t nblk) {
+// Histogram blocks: kHT threads, a contiguous range of tiles each (kHG tiles in flight, one per
+// group of kBT threads). Alphabets up to kHDenseMax are counted densely in LDS: kHSmallWords
+// counters (replicated for small alphabets, one replica per group of lanes) or, in the large-LDS
+// variant, windows of kHBigWords symbols (two passes over the block's tiles for 2^16 symbols).
+// Each block adds its nonzero counts to the global histogram once, so a block's range is made long
+// (hundreds of thousands of symbols) to amortise that flush.
+constexpr int kHT = 1024;
+constexpr int kHG = kHT / kBT;
+constexpr uint32_t kHSmallWords = 8192;   // 32 KB
+constexpr uint32_t kHBigWords = 32768;    // 128 KB
+constexpr uint32_t kHDenseMax = 65536;
+constexpr uint32_t kHMaxRep = 32;
+
+// Tiles per dense-histogram block: at least kHMinTiles, about kHTargetBlocks blocks for a long
+// sequence (several blocks per compute unit).
+constexpr uint64_t kHMinTiles = 8;
+constexpr uint64_t kHTargetBlocks = 1024;
+__host__ __device__ inline uint64_t hist_tiles_per_block(uint64_t total_tiles) {
+  const uint64_t t = (total_tiles + kHTargetBlocks - 1) / kHTargetBlocks;
+  return t > kHMinTiles ? t : kHMinTiles;
+}
+__host__ __device__ inline uint64_t hist_dense_blocks(uint64_t ntiles, uint64_t tpb) {
+  return (ntiles + tpb - 1) / tpb;
+}
+
+// Alphabets above kHDenseMax: an LDS cache of claimed symbols (open addressing, no eviction) with
+// global atomics for the symbols that find no slot; kBT threads, blocks strided over the tiles.
+template <typename E, typename PS, typename PH, typename PE>
+__device__ __forceinline__ void hist_hash_body(PS sym, uint64_t n, uint32_t sigma, uint32_t L, uint32_t aligned,
+                                               PH hist, PH tile_cnt0, PE err, uint64_t bid, uint64_t nblk) {
   using TL = Tile<E>;
-  extern __shared__ uint32_t s_h[];
+  __shared__ uint32_t s_keys[kHashSlots];
+  __shared__ uint32_t s_cnts[kHashSlots];
   __shared__ uint32_t s_w[kBT / 64];
   const uint32_t tid = threadIdx.x;
-  const uint32_t stride = sigma + 1;
-  const uint32_t hsize = kSmall ? nrep * stride : 2u * kHashSlots;
-  for (uint32_t i = tid; i < hsize; i += kBT) s_h[i] = 0;
+  for (uint32_t i = tid; i < (uint32_t)kHashSlots; i += kBT) s_keys[i] = 0, s_cnts[i] = 0;
   __syncthreads();
-  uint32_t* my_h = s_h + (kSmall ? (tid % nrep) * stride : 0u);
-  uint32_t* s_keys = s_h;
-  uint32_t* s_cnts = s_h + kHashSlots;
   const uint64_t ntiles = (n + TL::T - 1) >> TL::TSHIFT;
   uint32_t bad = 0;
   for (uint64_t t = bid; t < ntiles; t += nblk) {
@@ -260,40 +343,111 @@ __device__ __forceinline__ void hist_body(PS sym, uint64_t n, uint32_t sigma, ui
         const bool in = q0 + e < cnt;
         if (in && s >= sigma) bad = 1;
         if (in && s < sigma) {
-          if (L) {
-            uint32_t len;
-            const uint32_t code = encode_sym(s, sigma, L, pow2, &len);
-            ones += (code >> (L - 1)) & 1u;
-          }
-          if (kSmall) {
-            atomicAdd(&my_h[s], 1u);
-          } else {
-            const uint32_t h = (s * 2654435761u) >> (32 - 12);
-            const uint32_t old = atomicCAS(&s_keys[h], 0u, s + 1u);
-            if (old == 0u || old == s + 1u) atomicAdd(&s_cnts[h], 1u);
-            else atomic_add_u64(hist + s, 1ull);
-          }
+          // the level-0 bit of a symbol's code is the symbol's own bit L - 1 (reduced codes keep
+          // the first 2^(L-1) symbols in the left subtree)
+          ones += (s >> (L - 1)) & 1u;
+          const uint32_t h = (s * 2654435761u) >> (32 - 12);
+          const uint32_t old = atomicCAS(&s_keys[h], 0u, s + 1u);
+          if (old == 0u || old == s + 1u) atomicAdd(&s_cnts[h], 1u);
+          else atomic_add_u64(hist + s, 1ull);
         }
       }
     }
     uint32_t tot;
     block_excl_scan_u32(ones, s_w, tot);
-    if (tid == 0) tile_cnt0[t] = tot;
+    if (tid == 0 && tot) atomic_add_u64(tile_cnt0 + t, tot);
   }
   if (bad) (void)__hip_atomic_fetch_or(err, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   __syncthreads();
-  if (kSmall) {
-    for (uint32_t s = tid; s < sigma; s += kBT) {
-      uint64_t c = 0;
-      for (uint32_t r = 0; r < nrep; ++r) c += s_h[r * stride + s];
-      if (c) atomic_add_u64(hist + s, c);
-    }
-  } else {
-    for (uint32_t h = tid; h < (uint32_t)kHashSlots; h += kBT) {
-      const uint32_t key = s_keys[h];
-      if (key) atomic_add_u64(hist + (key - 1u), s_cnts[h]);
-    }
+  for (uint32_t h = tid; h < (uint32_t)kHashSlots; h += kBT) {
+    const uint32_t key = s_keys[h];
+    if (key) atomic_add_u64(hist + (key - 1u), s_cnts[h]);
   }
+}
+
+// Alphabets up to kHDenseMax (sigma + 1 <= kWords for the small variant): block bid of nblk takes
+// tiles [ntiles * bid / nblk, ntiles * (bid + 1) / nblk). Also adds, per level-0 tile, its ones
+// (code bit L - 1) to tile_cnt0 (cleared beforehand), one atomic per wave and tile.
+template <typename E, uint32_t kWords, typename PS, typename PH, typename PE>
+__device__ __forceinline__ void hist_dense_body(PS sym, uint64_t n, uint32_t sigma, uint32_t L, uint32_t aligned,
+                                                PH hist, PH tile_cnt0, PE err, uint64_t bid, uint64_t nblk) {
+  using TL = Tile<E>;
+  constexpr int EV = TL::EV, NCH = TL::NCH;
+  __shared__ uint32_t s_h[kWords];
+  const uint32_t tid = threadIdx.x, grp = tid / kBT, gt = tid % kBT, lane = tid & 63u;
+  const uint32_t win = min(sigma, kWords);
+  const uint32_t nrep = sigma + 1 <= kWords ? max(1u, min(kHMaxRep, kWords / (sigma + 1))) : 1u;
+  const uint32_t stride = nrep > 1 ? sigma + 1 : win;
+  uint32_t* my_h = s_h + (lane % nrep) * stride;
+  const uint64_t ntiles = (n + TL::T - 1) >> TL::TSHIFT;
+  const uint64_t tb = ntiles * bid / nblk, te = ntiles * (bid + 1) / nblk;
+  const uint64_t nit = (te - tb + kHG - 1) / kHG;
+  const uint32_t lsh = L ? L - 1 : 0;
+  uint32_t bad = 0;
+  for (uint32_t w0 = 0; w0 < sigma; w0 += win) {
+    const uint32_t wn = min(win, sigma - w0);
+    for (uint32_t i = tid; i < nrep * stride; i += kHT) s_h[i] = 0;
+    __syncthreads();
+    const bool first = w0 == 0;
+    for (uint64_t it = 0; it < nit; ++it) {
+      const uint64_t t = tb + it * kHG + grp;
+      if (t < te) {  // uniform over the group's waves
+        const uint64_t t0 = t << TL::TSHIFT;
+        const uint32_t cnt = (uint32_t)min<uint64_t>(TL::T, n - t0);
+        uint32_t ones = 0;
+        auto count_vec = [&](const uint4& x, uint32_t q0) {
+#pragma unroll
+          for (int e = 0; e < EV; ++e) {
+            const uint32_t s = vec_elem<E>(x, e);
+            if (q0 + e < cnt) {
+              const uint32_t r = s - w0;
+              if (r < wn) atomicAdd(&my_h[r], 1u);
+              if (first) {
+                bad |= s >= sigma ? 1u : 0u;
+                ones += s < sigma ? (s >> lsh) & 1u : 0u;
+              }
+            }
+          }
+        };
+        if (aligned && cnt == (uint32_t)TL::T) {
+          // whole aligned tile: every vector in flight at once, kept packed (4 registers each)
+          u32x4 vx[NCH];
+#pragma unroll
+          for (int k = 0; k < NCH; ++k) vx[k] = *pcast<const u32x4>(sym + t0 + (uint32_t)(k * kBT + gt) * EV);
+#pragma unroll
+          for (int k = 0; k < NCH; ++k) {
+            uint4 x;
+            __builtin_memcpy(&x, &vx[k], 16);
+            count_vec(x, (uint32_t)(k * kBT + gt) * EV);
+          }
+        } else {
+          // ragged last tile or unaligned sequence: one vector at a time
+#pragma unroll 1
+          for (int k = 0; k < NCH; ++k) {
+            const uint32_t q0 = (uint32_t)(k * kBT + gt) * EV;
+            E v[EV];
+            load16<E>(sym + t0, q0, cnt, aligned && (q0 + EV <= cnt), v);
+            uint4 x;
+            __builtin_memcpy(&x, v, 16);
+            count_vec(x, q0);
+          }
+        }
+        if (first && L) {
+#pragma unroll
+          for (int off = 32; off > 0; off >>= 1) ones += __shfl_xor(ones, off, 64);
+          if (lane == 0 && ones) atomic_add_u64(tile_cnt0 + t, (uint64_t)ones);
+        }
+      }
+    }
+    __syncthreads();
+    for (uint32_t r = tid; r < wn; r += kHT) {
+      uint32_t c = 0;
+      for (uint32_t k = 0; k < nrep; ++k) c += s_h[k * stride + r];
+      if (c) atomic_add_u64(hist + w0 + r, (uint64_t)c);
+    }
+    __syncthreads();
+  }
+  if (bad) (void)__hip_atomic_fetch_or(err, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
 // ---------------------------------------------------------------- node tables
@@ -343,26 +497,46 @@ __device__ __forceinline__ void node_walk_body(uint32_t sigma, uint64_t nheap, c
 __device__ __forceinline__ void node_final_body(uint64_t nheap, const uint64_t* __restrict__ zs,
                                                 NodeB* __restrict__ ntb, NodeQ* __restrict__ ntq,
                                                 LevelMeta* __restrict__ meta, uint64_t h) {
-  if (h >= nheap) return;
-  const uint32_t l = 63u - (uint32_t)__clzll(h + 1);
-  const uint64_t base = (1ull << l) - 1;
-  NodeB b = ntb[h];
-  NodeQ q;
-  if (b.start == kNoNode) {
-    q.start = kNoNode;
-    q.r0 = kNoNode;
-    ntq[h] = q;
-    return;
+  // every lane of the wave takes part in the level-size reduction at the end
+  const bool valid = h < nheap;
+  const uint32_t l = valid ? 63u - (uint32_t)__clzll(h + 1) : 0xFFFFFFFFu;
+  uint64_t endv = 0;
+  if (valid) {
+    const uint64_t base = (1ull << l) - 1;
+    NodeB b = ntb[h];
+    NodeQ q;
+    if (b.start == kNoNode) {
+      q.start = kNoNode;
+      q.r0 = kNoNode;
+      ntq[h] = q;
+    } else {
+      const uint64_t r0 = zs[h] - zs[base];
+      const uint64_t mid = b.off0;
+      q.start = b.start;
+      q.r0 = r0;
+      ntq[h] = q;
+      b.off0 = b.start - r0;
+      b.off1 = mid - b.start + r0;
+      ntb[h] = b;
+      endv = b.end;
+    }
   }
-  const uint64_t r0 = zs[h] - zs[base];
-  const uint64_t mid = b.off0;
-  q.start = b.start;
-  q.r0 = r0;
-  ntq[h] = q;
-  b.off0 = b.start - r0;
-  b.off1 = mid - b.start + r0;
-  ntb[h] = b;
-  atomicMax((unsigned long long*)&meta[l].n, (unsigned long long)b.end);
+  // level size = the largest node end of the level: one atomic per (wave, level) instead of per node
+  const uint32_t lane = threadIdx.x & 63u;
+  uint64_t pend = __ballot(valid);
+  while (pend) {
+    const int leader = __ffsll((unsigned long long)pend) - 1;
+    const uint32_t ll = __shfl(l, leader, 64);
+    const bool mine = valid && l == ll;
+    uint64_t v = mine ? endv : 0ull;
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+      const uint64_t o = __shfl_xor(v, off, 64);
+      v = o > v ? o : v;
+    }
+    if (lane == (uint32_t)leader && v) atomicMax((unsigned long long*)&meta[ll].n, (unsigned long long)v);
+    pend &= ~__ballot(mine);
+  }
 }
 
 // ---------------------------------------------------------------- per-level tile prefix
@@ -556,16 +730,6 @@ __device__ __forceinline__ void enter_node(const NodeB nb, uint32_t q, uint64_t 
   }
 }
 
-// Element e of a 16-byte vector of E (e a compile-time constant after unrolling).
-template <typename E>
-__device__ __forceinline__ uint32_t vec_elem(const uint4& x, uint32_t e) {
-  constexpr uint32_t per = 4 / sizeof(E);  // elements per dword
-  const uint32_t d = e / per;
-  const uint32_t dw = d < 2 ? (d == 0 ? x.x : x.y) : (d == 2 ? x.z : x.w);
-  if constexpr (sizeof(E) == 4) return dw;
-  else return (dw >> ((e % per) * 8 * sizeof(E))) & ((1u << (8 * sizeof(E))) - 1u);
-}
-
 // Element e of the 128-bit value (lo, hi) for a run-time e, by shifting (no indexed access, which
 // would put the vector in scratch memory).
 template <typename E>
@@ -593,7 +757,7 @@ struct TreeB {
   const void* sym;
   uint64_t n;
   uint32_t sigma, L, pow2, aligned;
-  uint32_t l2shift, sshift, nrep, tshift;
+  uint32_t l2shift, sshift, tshift, pad0;
   LevelMeta* meta;
   uint64_t* cum;
   NodeQ* nodes;
@@ -651,8 +815,15 @@ __device__ __forceinline__ LevelArgs forest_level_args(const TreeB& b, uint32_t 
 }
 
 // The body stays in the kernel (as a device function it needs far more registers).
+// Waves per SIMD the level pass is compiled for (a register budget): six where the body fits in
+// 80 registers without spilling, else five.
 template <typename E, bool kForest>
-__global__ __launch_bounds__(kBT) void k_level(LevelArgs a_one, ForestGrid fg) {
+constexpr int level_waves() {
+  return (sizeof(E) == 1 && !kForest) || (sizeof(E) == 2 && kForest) ? 6 : 5;
+}
+
+template <typename E, bool kForest>
+__global__ __launch_bounds__(kBT, (level_waves<E, kForest>())) void k_level(LevelArgs a_one, ForestGrid fg) {
   LevelArgsG a;
   uint64_t t;
   if constexpr (kForest) {
@@ -710,13 +881,13 @@ __global__ __launch_bounds__(kBT) void k_level(LevelArgs a_one, ForestGrid fg) {
     }
     __builtin_memcpy(&vx[k], v, 16);
   }
+  uint32_t vmask[NCH];  // bit bsh of every element of vector k (0 beyond the tile)
 #pragma unroll
   for (int k = 0; k < NCH; ++k) {
     const uint32_t q0 = (uint32_t)(k * kBT + tid) * EV;
-    uint32_t mask = 0;
-#pragma unroll
-    for (int e = 0; e < EV; ++e)
-      if (q0 + e < cnt) mask |= ((vec_elem<E>(vx[k], e) >> bsh) & 1u) << e;
+    const uint32_t valid = q0 >= cnt ? 0u : (q0 + EV <= cnt ? (uint32_t)((1ull << EV) - 1) : (1u << (cnt - q0)) - 1u);
+    const uint32_t mask = vec_bits<E>(vx[k], bsh) & valid;
+    vmask[k] = mask;
     uint64_t word = (uint64_t)mask << ((tid % G) * EV);
 #pragma unroll
     for (int off = 1; off < G; off <<= 1) word |= __shfl_xor(word, off, 64);
@@ -798,28 +969,31 @@ __global__ __launch_bounds__(kBT) void k_level(LevelArgs a_one, ForestGrid fg) {
   const uint32_t nbsh = L - 2 - l;
   const uint64_t pmask = (1ull << l) - 1ull;
   if (single) {
-    // zeros fill slots [0, Z), ones [Z, cnt)
+    // zeros fill slots [0, Z), ones [Z, cnt); each lane walks its vectors with running slots
     const uint32_t Z = cnt - tile_ones;
-#pragma unroll 1
+#pragma unroll
     for (int k = 0; k < NCH; ++k) {
       const uint32_t q0 = (uint32_t)(k * kBT + tid) * EV;
       if (q0 < cnt) {
-        // vector k without indexed access (an indexed register array would go to scratch)
-        uint4 x = vx[0];
+        const uint32_t r1 = r1loc(s_words, s_wpre, q0);
+        uint32_t p1 = Z + r1, p0 = q0 - r1;
+        const uint32_t m = vmask[k];
+        if (q0 + EV <= cnt) {
 #pragma unroll
-        for (int kk = 1; kk < NCH; ++kk)
-          if (k == kk) x = vx[kk];
-        uint32_t r1 = r1loc(s_words, s_wpre, q0);
-        uint32_t r0 = q0 - r1;
-        const uint32_t nv = min((uint32_t)EV, cnt - q0);
-#pragma unroll
-        for (int e = 0; e < EV; ++e) {
-          if ((uint32_t)e < nv) {
-            const uint32_t code = vec_elem<E>(x, e);
-            const uint32_t b = (code >> bsh) & 1u;
-            s_stage[b ? Z + r1 : r0] = (E)code;
-            r1 += b;
-            r0 += 1u - b;
+          for (int e = 0; e < EV; ++e) {
+            const uint32_t b = (m >> e) & 1u;
+            s_stage[b ? p1 : p0] = (E)vec_elem<E>(vx[k], e);
+            p1 += b;
+            p0 += b ^ 1u;
+          }
+        } else {
+          // ragged end of the last tile
+          const uint64_t lo = ((uint64_t)vx[k].y << 32) | vx[k].x, hi = ((uint64_t)vx[k].w << 32) | vx[k].z;
+          for (uint32_t e = 0; e < cnt - q0; ++e) {
+            const uint32_t b = (m >> e) & 1u;
+            s_stage[b ? p1 : p0] = (E)elem128<E>(lo, hi, e);
+            p1 += b;
+            p0 += b ^ 1u;
           }
         }
       }
@@ -832,21 +1006,25 @@ __global__ __launch_bounds__(kBT) void k_level(LevelArgs a_one, ForestGrid fg) {
     const uint32_t* st32 = reinterpret_cast<const uint32_t*>(s_stage);
     const uint32_t len0 = d0 < n_next ? (uint32_t)min<uint64_t>(Z, n_next - d0) : 0u;
     const uint32_t len1 = d1 < n_next ? (uint32_t)min<uint64_t>(cnt - Z, n_next - d1) : 0u;
-    const uint32_t C0 = len0 ? (uint32_t)(((d0 + len0 - 1) * sizeof(E) >> 4) - ((d0 * sizeof(E)) >> 4) + 1) : 0u;
-    const uint32_t C1 = len1 ? (uint32_t)(((d1 + len1 - 1) * sizeof(E) >> 4) - ((d1 * sizeof(E)) >> 4) + 1) : 0u;
-    constexpr uint32_t kTileB = (uint32_t)T * (uint32_t)sizeof(E);  // bytes of a destination tile
-    uint32_t cnt4[4] = {0u, 0u, 0u, 0u};                          // (run, first / second tile)
+    // Offsets relative to each run's first 16-byte destination chunk (32-bit): the run covers bytes
+    // [a_r, e_r) from that chunk's base g_r; tb_r is the base's offset inside its destination tile.
+    constexpr uint32_t w = (uint32_t)sizeof(E);
+    constexpr uint32_t kTileB = (uint32_t)T * w;  // bytes of a destination tile
+    const uint64_t g0 = (d0 * w) & ~15ull, g1 = (d1 * w) & ~15ull;
+    const uint32_t a0 = (uint32_t)(d0 * w) & 15u, a1 = (uint32_t)(d1 * w) & 15u;
+    const uint32_t e0 = a0 + len0 * w, e1 = a1 + len1 * w;
+    const uint32_t C0 = len0 ? (e0 + 15u) >> 4 : 0u, C1 = len1 ? (e1 + 15u) >> 4 : 0u;
+    const uint32_t tb0 = (uint32_t)g0 & (kTileB - 1u), tb1 = (uint32_t)g1 & (kTileB - 1u);
+    uint32_t acc0 = 0, acc1 = 0;  // next-level ones of run 0 / run 1: first tile low 16 bits, second high
     for (uint32_t c = tid; c < C0 + C1; c += kBT) {
       const bool bb = c >= C0;
-      const uint64_t d = bb ? d1 : d0;
-      const uint32_t len = bb ? len1 : len0;
-      const uint32_t slot0 = bb ? Z : 0u;
-      const uint64_t db = d * sizeof(E), de = (d + len) * sizeof(E);
-      const uint64_t cb = ((db >> 4) + (bb ? c - C0 : c)) << 4;
-      const uint64_t blo = max(db, cb), bhi = min(de, cb + 16);
-      const uint32_t src = slot0 * (uint32_t)sizeof(E) + (uint32_t)(blo - db);
+      const uint32_t rb = (bb ? c - C0 : c) << 4;  // chunk start, bytes from g_r
+      const uint32_t ar = bb ? a1 : a0, er = bb ? e1 : e0;
+      const uint32_t blo = max(rb, ar), bhi = min(rb + 16u, er);
+      const uint32_t src = (bb ? Z * w : 0u) + blo - ar;  // LDS byte of blo
+      WT_GLOBAL char* cp = outb + (bb ? g1 : g0) + rb;
       uint32_t nb = 0;
-      if (blo == cb && bhi == cb + 16) {
+      if (blo == rb && bhi == rb + 16u) {
         const uint32_t dw = src >> 2, sh = src & 3u;
         const uint32_t x0 = st32[dw], x1 = st32[dw + 1], x2 = st32[dw + 2], x3 = st32[dw + 3], x4 = st32[dw + 4];
         uint4 y;
@@ -854,30 +1032,32 @@ __global__ __launch_bounds__(kBT) void k_level(LevelArgs a_one, ForestGrid fg) {
         y.y = __builtin_amdgcn_alignbyte(x2, x1, sh);
         y.z = __builtin_amdgcn_alignbyte(x3, x2, sh);
         y.w = __builtin_amdgcn_alignbyte(x4, x3, sh);
-        st16(outb + cb, y);
-        // next-level bits of the 16/w elements: one bit per element, popcount per dword
-        constexpr uint32_t kLow = sizeof(E) == 1 ? 0x01010101u : (sizeof(E) == 2 ? 0x00010001u : 1u);
-        nb = __popc((y.x >> nbsh) & kLow) + __popc((y.y >> nbsh) & kLow) + __popc((y.z >> nbsh) & kLow) +
-             __popc((y.w >> nbsh) & kLow);
+        st16(cp, y);
+        nb = vec_count_bit<E>(y, nbsh);  // next-level ones of the 16 / w elements
       } else {
-        const uint32_t s0 = src / (uint32_t)sizeof(E);
-        WT_GLOBAL E* oe = pcast<E>(outb);
-        const uint64_t e0 = blo / sizeof(E), e1 = bhi / sizeof(E);
-        for (uint64_t e = e0; e < e1; ++e) {
-          const E v = s_stage[s0 + (uint32_t)(e - e0)];
-          oe[e] = v;
+        // run edge: element stores
+        WT_GLOBAL E* oe = pcast<E>(cp);
+        for (uint32_t x = blo; x < bhi; x += w) {
+          const E v = s_stage[(src + x - blo) / w];
+          oe[(x - rb) / w] = v;
           nb += ((uint32_t)v >> nbsh) & 1u;
         }
       }
-      const uint32_t sub = (uint32_t)(cb / kTileB - db / kTileB);  // 0 or 1
-      cnt4[(bb ? 2 : 0) + sub] += nb;
+      // a run of at most T elements touches at most two destination tiles
+      const uint32_t add = nb << (((bb ? tb1 : tb0) + rb) >= kTileB ? 16 : 0);
+      acc0 += bb ? 0u : add;
+      acc1 += bb ? add : 0u;
     }
 #pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      uint32_t v = cnt4[r];
+    for (int off = 32; off > 0; off >>= 1) {
+      acc0 += __shfl_xor(acc0, off, 64);
+      acc1 += __shfl_xor(acc1, off, 64);
+    }
+    if (lane == 0) {
+      const uint32_t v[4] = {acc0 & 0xFFFFu, acc0 >> 16, acc1 & 0xFFFFu, acc1 >> 16};
 #pragma unroll
-      for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
-      if (lane == 0 && v) atomicAdd(&s_nc[r], v);
+      for (int r = 0; r < 4; ++r)
+        if (v[r]) atomicAdd(&s_nc[r], v[r]);
     }
     __syncthreads();
     if (tid < 4) {
@@ -904,16 +1084,23 @@ __global__ __launch_bounds__(kBT) void k_level(LevelArgs a_one, ForestGrid fg) {
         if (Nf == Nl) {
           // the whole vector lies in one node
           if (Nf != curN) enter_node(ld_node(a.ntb + Nf), q0, t0, cnt, G0, G1, s_words, s_wpre, s_seg, &s_nseg, sa, zs, R1a), curN = Nf;
-          const uint32_t b0 = R1a, b1 = sa + zs - R1a;  // slot = b0 + rank0 or b1 + rank1 (tile-local)
+          // slot = R1a + rank0 or sa + zs - R1a + rank1 (tile-local ranks), as running slots
+          uint32_t p1 = sa + zs - R1a + r1, p0 = R1a + q0 - r1;
+          const uint32_t m = vmask[k];
+          if (nv == (uint32_t)EV) {
 #pragma unroll
-          for (int e = 0; e < EV; ++e) {
-            if ((uint32_t)e < nv) {
-              const uint32_t code = vec_elem<E>(vx[k], e);
-              const uint32_t b = (code >> bsh) & 1u;
-              const uint32_t q = q0 + e;
-              const uint32_t slot = b ? b1 + r1 : b0 + (q - r1);
-              s_stage[min(slot, (uint32_t)T - 1u)] = (E)code;
-              r1 += b;
+            for (int e = 0; e < EV; ++e) {
+              const uint32_t b = (m >> e) & 1u;
+              s_stage[min(b ? p1 : p0, (uint32_t)T - 1u)] = (E)vec_elem<E>(vx[k], e);
+              p1 += b;
+              p0 += b ^ 1u;
+            }
+          } else {
+            for (uint32_t e = 0; e < nv; ++e) {
+              const uint32_t b = (m >> e) & 1u;
+              s_stage[min(b ? p1 : p0, (uint32_t)T - 1u)] = (E)elem128<E>(lo, hi, e);
+              p1 += b;
+              p0 += b ^ 1u;
             }
           }
         } else {
@@ -991,8 +1178,7 @@ __global__ __launch_bounds__(kBT) void k_level(LevelArgs a_one, ForestGrid fg) {
           y.z = __builtin_amdgcn_alignbyte(x3, x2, sh);
           y.w = __builtin_amdgcn_alignbyte(x4, x3, sh);
           st16(outb + cb, y);
-#pragma unroll
-          for (int e = 0; e < EV; ++e) nb1 += (vec_elem<E>(y, e) >> nbsh) & 1u;
+          nb1 = vec_count_bit<E>(y, nbsh);
         } else {
           const uint32_t s0 = src / (uint32_t)sizeof(E);
           WT_GLOBAL E* oe = pcast<E>(outb);

@@ -57,13 +57,20 @@ __global__ __launch_bounds__(kBT) void kf_init(ForestGrid fg) {
   }
 }
 
-template <typename E, bool kSmall>
-__global__ __launch_bounds__(kBT) void kf_hist(ForestGrid fg) {
+template <typename E, uint32_t kWords>
+__global__ __launch_bounds__(kHT) void kf_hist_dense(ForestGrid fg) {
   const FB f = forest_block(fg);
   const TreeB& b = fg.tb[f.j];
-  hist_body<E, kSmall>((const WT_GLOBAL E*)b.sym, b.n, b.sigma, b.L, b.pow2, b.aligned, b.nrep,
-                       (WT_GLOBAL uint64_t*)b.hist, (WT_GLOBAL uint64_t*)b.tcnt, (WT_GLOBAL uint32_t*)b.err, f.bid,
-                       f.nblk);
+  hist_dense_body<E, kWords>((const WT_GLOBAL E*)b.sym, b.n, b.sigma, b.L, b.aligned, (WT_GLOBAL uint64_t*)b.hist,
+                             (WT_GLOBAL uint64_t*)b.tcnt, (WT_GLOBAL uint32_t*)b.err, f.bid, f.nblk);
+}
+
+template <typename E>
+__global__ __launch_bounds__(kBT) void kf_hist_hash(ForestGrid fg) {
+  const FB f = forest_block(fg);
+  const TreeB& b = fg.tb[f.j];
+  hist_hash_body<E>((const WT_GLOBAL E*)b.sym, b.n, b.sigma, b.L, b.aligned, (WT_GLOBAL uint64_t*)b.hist,
+                    (WT_GLOBAL uint64_t*)b.tcnt, (WT_GLOBAL uint32_t*)b.err, f.bid, f.nblk);
 }
 
 // which = 0: cumulative histogram (sigma + 1 entries); 1: node-table prefix (nheap + 1 entries).
@@ -551,9 +558,10 @@ extern "C" wt_status wt_build_forest(const wt_seq_desc* h_descs, uint32_t count,
 
   // per-tree state (build order) and block maps
   std::vector<TreeB> tb(count);
-  MapBuilder m_init, m_hist_small, m_hist_big, m_scan_c, m_scan_z, m_node, m_tile, m_level;
-  uint32_t n_small = 0, n_big = 0;
-  size_t lds_small = 16;
+  MapBuilder m_init, m_hist_small, m_hist_big, m_hist_hash, m_scan_c, m_scan_z, m_node, m_tile, m_level;
+  uint64_t all_tiles = 0;
+  for (uint32_t j = 0; j < count; ++j) all_tiles += sh[j].n ? ceil_div(sh[j].n, T) : 0;
+  const uint64_t hist_tpb = hist_tiles_per_block(all_tiles);
   std::vector<uint32_t> active(Lmax + 1, 0);  // trees with more than l levels
   for (uint32_t s = 0; s < count; ++s) {
     const uint32_t j = order[s];
@@ -599,24 +607,24 @@ extern "C" wt_status wt_build_forest(const wt_seq_desc* h_descs, uint32_t count,
     b.nchunks = o.nchunks;
     b.cstride = o.cstride;
     b.nheap = P.nheap;
-    const bool small = b.sigma <= 16384;
-    b.nrep = small ? std::max<uint32_t>(1u, std::min<uint32_t>(32u, 16383u / (b.sigma + 1))) : 1u;
-    if (small) lds_small = std::max<size_t>(lds_small, (size_t)b.nrep * (b.sigma + 1) * sizeof(uint32_t));
     for (uint32_t l = 0; l < b.L; ++l) active[l] = s + 1;
 
     const uint64_t ntiles_n = b.n ? ceil_div(b.n, T) : 0;
     m_init.add(s, std::min<uint64_t>(64, ceil_div(o.clear_n, (uint64_t)kBT * 16)));
-    // histogram: about eight tiles per block, so the per-block flush of the counters is amortised
-    m_hist_small.add(s, small ? ceil_div(ntiles_n, 8) : 0);
-    m_hist_big.add(s, small ? 0 : ceil_div(ntiles_n, 8));
-    if (ntiles_n) (small ? n_small : n_big) += 1;
+    // histogram: dense (small or large LDS) in long tile ranges, or the hashed count for alphabets
+    // above 2^16 (eight tiles per block, strided)
+    const int hk = b.sigma + 1 <= kHSmallWords ? 0 : (b.sigma <= kHDenseMax ? 1 : 2);
+    const uint64_t hdense = hist_dense_blocks(ntiles_n, hist_tpb);
+    m_hist_small.add(s, hk == 0 ? hdense : 0);
+    m_hist_big.add(s, hk == 1 ? hdense : 0);
+    m_hist_hash.add(s, hk == 2 ? ceil_div(ntiles_n, 8) : 0);
     m_scan_c.add(s, ceil_div(o.hist_n, kScanChunk));
     m_scan_z.add(s, b.L ? ceil_div(P.nheap + 1, kScanChunk) : 0);
     m_node.add(s, b.L ? ceil_div(P.nheap, kBT) : 0);
     m_tile.add(s, b.L ? o.nchunks + 1 : 0);
     m_level.add(s, b.L ? ntiles_n : 0);
   }
-  for (MapBuilder* m : {&m_init, &m_hist_small, &m_hist_big, &m_scan_c, &m_scan_z, &m_node, &m_tile, &m_level})
+  for (MapBuilder* m : {&m_init, &m_hist_small, &m_hist_big, &m_hist_hash, &m_scan_c, &m_scan_z, &m_node, &m_tile, &m_level})
     m->close();
 
   // one upload: tree states, build order, every map
@@ -634,6 +642,7 @@ extern "C" wt_status wt_build_forest(const wt_seq_desc* h_descs, uint32_t count,
   };
   auto put_map = [&](const MapBuilder& m) { return MapOff{put(m.bmap.data(), m.bmap.size() * 4), put(m.boff.data(), m.boff.size() * 4)}; };
   const MapOff u_init = put_map(m_init), u_hs = put_map(m_hist_small), u_hb = put_map(m_hist_big),
+               u_hh = put_map(m_hist_hash),
                u_sc = put_map(m_scan_c), u_sz = put_map(m_scan_z), u_node = put_map(m_node),
                u_tile = put_map(m_tile), u_level = put_map(m_level);
   const size_t u_out = round_up(hbuf.size(), 256);
@@ -667,16 +676,15 @@ extern "C" wt_status wt_build_forest(const wt_seq_desc* h_descs, uint32_t count,
     ++nk;
   };
   launch(kf_init, m_init.bmap.size(), kBT, 0, grid_of(u_init));
-  if (sym_bytes == 1) {
-    launch(kf_hist<uint8_t, true>, m_hist_small.bmap.size(), kBT, lds_small, grid_of(u_hs));
-    launch(kf_hist<uint8_t, false>, m_hist_big.bmap.size(), kBT, 2ull * kHashSlots * 4, grid_of(u_hb));
-  } else if (sym_bytes == 2) {
-    launch(kf_hist<uint16_t, true>, m_hist_small.bmap.size(), kBT, lds_small, grid_of(u_hs));
-    launch(kf_hist<uint16_t, false>, m_hist_big.bmap.size(), kBT, 2ull * kHashSlots * 4, grid_of(u_hb));
-  } else {
-    launch(kf_hist<uint32_t, true>, m_hist_small.bmap.size(), kBT, lds_small, grid_of(u_hs));
-    launch(kf_hist<uint32_t, false>, m_hist_big.bmap.size(), kBT, 2ull * kHashSlots * 4, grid_of(u_hb));
-  }
+  auto launch_hist = [&](auto e) {
+    using E = decltype(e);
+    launch(kf_hist_dense<E, kHSmallWords>, m_hist_small.bmap.size(), kHT, 0, grid_of(u_hs));
+    launch(kf_hist_dense<E, kHBigWords>, m_hist_big.bmap.size(), kHT, 0, grid_of(u_hb));
+    launch(kf_hist_hash<E>, m_hist_hash.bmap.size(), kBT, 0, grid_of(u_hh));
+  };
+  if (sym_bytes == 1) launch_hist(uint8_t{});
+  else if (sym_bytes == 2) launch_hist(uint16_t{});
+  else launch_hist(uint32_t{});
   launch(kf_scan_reduce, m_scan_c.bmap.size(), kBT, 0, grid_of(u_sc), 0u);
   launch(kf_scan_partials, count, 1024, 0, d_tb, 0u);
   launch(kf_scan_down, m_scan_c.bmap.size(), kBT, 0, grid_of(u_sc), 0u);
