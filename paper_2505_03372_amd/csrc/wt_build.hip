@@ -209,7 +209,8 @@ TreePlan plan_tree(uint64_t n, uint32_t w, uint64_t sigma, uint32_t L, uint32_t 
   const uint64_t cap_bits = round_up(round_up(std::max<uint64_t>(n, 1), p.tile) + 2048, 1024);
   p.words_per_level = cap_bits / 64;
   p.l1_per_level = round_up(ceil_div(n, kL1Bits) + 1, 16);
-  p.l2_per_level = round_up(ceil_div(n, l2_bits) + 1, 64);
+  // + one group of slack: a select reads up to 40 entries from the vector of its first candidate
+  p.l2_per_level = round_up(ceil_div(n, l2_bits) + 1 + 64, 64);
   p.smp_per_level = round_up(n / srate + 1, 16);
   p.nheap = L ? ((1ull << L) - 1) : 0;
   size_t off = 0;

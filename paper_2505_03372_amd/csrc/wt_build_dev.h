@@ -690,6 +690,24 @@ __device__ __forceinline__ void count_next(uint64_t cls, uint64_t dt, uint32_t n
   }
 }
 
+// Select samples of one wave's words: every lane with c set holds a word w whose r-th set bit
+// (r in [1, 64]) is sampled, at position pos0 + that bit, stored to *dst. The wave resolves those
+// lanes one at a time: lane i tests bit i of the word, and a ballot gives the bit.
+template <typename P>
+__device__ __forceinline__ void wave_sample(bool c, uint64_t w, uint32_t r, uint64_t pos0, P dst, uint32_t lane) {
+  uint64_t pend = __ballot(c);
+  while (pend) {
+    const int ld = __ffsll((unsigned long long)pend) - 1;
+    const uint64_t wl = ((uint64_t)(uint32_t)__builtin_amdgcn_readlane((int)(w >> 32), ld) << 32) |
+                        (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)w, ld);
+    const uint32_t rl = (uint32_t)__builtin_amdgcn_readlane((int)r, ld);
+    const bool hit = ((wl >> lane) & 1ull) && (uint32_t)__popcll(wl & ((1ull << lane) - 1ull)) + 1u == rl;
+    const uint64_t hm = __ballot(hit);
+    if (lane == (uint32_t)ld) *dst = pos0 + (uint64_t)(__ffsll((unsigned long long)hm) - 1);
+    pend &= pend - 1;
+  }
+}
+
 // Tile-local rank1 at x in [0, T]: ones in the words before x / 64 plus the low bits of that word.
 __device__ __forceinline__ uint32_t r1loc(const uint64_t* __restrict__ sw, const uint32_t* __restrict__ sp,
                                           uint32_t x) {
@@ -924,31 +942,34 @@ __global__ __launch_bounds__(kBT, (level_waves<E, kForest>())) void k_level(Leve
 
   // 3. bits and directory
   const uint64_t G0 = t0 - G1;  // zeros of the level before the tile
-  if (tid < (uint32_t)W) {
+  if (tid < (uint32_t)W) {  // whole waves (W is a multiple of 64)
     const uint64_t word = s_words[tid];
     const uint64_t gw = ((uint64_t)t * W) + tid;
     a.bits[m.bits + gw] = word;
     const uint32_t q = tid * 64u;
+    // a word holds at most one sampled one and one sampled zero (s >= 512 > 64)
+    bool c1 = false, c0 = false;
+    uint32_t r1 = 0, r0 = 0;
+    uint64_t i1 = 0, i0 = 0, zw = 0;
     if (q < cnt) {
       const uint64_t ones_before = G1 + s_wpre[tid];
       const uint32_t l2w_shift = a.l2shift - 6;
       if ((gw & ((1ull << l2w_shift) - 1)) == 0) a.L2[m.l2 + (gw >> l2w_shift)] = (uint16_t)(ones_before - l1val);
       const uint32_t sh = a.sshift;
-      const uint32_t pc = popc64(word);
-      const uint64_t k1 = (ones_before + pc) >> sh;
-      if (k1 > (ones_before >> sh)) {
-        const uint32_t r = (uint32_t)((k1 << sh) - ones_before);
-        a.smp[m.smp + k1 - 1] = t0 + q + select_in_word(word, r);
-      }
+      const uint64_t k1 = (ones_before + popc64(word)) >> sh;
+      c1 = k1 > (ones_before >> sh);
+      r1 = (uint32_t)((k1 << sh) - ones_before);
+      i1 = m.smp + k1 - 1;
       const uint32_t vb = min(64u, cnt - q);
-      const uint64_t zw = ~word & (vb == 64u ? ~0ull : ((1ull << vb) - 1ull));
+      zw = ~word & (vb == 64u ? ~0ull : ((1ull << vb) - 1ull));
       const uint64_t zeros_before = t0 + q - ones_before;
       const uint64_t k0 = (zeros_before + popc64(zw)) >> sh;
-      if (k0 > (zeros_before >> sh)) {
-        const uint32_t r = (uint32_t)((k0 << sh) - zeros_before);
-        a.smp[m.smp + m.smp_cap - k0] = t0 + q + select_in_word(zw, r);
-      }
+      c0 = k0 > (zeros_before >> sh);
+      r0 = (uint32_t)((k0 << sh) - zeros_before);
+      i0 = m.smp + m.smp_cap - k0;
     }
+    wave_sample(c1, word, r1, t0 + q, a.smp + i1, lane);
+    wave_sample(c0, zw, r0, t0 + q, a.smp + i0, lane);
   }
   if (tid == 0) {
     if ((t0 & (kL1Bits - 1)) == 0) a.L1[m.l1 + (t0 >> kL1Shift)] = G1;

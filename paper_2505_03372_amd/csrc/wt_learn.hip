@@ -253,6 +253,7 @@ __global__ void k_learn_compile(const LearnModel* __restrict__ models, LearnQ* _
   Q.eps = M.eps < 0 ? -1 : 0;
   Q.side = M.side;
   Q.cntf = (float)M.cnt;
+  Q.lenf = (float)M.len;
   Q.pad0 = 0;
   Q.pad1 = 0;
   double t[kH];
@@ -385,7 +386,7 @@ __global__ __launch_bounds__(kQT, 8) void k_select_learned(QArgs a, const LearnQ
   constexpr int GS = learn_gs<L2S>();
   __shared__ LevelMeta s_meta[WT_MAX_LEVELS];
   load_meta(a, s_meta);
-  for (uint64_t j = (uint64_t)blockIdx.x * kQT + threadIdx.x; j < q; j += (uint64_t)gridDim.x * kQT) {
+  for (uint64_t j = xcd_block() * kQT + threadIdx.x; j < q; j += (uint64_t)gridDim.x * kQT) {
     const uint64_t jj = perm ? perm[j] : j;
     out[jj] = select_learned_one<L2S, GS>(a, s_meta, qm, sym[jj], kin[jj]);
   }

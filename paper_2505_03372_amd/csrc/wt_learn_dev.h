@@ -28,7 +28,8 @@ struct LearnQ {
   uint32_t side;   // b
   float cntf;      // bits equal to b inside the node, as float (the input scale)
   uint32_t npieces;
-  uint64_t pad0;
+  float lenf;      // len as float (the output scale)
+  uint32_t pad0;
   float knot[kH];
   float2 piece[kH + 1];  // (slope, intercept) of v(u) on [knot[s-1], knot[s])
   uint64_t pad1;
@@ -58,7 +59,7 @@ __device__ __forceinline__ uint64_t count_before(const TreeDev& d, const LevelMe
 }
 
 // Position of the j-th (1-based, node-local) side-b bit of the node of model Q at level m.
-// GS: log2 of the L2 counts read at once around the prediction (one aligned group).
+// GS: log2 of the L2 counts read at once around the prediction.
 template <int L2S, int GS>
 __device__ __forceinline__ uint64_t select_learned_at(const TreeDev& d, const LevelMeta& m, const LearnQ& Q,
                                                       uint64_t j, uint32_t sshift) {
@@ -67,42 +68,62 @@ __device__ __forceinline__ uint64_t select_learned_at(const TreeDev& d, const Le
   if (Q.eps < 0) return select_at<L2S, false>(d, m, b, T, sshift);
   const float v = pla_eval(Q, ((float)j - 0.5f) / Q.cntf);
   const uint64_t start = Q.start, end = Q.start + Q.len;
-  const uint64_t guess = min(start + (uint64_t)((double)v * (double)Q.len), end - 1);
+  const uint64_t guess = min(start + (uint64_t)(v * Q.lenf), end - 1);  // FP32: a few positions off at most
   const uint64_t Blo = start >> L2S, Bhi = (end - 1) >> L2S;
   const uint64_t B0 = guess >> L2S;
   const uint64_t budget = (uint64_t)Q.eps;
   // largest B in [Blo, Bhi] with count_before(B) < T; count_before(Blo) <= rank0 < T always.
-  // First look at the aligned group of L2 counts holding B0 (inside one L1 block): the counts are
-  // non-decreasing, so the blocks below the target form a prefix of it.
+  // First look at the group of GN L2 counts centred on B0 (whole 16-byte vectors, inside B0's L1
+  // block): the counts are non-decreasing, so the blocks below the target form a prefix of it.
   constexpr uint32_t GN = 1u << GS;
-  const uint64_t gbase = B0 & ~(uint64_t)(GN - 1);
+  constexpr uint64_t kPer = kL1Bits >> L2S;
+  static_assert(GN <= kPer, "group inside an L1 block");
+  const uint64_t jb0 = B0 & ~(kPer - 1);
+  const uint64_t gbase = min(max(jb0, (B0 > GN / 2 ? B0 - GN / 2 : 0ull) & ~7ull), jb0 + kPer - GN);
   const uint64_t glo = max(gbase, Blo), ghi = min(gbase + GN - 1, Bhi);
   const uint64_t l1v = d.L1[m.l1 + ((gbase << L2S) >> kL1Shift)];
   const uint4* gp = reinterpret_cast<const uint4*>(d.L2 + m.l2 + gbase);
-  uint4 g[GN / 8];
-#pragma unroll
-  for (uint32_t i = 0; i < GN / 8; ++i) g[i] = gp[i];
-  // below(e) <=> count_before(gbase + e) < T, in 32-bit arithmetic with saturation
+  // below(e) <=> count_before(gbase + e) < T, in 32-bit arithmetic with saturation:
+  // y_e = l2 (b = 1) or e 2^L2S - l2 (b = 0), below <=> y_e < D
   int64_t D;
-  if (b) D = (int64_t)min<uint64_t>(T - min(T, l1v), 1ull << 20);  // l2 < D
+  if (b) D = (int64_t)min<uint64_t>(T - min(T, l1v), 1ull << 20);
   else {
     const uint64_t base0 = (gbase << L2S) - l1v;  // zeros before the group
     D = T > base0 ? (int64_t)min<uint64_t>(T - base0, 1ull << 20) : -(int64_t)min<uint64_t>(base0 - T, 1ull << 20);
   }
   const int32_t Di = (int32_t)D;
-  const uint32_t elo = (uint32_t)(glo - gbase), ehi = (uint32_t)(ghi - gbase);
+  const int32_t sgn = b ? 1 : -1, step = b ? 0 : (1 << L2S);
+  // Over the group (inside one L1 block) the counts never decrease: blocks before the node are below
+  // the target (count_before(Blo) <= rank0 < T) and blocks past the node are not, so the blocks
+  // below form a prefix of the group; only padding past the level's end is masked.
+  const uint64_t nL2 = (m.n + (1ull << L2S) - 1) >> L2S;
+  const uint32_t ehi = gbase + GN <= nL2 ? GN - 1 : (uint32_t)(ghi - gbase);
+  int32_t off = 0;
   uint32_t below = 0;
+  int32_t ylast = 0;  // y of the last block below the target
+#pragma unroll 2
+  for (uint32_t v = 0; v < GN / 8; ++v) {
+    const uint4 x = gp[v];
 #pragma unroll
-  for (uint32_t e = 0; e < GN; ++e) {
-    const uint32_t dw = (e & 7) < 4 ? ((e & 7) < 2 ? g[e >> 3].x : g[e >> 3].y) : ((e & 7) < 6 ? g[e >> 3].z : g[e >> 3].w);
-    const int32_t l2v = (int32_t)((dw >> ((e & 1) * 16)) & 0xFFFFu);
-    const bool lt = b ? (l2v < Di) : ((int32_t)(e << L2S) - l2v < Di);
-    below += (lt && e >= elo && e <= ehi) ? 1u : 0u;
+    for (uint32_t e = 0; e < 8; ++e) {
+      const uint32_t dw = e < 4 ? (e < 2 ? x.x : x.y) : (e < 6 ? x.z : x.w);
+      const int32_t l2v = (int32_t)((dw >> ((e & 1) * 16)) & 0xFFFFu);
+      const int32_t y = off + sgn * l2v;
+      const bool lt = v * 8 + e <= ehi && y < Di;
+      below += lt ? 1u : 0u;
+      ylast = lt ? y : ylast;
+      off += step;
+    }
   }
-  uint64_t lo, hi;  // invariant: count_before(lo) < T, and hi = Bhi + 1 or count_before(hi) >= T
+  // blocks gbase .. gbase + below - 1 are below the target; count from glo as the search expects
+  below = below > (uint32_t)(glo - gbase) ? below - (uint32_t)(glo - gbase) : 0u;
+  uint64_t lo = 0, hi = 0;  // invariant: count_before(lo) < T, and hi = Bhi + 1 or count_before(hi) >= T
+  bool over = false;        // the prediction missed by more than the error budget
+  uint32_t kk = 0;           // set when the group resolves the block: T - count_before(lo) = D - y(lo)
   if (below > 0 && (glo + below - 1 < ghi || ghi == Bhi)) {
     lo = glo + below - 1;
     hi = lo + 1;
+    kk = (uint32_t)(Di - ylast);
   } else if (below == 0) {
     // target left of the group (glo > Blo here): gallop left from glo
     hi = glo;
@@ -119,7 +140,10 @@ __device__ __forceinline__ uint64_t select_learned_at(const TreeDev& d, const Le
       }
       hi = nb;
       step <<= 1;
-      if (glo - nb > budget) return select_at<L2S, false>(d, m, b, T, sshift);
+      if (glo - nb > budget) {
+        over = true;
+        break;
+      }
     }
   } else {
     // every block of the group is below the target: gallop right from ghi
@@ -137,27 +161,20 @@ __device__ __forceinline__ uint64_t select_learned_at(const TreeDev& d, const Le
       }
       lo = nb;
       step <<= 1;
-      if (nb - ghi > budget) return select_at<L2S, false>(d, m, b, T, sshift);
+      if (nb - ghi > budget) {
+        over = true;
+        break;
+      }
     }
   }
+  if (over) return select_at<L2S, false>(d, m, b, T, sshift);
   while (hi - lo > 1) {
     const uint64_t mid = lo + ((hi - lo) >> 1);
     if (count_before<L2S>(d, m, b, mid << L2S) < T) lo = mid;
     else hi = mid;
   }
-  // word scan inside the block, then the in-word select
-  constexpr int L2W = (1 << L2S) / 64;
-  uint32_t kk = (uint32_t)(T - count_before<L2S>(d, m, b, lo << L2S));
-  const uint64_t* wp = d.bits + m.bits + (lo << (L2S - 6));
-#pragma unroll
-  for (int w = 0; w < L2W; ++w) {
-    uint64_t word = wp[w];
-    if (!b) word = ~word;
-    const uint32_t pc = popc64(word);
-    if (kk <= pc) return (lo << L2S) + 64u * (uint32_t)w + select_in_word(word, kk);
-    kk -= pc;
-  }
-  return select_at<L2S, false>(d, m, b, T, sshift);  // not reached for valid targets
+  if (!kk) kk = (uint32_t)(T - count_before<L2S>(d, m, b, lo << L2S));
+  return (lo << L2S) + block_select<L2S>(d.bits + m.bits + (lo << (L2S - 6)), b, kk);
 }
 
 // select_c(k) through the learned index (same results and sentinels as select_one).
@@ -173,15 +190,28 @@ __device__ __forceinline__ uint64_t select_learned_one(const QArgs& a, const Lev
   uint64_t r = k;
   for (int l = (int)len - 1; l >= 0; --l) {
     const uint64_t pc = (uint64_t)(code >> (a.L - 1 - l));  // child prefix at level l + 1
-    const LearnQ& Q = qm[(1ull << (l + 1)) - 2 + pc];
-    const uint64_t at = select_learned_at<L2S, GS>(a.d, meta[l], Q, r, a.sshift);
-    r = at - Q.start + 1;
+    const uint64_t mi = (1ull << (l + 1)) - 2 + pc;
+    // In a binned batch the lanes of a wave mostly share the model: then it is read through a
+    // wave-uniform address (scalar loads) instead of once per lane.
+    const uint64_t m0 = ((uint64_t)(uint32_t)__builtin_amdgcn_readfirstlane((int)(mi >> 32)) << 32) |
+                        (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)mi);
+    uint64_t at, start;
+    if (__ballot(mi != m0) == 0) {
+      const LearnQ& Q = qm[m0];
+      at = select_learned_at<L2S, GS>(a.d, meta[l], Q, r, a.sshift);
+      start = Q.start;
+    } else {
+      const LearnQ& Q = qm[mi];
+      at = select_learned_at<L2S, GS>(a.d, meta[l], Q, r, a.sshift);
+      start = Q.start;
+    }
+    r = at - start + 1;
   }
   return r - 1;
 }
 
-// Aligned group of L2 counts the learned correction reads at once: 2^WT_LEARN_GS entries (one fewer
-// power for 2048-bit blocks).
+// Group of L2 counts the learned correction reads at once around the prediction: 2^WT_LEARN_GS
+// entries (one fewer power for 2048-bit blocks).
 #ifndef WT_LEARN_GS
 #define WT_LEARN_GS 5
 #endif

@@ -30,7 +30,7 @@ __global__ __launch_bounds__(kQT) void k_access(QArgs a, const uint64_t* __restr
                                                 uint32_t* __restrict__ out, const uint32_t* __restrict__ perm) {
   __shared__ LevelMeta s_meta[WT_MAX_LEVELS];
   load_meta(a, s_meta);
-  for (uint64_t j = (uint64_t)blockIdx.x * kQT + threadIdx.x; j < q; j += (uint64_t)gridDim.x * kQT) {
+  for (uint64_t j = xcd_block() * kQT + threadIdx.x; j < q; j += (uint64_t)gridDim.x * kQT) {
     const uint64_t jj = perm ? perm[j] : j;
     out[jj] = access_one<L2S>(a, s_meta, pos[jj]);
   }
@@ -42,7 +42,7 @@ __global__ __launch_bounds__(kQT) void k_rank(QArgs a, const uint32_t* __restric
                                               uint64_t* __restrict__ out, const uint32_t* __restrict__ perm) {
   __shared__ LevelMeta s_meta[WT_MAX_LEVELS];
   load_meta(a, s_meta);
-  for (uint64_t j = (uint64_t)blockIdx.x * kQT + threadIdx.x; j < q; j += (uint64_t)gridDim.x * kQT) {
+  for (uint64_t j = xcd_block() * kQT + threadIdx.x; j < q; j += (uint64_t)gridDim.x * kQT) {
     const uint64_t jj = perm ? perm[j] : j;
     out[jj] = rank_one<L2S>(a, s_meta, sym[jj], pos[jj]);
   }
@@ -54,7 +54,7 @@ __global__ __launch_bounds__(kQT, 8) void k_select(QArgs a, const uint32_t* __re
                                                 uint64_t* __restrict__ out, const uint32_t* __restrict__ perm) {
   __shared__ LevelMeta s_meta[WT_MAX_LEVELS];
   load_meta(a, s_meta);
-  for (uint64_t j = (uint64_t)blockIdx.x * kQT + threadIdx.x; j < q; j += (uint64_t)gridDim.x * kQT) {
+  for (uint64_t j = xcd_block() * kQT + threadIdx.x; j < q; j += (uint64_t)gridDim.x * kQT) {
     const uint64_t jj = perm ? perm[j] : j;
     out[jj] = select_one<L2S>(a, s_meta, sym[jj], kin[jj]);
   }

@@ -48,6 +48,37 @@ __device__ __forceinline__ uint64_t rank1_at(const TreeDev& d, const LevelMeta& 
 }
 
 // Position of the k-th bit equal to b (1 <= k <= count of b) of the level (Algorithm 2).
+// Offset of the kk-th bit equal to b (kk >= 1, present) inside the L2 block whose words start at
+// wp: the word holding it is found by popcounts over 16-byte loads, then one in-word select after
+// the scan (lanes leave the scan at different words; the select runs once for the whole wave).
+template <int L2S>
+__device__ __forceinline__ uint32_t block_select(const uint64_t* __restrict__ wp, uint32_t b, uint32_t kk) {
+  constexpr int L2W = (1 << L2S) / 64;
+  const uint4* vp = reinterpret_cast<const uint4*>(wp);  // the block is 64-byte aligned
+  uint64_t sel = 0;
+  uint32_t wsel = 0;
+#pragma unroll 4
+  for (int v = 0; v < L2W / 2; ++v) {
+    const uint4 x = vp[v];
+    const uint64_t pair[2] = {((uint64_t)x.y << 32) | x.x, ((uint64_t)x.w << 32) | x.z};
+    bool done = false;
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const uint64_t word = b ? pair[h] : ~pair[h];
+      const uint32_t pc = popc64(word);
+      sel = word;
+      wsel = (uint32_t)(2 * v + h);
+      if (kk <= pc) {
+        done = true;
+        break;
+      }
+      kk -= pc;
+    }
+    if (done) break;
+  }
+  return 64u * wsel + select_in_word(sel, kk);
+}
+
 // kLine: resolve the L2 search on the first line of L2 counts in registers before the binary search
 // (faster; the form without it needs fewer registers).
 template <int L2S, bool kLine = true>
@@ -84,34 +115,47 @@ __device__ __forceinline__ uint64_t select_at(const TreeDev& d, const LevelMeta&
   const uint64_t jb = blk * kPer;
   uint64_t jlo = max(jb, lo_pos >> L2S);
   uint64_t jhi = min(min(jb + kPer, nL2) - 1, hi_pos >> L2S);
+  bool resolved = false;  // k already counted from the start of block jlo
   if constexpr (kLine) {
-    constexpr uint32_t GN = L2S <= 10 ? 64u : 32u;
-    const uint64_t gbase = jlo & ~(uint64_t)(GN - 1);
-    const uint64_t ghi = min(gbase + GN - 1, jhi);
+    // GN entries read at once (whole 16-byte vectors) from the vector holding jlo, moved down when
+    // needed so the group stays inside the L1 block. Over an L1 block the count of b before each L2
+    // block, y_e, never decreases, and it is below k at jlo (so at every entry from the group start
+    // to jlo) and not below k past jhi (past the next sample): the blocks below k are a prefix of
+    // the group, counted in registers. Only the level's last group can hold entries past its end,
+    // which are masked; a prefix that fills the group continues with the binary search.
+    constexpr uint32_t GN = L2S <= 9 ? 32u : 16u;
+    static_assert(GN % 8 == 0 && GN <= kPer, "group inside an L1 block");
+    const uint64_t gbase = min(jlo & ~7ull, jb + kPer - GN);
     const uint4* gp = reinterpret_cast<const uint4*>(L2 + gbase);
-    uint4 g[GN / 8];
-#pragma unroll
-    for (uint32_t i = 0; i < GN / 8; ++i) g[i] = gp[i];
-    const int32_t Ki = (int32_t)min<uint64_t>(k, 1ull << 20);
-    const int32_t rb = (int32_t)((gbase - jb) << L2S);  // bits from the L1 start to the group
-    const uint32_t elo = (uint32_t)(jlo - gbase), ehi = (uint32_t)(ghi - gbase);
+    const int32_t Ki = (int32_t)k;  // at most 2^16 (counted from the L1 block start)
+    const int32_t sgn = b ? 1 : -1, step = b ? 0 : (1 << L2S);
+    int32_t off = b ? 0 : (int32_t)((gbase - jb) << L2S);  // bits from the L1 start (b = 0)
+    // entries past ehi count only inside the level (the last group of a level may hold padding)
+    const uint32_t ehi = gbase + GN <= nL2 ? GN - 1 : (uint32_t)(jhi - gbase);
     uint32_t below = 0;
+    int32_t ylast = 0;  // y of the last block below k
+#pragma unroll 2
+    for (uint32_t v = 0; v < GN / 8; ++v) {
+      const uint4 x = gp[v];
 #pragma unroll
-    for (uint32_t e = 0; e < GN; ++e) {
-      const uint32_t dw =
-          (e & 7) < 4 ? ((e & 7) < 2 ? g[e >> 3].x : g[e >> 3].y) : ((e & 7) < 6 ? g[e >> 3].z : g[e >> 3].w);
-      const int32_t l2v = (int32_t)((dw >> ((e & 1) * 16)) & 0xFFFFu);
-      const bool lt = b ? (l2v < Ki) : (rb + (int32_t)(e << L2S) - l2v < Ki);
-      below += (lt && e >= elo && e <= ehi) ? 1u : 0u;
+      for (uint32_t e = 0; e < 8; ++e) {
+        const uint32_t dw = e < 4 ? (e < 2 ? x.x : x.y) : (e < 6 ? x.z : x.w);
+        const int32_t l2v = (int32_t)((dw >> ((e & 1) * 16)) & 0xFFFFu);
+        const int32_t y = off + sgn * l2v;
+        const bool lt = v * 8 + e <= ehi && y < Ki;
+        below += lt ? 1u : 0u;
+        ylast = lt ? y : ylast;
+        off += step;
+      }
     }
-    // blocks jlo .. jlo + below - 1 are below k; jlo itself always is
-    if (below == 0) below = 1;
-    if (jlo + below - 1 < ghi || ghi == jhi) {
-      jlo = jlo + below - 1;
-      jhi = jlo;
-    } else {
-      jlo = ghi;
+    const uint64_t last = gbase + below - 1;  // below >= 1
+    if (last < gbase + GN - 1 || last >= jhi) {
+      // resolved inside the group: y at that block is the count of b before it (from the L1 start)
+      k -= (uint64_t)ylast;
+      jhi = last;
+      resolved = true;
     }
+    jlo = last;
   }
   while (jlo < jhi) {
     const uint64_t mid = (jlo + jhi + 1) >> 1;
@@ -119,19 +163,8 @@ __device__ __forceinline__ uint64_t select_at(const TreeDev& d, const LevelMeta&
     if (cb < k) jlo = mid;
     else jhi = mid - 1;
   }
-  k -= b ? (uint64_t)L2[jlo] : ((jlo - jb) << L2S) - L2[jlo];
-  // word scan inside the L2 block, then the in-word select
-  const uint64_t* wp = d.bits + m.bits + (jlo << (L2S - 6));
-  uint32_t kk = (uint32_t)k;
-#pragma unroll
-  for (int w = 0; w < L2W; ++w) {
-    uint64_t word = wp[w];
-    if (!b) word = ~word;
-    const uint32_t pc = popc64(word);
-    if (kk <= pc) return (jlo << L2S) + 64u * (uint32_t)w + select_in_word(word, kk);
-    kk -= pc;
-  }
-  return nl;  // not reached for valid k
+  if (!resolved) k -= b ? (uint64_t)L2[jlo] : ((jlo - jb) << L2S) - L2[jlo];
+  return (jlo << L2S) + block_select<L2S>(d.bits + m.bits + (jlo << (L2S - 6)), b, (uint32_t)k);
 }
 
 // Algorithm 5 (top-down): the bit of the element picks the child; its position in the child is its
@@ -218,6 +251,17 @@ __device__ __forceinline__ uint64_t select_one(const QArgs& a, const LevelMeta* 
   return r - 1;
 }
 
+// Logical block of a grid-stride query launch. Workgroups go to the kXcd dies (XCDs, each with its
+// own L2) round-robin, so launch block g runs on die g mod kXcd; logical block x * G/kXcd + g/kXcd
+// gives every die a contiguous 1/kXcd of each grid-wide window of the batch. With a binned batch the
+// queries a die has in flight are then neighbours, and their lines are shared in that die's L2.
+constexpr uint32_t kXcd = 8;
+__device__ __forceinline__ uint64_t xcd_block() {
+  const uint32_t g = gridDim.x, b = blockIdx.x;
+  if (g % kXcd) return b;
+  return (uint64_t)(b % kXcd) * (g / kXcd) + b / kXcd;
+}
+
 __device__ __forceinline__ void load_meta(const QArgs& a, LevelMeta* s_meta) {
   if (threadIdx.x < a.L) s_meta[threadIdx.x] = a.d.meta[threadIdx.x];
   __syncthreads();
@@ -255,7 +299,10 @@ struct SortBufs {
 wt_status sort_batch(const wt_tree* t, const QArgs& a, int kind, const uint32_t* sym, const uint64_t* arg, uint64_t q,
                      hipStream_t st, SortBufs& sb, bool& binned);
 
-inline uint32_t query_grid(uint64_t q) { return (uint32_t)std::min<uint64_t>(ceil_div(q, kQT), 4096); }
+// Blocks of a query launch: at most 4096 (grid-stride over the batch), a multiple of kXcd.
+inline uint32_t query_grid(uint64_t q) {
+  return (uint32_t)round_up(std::min<uint64_t>(ceil_div(q, kQT), 4096), kXcd);
+}
 
 #define WT_DISPATCH_L2(bits, KERNEL, ...)                                                          \
   switch (bits) {                                                                                 \
