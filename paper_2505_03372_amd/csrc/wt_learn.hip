@@ -89,13 +89,24 @@ __device__ void block_loss_grad(const float* __restrict__ p, const float* u, con
   float loss = 0.f;
   for (int i = 0; i < nmine; ++i) mlp_point(p, u[i], v[i], scale, g, loss);
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  loss = wave_sum(loss);
-  if (lane == 0) s_wred[wv * 64] = loss;
+  // Wave reduce-scatter of the 64 slots [loss, g, 0...]: at each halving step a lane keeps one half
+  // of its current slots and adds the partner's copy of that half; lane l ends with the wave total
+  // of slot l (63 exchanges instead of 6 per value).
+  static_assert(kNP + 1 <= 64, "one slot per lane");
+  float x[64];
 #pragma unroll
-  for (int j = 0; j < kNP; ++j) {
-    const float s = wave_sum(g[j]);
-    if (lane == 0) s_wred[wv * 64 + 1 + j] = s;
+  for (int j = 0; j < 64; ++j) x[j] = j == 0 ? loss : (j <= kNP ? g[j - 1] : 0.f);
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) {
+    const bool up = (lane & o) != 0;
+#pragma unroll
+    for (int i = 0; i < o; ++i) {
+      const float send = up ? x[i] : x[i + o];
+      const float keep = up ? x[i + o] : x[i];
+      x[i] = keep + __shfl_xor(send, o, 64);
+    }
   }
+  if (lane <= kNP) s_wred[wv * 64 + lane] = x[0];
   __syncthreads();
   if (threadIdx.x < kNP + 1) {
     float s = 0.f;

@@ -167,6 +167,20 @@ __device__ __forceinline__ uint64_t select_at(const TreeDev& d, const LevelMeta&
   return (jlo << L2S) + block_select<L2S>(d.bits + m.bits + (jlo << (L2S - 6)), b, (uint32_t)k);
 }
 
+// 64-bit value of the wave's first active lane.
+__device__ __forceinline__ uint64_t first_lane_u64(uint64_t v) {
+  return ((uint64_t)(uint32_t)__builtin_amdgcn_readfirstlane((int)(v >> 32)) << 32) |
+         (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)v);
+}
+
+// Node-table entry `idx`. The lanes of a wave in a binned batch are mostly at the same node (always
+// at the upper levels): then the entry is read through a wave-uniform address (scalar load).
+__device__ __forceinline__ NodeQ node_at(const NodeQ* __restrict__ nodes, uint64_t idx) {
+  const uint64_t i0 = first_lane_u64(idx);
+  if (__ballot(idx != i0) == 0) return nodes[i0];
+  return nodes[idx];
+}
+
 // Algorithm 5 (top-down): the bit of the element picks the child; its position in the child is its
 // rank among the equal bits of the node. Stops once the node covers at most two symbols.
 // Positions >= n give 0xFFFFFFFF.
@@ -177,7 +191,7 @@ __device__ __forceinline__ uint32_t access_one(const QArgs& a, const LevelMeta* 
   uint64_t p = 0, x = i;
   for (uint32_t l = 0; l < a.L; ++l) {
     const uint32_t width = e - s;
-    const NodeQ nd = a.d.nodes[(1ull << l) - 1 + p];
+    const NodeQ nd = node_at(a.d.nodes, (1ull << l) - 1 + p);
     const LevelMeta& m = meta[l];
     const uint64_t y = nd.start + x;
     if (width <= 2) {
@@ -210,7 +224,7 @@ __device__ __forceinline__ uint64_t rank_one(const QArgs& a, const LevelMeta* me
   uint64_t p = 0, x = i;
   for (uint32_t l = 0; l < a.L; ++l) {
     if (e - s <= 1 || x == 0) break;
-    const NodeQ nd = a.d.nodes[(1ull << l) - 1 + p];
+    const NodeQ nd = node_at(a.d.nodes, (1ull << l) - 1 + p);
     const uint64_t y = nd.start + x;
     uint32_t bit;
     const uint64_t r0 = y - rank1_at<L2S>(a.d, meta[l], y, bit);
@@ -243,7 +257,7 @@ __device__ __forceinline__ uint64_t select_one(const QArgs& a, const LevelMeta* 
   for (int l = (int)len - 1; l >= 0; --l) {
     const uint64_t p = l ? (uint64_t)(code >> (a.L - l)) : 0ull;
     const uint32_t b = (code >> (a.L - 1 - l)) & 1u;
-    const NodeQ nd = a.d.nodes[(1ull << l) - 1 + p];
+    const NodeQ nd = node_at(a.d.nodes, (1ull << l) - 1 + p);
     const uint64_t target = b ? (nd.start - nd.r0) + r : nd.r0 + r;
     const uint64_t at = select_at<L2S>(a.d, meta[l], b, target, a.sshift);
     r = at - nd.start + 1;
