@@ -170,19 +170,19 @@ struct QTree {
   const LearnQ* lq;  // compiled learned-select models, or NULL
   uint32_t l2s;      // log2 |L2|
   uint32_t pad;
+  uint64_t vbase;    // start of the tree in the forest's concatenated position space (n + 1 per tree)
 };
 
 // Class of a query: op * 4 + (log2 |L2| - 8) for the four ops (a learned select on a tree without a
 // learned index is a plain select); kMixInvalid for an unknown tree or op.
 constexpr uint32_t kMixInvalid = 16;
 constexpr uint32_t kMixClasses = 17;
-constexpr uint64_t kMixDirectMax = 2048;  // batches up to this size skip the binning
-constexpr uint32_t kMixChunk = kQT * 16;  // queries per binning block
-
-struct MixRec {
-  uint32_t tree, sym;
-  uint64_t arg;
-};
+constexpr uint64_t kMixDirectMax = 2048;    // batches up to this size skip the binning
+constexpr uint32_t kMixChunk = kQT * 16;    // queries per class-sort block
+constexpr uint64_t kMixSortMin = 1ull << 16;  // batches from this size are sorted by (class, position)
+constexpr uint32_t kMixB = 2048;            // position buckets per class in that sort
+constexpr uint32_t kMixBucketClasses = 13;  // classes 0-11 (three ops x four |L2|) and the invalid one
+static_assert(kMixBucketClasses * kMixB <= kSortIdBins, "bucket ids");
 
 __device__ __forceinline__ uint32_t mix_class(const QTree* __restrict__ qt, uint32_t ntrees, uint32_t tree,
                                               uint32_t op) {
@@ -233,11 +233,8 @@ __global__ __launch_bounds__(kQT) void k_mix_count(const QTree* __restrict__ qt,
 // Pass 2: every query gets a slot inside its class's range (the order inside a class is free): the
 // block reserves its share of every class with one atomic, the waves split it with LDS atomics.
 __global__ __launch_bounds__(kQT) void k_mix_scatter(uint64_t q, const uint8_t* __restrict__ cls,
-                                                     const uint32_t* __restrict__ tree,
-                                                     const uint32_t* __restrict__ sym,
-                                                     const uint64_t* __restrict__ arg,
-                                                     const uint32_t* __restrict__ counts, uint32_t* __restrict__ cursor,
-                                                     uint32_t* __restrict__ perm, MixRec* __restrict__ rec) {
+                                                     const uint32_t* __restrict__ off, uint32_t* __restrict__ cursor,
+                                                     uint32_t* __restrict__ perm) {
   __shared__ uint32_t s_cnt[32];
   __shared__ uint32_t s_off[32];
   if (threadIdx.x < 32) s_cnt[threadIdx.x] = 0;
@@ -250,10 +247,8 @@ __global__ __launch_bounds__(kQT) void k_mix_scatter(uint64_t q, const uint8_t* 
   }
   __syncthreads();
   if (threadIdx.x < kMixClasses) {
-    uint32_t base = 0;
-    for (uint32_t c = 0; c < threadIdx.x; ++c) base += counts[c];
     const uint32_t n = s_cnt[threadIdx.x];
-    s_off[threadIdx.x] = n ? base + atomicAdd(&cursor[threadIdx.x], n) : 0u;
+    s_off[threadIdx.x] = n ? off[threadIdx.x] + atomicAdd(&cursor[threadIdx.x], n) : 0u;
   }
   __syncthreads();
   const uint32_t lane = threadIdx.x & 63u;
@@ -274,15 +269,60 @@ __global__ __launch_bounds__(kQT) void k_mix_scatter(uint64_t q, const uint8_t* 
       if (in && c == lc) slot = first + (uint32_t)__popcll(m & lt);
       pend &= ~m;
     }
-    if (in) {
-      perm[slot] = (uint32_t)j;
-      MixRec r;
-      r.tree = tree[j];
-      r.sym = sym ? sym[j] : 0u;
-      r.arg = arg[j];
-      rec[slot] = r;
-    }
+    if (in) perm[slot] = (uint32_t)j;
   }
+}
+
+// Start of every class's slots from the class counts (kMixClasses + 1 entries; the last is q).
+__global__ void k_mix_off_counts(const uint32_t* __restrict__ counts, uint64_t q, uint32_t* __restrict__ off) {
+  if (threadIdx.x != 0) return;
+  uint32_t run = 0;
+  for (uint32_t c = 0; c < kMixClasses; ++c) {
+    off[c] = run;
+    run += counts[c];
+  }
+  off[kMixClasses] = (uint32_t)q;
+}
+
+// Bucket of every query for the (class, position) sort: class (0-11, or 12 for an invalid query)
+// times kMixB plus its place in the forest's concatenated position space (the tree's start plus the
+// position, or for a select the rank of the occurrence in symbol order) >> shift. The queries of one
+// tree and region then share a bucket, so a wave's traversals share lines.
+__global__ __launch_bounds__(kQT) void k_mix_bucket(const QTree* __restrict__ qt, uint32_t ntrees,
+                                                    const uint32_t* __restrict__ tree, const uint8_t* __restrict__ op,
+                                                    const uint32_t* __restrict__ sym,
+                                                    const uint64_t* __restrict__ arg, uint64_t q, uint32_t shift,
+                                                    uint16_t* __restrict__ ids) {
+  for (uint64_t j = (uint64_t)blockIdx.x * kQT + threadIdx.x; j < q; j += (uint64_t)gridDim.x * kQT) {
+    const uint32_t tj = tree[j];
+    const uint32_t c = mix_class(qt, ntrees, tj, op[j]);
+    uint32_t id = 12u * kMixB;
+    if (c != kMixInvalid) {
+      const QTree& T = qt[tj];
+      const QArgs& a = T.a;
+      const uint64_t x = arg[j];
+      uint64_t key;
+      if ((c >> 2) == WT_OP_SELECT) {
+        const uint32_t cs = sym ? sym[j] : 0u;
+        key = a.n;
+        if (x != 0 && cs < a.sigma) {
+          const uint64_t lo = a.d.cum[cs], cnt = a.d.cum[cs + 1] - lo;
+          if (x <= cnt) key = lo + x - 1;
+        }
+      } else {
+        key = min(x, a.n);
+      }
+      id = c * kMixB + (uint32_t)min<uint64_t>((T.vbase + key) >> shift, kMixB - 1);
+    }
+    ids[j] = (uint16_t)id;
+  }
+}
+
+// Start of every class's slots from the bucket starts of the (class, position) sort.
+__global__ void k_mix_off_buckets(const uint32_t* __restrict__ tot, uint64_t q, uint32_t* __restrict__ off) {
+  const uint32_t c = threadIdx.x;
+  if (c < kMixClasses) off[c] = tot[(c < 12u ? c : 12u) * kMixB];
+  else if (c == kMixClasses) off[c] = (uint32_t)q;
 }
 
 // Pass 3: one kernel per class (op, |L2|), over that class's range of slots: every wave runs one
@@ -290,27 +330,21 @@ __global__ __launch_bounds__(kQT) void k_mix_scatter(uint64_t q, const uint8_t* 
 // the tree arguments live in vector registers; the bound keeps every class at 80 (6 waves per SIMD)
 // without spills.
 template <int OP, int L2S>
-__global__ __launch_bounds__(kQT, 6) void k_mix_run(const QTree* __restrict__ qt, const uint32_t* __restrict__ counts,
-                                                 const uint32_t* __restrict__ perm, const MixRec* __restrict__ rec,
+__global__ __launch_bounds__(kQT, 6) void k_mix_run(const QTree* __restrict__ qt, const uint32_t* __restrict__ off,
+                                                 const uint32_t* __restrict__ perm, const uint32_t* __restrict__ tree,
+                                                 const uint32_t* __restrict__ sym, const uint64_t* __restrict__ arg,
                                                  uint64_t* __restrict__ out) {
   constexpr uint32_t kC = OP * 4 + (L2S - 8);
-  __shared__ uint32_t s_rng[2];
-  if (threadIdx.x == 0) {
-    uint32_t b = 0;
-    for (uint32_t c = 0; c < kC; ++c) b += counts[c];
-    s_rng[0] = b;
-    s_rng[1] = b + counts[kC];
-  }
-  __syncthreads();
-  const uint64_t lo = s_rng[0], hi = s_rng[1];
+  const uint64_t lo = off[kC], hi = off[kC + 1];
   for (uint64_t s = lo + (uint64_t)blockIdx.x * kQT + threadIdx.x; s < hi; s += (uint64_t)gridDim.x * kQT) {
-    const MixRec r = rec[s];
-    const QArgs& a = qt[r.tree].a;
+    const uint32_t jj = perm[s];
+    const QArgs& a = qt[tree[jj]].a;
+    const uint64_t x = arg[jj];
     uint64_t res;
-    if constexpr (OP == WT_OP_ACCESS) res = access_one<L2S>(a, a.d.meta, r.arg);
-    else if constexpr (OP == WT_OP_RANK) res = rank_one<L2S>(a, a.d.meta, r.sym, r.arg);
-    else res = select_one<L2S>(a, a.d.meta, r.sym, r.arg);
-    out[perm[s]] = res;
+    if constexpr (OP == WT_OP_ACCESS) res = access_one<L2S>(a, a.d.meta, x);
+    else if constexpr (OP == WT_OP_RANK) res = rank_one<L2S>(a, a.d.meta, sym ? sym[jj] : 0u, x);
+    else res = select_one<L2S>(a, a.d.meta, sym ? sym[jj] : 0u, x);
+    out[jj] = res;
   }
 }
 
@@ -361,12 +395,10 @@ __global__ __launch_bounds__(kQT) void k_mix_direct(const QTree* __restrict__ qt
 }
 
 // Unknown tree or op.
-__global__ __launch_bounds__(kQT) void k_mix_invalid(const uint32_t* __restrict__ counts,
+__global__ __launch_bounds__(kQT) void k_mix_invalid(const uint32_t* __restrict__ off,
                                                      const uint32_t* __restrict__ perm, uint64_t* __restrict__ out) {
-  uint32_t b = 0;
-  for (uint32_t c = 0; c < kMixInvalid; ++c) b += counts[c];
-  const uint64_t hi = (uint64_t)b + counts[kMixInvalid];
-  for (uint64_t s = b + (uint64_t)blockIdx.x * kQT + threadIdx.x; s < hi; s += (uint64_t)gridDim.x * kQT)
+  const uint64_t lo = off[kMixInvalid], hi = off[kMixInvalid + 1];
+  for (uint64_t s = lo + (uint64_t)blockIdx.x * kQT + threadIdx.x; s < hi; s += (uint64_t)gridDim.x * kQT)
     out[perm[s]] = ~0ull;
 }
 
@@ -385,6 +417,7 @@ struct wt_forest {
   size_t block_bytes = 0;
   void* qtab = nullptr;         // per-tree query state for wt_query_mixed (made on first use)
   uint64_t qversion = 0;        // sum of the trees' learned-index versions when qtab was made
+  uint32_t vshift = 0;          // position-space shift of the (class, position) query sort
   wt_forest_info_t info{};
 };
 
@@ -815,47 +848,84 @@ extern "C" wt_status wt_forest_free(wt_forest* f) {
 
 namespace wt {
 
-// Scratch of one mixed batch: class counts and cursors, classes, slots, records (none for the
-// unbinned path).
-size_t mixed_scratch_bytes(uint64_t q) {
-  if (q <= kMixDirectMax) return 0;
-  const size_t o_perm = round_up(256 + q, 256), o_rec = round_up(o_perm + 4 * q, 256);
-  return o_rec + 16 * q;
+// Scratch of one mixed batch. Class sort (2048 < q < 2^16): class offsets, counts and cursors,
+// classes, slots. (class, position) sort: class offsets, bucket ids, sort passes, bucket starts,
+// slots. Nothing for the unbinned path.
+struct MixLayout {
+  size_t off = 0, counts = 0, cls = 0, ids = 0, sort = 0, tot = 0, perm = 0, total = 0;
+};
+MixLayout mix_layout(uint64_t q) {
+  MixLayout L;
+  if (q <= kMixDirectMax) return L;
+  size_t o = 0;
+  auto take = [&](size_t bytes) {
+    const size_t at = o;
+    o = round_up(o + bytes, 256);
+    return at;
+  };
+  L.off = take(4 * (kMixClasses + 1));
+  if (q < kMixSortMin) {
+    L.counts = take(4 * 64);
+    L.cls = take(q);
+  } else {
+    L.ids = take(2 * q);
+    L.sort = take(sort_ids_bytes(q));
+    L.tot = take(4 * kSortIdBins);
+  }
+  L.perm = take(4 * q);
+  L.total = o;
+  return L;
 }
 
-// Enqueues one mixed batch on st (scratch: mixed_scratch_bytes(q) bytes of device memory).
+size_t mixed_scratch_bytes(uint64_t q) { return mix_layout(q).total; }
+
+// Enqueues one mixed batch on st (scratch: mixed_scratch_bytes(q) bytes of device memory; vshift:
+// forest_vshift of the forest).
 hipError_t mixed_enqueue(const QTree* qt, uint32_t ntrees, const uint32_t* d_tree, const uint8_t* d_op,
                          const uint32_t* d_sym, const uint64_t* d_arg, uint64_t q, uint64_t* d_out, char* sb,
-                         hipStream_t st) {
+                         uint32_t vshift, hipStream_t st) {
   if (q <= kMixDirectMax) {
     hipLaunchKernelGGL(k_mix_direct, dim3((uint32_t)ceil_div(q, kQT)), dim3(kQT), 0, st, qt, ntrees, d_tree, d_op,
                        d_sym, d_arg, q, d_out);
     return hipGetLastError();
   }
-  const size_t o_cls = 256, o_perm = round_up(o_cls + q, 256), o_rec = round_up(o_perm + 4 * q, 256);
-  uint32_t* counts = (uint32_t*)sb;
-  uint32_t* cursor = counts + 32;
-  const uint32_t nchunk = (uint32_t)ceil_div(q, kMixChunk);
-  hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(64), 0, st, counts, 64u);
-  hipLaunchKernelGGL(k_mix_count, dim3(nchunk), dim3(kQT), 0, st, qt, ntrees, d_tree, d_op, q, (uint8_t*)(sb + o_cls),
-                     counts);
-  hipLaunchKernelGGL(k_mix_scatter, dim3(nchunk), dim3(kQT), 0, st, q, (const uint8_t*)(sb + o_cls), d_tree, d_sym,
-                     d_arg, (const uint32_t*)counts, cursor, (uint32_t*)(sb + o_perm), (MixRec*)(sb + o_rec));
+  const MixLayout L = mix_layout(q);
+  uint32_t* off = (uint32_t*)(sb + L.off);
+  uint32_t* perm = (uint32_t*)(sb + L.perm);
+  if (q < kMixSortMin) {
+    uint32_t* counts = (uint32_t*)(sb + L.counts);
+    uint32_t* cursor = counts + 32;
+    const uint32_t nchunk = (uint32_t)ceil_div(q, kMixChunk);
+    hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(64), 0, st, counts, 64u);
+    hipLaunchKernelGGL(k_mix_count, dim3(nchunk), dim3(kQT), 0, st, qt, ntrees, d_tree, d_op, q,
+                       (uint8_t*)(sb + L.cls), counts);
+    hipLaunchKernelGGL(k_mix_off_counts, dim3(1), dim3(64), 0, st, (const uint32_t*)counts, q, off);
+    hipLaunchKernelGGL(k_mix_scatter, dim3(nchunk), dim3(kQT), 0, st, q, (const uint8_t*)(sb + L.cls),
+                       (const uint32_t*)off, cursor, perm);
+  } else {
+    uint16_t* ids = (uint16_t*)(sb + L.ids);
+    uint32_t* tot = (uint32_t*)(sb + L.tot);
+    hipLaunchKernelGGL(k_mix_bucket, dim3((uint32_t)std::min<uint64_t>(ceil_div(q, kQT), 4096)), dim3(kQT), 0, st, qt,
+                       ntrees, d_tree, d_op, d_sym, d_arg, q, vshift, ids);
+    sort_ids_enqueue(ids, q, sb + L.sort, tot, perm, st);
+    hipLaunchKernelGGL(k_mix_off_buckets, dim3(1), dim3(64), 0, st, (const uint32_t*)tot, q, off);
+  }
   // the class sizes stay on the device: every class kernel is launched and finds its own range
   const uint32_t grid = (uint32_t)std::min<uint64_t>(ceil_div(q, kQT), 2048);
-  const uint32_t* pm = (const uint32_t*)(sb + o_perm);
-  const MixRec* rc = (const MixRec*)(sb + o_rec);
-#define WT_MIX(OP, S) hipLaunchKernelGGL((k_mix_run<OP, S>), dim3(grid), dim3(kQT), 0, st, qt, counts, pm, rc, d_out)
+  const uint32_t* po = off;
+  const uint32_t* pm = perm;
+#define WT_MIX(OP, S) \
+  hipLaunchKernelGGL((k_mix_run<OP, S>), dim3(grid), dim3(kQT), 0, st, qt, po, pm, d_tree, d_sym, d_arg, d_out)
   WT_MIX(0, 8); WT_MIX(0, 9); WT_MIX(0, 10); WT_MIX(0, 11);
   WT_MIX(1, 8); WT_MIX(1, 9); WT_MIX(1, 10); WT_MIX(1, 11);
   WT_MIX(2, 8); WT_MIX(2, 9); WT_MIX(2, 10); WT_MIX(2, 11);
 #undef WT_MIX
-  hipLaunchKernelGGL(k_mix_invalid, dim3(std::min<uint32_t>(grid, 64)), dim3(kQT), 0, st, (const uint32_t*)counts, pm,
-                     d_out);
+  hipLaunchKernelGGL(k_mix_invalid, dim3(std::min<uint32_t>(grid, 64)), dim3(kQT), 0, st, po, pm, d_out);
   return hipGetLastError();
 }
 
 uint32_t forest_count(const wt_forest* f) { return f->count; }
+uint32_t forest_vshift(const wt_forest* f) { return f->vshift; }
 
 // Query table of a forest, rebuilt when a tree's learned index changed since it was made.
 wt_status forest_qtab(const wt_forest* fc, hipStream_t st, const QTree** out) {
@@ -864,14 +934,20 @@ wt_status forest_qtab(const wt_forest* fc, hipStream_t st, const QTree** out) {
   for (const wt_tree* t : f->trees) ver += t->learn_version;
   if (!f->qtab || ver != f->qversion) {
     std::vector<QTree> hq(f->count);
+    uint64_t vb = 0;
     for (uint32_t j = 0; j < f->count; ++j) {
       const wt_tree* t = f->trees[j];
       std::memset(&hq[j], 0, sizeof(QTree));
+      hq[j].vbase = vb;
+      vb += t->n + 1;
       hq[j].a = make_args(t);
       hq[j].lq = t->learn && t->nmodels ? (const LearnQ*)((const char*)t->learn + (size_t)t->nmodels * learn_model_bytes())
                                         : nullptr;
       hq[j].l2s = log2_floor(t->l2_bits);
     }
+    uint32_t bits = 0;
+    while ((1ull << bits) < vb) ++bits;
+    f->vshift = bits > 11 ? bits - 11 : 0;  // kMixB = 2^11 buckets over the whole space
     if (!f->qtab) {
       f->qtab = dev_alloc(f->count * sizeof(QTree), st);
       if (!f->qtab) return fail(WT_ERR_OOM, "query table allocation failed");
@@ -904,7 +980,7 @@ extern "C" wt_status wt_query_mixed(const wt_forest* f, const uint32_t* d_tree, 
     sb = (char*)dev_alloc(bytes, st);
     if (!sb) return fail(WT_ERR_OOM, "wt_query_mixed: scratch allocation of %zu bytes failed", bytes);
   }
-  const hipError_t he = mixed_enqueue(qt, f->count, d_tree, d_op, d_sym, d_arg, q, d_out, sb, st);
+  const hipError_t he = mixed_enqueue(qt, f->count, d_tree, d_op, d_sym, d_arg, q, d_out, sb, f->vshift, st);
   if (sb) dev_free(sb, st);
   if (he != hipSuccess) return fail(WT_ERR_HIP, "wt_query_mixed: %s", hipGetErrorString(he));
   return WT_OK;

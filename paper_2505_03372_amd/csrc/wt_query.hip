@@ -189,6 +189,52 @@ __global__ __launch_bounds__(kBinT) void k_bin_scatter(QArgs a, const uint32_t* 
   }
 }
 
+// Counting sort by precomputed bucket ids (< kBins), same passes as above: bhist, then the bucket
+// offsets, then the slot order.
+__global__ __launch_bounds__(kBinT) void k_bin_count_ids(const uint16_t* __restrict__ ids, uint64_t q,
+                                                         uint32_t* __restrict__ bhist) {
+  __shared__ uint32_t h[kBins];
+  for (uint32_t b = threadIdx.x; b < kBins; b += kBinT) h[b] = 0;
+  __syncthreads();
+  const uint64_t c0 = (uint64_t)blockIdx.x * kBinChunk;
+  for (uint32_t i = threadIdx.x; i < kBinChunk; i += kBinT) {
+    const uint64_t j = c0 + i;
+    if (j < q) atomicAdd(&h[ids[j]], 1u);
+  }
+  __syncthreads();
+  for (uint32_t b = threadIdx.x; b < kBins; b += kBinT) bhist[(uint64_t)blockIdx.x * kBins + b] = h[b];
+}
+
+__global__ __launch_bounds__(kBinT) void k_bin_scatter_ids(const uint16_t* __restrict__ ids, uint64_t q,
+                                                           const uint32_t* __restrict__ bhist,
+                                                           const uint32_t* __restrict__ base,
+                                                           uint32_t* __restrict__ perm) {
+  __shared__ uint32_t cur[kBins];
+  for (uint32_t b = threadIdx.x; b < kBins; b += kBinT) cur[b] = base[b] + bhist[(uint64_t)blockIdx.x * kBins + b];
+  __syncthreads();
+  const uint64_t c0 = (uint64_t)blockIdx.x * kBinChunk;
+  for (uint32_t i = threadIdx.x; i < kBinChunk; i += kBinT) {
+    const uint64_t j = c0 + i;
+    if (j >= q) continue;
+    perm[atomicAdd(&cur[ids[j]], 1u)] = (uint32_t)j;
+  }
+}
+
+size_t sort_ids_bytes(uint64_t q) {
+  const uint32_t nblk = (uint32_t)ceil_div(q, kBinChunk);
+  return round_up((size_t)nblk * kBins * 4, 256) + round_up(4 * kBins, 256);
+}
+
+void sort_ids_enqueue(const uint16_t* ids, uint64_t q, char* scratch, uint32_t* tot, uint32_t* perm, hipStream_t st) {
+  const uint32_t nblk = (uint32_t)ceil_div(q, kBinChunk);
+  uint32_t* bhist = (uint32_t*)scratch;
+  hipLaunchKernelGGL(k_bin_count_ids, dim3(nblk), dim3(kBinT), 0, st, ids, q, bhist);
+  hipLaunchKernelGGL(k_bin_offsets, dim3(kBins / kQT), dim3(kQT), 0, st, bhist, nblk, tot);
+  hipLaunchKernelGGL(k_bin_scan, dim3(1), dim3(1024), 0, st, tot);
+  hipLaunchKernelGGL(k_bin_scatter_ids, dim3(nblk), dim3(kBinT), 0, st, ids, q, (const uint32_t*)bhist,
+                     (const uint32_t*)tot, perm);
+}
+
 // Bins the batch on st (kind 0 access, 1 rank, 2 select); binned = false when the batch is too small
 // to pay (or too large for 32-bit slots).
 wt_status sort_batch(const wt_tree* t, const QArgs& a, int kind, const uint32_t* sym, const uint64_t* arg,

@@ -314,6 +314,12 @@ wt_status sort_batch(const wt_tree* t, const QArgs& a, int kind, const uint32_t*
                      hipStream_t st, SortBufs& sb, bool& binned);
 
 // Blocks of a query launch: at most 4096 (grid-stride over the batch), a multiple of kXcd.
+// Counting sort of q queries by bucket id (ids[j] < 32768; wt_query.hip). scratch: sort_ids_bytes(q)
+// bytes; tot: 32768 entries, left holding the exclusive start of every bucket; perm: the slot order.
+size_t sort_ids_bytes(uint64_t q);
+void sort_ids_enqueue(const uint16_t* ids, uint64_t q, char* scratch, uint32_t* tot, uint32_t* perm, hipStream_t st);
+constexpr uint32_t kSortIdBins = 32768;
+
 inline uint32_t query_grid(uint64_t q) {
   return (uint32_t)round_up(std::min<uint64_t>(ceil_div(q, kQT), 4096), kXcd);
 }

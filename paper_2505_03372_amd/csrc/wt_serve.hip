@@ -26,9 +26,10 @@ struct QTree;
 size_t mixed_scratch_bytes(uint64_t q);
 hipError_t mixed_enqueue(const QTree* qt, uint32_t ntrees, const uint32_t* d_tree, const uint8_t* d_op,
                          const uint32_t* d_sym, const uint64_t* d_arg, uint64_t q, uint64_t* d_out, char* sb,
-                         hipStream_t st);
+                         uint32_t vshift, hipStream_t st);
 wt_status forest_qtab(const wt_forest* f, hipStream_t st, const QTree** out);
 uint32_t forest_count(const wt_forest* f);
+uint32_t forest_vshift(const wt_forest* f);
 
 namespace {
 
@@ -265,7 +266,8 @@ extern "C" wt_status wt_server_run(wt_server* s, const wt_request* reqs, uint32_
         if (e == hipSuccess && R.h_sym) e = hipMemcpyAsync(d_sym, R.h_sym, 4 * R.q, hipMemcpyHostToDevice, sl.st);
         if (e == hipSuccess) e = hipMemcpyAsync(d_arg, R.h_arg, 8 * R.q, hipMemcpyHostToDevice, sl.st);
         if (e == hipSuccess)
-          e = mixed_enqueue(qt, ntrees, d_tree, d_op, R.h_sym ? d_sym : nullptr, d_arg, R.q, d_out, scratch, sl.st);
+          e = mixed_enqueue(qt, ntrees, d_tree, d_op, R.h_sym ? d_sym : nullptr, d_arg, R.q, d_out, scratch,
+                            forest_vshift(s->f), sl.st);
         if (e == hipSuccess) e = hipMemcpyAsync(R.h_out, d_out, 8 * R.q, hipMemcpyDeviceToHost, sl.st);
         if (e == hipSuccess) e = hipEventRecord(sl.done, sl.st);
         if (e != hipSuccess) {

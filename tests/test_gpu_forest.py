@@ -122,10 +122,10 @@ def _mixed_reference(f, seqs, tree, op, sym, arg):
     return out
 
 
-def test_mixed_queries_match_per_tree_calls(small_forest):
+@pytest.mark.parametrize("q", [5001, 200003])  # class-sorted below 2^16 queries, (class, position)-sorted above
+def test_mixed_queries_match_per_tree_calls(small_forest, q):
     f, seqs = small_forest
     T = len(seqs)
-    q = 200003
     r = workloads.raw(0x3151, 0, 4 * q)
     tree = (r[:q] % np.uint64(T + 2)).astype(np.uint32)  # two unknown tree ids
     op = (r[q:2 * q] % np.uint64(5)).astype(np.uint8)     # op 3: learned select (plain here), op 4 unknown

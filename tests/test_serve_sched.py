@@ -14,10 +14,21 @@ def _reqs(sizes, arrivals):
     return [dict(q=int(q), arrival_s=float(a)) for q, a in zip(sizes, arrivals)]
 
 
+def _mixed_scratch(q):
+    """Device scratch of one mixed batch (class offsets; then class counts and classes below 2^16
+    queries, else bucket ids, the sort passes and the bucket starts; then the slot order)."""
+    r = lambda x: (x + 255) // 256 * 256  # noqa: E731
+    if q <= 2048:
+        return 0
+    if q < 1 << 16:
+        return r(4 * 18) + r(4 * 64) + r(q) + r(4 * q)
+    nblk = -(-q // (1024 * 256))
+    return r(4 * 18) + r(2 * q) + r(r(nblk * 32768 * 4) + r(4 * 32768)) + r(4 * 32768) + r(4 * q)
+
+
 def _request_bytes(q):
     r = lambda x: (x + 255) // 256 * 256  # noqa: E731
-    scratch = 0 if q <= 2048 else r(r(256 + q) + 4 * q) + 16 * q
-    return r(4 * q) + r(q) + r(4 * q) + r(8 * q) + r(8 * q) + r(scratch)
+    return r(4 * q) + r(q) + r(4 * q) + r(8 * q) + r(8 * q) + r(_mixed_scratch(q))
 
 
 def test_fifo_single_slot():
