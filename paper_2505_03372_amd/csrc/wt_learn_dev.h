@@ -39,6 +39,9 @@ static_assert(offsetof(LearnQ, knot) % 16 == 0 && offsetof(LearnQ, knot) + sizeo
               "header and switch points share the first line");
 
 // v(u) of a compiled model, clamped to [0, 1]: the piece is the number of switch points <= u.
+// kUniform: Q is at a wave-uniform address; every piece is read with it (scalar loads, no second
+// dependent read) and the lane's piece is picked in registers.
+template <bool kUniform = false>
 __device__ __forceinline__ float pla_eval(const LearnQ& Q, float u) {
   const float4* kp = reinterpret_cast<const float4*>(Q.knot);
   uint32_t s = 0;
@@ -47,7 +50,18 @@ __device__ __forceinline__ float pla_eval(const LearnQ& Q, float u) {
     const float4 x = kp[i];
     s += (uint32_t)(x.x <= u) + (uint32_t)(x.y <= u) + (uint32_t)(x.z <= u) + (uint32_t)(x.w <= u);
   }
-  const float2 pc = Q.piece[s];
+  float2 pc;
+  if constexpr (kUniform) {
+    pc = Q.piece[0];
+#pragma unroll
+    for (uint32_t i = 1; i <= (uint32_t)kH; ++i) {
+      const float2 y = Q.piece[i];
+      pc.x = s == i ? y.x : pc.x;
+      pc.y = s == i ? y.y : pc.y;
+    }
+  } else {
+    pc = Q.piece[s];
+  }
   return fminf(fmaxf(fmaf(pc.x, u, pc.y), 0.f), 1.f);
 }
 
@@ -60,13 +74,13 @@ __device__ __forceinline__ uint64_t count_before(const TreeDev& d, const LevelMe
 
 // Position of the j-th (1-based, node-local) side-b bit of the node of model Q at level m.
 // GS: log2 of the L2 counts read at once around the prediction.
-template <int L2S, int GS>
+template <int L2S, int GS, bool kUniform = false>
 __device__ __forceinline__ uint64_t select_learned_at(const TreeDev& d, const LevelMeta& m, const LearnQ& Q,
                                                       uint64_t j, uint32_t sshift) {
   const uint32_t b = Q.side;
   const uint64_t T = Q.rank0 + j;  // global target among the side-b bits of the level
   if (Q.eps < 0) return select_at<L2S, false>(d, m, b, T, sshift);
-  const float v = pla_eval(Q, ((float)j - 0.5f) / Q.cntf);
+  const float v = pla_eval<kUniform>(Q, ((float)j - 0.5f) / Q.cntf);
   const uint64_t start = Q.start, end = Q.start + Q.len;
   const uint64_t guess = min(start + (uint64_t)(v * Q.lenf), end - 1);  // FP32: a few positions off at most
   const uint64_t Blo = start >> L2S, Bhi = (end - 1) >> L2S;
@@ -198,7 +212,7 @@ __device__ __forceinline__ uint64_t select_learned_one(const QArgs& a, const Lev
     uint64_t at, start;
     if (__ballot(mi != m0) == 0) {
       const LearnQ& Q = qm[m0];
-      at = select_learned_at<L2S, GS>(a.d, meta[l], Q, r, a.sshift);
+      at = select_learned_at<L2S, GS, true>(a.d, meta[l], Q, r, a.sshift);
       start = Q.start;
     } else {
       const LearnQ& Q = qm[mi];

@@ -57,7 +57,7 @@ __device__ __forceinline__ uint32_t block_select(const uint64_t* __restrict__ wp
   const uint4* vp = reinterpret_cast<const uint4*>(wp);  // the block is 64-byte aligned
   uint64_t sel = 0;
   uint32_t wsel = 0;
-#pragma unroll 4
+#pragma unroll 1
   for (int v = 0; v < L2W / 2; ++v) {
     const uint4 x = vp[v];
     const uint64_t pair[2] = {((uint64_t)x.y << 32) | x.x, ((uint64_t)x.w << 32) | x.z};
@@ -132,9 +132,10 @@ __device__ __forceinline__ uint64_t select_at(const TreeDev& d, const LevelMeta&
     int32_t off = b ? 0 : (int32_t)((gbase - jb) << L2S);  // bits from the L1 start (b = 0)
     // entries past ehi count only inside the level (the last group of a level may hold padding)
     const uint32_t ehi = gbase + GN <= nL2 ? GN - 1 : (uint32_t)(jhi - gbase);
-    uint32_t below = 0;
+    uint32_t below = 0, seen = 0;
     int32_t ylast = 0;  // y of the last block below k
-#pragma unroll 2
+    // one vector at a time: a lane stops at the first vector that ends the prefix or reaches jhi
+#pragma unroll 1
     for (uint32_t v = 0; v < GN / 8; ++v) {
       const uint4 x = gp[v];
 #pragma unroll
@@ -147,9 +148,11 @@ __device__ __forceinline__ uint64_t select_at(const TreeDev& d, const LevelMeta&
         ylast = lt ? y : ylast;
         off += step;
       }
+      seen += 8;
+      if (below < seen || gbase + seen - 1 >= jhi) break;
     }
     const uint64_t last = gbase + below - 1;  // below >= 1
-    if (last < gbase + GN - 1 || last >= jhi) {
+    if (last < gbase + seen - 1 || last >= jhi) {
       // resolved inside the group: y at that block is the count of b before it (from the L1 start)
       k -= (uint64_t)ylast;
       jhi = last;
