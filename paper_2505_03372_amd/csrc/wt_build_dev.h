@@ -383,6 +383,8 @@ __device__ __forceinline__ void hist_dense_body(PS sym, uint64_t n, uint32_t sig
   const uint64_t tb = ntiles * bid / nblk, te = ntiles * (bid + 1) / nblk;
   const uint64_t nit = (te - tb + kHG - 1) / kHG;
   const uint32_t lsh = L ? L - 1 : 0;
+  // sigma covers every value of E (u8 with 256 symbols, u16 with 2^16): counted in one window
+  const bool full = sizeof(E) < 4 && sigma == (1u << (8 * sizeof(E))) && win == sigma;
   uint32_t bad = 0;
   for (uint32_t w0 = 0; w0 < sigma; w0 += win) {
     const uint32_t wn = min(win, sigma - w0);
@@ -409,7 +411,21 @@ __device__ __forceinline__ void hist_dense_body(PS sym, uint64_t n, uint32_t sig
             }
           }
         };
-        if (aligned && cnt == (uint32_t)TL::T) {
+        if (full && aligned && cnt == (uint32_t)TL::T) {
+          // every value of E is a symbol (one window, nothing out of range): per element only the
+          // counter address and the add; the level-0 ones per vector by a dot product
+          u32x4 vx[NCH];
+#pragma unroll
+          for (int k = 0; k < NCH; ++k) vx[k] = *pcast<const u32x4>(sym + t0 + (uint32_t)(k * kBT + gt) * EV);
+#pragma unroll
+          for (int k = 0; k < NCH; ++k) {
+            uint4 x;
+            __builtin_memcpy(&x, &vx[k], 16);
+#pragma unroll
+            for (int e = 0; e < EV; ++e) atomicAdd(&my_h[vec_elem<E>(x, e)], 1u);
+            ones += vec_count_bit<E>(x, lsh);
+          }
+        } else if (aligned && cnt == (uint32_t)TL::T) {
           // whole aligned tile: every vector in flight at once, kept packed (4 registers each)
           u32x4 vx[NCH];
 #pragma unroll

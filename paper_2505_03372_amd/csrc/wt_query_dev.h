@@ -17,7 +17,9 @@ struct QArgs {
 };
 
 // rank1 of the level at position i (0 <= i <= n_l) and the bit at i (meaningful for i < n_l).
-template <int L2S>
+// kMask: load only the 16-byte vectors of the L2 block up to the one holding word i / 64 (a lane's
+// loads past it are masked off and cost no address cycles; faster for rank, not for access).
+template <int L2S, bool kMask = false>
 __device__ __forceinline__ uint64_t rank1_at(const TreeDev& d, const LevelMeta& m, uint64_t i, uint32_t& bit) {
   constexpr int L2W = (1 << L2S) / 64;
   const uint64_t j = i >> L2S;
@@ -29,7 +31,8 @@ __device__ __forceinline__ uint64_t rank1_at(const TreeDev& d, const LevelMeta& 
     uint64_t w[L2W];
 #pragma unroll
     for (int k = 0; k < L2W / 2; ++k) {
-      const uint4 x = reinterpret_cast<const uint4*>(blk)[k];
+      uint4 x = make_uint4(0u, 0u, 0u, 0u);
+      if (!kMask || (uint32_t)(2 * k) <= wi) x = reinterpret_cast<const uint4*>(blk)[k];
       w[2 * k] = (uint64_t)x.x | ((uint64_t)x.y << 32);
       w[2 * k + 1] = (uint64_t)x.z | ((uint64_t)x.w << 32);
     }
@@ -230,7 +233,7 @@ __device__ __forceinline__ uint64_t rank_one(const QArgs& a, const LevelMeta* me
     const NodeQ nd = node_at(a.d.nodes, (1ull << l) - 1 + p);
     const uint64_t y = nd.start + x;
     uint32_t bit;
-    const uint64_t r0 = y - rank1_at<L2S>(a.d, meta[l], y, bit);
+    const uint64_t r0 = y - rank1_at<L2S, true>(a.d, meta[l], y, bit);
     const uint32_t split = s + (uint32_t)pow2_below(e - s);
     if (c < split) {
       x = r0 - nd.r0;
