@@ -82,10 +82,23 @@ __global__ __launch_bounds__(kHT) void k_hist_dense(const E* __restrict__ sym, u
 }
 
 template <typename E>
-__global__ __launch_bounds__(kBT) void k_hist_hash(const E* __restrict__ sym, uint64_t n, uint32_t sigma, uint32_t L,
-                                                   uint32_t aligned, uint64_t* __restrict__ hist,
-                                                   uint64_t* __restrict__ tile_cnt0, uint32_t* __restrict__ err) {
-  hist_hash_body<E>(sym, n, sigma, L, aligned, hist, tile_cnt0, err, blockIdx.x, gridDim.x);
+__global__ __launch_bounds__(kHT) void k_hist_gcount(const E* __restrict__ sym, uint64_t n, uint32_t sigma, uint32_t L,
+                                                     uint32_t aligned, uint64_t* __restrict__ gcnt,
+                                                     uint64_t* __restrict__ tile_cnt0, uint32_t* __restrict__ err) {
+  hist_group_count_body<E>(sym, n, sigma, L, aligned, gcnt, tile_cnt0, err, blockIdx.x, gridDim.x);
+}
+
+template <typename E>
+__global__ __launch_bounds__(kHT) void k_hist_gscatter(const E* __restrict__ sym, uint64_t n, uint32_t sigma,
+                                                       uint32_t aligned, const uint64_t* __restrict__ goff,
+                                                       E* __restrict__ dst) {
+  hist_group_scatter_body<E>(sym, n, sigma, aligned, goff, dst, blockIdx.x, gridDim.x);
+}
+
+template <typename E>
+__global__ __launch_bounds__(kHT) void k_hist_wcount(const E* __restrict__ src, const uint64_t* __restrict__ goff,
+                                                     uint64_t nblk1, uint32_t sigma, uint64_t* __restrict__ hist) {
+  hist_window_count_body<E>(src, goff, nblk1, sigma, hist, blockIdx.x);
 }
 
 __global__ void k_node_walk(uint32_t sigma, uint64_t nheap, const uint64_t* __restrict__ cum,
@@ -161,26 +174,50 @@ struct Scratch {
   }
 };
 
+// Buffers of the histogram phase; gcnt, goff and seq only for alphabets above kHDenseMax.
+struct HistBufs {
+  uint64_t* hist;
+  uint64_t* cnt0;
+  uint32_t* err;
+  uint64_t* gcnt;  // windows x blocks + 1 (radix step)
+  uint64_t* goff;  // its exclusive scan
+  uint64_t* part;  // scan partials
+  void* seq;       // n symbols in window order
+};
+
+// Entries of gcnt for an alphabet above kHDenseMax (0 otherwise).
+inline uint64_t hist_gcnt_entries(uint64_t n, uint32_t w, uint64_t sigma) {
+  if (sigma <= kHDenseMax || n == 0) return 0;
+  const uint64_t ntiles = ceil_div(n, tile_elems(w));
+  const uint64_t G = ceil_div(sigma, 1ull << kHWinShift);
+  return G * hist_dense_blocks(ntiles, hist_tiles_per_block(ntiles)) + 1;
+}
+
 template <typename E>
-hipError_t launch_hist(const void* d_sym, uint64_t n, uint32_t sigma, uint32_t L, uint64_t* hist, uint64_t* cnt0,
-                       uint32_t* err, hipStream_t st) {
+hipError_t launch_hist(const void* d_sym, uint64_t n, uint32_t sigma, uint32_t L, const HistBufs& hb, hipStream_t st) {
   using TL = Tile<E>;
   const uint64_t ntiles = ceil_div(n, TL::T);
   if (ntiles == 0) return hipSuccess;
   const uint32_t aligned = ((uintptr_t)d_sym & 15u) == 0;
+  const uint32_t grid = (uint32_t)hist_dense_blocks(ntiles, hist_tiles_per_block(ntiles));
   if (sigma <= kHDenseMax) {
-    const uint32_t grid = (uint32_t)hist_dense_blocks(ntiles, hist_tiles_per_block(ntiles));
     if (sigma + 1 <= kHSmallWords)
       hipLaunchKernelGGL((k_hist_dense<E, kHSmallWords>), dim3(grid), dim3(kHT), 0, st, (const E*)d_sym, n, sigma,
-                         L, aligned, hist, cnt0, err);
+                         L, aligned, hb.hist, hb.cnt0, hb.err);
     else
       hipLaunchKernelGGL((k_hist_dense<E, kHBigWords>), dim3(grid), dim3(kHT), 0, st, (const E*)d_sym, n, sigma, L,
-                         aligned, hist, cnt0, err);
-  } else {
-    const uint32_t grid = (uint32_t)std::min<uint64_t>(ntiles, 2048);
-    hipLaunchKernelGGL((k_hist_hash<E>), dim3(grid), dim3(kBT), 0, st, (const E*)d_sym, n, sigma, L, aligned, hist,
-                       cnt0, err);
+                         aligned, hb.hist, hb.cnt0, hb.err);
+    return hipGetLastError();
   }
+  const uint64_t G = ceil_div(sigma, 1ull << kHWinShift);
+  hipLaunchKernelGGL(k_hist_gcount<E>, dim3(grid), dim3(kHT), 0, st, (const E*)d_sym, n, sigma, L, aligned, hb.gcnt,
+                     hb.cnt0, hb.err);
+  hipError_t he = exclusive_scan_u64(hb.gcnt, G * grid + 1, hb.goff, hb.part, st);
+  if (he != hipSuccess) return he;
+  hipLaunchKernelGGL(k_hist_gscatter<E>, dim3(grid), dim3(kHT), 0, st, (const E*)d_sym, n, sigma, aligned,
+                     (const uint64_t*)hb.goff, (E*)hb.seq);
+  hipLaunchKernelGGL(k_hist_wcount<E>, dim3((uint32_t)ceil_div(n, kHWinChunk)), dim3(kHT), 0, st,
+                     (const E*)hb.seq, (const uint64_t*)hb.goff, (uint64_t)grid, sigma, hb.hist);
   return hipGetLastError();
 }
 
@@ -327,7 +364,10 @@ extern "C" wt_status wt_build(const void* d_sym, uint64_t n, uint32_t sym_bytes,
   const size_t o_ntb = take(std::max<uint64_t>(P.nheap, 1) * sizeof(NodeB));
   const size_t o_z = take((P.nheap + 1) * 8);
   const size_t o_zs = take((P.nheap + 1) * 8);
-  const size_t o_part = take(part_n * 8);
+  const uint64_t gcnt_n = hist_gcnt_entries(n, sym_bytes, sigma);
+  const size_t o_part = take(std::max<uint64_t>(part_n, ceil_div(gcnt_n, kScanChunk) + 1) * 8);
+  const size_t o_gcnt = take(gcnt_n * 8);
+  const size_t o_goff = take(gcnt_n * 8);
   const size_t o_err = take(64);
   Scratch S;
   S.st = st;
@@ -379,9 +419,10 @@ extern "C" wt_status wt_build(const void* d_sym, uint64_t n, uint32_t sym_bytes,
   WT_STEP(prof.end());
 
   WT_STEP(prof.begin("hist", -1));
-  if (sym_bytes == 1) WT_STEP(launch_hist<uint8_t>(d_sym, n, (uint32_t)sigma, L, hist, tcnt, err, st));
-  else if (sym_bytes == 2) WT_STEP(launch_hist<uint16_t>(d_sym, n, (uint32_t)sigma, L, hist, tcnt, err, st));
-  else WT_STEP(launch_hist<uint32_t>(d_sym, n, (uint32_t)sigma, L, hist, tcnt, err, st));
+  const HistBufs hb{hist, tcnt, err, (uint64_t*)(sb + o_gcnt), (uint64_t*)(sb + o_goff), part, seq[0]};
+  if (sym_bytes == 1) WT_STEP(launch_hist<uint8_t>(d_sym, n, (uint32_t)sigma, L, hb, st));
+  else if (sym_bytes == 2) WT_STEP(launch_hist<uint16_t>(d_sym, n, (uint32_t)sigma, L, hb, st));
+  else WT_STEP(launch_hist<uint32_t>(d_sym, n, (uint32_t)sigma, L, hb, st));
   WT_STEP(prof.end());
 
   WT_STEP(prof.begin("cum_hist", -1));

@@ -466,6 +466,139 @@ __device__ __forceinline__ void hist_dense_body(PS sym, uint64_t n, uint32_t sig
   if (bad) (void)__hip_atomic_fetch_or(err, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
+// Alphabets above kHDenseMax (single-tree build): a radix step keeps every count in LDS.
+//  1. group count: per block (tile ranges as in the dense histogram) the symbols per window of
+//     2^kHWinShift symbols, written window-major (gcnt[g * nblk + block]); the level-0 ones per tile
+//     and the out-of-range flag on the way;
+//  2. an exclusive scan of gcnt gives every (window, block) its slots;
+//  3. group scatter: the blocks place their symbols in window order (LDS cursors);
+//  4. window count: blocks over fixed ranges of the window-ordered symbols count each window piece
+//     densely in LDS and add the nonzero counts to the histogram.
+constexpr uint32_t kHWinShift = 15;          // 32768 symbols per window (128 KB of counters)
+constexpr uint32_t kHMaxWin = 512;           // windows for WT_MAX_SIGMA = 2^24
+constexpr uint64_t kHWinChunk = 1ull << 20;  // window-ordered symbols per block of the window count
+
+template <typename E, typename PS, typename PH, typename PE>
+__device__ __forceinline__ void hist_group_count_body(PS sym, uint64_t n, uint32_t sigma, uint32_t L, uint32_t aligned,
+                                                      PH gcnt, PH tile_cnt0, PE err, uint64_t bid, uint64_t nblk) {
+  using TL = Tile<E>;
+  constexpr int EV = TL::EV, NCH = TL::NCH;
+  __shared__ uint32_t s_g[kHMaxWin];
+  const uint32_t tid = threadIdx.x, grp = tid / kBT, gt = tid % kBT, lane = tid & 63u;
+  const uint32_t G = (sigma + (1u << kHWinShift) - 1) >> kHWinShift;
+  for (uint32_t i = tid; i < G; i += kHT) s_g[i] = 0;
+  __syncthreads();
+  const uint64_t ntiles = (n + TL::T - 1) >> TL::TSHIFT;
+  const uint64_t tb = ntiles * bid / nblk, te = ntiles * (bid + 1) / nblk;
+  const uint64_t nit = (te - tb + kHG - 1) / kHG;
+  const uint32_t lsh = L - 1;
+  uint32_t bad = 0;
+  for (uint64_t it = 0; it < nit; ++it) {
+    const uint64_t t = tb + it * kHG + grp;
+    if (t < te) {  // uniform over the group's waves
+      const uint64_t t0 = t << TL::TSHIFT;
+      const uint32_t cnt = (uint32_t)min<uint64_t>(TL::T, n - t0);
+      uint32_t ones = 0;
+#pragma unroll 1
+      for (int k = 0; k < NCH; ++k) {
+        const uint32_t q0 = (uint32_t)(k * kBT + gt) * EV;
+        E v[EV];
+        load16<E>(sym + t0, q0, cnt, aligned && (q0 + EV <= cnt), v);
+#pragma unroll
+        for (int e = 0; e < EV; ++e) {
+          const uint32_t x = (uint32_t)v[e];
+          if (q0 + e < cnt) {
+            if (x < sigma) {
+              atomicAdd(&s_g[x >> kHWinShift], 1u);
+              ones += (x >> lsh) & 1u;
+            } else {
+              bad = 1;
+            }
+          }
+        }
+      }
+#pragma unroll
+      for (int off = 32; off > 0; off >>= 1) ones += __shfl_xor(ones, off, 64);
+      if (lane == 0 && ones) atomic_add_u64(tile_cnt0 + t, (uint64_t)ones);
+    }
+  }
+  __syncthreads();
+  for (uint32_t g = tid; g < G; g += kHT) gcnt[(uint64_t)g * nblk + bid] = s_g[g];
+  if (bid == 0 && tid == 0) gcnt[(uint64_t)G * nblk] = 0;  // so the scan's last entry is the total
+  if (bad) (void)__hip_atomic_fetch_or(err, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// goff: the exclusive scan of gcnt. Symbols >= sigma are skipped (the build fails on them).
+template <typename E, typename PS, typename PD>
+__device__ __forceinline__ void hist_group_scatter_body(PS sym, uint64_t n, uint32_t sigma, uint32_t aligned,
+                                                        const uint64_t* __restrict__ goff, PD dst, uint64_t bid,
+                                                        uint64_t nblk) {
+  using TL = Tile<E>;
+  constexpr int EV = TL::EV, NCH = TL::NCH;
+  __shared__ uint32_t s_cur[kHMaxWin];
+  const uint32_t tid = threadIdx.x, grp = tid / kBT, gt = tid % kBT;
+  const uint32_t G = (sigma + (1u << kHWinShift) - 1) >> kHWinShift;
+  // slots of a block stay below n < 2^40; cursors count from the block's first slot per window
+  __shared__ uint64_t s_base[kHMaxWin];
+  for (uint32_t g = tid; g < G; g += kHT) {
+    s_base[g] = goff[(uint64_t)g * nblk + bid];
+    s_cur[g] = 0;
+  }
+  __syncthreads();
+  const uint64_t ntiles = (n + TL::T - 1) >> TL::TSHIFT;
+  const uint64_t tb = ntiles * bid / nblk, te = ntiles * (bid + 1) / nblk;
+  const uint64_t nit = (te - tb + kHG - 1) / kHG;
+  for (uint64_t it = 0; it < nit; ++it) {
+    const uint64_t t = tb + it * kHG + grp;
+    if (t >= te) continue;
+    const uint64_t t0 = t << TL::TSHIFT;
+    const uint32_t cnt = (uint32_t)min<uint64_t>(TL::T, n - t0);
+#pragma unroll 1
+    for (int k = 0; k < NCH; ++k) {
+      const uint32_t q0 = (uint32_t)(k * kBT + gt) * EV;
+      E v[EV];
+      load16<E>(sym + t0, q0, cnt, aligned && (q0 + EV <= cnt), v);
+#pragma unroll
+      for (int e = 0; e < EV; ++e) {
+        const uint32_t x = (uint32_t)v[e];
+        if (q0 + e < cnt && x < sigma) {
+          const uint32_t g = x >> kHWinShift;
+          dst[s_base[g] + atomicAdd(&s_cur[g], 1u)] = (E)x;
+        }
+      }
+    }
+  }
+}
+
+// Window count over the window-ordered symbols src[0, total): block bid takes
+// [bid * kHWinChunk, (bid + 1) * kHWinChunk) and counts each window piece in it densely.
+template <typename E, typename PS, typename PH>
+__device__ __forceinline__ void hist_window_count_body(PS src, const uint64_t* __restrict__ goff, uint64_t nblk1,
+                                                       uint32_t sigma, PH hist, uint64_t bid) {
+  __shared__ uint32_t s_h[1u << kHWinShift];
+  const uint32_t tid = threadIdx.x;
+  const uint32_t G = (sigma + (1u << kHWinShift) - 1) >> kHWinShift;
+  const uint64_t total = goff[(uint64_t)G * nblk1];  // the scan's end entry: all valid symbols
+  const uint64_t lo = bid * kHWinChunk, hi = min(lo + kHWinChunk, total);
+  if (lo >= hi) return;  // whole block
+  uint32_t g = (uint32_t)src[lo] >> kHWinShift;
+  const uint32_t glast = (uint32_t)src[hi - 1] >> kHWinShift;
+  for (; g <= glast; ++g) {
+    const uint64_t a = max(lo, goff[(uint64_t)g * nblk1]);
+    const uint64_t b = min(hi, g + 1 < G ? goff[(uint64_t)(g + 1) * nblk1] : total);
+    const uint32_t w0 = g << kHWinShift;
+    for (uint32_t i = tid; i < (1u << kHWinShift); i += kHT) s_h[i] = 0;
+    __syncthreads();
+    for (uint64_t j = a + tid; j < b; j += kHT) atomicAdd(&s_h[(uint32_t)src[j] - w0], 1u);
+    __syncthreads();
+    for (uint32_t r = tid; r < (1u << kHWinShift); r += kHT) {
+      const uint32_t c = s_h[r];
+      if (c) atomic_add_u64(hist + w0 + r, (uint64_t)c);
+    }
+    __syncthreads();
+  }
+}
+
 // ---------------------------------------------------------------- node tables
 
 // Heap entry h (level l = floor(lg(h+1)), code prefix p = h + 1 - 2^l): follow p from the root with

@@ -79,6 +79,8 @@ CASES = [
     (4, 3, 100001, "alternate", 512, 512),
     (4, 1 << 20, 300000, "sparse", 512, 4096),
     (4, 70001, 4097, "uniform", 512, 4096),
+    (4, 1 << 24, 200000, "uniform", 512, 4096),   # 512 histogram windows of 2^15 symbols
+    (4, 1000003, 500000, "zipf12", 512, 4096),    # last window partly used
 ]
 
 
@@ -119,6 +121,19 @@ def test_symbol_out_of_range_is_reported():
     t = G.gpu_build(S[:12345].copy(), 10)
     G.compare_queries(t, S[:12345], 10, *G.random_queries(S[:12345], 10, 512, 9))
     t.free()
+
+
+@pytest.mark.parametrize("width,sigma", [(1, 10), (2, 40000), (4, 1 << 20)])
+def test_symbol_out_of_range_is_reported_every_histogram(width, sigma):
+    """Each histogram variant (replicated LDS counters, LDS windows, the windowed radix step for
+    alphabets above 2^16) flags a symbol >= sigma, and builds nothing."""
+    import paper_2505_03372_amd as wt
+    S = workloads.uniform(6, 300000, sigma, width)
+    S[299999] = sigma
+    G.log("out-of-range build w=%d sigma=%d" % (width, sigma))
+    with pytest.raises(wt.WTError) as ei:
+        G.gpu_build(S, sigma)
+    assert ei.value.status == wt.WT_ERR_SYMBOL_RANGE
 
 
 def test_unaligned_input_pointer():
