@@ -161,7 +161,7 @@ wt_status wt_build_profile(const wt_tree* t, wt_prof_entry* out, uint32_t cap, u
 wt_status wt_query_profiling(int on);
 wt_status wt_query_profile(wt_prof_entry* out, uint32_t cap, uint32_t* count);
 
-/* ---- learned select index (spec extension of Section 5.4; not in the thesis) ----
+/* ---- learned select index (an extension of Section 5.4; not in the thesis) ----
  *
  * For every child node of the tree (a node's zeros side or ones side at some level) a small FP32
  * network u -> 1 -> 16 -> 1 (ReLU) -> v maps the node-local occurrence rank of a bit (u in [0, 1],
@@ -234,7 +234,7 @@ wt_status wt_learned_model(const wt_tree* t, uint32_t slot, wt_learned_model_t* 
 wt_status wt_mlp_loss_grad(const float* d_params, const float* d_u, const float* d_v, uint32_t P, float* d_out,
                            wt_stream_t stream);
 
-/* ---- batched forest build (spec extension; the thesis builds one tree at a time) ----
+/* ---- batched forest build (an extension; the thesis builds one tree at a time) ----
  *
  * Many independent sequences of uneven length and alphabet are built into a forest of wavelet trees
  * by one launch of a captured HIP graph. Every construction phase of Section 5.1 (histogram,
@@ -333,16 +333,17 @@ wt_status wt_forest_free(wt_forest* f);
  *             WT_OP_SELECT_LEARNED: accepted and answered as WT_OP_SELECT (the learned index is
  *                           not used inside mixed batches; wt_select_learned uses it)
  * with the results and sentinels of wt_access / wt_rank / wt_select, widened to 64 bits in d_out[j].
- * An unknown tree or op gives UINT64_MAX. Batches above 2048 queries are grouped by (op, |L2| of the
- * tree) on the device so that each wavefront runs one traversal; d_out is in the order of the
- * queries. d_sym may be NULL when every op is an access. At most 2^32 - 1 queries per call.
+ * An unknown tree or op gives UINT64_MAX. Batches above 16384 queries are grouped by (op, |L2| of the
+ * tree) on the device so that each wavefront runs one traversal, and from 2^16 queries also by
+ * place (tree and position in it) so that a wavefront's traversals share lines; d_out is in the
+ * order of the queries. d_sym may be NULL when every op is an access. At most 2^32 - 1 queries per call.
  */
 enum { WT_OP_ACCESS = 0, WT_OP_RANK = 1, WT_OP_SELECT = 2, WT_OP_SELECT_LEARNED = 3 };
 
 wt_status wt_query_mixed(const wt_forest* f, const uint32_t* d_tree, const uint8_t* d_op, const uint32_t* d_sym,
                          const uint64_t* d_arg, uint64_t q, uint64_t* d_out, wt_stream_t stream);
 
-/* ---- serving (spec extension): continuous batching over a resident forest ----
+/* ---- serving (an extension): continuous batching over a resident forest ----
  *
  * A server keeps a forest resident and replays a trace of query batches (requests) on its own clock:
  * a request becomes visible at its arrival time and is admitted in arrival order as soon as one of

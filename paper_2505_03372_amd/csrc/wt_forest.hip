@@ -177,7 +177,7 @@ struct QTree {
 // learned index is a plain select); kMixInvalid for an unknown tree or op.
 constexpr uint32_t kMixInvalid = 16;
 constexpr uint32_t kMixClasses = 17;
-constexpr uint64_t kMixDirectMax = 2048;    // batches up to this size skip the binning
+constexpr uint64_t kMixDirectMax = 16384;   // batches up to this size skip the binning
 constexpr uint32_t kMixChunk = kQT * 16;    // queries per class-sort block
 constexpr uint64_t kMixSortMin = 1ull << 16;  // batches from this size are sorted by (class, position)
 constexpr uint32_t kMixB = 2048;            // position buckets per class in that sort

@@ -122,7 +122,7 @@ def _mixed_reference(f, seqs, tree, op, sym, arg):
     return out
 
 
-@pytest.mark.parametrize("q", [5001, 200003])  # class-sorted below 2^16 queries, (class, position)-sorted above
+@pytest.mark.parametrize("q", [3001, 30001, 200003])  # one kernel up to 16384, class-sorted below 2^16, sorted by (class, position) above
 def test_mixed_queries_match_per_tree_calls(small_forest, q):
     f, seqs = small_forest
     T = len(seqs)

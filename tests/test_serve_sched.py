@@ -18,7 +18,7 @@ def _mixed_scratch(q):
     """Device scratch of one mixed batch (class offsets; then class counts and classes below 2^16
     queries, else bucket ids, the sort passes and the bucket starts; then the slot order)."""
     r = lambda x: (x + 255) // 256 * 256  # noqa: E731
-    if q <= 2048:
+    if q <= 16384:
         return 0
     if q < 1 << 16:
         return r(4 * 18) + r(4 * 64) + r(q) + r(4 * q)
