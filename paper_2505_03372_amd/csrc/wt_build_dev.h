@@ -199,7 +199,11 @@ __device__ __forceinline__ void fill_body(uint64_t* __restrict__ p, uint64_t n, 
 // ---------------------------------------------------------------- loads
 
 // Loads elements [q0, q0 + EV) of a tile into v; elements at or beyond cnt read as 0. `vec` says the
-// 16 bytes starting at q0 may be read as one vector (aligned and inside the buffer).
+// 16 bytes starting at q0 may be read as one vector (aligned and inside the buffer). A vector that
+// lies inside the tile but starts off a 16-byte boundary is read as the two aligned 16-byte blocks it
+// spans (both hold bytes of the sequence, so neither leaves its pages) and funnel-shifted. `base`
+// must be the same for every lane of the wave (tile offsets q0 * sizeof(E) are multiples of 16, so the
+// misalignment is then wave-uniform and picks its shift with scalar branches).
 template <typename E, typename P>
 __device__ __forceinline__ void load16(P base, uint32_t q0, uint32_t cnt, bool vec, E (&v)[16 / sizeof(E)]) {
   constexpr int EV = 16 / (int)sizeof(E);
@@ -211,10 +215,34 @@ __device__ __forceinline__ void load16(P base, uint32_t q0, uint32_t cnt, bool v
       for (int e = 0; e < EV; ++e)
         if (q0 + e >= cnt) v[e] = 0;
     }
-  } else {
-#pragma unroll
-    for (int e = 0; e < EV; ++e) v[e] = (q0 + e < cnt) ? base[q0 + e] : (E)0;
+    return;
   }
+  const uint32_t m = (uint32_t)((uintptr_t)(base + q0) & 15u);
+  if (q0 + EV <= cnt && m != 0) {
+    const auto blk = pcast<const u32x4>(pcast<const char>(base + q0) - m);
+    const u32x4 x0 = blk[0], x1 = blk[1];
+    const uint32_t d[8] = {x0.x, x0.y, x0.z, x0.w, x1.x, x1.y, x1.z, x1.w};
+    const uint32_t mu = (uint32_t)__builtin_amdgcn_readfirstlane((int)m);
+    const uint32_t sh = mu & 3u;
+    uint32_t y[4];
+    switch (mu >> 2) {
+#define WT_FUNNEL(K)                                                                     \
+  case K:                                                                                \
+    for (int i = 0; i < 4; ++i) y[i] = __builtin_amdgcn_alignbyte(d[i + K + 1], d[i + K], sh); \
+    break;
+      WT_FUNNEL(0)
+      WT_FUNNEL(1)
+      WT_FUNNEL(2)
+      default:
+        for (int i = 0; i < 4; ++i) y[i] = __builtin_amdgcn_alignbyte(d[i + 4], d[i + 3], sh);
+        break;
+#undef WT_FUNNEL
+    }
+    __builtin_memcpy(v, y, 16);
+    return;
+  }
+#pragma unroll
+  for (int e = 0; e < EV; ++e) v[e] = (q0 + e < cnt) ? base[q0 + e] : (E)0;
 }
 
 // Element e of a 16-byte vector of E (e a compile-time constant after unrolling).
@@ -1013,6 +1041,7 @@ __global__ __launch_bounds__(kBT, (level_waves<E, kForest>())) void k_level(Leve
   __shared__ uint64_t s_node[2];  // node of the tile's first and last element
   __shared__ uint64_t s_dst[2];   // single-node tile: destinations of its first zero and first one
   __shared__ uint32_t s_nc[4];    // single-node tile: next-level ones per (run, destination tile)
+  __shared__ uint2 s_enc[32];     // level 0 of a reduced alphabet: (high code bits, shift) by h
 
   const uint32_t tid = threadIdx.x, lane = tid & 63u;
   const uint32_t l = a.l, L = a.L;
@@ -1029,6 +1058,22 @@ __global__ __launch_bounds__(kBT, (level_waves<E, kForest>())) void k_level(Leve
   const uint32_t bsh = L - 1 - l;
   if (tid == 0) s_nseg = 0;
 
+  // The reduced code of a symbol c depends on h, the highest bit where c and sigma differ: it is the
+  // j1 = popc(sigma >> (h+1)) leading ones (the right steps taken before c's subtree), then c's low h
+  // bits placed so that the code has its length len(h), left-aligned to L bits. One table entry per h.
+  if (a.encode) {
+    if (tid < 32) {
+      const uint32_t h = tid, sg = a.sigma;
+      const uint32_t j1 = h < 31 ? (uint32_t)__popc(sg >> (h + 1)) : 0u;
+      const uint32_t len = j1 + ((sg & ((1u << h) - 1u)) == 0u ? 0u : 1u) + h;
+      uint2 te;
+      te.x = (len <= L && j1) ? ((1u << j1) - 1u) << (L - j1) : 0u;
+      te.y = len <= L ? L - len : 0u;
+      s_enc[h] = te;
+    }
+    __syncthreads();
+  }
+
   // 1. load, encode (level 0 of a reduced alphabet), bit words
   const WT_GLOBAL E* in = pcast<const E>(a.in) + t0;
   uint4 vx[NCH];
@@ -1042,8 +1087,9 @@ __global__ __launch_bounds__(kBT, (level_waves<E, kForest>())) void k_level(Leve
       for (int e = 0; e < EV; ++e) {
         uint32_t s = (uint32_t)v[e];
         if (s >= a.sigma) s = 0;  // out-of-range input: the build reports an error; keep indices valid
-        uint32_t len;
-        v[e] = (E)encode_sym(s, a.sigma, L, a.pow2, &len);
+        const uint32_t h = 31u - (uint32_t)__clz(s ^ a.sigma);
+        const uint2 te = s_enc[h];
+        v[e] = (E)(te.x | ((s & ((1u << h) - 1u)) << te.y));
       }
     }
     __builtin_memcpy(&vx[k], v, 16);
