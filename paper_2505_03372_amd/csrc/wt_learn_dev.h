@@ -15,6 +15,12 @@ namespace wt {
 constexpr int kH = 16;           // hidden units
 constexpr int kNP = 3 * kH + 1;  // parameters: w1[16], b1[16], w2[16], b2
 
+// L2 blocks the correction's group starts below the predicted block (rounded down to a vector).
+#ifndef WT_LEARN_LEAD
+#define WT_LEARN_LEAD 6
+#endif
+constexpr uint64_t kLearnLead = WT_LEARN_LEAD;
+
 // Query form of a trained model. With one input, the network is linear between the points where a
 // hidden unit switches on or off (u = -b1_k / w1_k), so on [0, 1] it is exactly a piecewise-linear
 // function with at most 16 switch points: they are stored ascending (unused: 2, above every input)
@@ -93,7 +99,7 @@ __device__ __forceinline__ uint64_t select_learned_at(const TreeDev& d, const Le
   constexpr uint64_t kPer = kL1Bits >> L2S;
   static_assert(GN <= kPer, "group inside an L1 block");
   const uint64_t jb0 = B0 & ~(kPer - 1);
-  const uint64_t gbase = min(max(jb0, (B0 > GN / 2 ? B0 - GN / 2 : 0ull) & ~7ull), jb0 + kPer - GN);
+  const uint64_t gbase = min(max(jb0, (B0 > kLearnLead ? B0 - kLearnLead : 0ull) & ~7ull), jb0 + kPer - GN);
   const uint64_t glo = max(gbase, Blo), ghi = min(gbase + GN - 1, Bhi);
   const uint64_t l1v = d.L1[m.l1 + ((gbase << L2S) >> kL1Shift)];
   const uint4* gp = reinterpret_cast<const uint4*>(d.L2 + m.l2 + gbase);
@@ -113,9 +119,11 @@ __device__ __forceinline__ uint64_t select_learned_at(const TreeDev& d, const Le
   const uint64_t nL2 = (m.n + (1ull << L2S) - 1) >> L2S;
   const uint32_t ehi = gbase + GN <= nL2 ? GN - 1 : (uint32_t)(ghi - gbase);
   int32_t off = 0;
-  uint32_t below = 0;
+  uint32_t below = 0, seen = 0;
   int32_t ylast = 0;  // y of the last block below the target
-#pragma unroll 2
+  // one vector at a time from a little below the prediction: a lane stops at the first vector that
+  // ends the prefix or reaches ghi
+#pragma unroll 1
   for (uint32_t v = 0; v < GN / 8; ++v) {
     const uint4 x = gp[v];
 #pragma unroll
@@ -128,6 +136,8 @@ __device__ __forceinline__ uint64_t select_learned_at(const TreeDev& d, const Le
       ylast = lt ? y : ylast;
       off += step;
     }
+    seen += 8;
+    if (below < seen || gbase + seen - 1 >= ghi) break;
   }
   // blocks gbase .. gbase + below - 1 are below the target; count from glo as the search expects
   below = below > (uint32_t)(glo - gbase) ? below - (uint32_t)(glo - gbase) : 0u;
