@@ -136,15 +136,21 @@ def test_symbol_out_of_range_is_reported_every_histogram(width, sigma):
     assert ei.value.status == wt.WT_ERR_SYMBOL_RANGE
 
 
-def test_unaligned_input_pointer():
+@pytest.mark.parametrize("width,sigma,shift", [(1, 7, 1), (1, 200, 13), (2, 1000, 1), (2, 40000, 5), (2, 7, 7),
+                                               (4, 3000, 1), (4, 3000, 3), (4, 1 << 20, 2)])
+def test_unaligned_input_pointer(width, sigma, shift):
+    """Symbols starting `shift` elements past a 16-byte boundary: every vector of the histogram and of
+    level 0 is read across two aligned blocks (each funnel shift; non-power-of-two alphabets take
+    the reduced codes of level 0)."""
     import torch
     import paper_2505_03372_amd as wt
-    S = workloads.uniform(77, 70001, 7, 1)
-    d = torch.from_numpy(np.concatenate([np.zeros(1, np.uint8), S])).cuda()[1:]
-    assert d.data_ptr() % 16 != 0
-    G.log("unaligned input build")
-    t = wt.build(d, 7)
-    G.compare_structure(t, oracle.OracleTree(S, 7))
+    n = 70001
+    S = workloads.uniform(77 + shift, n, sigma, width)
+    d = torch.from_numpy(np.concatenate([np.zeros(shift, dtype=S.dtype), S])).cuda()[shift:]
+    assert d.data_ptr() % 16 == (shift * width) % 16 != 0
+    G.log("unaligned input build w=%d sigma=%d shift=%d" % (width, sigma, shift))
+    t = wt.build(d, sigma)
+    G.compare_structure(t, oracle.OracleTree(S, sigma))
     t.free()
 
 
