@@ -456,6 +456,10 @@ def tune_bucket(n: int, sigma: int):
     return nb, sb
 
 
+_SEQ_DESC_NP = np.dtype([("d_sym", "<u8"), ("n", "<u8"), ("sigma", "<u8"), ("l2_bits", "<u4"),
+                         ("sample_rate", "<u4")])
+
+
 def _descs(seqs, sigmas, l2_bits=None, sample_rates=None):
     if len(seqs) == 0 or len(seqs) != len(sigmas):
         raise ValueError("need one sigma per sequence")
@@ -463,15 +467,22 @@ def _descs(seqs, sigmas, l2_bits=None, sample_rates=None):
     dt = seqs[0].dtype
     if dt not in dts:
         raise TypeError("symbols must be uint8, uint16 or uint32 (got %s)" % dt)
+    # one pass per property (a single pass reading several properties of each view is much slower)
+    bad = [j for j, d in enumerate([x.dtype for x in seqs]) if d != dt]
+    bad += [j for j, c in enumerate([x.is_cuda for x in seqs]) if not c]
+    bad += [j for j, c in enumerate([x.is_contiguous() for x in seqs]) if not c]
+    if bad:
+        raise ValueError("sequence %d: contiguous device tensor of %s expected" % (min(bad), dt))
+    ns = np.array([x.numel() for x in seqs], dtype=np.uint64)
+    ptrs = np.array([x.data_ptr() for x in seqs], dtype=np.uint64)
     descs = (SeqDesc * len(seqs))()
-    for j, x in enumerate(seqs):
-        if x.dtype != dt or not x.is_cuda or not x.is_contiguous():
-            raise ValueError("sequence %d: contiguous device tensor of %s expected" % (j, dt))
-        descs[j].d_sym = x.data_ptr() if x.numel() else 0
-        descs[j].n = x.numel()
-        descs[j].sigma = int(sigmas[j])
-        descs[j].l2_bits = int(l2_bits[j]) if l2_bits is not None else 0
-        descs[j].sample_rate = int(sample_rates[j]) if sample_rates is not None else 0
+    assert ctypes.sizeof(SeqDesc) == _SEQ_DESC_NP.itemsize
+    arr = np.frombuffer(descs, dtype=_SEQ_DESC_NP)
+    arr["d_sym"] = np.where(ns > 0, ptrs, 0)
+    arr["n"] = ns
+    arr["sigma"] = np.asarray(sigmas, dtype=np.uint64)
+    arr["l2_bits"] = np.asarray(l2_bits, dtype=np.uint32) if l2_bits is not None else 0
+    arr["sample_rate"] = np.asarray(sample_rates, dtype=np.uint32) if sample_rates is not None else 0
     return descs, dts[dt]
 
 
