@@ -213,6 +213,7 @@ def main_forest(args, torch, wt, workloads, dev):
         "rates": {"forest_build_symbols_per_s": n_total / fb, "forest_build_ms": fb * 1e3,
                   "forest_graph_ms": gms, "forest_plan_ms": float(np.median([r["info"]["plan_ms"] for r in recs])),
                   "forest_capture_ms": float(np.median([r["info"]["capture_ms"] for r in recs])),
+                  "forest_library_ms": float(np.median([r["info"]["total_ms"] for r in recs])),
                   "forest_graph_kernels": recs[0]["info"]["graph_kernels"],
                   "mixed_queries_per_s": q / fq, "mixed_ms": fq * 1e3,
                   "plain_build_symbols_per_s": n_total / pb, "plain_build_ms": pb * 1e3,

@@ -262,7 +262,14 @@ class Tree:
         self._h = ctypes.c_void_p(handle)
         self._keep = keepalive
         self._borrowed = borrowed
-        self.info = self._info()
+        self._inf = None
+
+    @property
+    def info(self) -> dict:
+        """Sizes and layout of the tree (read from the library on first use)."""
+        if self._inf is None:
+            self._inf = self._info()
+        return self._inf
 
     @property
     def handle(self):
