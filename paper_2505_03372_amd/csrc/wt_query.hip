@@ -26,38 +26,65 @@ namespace wt {
 // perm: NULL, or the queries in binned order: slot j runs query perm[j] (its arguments are read and its
 // answer written at that index).
 template <int L2S>
-__global__ __launch_bounds__(kQT) void k_access(QArgs a, const uint64_t* __restrict__ pos, uint64_t q,
-                                                uint32_t* __restrict__ out, const uint32_t* __restrict__ perm) {
+__global__ __launch_bounds__(kQB) void k_access(QArgs a, const uint64_t* __restrict__ pos, uint64_t q,
+                                                uint32_t* __restrict__ out, const uint32_t* __restrict__ perm,
+                                                uint32_t subshift) {
   __shared__ LevelMeta s_meta[WT_MAX_LEVELS];
+  __shared__ LocalOrder s_ord;
   load_meta(a, s_meta);
-  for (uint64_t j = xcd_block() * kQT + threadIdx.x; j < q; j += (uint64_t)gridDim.x * kQT) {
-    const uint64_t jj = perm ? perm[j] : j;
-    out[jj] = access_one<L2S>(a, s_meta, pos[jj]);
+  if (perm) {
+    for (uint64_t j0 = xcd_block() * kQB; j0 < q; j0 += (uint64_t)gridDim.x * kQB) {
+      uint32_t jj, c;
+      uint64_t x;
+      if (local_order<0>(a, nullptr, pos, perm, q, j0 + threadIdx.x, subshift, s_ord, jj, c, x))
+        out[jj] = access_one<L2S>(a, s_meta, x);
+    }
+    return;
   }
+  for (uint64_t j = xcd_block() * kQB + threadIdx.x; j < q; j += (uint64_t)gridDim.x * kQB)
+    out[j] = access_one<L2S>(a, s_meta, pos[j]);
 }
 
 template <int L2S>
-__global__ __launch_bounds__(kQT) void k_rank(QArgs a, const uint32_t* __restrict__ sym,
+__global__ __launch_bounds__(kQB) void k_rank(QArgs a, const uint32_t* __restrict__ sym,
                                               const uint64_t* __restrict__ pos, uint64_t q,
-                                              uint64_t* __restrict__ out, const uint32_t* __restrict__ perm) {
+                                              uint64_t* __restrict__ out, const uint32_t* __restrict__ perm,
+                                              uint32_t subshift) {
   __shared__ LevelMeta s_meta[WT_MAX_LEVELS];
+  __shared__ LocalOrder s_ord;
   load_meta(a, s_meta);
-  for (uint64_t j = xcd_block() * kQT + threadIdx.x; j < q; j += (uint64_t)gridDim.x * kQT) {
-    const uint64_t jj = perm ? perm[j] : j;
-    out[jj] = rank_one<L2S>(a, s_meta, sym[jj], pos[jj]);
+  if (perm) {
+    for (uint64_t j0 = xcd_block() * kQB; j0 < q; j0 += (uint64_t)gridDim.x * kQB) {
+      uint32_t jj, c;
+      uint64_t x;
+      if (local_order<1>(a, sym, pos, perm, q, j0 + threadIdx.x, subshift, s_ord, jj, c, x))
+        out[jj] = rank_one<L2S>(a, s_meta, c, x);
+    }
+    return;
   }
+  for (uint64_t j = xcd_block() * kQB + threadIdx.x; j < q; j += (uint64_t)gridDim.x * kQB)
+    out[j] = rank_one<L2S>(a, s_meta, sym[j], pos[j]);
 }
 
 template <int L2S>
-__global__ __launch_bounds__(kQT, 8) void k_select(QArgs a, const uint32_t* __restrict__ sym,
+__global__ __launch_bounds__(kQB, 8) void k_select(QArgs a, const uint32_t* __restrict__ sym,
                                                 const uint64_t* __restrict__ kin, uint64_t q,
-                                                uint64_t* __restrict__ out, const uint32_t* __restrict__ perm) {
+                                                uint64_t* __restrict__ out, const uint32_t* __restrict__ perm,
+                                              uint32_t subshift) {
   __shared__ LevelMeta s_meta[WT_MAX_LEVELS];
+  __shared__ LocalOrder s_ord;
   load_meta(a, s_meta);
-  for (uint64_t j = xcd_block() * kQT + threadIdx.x; j < q; j += (uint64_t)gridDim.x * kQT) {
-    const uint64_t jj = perm ? perm[j] : j;
-    out[jj] = select_one<L2S>(a, s_meta, sym[jj], kin[jj]);
+  if (perm) {
+    for (uint64_t j0 = xcd_block() * kQB; j0 < q; j0 += (uint64_t)gridDim.x * kQB) {
+      uint32_t jj, c;
+      uint64_t x;
+      if (local_order<2>(a, sym, kin, perm, q, j0 + threadIdx.x, subshift, s_ord, jj, c, x))
+        out[jj] = select_one<L2S>(a, s_meta, c, x);
+    }
+    return;
   }
+  for (uint64_t j = xcd_block() * kQB + threadIdx.x; j < q; j += (uint64_t)gridDim.x * kQB)
+    out[j] = select_one<L2S>(a, s_meta, sym[j], kin[j]);
 }
 
 // ---------------------------------------------------------------- per-kernel timing
@@ -100,17 +127,29 @@ constexpr uint32_t kBinT = 1024;                // threads of the counting and s
 constexpr uint32_t kBinChunk = kBinT * 256;     // queries per block
 constexpr uint64_t kSortMinQ = 1ull << 16;
 
-__device__ __forceinline__ uint64_t sort_key(const QArgs& a, int kind, uint32_t c, uint64_t x) {
-  if (kind != 2) return min(x, a.n);  // access, rank: the position
-  if (x == 0 || c >= a.sigma) return a.n;
-  const uint64_t lo = a.d.cum[c], cnt = a.d.cum[c + 1] - lo;
-  return x > cnt ? a.n : lo + x - 1;  // select: rank of the occurrence in symbol order
-}
+// Each thread takes kBinU queries of its chunk per round (kBinT apart, so every load is coalesced)
+// and issues all their loads before it uses any: with one 1024-thread block per CU, a round of one
+// query per thread would leave the passes waiting on one load chain at a time.
+constexpr uint32_t kBinU = 8;
+constexpr uint32_t kBinNone = 0xFFFFFFFFu;  // slot past the batch
 
 template <int KIND>
-__device__ __forceinline__ uint32_t sort_bin(const QArgs& a, const uint32_t* __restrict__ sym,
-                                             const uint64_t* __restrict__ arg, uint64_t j, uint32_t shift) {
-  return (uint32_t)min<uint64_t>(sort_key(a, KIND, KIND ? sym[j] : 0u, arg[j]) >> shift, kBins - 1);
+__device__ __forceinline__ void bin_round(const QArgs& a, const uint32_t* __restrict__ sym,
+                                          const uint64_t* __restrict__ arg, uint64_t q, uint32_t shift, uint64_t j0,
+                                          uint32_t (&bin)[kBinU]) {
+  uint64_t x[kBinU];
+  uint32_t c[kBinU];
+#pragma unroll
+  for (uint32_t u = 0; u < kBinU; ++u) {
+    const uint64_t j = j0 + (uint64_t)u * kBinT;
+    x[u] = j < q ? arg[j] : 0;
+    c[u] = (KIND && j < q) ? sym[j] : 0u;
+  }
+#pragma unroll
+  for (uint32_t u = 0; u < kBinU; ++u) {
+    const uint64_t j = j0 + (uint64_t)u * kBinT;
+    bin[u] = j < q ? (uint32_t)min<uint64_t>(sort_key(a, KIND, c[u], x[u]) >> shift, kBins - 1) : kBinNone;
+  }
 }
 
 template <int KIND>
@@ -121,24 +160,34 @@ __global__ __launch_bounds__(kBinT) void k_bin_count(QArgs a, const uint32_t* __
   for (uint32_t b = threadIdx.x; b < kBins; b += kBinT) h[b] = 0;
   __syncthreads();
   const uint64_t c0 = (uint64_t)blockIdx.x * kBinChunk;
-  for (uint32_t i = threadIdx.x; i < kBinChunk; i += kBinT) {
-    const uint64_t j = c0 + i;
-    if (j < q) atomicAdd(&h[sort_bin<KIND>(a, sym, arg, j, shift)], 1u);
+  for (uint32_t i = threadIdx.x; i < kBinChunk; i += kBinT * kBinU) {
+    uint32_t bin[kBinU];
+    bin_round<KIND>(a, sym, arg, q, shift, c0 + i, bin);
+#pragma unroll
+    for (uint32_t u = 0; u < kBinU; ++u)
+      if (bin[u] != kBinNone) atomicAdd(&h[bin[u]], 1u);
   }
   __syncthreads();
   for (uint32_t b = threadIdx.x; b < kBins; b += kBinT) bhist[(uint64_t)blockIdx.x * kBins + b] = h[b];
 }
 
-// Per bucket: exclusive prefix over the blocks (in place) and the bucket total.
+// Per bucket: exclusive prefix over the blocks (in place) and the bucket total. The column is read
+// 16 entries at a time (loads issued together) before they are rewritten.
 __global__ __launch_bounds__(kQT) void k_bin_offsets(uint32_t* __restrict__ bhist, uint32_t nblk,
                                                      uint32_t* __restrict__ tot) {
+  constexpr uint32_t R = 16;
   const uint32_t b = blockIdx.x * kQT + threadIdx.x;
   if (b >= kBins) return;
   uint32_t run = 0;
-  for (uint32_t k = 0; k < nblk; ++k) {
-    const uint32_t v = bhist[(uint64_t)k * kBins + b];
-    bhist[(uint64_t)k * kBins + b] = run;
-    run += v;
+  for (uint32_t k0 = 0; k0 < nblk; k0 += R) {
+    uint32_t v[R];
+#pragma unroll
+    for (uint32_t r = 0; r < R; ++r) v[r] = k0 + r < nblk ? bhist[(uint64_t)(k0 + r) * kBins + b] : 0u;
+#pragma unroll
+    for (uint32_t r = 0; r < R; ++r) {
+      if (k0 + r < nblk) bhist[(uint64_t)(k0 + r) * kBins + b] = run;
+      run += v[r];
+    }
   }
   tot[b] = run;
 }
@@ -181,11 +230,12 @@ __global__ __launch_bounds__(kBinT) void k_bin_scatter(QArgs a, const uint32_t* 
   for (uint32_t b = threadIdx.x; b < kBins; b += kBinT) cur[b] = base[b] + bhist[(uint64_t)blockIdx.x * kBins + b];
   __syncthreads();
   const uint64_t c0 = (uint64_t)blockIdx.x * kBinChunk;
-  for (uint32_t i = threadIdx.x; i < kBinChunk; i += kBinT) {
-    const uint64_t j = c0 + i;
-    if (j >= q) continue;
-    const uint32_t s = atomicAdd(&cur[sort_bin<KIND>(a, sym, arg, j, shift)], 1u);
-    perm[s] = (uint32_t)j;
+  for (uint32_t i = threadIdx.x; i < kBinChunk; i += kBinT * kBinU) {
+    uint32_t bin[kBinU];
+    bin_round<KIND>(a, sym, arg, q, shift, c0 + i, bin);
+#pragma unroll
+    for (uint32_t u = 0; u < kBinU; ++u)
+      if (bin[u] != kBinNone) perm[atomicAdd(&cur[bin[u]], 1u)] = (uint32_t)(c0 + i + u * kBinT);
   }
 }
 
@@ -197,9 +247,16 @@ __global__ __launch_bounds__(kBinT) void k_bin_count_ids(const uint16_t* __restr
   for (uint32_t b = threadIdx.x; b < kBins; b += kBinT) h[b] = 0;
   __syncthreads();
   const uint64_t c0 = (uint64_t)blockIdx.x * kBinChunk;
-  for (uint32_t i = threadIdx.x; i < kBinChunk; i += kBinT) {
-    const uint64_t j = c0 + i;
-    if (j < q) atomicAdd(&h[ids[j]], 1u);
+  for (uint32_t i = threadIdx.x; i < kBinChunk; i += kBinT * kBinU) {
+    uint32_t id[kBinU];
+#pragma unroll
+    for (uint32_t u = 0; u < kBinU; ++u) {
+      const uint64_t j = c0 + i + u * kBinT;
+      id[u] = j < q ? (uint32_t)ids[j] : kBinNone;
+    }
+#pragma unroll
+    for (uint32_t u = 0; u < kBinU; ++u)
+      if (id[u] != kBinNone) atomicAdd(&h[id[u]], 1u);
   }
   __syncthreads();
   for (uint32_t b = threadIdx.x; b < kBins; b += kBinT) bhist[(uint64_t)blockIdx.x * kBins + b] = h[b];
@@ -213,10 +270,16 @@ __global__ __launch_bounds__(kBinT) void k_bin_scatter_ids(const uint16_t* __res
   for (uint32_t b = threadIdx.x; b < kBins; b += kBinT) cur[b] = base[b] + bhist[(uint64_t)blockIdx.x * kBins + b];
   __syncthreads();
   const uint64_t c0 = (uint64_t)blockIdx.x * kBinChunk;
-  for (uint32_t i = threadIdx.x; i < kBinChunk; i += kBinT) {
-    const uint64_t j = c0 + i;
-    if (j >= q) continue;
-    perm[atomicAdd(&cur[ids[j]], 1u)] = (uint32_t)j;
+  for (uint32_t i = threadIdx.x; i < kBinChunk; i += kBinT * kBinU) {
+    uint32_t id[kBinU];
+#pragma unroll
+    for (uint32_t u = 0; u < kBinU; ++u) {
+      const uint64_t j = c0 + i + u * kBinT;
+      id[u] = j < q ? (uint32_t)ids[j] : kBinNone;
+    }
+#pragma unroll
+    for (uint32_t u = 0; u < kBinU; ++u)
+      if (id[u] != kBinNone) perm[atomicAdd(&cur[id[u]], 1u)] = (uint32_t)(c0 + i + u * kBinT);
   }
 }
 
@@ -256,6 +319,7 @@ wt_status sort_batch(const wt_tree* t, const QArgs& a, int kind, const uint32_t*
   uint32_t bits = 0;
   while ((1ull << bits) < a.n + 1) ++bits;
   const uint32_t shift = bits > 15 ? bits - 15 : 0;
+  sb.subshift = shift > kQBBits ? shift - kQBBits : 0;
   qprof_begin("sort_count", st);
   if (kind == 0) hipLaunchKernelGGL(k_bin_count<0>, dim3(nblk), dim3(kBinT), 0, st, a, sym, arg, q, shift, bhist);
   else if (kind == 1) hipLaunchKernelGGL(k_bin_count<1>, dim3(nblk), dim3(kBinT), 0, st, a, sym, arg, q, shift, bhist);
@@ -301,10 +365,10 @@ extern "C" wt_status wt_access(const wt_tree* t, const uint64_t* d_pos, uint64_t
   if (rc != WT_OK) return rc;
   qprof_begin("access", st);
   if (binned) {
-    WT_DISPATCH_L2(t->l2_bits, k_access, a, d_pos, q, d_out, (const uint32_t*)sb.perm);
+    WT_DISPATCH_L2(t->l2_bits, k_access, a, d_pos, q, d_out, (const uint32_t*)sb.perm, sb.subshift);
     dev_free(sb.block, st);
   } else {
-    WT_DISPATCH_L2(t->l2_bits, k_access, a, d_pos, q, d_out, (const uint32_t*)nullptr);
+    WT_DISPATCH_L2(t->l2_bits, k_access, a, d_pos, q, d_out, (const uint32_t*)nullptr, 0u);
   }
   qprof_end(st);
   WT_HIP(hipGetLastError());
@@ -326,10 +390,10 @@ extern "C" wt_status wt_rank(const wt_tree* t, const uint32_t* d_sym, const uint
   if (rc != WT_OK) return rc;
   qprof_begin("rank", st);
   if (binned) {
-    WT_DISPATCH_L2(t->l2_bits, k_rank, a, d_sym, d_pos, q, d_out, (const uint32_t*)sb.perm);
+    WT_DISPATCH_L2(t->l2_bits, k_rank, a, d_sym, d_pos, q, d_out, (const uint32_t*)sb.perm, sb.subshift);
     dev_free(sb.block, st);
   } else {
-    WT_DISPATCH_L2(t->l2_bits, k_rank, a, d_sym, d_pos, q, d_out, (const uint32_t*)nullptr);
+    WT_DISPATCH_L2(t->l2_bits, k_rank, a, d_sym, d_pos, q, d_out, (const uint32_t*)nullptr, 0u);
   }
   qprof_end(st);
   WT_HIP(hipGetLastError());
@@ -351,10 +415,10 @@ extern "C" wt_status wt_select(const wt_tree* t, const uint32_t* d_sym, const ui
   if (rc != WT_OK) return rc;
   qprof_begin("select", st);
   if (binned) {
-    WT_DISPATCH_L2(t->l2_bits, k_select, a, d_sym, d_k, q, d_out, (const uint32_t*)sb.perm);
+    WT_DISPATCH_L2(t->l2_bits, k_select, a, d_sym, d_k, q, d_out, (const uint32_t*)sb.perm, sb.subshift);
     dev_free(sb.block, st);
   } else {
-    WT_DISPATCH_L2(t->l2_bits, k_select, a, d_sym, d_k, q, d_out, (const uint32_t*)nullptr);
+    WT_DISPATCH_L2(t->l2_bits, k_select, a, d_sym, d_k, q, d_out, (const uint32_t*)nullptr, 0u);
   }
   qprof_end(st);
   WT_HIP(hipGetLastError());

@@ -282,6 +282,80 @@ __device__ __forceinline__ uint64_t xcd_block() {
   return (uint64_t)(b % kXcd) * (g / kXcd) + b / kXcd;
 }
 
+// Binning key of a query: access and rank, the position; select, the rank of the wanted occurrence
+// in symbol order (cum[c] + k - 1). Invalid queries key n.
+__device__ __forceinline__ uint64_t sort_key(const QArgs& a, int kind, uint32_t c, uint64_t x) {
+  if (kind != 2) return min(x, a.n);
+  if (x == 0 || c >= a.sigma) return a.n;
+  const uint64_t lo = a.d.cum[c], cnt = a.d.cum[c + 1] - lo;
+  return x > cnt ? a.n : lo + x - 1;
+}
+
+// Threads per block of the access / rank / select traversal kernels.
+#ifndef WT_QB
+#define WT_QB 1024
+#endif
+constexpr uint32_t kQB = WT_QB;
+constexpr uint32_t kQBBits = kQB == 1024 ? 10 : kQB == 512 ? 9 : 8;
+static_assert((1u << kQBBits) == kQB, "traversal block: 256, 512 or 1024 threads");
+
+// A binned launch takes kQB consecutive slots per block and round, which lie in one or two buckets.
+// A counting sort in LDS by the next kQBBits key bits below the bucket gives each wave queries whose
+// answers are close together, so the lanes of one load instruction share lines (not only the caches
+// do); the larger the block, the narrower the key range of a wave.
+struct LocalOrder {
+  uint32_t cnt[kQB];  // one sub-bucket counter per thread
+  uint32_t wsum[kQB / 64];
+  uint32_t id[kQB];
+  uint32_t sym[kQB];
+  uint64_t arg[kQB];
+};
+
+// Slot j of the binned order (perm), reordered inside the block: returns false for a lane past the
+// batch, else the query index jj and its arguments (c, x). Called by every thread of the block.
+template <int KIND>
+__device__ __forceinline__ bool local_order(const QArgs& a, const uint32_t* __restrict__ sym,
+                                            const uint64_t* __restrict__ arg, const uint32_t* __restrict__ perm,
+                                            uint64_t q, uint64_t j, uint32_t subshift, LocalOrder& L, uint32_t& jj,
+                                            uint32_t& c, uint64_t& x) {
+  constexpr uint32_t kNone = 0xFFFFFFFFu;
+  const uint32_t t = threadIdx.x;
+  uint32_t id = kNone, cc = 0, sub = kQB - 1;
+  uint64_t xx = 0;
+  if (j < q) {
+    id = perm[j];
+    xx = arg[id];
+    if (KIND) cc = sym[id];
+    sub = (uint32_t)(sort_key(a, KIND, cc, xx) >> subshift) & (kQB - 1);
+  }
+  L.cnt[t] = 0;
+  __syncthreads();
+  const uint32_t r = atomicAdd(&L.cnt[sub], 1u);
+  __syncthreads();
+  const uint32_t v = L.cnt[t], lane = t & 63u;
+  uint32_t inc = v;
+#pragma unroll
+  for (uint32_t off = 1; off < 64; off <<= 1) {
+    const uint32_t y = __shfl_up(inc, off, 64);
+    if (lane >= off) inc += y;
+  }
+  if (lane == 63) L.wsum[t >> 6] = inc;
+  __syncthreads();
+  uint32_t pre = 0;
+  for (uint32_t w = 0; w < (t >> 6); ++w) pre += L.wsum[w];
+  L.cnt[t] = pre + inc - v;
+  __syncthreads();
+  const uint32_t slot = L.cnt[sub] + r;
+  L.id[slot] = id;
+  L.sym[slot] = cc;
+  L.arg[slot] = xx;
+  __syncthreads();
+  jj = L.id[t];
+  c = L.sym[t];
+  x = L.arg[t];
+  return jj != kNone;
+}
+
 __device__ __forceinline__ void load_meta(const QArgs& a, LevelMeta* s_meta) {
   if (threadIdx.x < a.L) s_meta[threadIdx.x] = a.d.meta[threadIdx.x];
   __syncthreads();
@@ -315,27 +389,28 @@ struct SortBufs {
   uint32_t* perm;
   uint32_t* ssym;
   uint64_t* sarg;
+  uint32_t subshift = 0;  // key bits below the ones that order queries inside a block
 };
 wt_status sort_batch(const wt_tree* t, const QArgs& a, int kind, const uint32_t* sym, const uint64_t* arg, uint64_t q,
                      hipStream_t st, SortBufs& sb, bool& binned);
 
-// Blocks of a query launch: at most 4096 (grid-stride over the batch), a multiple of kXcd.
 // Counting sort of q queries by bucket id (ids[j] < 32768; wt_query.hip). scratch: sort_ids_bytes(q)
 // bytes; tot: 32768 entries, left holding the exclusive start of every bucket; perm: the slot order.
 size_t sort_ids_bytes(uint64_t q);
 void sort_ids_enqueue(const uint16_t* ids, uint64_t q, char* scratch, uint32_t* tot, uint32_t* perm, hipStream_t st);
 constexpr uint32_t kSortIdBins = 32768;
 
+// Blocks of a traversal launch: at most 2^20 threads (grid-stride over the batch), a multiple of kXcd.
 inline uint32_t query_grid(uint64_t q) {
-  return (uint32_t)round_up(std::min<uint64_t>(ceil_div(q, kQT), 4096), kXcd);
+  return (uint32_t)round_up(std::min<uint64_t>(ceil_div(q, kQB), 4096 * kQT / kQB), kXcd);
 }
 
 #define WT_DISPATCH_L2(bits, KERNEL, ...)                                                          \
   switch (bits) {                                                                                 \
-    case 256: hipLaunchKernelGGL(KERNEL<8>, dim3(grid), dim3(kQT), 0, st, __VA_ARGS__); break;   \
-    case 512: hipLaunchKernelGGL(KERNEL<9>, dim3(grid), dim3(kQT), 0, st, __VA_ARGS__); break;   \
-    case 1024: hipLaunchKernelGGL(KERNEL<10>, dim3(grid), dim3(kQT), 0, st, __VA_ARGS__); break; \
-    default: hipLaunchKernelGGL(KERNEL<11>, dim3(grid), dim3(kQT), 0, st, __VA_ARGS__); break;   \
+    case 256: hipLaunchKernelGGL(KERNEL<8>, dim3(grid), dim3(kQB), 0, st, __VA_ARGS__); break;   \
+    case 512: hipLaunchKernelGGL(KERNEL<9>, dim3(grid), dim3(kQB), 0, st, __VA_ARGS__); break;   \
+    case 1024: hipLaunchKernelGGL(KERNEL<10>, dim3(grid), dim3(kQB), 0, st, __VA_ARGS__); break; \
+    default: hipLaunchKernelGGL(KERNEL<11>, dim3(grid), dim3(kQB), 0, st, __VA_ARGS__); break;   \
   }
 
 }  // namespace wt
