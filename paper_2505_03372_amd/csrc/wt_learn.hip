@@ -388,26 +388,26 @@ __global__ void k_learn_finish(LearnModel* __restrict__ models, LearnQ* __restri
 // ---------------------------------------------------------------- learned select
 
 
-template <int L2S>
-__global__ __launch_bounds__(kQB, 8) void k_select_learned(QArgs a, const LearnQ* __restrict__ qm,
+template <int L2S, uint32_t QB>
+__global__ __launch_bounds__(QB, 8) void k_select_learned(QArgs a, const LearnQ* __restrict__ qm,
                                                         const uint32_t* __restrict__ sym,
                                                         const uint64_t* __restrict__ kin, uint64_t q,
                                                         uint64_t* __restrict__ out,
                                                         const uint32_t* __restrict__ perm, uint32_t subshift) {
   constexpr int GS = learn_gs<L2S>();
   __shared__ LevelMeta s_meta[WT_MAX_LEVELS];
-  __shared__ LocalOrder s_ord;
+  __shared__ LocalOrder<QB> s_ord;
   load_meta(a, s_meta);
   if (perm) {
-    for (uint64_t j0 = xcd_block() * kQB; j0 < q; j0 += (uint64_t)gridDim.x * kQB) {
+    for (uint64_t j0 = xcd_block() * QB; j0 < q; j0 += (uint64_t)gridDim.x * QB) {
       uint32_t jj, c;
       uint64_t x;
-      if (local_order<2>(a, sym, kin, perm, q, j0 + threadIdx.x, subshift, s_ord, jj, c, x))
+      if (local_order<2, QB>(a, sym, kin, perm, q, j0 + threadIdx.x, subshift, s_ord, jj, c, x))
         out[jj] = select_learned_one<L2S, GS>(a, s_meta, qm, c, x);
     }
     return;
   }
-  for (uint64_t j = xcd_block() * kQB + threadIdx.x; j < q; j += (uint64_t)gridDim.x * kQB)
+  for (uint64_t j = xcd_block() * QB + threadIdx.x; j < q; j += (uint64_t)gridDim.x * QB)
     out[j] = select_learned_one<L2S, GS>(a, s_meta, qm, sym[j], kin[j]);
 }
 // One evaluation of the training objective (same device code as k_learn_train).
@@ -551,7 +551,6 @@ extern "C" wt_status wt_select_learned(const wt_tree* t, const uint32_t* d_sym, 
   if (!d_sym || !d_k || !d_out) return fail(WT_ERR_ARG, "wt_select_learned: NULL buffer");
   hipStream_t st = (hipStream_t)stream;
   const QArgs a = make_args(t);
-  const uint32_t grid = query_grid(q);
   const LearnQ* qm = (const LearnQ*)((const char*)t->learn + (size_t)t->nmodels * sizeof(LearnModel));
   SortBufs sb;
   bool binned;
@@ -559,10 +558,12 @@ extern "C" wt_status wt_select_learned(const wt_tree* t, const uint32_t* d_sym, 
   if (rc != WT_OK) return rc;
   qprof_begin("select_learned", st);
   if (binned) {
-    WT_DISPATCH_L2(t->l2_bits, k_select_learned, a, qm, d_sym, d_k, q, d_out, (const uint32_t*)sb.perm, sb.subshift);
+    const uint32_t grid = query_grid(q, kQB);
+    WT_DISPATCH_L2(t->l2_bits, kQB, k_select_learned, a, qm, d_sym, d_k, q, d_out, (const uint32_t*)sb.perm, sb.subshift);
     dev_free(sb.block, st);
   } else {
-    WT_DISPATCH_L2(t->l2_bits, k_select_learned, a, qm, d_sym, d_k, q, d_out, (const uint32_t*)nullptr, 0u);
+    const uint32_t grid = query_grid(q, kQT);
+    WT_DISPATCH_L2(t->l2_bits, kQT, k_select_learned, a, qm, d_sym, d_k, q, d_out, (const uint32_t*)nullptr, 0u);
   }
   qprof_end(st);
   WT_HIP(hipGetLastError());

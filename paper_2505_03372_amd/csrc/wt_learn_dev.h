@@ -19,6 +19,9 @@ constexpr int kNP = 3 * kH + 1;  // parameters: w1[16], b1[16], w2[16], b2
 #ifndef WT_LEARN_LEAD
 #define WT_LEARN_LEAD 6
 #endif
+#ifndef WT_LEARN_LEAD_EPS
+#define WT_LEARN_LEAD_EPS 0
+#endif
 constexpr uint64_t kLearnLead = WT_LEARN_LEAD;
 
 // Query form of a trained model. With one input, the network is linear between the points where a
@@ -93,18 +96,25 @@ __device__ __forceinline__ uint64_t select_learned_at(const TreeDev& d, const Le
   const uint64_t B0 = guess >> L2S;
   const uint64_t budget = (uint64_t)Q.eps;
   // largest B in [Blo, Bhi] with count_before(B) < T; count_before(Blo) <= rank0 < T always.
-  // First look at the group of GN L2 counts centred on B0 (whole 16-byte vectors, inside B0's L1
-  // block): the counts are non-decreasing, so the blocks below the target form a prefix of it.
+  // First look at the group of GN L2 counts starting a little below B0 (whole 16-byte vectors; it may
+  // cross into the next L1 block, whose vectors add the difference of the two L1 counts): the counts
+  // never decrease, so the blocks below the target form a prefix of the group.
   constexpr uint32_t GN = 1u << GS;
-  constexpr uint64_t kPer = kL1Bits >> L2S;
-  static_assert(GN <= kPer, "group inside an L1 block");
-  const uint64_t jb0 = B0 & ~(kPer - 1);
-  const uint64_t gbase = min(max(jb0, (B0 > kLearnLead ? B0 - kLearnLead : 0ull) & ~7ull), jb0 + kPer - GN);
+  constexpr uint32_t kPerShift = kL1Shift - L2S;  // log2 of the L2 blocks per L1 block
+  static_assert(GN <= (1u << kPerShift), "a group crosses at most one L1 boundary");
+#if WT_LEARN_LEAD_EPS
+  const uint64_t lead = min<uint64_t>((uint64_t)Q.eps, kLearnLead);
+#else
+  const uint64_t lead = kLearnLead;
+#endif
+  const uint64_t gbase = (B0 > lead ? B0 - lead : 0ull) & ~7ull;
   const uint64_t glo = max(gbase, Blo), ghi = min(gbase + GN - 1, Bhi);
-  const uint64_t l1v = d.L1[m.l1 + ((gbase << L2S) >> kL1Shift)];
+  const uint64_t la = gbase >> kPerShift;
+  const uint64_t l1v = d.L1[m.l1 + la];
+  const uint64_t l1n = d.L1[m.l1 + ((gbase + GN - 1) >> kPerShift)];  // == l1v inside one block
   const uint4* gp = reinterpret_cast<const uint4*>(d.L2 + m.l2 + gbase);
   // below(e) <=> count_before(gbase + e) < T, in 32-bit arithmetic with saturation:
-  // y_e = l2 (b = 1) or e 2^L2S - l2 (b = 0), below <=> y_e < D
+  // y_e = l2 (b = 1) or e 2^L2S - l2 (b = 0), plus the L1 step in the next block, below <=> y_e < D
   int64_t D;
   if (b) D = (int64_t)min<uint64_t>(T - min(T, l1v), 1ull << 20);
   else {
@@ -113,30 +123,35 @@ __device__ __forceinline__ uint64_t select_learned_at(const TreeDev& d, const Le
   }
   const int32_t Di = (int32_t)D;
   const int32_t sgn = b ? 1 : -1, step = b ? 0 : (1 << L2S);
-  // Over the group (inside one L1 block) the counts never decrease: blocks before the node are below
-  // the target (count_before(Blo) <= rank0 < T) and blocks past the node are not, so the blocks
-  // below form a prefix of the group; only padding past the level's end is masked.
+  // entries from `cross` on lie in the next L1 block: there y adds the L1 step (at most one L1 block
+  // of bits)
+  const int32_t dl1 = sgn * (int32_t)(l1n - l1v);
+  const uint32_t cross = (uint32_t)min<uint64_t>(((la + 1) << kPerShift) - gbase, GN);
+  // Blocks before the node are below the target (count_before(Blo) <= rank0 < T) and blocks past the
+  // node are not, so only padding past the level's end is masked.
   const uint64_t nL2 = (m.n + (1ull << L2S) - 1) >> L2S;
   const uint32_t ehi = gbase + GN <= nL2 ? GN - 1 : (uint32_t)(ghi - gbase);
   int32_t off = 0;
   uint32_t below = 0, seen = 0;
   int32_t ylast = 0;  // y of the last block below the target
-  // one vector at a time from a little below the prediction: a lane stops at the first vector that
-  // ends the prefix or reaches ghi
+  // two vectors at a time: a lane stops at the first pair that ends the prefix or reaches ghi
 #pragma unroll 1
-  for (uint32_t v = 0; v < GN / 8; ++v) {
-    const uint4 x = gp[v];
+  for (uint32_t v = 0; v < GN / 8; v += 2) {
+    const uint4 xa = gp[v], xb = gp[v + 1];
+    const int32_t adja = 8 * v < cross ? 0 : dl1, adjb = 8 * v + 8 < cross ? 0 : dl1;
 #pragma unroll
-    for (uint32_t e = 0; e < 8; ++e) {
-      const uint32_t dw = e < 4 ? (e < 2 ? x.x : x.y) : (e < 6 ? x.z : x.w);
-      const int32_t l2v = (int32_t)((dw >> ((e & 1) * 16)) & 0xFFFFu);
-      const int32_t y = off + sgn * l2v;
+    for (uint32_t e = 0; e < 16; ++e) {
+      const uint4 x = e < 8 ? xa : xb;
+      const uint32_t ee = e & 7;
+      const uint32_t dw = ee < 4 ? (ee < 2 ? x.x : x.y) : (ee < 6 ? x.z : x.w);
+      const int32_t l2v = (int32_t)((dw >> ((ee & 1) * 16)) & 0xFFFFu);
+      const int32_t y = off + sgn * l2v + (e < 8 ? adja : adjb);
       const bool lt = v * 8 + e <= ehi && y < Di;
       below += lt ? 1u : 0u;
       ylast = lt ? y : ylast;
       off += step;
     }
-    seen += 8;
+    seen += 16;
     if (below < seen || gbase + seen - 1 >= ghi) break;
   }
   // blocks gbase .. gbase + below - 1 are below the target; count from glo as the search expects

@@ -25,65 +25,65 @@ namespace wt {
 
 // perm: NULL, or the queries in binned order: slot j runs query perm[j] (its arguments are read and its
 // answer written at that index).
-template <int L2S>
-__global__ __launch_bounds__(kQB) void k_access(QArgs a, const uint64_t* __restrict__ pos, uint64_t q,
+template <int L2S, uint32_t QB>
+__global__ __launch_bounds__(QB) void k_access(QArgs a, const uint64_t* __restrict__ pos, uint64_t q,
                                                 uint32_t* __restrict__ out, const uint32_t* __restrict__ perm,
                                                 uint32_t subshift) {
   __shared__ LevelMeta s_meta[WT_MAX_LEVELS];
-  __shared__ LocalOrder s_ord;
+  __shared__ LocalOrder<QB> s_ord;
   load_meta(a, s_meta);
   if (perm) {
-    for (uint64_t j0 = xcd_block() * kQB; j0 < q; j0 += (uint64_t)gridDim.x * kQB) {
+    for (uint64_t j0 = xcd_block() * QB; j0 < q; j0 += (uint64_t)gridDim.x * QB) {
       uint32_t jj, c;
       uint64_t x;
-      if (local_order<0>(a, nullptr, pos, perm, q, j0 + threadIdx.x, subshift, s_ord, jj, c, x))
+      if (local_order<0, QB>(a, nullptr, pos, perm, q, j0 + threadIdx.x, subshift, s_ord, jj, c, x))
         out[jj] = access_one<L2S>(a, s_meta, x);
     }
     return;
   }
-  for (uint64_t j = xcd_block() * kQB + threadIdx.x; j < q; j += (uint64_t)gridDim.x * kQB)
+  for (uint64_t j = xcd_block() * QB + threadIdx.x; j < q; j += (uint64_t)gridDim.x * QB)
     out[j] = access_one<L2S>(a, s_meta, pos[j]);
 }
 
-template <int L2S>
-__global__ __launch_bounds__(kQB) void k_rank(QArgs a, const uint32_t* __restrict__ sym,
+template <int L2S, uint32_t QB>
+__global__ __launch_bounds__(QB) void k_rank(QArgs a, const uint32_t* __restrict__ sym,
                                               const uint64_t* __restrict__ pos, uint64_t q,
                                               uint64_t* __restrict__ out, const uint32_t* __restrict__ perm,
                                               uint32_t subshift) {
   __shared__ LevelMeta s_meta[WT_MAX_LEVELS];
-  __shared__ LocalOrder s_ord;
+  __shared__ LocalOrder<QB> s_ord;
   load_meta(a, s_meta);
   if (perm) {
-    for (uint64_t j0 = xcd_block() * kQB; j0 < q; j0 += (uint64_t)gridDim.x * kQB) {
+    for (uint64_t j0 = xcd_block() * QB; j0 < q; j0 += (uint64_t)gridDim.x * QB) {
       uint32_t jj, c;
       uint64_t x;
-      if (local_order<1>(a, sym, pos, perm, q, j0 + threadIdx.x, subshift, s_ord, jj, c, x))
+      if (local_order<1, QB>(a, sym, pos, perm, q, j0 + threadIdx.x, subshift, s_ord, jj, c, x))
         out[jj] = rank_one<L2S>(a, s_meta, c, x);
     }
     return;
   }
-  for (uint64_t j = xcd_block() * kQB + threadIdx.x; j < q; j += (uint64_t)gridDim.x * kQB)
+  for (uint64_t j = xcd_block() * QB + threadIdx.x; j < q; j += (uint64_t)gridDim.x * QB)
     out[j] = rank_one<L2S>(a, s_meta, sym[j], pos[j]);
 }
 
-template <int L2S>
-__global__ __launch_bounds__(kQB, 8) void k_select(QArgs a, const uint32_t* __restrict__ sym,
+template <int L2S, uint32_t QB>
+__global__ __launch_bounds__(QB, 8) void k_select(QArgs a, const uint32_t* __restrict__ sym,
                                                 const uint64_t* __restrict__ kin, uint64_t q,
                                                 uint64_t* __restrict__ out, const uint32_t* __restrict__ perm,
                                               uint32_t subshift) {
   __shared__ LevelMeta s_meta[WT_MAX_LEVELS];
-  __shared__ LocalOrder s_ord;
+  __shared__ LocalOrder<QB> s_ord;
   load_meta(a, s_meta);
   if (perm) {
-    for (uint64_t j0 = xcd_block() * kQB; j0 < q; j0 += (uint64_t)gridDim.x * kQB) {
+    for (uint64_t j0 = xcd_block() * QB; j0 < q; j0 += (uint64_t)gridDim.x * QB) {
       uint32_t jj, c;
       uint64_t x;
-      if (local_order<2>(a, sym, kin, perm, q, j0 + threadIdx.x, subshift, s_ord, jj, c, x))
+      if (local_order<2, QB>(a, sym, kin, perm, q, j0 + threadIdx.x, subshift, s_ord, jj, c, x))
         out[jj] = select_one<L2S>(a, s_meta, c, x);
     }
     return;
   }
-  for (uint64_t j = xcd_block() * kQB + threadIdx.x; j < q; j += (uint64_t)gridDim.x * kQB)
+  for (uint64_t j = xcd_block() * QB + threadIdx.x; j < q; j += (uint64_t)gridDim.x * QB)
     out[j] = select_one<L2S>(a, s_meta, sym[j], kin[j]);
 }
 
@@ -319,7 +319,7 @@ wt_status sort_batch(const wt_tree* t, const QArgs& a, int kind, const uint32_t*
   uint32_t bits = 0;
   while ((1ull << bits) < a.n + 1) ++bits;
   const uint32_t shift = bits > 15 ? bits - 15 : 0;
-  sb.subshift = shift > kQBBits ? shift - kQBBits : 0;
+  sb.subshift = shift > qb_bits(kQB) ? shift - qb_bits(kQB) : 0;
   qprof_begin("sort_count", st);
   if (kind == 0) hipLaunchKernelGGL(k_bin_count<0>, dim3(nblk), dim3(kBinT), 0, st, a, sym, arg, q, shift, bhist);
   else if (kind == 1) hipLaunchKernelGGL(k_bin_count<1>, dim3(nblk), dim3(kBinT), 0, st, a, sym, arg, q, shift, bhist);
@@ -358,17 +358,18 @@ extern "C" wt_status wt_access(const wt_tree* t, const uint64_t* d_pos, uint64_t
   if (!d_pos || !d_out) return fail(WT_ERR_ARG, "wt_access: NULL buffer");
   hipStream_t st = (hipStream_t)stream;
   const QArgs a = make_args(t);
-  const uint32_t grid = query_grid(q);
   SortBufs sb;
   bool binned;
   const wt_status rc = sort_batch(t, a, 0, nullptr, d_pos, q, st, sb, binned);
   if (rc != WT_OK) return rc;
   qprof_begin("access", st);
   if (binned) {
-    WT_DISPATCH_L2(t->l2_bits, k_access, a, d_pos, q, d_out, (const uint32_t*)sb.perm, sb.subshift);
+    const uint32_t grid = query_grid(q, kQB);
+    WT_DISPATCH_L2(t->l2_bits, kQB, k_access, a, d_pos, q, d_out, (const uint32_t*)sb.perm, sb.subshift);
     dev_free(sb.block, st);
   } else {
-    WT_DISPATCH_L2(t->l2_bits, k_access, a, d_pos, q, d_out, (const uint32_t*)nullptr, 0u);
+    const uint32_t grid = query_grid(q, kQT);
+    WT_DISPATCH_L2(t->l2_bits, kQT, k_access, a, d_pos, q, d_out, (const uint32_t*)nullptr, 0u);
   }
   qprof_end(st);
   WT_HIP(hipGetLastError());
@@ -383,17 +384,18 @@ extern "C" wt_status wt_rank(const wt_tree* t, const uint32_t* d_sym, const uint
   if (!d_sym || !d_pos || !d_out) return fail(WT_ERR_ARG, "wt_rank: NULL buffer");
   hipStream_t st = (hipStream_t)stream;
   const QArgs a = make_args(t);
-  const uint32_t grid = query_grid(q);
   SortBufs sb;
   bool binned;
   const wt_status rc = sort_batch(t, a, 1, d_sym, d_pos, q, st, sb, binned);
   if (rc != WT_OK) return rc;
   qprof_begin("rank", st);
   if (binned) {
-    WT_DISPATCH_L2(t->l2_bits, k_rank, a, d_sym, d_pos, q, d_out, (const uint32_t*)sb.perm, sb.subshift);
+    const uint32_t grid = query_grid(q, kQB);
+    WT_DISPATCH_L2(t->l2_bits, kQB, k_rank, a, d_sym, d_pos, q, d_out, (const uint32_t*)sb.perm, sb.subshift);
     dev_free(sb.block, st);
   } else {
-    WT_DISPATCH_L2(t->l2_bits, k_rank, a, d_sym, d_pos, q, d_out, (const uint32_t*)nullptr, 0u);
+    const uint32_t grid = query_grid(q, kQT);
+    WT_DISPATCH_L2(t->l2_bits, kQT, k_rank, a, d_sym, d_pos, q, d_out, (const uint32_t*)nullptr, 0u);
   }
   qprof_end(st);
   WT_HIP(hipGetLastError());
@@ -408,17 +410,18 @@ extern "C" wt_status wt_select(const wt_tree* t, const uint32_t* d_sym, const ui
   if (!d_sym || !d_k || !d_out) return fail(WT_ERR_ARG, "wt_select: NULL buffer");
   hipStream_t st = (hipStream_t)stream;
   const QArgs a = make_args(t);
-  const uint32_t grid = query_grid(q);
   SortBufs sb;
   bool binned;
   const wt_status rc = sort_batch(t, a, 2, d_sym, d_k, q, st, sb, binned);
   if (rc != WT_OK) return rc;
   qprof_begin("select", st);
   if (binned) {
-    WT_DISPATCH_L2(t->l2_bits, k_select, a, d_sym, d_k, q, d_out, (const uint32_t*)sb.perm, sb.subshift);
+    const uint32_t grid = query_grid(q, kQB);
+    WT_DISPATCH_L2(t->l2_bits, kQB, k_select, a, d_sym, d_k, q, d_out, (const uint32_t*)sb.perm, sb.subshift);
     dev_free(sb.block, st);
   } else {
-    WT_DISPATCH_L2(t->l2_bits, k_select, a, d_sym, d_k, q, d_out, (const uint32_t*)nullptr, 0u);
+    const uint32_t grid = query_grid(q, kQT);
+    WT_DISPATCH_L2(t->l2_bits, kQT, k_select, a, d_sym, d_k, q, d_out, (const uint32_t*)nullptr, 0u);
   }
   qprof_end(st);
   WT_HIP(hipGetLastError());

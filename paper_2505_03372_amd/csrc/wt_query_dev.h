@@ -53,37 +53,61 @@ __device__ __forceinline__ uint64_t rank1_at(const TreeDev& d, const LevelMeta& 
 // Position of the k-th bit equal to b (1 <= k <= count of b) of the level (Algorithm 2).
 // Offset of the kk-th bit equal to b (kk >= 1, present) inside the L2 block whose words start at
 // wp: the word holding it is found by popcounts over 16-byte loads, then one in-word select after
-// the scan (lanes leave the scan at different words; the select runs once for the whole wave).
-template <int L2S>
+// the scan (the select runs once for the whole wave). Blocks up to 512 bits are loaded at once (one
+// memory round trip: the traversal is bound by its chain of dependent loads); larger ones are
+// scanned a vector at a time, a lane leaving at the vector that holds its bit (also the form for
+// kAll = false, which needs fewer registers).
+template <int L2S, bool kAll = true>
 __device__ __forceinline__ uint32_t block_select(const uint64_t* __restrict__ wp, uint32_t b, uint32_t kk) {
   constexpr int L2W = (1 << L2S) / 64;
   const uint4* vp = reinterpret_cast<const uint4*>(wp);  // the block is 64-byte aligned
   uint64_t sel = 0;
   uint32_t wsel = 0;
-#pragma unroll 1
-  for (int v = 0; v < L2W / 2; ++v) {
-    const uint4 x = vp[v];
-    const uint64_t pair[2] = {((uint64_t)x.y << 32) | x.x, ((uint64_t)x.w << 32) | x.z};
+  if constexpr (kAll && L2W <= 8) {
+    uint4 x[L2W / 2];
+#pragma unroll
+    for (int v = 0; v < L2W / 2; ++v) x[v] = vp[v];
     bool done = false;
 #pragma unroll
-    for (int h = 0; h < 2; ++h) {
-      const uint64_t word = b ? pair[h] : ~pair[h];
-      const uint32_t pc = popc64(word);
-      sel = word;
-      wsel = (uint32_t)(2 * v + h);
-      if (kk <= pc) {
-        done = true;
-        break;
+    for (int v = 0; v < L2W / 2; ++v) {
+      const uint64_t pair[2] = {((uint64_t)x[v].y << 32) | x[v].x, ((uint64_t)x[v].w << 32) | x[v].z};
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        const uint64_t word = b ? pair[h] : ~pair[h];
+        const uint32_t pc = popc64(word);
+        const bool hit = !done && kk <= pc;
+        sel = hit ? word : sel;
+        wsel = hit ? (uint32_t)(2 * v + h) : wsel;
+        kk -= (!done && !hit) ? pc : 0u;
+        done = done || hit;
       }
-      kk -= pc;
     }
-    if (done) break;
+  } else {
+#pragma unroll 1
+    for (int v = 0; v < L2W / 2; ++v) {
+      const uint4 x = vp[v];
+      const uint64_t pair[2] = {((uint64_t)x.y << 32) | x.x, ((uint64_t)x.w << 32) | x.z};
+      bool done = false;
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        const uint64_t word = b ? pair[h] : ~pair[h];
+        const uint32_t pc = popc64(word);
+        sel = word;
+        wsel = (uint32_t)(2 * v + h);
+        if (kk <= pc) {
+          done = true;
+          break;
+        }
+        kk -= pc;
+      }
+      if (done) break;
+    }
   }
   return 64u * wsel + select_in_word(sel, kk);
 }
 
-// kLine: resolve the L2 search on the first line of L2 counts in registers before the binary search
-// (faster; the form without it needs fewer registers).
+// kLine: resolve the L2 search on the first L2 counts in registers before the binary search, and
+// load the found block's words at once (faster; the form without either needs fewer registers).
 template <int L2S, bool kLine = true>
 __device__ __forceinline__ uint64_t select_at(const TreeDev& d, const LevelMeta& m, uint32_t b, uint64_t k,
                                               uint32_t sshift) {
@@ -137,21 +161,23 @@ __device__ __forceinline__ uint64_t select_at(const TreeDev& d, const LevelMeta&
     const uint32_t ehi = gbase + GN <= nL2 ? GN - 1 : (uint32_t)(jhi - gbase);
     uint32_t below = 0, seen = 0;
     int32_t ylast = 0;  // y of the last block below k
-    // one vector at a time: a lane stops at the first vector that ends the prefix or reaches jhi
+    // two vectors at a time: a lane stops at the first pair that ends the prefix or reaches jhi
 #pragma unroll 1
-    for (uint32_t v = 0; v < GN / 8; ++v) {
-      const uint4 x = gp[v];
+    for (uint32_t v = 0; v < GN / 8; v += 2) {
+      const uint4 xa = gp[v], xb = gp[v + 1];
 #pragma unroll
-      for (uint32_t e = 0; e < 8; ++e) {
-        const uint32_t dw = e < 4 ? (e < 2 ? x.x : x.y) : (e < 6 ? x.z : x.w);
-        const int32_t l2v = (int32_t)((dw >> ((e & 1) * 16)) & 0xFFFFu);
+      for (uint32_t e = 0; e < 16; ++e) {
+        const uint4 x = e < 8 ? xa : xb;
+        const uint32_t ee = e & 7;
+        const uint32_t dw = ee < 4 ? (ee < 2 ? x.x : x.y) : (ee < 6 ? x.z : x.w);
+        const int32_t l2v = (int32_t)((dw >> ((ee & 1) * 16)) & 0xFFFFu);
         const int32_t y = off + sgn * l2v;
         const bool lt = v * 8 + e <= ehi && y < Ki;
         below += lt ? 1u : 0u;
         ylast = lt ? y : ylast;
         off += step;
       }
-      seen += 8;
+      seen += 16;
       if (below < seen || gbase + seen - 1 >= jhi) break;
     }
     const uint64_t last = gbase + below - 1;  // below >= 1
@@ -170,7 +196,7 @@ __device__ __forceinline__ uint64_t select_at(const TreeDev& d, const LevelMeta&
     else jhi = mid - 1;
   }
   if (!resolved) k -= b ? (uint64_t)L2[jlo] : ((jlo - jb) << L2S) - L2[jlo];
-  return (jlo << L2S) + block_select<L2S>(d.bits + m.bits + (jlo << (L2S - 6)), b, (uint32_t)k);
+  return (jlo << L2S) + block_select<L2S, kLine>(d.bits + m.bits + (jlo << (L2S - 6)), b, (uint32_t)k);
 }
 
 // 64-bit value of the wave's first active lane.
@@ -291,42 +317,43 @@ __device__ __forceinline__ uint64_t sort_key(const QArgs& a, int kind, uint32_t 
   return x > cnt ? a.n : lo + x - 1;
 }
 
-// Threads per block of the access / rank / select traversal kernels.
+// Threads per block of the access / rank / select traversal kernels: binned batches use kQB (the
+// in-block reorder below works over the whole block), unbinned ones kQT (small batches spread over
+// more CUs).
 #ifndef WT_QB
 #define WT_QB 1024
 #endif
 constexpr uint32_t kQB = WT_QB;
-constexpr uint32_t kQBBits = kQB == 1024 ? 10 : kQB == 512 ? 9 : 8;
-static_assert((1u << kQBBits) == kQB, "traversal block: 256, 512 or 1024 threads");
+constexpr uint32_t qb_bits(uint32_t qb) { return qb == 1024 ? 10 : qb == 512 ? 9 : 8; }
+static_assert((1u << qb_bits(kQB)) == kQB, "traversal block: 256, 512 or 1024 threads");
 
-// A binned launch takes kQB consecutive slots per block and round, which lie in one or two buckets.
-// A counting sort in LDS by the next kQBBits key bits below the bucket gives each wave queries whose
-// answers are close together, so the lanes of one load instruction share lines (not only the caches
-// do); the larger the block, the narrower the key range of a wave.
+// A binned launch takes QB consecutive slots per block and round, which lie in one or two buckets.
+// A counting sort in LDS by the next qb_bits(QB) key bits below the bucket gives each wave queries
+// whose answers are close together, so the lanes of one load instruction share lines (not only the
+// caches do); the larger the block, the narrower the key range of a wave.
+template <uint32_t QB>
 struct LocalOrder {
-  uint32_t cnt[kQB];  // one sub-bucket counter per thread
-  uint32_t wsum[kQB / 64];
-  uint32_t id[kQB];
-  uint32_t sym[kQB];
-  uint64_t arg[kQB];
+  uint32_t cnt[QB];  // one sub-bucket counter per thread
+  uint32_t wsum[QB / 64];
+  uint32_t id[QB];
+  uint32_t sym[QB];
+  uint64_t arg[QB];
 };
 
-// Slot j of the binned order (perm), reordered inside the block: returns false for a lane past the
-// batch, else the query index jj and its arguments (c, x). Called by every thread of the block.
-template <int KIND>
+template <int KIND, uint32_t QB>
 __device__ __forceinline__ bool local_order(const QArgs& a, const uint32_t* __restrict__ sym,
                                             const uint64_t* __restrict__ arg, const uint32_t* __restrict__ perm,
-                                            uint64_t q, uint64_t j, uint32_t subshift, LocalOrder& L, uint32_t& jj,
-                                            uint32_t& c, uint64_t& x) {
+                                            uint64_t q, uint64_t j, uint32_t subshift, LocalOrder<QB>& L,
+                                            uint32_t& jj, uint32_t& c, uint64_t& x) {
   constexpr uint32_t kNone = 0xFFFFFFFFu;
   const uint32_t t = threadIdx.x;
-  uint32_t id = kNone, cc = 0, sub = kQB - 1;
+  uint32_t id = kNone, cc = 0, sub = QB - 1;
   uint64_t xx = 0;
   if (j < q) {
     id = perm[j];
     xx = arg[id];
     if (KIND) cc = sym[id];
-    sub = (uint32_t)(sort_key(a, KIND, cc, xx) >> subshift) & (kQB - 1);
+    sub = (uint32_t)(sort_key(a, KIND, cc, xx) >> subshift) & (QB - 1);
   }
   L.cnt[t] = 0;
   __syncthreads();
@@ -401,16 +428,16 @@ void sort_ids_enqueue(const uint16_t* ids, uint64_t q, char* scratch, uint32_t* 
 constexpr uint32_t kSortIdBins = 32768;
 
 // Blocks of a traversal launch: at most 2^20 threads (grid-stride over the batch), a multiple of kXcd.
-inline uint32_t query_grid(uint64_t q) {
-  return (uint32_t)round_up(std::min<uint64_t>(ceil_div(q, kQB), 4096 * kQT / kQB), kXcd);
+inline uint32_t query_grid(uint64_t q, uint32_t qb) {
+  return (uint32_t)round_up(std::min<uint64_t>(ceil_div(q, qb), 4096 * kQT / qb), kXcd);
 }
 
-#define WT_DISPATCH_L2(bits, KERNEL, ...)                                                          \
-  switch (bits) {                                                                                 \
-    case 256: hipLaunchKernelGGL(KERNEL<8>, dim3(grid), dim3(kQB), 0, st, __VA_ARGS__); break;   \
-    case 512: hipLaunchKernelGGL(KERNEL<9>, dim3(grid), dim3(kQB), 0, st, __VA_ARGS__); break;   \
-    case 1024: hipLaunchKernelGGL(KERNEL<10>, dim3(grid), dim3(kQB), 0, st, __VA_ARGS__); break; \
-    default: hipLaunchKernelGGL(KERNEL<11>, dim3(grid), dim3(kQB), 0, st, __VA_ARGS__); break;   \
+#define WT_DISPATCH_L2(bits, QB, KERNEL, ...)                                                          \
+  switch (bits) {                                                                                     \
+    case 256: hipLaunchKernelGGL((KERNEL<8, QB>), dim3(grid), dim3(QB), 0, st, __VA_ARGS__); break;   \
+    case 512: hipLaunchKernelGGL((KERNEL<9, QB>), dim3(grid), dim3(QB), 0, st, __VA_ARGS__); break;   \
+    case 1024: hipLaunchKernelGGL((KERNEL<10, QB>), dim3(grid), dim3(QB), 0, st, __VA_ARGS__); break; \
+    default: hipLaunchKernelGGL((KERNEL<11, QB>), dim3(grid), dim3(QB), 0, st, __VA_ARGS__); break;   \
   }
 
 }  // namespace wt
