@@ -457,7 +457,7 @@ def main():
         qbytes = 64.0 * info["levels"] * q
         qa = qbytes / (per_step[dom] * 1e-3) / 1e9
         roof = {"kernel": {"access": "k_access", "rank": "k_rank", "select": "k_select",
-                           "select_learned": "k_select_learned"}[dom] + "<9>",
+                           "select_learned": "k_select_learned"}[dom] + "<9, 1024u>",
                 "bound": "hbm", "achieved": qa, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": qa / HBM_PEAK_GBS,
                 "traffic": None, "bytes_per_launch": qbytes, "avg_launch_ms": per_step[dom], "launches": len(kms[dom]),
                 "note": "random access: 64 B (one L2 block of bits) per level per query"}

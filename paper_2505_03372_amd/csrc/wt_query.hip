@@ -26,7 +26,7 @@ namespace wt {
 // perm: NULL, or the queries in binned order: slot j runs query perm[j] (its arguments are read and its
 // answer written at that index).
 template <int L2S, uint32_t QB>
-__global__ __launch_bounds__(QB) void k_access(QArgs a, const uint64_t* __restrict__ pos, uint64_t q,
+__global__ __launch_bounds__(QB, 8) void k_access(QArgs a, const uint64_t* __restrict__ pos, uint64_t q,
                                                 uint32_t* __restrict__ out, const uint32_t* __restrict__ perm,
                                                 uint32_t subshift) {
   __shared__ LevelMeta s_meta[WT_MAX_LEVELS];
@@ -46,7 +46,7 @@ __global__ __launch_bounds__(QB) void k_access(QArgs a, const uint64_t* __restri
 }
 
 template <int L2S, uint32_t QB>
-__global__ __launch_bounds__(QB) void k_rank(QArgs a, const uint32_t* __restrict__ sym,
+__global__ __launch_bounds__(QB, 8) void k_rank(QArgs a, const uint32_t* __restrict__ sym,
                                               const uint64_t* __restrict__ pos, uint64_t q,
                                               uint64_t* __restrict__ out, const uint32_t* __restrict__ perm,
                                               uint32_t subshift) {

@@ -221,14 +221,21 @@ __device__ __forceinline__ uint32_t access_one(const QArgs& a, const LevelMeta* 
   if (i >= a.n) return 0xFFFFFFFFu;
   uint32_t s = 0, e = a.sigma;
   uint64_t p = 0, x = i;
+  NodeQ nd = node_at(a.d.nodes, 0);
   for (uint32_t l = 0; l < a.L; ++l) {
     const uint32_t width = e - s;
-    const NodeQ nd = node_at(a.d.nodes, (1ull << l) - 1 + p);
     const LevelMeta& m = meta[l];
     const uint64_t y = nd.start + x;
     if (width <= 2) {
       if (width == 2) s += (uint32_t)(a.d.bits[m.bits + (y >> 6)] >> (y & 63)) & 1u;
       break;
+    }
+    // the two children are adjacent entries of the next level: load both with this level's reads
+    NodeQ c0 = nd, c1 = nd;
+    if (l + 1 < a.L) {
+      const uint64_t ci = (2ull << l) - 1 + 2 * p;
+      c0 = a.d.nodes[ci];
+      c1 = a.d.nodes[ci + 1];
     }
     uint32_t bit;
     const uint64_t r0 = y - rank1_at<L2S>(a.d, m, y, bit);
@@ -237,10 +244,12 @@ __device__ __forceinline__ uint32_t access_one(const QArgs& a, const LevelMeta* 
       x = r0 - nd.r0;
       e = s + half;
       p = 2 * p;
+      nd = c0;
     } else {
       x = x - (r0 - nd.r0);
       s += half;
       p = 2 * p + 1;
+      nd = c1;
     }
   }
   return s;
@@ -254,14 +263,18 @@ __device__ __forceinline__ uint64_t rank_one(const QArgs& a, const LevelMeta* me
   if (c >= a.sigma) return 0;
   uint32_t s = 0, e = a.sigma;
   uint64_t p = 0, x = i;
+  NodeQ nd = node_at(a.d.nodes, 0);
   for (uint32_t l = 0; l < a.L; ++l) {
     if (e - s <= 1 || x == 0) break;
-    const NodeQ nd = node_at(a.d.nodes, (1ull << l) - 1 + p);
     const uint64_t y = nd.start + x;
+    const uint32_t split = s + (uint32_t)pow2_below(e - s);
+    const bool right = c >= split;
+    // the symbol fixes the next node: load its entry with this level's reads
+    NodeQ nx = nd;
+    if (l + 1 < a.L) nx = a.d.nodes[(2ull << l) - 1 + 2 * p + (right ? 1 : 0)];
     uint32_t bit;
     const uint64_t r0 = y - rank1_at<L2S, true>(a.d, meta[l], y, bit);
-    const uint32_t split = s + (uint32_t)pow2_below(e - s);
-    if (c < split) {
+    if (!right) {
       x = r0 - nd.r0;
       e = split;
       p = 2 * p;
@@ -270,6 +283,7 @@ __device__ __forceinline__ uint64_t rank_one(const QArgs& a, const LevelMeta* me
       s = split;
       p = 2 * p + 1;
     }
+    nd = nx;
   }
   return x;
 }
