@@ -76,8 +76,8 @@ def source_hash(paths) -> str:
 
 
 def load_traffic(per_launch_alg: float):
-    """HBM traffic of the level kernel from the committed rocprofv3 counter summary, if it was taken
-    on the current kernel source."""
+    """HBM traffic of the level kernel from the committed rocprofv3 counter summary (taken on the
+    2^30 u8 Zipf workload), if it was taken on the current kernel source."""
     if not os.path.exists(PMC_FILE):
         return None
     with open(PMC_FILE) as f:
@@ -436,7 +436,8 @@ def main():
         rates["kernel_%s_ms_per_step" % k] = per_call
     kname = {1: "k_level<uint8_t>", 2: "k_level<uint16_t>", 4: "k_level<uint32_t>"}[width]
     build_roof = {"kernel": kname, "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                  "frac": achieved / HBM_PEAK_GBS, "traffic": load_traffic(avg_bytes),
+                  "frac": achieved / HBM_PEAK_GBS,
+                  "traffic": load_traffic(avg_bytes) if args.workload == "text_zipf" else None,
                   "bytes_per_launch": avg_bytes, "avg_launch_ms": avg_ms, "launches": len(level_ms)}
     # the whole build (every kernel between the symbols on the device and the finished tree): one read
     # of the symbols for the histogram plus every level pass's bytes
