@@ -147,3 +147,29 @@ def test_learned_select_full_size_text_zipf():
     idx = np.arange(0, got.size, 1024)
     G._assert_eq("learned select", got[idx], oracle.select(wl.S, wl.sigma, wl.sel_c[idx], wl.sel_k[idx]), wl.sel_k[idx])
     t.free()
+
+
+@pytest.mark.parametrize("width,sigma,n,kind", [(1, 40, (1 << 21) + 777, "zipf"), (2, 1000, (1 << 20) + 13, "uniform")])
+def test_learned_select_every_occurrence_binned(width, sigma, n, kind):
+    """Every occurrence of every symbol asked at once, in shuffled order (one binned batch): every
+    position of the sequence is the answer of one query, including those just past an L1 block
+    boundary, where the learned correction's group crosses into the next L1 block. The answers are
+    the positions of each symbol in increasing order (a stable sort of S by symbol)."""
+    seed = 0xE0CC + n
+    S = make_seq(kind, n, sigma, width, seed)
+    G.log("every occurrence, w=%d sigma=%d n=%d kind=%s" % (width, sigma, n, kind))
+    t = G.gpu_build(S, sigma)
+    t.learn_select()
+    cnt = np.bincount(S, minlength=sigma)
+    sc = np.repeat(np.arange(sigma, dtype=np.uint32), cnt)
+    sk = (np.arange(n, dtype=np.uint64) - np.repeat(np.cumsum(cnt) - cnt, cnt).astype(np.uint64) + 1)
+    exp = np.argsort(S, kind="stable").astype(np.uint64)
+    perm = np.random.default_rng(seed).permutation(n)
+    sc, sk, exp = sc[perm], sk[perm], exp[perm]
+    args = np.stack([sc.astype(np.uint64), sk], 1)
+    got = G.host(t.select_learned(G.dev(sc), G.dev(sk)))
+    G._assert_eq("learned select, every occurrence", got, exp, args)
+    G._assert_eq("plain select, every occurrence", G.host(t.select(G.dev(sc), G.dev(sk))), exp, args)
+    idx = np.arange(0, n, 997)
+    G._assert_eq("oracle sample", exp[idx], oracle.select(S, sigma, sc[idx], sk[idx]), args[idx])
+    t.free()
