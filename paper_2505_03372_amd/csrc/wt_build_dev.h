@@ -204,6 +204,26 @@ __device__ __forceinline__ void fill_body(uint64_t* __restrict__ p, uint64_t n, 
 // spans (both hold bytes of the sequence, so neither leaves its pages) and funnel-shifted. `base`
 // must be the same for every lane of the wave (tile offsets q0 * sizeof(E) are multiples of 16, so the
 // misalignment is then wave-uniform and picks its shift with scalar branches).
+// The 16 bytes starting m bytes (0 < m < 16, wave-uniform) into the aligned pair of blocks x0, x1.
+__device__ __forceinline__ void funnel16(const u32x4& x0, const u32x4& x1, uint32_t m, uint32_t (&y)[4]) {
+  const uint32_t d[8] = {x0.x, x0.y, x0.z, x0.w, x1.x, x1.y, x1.z, x1.w};
+  const uint32_t mu = (uint32_t)__builtin_amdgcn_readfirstlane((int)m);
+  const uint32_t sh = mu & 3u;
+  switch (mu >> 2) {
+#define WT_FUNNEL(K)                                                                     \
+  case K:                                                                                \
+    for (int i = 0; i < 4; ++i) y[i] = __builtin_amdgcn_alignbyte(d[i + K + 1], d[i + K], sh); \
+    break;
+    WT_FUNNEL(0)
+    WT_FUNNEL(1)
+    WT_FUNNEL(2)
+    default:
+      for (int i = 0; i < 4; ++i) y[i] = __builtin_amdgcn_alignbyte(d[i + 4], d[i + 3], sh);
+      break;
+#undef WT_FUNNEL
+  }
+}
+
 template <typename E, typename P>
 __device__ __forceinline__ void load16(P base, uint32_t q0, uint32_t cnt, bool vec, E (&v)[16 / sizeof(E)]) {
   constexpr int EV = 16 / (int)sizeof(E);
@@ -221,23 +241,8 @@ __device__ __forceinline__ void load16(P base, uint32_t q0, uint32_t cnt, bool v
   if (q0 + EV <= cnt && m != 0) {
     const auto blk = pcast<const u32x4>(pcast<const char>(base + q0) - m);
     const u32x4 x0 = blk[0], x1 = blk[1];
-    const uint32_t d[8] = {x0.x, x0.y, x0.z, x0.w, x1.x, x1.y, x1.z, x1.w};
-    const uint32_t mu = (uint32_t)__builtin_amdgcn_readfirstlane((int)m);
-    const uint32_t sh = mu & 3u;
     uint32_t y[4];
-    switch (mu >> 2) {
-#define WT_FUNNEL(K)                                                                     \
-  case K:                                                                                \
-    for (int i = 0; i < 4; ++i) y[i] = __builtin_amdgcn_alignbyte(d[i + K + 1], d[i + K], sh); \
-    break;
-      WT_FUNNEL(0)
-      WT_FUNNEL(1)
-      WT_FUNNEL(2)
-      default:
-        for (int i = 0; i < 4; ++i) y[i] = __builtin_amdgcn_alignbyte(d[i + 4], d[i + 3], sh);
-        break;
-#undef WT_FUNNEL
-    }
+    funnel16(x0, x1, m, y);
     __builtin_memcpy(v, y, 16);
     return;
   }
@@ -464,8 +469,35 @@ __device__ __forceinline__ void hist_dense_body(PS sym, uint64_t n, uint32_t sig
             __builtin_memcpy(&x, &vx[k], 16);
             count_vec(x, (uint32_t)(k * kBT + gt) * EV);
           }
+        } else if (sizeof(E) < 4 && !aligned && cnt == (uint32_t)TL::T && ((uintptr_t)(sym + t0) & 15u) != 0) {
+          // whole tile of a u8/u16 sequence that starts off a 16-byte boundary (forest trees at
+          // arbitrary offsets): the two aligned blocks of every vector in flight at once, then
+          // funnel-shifted (every vector of the tile has the same misalignment; both blocks hold
+          // bytes of the tile). Not compiled for u32, whose dense count would lose occupancy.
+          const uint32_t m = (uint32_t)((uintptr_t)(sym + t0) & 15u);
+          u32x4 va[NCH], vb[NCH];
+#pragma unroll
+          for (int k = 0; k < NCH; ++k) {
+            const auto blk = pcast<const u32x4>(pcast<const char>(sym + t0 + (uint32_t)(k * kBT + gt) * EV) - m);
+            va[k] = blk[0];
+            vb[k] = blk[1];
+          }
+#pragma unroll
+          for (int k = 0; k < NCH; ++k) {
+            uint32_t y[4];
+            funnel16(va[k], vb[k], m, y);
+            uint4 x;
+            __builtin_memcpy(&x, y, 16);
+            if (full) {
+#pragma unroll
+              for (int e = 0; e < EV; ++e) atomicAdd(&my_h[vec_elem<E>(x, e)], 1u);
+              ones += vec_count_bit<E>(x, lsh);
+            } else {
+              count_vec(x, (uint32_t)(k * kBT + gt) * EV);
+            }
+          }
         } else {
-          // ragged last tile or unaligned sequence: one vector at a time
+          // ragged last tile: one vector at a time
 #pragma unroll 1
           for (int k = 0; k < NCH; ++k) {
             const uint32_t q0 = (uint32_t)(k * kBT + gt) * EV;

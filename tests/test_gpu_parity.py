@@ -136,12 +136,14 @@ def test_symbol_out_of_range_is_reported_every_histogram(width, sigma):
     assert ei.value.status == wt.WT_ERR_SYMBOL_RANGE
 
 
-@pytest.mark.parametrize("width,sigma,shift", [(1, 7, 1), (1, 200, 13), (2, 1000, 1), (2, 40000, 5), (2, 7, 7),
-                                               (4, 3000, 1), (4, 3000, 3), (4, 1 << 20, 2)])
+@pytest.mark.parametrize("width,sigma,shift", [(1, 7, 1), (1, 200, 13), (1, 200, 5), (1, 256, 3), (2, 1000, 1),
+                                               (2, 40000, 5), (2, 7, 7), (2, 300, 3), (2, 1 << 16, 3), (4, 3000, 1),
+                                               (4, 3000, 3), (4, 1 << 20, 2)])
 def test_unaligned_input_pointer(width, sigma, shift):
     """Symbols starting `shift` elements past a 16-byte boundary: every vector of the histogram and of
-    level 0 is read across two aligned blocks (each funnel shift; non-power-of-two alphabets take
-    the reduced codes of level 0)."""
+    level 0 is read across two aligned blocks (each funnel shift, whole tiles and the ragged last
+    one; alphabets covering the whole symbol type take the histogram's full-range count;
+    non-power-of-two alphabets take the reduced codes of level 0)."""
     import torch
     import paper_2505_03372_amd as wt
     n = 70001
