@@ -317,6 +317,8 @@ def main():
     ap.add_argument("--workload", default="text_zipf")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-learned", action="store_true", help="skip the learned select index (training + queries)")
+    ap.add_argument("--l2-bits", type=int, default=0, help="bits per L2 block (256..2048; 0: library default)")
+    ap.add_argument("--sample-rate", type=int, default=0, help="select sample rate s (0: library default)")
     ap.add_argument("--cpu-sample-log2", type=int, default=25)
     ap.add_argument("--cpu-queries-log2", type=int, default=20)
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -363,7 +365,7 @@ def main():
     wt.query_profiling(True)
 
     def step(record):
-        t = wt.build(S, sigma, profile=True)
+        t = wt.build(S, sigma, l2_bits=args.l2_bits, sample_rate=args.sample_rate, profile=True)
         evs = {}
         linfo = None
         if "select" in kinds and not args.no_learned:
@@ -455,13 +457,15 @@ def main():
     if dom == "level":
         roof = build_roof
     else:
-        qbytes = 64.0 * info["levels"] * q
+        blk = info["l2_bits"] // 8  # bytes of one L2 block of bits
+        qbytes = float(blk) * info["levels"] * q
         qa = qbytes / (per_step[dom] * 1e-3) / 1e9
         roof = {"kernel": {"access": "k_access", "rank": "k_rank", "select": "k_select",
-                           "select_learned": "k_select_learned"}[dom] + "<9, 1024u>",
+                           "select_learned": "k_select_learned"}[dom]
+                          + "<%d, 1024u>" % (info["l2_bits"].bit_length() - 1),
                 "bound": "hbm", "achieved": qa, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": qa / HBM_PEAK_GBS,
                 "traffic": None, "bytes_per_launch": qbytes, "avg_launch_ms": per_step[dom], "launches": len(kms[dom]),
-                "note": "random access: 64 B (one L2 block of bits) per level per query"}
+                "note": "random access: %d B (one L2 block of bits) per level per query" % blk}
         if args.workload == "text_zipf":
             roof["traffic"] = load_query_traffic(roof["kernel"], q)
     line = {
@@ -478,7 +482,7 @@ def main():
         "dtype": {1: "u8", 2: "u16", 4: "u32"}[width],
         "data": "synthetic",
         "config": {"workload": args.workload, "n": n, "sym_bytes": width, "sigma": sigma, "queries_per_kind": q,
-                   "query_kinds": list(kinds), "l2_bits": 512, "sample_rate": 4096},
+                   "query_kinds": list(kinds), "l2_bits": info["l2_bits"], "sample_rate": info["sample_rate"]},
         "rates": rates,
         "roofline": roof,
         "roofline_build": build_roof,
