@@ -49,18 +49,21 @@ __device__ __forceinline__ float mlp_eval(const float* __restrict__ p, float u) 
   return y;
 }
 
-// Adds the contribution of one point (u, v) to the loss and the gradient (scale = 2 / P).
-__device__ __forceinline__ void mlp_point(const float* __restrict__ p, float u, float v, float scale, float* g,
-                                          float& loss) {
+// Adds the contribution of one point (u, v) to the loss and the gradient (scale = 2 / P); a point with
+// scale = wl = 0 adds nothing (a thread's unused point slots), so every slot is computed without a
+// branch and the slots' independent chains overlap. The output sum is taken as four partial sums.
+__device__ __forceinline__ void mlp_point(const float* __restrict__ p, float u, float v, float scale, float wl,
+                                          float* g, float& loss) {
   float h[kH];
-  float y = p[3 * kH];
+  float ys[4] = {p[3 * kH], 0.f, 0.f, 0.f};
 #pragma unroll
   for (int k = 0; k < kH; ++k) {
     h[k] = fmaf(p[k], u, p[kH + k]);
-    y += p[2 * kH + k] * fmaxf(h[k], 0.f);
+    ys[k & 3] = fmaf(p[2 * kH + k], fmaxf(h[k], 0.f), ys[k & 3]);
   }
+  const float y = (ys[0] + ys[1]) + (ys[2] + ys[3]);
   const float r = y - v;
-  loss += r * r;
+  loss += wl * (r * r);
   const float gy = scale * r;
   g[3 * kH] += gy;
 #pragma unroll
@@ -87,7 +90,11 @@ __device__ void block_loss_grad(const float* __restrict__ p, const float* u, con
 #pragma unroll
   for (int j = 0; j < kNP; ++j) g[j] = 0.f;
   float loss = 0.f;
-  for (int i = 0; i < nmine; ++i) mlp_point(p, u[i], v[i], scale, g, loss);
+#pragma unroll
+  for (int i = 0; i < kPMax / kLT; ++i) {
+    const bool use = i < nmine;
+    mlp_point(p, u[i], v[i], use ? scale : 0.f, use ? 1.f : 0.f, g, loss);
+  }
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   // Wave reduce-scatter of the 64 slots [loss, g, 0...]: at each halving step a lane keeps one half
   // of its current slots and adds the partner's copy of that half; lane l ends with the wave total
