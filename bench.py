@@ -399,6 +399,29 @@ def main():
         step(recs)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
+    wt.query_profiling(False)
+    unbinned = None
+    if "select" in kinds and not args.no_learned:
+        # Outside the timed steps: select in batches below the binning size (answered in input order,
+        # so every level's reads land on random lines), where the learned index saves the node entry,
+        # the samples and the L1 search that binned batches turn into shared cache hits.
+        t = wt.build(S, sigma, l2_bits=args.l2_bits, sample_rate=args.sample_rate)
+        t.learn_select()
+        sc, sk = kinds["select"]
+        nq, chunk = min(q, 1 << 24), 1 << 15
+        unbinned = {"queries": nq, "batch": chunk}
+        for variant, fn, out in (("plain", t.select, outs["select"]), ("learned", t.select_learned,
+                                                                        outs["select_learned"])):
+            for _ in range(2):  # the first pass warms up
+                e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                e0.record(stream)
+                for i in range(0, nq, chunk):
+                    fn(sc[i:i + chunk], sk[i:i + chunk], out=out[i:i + chunk])
+                e1.record(stream)
+                torch.cuda.synchronize()
+            unbinned[variant + "_ms"] = e0.elapsed_time(e1)
+        unbinned["learned_vs_plain_speedup"] = unbinned["plain_ms"] / unbinned["learned_ms"]
+        t.free()
     ms_per_step = (t1 - t0) * 1e3 / args.steps
 
     info = recs[0][2]
@@ -430,6 +453,8 @@ def main():
         rates["learned_mean_err_blocks"] = li["mean_err_blocks"]
         rates["untrained_mean_err_blocks"] = li["mean_err_init_blocks"]
         rates["learned_vs_plain_select_speedup"] = float(np.median(qms["select"]) / np.median(qms["select_learned"]))
+    if unbinned is not None:
+        rates["select_unbinned"] = unbinned
     for k in qms:
         rates[k + "_ms_median"] = float(np.median(qms[k]))
     # kernels of the query calls: traversal kernels and the binning passes (per call, summed over kinds)

@@ -22,6 +22,10 @@ constexpr int kNP = 3 * kH + 1;  // parameters: w1[16], b1[16], w2[16], b2
 #ifndef WT_LEARN_LEAD_EPS
 #define WT_LEARN_LEAD_EPS 0
 #endif
+// form of the sampled search taken by waves whose lanes are on different models
+#ifndef WT_LEARN_MIXED_LINE
+#define WT_LEARN_MIXED_LINE true
+#endif
 constexpr uint64_t kLearnLead = WT_LEARN_LEAD;
 
 // Query form of a trained model. With one input, the network is linear between the points where a
@@ -240,9 +244,14 @@ __device__ __forceinline__ uint64_t select_learned_one(const QArgs& a, const Lev
       at = select_learned_at<L2S, GS, true>(a.d, meta[l], Q, r, a.sshift);
       start = Q.start;
     } else {
-      const LearnQ& Q = qm[mi];
-      at = select_learned_at<L2S, GS>(a.d, meta[l], Q, r, a.sshift);
-      start = Q.start;
+      // Lanes on different models (small unbinned batches): each would read its own model through
+      // two dependent vector loads, which costs more than the sampled search it replaces, so this
+      // level takes the sampled search (the node entry gives the same target and start as the model).
+      const uint64_t p = l ? (uint64_t)(code >> (a.L - l)) : 0ull;
+      const uint32_t b = (code >> (a.L - 1 - l)) & 1u;
+      const NodeQ nd = a.d.nodes[(1ull << l) - 1 + p];
+      at = select_at<L2S, WT_LEARN_MIXED_LINE>(a.d, meta[l], b, b ? (nd.start - nd.r0) + r : nd.r0 + r, a.sshift);
+      start = nd.start;
     }
     r = at - start + 1;
   }
