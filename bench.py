@@ -1,6 +1,7 @@
 """Benchmark of the wavelet-tree hot path on one MI355X.
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload text_zipf|forest|serve]
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload text_zipf|large_alpha|forest|serve]
+                    [--l2-bits B] [--sample-rate S] [--no-learned] [--no-cpu-baseline]
 
 One step = one pass of the whole hot path over one batch of synthetic input already resident in
 HBM: build the level-wise wavelet tree of n symbols (histogram, node tables, every level's bits,
@@ -14,6 +15,8 @@ step; `roofline_build` the build's level pass, timed with HIP events recorded by
 around every level launch on the build stream; `roofline_build_total` the whole build (histogram
 read plus every level pass, over the median build time).
 `cpu_baseline` times the plain CPU oracle on a bounded prefix of the same workload.
+`rates.select_unbinned` compares plain and learned select on 2^24 of the queries asked in batches of
+2^15 (below the binning size), outside the timed steps.
 
 --workload forest: 1024 u16 sequences (lengths log-uniform in [2^10, 2^24], alphabets log-uniform in
 [4, 2^16], Zipf 1.0) built as one forest (one captured graph launch, |L2| and s from the autotuner)

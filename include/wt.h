@@ -195,8 +195,11 @@ typedef struct {
 /* Trains (or retrains) the models of a tree; enqueued on `stream`, waits for completion. */
 wt_status wt_learn_select(wt_tree* t, const wt_learn_opts* opts, wt_stream_t stream);
 
-/* Batched select through the learned index (same arguments and results as wt_select).
-   WT_ERR_STATE if wt_learn_select has not been called on the tree. */
+/* Batched select through the learned index (same arguments and results as wt_select). On every
+   level, a wavefront whose queries share the level's model predicts the L2 block with it and corrects
+   the prediction exactly; a wavefront whose queries are on different models (small unbinned batches)
+   takes the sampled binary search of wt_select for that level, as does a prediction that misses by
+   more than the model's error budget. WT_ERR_STATE if wt_learn_select has not been called on the tree. */
 wt_status wt_select_learned(const wt_tree* t, const uint32_t* d_sym, const uint64_t* d_k, uint64_t q,
                             uint64_t* d_out, wt_stream_t stream);
 
