@@ -594,7 +594,9 @@ extern "C" wt_status wt_build_forest(const wt_seq_desc* h_descs, uint32_t count,
   MapBuilder m_init, m_hist_small, m_hist_big, m_hist_hash, m_scan_c, m_scan_z, m_node, m_tile, m_level;
   uint64_t all_tiles = 0;
   for (uint32_t j = 0; j < count; ++j) all_tiles += sh[j].n ? ceil_div(sh[j].n, T) : 0;
-  const uint64_t hist_tpb = hist_tiles_per_block(all_tiles);
+  // histogram blocks of a quarter of the single-tree size: most of a forest's trees get one block,
+  // and shorter blocks for the long ones leave a shorter tail behind the last full round of blocks
+  const uint64_t hist_tpb = std::max<uint64_t>(ceil_div(all_tiles, 4 * kHTargetBlocks), kHMinTiles);
   std::vector<uint32_t> active(Lmax + 1, 0);  // trees with more than l levels
   for (uint32_t s = 0; s < count; ++s) {
     const uint32_t j = order[s];
