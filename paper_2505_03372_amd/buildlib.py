@@ -2,7 +2,8 @@
 
     python -m paper_2505_03372_amd.buildlib
 
-Compiles csrc/*.hip with hipcc into one shared library exporting the C ABI of include/wt.h.
+Compiles every csrc/*.hip with hipcc (one process per source, in parallel) and links the objects into
+one shared library exporting the C ABI of include/wt.h.
 """
 from __future__ import annotations
 
@@ -10,18 +11,19 @@ import glob
 import os
 import subprocess
 import sys
+from concurrent.futures import ThreadPoolExecutor
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "libwt.so")
 ARCH = os.environ.get("WT_OFFLOAD_ARCH", "gfx950")
+OBJDIR = os.path.join(HERE, "_build")
 
 HIPCC_FLAGS = [
     "--offload-arch=" + ARCH,
     "-O3",
     "-std=c++17",
     "-fPIC",
-    "-shared",
     "-Wall",
     "-Wno-unused-function",
     # keep the compiler from forming packed FP32 instructions (none of this code needs them)
@@ -33,13 +35,34 @@ def sources():
     return sorted(glob.glob(os.path.join(HERE, "csrc", "*.hip")))
 
 
+def _jobs() -> int:
+    try:
+        return max(1, min(16, int(os.environ.get("MAX_JOBS", "0")) or os.cpu_count() or 1))
+    except ValueError:
+        return 4
+
+
 def build(verbose: bool = False) -> str:
     hipcc = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
+    os.makedirs(OBJDIR, exist_ok=True)
+    inc = ["-I", os.path.join(ROOT, "include")]
+    objs = []
+    cmds = []
+    for src in sources():
+        obj = os.path.join(OBJDIR, os.path.splitext(os.path.basename(src))[0] + ".o")
+        objs.append(obj)
+        cmds.append([hipcc] + HIPCC_FLAGS + inc + ["-c", src, "-o", obj])
+
+    def run(cmd):
+        if verbose:
+            print(" ".join(cmd), flush=True)
+        subprocess.check_call(cmd)
+
+    with ThreadPoolExecutor(max_workers=_jobs()) as ex:
+        list(ex.map(run, cmds))
     tmp = LIB + ".tmp%d" % os.getpid()
-    cmd = [hipcc] + HIPCC_FLAGS + ["-I", os.path.join(ROOT, "include")] + sources() + ["-o", tmp]
-    if verbose:
-        print(" ".join(cmd), flush=True)
-    subprocess.check_call(cmd)
+    link = [hipcc, "--offload-arch=" + ARCH, "-shared", "-fPIC"] + objs + ["-o", tmp]
+    run(link)
     os.replace(tmp, LIB)
     return LIB
 
