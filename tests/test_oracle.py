@@ -289,3 +289,41 @@ def test_mlp_reference_gradients_match_finite_differences():
 def test_mlp_init_is_identity_on_unit_interval():
     u = np.linspace(0, 1, 101)
     assert np.allclose(oracle.mlp_forward(oracle.mlp_init(), u), u, atol=1e-15)
+
+
+def _mlp_clamp_theta():
+    """A network whose units are negative on part of [0, 1] (and two of them everywhere):
+    unit 0: h = 2u - 0.5 (on for u > 1/4), weight 3; unit 1: h = 0.25 - u (on for u < 1/4), weight -2;
+    units 2..15: h = -1 (never on), weight 1; output bias 0.1."""
+    th = np.zeros(oracle.MLP_PARAMS)
+    th[0], th[16], th[32] = 2.0, -0.5, 3.0
+    th[1], th[17], th[33] = -1.0, 0.25, -2.0
+    for k in range(2, 16):
+        th[k], th[16 + k], th[32 + k] = 0.0, -1.0, 1.0
+    th[48] = 0.1
+    return th
+
+
+def test_mlp_forward_hand_values_where_relu_clamps():
+    # y(u) = 0.1 + 3 max(2u - 0.5, 0) - 2 max(0.25 - u, 0) + 14 max(-1, 0), worked by hand:
+    #   u = 0:    0.1 + 0   - 0.5 = -0.4      u = 0.1: 0.1 + 0 - 0.3 = -0.2
+    #   u = 0.25: 0.1 + 0   - 0   =  0.1      u = 0.5: 0.1 + 1.5 - 0 = 1.6
+    #   u = 1:    0.1 + 4.5 - 0   =  4.6
+    # Dropping the clamp would add 14 * (-1) plus the negative parts of units 0 and 1.
+    th = _mlp_clamp_theta()
+    u = np.array([0.0, 0.1, 0.25, 0.5, 1.0])
+    exp = np.array([-0.4, -0.2, 0.1, 1.6, 4.6])
+    np.testing.assert_allclose(oracle.mlp_forward(th, u), exp, rtol=0, atol=1e-12)
+
+
+def test_mlp_gradient_hand_values_where_relu_clamps():
+    # One point (u, v) = (0.5, 1.0): y = 1.6, r = 0.6, loss = 0.36, dL/dy = 2 r = 1.2.
+    # Unit 0 is on (h0 = 0.5): dL/dw2_0 = 1.2 * 0.5 = 0.6, dL/db1_0 = 1.2 * 3 = 3.6, dL/dw1_0 = 3.6 * 0.5 = 1.8.
+    # Unit 1 (h1 = -0.25) and units 2..15 (h = -1) are off: every derivative of theirs is 0.
+    # dL/db2 = 1.2.
+    th = _mlp_clamp_theta()
+    loss, g = oracle.mlp_loss_grad(th, np.array([0.5]), np.array([1.0]))
+    assert abs(loss - 0.36) < 1e-12
+    exp = np.zeros(oracle.MLP_PARAMS)
+    exp[32], exp[16], exp[0], exp[48] = 0.6, 3.6, 1.8, 1.2
+    np.testing.assert_allclose(g, exp, rtol=0, atol=1e-12)
