@@ -102,23 +102,57 @@ def load_query_traffic(kernel: str, q: int):
     return k["traffic_bytes"] if k else None
 
 
-def cpu_baseline(name: str, n_sample: int, q_sample: int) -> dict:
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(name: str, n_sample: int, q_sample: int, runs: int = 3) -> dict:
+    """The CPU oracle on a bounded prefix of the workload: every level's bits, directory and samples,
+    then access/rank/select by sweeps, once on one thread and once on every host thread (OpenMP),
+    median of `runs` runs each."""
     import oracle
     import workloads
     S, sigma = workloads.make_text(name, n=n_sample)
     qs = workloads.make_queries(name, S, sigma, q=q_sample)
-    t0 = time.perf_counter()
-    oracle.OracleTree(S, sigma)
-    t1 = time.perf_counter()
-    oracle.access(S, qs["acc_pos"])
-    oracle.rank(S, sigma, qs["rank_c"], qs["rank_i"])
-    oracle.select(S, sigma, qs["sel_c"], qs["sel_k"])
-    t2 = time.perf_counter()
     items = n_sample + 3 * q_sample
-    return {"value": items / (t2 - t0), "unit": "(symbols+queries)/s", "cores": 1, "kind": "oracle",
-            "sample": "first 2^%d symbols of the same text (oracle build of every level, directory, samples and "
-                      "node tables: %.2f s) + 2^%d access, rank and select queries drawn with the same recipe "
-                      "(sweeps: %.2f s)" % (n_sample.bit_length() - 1, t1 - t0, q_sample.bit_length() - 1, t2 - t1)}
+
+    def leg(nt):
+        tb, tq = [], []
+        for _ in range(runs):
+            t0 = time.perf_counter()
+            oracle.par_tree(S, sigma, nthreads=nt)
+            t1 = time.perf_counter()
+            oracle.par_access(S, qs["acc_pos"], nt)
+            oracle.par_rank(S, sigma, qs["rank_c"], qs["rank_i"], nt)
+            oracle.par_select(S, sigma, qs["sel_c"], qs["sel_k"], nt)
+            t2 = time.perf_counter()
+            tb.append(t1 - t0)
+            tq.append(t2 - t1)
+        tot = [a + b for a, b in zip(tb, tq)]
+        return {"value": items / float(np.median(tot)), "threads": nt, "build_s_median": float(np.median(tb)),
+                "queries_s_median": float(np.median(tq))}
+
+    all_threads = oracle.par_threads(0)
+    one = leg(1)
+    many = leg(all_threads)
+    try:
+        affinity = len(os.sched_getaffinity(0))
+    except AttributeError:
+        affinity = os.cpu_count()
+    return {"value": many["value"], "unit": "(symbols+queries)/s", "cores": all_threads, "kind": "oracle",
+            "sample": "first 2^%d symbols of the same text (every level's bits, rank directory and select samples, "
+                      "one level per thread) + 2^%d access, rank and select queries drawn with the same recipe "
+                      "(chunked sweeps over the text); median of %d runs"
+                      % (n_sample.bit_length() - 1, q_sample.bit_length() - 1, runs),
+            "single_thread": one, "all_threads": many, "cpu_model": cpu_model(), "nproc": os.cpu_count(),
+            "affinity_cpus": affinity, "omp_num_threads": os.environ.get("OMP_NUM_THREADS")}
 
 
 def forest_level_bytes(f, w: int) -> float:
@@ -319,6 +353,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="text_zipf")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-extra", action="store_true", help="skip the large-alphabet leg of the default run")
     ap.add_argument("--no-learned", action="store_true", help="skip the learned select index (training + queries)")
     ap.add_argument("--l2-bits", type=int, default=0, help="bits per L2 block (256..2048; 0: library default)")
     ap.add_argument("--sample-rate", type=int, default=0, help="select sample rate s (0: library default)")
@@ -344,10 +379,63 @@ def main():
         return main_forest(args, torch, wt, workloads, dev)
     if args.workload == "serve":
         return main_serve(args, torch, wt, workloads, dev)
-    idx, n, width, sigma, q = workloads.CONFIGS[args.workload]
-    print("# generating workload %s: n=%d width=%d sigma=%d q=%d" % (args.workload, n, width, sigma, q),
+    res = run_tree(args, torch, wt, workloads, dev, args.workload, args.steps, args.warmup,
+                   learned=not args.no_learned, kinds_wanted=("access", "rank", "select"))
+    n, width, sigma, q = res["n"], res["width"], res["sigma"], res["q"]
+    ms_per_step = res["ms_per_step"]
+    line = {
+        "metric": "build symbols/s + access/rank/select queries/s; learned vs plain select",
+        "value": res["items"] / (ms_per_step * 1e-3),
+        "unit": "(symbols+queries)/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": {1: "u8", 2: "u16", 4: "u32"}[width],
+        "data": "synthetic",
+        "config": {"workload": args.workload, "n": n, "sym_bytes": width, "sigma": sigma, "queries_per_kind": q,
+                   "query_kinds": res["kinds"], "l2_bits": res["info"]["l2_bits"],
+                   "sample_rate": res["info"]["sample_rate"]},
+        "rates": res["rates"],
+        "roofline": res["roofline"],
+        "roofline_build": res["roofline_build"],
+        "roofline_build_total": res["roofline_build_total"],
+    }
+    if args.workload == "text_zipf" and not args.no_extra:
+        # the large-alphabet configuration (2^28 u32 symbols, sigma 2^20, 2^24 rank + 2^24 select), measured
+        # in the same run after the main workload, outside its timed steps
+        print("# large-alphabet leg", file=sys.stderr, flush=True)
+        la = run_tree(args, torch, wt, workloads, dev, "large_alpha", 5, 2, learned=False,
+                      kinds_wanted=("rank", "select"))
+        line["large_alpha"] = {
+            "config": {"workload": "large_alpha", "n": la["n"], "sym_bytes": la["width"], "sigma": la["sigma"],
+                       "queries_per_kind": la["q"], "query_kinds": la["kinds"], "steps": 5, "warmup": 2},
+            "ms_per_step": la["ms_per_step"], "value": la["items"] / (la["ms_per_step"] * 1e-3),
+            "unit": "(symbols+queries)/s", "rates": la["rates"], "roofline": la["roofline"],
+            "roofline_build": la["roofline_build"], "roofline_build_total": la["roofline_build_total"]}
+    if args.calibrate_copy:
+        src = torch.empty(1 << 30, dtype=torch.uint8, device=dev)
+        dst = torch.empty_like(src)
+        for _ in range(2):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        line["calibration_copy_bytes"] = 1 << 30
+        del src, dst
+    if not args.no_cpu_baseline:
+        print("# timing the CPU oracle on a bounded sample", file=sys.stderr, flush=True)
+        line["cpu_baseline"] = cpu_baseline(args.workload, 1 << args.cpu_sample_log2, 1 << args.cpu_queries_log2)
+    print(json.dumps(line), flush=True)
+
+
+def run_tree(args, torch, wt, workloads, dev, name, steps, warmup, learned, kinds_wanted):
+    """Timed steps of one single-tree workload: build (+ learned-index training) + queries + free."""
+    idx, n, width, sigma, q = workloads.CONFIGS[name]
+    print("# generating workload %s: n=%d width=%d sigma=%d q=%d" % (name, n, width, sigma, q),
           file=sys.stderr, flush=True)
-    wl = workloads.make(args.workload)
+    wl = workloads.make(name, kinds=kinds_wanted)
     S = torch.from_numpy(wl.S).to(dev)
     kinds = {}
     if wl.acc_pos is not None:
@@ -366,12 +454,21 @@ def main():
 
     stream = torch.cuda.current_stream()
     wt.query_profiling(True)
+    use_learned = learned and "select" in kinds
 
     def step(record):
+        # the build is timed by one event pair around the whole wt_build call on its stream (it includes
+        # the library's allocations, launch gaps and the final read-back of the level sizes), beside the
+        # sum of the per-kernel events the library records and the host wall time of the call
+        eb0, eb1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        eb0.record(stream)
+        h0 = time.perf_counter()
         t = wt.build(S, sigma, l2_bits=args.l2_bits, sample_rate=args.sample_rate, profile=True)
+        h1 = time.perf_counter()
+        eb1.record(stream)
         evs = {}
         linfo = None
-        if "select" in kinds and not args.no_learned:
+        if use_learned:
             linfo = t.learn_select()
         for kind, a in kinds.items():
             for variant in (("plain", "learned") if kind == "select" and linfo is not None else ("plain",)):
@@ -390,21 +487,21 @@ def main():
                 evs[kind if variant == "plain" else "select_learned"] = (e0, e1)
         qprof = wt.query_profile()  # per-kernel durations of this step's query calls (waits for them)
         if record is not None:
-            record.append((t.profile(), evs, t.info, linfo, qprof))
+            record.append((t.profile(), evs, t.info, linfo, qprof, (eb0, eb1), (h1 - h0) * 1e3))
         t.free()
 
-    for _ in range(args.warmup):
+    for _ in range(warmup):
         step(None)
     torch.cuda.synchronize()
     recs = []
     t0 = time.perf_counter()
-    for _ in range(args.steps):
+    for _ in range(steps):
         step(recs)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     wt.query_profiling(False)
     unbinned = None
-    if "select" in kinds and not args.no_learned:
+    if use_learned:
         # Outside the timed steps: select in batches below the binning size (answered in input order,
         # so every level's reads land on random lines), where the learned index saves the node entry,
         # the samples and the L1 search that binned batches turn into shared cache hits.
@@ -425,17 +522,19 @@ def main():
             unbinned[variant + "_ms"] = e0.elapsed_time(e1)
         unbinned["learned_vs_plain_speedup"] = unbinned["plain_ms"] / unbinned["learned_ms"]
         t.free()
-    ms_per_step = (t1 - t0) * 1e3 / args.steps
+    ms_per_step = (t1 - t0) * 1e3 / steps
 
     info = recs[0][2]
-    level_ms, build_ms, learn_ms = [], [], []
+    level_ms, build_ms, build_ev_ms, build_wall_ms, learn_ms = [], [], [], [], []
     qms = {}
     kms = {}
-    for prof, evs, _, linfo, qprof in recs:
+    for prof, evs, _, linfo, qprof, (eb0, eb1), wall in recs:
         for e in qprof:
             kms.setdefault(e["kernel"], []).append(e["ms"])
         level_ms += [p["ms"] for p in prof if p["kernel"] == "level"]
         build_ms.append(sum(p["ms"] for p in prof))
+        build_ev_ms.append(eb0.elapsed_time(eb1))
+        build_wall_ms.append(wall)
         if linfo is not None:
             learn_ms.append(linfo["train_ms"])
         for k, (e0, e1) in evs.items():
@@ -445,10 +544,13 @@ def main():
     avg_ms = float(np.mean(level_ms))
     achieved = avg_bytes / (avg_ms * 1e-3) / 1e9
     items = n + q * len(qms)
-    rates = {"build_symbols_per_s": n / (np.median(build_ms) * 1e-3)}
+    bms = float(np.median(build_ev_ms))
+    rates = {"build_symbols_per_s": n / (bms * 1e-3)}
     for k in qms:
         rates[k + "_queries_per_s"] = q / (np.median(qms[k]) * 1e-3)
-    rates["build_ms_median"] = float(np.median(build_ms))
+    rates["build_ms_median"] = bms
+    rates["build_kernel_sum_ms_median"] = float(np.median(build_ms))
+    rates["build_host_wall_ms_median"] = float(np.median(build_wall_ms))
     if learn_ms:
         rates["learn_train_ms_median"] = float(np.median(learn_ms))
         li = recs[0][3]
@@ -467,15 +569,17 @@ def main():
     kname = {1: "k_level<uint8_t>", 2: "k_level<uint16_t>", 4: "k_level<uint32_t>"}[width]
     build_roof = {"kernel": kname, "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                   "frac": achieved / HBM_PEAK_GBS,
-                  "traffic": load_traffic(avg_bytes) if args.workload == "text_zipf" else None,
+                  "traffic": load_traffic(avg_bytes) if name == "text_zipf" else None,
                   "bytes_per_launch": avg_bytes, "avg_launch_ms": avg_ms, "launches": len(level_ms)}
     # the whole build (every kernel between the symbols on the device and the finished tree): one read
-    # of the symbols for the histogram plus every level pass's bytes
+    # of the symbols for the histogram plus every level pass's bytes, over the event pair around wt_build
+    # (frac) and over the sum of the kernels' own events (frac_kernel_sum)
     total_bytes = float(n * width + sum(per_launch))
-    bms = float(np.median(build_ms))
+    ksum = float(np.median(build_ms))
     build_total = {"bound": "hbm", "bytes": total_bytes, "ms": bms,
                    "achieved": total_bytes / (bms * 1e-3) / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                   "frac": total_bytes / (bms * 1e-3) / 1e9 / HBM_PEAK_GBS}
+                   "frac": total_bytes / (bms * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                   "ms_kernel_sum": ksum, "frac_kernel_sum": total_bytes / (ksum * 1e-3) / 1e9 / HBM_PEAK_GBS}
     # the kernel with the most time in a step: queries touch at least one 64-byte L2 block of bits per
     # level (random HBM lines), the level pass streams its level
     # the traversal kernel of each query kind, timed alone (events around the kernel on its stream)
@@ -494,40 +598,14 @@ def main():
                 "bound": "hbm", "achieved": qa, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": qa / HBM_PEAK_GBS,
                 "traffic": None, "bytes_per_launch": qbytes, "avg_launch_ms": per_step[dom], "launches": len(kms[dom]),
                 "note": "random access: %d B (one L2 block of bits) per level per query" % blk}
-        if args.workload == "text_zipf":
+        if name == "text_zipf":
             roof["traffic"] = load_query_traffic(roof["kernel"], q)
-    line = {
-        "metric": "build symbols/s + access/rank/select queries/s; learned vs plain select",
-        "value": items / (ms_per_step * 1e-3),
-        "unit": "(symbols+queries)/s",
-        "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
-        "ms_per_step": ms_per_step,
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": {1: "u8", 2: "u16", 4: "u32"}[width],
-        "data": "synthetic",
-        "config": {"workload": args.workload, "n": n, "sym_bytes": width, "sigma": sigma, "queries_per_kind": q,
-                   "query_kinds": list(kinds), "l2_bits": info["l2_bits"], "sample_rate": info["sample_rate"]},
-        "rates": rates,
-        "roofline": roof,
-        "roofline_build": build_roof,
-        "roofline_build_total": build_total,
-    }
-    if args.calibrate_copy:
-        src = torch.empty(1 << 30, dtype=torch.uint8, device=dev)
-        dst = torch.empty_like(src)
-        for _ in range(2):
-            dst.copy_(src)
-        torch.cuda.synchronize()
-        line["calibration_copy_bytes"] = 1 << 30
-        del src, dst
-    if not args.no_cpu_baseline:
-        print("# timing the CPU oracle on a bounded sample", file=sys.stderr, flush=True)
-        line["cpu_baseline"] = cpu_baseline(args.workload, 1 << args.cpu_sample_log2, 1 << args.cpu_queries_log2)
-    print(json.dumps(line), flush=True)
+    del S, kinds, outs
+    torch.cuda.synchronize()
+    torch.cuda.empty_cache()
+    return {"n": n, "width": width, "sigma": sigma, "q": q, "kinds": list(qms.keys()), "info": info,
+            "items": items, "ms_per_step": ms_per_step, "rates": rates, "roofline": roof,
+            "roofline_build": build_roof, "roofline_build_total": build_total}
 
 
 if __name__ == "__main__":

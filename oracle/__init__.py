@@ -19,6 +19,7 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "wt_oracle.c")
+_SRC_PAR = os.path.join(_HERE, "wt_oracle_par.c")
 _LIB = os.path.join(_HERE, "libwtoracle.so")
 
 ACCESS_INVALID = 0xFFFFFFFF
@@ -30,10 +31,11 @@ _u16p = ctypes.POINTER(ctypes.c_uint16)
 
 
 def build_lib(force: bool = False) -> str:
-    """Compile wt_oracle.c into libwtoracle.so with gcc."""
-    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+    """Compile wt_oracle.c and its all-core form wt_oracle_par.c (OpenMP) into libwtoracle.so with gcc."""
+    newest = max(os.path.getmtime(_SRC), os.path.getmtime(_SRC_PAR))
+    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < newest:
         tmp = _LIB + ".tmp%d" % os.getpid()
-        subprocess.check_call(["gcc", "-O2", "-fPIC", "-shared", "-o", tmp, _SRC])
+        subprocess.check_call(["gcc", "-O2", "-fPIC", "-shared", "-fopenmp", "-o", tmp, _SRC, _SRC_PAR])
         os.replace(tmp, _LIB)
     return _LIB
 
@@ -67,6 +69,19 @@ def lib():
         L.oracle_mlp_forward.argtypes = [_f64p, ctypes.c_double]
         L.oracle_mlp_loss_grad.restype = ctypes.c_double
         L.oracle_mlp_loss_grad.argtypes = [_f64p, _f64p, _f64p, ctypes.c_int, _f64p]
+        L.oracle_par_threads.restype = ctypes.c_int
+        L.oracle_par_threads.argtypes = [ctypes.c_int]
+        L.oracle_par_access.argtypes = [ctypes.c_void_p, ctypes.c_uint64, ctypes.c_int, _u64p, ctypes.c_uint64, _u32p,
+                                        ctypes.c_int]
+        L.oracle_par_rank.argtypes = [ctypes.c_void_p, ctypes.c_uint64, ctypes.c_int, ctypes.c_uint64, _u32p, _u64p,
+                                      ctypes.c_uint64, _u64p, ctypes.c_int]
+        L.oracle_par_select.argtypes = [ctypes.c_void_p, ctypes.c_uint64, ctypes.c_int, ctypes.c_uint64, _u32p,
+                                        _u64p, ctypes.c_uint64, _u64p, ctypes.c_int]
+        L.oracle_par_tree.restype = ctypes.c_int
+        L.oracle_par_tree.argtypes = [ctypes.c_void_p, ctypes.c_uint64, ctypes.c_int, ctypes.c_uint64,
+                                      ctypes.c_uint64, ctypes.c_uint64, ctypes.c_uint64, _u64p, _u64p,
+                                      ctypes.c_uint64, _u64p, ctypes.c_uint64, _u16p, ctypes.c_uint64, _u64p, _u64p,
+                                      _u64p, _u64p, ctypes.c_int]
         _lib = L
     return _lib
 
@@ -188,6 +203,80 @@ def select(S: np.ndarray, sigma: int, c: np.ndarray, k: np.ndarray) -> np.ndarra
     out = np.empty(c.size, dtype=np.uint64)
     lib().oracle_select(ctypes.c_void_p(S.ctypes.data), S.size, S.dtype.itemsize, sigma, _p(c, _u32p),
                         _p(k, _u64p), c.size, _p(out, _u64p))
+    return out
+
+
+# ---- all-core form (OpenMP; wt_oracle_par.c): same answers, work spread over host threads ----
+
+
+def par_threads(nthreads: int = 0) -> int:
+    """Threads the all-core functions use (0: OpenMP's default, i.e. OMP_NUM_THREADS or the cores)."""
+    return int(lib().oracle_par_threads(nthreads))
+
+
+def par_access(S: np.ndarray, pos: np.ndarray, nthreads: int = 0) -> np.ndarray:
+    S = _seq(S)
+    pos = np.ascontiguousarray(pos, dtype=np.uint64)
+    out = np.empty(pos.size, dtype=np.uint32)
+    lib().oracle_par_access(ctypes.c_void_p(S.ctypes.data), S.size, S.dtype.itemsize, _p(pos, _u64p), pos.size,
+                            _p(out, _u32p), nthreads)
+    return out
+
+
+def par_rank(S: np.ndarray, sigma: int, c: np.ndarray, i: np.ndarray, nthreads: int = 0) -> np.ndarray:
+    assert sigma >= 1
+    S = _seq(S)
+    c = np.ascontiguousarray(c, dtype=np.uint32)
+    i = np.ascontiguousarray(i, dtype=np.uint64)
+    out = np.empty(c.size, dtype=np.uint64)
+    lib().oracle_par_rank(ctypes.c_void_p(S.ctypes.data), S.size, S.dtype.itemsize, sigma, _p(c, _u32p),
+                          _p(i, _u64p), c.size, _p(out, _u64p), nthreads)
+    return out
+
+
+def par_select(S: np.ndarray, sigma: int, c: np.ndarray, k: np.ndarray, nthreads: int = 0) -> np.ndarray:
+    assert sigma >= 1
+    S = _seq(S)
+    c = np.ascontiguousarray(c, dtype=np.uint32)
+    k = np.ascontiguousarray(k, dtype=np.uint64)
+    out = np.empty(c.size, dtype=np.uint64)
+    lib().oracle_par_select(ctypes.c_void_p(S.ctypes.data), S.size, S.dtype.itemsize, sigma, _p(c, _u32p),
+                            _p(k, _u64p), c.size, _p(out, _u64p), nthreads)
+    return out
+
+
+def par_tree(S: np.ndarray, sigma: int, l2_bits: int = 512, sample_rate: int = 4096, nthreads: int = 0) -> dict:
+    """Every level's bits, directory and samples, one level per thread (wt_oracle_par.c)."""
+    S = _seq(S)
+    n = int(S.size)
+    L = num_levels(sigma)
+    Lr = max(L, 1)
+    stride = max(1, (n + 63) // 64)
+    l1s = (n + 65535) // 65536 + 1
+    l2s = (n + l2_bits - 1) // l2_bits + 1
+    ss = n // sample_rate + 1
+    bits = np.zeros((Lr, stride), dtype=np.uint64)
+    level_n = np.zeros(Lr, dtype=np.uint64)
+    L1 = np.zeros((Lr, l1s), dtype=np.uint64)
+    L2 = np.zeros((Lr, l2s), dtype=np.uint16)
+    s1 = np.zeros((Lr, ss), dtype=np.uint64)
+    s0 = np.zeros((Lr, ss), dtype=np.uint64)
+    n1 = np.zeros(Lr, dtype=np.uint64)
+    n0 = np.zeros(Lr, dtype=np.uint64)
+    rc = lib().oracle_par_tree(ctypes.c_void_p(S.ctypes.data), n, S.dtype.itemsize, sigma, l2_bits, sample_rate,
+                               stride, _p(bits, _u64p), _p(level_n, _u64p), l1s, _p(L1, _u64p), l2s, _p(L2, _u16p),
+                               ss, _p(s1, _u64p), _p(n1, _u64p), _p(s0, _u64p), _p(n0, _u64p), nthreads)
+    if rc != 0:
+        raise ValueError("symbol out of range")
+    out = {"L": L, "level_n": [int(x) for x in level_n[:L]], "bits": [], "L1": [], "L2": [], "samples1": [],
+           "samples0": []}
+    for l in range(L):
+        nl = out["level_n"][l]
+        out["bits"].append(bits[l, : (nl + 63) // 64])
+        out["L1"].append(L1[l, : (nl + 65535) // 65536 + 1])
+        out["L2"].append(L2[l, : (nl + l2_bits - 1) // l2_bits + 1])
+        out["samples1"].append(s1[l, : int(n1[l])])
+        out["samples0"].append(s0[l, : int(n0[l])])
     return out
 
 

@@ -99,6 +99,31 @@ def test_structure_and_answers(width, sigma, n, kind, l2, srate):
     t.free()
 
 
+# More than 1024 tiles per level (the tile prefix then runs in chunks of 1024 tiles): the whole
+# structure against the oracle, with a ragged last tile.
+BIG_CASES = [
+    (1, 256, (1 << 25) + 12345, "zipf", 512, 4096),   # 2049 tiles of 16384 u8 symbols
+    (4, 70001, 5_000_003, "zipf12", 512, 4096),       # 1221 tiles of 4096 u32 symbols, reduced codes
+]
+
+
+@pytest.mark.timeout(600)
+@pytest.mark.parametrize("width,sigma,n,kind,l2,srate", BIG_CASES,
+                         ids=["w%d-s%d-n%d-%s-l2_%d-s%d" % c for c in BIG_CASES])
+def test_structure_above_1024_tiles(width, sigma, n, kind, l2, srate):
+    seed = 0xB16 + width
+    S = make_seq(kind, n, sigma, width, seed)
+    G.log("big case w=%d sigma=%d n=%d kind=%s: build" % (width, sigma, n, kind))
+    t = G.gpu_build(S, sigma, l2_bits=l2, sample_rate=srate)
+    G.log("  oracle tree")
+    ot = oracle.OracleTree(S, sigma, l2_bits=l2, sample_rate=srate)
+    G.compare_structure(t, ot)
+    G.log("  queries")
+    G.compare_queries(t, S, sigma, *G.random_queries(S, sigma, 1 << 14, seed))
+    G.compare_queries(t, S, sigma, *G.edge_queries(S, sigma))
+    t.free()
+
+
 def test_plain_small_config_exact():
     wl = workloads.make("plain_small")
     G.log("plain_small: n=%d sigma=%d build" % (wl.n, wl.sigma))
