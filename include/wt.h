@@ -73,12 +73,21 @@ wt_status wt_set_allocator(wt_alloc_fn alloc_fn, wt_free_fn free_fn, void* ctx);
  *   sigma     declared alphabet size, 1 <= sigma <= min(2^(8 sym_bytes), WT_MAX_SIGMA); every
  *             symbol must lie in [0, sigma). Absent symbols are allowed. Alphabets that are not
  *             powers of two use the thesis's reduced codes (Algorithm 3).
+ *             sigma = 0: extract the alphabet (Section 5.1's minimal alphabet; Section 6.3.1 builds
+ *             with the alphabet extracted and passed): the distinct values of d_sym, in increasing
+ *             order, become the codes 0 .. d-1 and the tree is built over them with sigma = d (at most
+ *             WT_MAX_SIGMA distinct values; an empty sequence gets sigma = 1 and no symbol). The tree
+ *             keeps the map both ways: every query call takes and returns the caller's values (a value
+ *             that does not occur is absent: rank 0, select n), wt_info reports sigma = d and
+ *             alphabet_extracted = 1, and WT_PART_ALPHABET exports the values. The extraction reads
+ *             d_sym three times more (largest value for 4-byte symbols, presence, rewrite as codes)
+ *             and needs a presence map of (largest value + 1) / 4 bytes, kept with the tree.
  *   opts      may be NULL (defaults).
  *   out       receives the tree on WT_OK, NULL otherwise.
  * The call enqueues the build on `stream` and waits for it to finish (it must read back the
  * level sizes and the symbol-range flag). d_sym is not retained.
- * Errors: WT_ERR_ARG (bad arguments), WT_ERR_SYMBOL_RANGE (a symbol >= sigma), WT_ERR_OOM,
- * WT_ERR_HIP.
+ * Errors: WT_ERR_ARG (bad arguments, more than WT_MAX_SIGMA distinct values), WT_ERR_SYMBOL_RANGE
+ * (a symbol >= sigma), WT_ERR_OOM, WT_ERR_HIP.
  */
 wt_status wt_build(const void* d_sym, uint64_t n, uint32_t sym_bytes, uint64_t sigma, const wt_build_opts* opts,
                    wt_stream_t stream, wt_tree** out);
@@ -114,6 +123,9 @@ typedef struct {
   uint64_t level_n[WT_MAX_LEVELS];    /* elements per level (n_l) */
   uint64_t level_ones[WT_MAX_LEVELS]; /* ones per level */
   uint64_t bytes_bits, bytes_l1, bytes_l2, bytes_samples, bytes_nodes, bytes_total; /* allocated */
+  uint32_t alphabet_extracted; /* 1: built with sigma = 0 (queries map values to codes and back) */
+  uint32_t reserved0;
+  uint64_t max_symbol;         /* largest symbol value of the alphabet */
 } wt_info_t;
 
 wt_status wt_info(const wt_tree* t, wt_info_t* out);
@@ -127,6 +139,8 @@ wt_status wt_info(const wt_tree* t, wt_info_t* out);
  *   WT_PART_NODE_START u64[2^l]               start of the node with code prefix p (UINT64_MAX: no node)
  *   WT_PART_NODE_R0    u64[2^l]               rank0 of the level at that start (UINT64_MAX: no node)
  *   WT_PART_CUM_HIST   u64[sigma+1]           exclusive prefix sums of the histogram (level ignored)
+ *   WT_PART_ALPHABET   u32[sigma]             symbol value of every code (level ignored): the sorted
+ *                                             distinct values of an extracted alphabet, else 0 .. sigma-1
  */
 enum {
   WT_PART_BITS = 0,
@@ -136,7 +150,8 @@ enum {
   WT_PART_SAMPLES0 = 4,
   WT_PART_NODE_START = 5,
   WT_PART_NODE_R0 = 6,
-  WT_PART_CUM_HIST = 7
+  WT_PART_CUM_HIST = 7,
+  WT_PART_ALPHABET = 8
 };
 
 /* Copy one part to host memory h_dst of cap bytes; *needed receives the byte size of the part

@@ -69,6 +69,8 @@ def lib():
         L.oracle_mlp_forward.argtypes = [_f64p, ctypes.c_double]
         L.oracle_mlp_loss_grad.restype = ctypes.c_double
         L.oracle_mlp_loss_grad.argtypes = [_f64p, _f64p, _f64p, ctypes.c_int, _f64p]
+        L.oracle_alphabet.restype = ctypes.c_uint64
+        L.oracle_alphabet.argtypes = [ctypes.c_void_p, ctypes.c_uint64, ctypes.c_int, _u64p]
         L.oracle_par_threads.restype = ctypes.c_int
         L.oracle_par_threads.argtypes = [ctypes.c_int]
         L.oracle_par_access.argtypes = [ctypes.c_void_p, ctypes.c_uint64, ctypes.c_int, _u64p, ctypes.c_uint64, _u32p,
@@ -115,6 +117,14 @@ def hist(S: np.ndarray, sigma: int) -> np.ndarray:
     if bad:
         raise ValueError("symbol out of range")
     return h[:sigma]
+
+
+def alphabet(S: np.ndarray) -> np.ndarray:
+    """The minimal alphabet: the distinct values of S in increasing order (wt_oracle.c)."""
+    S = _seq(S)
+    vals = np.zeros(max(S.size, 1), dtype=np.uint64)
+    d = lib().oracle_alphabet(ctypes.c_void_p(S.ctypes.data), S.size, S.dtype.itemsize, _p(vals, _u64p))
+    return vals[:d].copy()
 
 
 class OracleTree:

@@ -213,6 +213,22 @@ void oracle_nodes(const void* S, uint64_t n, int w, uint64_t sigma, int l, const
   free(zeros_before); free(code); free(len); free(exists); free(count);
 }
 
+/* Minimal alphabet (Section 5.1: the symbols are the distinct values of the sequence, numbered in
+   increasing order): the distinct values of S, ascending, in values[] (capacity n); returns their number. */
+static int u64_cmp(const void* a, const void* b) {
+  uint64_t x = *(const uint64_t*)a, y = *(const uint64_t*)b;
+  return x < y ? -1 : (x > y);
+}
+
+uint64_t oracle_alphabet(const void* S, uint64_t n, int w, uint64_t* values) {
+  for (uint64_t i = 0; i < n; ++i) values[i] = sym_at(S, w, i);
+  qsort(values, n, sizeof(uint64_t), u64_cmp);
+  uint64_t d = 0;
+  for (uint64_t i = 0; i < n; ++i)
+    if (d == 0 || values[i] != values[d - 1]) values[d++] = values[i];
+  return d;
+}
+
 /* ---- query answers from the raw sequence (sweep over S) ---- */
 
 void oracle_access(const void* S, uint64_t n, int w, const uint64_t* pos, uint64_t q, uint32_t* out) {

@@ -23,7 +23,8 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libwt.so")
 
 WT_OK, WT_ERR_ARG, WT_ERR_SYMBOL_RANGE, WT_ERR_OOM, WT_ERR_HIP, WT_ERR_STATE = range(6)
-PART_BITS, PART_L1, PART_L2, PART_SAMPLES1, PART_SAMPLES0, PART_NODE_START, PART_NODE_R0, PART_CUM_HIST = range(8)
+PART_BITS, PART_L1, PART_L2, PART_SAMPLES1, PART_SAMPLES0, PART_NODE_START, PART_NODE_R0, PART_CUM_HIST, \
+    PART_ALPHABET = range(9)
 BUILD_PROFILE = 1
 MAX_LEVELS = 24
 MAX_SIGMA = 1 << 24
@@ -62,7 +63,8 @@ class Info(ctypes.Structure):
                 ("sym_bytes", ctypes.c_uint32), ("l2_bits", ctypes.c_uint32), ("sample_rate", ctypes.c_uint32),
                 ("level_n", ctypes.c_uint64 * MAX_LEVELS), ("level_ones", ctypes.c_uint64 * MAX_LEVELS),
                 ("bytes_bits", ctypes.c_uint64), ("bytes_l1", ctypes.c_uint64), ("bytes_l2", ctypes.c_uint64),
-                ("bytes_samples", ctypes.c_uint64), ("bytes_nodes", ctypes.c_uint64), ("bytes_total", ctypes.c_uint64)]
+                ("bytes_samples", ctypes.c_uint64), ("bytes_nodes", ctypes.c_uint64), ("bytes_total", ctypes.c_uint64),
+                ("alphabet_extracted", ctypes.c_uint32), ("reserved0", ctypes.c_uint32), ("max_symbol", ctypes.c_uint64)]
 
 
 class LearnOpts(ctypes.Structure):
@@ -282,7 +284,8 @@ class Tree:
         return dict(n=inf.n, sigma=inf.sigma, levels=L, sym_bytes=inf.sym_bytes, l2_bits=inf.l2_bits,
                     sample_rate=inf.sample_rate, level_n=list(inf.level_n[:L]), level_ones=list(inf.level_ones[:L]),
                     bytes_bits=inf.bytes_bits, bytes_l1=inf.bytes_l1, bytes_l2=inf.bytes_l2,
-                    bytes_samples=inf.bytes_samples, bytes_nodes=inf.bytes_nodes, bytes_total=inf.bytes_total)
+                    bytes_samples=inf.bytes_samples, bytes_nodes=inf.bytes_nodes, bytes_total=inf.bytes_total,
+                    alphabet_extracted=bool(inf.alphabet_extracted), max_symbol=inf.max_symbol)
 
     @property
     def n(self) -> int:
@@ -358,7 +361,7 @@ class Tree:
     def export(self, part: int, level: int = 0) -> np.ndarray:
         need = ctypes.c_size_t(0)
         _check(lib().wt_export(self._h, level, part, None, 0, ctypes.byref(need)))
-        dt = np.uint16 if part == PART_L2 else np.uint64
+        dt = np.uint16 if part == PART_L2 else np.uint32 if part == PART_ALPHABET else np.uint64
         buf = np.zeros(max(need.value // np.dtype(dt).itemsize, 1), dtype=dt)
         _check(lib().wt_export(self._h, level, part, ctypes.c_void_p(buf.ctypes.data), buf.nbytes,
                                ctypes.byref(need)))
@@ -385,7 +388,8 @@ class Tree:
 
 
 def build(sym, sigma: int, l2_bits: int = 512, sample_rate: int = 4096, profile: bool = False, stream=None) -> Tree:
-    """Build the wavelet tree of a contiguous device tensor of uint8/uint16/uint32 symbols."""
+    """Build the wavelet tree of a contiguous device tensor of uint8/uint16/uint32 symbols. sigma: declared
+    alphabet size (symbols in [0, sigma)), or 0 to extract the alphabet (the distinct values)."""
     dts = _sym_dtypes()
     if sym.dtype not in dts:
         raise TypeError("symbols must be uint8, uint16 or uint32 (got %s)" % sym.dtype)

@@ -83,6 +83,8 @@ extern "C" wt_status wt_free(wt_tree* t) {
   if (t->borrowed) return fail(WT_ERR_STATE, "wt_free: the tree belongs to a forest (use wt_forest_free)");
   WT_HIP(hipDeviceSynchronize());
   if (t->learn) dev_free(t->learn, nullptr);
+  if (t->alpha_block) dev_free(t->alpha_block, nullptr);
+  if (t->alpha) dev_free((void*)t->alpha, nullptr);
   dev_free(t->block, nullptr);
   WT_HIP(hipDeviceSynchronize());
   delete t;
@@ -109,12 +111,27 @@ extern "C" wt_status wt_info(const wt_tree* t, wt_info_t* out) {
   out->bytes_samples = t->bytes_smp;
   out->bytes_nodes = t->bytes_nodes + t->bytes_cum;
   out->bytes_total = t->block_bytes;
+  out->alphabet_extracted = t->amap ? 1u : 0u;
+  out->max_symbol = t->amap ? t->max_symbol : (t->sigma ? t->sigma - 1 : 0);
   return WT_OK;
 }
 
 extern "C" wt_status wt_export(const wt_tree* t, int level, int part, void* h_dst, size_t cap, size_t* needed) {
   clear_error();
   if (!t) return fail(WT_ERR_ARG, "wt_export: tree is NULL");
+  if (part == WT_PART_ALPHABET) {
+    const size_t bytes = (size_t)t->sigma * 4;
+    if (needed) *needed = bytes;
+    if (!h_dst) return WT_OK;
+    if (cap < bytes) return fail(WT_ERR_ARG, "wt_export: capacity %zu < %zu bytes", cap, bytes);
+    if (t->alpha) {
+      WT_HIP(hipDeviceSynchronize());
+      WT_HIP(hipMemcpy(h_dst, t->alpha, bytes, hipMemcpyDeviceToHost));
+    } else {
+      for (uint64_t c = 0; c < t->sigma; ++c) ((uint32_t*)h_dst)[c] = (uint32_t)c;
+    }
+    return WT_OK;
+  }
   if (part != WT_PART_CUM_HIST && (level < 0 || (uint32_t)level >= t->L))
     return fail(WT_ERR_ARG, "wt_export: level %d out of range [0, %u)", level, t->L);
   const LevelMeta m = part == WT_PART_CUM_HIST ? LevelMeta{} : t->hmeta[level];

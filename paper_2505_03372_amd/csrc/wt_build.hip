@@ -48,7 +48,7 @@ __global__ __launch_bounds__(kBT) void k_scan_down(const uint64_t* __restrict__ 
 }
 
 // out[i] = sum of in[0, i) for i in [0, n); `part` needs ceil(n / kScanChunk) entries.
-static hipError_t exclusive_scan_u64(const uint64_t* in, uint64_t n, uint64_t* out, uint64_t* part,
+hipError_t exclusive_scan_u64(const uint64_t* in, uint64_t n, uint64_t* out, uint64_t* part,
                                      hipStream_t st) {
   if (n == 0) return hipSuccess;
   const uint64_t nb = ceil_div(n, kScanChunk);
@@ -271,9 +271,10 @@ TreePlan plan_tree(uint64_t n, uint32_t w, uint64_t sigma, uint32_t L, uint32_t 
 
 using namespace wt;
 
-extern "C" wt_status wt_build(const void* d_sym, uint64_t n, uint32_t sym_bytes, uint64_t sigma,
-                              const wt_build_opts* opts, wt_stream_t stream, wt_tree** out) {
-  clear_error();
+// The build of wt_build for a declared alphabet (sigma >= 1); wt_build (wt_alpha.hip) first extracts
+// the alphabet when sigma = 0.
+wt_status wt::build_tree(const void* d_sym, uint64_t n, uint32_t sym_bytes, uint64_t sigma, const wt_build_opts* opts,
+                         wt_stream_t stream, wt_tree** out) {
   if (!out) return fail(WT_ERR_ARG, "wt_build: out is NULL");
   *out = nullptr;
   if (sym_bytes != 1 && sym_bytes != 2 && sym_bytes != 4)

@@ -23,11 +23,30 @@ struct wt_tree {
   uint32_t nmodels = 0;
   uint32_t learn_version = 0;  // incremented by every training of the learned index
   wt_learned_info_t linfo{};
+  // Alphabet extracted by the build (sigma = 0 given): the tree is built over the codes [0, sigma) of
+  // the distinct values; amap maps a value to its code, alpha a code to its value.
+  void* alpha_block = nullptr;
+  const wt::AWord* amap = nullptr;
+  uint64_t amap_words = 0;  // values [0, 64 amap_words) are covered
+  const uint32_t* alpha = nullptr;
+  uint64_t max_symbol = 0;
 };
 
 namespace wt {
 
 wt_status fail(wt_status s, const char* fmt, ...);
+
+// Build of a declared alphabet (wt_build.hip); wt_build itself also handles sigma = 0.
+wt_status build_tree(const void* d_sym, uint64_t n, uint32_t sym_bytes, uint64_t sigma, const wt_build_opts* opts,
+                     wt_stream_t stream, wt_tree** out);
+// Extracted alphabets (wt_alpha.hip): query symbols as codes (*mapped = d_sym when the tree has a
+// declared alphabet; otherwise a q-entry buffer, returned in *scratch for the caller to free after the
+// traversal) and access answers back to values.
+wt_status alpha_map_syms(const wt_tree* t, const uint32_t* d_sym, uint64_t q, hipStream_t st, const uint32_t** mapped,
+                         void** scratch);
+wt_status alpha_unmap_access(const wt_tree* t, uint32_t* d_out, uint64_t q, hipStream_t st);
+// out[i] = sum of in[0, i) (wt_build.hip); part: ceil(n / 4096) + 1 entries of scratch.
+hipError_t exclusive_scan_u64(const uint64_t* in, uint64_t n, uint64_t* out, uint64_t* part, hipStream_t st);
 void clear_error();
 void* dev_alloc(size_t bytes, hipStream_t s);
 void dev_free(void* p, hipStream_t s);

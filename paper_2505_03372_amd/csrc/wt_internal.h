@@ -37,6 +37,14 @@ struct NodeB {
   uint64_t off0, off1;  // level-(l+1) position of an element = off_b + rank_b(position)
 };
 
+// Presence word of an extracted alphabet: bit v mod 64 of word v / 64 is set when value v occurs;
+// `pre` counts the values present in every earlier word (the code of the first value of this word).
+struct AWord {
+  uint64_t bits;
+  uint32_t pre;
+  uint32_t pad;
+};
+
 struct TreeDev {
   uint64_t* bits;
   uint64_t* L1;

@@ -561,18 +561,26 @@ extern "C" wt_status wt_select_learned(const wt_tree* t, const uint32_t* d_sym, 
   const LearnQ* qm = (const LearnQ*)((const char*)t->learn + (size_t)t->nmodels * sizeof(LearnModel));
   SortBufs sb;
   bool binned;
-  const wt_status rc = sort_batch(t, a, 2, d_sym, d_k, q, st, sb, binned);
+  const uint32_t* sym = d_sym;
+  void* mapped = nullptr;
+  wt_status rc = alpha_map_syms(t, d_sym, q, st, &sym, &mapped);
   if (rc != WT_OK) return rc;
+  rc = sort_batch(t, a, 2, sym, d_k, q, st, sb, binned);
+  if (rc != WT_OK) {
+    if (mapped) dev_free(mapped, st);
+    return rc;
+  }
   qprof_begin("select_learned", st);
   if (binned) {
     const uint32_t grid = query_grid(q, kQB);
-    WT_DISPATCH_L2(t->l2_bits, kQB, k_select_learned, a, qm, d_sym, d_k, q, d_out, (const uint32_t*)sb.perm, sb.subshift);
+    WT_DISPATCH_L2(t->l2_bits, kQB, k_select_learned, a, qm, sym, d_k, q, d_out, (const uint32_t*)sb.perm, sb.subshift);
     dev_free(sb.block, st);
   } else {
     const uint32_t grid = query_grid(q, kQT);
-    WT_DISPATCH_L2(t->l2_bits, kQT, k_select_learned, a, qm, d_sym, d_k, q, d_out, (const uint32_t*)nullptr, 0u);
+    WT_DISPATCH_L2(t->l2_bits, kQT, k_select_learned, a, qm, sym, d_k, q, d_out, (const uint32_t*)nullptr, 0u);
   }
   qprof_end(st);
+  if (mapped) dev_free(mapped, st);
   WT_HIP(hipGetLastError());
   return WT_OK;
 }

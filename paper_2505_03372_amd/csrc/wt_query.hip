@@ -373,7 +373,7 @@ extern "C" wt_status wt_access(const wt_tree* t, const uint64_t* d_pos, uint64_t
   }
   qprof_end(st);
   WT_HIP(hipGetLastError());
-  return WT_OK;
+  return alpha_unmap_access(t, d_out, q, st);
 }
 
 extern "C" wt_status wt_rank(const wt_tree* t, const uint32_t* d_sym, const uint64_t* d_pos, uint64_t q,
@@ -386,18 +386,26 @@ extern "C" wt_status wt_rank(const wt_tree* t, const uint32_t* d_sym, const uint
   const QArgs a = make_args(t);
   SortBufs sb;
   bool binned;
-  const wt_status rc = sort_batch(t, a, 1, d_sym, d_pos, q, st, sb, binned);
+  const uint32_t* sym = d_sym;
+  void* mapped = nullptr;
+  wt_status rc = alpha_map_syms(t, d_sym, q, st, &sym, &mapped);
   if (rc != WT_OK) return rc;
+  rc = sort_batch(t, a, 1, sym, d_pos, q, st, sb, binned);
+  if (rc != WT_OK) {
+    if (mapped) dev_free(mapped, st);
+    return rc;
+  }
   qprof_begin("rank", st);
   if (binned) {
     const uint32_t grid = query_grid(q, kQB);
-    WT_DISPATCH_L2(t->l2_bits, kQB, k_rank, a, d_sym, d_pos, q, d_out, (const uint32_t*)sb.perm, sb.subshift);
+    WT_DISPATCH_L2(t->l2_bits, kQB, k_rank, a, sym, d_pos, q, d_out, (const uint32_t*)sb.perm, sb.subshift);
     dev_free(sb.block, st);
   } else {
     const uint32_t grid = query_grid(q, kQT);
-    WT_DISPATCH_L2(t->l2_bits, kQT, k_rank, a, d_sym, d_pos, q, d_out, (const uint32_t*)nullptr, 0u);
+    WT_DISPATCH_L2(t->l2_bits, kQT, k_rank, a, sym, d_pos, q, d_out, (const uint32_t*)nullptr, 0u);
   }
   qprof_end(st);
+  if (mapped) dev_free(mapped, st);
   WT_HIP(hipGetLastError());
   return WT_OK;
 }
@@ -412,18 +420,26 @@ extern "C" wt_status wt_select(const wt_tree* t, const uint32_t* d_sym, const ui
   const QArgs a = make_args(t);
   SortBufs sb;
   bool binned;
-  const wt_status rc = sort_batch(t, a, 2, d_sym, d_k, q, st, sb, binned);
+  const uint32_t* sym = d_sym;
+  void* mapped = nullptr;
+  wt_status rc = alpha_map_syms(t, d_sym, q, st, &sym, &mapped);
   if (rc != WT_OK) return rc;
+  rc = sort_batch(t, a, 2, sym, d_k, q, st, sb, binned);
+  if (rc != WT_OK) {
+    if (mapped) dev_free(mapped, st);
+    return rc;
+  }
   qprof_begin("select", st);
   if (binned) {
     const uint32_t grid = query_grid(q, kQB);
-    WT_DISPATCH_L2(t->l2_bits, kQB, k_select, a, d_sym, d_k, q, d_out, (const uint32_t*)sb.perm, sb.subshift);
+    WT_DISPATCH_L2(t->l2_bits, kQB, k_select, a, sym, d_k, q, d_out, (const uint32_t*)sb.perm, sb.subshift);
     dev_free(sb.block, st);
   } else {
     const uint32_t grid = query_grid(q, kQT);
-    WT_DISPATCH_L2(t->l2_bits, kQT, k_select, a, d_sym, d_k, q, d_out, (const uint32_t*)nullptr, 0u);
+    WT_DISPATCH_L2(t->l2_bits, kQT, k_select, a, sym, d_k, q, d_out, (const uint32_t*)nullptr, 0u);
   }
   qprof_end(st);
+  if (mapped) dev_free(mapped, st);
   WT_HIP(hipGetLastError());
   return WT_OK;
 }

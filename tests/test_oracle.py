@@ -327,3 +327,15 @@ def test_mlp_gradient_hand_values_where_relu_clamps():
     exp = np.zeros(oracle.MLP_PARAMS)
     exp[32], exp[16], exp[0], exp[48] = 0.6, 3.6, 1.8, 1.2
     np.testing.assert_allclose(g, exp, rtol=0, atol=1e-12)
+
+
+def test_alphabet_hand_example_and_library_routine():
+    # hand example: the distinct values of (7, 3, 7, 100, 3, 0) in increasing order are (0, 3, 7, 100)
+    S = np.array([7, 3, 7, 100, 3, 0], dtype=np.uint32)
+    assert oracle.alphabet(S).tolist() == [0, 3, 7, 100]
+    assert oracle.alphabet(np.zeros(0, np.uint8)).size == 0
+    assert oracle.alphabet(np.full(9, 200, np.uint8)).tolist() == [200]
+    # against numpy's unique on random inputs of every width
+    for w, hi in ((1, 256), (2, 60000), (4, 1 << 31)):
+        S = (workloads.raw(0xA1 + w, 0, 20000) % np.uint64(hi)).astype(workloads.dtype_for(w))
+        np.testing.assert_array_equal(oracle.alphabet(S), np.unique(S).astype(np.uint64))
