@@ -196,6 +196,8 @@ extern "C" wt_status wt_build(const void* d_sym, uint64_t n, uint32_t sym_bytes,
     return fail(WT_ERR_ARG, "wt_build: sym_bytes must be 1, 2 or 4 (got %u)", sym_bytes);
   if (n && !d_sym) return fail(WT_ERR_ARG, "wt_build: d_sym is NULL");
   if (n >= (1ull << 40)) return fail(WT_ERR_ARG, "wt_build: n too large");
+  const wt_status orc = check_build_opts(opts);
+  if (orc != WT_OK) return orc;
   hipStream_t st = (hipStream_t)stream;
 
   // device buffers released on every exit: the scratch always, the map unless a tree takes it

@@ -271,6 +271,16 @@ TreePlan plan_tree(uint64_t n, uint32_t w, uint64_t sigma, uint32_t L, uint32_t 
 
 using namespace wt;
 
+wt_status wt::check_build_opts(const wt_build_opts* opts) {
+  const uint32_t l2_bits = opts && opts->l2_bits ? opts->l2_bits : 512;
+  const uint32_t srate = opts && opts->sample_rate ? opts->sample_rate : 4096;
+  if (l2_bits != 256 && l2_bits != 512 && l2_bits != 1024 && l2_bits != 2048)
+    return fail(WT_ERR_ARG, "wt_build: l2_bits must be 256, 512, 1024 or 2048");
+  if (srate < 512 || srate > (1u << 20) || (srate & (srate - 1)))
+    return fail(WT_ERR_ARG, "wt_build: sample_rate must be a power of two in [512, 2^20]");
+  return WT_OK;
+}
+
 // The build of wt_build for a declared alphabet (sigma >= 1); wt_build (wt_alpha.hip) first extracts
 // the alphabet when sigma = 0.
 wt_status wt::build_tree(const void* d_sym, uint64_t n, uint32_t sym_bytes, uint64_t sigma, const wt_build_opts* opts,
@@ -287,16 +297,14 @@ wt_status wt::build_tree(const void* d_sym, uint64_t n, uint32_t sym_bytes, uint
     return fail(WT_ERR_ARG, "wt_build: sigma %llu does not fit %u-byte symbols", (unsigned long long)sigma,
                 sym_bytes);
   if (n >= (1ull << 40)) return fail(WT_ERR_ARG, "wt_build: n too large");
+  const wt_status orc = check_build_opts(opts);
+  if (orc != WT_OK) return orc;
   uint32_t l2_bits = 512, srate = 4096, flags = 0;
   if (opts) {
     if (opts->l2_bits) l2_bits = opts->l2_bits;
     if (opts->sample_rate) srate = opts->sample_rate;
     flags = opts->flags;
   }
-  if (l2_bits != 256 && l2_bits != 512 && l2_bits != 1024 && l2_bits != 2048)
-    return fail(WT_ERR_ARG, "wt_build: l2_bits must be 256, 512, 1024 or 2048");
-  if (srate < 512 || srate > (1u << 20) || (srate & (srate - 1)))
-    return fail(WT_ERR_ARG, "wt_build: sample_rate must be a power of two in [512, 2^20]");
 
   hipStream_t st = (hipStream_t)stream;
   int dev = 0;

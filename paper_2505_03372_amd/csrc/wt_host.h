@@ -36,6 +36,8 @@ namespace wt {
 
 wt_status fail(wt_status s, const char* fmt, ...);
 
+// Validation of the build options (|L2| and s), shared by both build paths (wt_build.hip).
+wt_status check_build_opts(const wt_build_opts* opts);
 // Build of a declared alphabet (wt_build.hip); wt_build itself also handles sigma = 0.
 wt_status build_tree(const void* d_sym, uint64_t n, uint32_t sym_bytes, uint64_t sigma, const wt_build_opts* opts,
                      wt_stream_t stream, wt_tree** out);

@@ -46,7 +46,8 @@ def test_build_rejects_bad_arguments_before_touching_the_device(wt):
     dummy = ctypes.c_void_p(0x1000)  # never dereferenced: validation fails first
     cases = [
         (dummy, 10, 3, 256),          # symbol width
-        (dummy, 10, 1, 0),            # sigma 0
+        (dummy, 10, 5, 0),            # symbol width, alphabet to extract
+        (ctypes.c_void_p(0), 10, 4, 0),  # null symbols, alphabet to extract
         (dummy, 10, 1, 257),          # sigma beyond the width
         (dummy, 10, 4, (1 << 24) + 1),  # sigma beyond the node-table limit
         (ctypes.c_void_p(0), 10, 1, 4),  # null symbols with n > 0
@@ -60,6 +61,8 @@ def test_build_rejects_bad_arguments_before_touching_the_device(wt):
     assert L.wt_build(dummy, 10, 1, 4, ctypes.byref(bad), None, ctypes.byref(out)) == wt.WT_ERR_ARG
     bad = wt.BuildOpts(512, 3000, 0, 0)
     assert L.wt_build(dummy, 10, 1, 4, ctypes.byref(bad), None, ctypes.byref(out)) == wt.WT_ERR_ARG
+    # the extraction path (sigma = 0) checks the options before its first device call
+    assert L.wt_build(dummy, 10, 1, 0, ctypes.byref(bad), None, ctypes.byref(out)) == wt.WT_ERR_ARG
     assert L.wt_build(dummy, 10, 1, 4, None, None, None) == wt.WT_ERR_ARG
 
 
