@@ -70,31 +70,31 @@ __global__ __launch_bounds__(kAT) void k_alpha_presence(const E* __restrict__ s,
 
 __global__ __launch_bounds__(kAT) void k_alpha_count(const AWord* __restrict__ aw, uint64_t nw,
                                                      uint64_t* __restrict__ cnt) {
-  const uint64_t w = (uint64_t)blockIdx.x * kAT + threadIdx.x;
-  if (w < nw) cnt[w] = (uint64_t)__popcll(aw[w].bits);
+  for (uint64_t w = (uint64_t)blockIdx.x * kAT + threadIdx.x; w < nw; w += (uint64_t)gridDim.x * kAT)
+    cnt[w] = (uint64_t)__popcll(aw[w].bits);
 }
 
 // Codes of the words' first values; total = distinct values.
 __global__ __launch_bounds__(kAT) void k_alpha_pre(AWord* __restrict__ aw, uint64_t nw, const uint64_t* __restrict__ pre,
                                                    const uint64_t* __restrict__ cnt, uint64_t* __restrict__ total) {
-  const uint64_t w = (uint64_t)blockIdx.x * kAT + threadIdx.x;
-  if (w >= nw) return;
-  aw[w].pre = (uint32_t)pre[w];
-  aw[w].pad = 0;
-  if (w == nw - 1) *total = pre[w] + cnt[w];
+  for (uint64_t w = (uint64_t)blockIdx.x * kAT + threadIdx.x; w < nw; w += (uint64_t)gridDim.x * kAT) {
+    aw[w].pre = (uint32_t)pre[w];
+    aw[w].pad = 0;
+    if (w == nw - 1) *total = pre[w] + cnt[w];
+  }
 }
 
 // alpha[code] = value.
 __global__ __launch_bounds__(kAT) void k_alpha_list(const AWord* __restrict__ aw, uint64_t nw,
                                                     uint32_t* __restrict__ alpha) {
-  const uint64_t w = (uint64_t)blockIdx.x * kAT + threadIdx.x;
-  if (w >= nw) return;
-  uint64_t b = aw[w].bits;
-  uint32_t r = aw[w].pre;
-  while (b) {
-    const uint32_t j = (uint32_t)__ffsll((unsigned long long)b) - 1u;
-    alpha[r++] = (uint32_t)(64 * w + j);
-    b &= b - 1;
+  for (uint64_t w = (uint64_t)blockIdx.x * kAT + threadIdx.x; w < nw; w += (uint64_t)gridDim.x * kAT) {
+    uint64_t b = aw[w].bits;
+    uint32_t r = aw[w].pre;
+    while (b) {
+      const uint32_t j = (uint32_t)__ffsll((unsigned long long)b) - 1u;
+      alpha[r++] = (uint32_t)(64 * w + j);
+      b &= b - 1;
+    }
   }
 }
 
