@@ -27,12 +27,15 @@ def _need_gpu():
 
 
 def _seq(width, n, d, hi, seed):
-    """n symbols over d distinct values drawn from [0, hi), Zipf(1.0) over a seeded permutation."""
+    """n >= d symbols over exactly d distinct values drawn from [0, hi): every value once, in a seeded
+    order, then Zipf(1.0) over a seeded permutation."""
     vals = np.unique(workloads.raw(workloads.subseed(seed, 1), 0, 4 * d) % np.uint64(hi))
     vals = vals[workloads.permutation(workloads.subseed(seed, 2), vals.size)][:d]
-    assert vals.size == d
-    idx = workloads.zipf(workloads.subseed(seed, 3), n, d, 1.0, 4, workloads.permutation(workloads.subseed(seed, 4), d))
-    return vals[idx.astype(np.int64)].astype(workloads.dtype_for(width)), np.sort(vals)
+    assert vals.size == d and n >= d
+    idx = workloads.zipf(workloads.subseed(seed, 3), n - d, d, 1.0, 4,
+                         workloads.permutation(workloads.subseed(seed, 4), d))
+    S = np.concatenate([vals, vals[idx.astype(np.int64)]]).astype(workloads.dtype_for(width))
+    return S, np.sort(vals)
 
 
 def _codes(alpha, x):
