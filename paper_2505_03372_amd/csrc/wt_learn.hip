@@ -400,16 +400,16 @@ __global__ __launch_bounds__(QB, 8) void k_select_learned(QArgs a, const LearnQ*
                                                         const uint32_t* __restrict__ sym,
                                                         const uint64_t* __restrict__ kin, uint64_t q,
                                                         uint64_t* __restrict__ out,
-                                                        const uint32_t* __restrict__ perm, uint32_t subshift) {
+                                                        const SQ* __restrict__ sq, uint32_t subshift) {
   constexpr int GS = learn_gs<L2S>();
   __shared__ LevelMeta s_meta[WT_MAX_LEVELS];
   __shared__ LocalOrder<QB> s_ord;
   load_meta(a, s_meta);
-  if (perm) {
+  if (sq) {
     for (uint64_t j0 = xcd_block() * QB; j0 < q; j0 += (uint64_t)gridDim.x * QB) {
       uint32_t jj, c;
       uint64_t x;
-      if (local_order<2, QB>(a, sym, kin, perm, q, j0 + threadIdx.x, subshift, s_ord, jj, c, x))
+      if (local_order<2, QB>(a, sq, q, j0 + threadIdx.x, subshift, s_ord, jj, c, x))
         out[jj] = select_learned_one<L2S, GS>(a, s_meta, qm, c, x);
     }
     return;
@@ -573,11 +573,11 @@ extern "C" wt_status wt_select_learned(const wt_tree* t, const uint32_t* d_sym, 
   qprof_begin("select_learned", st);
   if (binned) {
     const uint32_t grid = query_grid(q, kQB);
-    WT_DISPATCH_L2(t->l2_bits, kQB, k_select_learned, a, qm, sym, d_k, q, d_out, (const uint32_t*)sb.perm, sb.subshift);
+    WT_DISPATCH_L2(t->l2_bits, kQB, k_select_learned, a, qm, sym, d_k, q, d_out, (const SQ*)sb.sq, sb.subshift);
     dev_free(sb.block, st);
   } else {
     const uint32_t grid = query_grid(q, kQT);
-    WT_DISPATCH_L2(t->l2_bits, kQT, k_select_learned, a, qm, sym, d_k, q, d_out, (const uint32_t*)nullptr, 0u);
+    WT_DISPATCH_L2(t->l2_bits, kQT, k_select_learned, a, qm, sym, d_k, q, d_out, (const SQ*)nullptr, 0u);
   }
   qprof_end(st);
   if (mapped) dev_free(mapped, st);

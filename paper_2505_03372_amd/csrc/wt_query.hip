@@ -23,20 +23,20 @@
 
 namespace wt {
 
-// perm: NULL, or the queries in binned order: slot j runs query perm[j] (its arguments are read and its
+// sq: NULL, or the queries in binned order: slot j runs query sq[j].id with the arguments stored in sq[j] (its
 // answer written at that index).
 template <int L2S, uint32_t QB>
 __global__ __launch_bounds__(QB, 8) void k_access(QArgs a, const uint64_t* __restrict__ pos, uint64_t q,
-                                                uint32_t* __restrict__ out, const uint32_t* __restrict__ perm,
+                                                uint32_t* __restrict__ out, const SQ* __restrict__ sq,
                                                 uint32_t subshift) {
   __shared__ LevelMeta s_meta[WT_MAX_LEVELS];
   __shared__ LocalOrder<QB> s_ord;
   load_meta(a, s_meta);
-  if (perm) {
+  if (sq) {
     for (uint64_t j0 = xcd_block() * QB; j0 < q; j0 += (uint64_t)gridDim.x * QB) {
       uint32_t jj, c;
       uint64_t x;
-      if (local_order<0, QB>(a, nullptr, pos, perm, q, j0 + threadIdx.x, subshift, s_ord, jj, c, x))
+      if (local_order<0, QB>(a, sq, q, j0 + threadIdx.x, subshift, s_ord, jj, c, x))
         out[jj] = access_one<L2S>(a, s_meta, x);
     }
     return;
@@ -48,16 +48,16 @@ __global__ __launch_bounds__(QB, 8) void k_access(QArgs a, const uint64_t* __res
 template <int L2S, uint32_t QB>
 __global__ __launch_bounds__(QB, 8) void k_rank(QArgs a, const uint32_t* __restrict__ sym,
                                               const uint64_t* __restrict__ pos, uint64_t q,
-                                              uint64_t* __restrict__ out, const uint32_t* __restrict__ perm,
+                                              uint64_t* __restrict__ out, const SQ* __restrict__ sq,
                                               uint32_t subshift) {
   __shared__ LevelMeta s_meta[WT_MAX_LEVELS];
   __shared__ LocalOrder<QB> s_ord;
   load_meta(a, s_meta);
-  if (perm) {
+  if (sq) {
     for (uint64_t j0 = xcd_block() * QB; j0 < q; j0 += (uint64_t)gridDim.x * QB) {
       uint32_t jj, c;
       uint64_t x;
-      if (local_order<1, QB>(a, sym, pos, perm, q, j0 + threadIdx.x, subshift, s_ord, jj, c, x))
+      if (local_order<1, QB>(a, sq, q, j0 + threadIdx.x, subshift, s_ord, jj, c, x))
         out[jj] = rank_one<L2S>(a, s_meta, c, x);
     }
     return;
@@ -69,16 +69,16 @@ __global__ __launch_bounds__(QB, 8) void k_rank(QArgs a, const uint32_t* __restr
 template <int L2S, uint32_t QB>
 __global__ __launch_bounds__(QB, 8) void k_select(QArgs a, const uint32_t* __restrict__ sym,
                                                 const uint64_t* __restrict__ kin, uint64_t q,
-                                                uint64_t* __restrict__ out, const uint32_t* __restrict__ perm,
-                                              uint32_t subshift) {
+                                                uint64_t* __restrict__ out, const SQ* __restrict__ sq,
+                                                uint32_t subshift) {
   __shared__ LevelMeta s_meta[WT_MAX_LEVELS];
   __shared__ LocalOrder<QB> s_ord;
   load_meta(a, s_meta);
-  if (perm) {
+  if (sq) {
     for (uint64_t j0 = xcd_block() * QB; j0 < q; j0 += (uint64_t)gridDim.x * QB) {
       uint32_t jj, c;
       uint64_t x;
-      if (local_order<2, QB>(a, sym, kin, perm, q, j0 + threadIdx.x, subshift, s_ord, jj, c, x))
+      if (local_order<2, QB>(a, sq, q, j0 + threadIdx.x, subshift, s_ord, jj, c, x))
         out[jj] = select_one<L2S>(a, s_meta, c, x);
     }
     return;
@@ -136,9 +136,7 @@ constexpr uint32_t kBinNone = 0xFFFFFFFFu;  // slot past the batch
 template <int KIND>
 __device__ __forceinline__ void bin_round(const QArgs& a, const uint32_t* __restrict__ sym,
                                           const uint64_t* __restrict__ arg, uint64_t q, uint32_t shift, uint64_t j0,
-                                          uint32_t (&bin)[kBinU]) {
-  uint64_t x[kBinU];
-  uint32_t c[kBinU];
+                                          uint32_t (&bin)[kBinU], uint64_t (&x)[kBinU], uint32_t (&c)[kBinU]) {
 #pragma unroll
   for (uint32_t u = 0; u < kBinU; ++u) {
     const uint64_t j = j0 + (uint64_t)u * kBinT;
@@ -161,8 +159,9 @@ __global__ __launch_bounds__(kBinT) void k_bin_count(QArgs a, const uint32_t* __
   __syncthreads();
   const uint64_t c0 = (uint64_t)blockIdx.x * kBinChunk;
   for (uint32_t i = threadIdx.x; i < kBinChunk; i += kBinT * kBinU) {
-    uint32_t bin[kBinU];
-    bin_round<KIND>(a, sym, arg, q, shift, c0 + i, bin);
+    uint32_t bin[kBinU], c[kBinU];
+    uint64_t x[kBinU];
+    bin_round<KIND>(a, sym, arg, q, shift, c0 + i, bin, x, c);
 #pragma unroll
     for (uint32_t u = 0; u < kBinU; ++u)
       if (bin[u] != kBinNone) atomicAdd(&h[bin[u]], 1u);
@@ -221,21 +220,29 @@ __global__ __launch_bounds__(1024) void k_bin_scan(uint32_t* __restrict__ tot) {
   }
 }
 
+// Every query is written at its slot with its arguments (SQ).
 template <int KIND>
 __global__ __launch_bounds__(kBinT) void k_bin_scatter(QArgs a, const uint32_t* __restrict__ sym,
                                                      const uint64_t* __restrict__ arg, uint64_t q, uint32_t shift,
                                                      const uint32_t* __restrict__ bhist,
-                                                     const uint32_t* __restrict__ base, uint32_t* __restrict__ perm) {
+                                                     const uint32_t* __restrict__ base, SQ* __restrict__ sq) {
   __shared__ uint32_t cur[kBins];
   for (uint32_t b = threadIdx.x; b < kBins; b += kBinT) cur[b] = base[b] + bhist[(uint64_t)blockIdx.x * kBins + b];
   __syncthreads();
   const uint64_t c0 = (uint64_t)blockIdx.x * kBinChunk;
   for (uint32_t i = threadIdx.x; i < kBinChunk; i += kBinT * kBinU) {
-    uint32_t bin[kBinU];
-    bin_round<KIND>(a, sym, arg, q, shift, c0 + i, bin);
+    uint32_t bin[kBinU], c[kBinU];
+    uint64_t x[kBinU];
+    bin_round<KIND>(a, sym, arg, q, shift, c0 + i, bin, x, c);
 #pragma unroll
     for (uint32_t u = 0; u < kBinU; ++u)
-      if (bin[u] != kBinNone) perm[atomicAdd(&cur[bin[u]], 1u)] = (uint32_t)(c0 + i + u * kBinT);
+      if (bin[u] != kBinNone) {
+        SQ r;
+        r.id = (uint32_t)(c0 + i + u * kBinT);
+        r.sym = c[u];
+        r.arg = x[u];
+        sq[atomicAdd(&cur[bin[u]], 1u)] = r;
+      }
   }
 }
 
@@ -306,16 +313,13 @@ wt_status sort_batch(const wt_tree* t, const QArgs& a, int kind, const uint32_t*
   if (q < kSortMinQ || q >= (1ull << 32)) return WT_OK;
   const uint32_t nblk = (uint32_t)ceil_div(q, kBinChunk);
   const size_t o_t = round_up((size_t)nblk * kBins * 4, 256), o_p = o_t + round_up(4 * kBins, 256),
-               bytes = o_p + 4 * q;
+               bytes = o_p + sizeof(SQ) * q;
   sb.block = (char*)dev_alloc(bytes, st);
   if (!sb.block) return fail(WT_ERR_OOM, "query binning: scratch allocation of %zu bytes failed", bytes);
   uint32_t* bhist = (uint32_t*)sb.block;
   uint32_t* tot = (uint32_t*)(sb.block + o_t);
   sb.cnt = tot;
-  sb.bucket = nullptr;
-  sb.perm = (uint32_t*)(sb.block + o_p);
-  sb.ssym = nullptr;
-  sb.sarg = nullptr;
+  sb.sq = (SQ*)(sb.block + o_p);
   uint32_t bits = 0;
   while ((1ull << bits) < a.n + 1) ++bits;
   const uint32_t shift = bits > 15 ? bits - 15 : 0;
@@ -332,13 +336,13 @@ wt_status sort_batch(const wt_tree* t, const QArgs& a, int kind, const uint32_t*
   qprof_begin("sort_scatter", st);
   if (kind == 0)
     hipLaunchKernelGGL(k_bin_scatter<0>, dim3(nblk), dim3(kBinT), 0, st, a, sym, arg, q, shift, (const uint32_t*)bhist,
-                       (const uint32_t*)tot, sb.perm);
+                       (const uint32_t*)tot, sb.sq);
   else if (kind == 1)
     hipLaunchKernelGGL(k_bin_scatter<1>, dim3(nblk), dim3(kBinT), 0, st, a, sym, arg, q, shift, (const uint32_t*)bhist,
-                       (const uint32_t*)tot, sb.perm);
+                       (const uint32_t*)tot, sb.sq);
   else
     hipLaunchKernelGGL(k_bin_scatter<2>, dim3(nblk), dim3(kBinT), 0, st, a, sym, arg, q, shift, (const uint32_t*)bhist,
-                       (const uint32_t*)tot, sb.perm);
+                       (const uint32_t*)tot, sb.sq);
   qprof_end(st);
   WT_HIP(hipGetLastError());
   binned = true;
@@ -365,11 +369,11 @@ extern "C" wt_status wt_access(const wt_tree* t, const uint64_t* d_pos, uint64_t
   qprof_begin("access", st);
   if (binned) {
     const uint32_t grid = query_grid(q, kQB);
-    WT_DISPATCH_L2(t->l2_bits, kQB, k_access, a, d_pos, q, d_out, (const uint32_t*)sb.perm, sb.subshift);
+    WT_DISPATCH_L2(t->l2_bits, kQB, k_access, a, d_pos, q, d_out, (const SQ*)sb.sq, sb.subshift);
     dev_free(sb.block, st);
   } else {
     const uint32_t grid = query_grid(q, kQT);
-    WT_DISPATCH_L2(t->l2_bits, kQT, k_access, a, d_pos, q, d_out, (const uint32_t*)nullptr, 0u);
+    WT_DISPATCH_L2(t->l2_bits, kQT, k_access, a, d_pos, q, d_out, (const SQ*)nullptr, 0u);
   }
   qprof_end(st);
   WT_HIP(hipGetLastError());
@@ -398,11 +402,11 @@ extern "C" wt_status wt_rank(const wt_tree* t, const uint32_t* d_sym, const uint
   qprof_begin("rank", st);
   if (binned) {
     const uint32_t grid = query_grid(q, kQB);
-    WT_DISPATCH_L2(t->l2_bits, kQB, k_rank, a, sym, d_pos, q, d_out, (const uint32_t*)sb.perm, sb.subshift);
+    WT_DISPATCH_L2(t->l2_bits, kQB, k_rank, a, sym, d_pos, q, d_out, (const SQ*)sb.sq, sb.subshift);
     dev_free(sb.block, st);
   } else {
     const uint32_t grid = query_grid(q, kQT);
-    WT_DISPATCH_L2(t->l2_bits, kQT, k_rank, a, sym, d_pos, q, d_out, (const uint32_t*)nullptr, 0u);
+    WT_DISPATCH_L2(t->l2_bits, kQT, k_rank, a, sym, d_pos, q, d_out, (const SQ*)nullptr, 0u);
   }
   qprof_end(st);
   if (mapped) dev_free(mapped, st);
@@ -432,11 +436,11 @@ extern "C" wt_status wt_select(const wt_tree* t, const uint32_t* d_sym, const ui
   qprof_begin("select", st);
   if (binned) {
     const uint32_t grid = query_grid(q, kQB);
-    WT_DISPATCH_L2(t->l2_bits, kQB, k_select, a, sym, d_k, q, d_out, (const uint32_t*)sb.perm, sb.subshift);
+    WT_DISPATCH_L2(t->l2_bits, kQB, k_select, a, sym, d_k, q, d_out, (const SQ*)sb.sq, sb.subshift);
     dev_free(sb.block, st);
   } else {
     const uint32_t grid = query_grid(q, kQT);
-    WT_DISPATCH_L2(t->l2_bits, kQT, k_select, a, sym, d_k, q, d_out, (const uint32_t*)nullptr, 0u);
+    WT_DISPATCH_L2(t->l2_bits, kQT, k_select, a, sym, d_k, q, d_out, (const SQ*)nullptr, 0u);
   }
   qprof_end(st);
   if (mapped) dev_free(mapped, st);

@@ -354,19 +354,27 @@ struct LocalOrder {
   uint64_t arg[QB];
 };
 
+// A query of a binned batch, written at its slot by the binning: its index in the batch and its
+// arguments (so the traversal reads its slots in order instead of gathering through a permutation).
+struct SQ {
+  uint32_t id;
+  uint32_t sym;
+  uint64_t arg;
+};
+
 template <int KIND, uint32_t QB>
-__device__ __forceinline__ bool local_order(const QArgs& a, const uint32_t* __restrict__ sym,
-                                            const uint64_t* __restrict__ arg, const uint32_t* __restrict__ perm,
-                                            uint64_t q, uint64_t j, uint32_t subshift, LocalOrder<QB>& L,
-                                            uint32_t& jj, uint32_t& c, uint64_t& x) {
+__device__ __forceinline__ bool local_order(const QArgs& a, const SQ* __restrict__ sq, uint64_t q, uint64_t j,
+                                            uint32_t subshift, LocalOrder<QB>& L, uint32_t& jj, uint32_t& c,
+                                            uint64_t& x) {
   constexpr uint32_t kNone = 0xFFFFFFFFu;
   const uint32_t t = threadIdx.x;
   uint32_t id = kNone, cc = 0, sub = QB - 1;
   uint64_t xx = 0;
   if (j < q) {
-    id = perm[j];
-    xx = arg[id];
-    if (KIND) cc = sym[id];
+    const SQ r = sq[j];
+    id = r.id;
+    xx = r.arg;
+    cc = r.sym;
     sub = (uint32_t)(sort_key(a, KIND, cc, xx) >> subshift) & (QB - 1);
   }
   L.cnt[t] = 0;
@@ -420,16 +428,13 @@ inline QArgs make_args(const wt_tree* t) {
 void qprof_begin(const char* name, hipStream_t st);
 void qprof_end(hipStream_t st);
 
-// Locality binning of a query batch (wt_query.hip): on success with `binned`, perm holds the queries in
-// bucket order (slot j runs query perm[j]); the caller frees `block` (stream-ordered) after its
-// traversal.
+// Locality binning of a query batch (wt_query.hip): on success with `binned`, sq holds the queries in
+// bucket order (slot j runs query sq[j].id with the arguments stored beside it); the caller frees
+// `block` (stream-ordered) after its traversal.
 struct SortBufs {
   char* block = nullptr;
   uint32_t* cnt;
-  uint32_t* bucket;
-  uint32_t* perm;
-  uint32_t* ssym;
-  uint64_t* sarg;
+  SQ* sq;
   uint32_t subshift = 0;  // key bits below the ones that order queries inside a block
 };
 wt_status sort_batch(const wt_tree* t, const QArgs& a, int kind, const uint32_t* sym, const uint64_t* arg, uint64_t q,
