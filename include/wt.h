@@ -176,6 +176,22 @@ wt_status wt_build_profile(const wt_tree* t, wt_prof_entry* out, uint32_t cap, u
 wt_status wt_query_profiling(int on);
 wt_status wt_query_profile(wt_prof_entry* out, uint32_t cap, uint32_t* count);
 
+/* ---- rank and select support of a plain bit array (Section 4, Algorithms 1 and 2) ----
+ *
+ * wt_bv_build copies the bits d_words[0, ceil(n_bits / 64)) (bit j at bit j mod 64 of word j / 64,
+ * LSB-first; bits past n_bits are ignored) into library memory and builds their rank directory
+ * (L1 per 65536 bits, L2 per |L2| bits; Section 4.1) and select samples (every s-th one and zero;
+ * Section 4.2), with |L2| and s from opts (NULL: 512 and 4096). A bit array is the one level of a
+ * wavelet tree over the binary alphabet, so the result is an ordinary tree with sigma = 2 and one
+ * level: wt_access(i) gives bit i, wt_rank with symbol b gives rank_b(i) (b in {0, 1}), wt_select
+ * with symbol b gives the 0-based position of the k-th bit b, with the sentinels of those calls;
+ * wt_export, wt_info, wt_learn_select / wt_select_learned and wt_free work on it as on any tree.
+ * Enqueued on `stream`, waits for completion; d_words is not retained.
+ * Errors: WT_ERR_ARG (NULL pointers, n_bits >= 2^40, bad options), WT_ERR_OOM, WT_ERR_HIP.
+ */
+wt_status wt_bv_build(const uint64_t* d_words, uint64_t n_bits, const wt_build_opts* opts, wt_stream_t stream,
+                      wt_tree** out);
+
 /* ---- learned select index (an extension of Section 5.4; not in the thesis) ----
  *
  * For every child node of the tree (a node's zeros side or ones side at some level) a small FP32

@@ -37,7 +37,7 @@ ABI_FUNCTIONS = ("wt_set_allocator", "wt_build", "wt_free", "wt_access", "wt_ran
                  "wt_select_learned", "wt_learned_info", "wt_learned_model", "wt_mlp_loss_grad",
                  "wt_build_forest", "wt_forest_tree", "wt_forest_info", "wt_forest_free", "wt_query_mixed",
                  "wt_autotune", "wt_server_create", "wt_server_run", "wt_server_destroy", "wt_query_profiling",
-                 "wt_query_profile")
+                 "wt_query_profile", "wt_bv_build")
 OP_ACCESS, OP_RANK, OP_SELECT, OP_SELECT_LEARNED = 0, 1, 2, 3
 TUNE_NB, TUNE_SB = 21, 7
 MLP_PARAMS = 49
@@ -159,6 +159,8 @@ def lib():
     vp, u64, u32 = ctypes.c_void_p, ctypes.c_uint64, ctypes.c_uint32
     L.wt_build.restype = ctypes.c_int
     L.wt_build.argtypes = [vp, u64, u32, u64, ctypes.POINTER(BuildOpts), vp, ctypes.POINTER(vp)]
+    L.wt_bv_build.restype = ctypes.c_int
+    L.wt_bv_build.argtypes = [vp, u64, ctypes.POINTER(BuildOpts), vp, ctypes.POINTER(vp)]
     L.wt_free.restype = ctypes.c_int
     L.wt_free.argtypes = [vp]
     L.wt_access.restype = ctypes.c_int
@@ -385,6 +387,21 @@ class Tree:
             self.free()
         except Exception:
             pass
+
+
+def build_bitvector(words, n_bits: int, l2_bits: int = 512, sample_rate: int = 4096, stream=None) -> Tree:
+    """Rank/select support of a plain bit array: `words` is a device tensor of uint64 words (bit j at bit
+    j mod 64 of word j / 64); the result is a tree over the binary alphabet (sigma = 2, one level):
+    access(i) is bit i, rank(b, i) is rank_b(i), select(b, k) the position of the k-th bit b."""
+    torch = _torch()
+    if n_bits and (words.dtype != torch.uint64 or not words.is_cuda or not words.is_contiguous()
+                   or words.numel() * 64 < n_bits):
+        raise ValueError("words must be a contiguous device tensor of uint64 holding n_bits bits")
+    opts = BuildOpts(l2_bits, sample_rate, 0, 0)
+    h = ctypes.c_void_p(0)
+    _check(lib().wt_bv_build(ctypes.c_void_p(words.data_ptr() if n_bits else 0), n_bits, ctypes.byref(opts),
+                             ctypes.c_void_p(_stream_handle(stream)), ctypes.byref(h)))
+    return Tree(h.value)
 
 
 def build(sym, sigma: int, l2_bits: int = 512, sample_rate: int = 4096, profile: bool = False, stream=None) -> Tree:

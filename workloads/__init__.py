@@ -67,6 +67,8 @@ def lib():
         L.gen_draw_from_seq.argtypes = [ctypes.c_uint64, ctypes.c_void_p, ctypes.c_uint64, ctypes.c_int,
                                         ctypes.c_uint64, _u32p]
         L.gen_draw_rank_in_count.argtypes = [ctypes.c_uint64, _u32p, _u64p, ctypes.c_uint64, _u64p]
+        L.gen_bits.argtypes = [ctypes.c_uint64, ctypes.c_uint64, ctypes.c_uint64, ctypes.c_double, ctypes.c_double,
+                               _u64p]
         _lib = L
     return _lib
 
@@ -220,6 +222,40 @@ def make(name: str, n: int | None = None, q: int | None = None, kinds=("access",
     S, sigma = make_text(name, n)
     qs = make_queries(name, S, sigma, q, kinds)
     return Workload(name=name, S=S, sigma=sigma, **qs)
+
+
+# ---- bit arrays of the rank/select benchmark (thesis Section 6.1, after Kurpicz's experiments) ----
+
+BITVEC = dict(index=5, n_bits=1 << 32, fills=(0.1, 0.5, 0.9), queries=100_000_000, l2_bits=512, sample_rate=16384)
+
+
+def bit_words(seed: int, n_bits: int, fill: float, adversarial: bool) -> np.ndarray:
+    """u64 words of a bit array whose fraction `fill` of bits are ones (in expectation). Uniform: every bit
+    is one with probability fill. Adversarial: 99 % of the ones in the last fraction `fill` of the array
+    and 1 % in the first 1 - fill, i.e. densities 0.99 there and 0.01 fill / (1 - fill) before."""
+    words = np.zeros(max((n_bits + 63) // 64, 1), dtype=np.uint64)
+    if adversarial:
+        split = int(round((1.0 - fill) * n_bits))
+        p_lo = 0.01 * fill / (1.0 - fill) if fill < 1.0 else 0.0
+        p_hi = 0.99
+    else:
+        split, p_lo, p_hi = 0, fill, fill
+    lib().gen_bits(seed, n_bits, split, p_lo, p_hi, _ptr(words, _u64p))
+    return words[: (n_bits + 63) // 64]
+
+
+def unpack_bits(words: np.ndarray, n_bits: int) -> np.ndarray:
+    """Bits as a u8 array of 0/1 (bit j of the array at index j)."""
+    return np.unpackbits(words.view(np.uint8), bitorder="little")[:n_bits]
+
+
+def make_bitvec_queries(seed: int, n_bits: int, ones: int, q: int) -> dict:
+    """access and rank positions uniform in [0, n) and [0, n]; select k uniform in [1, count_b]."""
+    zeros = n_bits - ones
+    out = {"pos": uniform(subseed(seed, 1), q, max(n_bits, 1)), "rank_i": uniform(subseed(seed, 2), q, n_bits + 1)}
+    out["k1"] = 1 + uniform(subseed(seed, 3), q, max(ones, 1)) if ones else np.zeros(q, np.uint64)
+    out["k0"] = 1 + uniform(subseed(seed, 4), q, max(zeros, 1)) if zeros else np.zeros(q, np.uint64)
+    return out
 
 
 # ---- batched forest: many sequences of uneven length and alphabet ----

@@ -130,3 +130,20 @@ void gen_draw_rank_in_count(uint64_t seed, const uint32_t* c, const uint64_t* co
     out_k[j] = m ? 1 + below(rng_at(seed, (uint64_t)j), m) : 0;
   }
 }
+
+/* Words of a bit array (bit j at bit j mod 64 of word j / 64): bit j is one when the uniform double of
+   out(seed, j) is below p_lo for j < split and below p_hi from split on; bits past n_bits are zero. */
+void gen_bits(uint64_t seed, uint64_t n_bits, uint64_t split, double p_lo, double p_hi, uint64_t* words) {
+  const int64_t nw = (int64_t)((n_bits + 63) / 64);
+#pragma omp parallel for schedule(static)
+  for (int64_t w = 0; w < nw; ++w) {
+    uint64_t x = 0;
+    for (uint64_t b = 0; b < 64; ++b) {
+      const uint64_t j = 64 * (uint64_t)w + b;
+      if (j >= n_bits) break;
+      const double p = j < split ? p_lo : p_hi;
+      if (unit01(rng_at(seed, j)) < p) x |= 1ull << b;
+    }
+    words[w] = x;
+  }
+}
