@@ -69,6 +69,10 @@ def lib():
         L.oracle_mlp_forward.argtypes = [_f64p, ctypes.c_double]
         L.oracle_mlp_loss_grad.restype = ctypes.c_double
         L.oracle_mlp_loss_grad.argtypes = [_f64p, _f64p, _f64p, ctypes.c_int, _f64p]
+        L.oracle_wm_level_bits.restype = ctypes.c_int
+        L.oracle_wm_level_bits.argtypes = [ctypes.c_void_p, ctypes.c_uint64, ctypes.c_int, ctypes.c_uint64,
+                                           ctypes.c_uint64, _u64p, _u64p]
+        L.oracle_wm_starts.argtypes = [ctypes.c_void_p, ctypes.c_uint64, ctypes.c_int, ctypes.c_uint64, _u64p]
         L.oracle_alphabet.restype = ctypes.c_uint64
         L.oracle_alphabet.argtypes = [ctypes.c_void_p, ctypes.c_uint64, ctypes.c_int, _u64p]
         L.oracle_par_threads.restype = ctypes.c_int
@@ -185,6 +189,55 @@ class OracleTree:
 
     def bit_string(self, l: int) -> str:
         return "".join(str(self.bit(l, j)) for j in range(self.level_n[l]))
+
+
+class OracleMatrix:
+    """Every part of the wavelet matrix of S (all n elements at every level; see wt_oracle.c), with the
+    same rank directory and select samples per level as the tree."""
+
+    def __init__(self, S: np.ndarray, sigma: int, l2_bits: int = 512, sample_rate: int = 4096):
+        S = _seq(S)
+        self.n = int(S.size)
+        self.sigma = int(sigma)
+        self.L = num_levels(sigma)
+        L, n = self.L, self.n
+        stride = max(1, (n + 63) // 64)
+        bits = np.zeros((max(L, 1), stride), dtype=np.uint64)
+        zeros = np.zeros(max(L, 1), dtype=np.uint64)
+        rc = lib().oracle_wm_level_bits(ctypes.c_void_p(S.ctypes.data), n, S.dtype.itemsize, sigma, stride,
+                                        _p(bits, _u64p), _p(zeros, _u64p))
+        if rc != 0:
+            raise ValueError("symbol out of range")
+        self.zeros = [int(z) for z in zeros[:L]]
+        self.starts = np.zeros(max(sigma, 1), dtype=np.uint64)
+        lib().oracle_wm_starts(ctypes.c_void_p(S.ctypes.data), n, S.dtype.itemsize, sigma, _p(self.starts, _u64p))
+        self.starts = self.starts[:sigma]
+        self.bits, self.L1, self.L2, self.samples1, self.samples0, self.ones = [], [], [], [], [], []
+        for l in range(L):
+            row = np.ascontiguousarray(bits[l, : (n + 63) // 64])
+            self.bits.append(row)
+            rowp = np.ascontiguousarray(bits[l])
+            L1 = np.zeros((n + 65535) // 65536 + 1, dtype=np.uint64)
+            L2 = np.zeros((n + l2_bits - 1) // l2_bits + 1, dtype=np.uint16)
+            lib().oracle_directory(_p(rowp, _u64p), n, l2_bits, _p(L1, _u64p), _p(L2, _u16p))
+            self.L1.append(L1)
+            self.L2.append(L2)
+            cap = n // sample_rate + 1
+            s1 = np.zeros(cap, dtype=np.uint64)
+            s0 = np.zeros(cap, dtype=np.uint64)
+            n1 = ctypes.c_uint64(0)
+            n0 = ctypes.c_uint64(0)
+            lib().oracle_samples(_p(rowp, _u64p), n, sample_rate, _p(s1, _u64p), ctypes.byref(n1),
+                                 _p(s0, _u64p), ctypes.byref(n0))
+            self.samples1.append(s1[: n1.value].copy())
+            self.samples0.append(s0[: n0.value].copy())
+            self.ones.append(int(L1[-1]))
+
+    def bit(self, l: int, j: int) -> int:
+        return int((int(self.bits[l][j // 64]) >> (j % 64)) & 1)
+
+    def bit_string(self, l: int) -> str:
+        return "".join(str(self.bit(l, j)) for j in range(self.n))
 
 
 def access(S: np.ndarray, pos: np.ndarray) -> np.ndarray:

@@ -213,6 +213,63 @@ void oracle_nodes(const void* S, uint64_t n, int w, uint64_t sigma, int l, const
   free(zeros_before); free(code); free(len); free(exists); free(count);
 }
 
+/*
+ * Wavelet matrix (named in the thesis's Conclusion as a further layout; the structure of Claude,
+ * Navarro and Ordonez): every level holds all n elements. Symbols are plain L-bit binary numbers
+ * (L = ceil(lg sigma)). Level l holds S stably sorted by the key rev_l(c >> (L - l)), the top l bits
+ * of the symbol read in reverse order (the least significant of them first), which is what l stable
+ * zeros-then-ones partitions by the bits L-1, L-2, ... leave behind; its bit for an element is bit
+ * L-1-l of the symbol. zeros[l] receives the zeros of level l. Returns -1 if a symbol is >= sigma.
+ */
+static uint64_t rev_bits(uint64_t x, int l) {
+  uint64_t r = 0;
+  for (int i = 0; i < l; ++i) r |= ((x >> i) & 1) << (l - 1 - i);
+  return r;
+}
+
+int oracle_wm_level_bits(const void* S, uint64_t n, int w, uint64_t sigma, uint64_t stride, uint64_t* bits,
+                         uint64_t* zeros) {
+  int L = oracle_num_levels(sigma);
+  if (L == 0) return 0;
+  for (uint64_t i = 0; i < n; ++i)
+    if (sym_at(S, w, i) >= sigma) return -1;
+  uint64_t* order = (uint64_t*)malloc((n ? n : 1) * sizeof(uint64_t));
+  memset(bits, 0, (size_t)L * stride * sizeof(uint64_t));
+  for (int l = 0; l < L; ++l) {
+    /* stable counting sort of positions by the reversed top-l bits */
+    uint64_t nkeys = 1ull << l;
+    uint64_t* start = (uint64_t*)calloc(nkeys + 1, sizeof(uint64_t));
+    for (uint64_t i = 0; i < n; ++i) start[rev_bits(sym_at(S, w, i) >> (L - l), l) + 1]++;
+    for (uint64_t k = 0; k < nkeys; ++k) start[k + 1] += start[k];
+    for (uint64_t i = 0; i < n; ++i) order[start[rev_bits(sym_at(S, w, i) >> (L - l), l)]++] = i;
+    free(start);
+    uint64_t* row = bits + (size_t)l * stride;
+    uint64_t z = 0;
+    for (uint64_t r = 0; r < n; ++r) {
+      uint64_t b = (sym_at(S, w, order[r]) >> (L - 1 - l)) & 1;
+      if (b) row[r / 64] |= 1ull << (r % 64);
+      else ++z;
+    }
+    zeros[l] = z;
+  }
+  free(order);
+  return 0;
+}
+
+/* Start of every symbol's run in the order below the last wavelet-matrix level (S stably sorted by
+   rev_L(c)): starts[c] = number of elements whose reversed symbol is smaller than rev_L(c). */
+void oracle_wm_starts(const void* S, uint64_t n, int w, uint64_t sigma, uint64_t* starts) {
+  int L = oracle_num_levels(sigma);
+  for (uint64_t c = 0; c < sigma; ++c) {
+    uint64_t rc = rev_bits(c, L), before = 0;
+    for (uint64_t i = 0; i < n; ++i) {
+      uint64_t x = sym_at(S, w, i);
+      if (x < sigma && rev_bits(x, L) < rc) ++before;
+    }
+    starts[c] = before;
+  }
+}
+
 /* Minimal alphabet (Section 5.1: the symbols are the distinct values of the sequence, numbered in
    increasing order): the distinct values of S, ascending, in values[] (capacity n); returns their number. */
 static int u64_cmp(const void* a, const void* b) {
