@@ -257,17 +257,34 @@ int oracle_wm_level_bits(const void* S, uint64_t n, int w, uint64_t sigma, uint6
 }
 
 /* Start of every symbol's run in the order below the last wavelet-matrix level (S stably sorted by
-   rev_L(c)): starts[c] = number of elements whose reversed symbol is smaller than rev_L(c). */
+   rev_L(c)): starts[c] = number of elements whose reversed symbol is smaller than rev_L(c), i.e. the
+   exclusive prefix sums of the counts taken in increasing order of the reversed symbols (a sort of
+   the symbols by their reversed codes gives that order). */
+typedef struct { uint64_t key, c; } rkey;
+
+static int rkey_cmp(const void* a, const void* b) {
+  const rkey* x = (const rkey*)a;
+  const rkey* y = (const rkey*)b;
+  return x->key < y->key ? -1 : (x->key > y->key);
+}
+
 void oracle_wm_starts(const void* S, uint64_t n, int w, uint64_t sigma, uint64_t* starts) {
   int L = oracle_num_levels(sigma);
-  for (uint64_t c = 0; c < sigma; ++c) {
-    uint64_t rc = rev_bits(c, L), before = 0;
-    for (uint64_t i = 0; i < n; ++i) {
-      uint64_t x = sym_at(S, w, i);
-      if (x < sigma && rev_bits(x, L) < rc) ++before;
-    }
-    starts[c] = before;
+  uint64_t* cnt = (uint64_t*)calloc(sigma ? sigma : 1, sizeof(uint64_t));
+  for (uint64_t i = 0; i < n; ++i) {
+    uint64_t x = sym_at(S, w, i);
+    if (x < sigma) cnt[x]++;
   }
+  rkey* order = (rkey*)malloc((sigma ? sigma : 1) * sizeof(rkey));
+  for (uint64_t c = 0; c < sigma; ++c) { order[c].key = rev_bits(c, L); order[c].c = c; }
+  qsort(order, sigma, sizeof(rkey), rkey_cmp);
+  uint64_t before = 0;
+  for (uint64_t r = 0; r < sigma; ++r) {
+    starts[order[r].c] = before;
+    before += cnt[order[r].c];
+  }
+  free(order);
+  free(cnt);
 }
 
 /* Minimal alphabet (Section 5.1: the symbols are the distinct values of the sequence, numbered in
