@@ -116,6 +116,20 @@ wt_status wt_rank(const wt_tree* t, const uint32_t* d_sym, const uint64_t* d_pos
 wt_status wt_select(const wt_tree* t, const uint32_t* d_sym, const uint64_t* d_k, uint64_t q, uint64_t* d_out,
                     wt_stream_t stream);
 
+/*
+ * wt_select without allocation, for callers that cannot allocate device memory (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc): same arguments, answers and
+ * sentinels as wt_select, and the same kernels. The binning buffers (and, for a tree built with
+ * sigma = 0, the symbols mapped to codes) live in a statically sized device array of the library,
+ * about 20.6 MiB, that every GPU the library runs on holds until the process ends; the call makes no
+ * allocation and no hipFree. At most 2^20 queries per call (WT_ERR_ARG above that; use wt_select).
+ * Every call on one GPU shares that GPU's array: calls that overlap on one GPU (two streams, or two
+ * threads) race and must be serialised by the caller (one stream, or an event between them).
+ * The first call on a device looks up the array's device address (hipGetSymbolAddress).
+ */
+wt_status wt_select_noalloc(const wt_tree* t, const uint32_t* d_sym, const uint64_t* d_k, uint64_t q,
+                            uint64_t* d_out, wt_stream_t stream);
+
 /* Sizes and per-level counts of a built tree. */
 typedef struct {
   uint64_t n, sigma;

@@ -37,7 +37,7 @@ ABI_FUNCTIONS = ("wt_set_allocator", "wt_build", "wt_free", "wt_access", "wt_ran
                  "wt_select_learned", "wt_learned_info", "wt_learned_model", "wt_mlp_loss_grad",
                  "wt_build_forest", "wt_forest_tree", "wt_forest_info", "wt_forest_free", "wt_query_mixed",
                  "wt_autotune", "wt_server_create", "wt_server_run", "wt_server_destroy", "wt_query_profiling",
-                 "wt_query_profile", "wt_bv_build")
+                 "wt_query_profile", "wt_bv_build", "wt_select_noalloc")
 OP_ACCESS, OP_RANK, OP_SELECT, OP_SELECT_LEARNED = 0, 1, 2, 3
 TUNE_NB, TUNE_SB = 21, 7
 MLP_PARAMS = 49
@@ -169,6 +169,8 @@ def lib():
     L.wt_rank.argtypes = [vp, vp, vp, u64, vp, vp]
     L.wt_select.restype = ctypes.c_int
     L.wt_select.argtypes = [vp, vp, vp, u64, vp, vp]
+    L.wt_select_noalloc.restype = ctypes.c_int
+    L.wt_select_noalloc.argtypes = [vp, vp, vp, u64, vp, vp]
     L.wt_info.restype = ctypes.c_int
     L.wt_info.argtypes = [vp, ctypes.POINTER(Info)]
     L.wt_export.restype = ctypes.c_int
@@ -326,6 +328,17 @@ class Tree:
             out = torch.empty(q, dtype=torch.uint64, device=k.device)
         _check(lib().wt_select(self._h, _dev_ptr(sym, torch.uint32, "sym"), _dev_ptr(k, torch.uint64, "k"), q,
                                _dev_ptr(out, torch.uint64, "out"), ctypes.c_void_p(_stream_handle(stream))))
+        return out
+
+    def select_noalloc(self, sym, k, out, stream=None):
+        """select through wt_select_noalloc (no device allocation; out must be given, q <= 2^20)."""
+        torch = _torch()
+        q = k.numel()
+        if sym.numel() != q or out.numel() != q:
+            raise ValueError("sym, k and out must have the same length")
+        _check(lib().wt_select_noalloc(self._h, _dev_ptr(sym, torch.uint32, "sym"), _dev_ptr(k, torch.uint64, "k"),
+                                       q, _dev_ptr(out, torch.uint64, "out"),
+                                       ctypes.c_void_p(_stream_handle(stream))))
         return out
 
     def learn_select(self, epochs: int = 0, max_points: int = 0, lr: float = 0.0, stream=None) -> dict:

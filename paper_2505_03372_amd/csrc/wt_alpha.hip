@@ -139,21 +139,21 @@ __global__ __launch_bounds__(kAT) void k_alpha_unmap(const uint32_t* __restrict_
 static uint32_t grid_for(uint64_t n) { return (uint32_t)std::min<uint64_t>(std::max<uint64_t>(ceil_div(n, kAT), 1), 8192); }
 
 wt_status alpha_map_syms(const wt_tree* t, const uint32_t* d_sym, uint64_t q, hipStream_t st, const uint32_t** mapped,
-                         void** scratch) {
+                         void** scratch, uint32_t* buf) {
   *mapped = d_sym;
   *scratch = nullptr;
   if (!t->amap || q == 0) return WT_OK;
-  uint32_t* m = (uint32_t*)dev_alloc(q * 4, st);
+  uint32_t* m = buf ? buf : (uint32_t*)dev_alloc(q * 4, st);
   if (!m) return fail(WT_ERR_OOM, "symbol mapping: allocation of %llu bytes failed", (unsigned long long)(q * 4));
   hipLaunchKernelGGL(k_alpha_map, dim3(grid_for(q)), dim3(kAT), 0, st, t->amap, t->amap_words, (uint32_t)t->sigma,
                      d_sym, q, m);
   const hipError_t e = hipGetLastError();
   if (e != hipSuccess) {
-    dev_free(m, st);
+    if (!buf) dev_free(m, st);
     return fail(WT_ERR_HIP, "symbol mapping: %s", hipGetErrorString(e));
   }
   *mapped = m;
-  *scratch = m;
+  *scratch = buf ? nullptr : m;
   return WT_OK;
 }
 

@@ -43,9 +43,10 @@ wt_status build_tree(const void* d_sym, uint64_t n, uint32_t sym_bytes, uint64_t
                      wt_stream_t stream, wt_tree** out);
 // Extracted alphabets (wt_alpha.hip): query symbols as codes (*mapped = d_sym when the tree has a
 // declared alphabet; otherwise a q-entry buffer, returned in *scratch for the caller to free after the
-// traversal) and access answers back to values.
+// traversal; with `buf` given, that q-entry buffer is used and nothing is allocated) and access answers
+// back to values.
 wt_status alpha_map_syms(const wt_tree* t, const uint32_t* d_sym, uint64_t q, hipStream_t st, const uint32_t** mapped,
-                         void** scratch);
+                         void** scratch, uint32_t* buf = nullptr);
 wt_status alpha_unmap_access(const wt_tree* t, uint32_t* d_out, uint64_t q, hipStream_t st);
 // out[i] = sum of in[0, i) (wt_build.hip); part: ceil(n / 4096) + 1 entries of scratch.
 hipError_t exclusive_scan_u64(const uint64_t* in, uint64_t n, uint64_t* out, uint64_t* part, hipStream_t st);

@@ -15,6 +15,7 @@
 
 #include <algorithm>
 #include <cstring>
+#include <mutex>
 #include <vector>
 
 #include "wt_host.h"
@@ -307,19 +308,29 @@ void sort_ids_enqueue(const uint16_t* ids, uint64_t q, char* scratch, uint32_t* 
 
 // Bins the batch on st (kind 0 access, 1 rank, 2 select); binned = false when the batch is too small
 // to pay (or too large for 32-bit slots).
+// Bytes of the binning buffers of a batch of q queries: per-block bucket histograms, bucket totals, slots.
+size_t sort_batch_bytes(uint64_t q) {
+  const uint32_t nblk = (uint32_t)ceil_div(q, kBinChunk);
+  return round_up((size_t)nblk * kBins * 4, 256) + round_up(4 * kBins, 256) + round_up(sizeof(SQ) * q, 256);
+}
+
 wt_status sort_batch(const wt_tree* t, const QArgs& a, int kind, const uint32_t* sym, const uint64_t* arg,
-                     uint64_t q, hipStream_t st, SortBufs& sb, bool& binned) {
+                     uint64_t q, hipStream_t st, SortBufs& sb, bool& binned, char* pre) {
   binned = false;
   if (q < kSortMinQ || q >= (1ull << 32)) return WT_OK;
   const uint32_t nblk = (uint32_t)ceil_div(q, kBinChunk);
-  const size_t o_t = round_up((size_t)nblk * kBins * 4, 256), o_p = o_t + round_up(4 * kBins, 256),
-               bytes = o_p + sizeof(SQ) * q;
-  sb.block = (char*)dev_alloc(bytes, st);
-  if (!sb.block) return fail(WT_ERR_OOM, "query binning: scratch allocation of %zu bytes failed", bytes);
-  uint32_t* bhist = (uint32_t*)sb.block;
-  uint32_t* tot = (uint32_t*)(sb.block + o_t);
+  const size_t o_t = round_up((size_t)nblk * kBins * 4, 256), o_p = o_t + round_up(4 * kBins, 256);
+  char* blk = pre;
+  if (!blk) {
+    const size_t bytes = sort_batch_bytes(q);
+    sb.block = (char*)dev_alloc(bytes, st);
+    if (!sb.block) return fail(WT_ERR_OOM, "query binning: scratch allocation of %zu bytes failed", bytes);
+    blk = sb.block;
+  }
+  uint32_t* bhist = (uint32_t*)blk;
+  uint32_t* tot = (uint32_t*)(blk + o_t);
   sb.cnt = tot;
-  sb.sq = (SQ*)(sb.block + o_p);
+  sb.sq = (SQ*)(blk + o_p);
   uint32_t bits = 0;
   while ((1ull << bits) < a.n + 1) ++bits;
   const uint32_t shift = bits > 15 ? bits - 15 : 0;
@@ -444,6 +455,81 @@ extern "C" wt_status wt_select(const wt_tree* t, const uint32_t* d_sym, const ui
   }
   qprof_end(st);
   if (mapped) dev_free(mapped, st);
+  WT_HIP(hipGetLastError());
+  return WT_OK;
+}
+
+// ---------------------------------------------------------------- select without allocation
+
+namespace wt {
+namespace {
+// Largest batch of wt_select_noalloc and the bytes of its scratch: the binning buffers of such a batch
+// followed by its symbols mapped to codes (trees with an extracted alphabet).
+constexpr uint64_t kNoAllocMaxQ = 1ull << 20;
+constexpr size_t kNoAllocSortBytes = ((kNoAllocMaxQ + kBinChunk - 1) / kBinChunk) * kBins * 4 +
+                                     4 * kBins + sizeof(SQ) * kNoAllocMaxQ;
+constexpr size_t kNoAllocBytes = kNoAllocSortBytes + 4 * kNoAllocMaxQ;
+static_assert(kNoAllocSortBytes % 256 == 0, "mapped symbols start 256-byte aligned");
+}  // namespace
+}  // namespace wt
+
+// Device memory of wt_select_noalloc (each GPU holds its own copy while the library is loaded). Host
+// code never passes this name to a kernel: it takes the device address from hipGetSymbolAddress.
+static __device__ __align__(256) char scratch[wt::kNoAllocBytes];
+
+namespace wt {
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+char* g_scratch_ptr[kMaxDevices] = {};
+
+// Address of the current device's scratch array, looked up once per device.
+wt_status noalloc_scratch(char** out) {
+  int dev = 0;
+  WT_HIP(hipGetDevice(&dev));
+  if (dev < 0 || dev >= kMaxDevices) return fail(WT_ERR_STATE, "wt_select_noalloc: device %d out of range", dev);
+  std::lock_guard<std::mutex> g(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    WT_HIP(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+    if (!p) return fail(WT_ERR_HIP, "wt_select_noalloc: no device address for the scratch array");
+    g_scratch_ptr[dev] = (char*)p;
+  }
+  *out = g_scratch_ptr[dev];
+  return WT_OK;
+}
+}  // namespace
+}  // namespace wt
+
+extern "C" wt_status wt_select_noalloc(const wt_tree* t, const uint32_t* d_sym, const uint64_t* d_k, uint64_t q,
+                                       uint64_t* d_out, wt_stream_t stream) {
+  clear_error();
+  if (!t) return fail(WT_ERR_ARG, "wt_select_noalloc: tree is NULL");
+  if (q > kNoAllocMaxQ)
+    return fail(WT_ERR_ARG, "wt_select_noalloc: %llu queries exceed the limit of %llu (use wt_select)",
+                (unsigned long long)q, (unsigned long long)kNoAllocMaxQ);
+  if (q == 0) return WT_OK;
+  if (!d_sym || !d_k || !d_out) return fail(WT_ERR_ARG, "wt_select_noalloc: NULL buffer");
+  char* buf = nullptr;
+  wt_status rc = noalloc_scratch(&buf);
+  if (rc != WT_OK) return rc;
+  hipStream_t st = (hipStream_t)stream;
+  const QArgs a = make_args(t);
+  const uint32_t* sym = d_sym;
+  void* mapped = nullptr;
+  rc = alpha_map_syms(t, d_sym, q, st, &sym, &mapped, (uint32_t*)(buf + kNoAllocSortBytes));
+  if (rc != WT_OK) return rc;
+  SortBufs sb;
+  bool binned;
+  rc = sort_batch(t, a, 2, sym, d_k, q, st, sb, binned, buf);
+  if (rc != WT_OK) return rc;
+  if (binned) {
+    const uint32_t grid = query_grid(q, kQB);
+    WT_DISPATCH_L2(t->l2_bits, kQB, k_select, a, sym, d_k, q, d_out, (const SQ*)sb.sq, sb.subshift);
+  } else {
+    const uint32_t grid = query_grid(q, kQT);
+    WT_DISPATCH_L2(t->l2_bits, kQT, k_select, a, sym, d_k, q, d_out, (const SQ*)nullptr, 0u);
+  }
   WT_HIP(hipGetLastError());
   return WT_OK;
 }

@@ -430,7 +430,8 @@ void qprof_end(hipStream_t st);
 
 // Locality binning of a query batch (wt_query.hip): on success with `binned`, sq holds the queries in
 // bucket order (slot j runs query sq[j].id with the arguments stored beside it); the caller frees
-// `block` (stream-ordered) after its traversal.
+// `block` (stream-ordered) after its traversal. With `pre` given (sort_batch_bytes(q) bytes of device
+// memory), the buffers are carved from it, nothing is allocated and `block` stays NULL.
 struct SortBufs {
   char* block = nullptr;
   uint32_t* cnt;
@@ -438,7 +439,8 @@ struct SortBufs {
   uint32_t subshift = 0;  // key bits below the ones that order queries inside a block
 };
 wt_status sort_batch(const wt_tree* t, const QArgs& a, int kind, const uint32_t* sym, const uint64_t* arg, uint64_t q,
-                     hipStream_t st, SortBufs& sb, bool& binned);
+                     hipStream_t st, SortBufs& sb, bool& binned, char* pre = nullptr);
+size_t sort_batch_bytes(uint64_t q);
 
 // Counting sort of q queries by bucket id (ids[j] < 32768; wt_query.hip). scratch: sort_ids_bytes(q)
 // bytes; tot: 32768 entries, left holding the exclusive start of every bucket; perm: the slot order.
