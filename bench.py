@@ -1,6 +1,6 @@
 """Benchmark of the wavelet-tree hot path on one MI355X.
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload text_zipf|large_alpha|forest|serve]
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload text_zipf|large_alpha|forest|serve|bitvec]
                     [--l2-bits B] [--sample-rate S] [--no-learned] [--no-cpu-baseline]
 
 One step = one pass of the whole hot path over one batch of synthetic input already resident in
@@ -26,6 +26,11 @@ and three query calls per tree) for the comparison.
 in [1, 2^20] (70 % select, 20 % rank, 10 % access) from page-locked host memory, replayed at
 saturation and at Poisson arrivals of 0.5, 0.8 and 0.95 of the saturation rate; p50/p99 latency and
 queries/s. (Selects inside mixed batches use the plain sampled search.)
+
+The default run also measures, outside its timed steps, the large-alphabet configuration (2^28 u32
+symbols, sigma 2^20; key `large_alpha`) and the rank/select benchmark of plain bit arrays (2^32 bits,
+fill 10/50/90 %, uniform and adversarial placement, |L2| 512, s 16384, 10^8 queries of each of
+rank0/rank1/select0/select1; key `bitvec`).
 """
 from __future__ import annotations
 
@@ -346,6 +351,96 @@ def main_serve(args, torch, wt, workloads, dev):
     print(json.dumps(line), flush=True)
 
 
+def run_bitvec(torch, wt, workloads, dev, n_bits: int, nq: int, reps: int = 3) -> dict:
+    """Rank/select support of plain bit arrays (the thesis's rank/select benchmark): fill 10/50/90 %,
+    uniform and adversarial placement of the ones, |L2| = 512, s = 16384; per array the build (event
+    pair around wt_bv_build) and nq each of rank0, rank1, select0, select1 (positions uniform in
+    [0, n_bits), k uniform in [1, count of b]); medians of `reps` timed runs after one warm-up."""
+    l2, srate = 512, 16384
+    base = workloads.subseed(workloads.base_seed(5), 0)
+    pos = torch.from_numpy(workloads.uniform(workloads.subseed(base, 1), nq, n_bits)).to(dev)
+    raw = torch.from_numpy((workloads.raw(workloads.subseed(base, 2), 0, nq) >> np.uint64(1)).astype(np.int64)).to(dev)
+    out = torch.empty(nq, dtype=torch.uint64, device=dev)
+    syms = [torch.full((nq,), b, dtype=torch.uint32, device=dev) for b in (0, 1)]
+    stream = torch.cuda.current_stream()
+
+    def timed(fn):
+        ms = []
+        for r in range(reps + 1):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            fn()
+            e1.record(stream)
+            torch.cuda.synchronize()
+            if r:
+                ms.append(e0.elapsed_time(e1))
+        return float(np.median(ms))
+
+    res = {}
+    wt.query_profiling(True)
+    for dist in ("uniform", "adversarial"):
+        for fill in (0.1, 0.5, 0.9):
+            adv = dist == "adversarial"
+            seed = workloads.subseed(base, 10 + 10 * int(adv) + int(round(fill * 10)))
+            words = torch.from_numpy(workloads.bit_words(seed, n_bits, fill, adv)).to(dev)
+            torch.cuda.synchronize()
+            bl = []
+            for rep in range(reps + 1):
+                e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                e0.record(stream)
+                t = wt.build_bitvector(words, n_bits, l2_bits=l2, sample_rate=srate)
+                e1.record(stream)
+                torch.cuda.synchronize()
+                if rep:
+                    bl.append(e0.elapsed_time(e1))
+                if rep < reps:
+                    t.free()
+            bms = float(np.median(bl))
+            ones = t.info["level_ones"][0]
+            cnt = {1: ones, 0: n_bits - ones}
+            r = {"build_ms": bms, "ones": ones}
+            kern = {}
+
+            def kernels(key):
+                # per-kernel time of the calls just timed (binning passes and traversal), mean per call
+                acc = {}
+                for e in wt.query_profile():
+                    acc[e["kernel"]] = acc.get(e["kernel"], 0.0) + e["ms"] / (reps + 1)
+                kern[key] = acc
+
+            wt.query_profile()  # drop what the build left
+            for b in (0, 1):
+                r["rank%d_ms" % b] = timed(lambda: t.rank(syms[b], pos, out=out))
+                kernels("rank%d" % b)
+                k = (raw % max(cnt[b], 1) + 1).to(torch.uint64)
+                r["select%d_ms" % b] = timed(lambda: t.select(syms[b], k, out=out))
+                kernels("select%d" % b)
+                del k
+            for key in ("rank0", "rank1", "select0", "select1"):
+                r[key + "_queries_per_s"] = nq / (r[key + "_ms"] * 1e-3)
+            r["kernel_ms_per_call"] = kern
+            r["build_bits_per_s"] = n_bits / (bms * 1e-3)
+            res["%s_%d" % (dist, int(fill * 100))] = r
+            t.free()
+            del words
+    # roofline of the slowest query kind: one 64-byte block of bits per query (random lines)
+    worst = max(((k, q) for k, v in res.items() for q in ("rank0", "rank1", "select0", "select1")),
+                key=lambda kq: res[kq[0]][kq[1] + "_ms"])
+    wt.query_profiling(False)
+    wms = res[worst[0]][worst[1] + "_ms"]
+    ach = 64.0 * nq / (wms * 1e-3) / 1e9
+    del pos, raw, out, syms
+    torch.cuda.synchronize()
+    torch.cuda.empty_cache()
+    return {"config": {"workload": "bitvec", "n_bits": n_bits, "queries_per_kind": nq, "l2_bits": l2,
+                       "sample_rate": srate, "fills": [10, 50, 90], "placements": ["uniform", "adversarial"],
+                       "runs": "median of %d after one warm-up" % reps},
+            "arrays": res,
+            "roofline_slowest": {"array": worst[0], "kind": worst[1], "bound": "hbm", "achieved": ach,
+                                 "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": ach / HBM_PEAK_GBS,
+                                 "note": "64 B (one L2 block of bits) per query, random lines"}}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -353,10 +448,12 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="text_zipf")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-extra", action="store_true", help="skip the large-alphabet leg of the default run")
+    ap.add_argument("--no-extra", action="store_true", help="skip the large-alphabet and bit-array legs of the default run")
     ap.add_argument("--no-learned", action="store_true", help="skip the learned select index (training + queries)")
     ap.add_argument("--l2-bits", type=int, default=0, help="bits per L2 block (256..2048; 0: library default)")
     ap.add_argument("--sample-rate", type=int, default=0, help="select sample rate s (0: library default)")
+    ap.add_argument("--bitvec-log2", type=int, default=32, help="bits of each array of the bit-array leg")
+    ap.add_argument("--bitvec-queries", type=int, default=100_000_000, help="queries per kind of the bit-array leg")
     ap.add_argument("--cpu-sample-log2", type=int, default=25)
     ap.add_argument("--cpu-queries-log2", type=int, default=20)
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -379,6 +476,17 @@ def main():
         return main_forest(args, torch, wt, workloads, dev)
     if args.workload == "serve":
         return main_serve(args, torch, wt, workloads, dev)
+    if args.workload == "bitvec":
+        bv = run_bitvec(torch, wt, workloads, dev, 1 << args.bitvec_log2, args.bitvec_queries)
+        worst = bv["roofline_slowest"]
+        tot_ms = sum(r[k] for r in bv["arrays"].values() for k in r if k.endswith("_ms"))
+        items = sum((1 << args.bitvec_log2) + 4 * args.bitvec_queries for _ in bv["arrays"])
+        print(json.dumps({"metric": "bit-array build bits/s + rank/select queries/s", "value": items / (tot_ms * 1e-3),
+                          "unit": "(bits+queries)/s", "n_gpus": 1, "steps": 3, "warmup": 1, "ms_per_step": tot_ms,
+                          "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "u64",
+                          "data": "synthetic", "config": bv["config"], "arrays": bv["arrays"], "roofline": worst}),
+              flush=True)
+        return
     res = run_tree(args, torch, wt, workloads, dev, args.workload, args.steps, args.warmup,
                    learned=not args.no_learned, kinds_wanted=("access", "rank", "select"))
     n, width, sigma, q = res["n"], res["width"], res["sigma"], res["q"]
@@ -416,6 +524,10 @@ def main():
             "ms_per_step": la["ms_per_step"], "value": la["items"] / (la["ms_per_step"] * 1e-3),
             "unit": "(symbols+queries)/s", "rates": la["rates"], "roofline": la["roofline"],
             "roofline_build": la["roofline_build"], "roofline_build_total": la["roofline_build_total"]}
+    if args.workload == "text_zipf" and not args.no_extra:
+        # the rank/select benchmark of plain bit arrays, outside the timed steps
+        print("# bit-array leg", file=sys.stderr, flush=True)
+        line["bitvec"] = run_bitvec(torch, wt, workloads, dev, 1 << args.bitvec_log2, args.bitvec_queries)
     if args.calibrate_copy:
         src = torch.empty(1 << 30, dtype=torch.uint8, device=dev)
         dst = torch.empty_like(src)

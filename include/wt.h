@@ -50,11 +50,23 @@ typedef enum {
 typedef struct {
   uint32_t l2_bits;     /* L2 block size |L2| in bits (Section 4.1): 256, 512 (default), 1024, 2048 */
   uint32_t sample_rate; /* select sample interval s (Section 4.2): power of two in [512, 2^20]; default 4096 */
-  uint32_t flags;       /* WT_BUILD_PROFILE: time every build kernel with HIP events (wt_build_profile) */
+  uint32_t flags;       /* WT_BUILD_PROFILE: time every build kernel with HIP events (wt_build_profile);
+                           WT_BUILD_MATRIX: build the wavelet matrix instead of the level-wise tree */
   uint32_t reserved;
 } wt_build_opts;
 
 #define WT_BUILD_PROFILE 1u
+/* Wavelet matrix (the layout the thesis's Conclusion names as further work; the structure of Claude,
+   Navarro and Ordonez): L = ceil(lg sigma) levels of n bits each, symbols as plain L-bit numbers (no
+   reduced codes). Level 0 holds S; level l + 1 holds level l stably partitioned by its bit: every zero
+   of the whole level before every one (no nodes), so an element at position p of level l with bit b is
+   at rank0_l(p), or at zeros_l + rank1_l(p), in level l + 1. Bit l of an element is bit L-1-l of its
+   symbol. Queries need one binary rank (access, rank) or select (select) per level and no node table;
+   rank and select also read start[c], the first position of symbol c's run in the order below the
+   last level. The same calls (access, rank, select and their sentinels, alphabet extraction, info,
+   export of bits / L1 / L2 / samples / WT_PART_WM_STARTS, wt_select_noalloc, wt_free) work on it; the
+   learned index, forests and the node-table parts do not (WT_ERR_ARG). */
+#define WT_BUILD_MATRIX 2u
 
 /* Largest declared alphabet: the node tables are indexed by code prefix (2^L entries). */
 #define WT_MAX_SIGMA (1ull << 24)
@@ -138,7 +150,7 @@ typedef struct {
   uint64_t level_ones[WT_MAX_LEVELS]; /* ones per level */
   uint64_t bytes_bits, bytes_l1, bytes_l2, bytes_samples, bytes_nodes, bytes_total; /* allocated */
   uint32_t alphabet_extracted; /* 1: built with sigma = 0 (queries map values to codes and back) */
-  uint32_t reserved0;
+  uint32_t matrix;             /* 1: a wavelet matrix (WT_BUILD_MATRIX); level_n[l] = n at every level */
   uint64_t max_symbol;         /* largest symbol value of the alphabet */
 } wt_info_t;
 
@@ -155,6 +167,10 @@ wt_status wt_info(const wt_tree* t, wt_info_t* out);
  *   WT_PART_CUM_HIST   u64[sigma+1]           exclusive prefix sums of the histogram (level ignored)
  *   WT_PART_ALPHABET   u32[sigma]             symbol value of every code (level ignored): the sorted
  *                                             distinct values of an extracted alphabet, else 0 .. sigma-1
+ *   WT_PART_WM_STARTS  u64[sigma]             wavelet matrix only (level ignored): first position of every
+ *                                             code's run in the order below the last level (the elements
+ *                                             sorted stably by their codes read bit-reversed)
+ * A wavelet matrix has no node parts (WT_PART_NODE_START / WT_PART_NODE_R0 give WT_ERR_ARG).
  */
 enum {
   WT_PART_BITS = 0,
@@ -165,7 +181,8 @@ enum {
   WT_PART_NODE_START = 5,
   WT_PART_NODE_R0 = 6,
   WT_PART_CUM_HIST = 7,
-  WT_PART_ALPHABET = 8
+  WT_PART_ALPHABET = 8,
+  WT_PART_WM_STARTS = 9
 };
 
 /* Copy one part to host memory h_dst of cap bytes; *needed receives the byte size of the part

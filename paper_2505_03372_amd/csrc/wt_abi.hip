@@ -112,6 +112,7 @@ extern "C" wt_status wt_info(const wt_tree* t, wt_info_t* out) {
   out->bytes_nodes = t->bytes_nodes + t->bytes_cum;
   out->bytes_total = t->block_bytes;
   out->alphabet_extracted = t->amap ? 1u : 0u;
+  out->matrix = t->matrix;
   out->max_symbol = t->amap ? t->max_symbol : (t->sigma ? t->sigma - 1 : 0);
   return WT_OK;
 }
@@ -132,6 +133,18 @@ extern "C" wt_status wt_export(const wt_tree* t, int level, int part, void* h_ds
     }
     return WT_OK;
   }
+  if (part == WT_PART_WM_STARTS) {
+    if (!t->matrix) return fail(WT_ERR_ARG, "wt_export: WT_PART_WM_STARTS needs a wavelet matrix");
+    const size_t bytes = (size_t)t->sigma * 8;
+    if (needed) *needed = bytes;
+    if (!h_dst) return WT_OK;
+    if (cap < bytes) return fail(WT_ERR_ARG, "wt_export: capacity %zu < %zu bytes", cap, bytes);
+    WT_HIP(hipDeviceSynchronize());
+    WT_HIP(hipMemcpy(h_dst, t->dev.wstart, bytes, hipMemcpyDeviceToHost));
+    return WT_OK;
+  }
+  if (t->matrix && (part == WT_PART_NODE_START || part == WT_PART_NODE_R0))
+    return fail(WT_ERR_ARG, "wt_export: a wavelet matrix has no node table");
   if (part != WT_PART_CUM_HIST && (level < 0 || (uint32_t)level >= t->L))
     return fail(WT_ERR_ARG, "wt_export: level %d out of range [0, %u)", level, t->L);
   const LevelMeta m = part == WT_PART_CUM_HIST ? LevelMeta{} : t->hmeta[level];

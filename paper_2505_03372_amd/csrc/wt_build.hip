@@ -126,6 +126,66 @@ __global__ __launch_bounds__(kBT) void k_tile_scan(LevelMeta* __restrict__ meta,
 
 
 
+// ---------------------------------------------------------------- wavelet matrix
+
+// Bit-reversal of the low L bits of x (L >= 1).
+__device__ __forceinline__ uint32_t rev_low(uint32_t x, uint32_t L) { return __brev(x) >> (32u - L); }
+
+// Ones of every level of a wavelet matrix from the cumulative histogram: level l holds every element,
+// and its bit is bit k = L-1-l of the symbol, set on the ranges [(2j+1) 2^k, (2j+2) 2^k) of symbols.
+// Grid (blocks, L): each block adds its share of the ranges of level blockIdx.y.
+__global__ __launch_bounds__(kBT) void k_wm_ones(const uint64_t* __restrict__ cum, uint32_t sigma, uint32_t L,
+                                                 uint64_t* __restrict__ ones) {
+  __shared__ uint64_t s_w[kBT / 64];
+  const uint32_t l = blockIdx.y, k = L - 1 - l;
+  const uint64_t step = 1ull << k;
+  const uint64_t nr = sigma > step ? ((uint64_t)sigma - step + 2 * step - 1) >> (k + 1) : 0ull;
+  uint64_t sum = 0;
+  for (uint64_t j = (uint64_t)blockIdx.x * kBT + threadIdx.x; j < nr; j += (uint64_t)gridDim.x * kBT) {
+    const uint64_t a = (2 * j + 1) << k, b = min<uint64_t>((2 * j + 2) << k, sigma);
+    sum += cum[b] - cum[a];
+  }
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) sum += __shfl_xor(sum, off, 64);
+  if ((threadIdx.x & 63u) == 0) s_w[threadIdx.x >> 6] = sum;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    uint64_t t = 0;
+    for (uint32_t w = 0; w < kBT / 64; ++w) t += s_w[w];
+    if (t) atomic_add_u64(ones + l, t);
+  }
+}
+
+// Node table of the level passes (one node per level: zeros to [0, Z_l), ones from Z_l) and the level
+// sizes (every level holds all n elements).
+__global__ void k_wm_final(uint64_t n, uint32_t L, const uint64_t* __restrict__ ones, NodeB* __restrict__ ntb,
+                           LevelMeta* __restrict__ meta) {
+  const uint32_t l = threadIdx.x;
+  if (l >= L) return;
+  NodeB b;
+  b.start = 0;
+  b.end = n;
+  b.off0 = 0;
+  b.off1 = n - ones[l];
+  ntb[l] = b;
+  meta[l].n = n;
+}
+
+// rc[rev_L(c)] = count of c (0 for the reversed codes of no symbol), for the 2^L codes.
+__global__ __launch_bounds__(kBT) void k_wm_rcount(const uint64_t* __restrict__ hist, uint32_t sigma, uint32_t L,
+                                                   uint64_t* __restrict__ rc) {
+  const uint64_t nc = 1ull << L;
+  for (uint64_t c = (uint64_t)blockIdx.x * kBT + threadIdx.x; c < nc; c += (uint64_t)gridDim.x * kBT)
+    rc[rev_low((uint32_t)c, L)] = c < sigma ? hist[c] : 0ull;
+}
+
+// start[c] = elements whose reversed code is below rev_L(c) (exclusive scan rs of rc).
+__global__ __launch_bounds__(kBT) void k_wm_starts(const uint64_t* __restrict__ rs, uint32_t sigma, uint32_t L,
+                                                   uint64_t* __restrict__ wstart) {
+  for (uint64_t c = (uint64_t)blockIdx.x * kBT + threadIdx.x; c < sigma; c += (uint64_t)gridDim.x * kBT)
+    wstart[c] = rs[rev_low((uint32_t)c, L)];
+}
+
 // ---------------------------------------------------------------- host orchestration
 
 namespace {
@@ -232,7 +292,8 @@ hipError_t launch_level(const LevelArgs& a, uint64_t n, hipStream_t st) {
 
 }  // namespace
 
-TreePlan plan_tree(uint64_t n, uint32_t w, uint64_t sigma, uint32_t L, uint32_t l2_bits, uint32_t srate) {
+TreePlan plan_tree(uint64_t n, uint32_t w, uint64_t sigma, uint32_t L, uint32_t l2_bits, uint32_t srate,
+                   bool matrix) {
   TreePlan p{};
   p.n = n;
   p.sigma = sigma;
@@ -258,7 +319,8 @@ TreePlan plan_tree(uint64_t n, uint32_t w, uint64_t sigma, uint32_t L, uint32_t 
   };
   p.off_meta = take(sizeof(LevelMeta) * WT_MAX_LEVELS);
   p.off_cum = take((sigma + 1) * sizeof(uint64_t));
-  p.off_nodes = take(std::max<uint64_t>(p.nheap, 1) * sizeof(NodeQ));
+  p.off_nodes = take(matrix ? sizeof(NodeQ) : std::max<uint64_t>(p.nheap, 1) * sizeof(NodeQ));
+  p.off_wstart = take(matrix ? std::max<uint64_t>(sigma, 1) * sizeof(uint64_t) : 0);
   p.off_bits = take((size_t)L * p.words_per_level * sizeof(uint64_t));
   p.off_l1 = take((size_t)L * p.l1_per_level * sizeof(uint64_t));
   p.off_l2 = take((size_t)L * p.l2_per_level * sizeof(uint16_t));
@@ -312,8 +374,10 @@ wt_status wt::build_tree(const void* d_sym, uint64_t n, uint32_t sym_bytes, uint
 
   uint32_t L = 0;
   while ((1ull << L) < sigma) ++L;
-  const uint32_t pow2 = (sigma & (sigma - 1)) == 0;
-  const TreePlan P = plan_tree(n, sym_bytes, sigma, L, l2_bits, srate);
+  const bool matrix = (flags & WT_BUILD_MATRIX) != 0;
+  // a wavelet matrix uses the plain L-bit symbols as codes, whatever sigma
+  const uint32_t pow2 = matrix || (sigma & (sigma - 1)) == 0;
+  const TreePlan P = plan_tree(n, sym_bytes, sigma, L, l2_bits, srate, matrix);
 
   wt_tree* t = new wt_tree();
   t->n = n;
@@ -323,6 +387,7 @@ wt_status wt::build_tree(const void* d_sym, uint64_t n, uint32_t sym_bytes, uint
   t->l2_bits = l2_bits;
   t->srate = srate;
   t->pow2 = pow2;
+  t->matrix = matrix ? 1u : 0u;
   t->device = dev;
   t->block_bytes = P.total;
   t->block = dev_alloc(P.total, st);
@@ -338,11 +403,12 @@ wt_status wt::build_tree(const void* d_sym, uint64_t n, uint32_t sym_bytes, uint
   t->dev.L1 = (uint64_t*)(base + P.off_l1);
   t->dev.L2 = (uint16_t*)(base + P.off_l2);
   t->dev.smp = (uint64_t*)(base + P.off_smp);
+  t->dev.wstart = matrix ? (uint64_t*)(base + P.off_wstart) : nullptr;
   t->bytes_bits = (size_t)L * P.words_per_level * 8;
   t->bytes_l1 = (size_t)L * P.l1_per_level * 8;
   t->bytes_l2 = (size_t)L * P.l2_per_level * 2;
   t->bytes_smp = (size_t)L * P.smp_per_level * 8;
-  t->bytes_nodes = (size_t)std::max<uint64_t>(P.nheap, 1) * sizeof(NodeQ);
+  t->bytes_nodes = matrix ? std::max<uint64_t>(sigma, 1) * 8 : (size_t)std::max<uint64_t>(P.nheap, 1) * sizeof(NodeQ);
   t->bytes_cum = (sigma + 1) * 8;
 
   auto bail = [&](wt_status s) {
@@ -370,9 +436,11 @@ wt_status wt::build_tree(const void* d_sym, uint64_t n, uint32_t sym_bytes, uint
   const uint64_t cstride = (ntiles + 1) + (nchunks + 1);  // per level: tile counts, then chunk counts
   const size_t o_cnt = take((size_t)std::max<uint32_t>(L, 1) * cstride * 8);
   const size_t o_pre = take((size_t)std::max<uint32_t>(L, 1) * (ntiles + 1) * 8);
-  const size_t o_ntb = take(std::max<uint64_t>(P.nheap, 1) * sizeof(NodeB));
+  // the matrix: one build node per level; z / zs hold the counts by reversed code and their scan
+  const size_t o_ntb = take(std::max<uint64_t>(matrix ? L : P.nheap, 1) * sizeof(NodeB));
   const size_t o_z = take((P.nheap + 1) * 8);
   const size_t o_zs = take((P.nheap + 1) * 8);
+  const size_t o_wones = take(WT_MAX_LEVELS * 8);
   const uint64_t gcnt_n = hist_gcnt_entries(n, sym_bytes, sigma);
   const size_t o_part = take(std::max<uint64_t>(part_n, ceil_div(gcnt_n, kScanChunk) + 1) * 8);
   const size_t o_gcnt = take(gcnt_n * 8);
@@ -392,6 +460,7 @@ wt_status wt::build_tree(const void* d_sym, uint64_t n, uint32_t sym_bytes, uint
   uint64_t* zs = (uint64_t*)(sb + o_zs);
   uint64_t* part = (uint64_t*)(sb + o_part);
   uint32_t* err = (uint32_t*)(sb + o_err);
+  uint64_t* wones = (uint64_t*)(sb + o_wones);
 
   Prof prof;
   prof.on = (flags & WT_BUILD_PROFILE) != 0;
@@ -424,6 +493,7 @@ wt_status wt::build_tree(const void* d_sym, uint64_t n, uint32_t sym_bytes, uint
   hipLaunchKernelGGL(k_fill_u64, dim3(256), dim3(kBT), 0, st, tcnt, (uint64_t)std::max<uint32_t>(L, 1) * cstride,
                      0ull);
   hipLaunchKernelGGL(k_fill_u64, dim3(1), dim3(64), 0, st, (uint64_t*)err, 8ull, 0ull);
+  if (matrix) hipLaunchKernelGGL(k_fill_u64, dim3(1), dim3(64), 0, st, wones, (uint64_t)WT_MAX_LEVELS, 0ull);
   WT_STEP(hipGetLastError());
   WT_STEP(prof.end());
 
@@ -438,7 +508,27 @@ wt_status wt::build_tree(const void* d_sym, uint64_t n, uint32_t sym_bytes, uint
   WT_STEP(exclusive_scan_u64(hist, hist_n, t->dev.cum, part, st));
   WT_STEP(prof.end());
 
-  if (L > 0) {
+  if (matrix) {
+    // level sizes, the one node of every level, and every symbol's start below the last level
+    WT_STEP(prof.begin("nodes", -1));
+    if (L > 0) {
+      const uint32_t nbo = (uint32_t)std::min<uint64_t>(ceil_div(sigma, 2ull * kBT * 8), 256);
+      hipLaunchKernelGGL(k_wm_ones, dim3(std::max(nbo, 1u), L), dim3(kBT), 0, st, (const uint64_t*)t->dev.cum,
+                         (uint32_t)sigma, L, wones);
+      hipLaunchKernelGGL(k_wm_final, dim3(1), dim3(64), 0, st, n, L, (const uint64_t*)wones, ntb, t->dev.meta);
+      const uint64_t nc = 1ull << L;
+      const uint32_t nbc = (uint32_t)std::min<uint64_t>(ceil_div(nc, kBT), 4096);
+      hipLaunchKernelGGL(k_wm_rcount, dim3(nbc), dim3(kBT), 0, st, (const uint64_t*)hist, (uint32_t)sigma, L, z);
+      WT_STEP(hipGetLastError());
+      WT_STEP(exclusive_scan_u64(z, nc, zs, part, st));
+      hipLaunchKernelGGL(k_wm_starts, dim3(nbc), dim3(kBT), 0, st, (const uint64_t*)zs, (uint32_t)sigma, L,
+                         t->dev.wstart);
+    } else {
+      hipLaunchKernelGGL(k_fill_u64, dim3(1), dim3(64), 0, st, t->dev.wstart, 1ull, 0ull);
+    }
+    WT_STEP(hipGetLastError());
+    WT_STEP(prof.end());
+  } else if (L > 0) {
     WT_STEP(prof.begin("nodes", -1));
     const uint32_t nb = (uint32_t)ceil_div(P.nheap, kBT);
     hipLaunchKernelGGL(k_node_walk, dim3(nb), dim3(kBT), 0, st, (uint32_t)sigma, P.nheap,
@@ -479,7 +569,7 @@ wt_status wt::build_tree(const void* d_sym, uint64_t n, uint32_t sym_bytes, uint
     a.meta = t->dev.meta;
     a.pre = pre_l;
     a.cnt_next = (l + 1 < L) ? tcnt + (size_t)(l + 1) * cstride : nullptr;
-    a.ntb = ntb + ((1ull << l) - 1);
+    a.ntb = matrix ? ntb + l : ntb + ((1ull << l) - 1);
     a.l = l;
     a.L = L;
     a.sigma = (uint32_t)sigma;
@@ -489,6 +579,7 @@ wt_status wt::build_tree(const void* d_sym, uint64_t n, uint32_t sym_bytes, uint
     a.encode = (l == 0 && !pow2) ? 1u : 0u;
     a.in_vec = (l == 0) ? 0u : 1u;
     a.in_aligned = (l == 0) ? (((uintptr_t)d_sym & 15u) == 0) : 1u;
+    a.matrix = matrix ? 1u : 0u;
     WT_STEP(prof.begin("level", (int)l));
     if (sym_bytes == 1) WT_STEP(launch_level<uint8_t>(a, n, st));
     else if (sym_bytes == 2) WT_STEP(launch_level<uint16_t>(a, n, st));

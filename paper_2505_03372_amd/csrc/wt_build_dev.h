@@ -829,6 +829,7 @@ struct LevelArgs {
   uint32_t encode;      // level 0 of a reduced alphabet: turn symbols into codes
   uint32_t in_vec;      // the input may be read with 16-byte vectors everywhere (padded and aligned)
   uint32_t in_aligned;  // the input base is 16-byte aligned (vectors only inside the sequence)
+  uint32_t matrix;      // wavelet matrix: the whole level is one node (ntb[0]: zeros then ones)
 };
 
 // The level pass's view of LevelArgs, with its pointers in the global address space.
@@ -845,7 +846,7 @@ struct LevelArgsG {
   const WT_GLOBAL NodeB* ntb;
   uint32_t l, L, sigma, pow2;
   uint32_t l2shift, sshift;
-  uint32_t encode, in_vec, in_aligned;
+  uint32_t encode, in_vec, in_aligned, matrix;
 };
 
 __device__ __forceinline__ LevelArgsG to_global(const LevelArgs& a) {
@@ -869,6 +870,7 @@ __device__ __forceinline__ LevelArgsG to_global(const LevelArgs& a) {
   g.encode = a.encode;
   g.in_vec = a.in_vec;
   g.in_aligned = a.in_aligned;
+  g.matrix = a.matrix;
   return g;
 }
 
@@ -1038,6 +1040,7 @@ __device__ __forceinline__ LevelArgs forest_level_args(const TreeB& b, uint32_t 
   a.encode = (l == 0 && !b.pow2) ? 1u : 0u;
   a.in_vec = l == 0 ? 0u : 1u;
   a.in_aligned = l == 0 ? b.aligned : 1u;
+  a.matrix = 0;
   return a;
 }
 
@@ -1140,9 +1143,10 @@ __global__ __launch_bounds__(kBT, (level_waves<E, kForest>())) void k_level(Leve
     if (q0 < cnt && q0 + EV > cnt - 1) {
       const uint32_t cx = elem128<E>(((uint64_t)vx[k].y << 32) | vx[k].x, ((uint64_t)vx[k].w << 32) | vx[k].z,
                                      cnt - 1 - q0);
-      s_node[1] = l ? ((uint64_t)cx >> (L - l)) & ((1ull << l) - 1ull) : 0ull;
+      s_node[1] = (l && !a.matrix) ? ((uint64_t)cx >> (L - l)) & ((1ull << l) - 1ull) : 0ull;
     }
-    if (q0 == 0) s_node[0] = l ? ((uint64_t)vec_elem<E>(vx[k], 0) >> (L - l)) & ((1ull << l) - 1ull) : 0ull;
+    if (q0 == 0)
+      s_node[0] = (l && !a.matrix) ? ((uint64_t)vec_elem<E>(vx[k], 0) >> (L - l)) & ((1ull << l) - 1ull) : 0ull;
   }
   if (tid < 4) s_nc[tid] = 0;
   __syncthreads();

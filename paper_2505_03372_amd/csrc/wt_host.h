@@ -11,6 +11,7 @@
 struct wt_tree {
   uint64_t n = 0, sigma = 0;
   uint32_t L = 0, w = 0, l2_bits = 512, srate = 4096, pow2 = 1;
+  uint32_t matrix = 0;  // 1: wavelet matrix (no node table; dev.wstart holds the symbols' bottom starts)
   int device = 0;
   void* block = nullptr;  // one allocation holding every device part of the tree
   bool borrowed = false;  // the parts live in a forest's allocation (freed with the forest)
@@ -71,13 +72,15 @@ struct TreePlan {
   uint64_t words_per_level;  // bit words per level (padded to whole tiles + one L2 block, 128 B aligned)
   uint64_t l1_per_level, l2_per_level, smp_per_level;
   uint64_t nheap;  // node table entries: 2^L - 1
-  size_t off_meta, off_cum, off_nodes, off_bits, off_l1, off_l2, off_smp, total;
+  size_t off_meta, off_cum, off_nodes, off_bits, off_l1, off_l2, off_smp, off_wstart, total;
 };
 
 // Bytes of one training record of the learned index (the query forms follow the records).
 size_t learn_model_bytes();
 
-TreePlan plan_tree(uint64_t n, uint32_t w, uint64_t sigma, uint32_t L, uint32_t l2_bits, uint32_t srate);
+// matrix: the parts of a wavelet matrix (no node table; sigma bottom starts instead).
+TreePlan plan_tree(uint64_t n, uint32_t w, uint64_t sigma, uint32_t L, uint32_t l2_bits, uint32_t srate,
+                   bool matrix = false);
 
 // Bytes of the level sequence one level-kernel block handles; a tile holds kTileBytes / w elements.
 constexpr uint32_t kTileBytes = 16384;

@@ -53,6 +53,7 @@ struct TreeDev {
   NodeQ* nodes;
   uint64_t* cum;  // sigma + 1
   LevelMeta* meta;
+  uint64_t* wstart;  // wavelet matrix: first position of every symbol's run below the last level; tree: NULL
 };
 
 // ---- small device helpers ----

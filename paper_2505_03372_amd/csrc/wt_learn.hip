@@ -452,6 +452,7 @@ size_t learn_model_bytes() { return sizeof(LearnModel); }
 extern "C" wt_status wt_learn_select(wt_tree* t, const wt_learn_opts* opts, wt_stream_t stream) {
   clear_error();
   if (!t) return fail(WT_ERR_ARG, "wt_learn_select: tree is NULL");
+  if (t->matrix) return fail(WT_ERR_ARG, "wt_learn_select: the learned index needs the tree's node table (not a wavelet matrix)");
   uint32_t epochs = 500, pmax = kPMax;
   float lr = 3e-3f;
   if (opts) {

@@ -26,7 +26,7 @@ namespace wt {
 
 // sq: NULL, or the queries in binned order: slot j runs query sq[j].id with the arguments stored in sq[j] (its
 // answer written at that index).
-template <int L2S, uint32_t QB>
+template <int L2S, uint32_t QB, bool WM = false>
 __global__ __launch_bounds__(QB, 8) void k_access(QArgs a, const uint64_t* __restrict__ pos, uint64_t q,
                                                 uint32_t* __restrict__ out, const SQ* __restrict__ sq,
                                                 uint32_t subshift) {
@@ -38,15 +38,15 @@ __global__ __launch_bounds__(QB, 8) void k_access(QArgs a, const uint64_t* __res
       uint32_t jj, c;
       uint64_t x;
       if (local_order<0, QB>(a, sq, q, j0 + threadIdx.x, subshift, s_ord, jj, c, x))
-        out[jj] = access_one<L2S>(a, s_meta, x);
+        out[jj] = WM ? wm_access_one<L2S>(a, s_meta, x) : access_one<L2S>(a, s_meta, x);
     }
     return;
   }
   for (uint64_t j = xcd_block() * QB + threadIdx.x; j < q; j += (uint64_t)gridDim.x * QB)
-    out[j] = access_one<L2S>(a, s_meta, pos[j]);
+    out[j] = WM ? wm_access_one<L2S>(a, s_meta, pos[j]) : access_one<L2S>(a, s_meta, pos[j]);
 }
 
-template <int L2S, uint32_t QB>
+template <int L2S, uint32_t QB, bool WM = false>
 __global__ __launch_bounds__(QB, 8) void k_rank(QArgs a, const uint32_t* __restrict__ sym,
                                               const uint64_t* __restrict__ pos, uint64_t q,
                                               uint64_t* __restrict__ out, const SQ* __restrict__ sq,
@@ -59,15 +59,15 @@ __global__ __launch_bounds__(QB, 8) void k_rank(QArgs a, const uint32_t* __restr
       uint32_t jj, c;
       uint64_t x;
       if (local_order<1, QB>(a, sq, q, j0 + threadIdx.x, subshift, s_ord, jj, c, x))
-        out[jj] = rank_one<L2S>(a, s_meta, c, x);
+        out[jj] = WM ? wm_rank_one<L2S>(a, s_meta, c, x) : rank_one<L2S>(a, s_meta, c, x);
     }
     return;
   }
   for (uint64_t j = xcd_block() * QB + threadIdx.x; j < q; j += (uint64_t)gridDim.x * QB)
-    out[j] = rank_one<L2S>(a, s_meta, sym[j], pos[j]);
+    out[j] = WM ? wm_rank_one<L2S>(a, s_meta, sym[j], pos[j]) : rank_one<L2S>(a, s_meta, sym[j], pos[j]);
 }
 
-template <int L2S, uint32_t QB>
+template <int L2S, uint32_t QB, bool WM = false>
 __global__ __launch_bounds__(QB, 8) void k_select(QArgs a, const uint32_t* __restrict__ sym,
                                                 const uint64_t* __restrict__ kin, uint64_t q,
                                                 uint64_t* __restrict__ out, const SQ* __restrict__ sq,
@@ -80,12 +80,12 @@ __global__ __launch_bounds__(QB, 8) void k_select(QArgs a, const uint32_t* __res
       uint32_t jj, c;
       uint64_t x;
       if (local_order<2, QB>(a, sq, q, j0 + threadIdx.x, subshift, s_ord, jj, c, x))
-        out[jj] = select_one<L2S>(a, s_meta, c, x);
+        out[jj] = WM ? wm_select_one<L2S>(a, s_meta, c, x) : select_one<L2S>(a, s_meta, c, x);
     }
     return;
   }
   for (uint64_t j = xcd_block() * QB + threadIdx.x; j < q; j += (uint64_t)gridDim.x * QB)
-    out[j] = select_one<L2S>(a, s_meta, sym[j], kin[j]);
+    out[j] = WM ? wm_select_one<L2S>(a, s_meta, sym[j], kin[j]) : select_one<L2S>(a, s_meta, sym[j], kin[j]);
 }
 
 // ---------------------------------------------------------------- per-kernel timing
@@ -380,11 +380,13 @@ extern "C" wt_status wt_access(const wt_tree* t, const uint64_t* d_pos, uint64_t
   qprof_begin("access", st);
   if (binned) {
     const uint32_t grid = query_grid(q, kQB);
-    WT_DISPATCH_L2(t->l2_bits, kQB, k_access, a, d_pos, q, d_out, (const SQ*)sb.sq, sb.subshift);
+    if (t->matrix) { WT_DISPATCH_L2_WM(t->l2_bits, kQB, true, k_access, a, d_pos, q, d_out, (const SQ*)sb.sq, sb.subshift); }
+    else { WT_DISPATCH_L2(t->l2_bits, kQB, k_access, a, d_pos, q, d_out, (const SQ*)sb.sq, sb.subshift); }
     dev_free(sb.block, st);
   } else {
     const uint32_t grid = query_grid(q, kQT);
-    WT_DISPATCH_L2(t->l2_bits, kQT, k_access, a, d_pos, q, d_out, (const SQ*)nullptr, 0u);
+    if (t->matrix) { WT_DISPATCH_L2_WM(t->l2_bits, kQT, true, k_access, a, d_pos, q, d_out, (const SQ*)nullptr, 0u); }
+    else { WT_DISPATCH_L2(t->l2_bits, kQT, k_access, a, d_pos, q, d_out, (const SQ*)nullptr, 0u); }
   }
   qprof_end(st);
   WT_HIP(hipGetLastError());
@@ -413,11 +415,13 @@ extern "C" wt_status wt_rank(const wt_tree* t, const uint32_t* d_sym, const uint
   qprof_begin("rank", st);
   if (binned) {
     const uint32_t grid = query_grid(q, kQB);
-    WT_DISPATCH_L2(t->l2_bits, kQB, k_rank, a, sym, d_pos, q, d_out, (const SQ*)sb.sq, sb.subshift);
+    if (t->matrix) { WT_DISPATCH_L2_WM(t->l2_bits, kQB, true, k_rank, a, sym, d_pos, q, d_out, (const SQ*)sb.sq, sb.subshift); }
+    else { WT_DISPATCH_L2(t->l2_bits, kQB, k_rank, a, sym, d_pos, q, d_out, (const SQ*)sb.sq, sb.subshift); }
     dev_free(sb.block, st);
   } else {
     const uint32_t grid = query_grid(q, kQT);
-    WT_DISPATCH_L2(t->l2_bits, kQT, k_rank, a, sym, d_pos, q, d_out, (const SQ*)nullptr, 0u);
+    if (t->matrix) { WT_DISPATCH_L2_WM(t->l2_bits, kQT, true, k_rank, a, sym, d_pos, q, d_out, (const SQ*)nullptr, 0u); }
+    else { WT_DISPATCH_L2(t->l2_bits, kQT, k_rank, a, sym, d_pos, q, d_out, (const SQ*)nullptr, 0u); }
   }
   qprof_end(st);
   if (mapped) dev_free(mapped, st);
@@ -447,11 +451,13 @@ extern "C" wt_status wt_select(const wt_tree* t, const uint32_t* d_sym, const ui
   qprof_begin("select", st);
   if (binned) {
     const uint32_t grid = query_grid(q, kQB);
-    WT_DISPATCH_L2(t->l2_bits, kQB, k_select, a, sym, d_k, q, d_out, (const SQ*)sb.sq, sb.subshift);
+    if (t->matrix) { WT_DISPATCH_L2_WM(t->l2_bits, kQB, true, k_select, a, sym, d_k, q, d_out, (const SQ*)sb.sq, sb.subshift); }
+    else { WT_DISPATCH_L2(t->l2_bits, kQB, k_select, a, sym, d_k, q, d_out, (const SQ*)sb.sq, sb.subshift); }
     dev_free(sb.block, st);
   } else {
     const uint32_t grid = query_grid(q, kQT);
-    WT_DISPATCH_L2(t->l2_bits, kQT, k_select, a, sym, d_k, q, d_out, (const SQ*)nullptr, 0u);
+    if (t->matrix) { WT_DISPATCH_L2_WM(t->l2_bits, kQT, true, k_select, a, sym, d_k, q, d_out, (const SQ*)nullptr, 0u); }
+    else { WT_DISPATCH_L2(t->l2_bits, kQT, k_select, a, sym, d_k, q, d_out, (const SQ*)nullptr, 0u); }
   }
   qprof_end(st);
   if (mapped) dev_free(mapped, st);
@@ -525,10 +531,12 @@ extern "C" wt_status wt_select_noalloc(const wt_tree* t, const uint32_t* d_sym, 
   if (rc != WT_OK) return rc;
   if (binned) {
     const uint32_t grid = query_grid(q, kQB);
-    WT_DISPATCH_L2(t->l2_bits, kQB, k_select, a, sym, d_k, q, d_out, (const SQ*)sb.sq, sb.subshift);
+    if (t->matrix) { WT_DISPATCH_L2_WM(t->l2_bits, kQB, true, k_select, a, sym, d_k, q, d_out, (const SQ*)sb.sq, sb.subshift); }
+    else { WT_DISPATCH_L2(t->l2_bits, kQB, k_select, a, sym, d_k, q, d_out, (const SQ*)sb.sq, sb.subshift); }
   } else {
     const uint32_t grid = query_grid(q, kQT);
-    WT_DISPATCH_L2(t->l2_bits, kQT, k_select, a, sym, d_k, q, d_out, (const SQ*)nullptr, 0u);
+    if (t->matrix) { WT_DISPATCH_L2_WM(t->l2_bits, kQT, true, k_select, a, sym, d_k, q, d_out, (const SQ*)nullptr, 0u); }
+    else { WT_DISPATCH_L2(t->l2_bits, kQT, k_select, a, sym, d_k, q, d_out, (const SQ*)nullptr, 0u); }
   }
   WT_HIP(hipGetLastError());
   return WT_OK;

@@ -311,6 +311,61 @@ __device__ __forceinline__ uint64_t select_one(const QArgs& a, const LevelMeta* 
   return r - 1;
 }
 
+// ---- wavelet matrix: every level holds all n elements; an element at position p of level l with bit b
+// is at rank0_l(p) (b = 0) or zeros_l + rank1_l(p) (b = 1) in level l + 1, and its bit at level l is
+// bit L-1-l of its symbol. One binary rank or select per level, no node table.
+
+// access: the bits read top-down spell the symbol.
+template <int L2S>
+__device__ __forceinline__ uint32_t wm_access_one(const QArgs& a, const LevelMeta* meta, uint64_t i) {
+  if (i >= a.n) return 0xFFFFFFFFu;
+  uint32_t c = 0;
+  uint64_t p = i;
+  for (uint32_t l = 0; l < a.L; ++l) {
+    const LevelMeta& m = meta[l];
+    uint32_t bit;
+    const uint64_t r1 = rank1_at<L2S>(a.d, m, p, bit);
+    c = (c << 1) | bit;
+    p = bit ? (m.n - m.ones) + r1 : p - r1;
+  }
+  return c;
+}
+
+// rank: follow position i down the symbol's bits; below the last level the occurrences of c before i
+// end just before the followed position, and c's run starts at wstart[c].
+template <int L2S>
+__device__ __forceinline__ uint64_t wm_rank_one(const QArgs& a, const LevelMeta* meta, uint32_t c, uint64_t i) {
+  if (i > a.n) return ~0ull;
+  if (c >= a.sigma) return 0;
+  const uint64_t base = a.d.wstart[c];
+  uint64_t p = i;
+  for (uint32_t l = 0; l < a.L; ++l) {
+    const LevelMeta& m = meta[l];
+    const uint32_t b = (c >> (a.L - 1 - l)) & 1u;
+    uint32_t bit;
+    const uint64_t r1 = rank1_at<L2S, true>(a.d, m, p, bit);
+    p = b ? (m.n - m.ones) + r1 : p - r1;
+  }
+  return p - base;
+}
+
+// select: the k-th occurrence sits at wstart[c] + k - 1 below the last level; going up, a position p of
+// level l + 1 is the (p + 1)-th zero of level l (b = 0) or its (p - zeros_l + 1)-th one (b = 1).
+template <int L2S>
+__device__ __forceinline__ uint64_t wm_select_one(const QArgs& a, const LevelMeta* meta, uint32_t c, uint64_t k) {
+  if (k == 0) return ~0ull;
+  if (c >= a.sigma) return a.n;
+  if (k > a.d.cum[c + 1] - a.d.cum[c]) return a.n;
+  if (a.L == 0) return k - 1;
+  uint64_t p = a.d.wstart[c] + k - 1;
+  for (int l = (int)a.L - 1; l >= 0; --l) {
+    const LevelMeta& m = meta[l];
+    const uint32_t b = (c >> (a.L - 1 - l)) & 1u;
+    p = select_at<L2S>(a.d, m, b, b ? p - (m.n - m.ones) + 1 : p + 1, a.sshift);
+  }
+  return p;
+}
+
 // Logical block of a grid-stride query launch. Workgroups go to the kXcd dies (XCDs, each with its
 // own L2) round-robin, so launch block g runs on die g mod kXcd; logical block x * G/kXcd + g/kXcd
 // gives every die a contiguous 1/kXcd of each grid-wide window of the batch. With a binned batch the
@@ -322,13 +377,14 @@ __device__ __forceinline__ uint64_t xcd_block() {
   return (uint64_t)(b % kXcd) * (g / kXcd) + b / kXcd;
 }
 
-// Binning key of a query: access and rank, the position; select, the rank of the wanted occurrence
-// in symbol order (cum[c] + k - 1). Invalid queries key n.
+// Binning key of a query: access and rank, the position; select, the position of the wanted
+// occurrence below the last level: in a tree, its rank in symbol order (cum[c] + k - 1), in a wavelet
+// matrix wstart[c] + k - 1. Invalid queries key n.
 __device__ __forceinline__ uint64_t sort_key(const QArgs& a, int kind, uint32_t c, uint64_t x) {
   if (kind != 2) return min(x, a.n);
   if (x == 0 || c >= a.sigma) return a.n;
   const uint64_t lo = a.d.cum[c], cnt = a.d.cum[c + 1] - lo;
-  return x > cnt ? a.n : lo + x - 1;
+  return x > cnt ? a.n : (a.d.wstart ? a.d.wstart[c] : lo) + x - 1;
 }
 
 // Threads per block of the access / rank / select traversal kernels: binned batches use kQB (the
@@ -452,6 +508,15 @@ constexpr uint32_t kSortIdBins = 32768;
 inline uint32_t query_grid(uint64_t q, uint32_t qb) {
   return (uint32_t)round_up(std::min<uint64_t>(ceil_div(q, qb), 4096 * kQT / qb), kXcd);
 }
+
+// Launch of KERNEL<L2S, QB, WM> for the tree's |L2| (WM: the wavelet-matrix traversal).
+#define WT_DISPATCH_L2_WM(bits, QB, WM, KERNEL, ...)                                                              \
+  switch (bits) {                                                                                                 \
+    case 256: hipLaunchKernelGGL((KERNEL<8, QB, WM>), dim3(grid), dim3(QB), 0, st, __VA_ARGS__); break;          \
+    case 512: hipLaunchKernelGGL((KERNEL<9, QB, WM>), dim3(grid), dim3(QB), 0, st, __VA_ARGS__); break;          \
+    case 1024: hipLaunchKernelGGL((KERNEL<10, QB, WM>), dim3(grid), dim3(QB), 0, st, __VA_ARGS__); break;        \
+    default: hipLaunchKernelGGL((KERNEL<11, QB, WM>), dim3(grid), dim3(QB), 0, st, __VA_ARGS__); break;          \
+  }
 
 #define WT_DISPATCH_L2(bits, QB, KERNEL, ...)                                                          \
   switch (bits) {                                                                                     \
