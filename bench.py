@@ -27,7 +27,9 @@ in [1, 2^20] (70 % select, 20 % rank, 10 % access) from page-locked host memory,
 saturation and at Poisson arrivals of 0.5, 0.8 and 0.95 of the saturation rate; p50/p99 latency and
 queries/s. (Selects inside mixed batches use the plain sampled search.)
 
-The default run also measures, outside its timed steps, the large-alphabet configuration (2^28 u32
+The default run also measures, outside its timed steps, the wavelet matrix of the same sequence
+answering the same queries (key `matrix`), queries from host memory (wt_query_host, 10^5..10^7 of
+each kind, page-locked and pageable arrays; key `host_queries`), the large-alphabet configuration (2^28 u32
 symbols, sigma 2^20; key `large_alpha`) and the rank/select benchmark of plain bit arrays (2^32 bits,
 fill 10/50/90 %, uniform and adversarial placement, |L2| 512, s 16384, 10^8 queries of each of
 rank0/rank1/select0/select1; key `bitvec`).
@@ -441,6 +443,73 @@ def run_bitvec(torch, wt, workloads, dev, n_bits: int, nq: int, reps: int = 3) -
                                  "note": "64 B (one L2 block of bits) per query, random lines"}}
 
 
+def run_hostq(torch, wt, t, kinds, sizes, reps: int = 3) -> dict:
+    """Queries from host memory (wt_query_host): for every query kind and batch size, the end-to-end time
+    of the call (copies in, kernels, copies out) with page-locked and with pageable host arrays, beside
+    the device-resident call on the same queries (median of `reps` after one warm-up; the first call of a
+    page-locked configuration also builds its graph, which the warm-up absorbs)."""
+    qmax = max(sizes)
+    res = {}
+    ops = {"access": wt.OP_ACCESS, "rank": wt.OP_RANK, "select": wt.OP_SELECT}
+    stream = torch.cuda.current_stream()
+    for kind, a in kinds.items():
+        dsym, darg = (None, a[0]) if kind == "access" else (a[0], a[1])
+        qk = min(qmax, darg.numel())
+        arg_pg = darg[:qk].cpu().numpy().copy()
+        sym_pg = None if dsym is None else dsym[:qk].cpu().numpy().copy()
+        arg_pin = torch.from_numpy(arg_pg).pin_memory()
+        sym_pin = None if sym_pg is None else torch.from_numpy(sym_pg).pin_memory()
+        odt = np.uint32 if kind == "access" else np.uint64
+        out_pg = np.zeros(qk, dtype=odt)
+        out_pin = torch.zeros(qk, dtype=torch.uint32 if kind == "access" else torch.uint64).pin_memory()
+        dout = torch.empty(qk, dtype=torch.uint32 if kind == "access" else torch.uint64, device=darg.device)
+        for q in sizes:
+            if q > qk:
+                continue
+            r = {}
+            for mem in ("pinned", "pageable"):
+                if mem == "pinned":
+                    arg_h, sym_h, out_h = arg_pin[:q], None if sym_pin is None else sym_pin[:q], out_pin[:q]
+                else:
+                    arg_h, sym_h, out_h = arg_pg[:q], None if sym_pg is None else sym_pg[:q], out_pg[:q]
+                ms = []
+                for i in range(reps + 1):
+                    t0 = time.perf_counter()
+                    _, st = t.query_host(ops[kind], arg_h, sym_h, out=out_h)
+                    t1 = time.perf_counter()
+                    if i:
+                        ms.append((t1 - t0) * 1e3)
+                r[mem + "_ms"] = float(np.median(ms))
+                r[mem + "_queries_per_s"] = q / (r[mem + "_ms"] * 1e-3)
+                r[mem + "_chunks"] = st["chunks"]
+                r[mem + "_graph"] = st["graph"]
+            dms = []
+            for i in range(reps + 1):
+                e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                e0.record(stream)
+                if kind == "access":
+                    t.access(darg[:q], out=dout[:q])
+                elif kind == "rank":
+                    t.rank(dsym[:q], darg[:q], out=dout[:q])
+                else:
+                    t.select(dsym[:q], darg[:q], out=dout[:q])
+                e1.record(stream)
+                torch.cuda.synchronize()
+                if i:
+                    dms.append(e0.elapsed_time(e1))
+            r["device_resident_ms"] = float(np.median(dms))
+            r["device_resident_queries_per_s"] = q / (r["device_resident_ms"] * 1e-3)
+            r["pinned_vs_pageable_speedup"] = r["pageable_ms"] / r["pinned_ms"]
+            res["%s_q%d" % (kind, q)] = r
+            # the answers are those of the device-resident call
+            ref = dout[:q].cpu().numpy()
+            assert np.array_equal(out_pg[:q], ref) and np.array_equal(out_pin[:q].numpy(), ref), \
+                "host-sourced %s differs from the device-resident answers" % kind
+        del arg_pin, sym_pin, out_pin, dout
+    wt.lib().wt_query_host_release()
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -454,6 +523,8 @@ def main():
     ap.add_argument("--sample-rate", type=int, default=0, help="select sample rate s (0: library default)")
     ap.add_argument("--bitvec-log2", type=int, default=32, help="bits of each array of the bit-array leg")
     ap.add_argument("--bitvec-queries", type=int, default=100_000_000, help="queries per kind of the bit-array leg")
+    ap.add_argument("--hostq-max-log10", type=int, default=7,
+                    help="largest host-sourced batch of the default run, 10^k queries (5..8)")
     ap.add_argument("--cpu-sample-log2", type=int, default=25)
     ap.add_argument("--cpu-queries-log2", type=int, default=20)
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -488,7 +559,9 @@ def main():
               flush=True)
         return
     res = run_tree(args, torch, wt, workloads, dev, args.workload, args.steps, args.warmup,
-                   learned=not args.no_learned, kinds_wanted=("access", "rank", "select"))
+                   learned=not args.no_learned, kinds_wanted=("access", "rank", "select"),
+                   matrix_steps=0 if args.no_extra else 3,
+                   hostq_sizes=() if args.no_extra else tuple(10 ** e for e in range(5, args.hostq_max_log10 + 1)))
     n, width, sigma, q = res["n"], res["width"], res["sigma"], res["q"]
     ms_per_step = res["ms_per_step"]
     line = {
@@ -512,6 +585,10 @@ def main():
         "roofline_build": res["roofline_build"],
         "roofline_build_total": res["roofline_build_total"],
     }
+    if res["matrix"] is not None:
+        line["matrix"] = res["matrix"]
+    if res["hostq"] is not None:
+        line["host_queries"] = res["hostq"]
     if args.workload == "text_zipf" and not args.no_extra:
         # the large-alphabet configuration (2^28 u32 symbols, sigma 2^20, 2^24 rank + 2^24 select), measured
         # in the same run after the main workload, outside its timed steps
@@ -542,7 +619,8 @@ def main():
     print(json.dumps(line), flush=True)
 
 
-def run_tree(args, torch, wt, workloads, dev, name, steps, warmup, learned, kinds_wanted):
+def run_tree(args, torch, wt, workloads, dev, name, steps, warmup, learned, kinds_wanted, matrix_steps=0,
+             hostq_sizes=()):
     """Timed steps of one single-tree workload: build (+ learned-index training) + queries + free."""
     idx, n, width, sigma, q = workloads.CONFIGS[name]
     print("# generating workload %s: n=%d width=%d sigma=%d q=%d" % (name, n, width, sigma, q),
@@ -568,19 +646,19 @@ def run_tree(args, torch, wt, workloads, dev, name, steps, warmup, learned, kind
     wt.query_profiling(True)
     use_learned = learned and "select" in kinds
 
-    def step(record):
+    def step(record, matrix=False):
         # the build is timed by one event pair around the whole wt_build call on its stream (it includes
         # the library's allocations, launch gaps and the final read-back of the level sizes), beside the
         # sum of the per-kernel events the library records and the host wall time of the call
         eb0, eb1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         eb0.record(stream)
         h0 = time.perf_counter()
-        t = wt.build(S, sigma, l2_bits=args.l2_bits, sample_rate=args.sample_rate, profile=True)
+        t = wt.build(S, sigma, l2_bits=args.l2_bits, sample_rate=args.sample_rate, profile=True, matrix=matrix)
         h1 = time.perf_counter()
         eb1.record(stream)
         evs = {}
         linfo = None
-        if use_learned:
+        if use_learned and not matrix:
             linfo = t.learn_select()
         for kind, a in kinds.items():
             for variant in (("plain", "learned") if kind == "select" and linfo is not None else ("plain",)):
@@ -635,6 +713,38 @@ def run_tree(args, torch, wt, workloads, dev, name, steps, warmup, learned, kind
         unbinned["learned_vs_plain_speedup"] = unbinned["plain_ms"] / unbinned["learned_ms"]
         t.free()
     ms_per_step = (t1 - t0) * 1e3 / steps
+    hostq = None
+    if hostq_sizes:
+        t = wt.build(S, sigma, l2_bits=args.l2_bits, sample_rate=args.sample_rate)
+        hostq = run_hostq(torch, wt, t, kinds, hostq_sizes)
+        t.free()
+    mat = None
+    if matrix_steps:
+        # the wavelet matrix of the same sequence answering the same queries (outside the timed steps)
+        wt.query_profiling(True)
+        step(None, matrix=True)
+        mrecs = []
+        m0 = time.perf_counter()
+        for _ in range(matrix_steps):
+            step(mrecs, matrix=True)
+        torch.cuda.synchronize()
+        m1 = time.perf_counter()
+        wt.query_profiling(False)
+        mat = {"steps": matrix_steps, "ms_per_step": (m1 - m0) * 1e3 / matrix_steps,
+               "build_ms_median": float(np.median([r[5][0].elapsed_time(r[5][1]) for r in mrecs])),
+               "build_kernel_sum_ms_median": float(np.median([sum(p["ms"] for p in r[0]) for r in mrecs]))}
+        mat["build_symbols_per_s"] = n / (mat["build_ms_median"] * 1e-3)
+        mk = {}
+        for r in mrecs:
+            for k, (e0, e1) in r[1].items():
+                mat.setdefault(k + "_ms_median", []).append(e0.elapsed_time(e1))
+            for e in r[4]:
+                mk.setdefault(e["kernel"], []).append(e["ms"])
+        for k in [k for k in mat if k.endswith("_ms_median") and isinstance(mat[k], list)]:
+            mat[k] = float(np.median(mat[k]))
+            mat[k.replace("_ms_median", "_queries_per_s")] = q / (mat[k] * 1e-3)
+        for k, v in mk.items():
+            mat["kernel_%s_ms_per_step" % k] = float(np.sum(v)) / matrix_steps
 
     info = recs[0][2]
     level_ms, build_ms, build_ev_ms, build_wall_ms, learn_ms = [], [], [], [], []
@@ -717,7 +827,7 @@ def run_tree(args, torch, wt, workloads, dev, name, steps, warmup, learned, kind
     torch.cuda.empty_cache()
     return {"n": n, "width": width, "sigma": sigma, "q": q, "kinds": list(qms.keys()), "info": info,
             "items": items, "ms_per_step": ms_per_step, "rates": rates, "roofline": roof,
-            "roofline_build": build_roof, "roofline_build_total": build_total}
+            "roofline_build": build_roof, "roofline_build_total": build_total, "matrix": mat, "hostq": hostq}
 
 
 if __name__ == "__main__":

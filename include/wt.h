@@ -408,6 +408,50 @@ enum { WT_OP_ACCESS = 0, WT_OP_RANK = 1, WT_OP_SELECT = 2, WT_OP_SELECT_LEARNED 
 wt_status wt_query_mixed(const wt_forest* f, const uint32_t* d_tree, const uint8_t* d_op, const uint32_t* d_sym,
                          const uint64_t* d_arg, uint64_t q, uint64_t* d_out, wt_stream_t stream);
 
+/* ---- queries from host memory (Section 5.2.1; Sections 6.3.2-6.3.4) ----
+ *
+ * wt_query_host answers q queries whose arguments and answers live in host memory: op is
+ * WT_OP_ACCESS (h_arg = positions, h_out = u32 answers, h_sym unused), WT_OP_RANK (h_sym, h_arg =
+ * positions, u64 answers) or WT_OP_SELECT (h_sym, h_arg = k, u64 answers), with the answers and
+ * sentinels of wt_access / wt_rank / wt_select. The batch is cut into chunks of opts->chunk queries
+ * (0: 2^22; at most 2^28); each chunk is copied to the device, answered and copied back, and a chunk's
+ * copies overlap the kernels of its neighbours, with at most two chunks (their arguments and answers) on
+ * the device at a time and one chunk's kernels running at a time.
+ *  - Page-locked host arrays (hipHostMalloc, torch pin_memory): with more than one chunk the whole
+ *    pipeline is one HIP graph (copy nodes plus each chunk's kernels), instantiated on the first call and
+ *    kept, with its chunk buffers, for calls with the same tree, op, arrays, q and chunk (one such graph
+ *    per process; wt_query_host_release drops it). WT_HOST_NO_GRAPH enqueues the chunks on streams instead.
+ *  - Pageable host arrays: every chunk goes through two page-locked staging slots that the host fills
+ *    and empties with its own threads while the device works (no host memory is pinned in place); the
+ *    staging buffers are kept for later calls until wt_query_host_release.
+ * The call waits for the answers (they are in h_out when it returns). Work starts after what is queued
+ * on `stream`. Concurrent calls are safe (serialised on the shared graph and staging). The tree must stay
+ * alive during the call. stats may be NULL.
+ * Errors: WT_ERR_ARG (NULL arrays, unknown op, chunk too large), WT_ERR_OOM, WT_ERR_HIP.
+ */
+typedef struct {
+  uint64_t chunk;   /* queries per chunk; 0 = 2^22 */
+  uint32_t flags;   /* WT_HOST_NO_GRAPH */
+  uint32_t reserved;
+} wt_host_opts;
+
+#define WT_HOST_NO_GRAPH 1u
+
+typedef struct {
+  uint32_t chunks;  /* chunks the batch was cut into */
+  uint32_t pinned;  /* 1: the arrays were page-locked (no staging) */
+  uint32_t graph;   /* 1: answered by the captured graph */
+  uint32_t reserved;
+  float ms;         /* wall time of the call (host clock), copies included */
+  uint32_t reserved2;
+} wt_host_stats;
+
+wt_status wt_query_host(const wt_tree* t, int op, const uint32_t* h_sym, const uint64_t* h_arg, uint64_t q,
+                        void* h_out, const wt_host_opts* opts, wt_host_stats* stats, wt_stream_t stream);
+
+/* Drops the cached graph (and its device chunk buffers) and the page-locked staging of wt_query_host. */
+wt_status wt_query_host_release(void);
+
 /* ---- serving (an extension): continuous batching over a resident forest ----
  *
  * A server keeps a forest resident and replays a trace of query batches (requests) on its own clock:

@@ -38,10 +38,22 @@ ABI_FUNCTIONS = ("wt_set_allocator", "wt_build", "wt_free", "wt_access", "wt_ran
                  "wt_select_learned", "wt_learned_info", "wt_learned_model", "wt_mlp_loss_grad",
                  "wt_build_forest", "wt_forest_tree", "wt_forest_info", "wt_forest_free", "wt_query_mixed",
                  "wt_autotune", "wt_server_create", "wt_server_run", "wt_server_destroy", "wt_query_profiling",
-                 "wt_query_profile", "wt_bv_build", "wt_select_noalloc")
+                 "wt_query_profile", "wt_bv_build", "wt_select_noalloc", "wt_query_host", "wt_query_host_release")
 OP_ACCESS, OP_RANK, OP_SELECT, OP_SELECT_LEARNED = 0, 1, 2, 3
 TUNE_NB, TUNE_SB = 21, 7
 MLP_PARAMS = 49
+
+
+class HostOpts(ctypes.Structure):
+    _fields_ = [("chunk", ctypes.c_uint64), ("flags", ctypes.c_uint32), ("reserved", ctypes.c_uint32)]
+
+
+class HostStats(ctypes.Structure):
+    _fields_ = [("chunks", ctypes.c_uint32), ("pinned", ctypes.c_uint32), ("graph", ctypes.c_uint32),
+                ("reserved", ctypes.c_uint32), ("ms", ctypes.c_float), ("reserved2", ctypes.c_uint32)]
+
+
+HOST_NO_GRAPH = 1
 
 
 class WTLibraryMissing(RuntimeError):
@@ -172,6 +184,11 @@ def lib():
     L.wt_select.argtypes = [vp, vp, vp, u64, vp, vp]
     L.wt_select_noalloc.restype = ctypes.c_int
     L.wt_select_noalloc.argtypes = [vp, vp, vp, u64, vp, vp]
+    L.wt_query_host.restype = ctypes.c_int
+    L.wt_query_host.argtypes = [vp, ctypes.c_int, vp, vp, u64, vp, ctypes.POINTER(HostOpts), ctypes.POINTER(HostStats),
+                                vp]
+    L.wt_query_host_release.restype = ctypes.c_int
+    L.wt_query_host_release.argtypes = []
     L.wt_info.restype = ctypes.c_int
     L.wt_info.argtypes = [vp, ctypes.POINTER(Info)]
     L.wt_export.restype = ctypes.c_int
@@ -341,6 +358,21 @@ class Tree:
                                        q, _dev_ptr(out, torch.uint64, "out"),
                                        ctypes.c_void_p(_stream_handle(stream))))
         return out
+
+    def query_host(self, op: int, arg, sym=None, out=None, chunk: int = 0, graph: bool = True, stream=None):
+        """wt_query_host: op OP_ACCESS / OP_RANK / OP_SELECT over host arrays (numpy or CPU tensors, pinned
+        or pageable); returns (answers, stats)."""
+        q = int(arg.shape[0])
+        if out is None:
+            out = np.empty(q, dtype=np.uint32 if op == OP_ACCESS else np.uint64)
+        if sym is not None and int(sym.shape[0]) != q:
+            raise ValueError("sym and arg must have the same length")
+        opts = HostOpts(chunk, 0 if graph else HOST_NO_GRAPH, 0)
+        st = HostStats()
+        _check(lib().wt_query_host(self._h, op, ctypes.c_void_p(_host_ptr(sym) if sym is not None else 0),
+                                   ctypes.c_void_p(_host_ptr(arg)), q, ctypes.c_void_p(_host_ptr(out)),
+                                   ctypes.byref(opts), ctypes.byref(st), ctypes.c_void_p(_stream_handle(stream))))
+        return out, {f: getattr(st, f) for f, _ in HostStats._fields_ if not f.startswith("reserved")}
 
     def learn_select(self, epochs: int = 0, max_points: int = 0, lr: float = 0.0, stream=None) -> dict:
         """Train the learned select index of this tree on the GPU; returns its statistics."""

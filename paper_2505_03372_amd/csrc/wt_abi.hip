@@ -1,6 +1,8 @@
 // C ABI plumbing: errors, allocator hook, tree lifetime, info, canonical export, profile.
 #include <hip/hip_runtime.h>
 
+#include <atomic>
+
 #include <algorithm>
 #include <cstdarg>
 #include <cstdio>
@@ -60,6 +62,11 @@ void dev_free(void* p, hipStream_t s) {
 }
 
 }  // namespace wt
+
+uint64_t wt::next_tree_uid() {
+  static std::atomic<uint64_t> next{1};
+  return next.fetch_add(1);
+}
 
 using namespace wt;
 

@@ -8,7 +8,13 @@
 
 #include "wt_internal.h"
 
+namespace wt {
+// A number no other tree object of the process has had (keys of cached per-tree state).
+uint64_t next_tree_uid();
+}  // namespace wt
+
 struct wt_tree {
+  uint64_t uid = wt::next_tree_uid();
   uint64_t n = 0, sigma = 0;
   uint32_t L = 0, w = 0, l2_bits = 512, srate = 4096, pow2 = 1;
   uint32_t matrix = 0;  // 1: wavelet matrix (no node table; dev.wstart holds the symbols' bottom starts)

@@ -335,16 +335,16 @@ wt_status sort_batch(const wt_tree* t, const QArgs& a, int kind, const uint32_t*
   while ((1ull << bits) < a.n + 1) ++bits;
   const uint32_t shift = bits > 15 ? bits - 15 : 0;
   sb.subshift = shift > qb_bits(kQB) ? shift - qb_bits(kQB) : 0;
-  qprof_begin("sort_count", st);
+  if (!pre) qprof_begin("sort_count", st);
   if (kind == 0) hipLaunchKernelGGL(k_bin_count<0>, dim3(nblk), dim3(kBinT), 0, st, a, sym, arg, q, shift, bhist);
   else if (kind == 1) hipLaunchKernelGGL(k_bin_count<1>, dim3(nblk), dim3(kBinT), 0, st, a, sym, arg, q, shift, bhist);
   else hipLaunchKernelGGL(k_bin_count<2>, dim3(nblk), dim3(kBinT), 0, st, a, sym, arg, q, shift, bhist);
-  qprof_end(st);
-  qprof_begin("sort_scan", st);
+  if (!pre) qprof_end(st);
+  if (!pre) qprof_begin("sort_scan", st);
   hipLaunchKernelGGL(k_bin_offsets, dim3(kBins / kQT), dim3(kQT), 0, st, bhist, nblk, tot);
   hipLaunchKernelGGL(k_bin_scan, dim3(1), dim3(1024), 0, st, tot);
-  qprof_end(st);
-  qprof_begin("sort_scatter", st);
+  if (!pre) qprof_end(st);
+  if (!pre) qprof_begin("sort_scatter", st);
   if (kind == 0)
     hipLaunchKernelGGL(k_bin_scatter<0>, dim3(nblk), dim3(kBinT), 0, st, a, sym, arg, q, shift, (const uint32_t*)bhist,
                        (const uint32_t*)tot, sb.sq);
@@ -354,11 +354,70 @@ wt_status sort_batch(const wt_tree* t, const QArgs& a, int kind, const uint32_t*
   else
     hipLaunchKernelGGL(k_bin_scatter<2>, dim3(nblk), dim3(kBinT), 0, st, a, sym, arg, q, shift, (const uint32_t*)bhist,
                        (const uint32_t*)tot, sb.sq);
-  qprof_end(st);
+  if (!pre) qprof_end(st);
   WT_HIP(hipGetLastError());
   binned = true;
   (void)t;
   return WT_OK;
+}
+
+}  // namespace wt
+
+namespace wt {
+
+// Bytes of the preallocated scratch of query_run for q queries: the binning buffers, then the symbols
+// mapped to codes (trees with an extracted alphabet).
+size_t query_scratch_bytes(uint64_t q) { return round_up(sort_batch_bytes(q), 256) + round_up(4 * q, 256); }
+
+// One batch of queries of one kind (0 access, 1 rank, 2 select) on st: symbols mapped to codes (extracted
+// alphabets), binning of large batches, the traversal kernel of the tree or matrix, access answers mapped
+// back to values. pre: NULL (buffers allocated and freed stream-ordered) or query_scratch_bytes(q) bytes
+// of device memory (nothing allocated, no profiling events).
+wt_status query_run(const wt_tree* t, int kind, const uint32_t* d_sym, const uint64_t* d_arg, uint64_t q, void* d_out,
+                    hipStream_t st, char* pre) {
+  const QArgs a = make_args(t);
+  const uint32_t* sym = d_sym;
+  void* mapped = nullptr;
+  if (kind != 0) {
+    const wt_status rc = alpha_map_syms(t, d_sym, q, st, &sym, &mapped,
+                                        pre ? (uint32_t*)(pre + round_up(sort_batch_bytes(q), 256)) : nullptr);
+    if (rc != WT_OK) return rc;
+  }
+  SortBufs sb;
+  bool binned;
+  const wt_status rc = sort_batch(t, a, kind, sym, d_arg, q, st, sb, binned, pre);
+  if (rc != WT_OK) {
+    if (mapped) dev_free(mapped, st);
+    return rc;
+  }
+  static const char* const kName[3] = {"access", "rank", "select"};
+  if (!pre) qprof_begin(kName[kind], st);
+  const SQ* sq = binned ? (const SQ*)sb.sq : nullptr;
+  const uint32_t sub = binned ? sb.subshift : 0u;
+  const uint32_t grid = query_grid(q, binned ? kQB : kQT);
+  uint32_t* o32 = (uint32_t*)d_out;
+  uint64_t* o64 = (uint64_t*)d_out;
+#define WT_RUN(QB)                                                                                          \
+  do {                                                                                                      \
+    if (kind == 0) {                                                                                        \
+      if (t->matrix) { WT_DISPATCH_L2_WM(t->l2_bits, QB, true, k_access, a, d_arg, q, o32, sq, sub); }     \
+      else { WT_DISPATCH_L2(t->l2_bits, QB, k_access, a, d_arg, q, o32, sq, sub); }                         \
+    } else if (kind == 1) {                                                                                 \
+      if (t->matrix) { WT_DISPATCH_L2_WM(t->l2_bits, QB, true, k_rank, a, sym, d_arg, q, o64, sq, sub); }  \
+      else { WT_DISPATCH_L2(t->l2_bits, QB, k_rank, a, sym, d_arg, q, o64, sq, sub); }                      \
+    } else {                                                                                                \
+      if (t->matrix) { WT_DISPATCH_L2_WM(t->l2_bits, QB, true, k_select, a, sym, d_arg, q, o64, sq, sub); } \
+      else { WT_DISPATCH_L2(t->l2_bits, QB, k_select, a, sym, d_arg, q, o64, sq, sub); }                    \
+    }                                                                                                       \
+  } while (0)
+  if (binned) WT_RUN(kQB);
+  else WT_RUN(kQT);
+#undef WT_RUN
+  if (!pre) qprof_end(st);
+  if (sb.block) dev_free(sb.block, st);
+  if (mapped) dev_free(mapped, st);
+  WT_HIP(hipGetLastError());
+  return kind == 0 ? alpha_unmap_access(t, o32, q, st) : WT_OK;
 }
 
 }  // namespace wt
@@ -371,26 +430,7 @@ extern "C" wt_status wt_access(const wt_tree* t, const uint64_t* d_pos, uint64_t
   if (!t) return fail(WT_ERR_ARG, "wt_access: tree is NULL");
   if (q == 0) return WT_OK;
   if (!d_pos || !d_out) return fail(WT_ERR_ARG, "wt_access: NULL buffer");
-  hipStream_t st = (hipStream_t)stream;
-  const QArgs a = make_args(t);
-  SortBufs sb;
-  bool binned;
-  const wt_status rc = sort_batch(t, a, 0, nullptr, d_pos, q, st, sb, binned);
-  if (rc != WT_OK) return rc;
-  qprof_begin("access", st);
-  if (binned) {
-    const uint32_t grid = query_grid(q, kQB);
-    if (t->matrix) { WT_DISPATCH_L2_WM(t->l2_bits, kQB, true, k_access, a, d_pos, q, d_out, (const SQ*)sb.sq, sb.subshift); }
-    else { WT_DISPATCH_L2(t->l2_bits, kQB, k_access, a, d_pos, q, d_out, (const SQ*)sb.sq, sb.subshift); }
-    dev_free(sb.block, st);
-  } else {
-    const uint32_t grid = query_grid(q, kQT);
-    if (t->matrix) { WT_DISPATCH_L2_WM(t->l2_bits, kQT, true, k_access, a, d_pos, q, d_out, (const SQ*)nullptr, 0u); }
-    else { WT_DISPATCH_L2(t->l2_bits, kQT, k_access, a, d_pos, q, d_out, (const SQ*)nullptr, 0u); }
-  }
-  qprof_end(st);
-  WT_HIP(hipGetLastError());
-  return alpha_unmap_access(t, d_out, q, st);
+  return query_run(t, 0, nullptr, d_pos, q, d_out, (hipStream_t)stream, nullptr);
 }
 
 extern "C" wt_status wt_rank(const wt_tree* t, const uint32_t* d_sym, const uint64_t* d_pos, uint64_t q,
@@ -399,34 +439,7 @@ extern "C" wt_status wt_rank(const wt_tree* t, const uint32_t* d_sym, const uint
   if (!t) return fail(WT_ERR_ARG, "wt_rank: tree is NULL");
   if (q == 0) return WT_OK;
   if (!d_sym || !d_pos || !d_out) return fail(WT_ERR_ARG, "wt_rank: NULL buffer");
-  hipStream_t st = (hipStream_t)stream;
-  const QArgs a = make_args(t);
-  SortBufs sb;
-  bool binned;
-  const uint32_t* sym = d_sym;
-  void* mapped = nullptr;
-  wt_status rc = alpha_map_syms(t, d_sym, q, st, &sym, &mapped);
-  if (rc != WT_OK) return rc;
-  rc = sort_batch(t, a, 1, sym, d_pos, q, st, sb, binned);
-  if (rc != WT_OK) {
-    if (mapped) dev_free(mapped, st);
-    return rc;
-  }
-  qprof_begin("rank", st);
-  if (binned) {
-    const uint32_t grid = query_grid(q, kQB);
-    if (t->matrix) { WT_DISPATCH_L2_WM(t->l2_bits, kQB, true, k_rank, a, sym, d_pos, q, d_out, (const SQ*)sb.sq, sb.subshift); }
-    else { WT_DISPATCH_L2(t->l2_bits, kQB, k_rank, a, sym, d_pos, q, d_out, (const SQ*)sb.sq, sb.subshift); }
-    dev_free(sb.block, st);
-  } else {
-    const uint32_t grid = query_grid(q, kQT);
-    if (t->matrix) { WT_DISPATCH_L2_WM(t->l2_bits, kQT, true, k_rank, a, sym, d_pos, q, d_out, (const SQ*)nullptr, 0u); }
-    else { WT_DISPATCH_L2(t->l2_bits, kQT, k_rank, a, sym, d_pos, q, d_out, (const SQ*)nullptr, 0u); }
-  }
-  qprof_end(st);
-  if (mapped) dev_free(mapped, st);
-  WT_HIP(hipGetLastError());
-  return WT_OK;
+  return query_run(t, 1, d_sym, d_pos, q, d_out, (hipStream_t)stream, nullptr);
 }
 
 extern "C" wt_status wt_select(const wt_tree* t, const uint32_t* d_sym, const uint64_t* d_k, uint64_t q,
@@ -435,47 +448,20 @@ extern "C" wt_status wt_select(const wt_tree* t, const uint32_t* d_sym, const ui
   if (!t) return fail(WT_ERR_ARG, "wt_select: tree is NULL");
   if (q == 0) return WT_OK;
   if (!d_sym || !d_k || !d_out) return fail(WT_ERR_ARG, "wt_select: NULL buffer");
-  hipStream_t st = (hipStream_t)stream;
-  const QArgs a = make_args(t);
-  SortBufs sb;
-  bool binned;
-  const uint32_t* sym = d_sym;
-  void* mapped = nullptr;
-  wt_status rc = alpha_map_syms(t, d_sym, q, st, &sym, &mapped);
-  if (rc != WT_OK) return rc;
-  rc = sort_batch(t, a, 2, sym, d_k, q, st, sb, binned);
-  if (rc != WT_OK) {
-    if (mapped) dev_free(mapped, st);
-    return rc;
-  }
-  qprof_begin("select", st);
-  if (binned) {
-    const uint32_t grid = query_grid(q, kQB);
-    if (t->matrix) { WT_DISPATCH_L2_WM(t->l2_bits, kQB, true, k_select, a, sym, d_k, q, d_out, (const SQ*)sb.sq, sb.subshift); }
-    else { WT_DISPATCH_L2(t->l2_bits, kQB, k_select, a, sym, d_k, q, d_out, (const SQ*)sb.sq, sb.subshift); }
-    dev_free(sb.block, st);
-  } else {
-    const uint32_t grid = query_grid(q, kQT);
-    if (t->matrix) { WT_DISPATCH_L2_WM(t->l2_bits, kQT, true, k_select, a, sym, d_k, q, d_out, (const SQ*)nullptr, 0u); }
-    else { WT_DISPATCH_L2(t->l2_bits, kQT, k_select, a, sym, d_k, q, d_out, (const SQ*)nullptr, 0u); }
-  }
-  qprof_end(st);
-  if (mapped) dev_free(mapped, st);
-  WT_HIP(hipGetLastError());
-  return WT_OK;
+  return query_run(t, 2, d_sym, d_k, q, d_out, (hipStream_t)stream, nullptr);
 }
 
 // ---------------------------------------------------------------- select without allocation
 
 namespace wt {
 namespace {
-// Largest batch of wt_select_noalloc and the bytes of its scratch: the binning buffers of such a batch
-// followed by its symbols mapped to codes (trees with an extracted alphabet).
+// Largest batch of wt_select_noalloc and the bytes of its scratch (query_scratch_bytes of such a batch).
 constexpr uint64_t kNoAllocMaxQ = 1ull << 20;
-constexpr size_t kNoAllocSortBytes = ((kNoAllocMaxQ + kBinChunk - 1) / kBinChunk) * kBins * 4 +
-                                     4 * kBins + sizeof(SQ) * kNoAllocMaxQ;
-constexpr size_t kNoAllocBytes = kNoAllocSortBytes + 4 * kNoAllocMaxQ;
-static_assert(kNoAllocSortBytes % 256 == 0, "mapped symbols start 256-byte aligned");
+constexpr size_t kNoAllocBytes = ((kNoAllocMaxQ + kBinChunk - 1) / kBinChunk) * kBins * 4 + 4 * kBins +
+                                 sizeof(SQ) * kNoAllocMaxQ + 4 * kNoAllocMaxQ;
+static_assert(((kNoAllocMaxQ + kBinChunk - 1) / kBinChunk) * kBins * 4 % 256 == 0 && (4 * kBins) % 256 == 0 &&
+                  (sizeof(SQ) * kNoAllocMaxQ) % 256 == 0 && (4 * kNoAllocMaxQ) % 256 == 0,
+              "the parts of the scratch are whole 256-byte units, as query_scratch_bytes rounds them");
 }  // namespace
 }  // namespace wt
 
@@ -517,29 +503,9 @@ extern "C" wt_status wt_select_noalloc(const wt_tree* t, const uint32_t* d_sym, 
   if (q == 0) return WT_OK;
   if (!d_sym || !d_k || !d_out) return fail(WT_ERR_ARG, "wt_select_noalloc: NULL buffer");
   char* buf = nullptr;
-  wt_status rc = noalloc_scratch(&buf);
+  const wt_status rc = noalloc_scratch(&buf);
   if (rc != WT_OK) return rc;
-  hipStream_t st = (hipStream_t)stream;
-  const QArgs a = make_args(t);
-  const uint32_t* sym = d_sym;
-  void* mapped = nullptr;
-  rc = alpha_map_syms(t, d_sym, q, st, &sym, &mapped, (uint32_t*)(buf + kNoAllocSortBytes));
-  if (rc != WT_OK) return rc;
-  SortBufs sb;
-  bool binned;
-  rc = sort_batch(t, a, 2, sym, d_k, q, st, sb, binned, buf);
-  if (rc != WT_OK) return rc;
-  if (binned) {
-    const uint32_t grid = query_grid(q, kQB);
-    if (t->matrix) { WT_DISPATCH_L2_WM(t->l2_bits, kQB, true, k_select, a, sym, d_k, q, d_out, (const SQ*)sb.sq, sb.subshift); }
-    else { WT_DISPATCH_L2(t->l2_bits, kQB, k_select, a, sym, d_k, q, d_out, (const SQ*)sb.sq, sb.subshift); }
-  } else {
-    const uint32_t grid = query_grid(q, kQT);
-    if (t->matrix) { WT_DISPATCH_L2_WM(t->l2_bits, kQT, true, k_select, a, sym, d_k, q, d_out, (const SQ*)nullptr, 0u); }
-    else { WT_DISPATCH_L2(t->l2_bits, kQT, k_select, a, sym, d_k, q, d_out, (const SQ*)nullptr, 0u); }
-  }
-  WT_HIP(hipGetLastError());
-  return WT_OK;
+  return query_run(t, 2, d_sym, d_k, q, d_out, (hipStream_t)stream, buf);
 }
 
 extern "C" wt_status wt_query_profiling(int on) {

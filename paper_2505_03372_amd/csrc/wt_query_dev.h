@@ -498,6 +498,12 @@ wt_status sort_batch(const wt_tree* t, const QArgs& a, int kind, const uint32_t*
                      hipStream_t st, SortBufs& sb, bool& binned, char* pre = nullptr);
 size_t sort_batch_bytes(uint64_t q);
 
+// One batch of queries of one kind (0 access: u32 answers; 1 rank, 2 select: u64 answers) on st, with
+// pre = NULL (buffers allocated) or query_scratch_bytes(q) bytes of device scratch (wt_query.hip).
+size_t query_scratch_bytes(uint64_t q);
+wt_status query_run(const wt_tree* t, int kind, const uint32_t* d_sym, const uint64_t* d_arg, uint64_t q, void* d_out,
+                    hipStream_t st, char* pre);
+
 // Counting sort of q queries by bucket id (ids[j] < 32768; wt_query.hip). scratch: sort_ids_bytes(q)
 // bytes; tot: 32768 entries, left holding the exclusive start of every bucket; perm: the slot order.
 size_t sort_ids_bytes(uint64_t q);
