@@ -51,7 +51,8 @@ typedef struct {
   uint32_t l2_bits;     /* L2 block size |L2| in bits (Section 4.1): 256, 512 (default), 1024, 2048 */
   uint32_t sample_rate; /* select sample interval s (Section 4.2): power of two in [512, 2^20]; default 4096 */
   uint32_t flags;       /* WT_BUILD_PROFILE: time every build kernel with HIP events (wt_build_profile);
-                           WT_BUILD_MATRIX: build the wavelet matrix instead of the level-wise tree */
+                           WT_BUILD_MATRIX: build the wavelet matrix instead of the level-wise tree;
+                           WT_BUILD_WIDE: keep full-width codes at every level */
   uint32_t reserved;
 } wt_build_opts;
 
@@ -67,6 +68,10 @@ typedef struct {
    export of bits / L1 / L2 / samples / WT_PART_WM_STARTS, wt_select_noalloc, wt_free) work on it; the
    learned index, forests and the node-table parts do not (WT_ERR_ARG). */
 #define WT_BUILD_MATRIX 2u
+/* Carry full-width codes at every level. By default the level sequence narrows (4 -> 2 -> 1 bytes per
+   element) as soon as the code bits the remaining levels need fit, and the levels after the code's
+   prefix bits are dropped find each element's node by its position; the tree is the same either way. */
+#define WT_BUILD_WIDE 4u
 
 /* Largest declared alphabet: the node tables are indexed by code prefix (2^L entries). */
 #define WT_MAX_SIGMA (1ull << 24)

@@ -27,6 +27,7 @@ PART_BITS, PART_L1, PART_L2, PART_SAMPLES1, PART_SAMPLES0, PART_NODE_START, PART
     PART_ALPHABET, PART_WM_STARTS = range(10)
 BUILD_PROFILE = 1
 BUILD_MATRIX = 2
+BUILD_WIDE = 4
 MAX_LEVELS = 24
 MAX_SIGMA = 1 << 24
 ACCESS_INVALID = 0xFFFFFFFF
@@ -451,16 +452,17 @@ def build_bitvector(words, n_bits: int, l2_bits: int = 512, sample_rate: int = 4
 
 
 def build(sym, sigma: int, l2_bits: int = 512, sample_rate: int = 4096, profile: bool = False, stream=None,
-          matrix: bool = False) -> Tree:
+          matrix: bool = False, wide: bool = False) -> Tree:
     """Build the wavelet tree of a contiguous device tensor of uint8/uint16/uint32 symbols. sigma: declared
     alphabet size (symbols in [0, sigma)), or 0 to extract the alphabet (the distinct values). matrix: build
-    the wavelet matrix instead (same queries)."""
+    the wavelet matrix instead (same queries). wide: keep full-width codes at every level (same tree)."""
     dts = _sym_dtypes()
     if sym.dtype not in dts:
         raise TypeError("symbols must be uint8, uint16 or uint32 (got %s)" % sym.dtype)
     if not sym.is_cuda or not sym.is_contiguous():
         raise ValueError("symbols must be a contiguous device tensor")
-    opts = BuildOpts(l2_bits, sample_rate, (BUILD_PROFILE if profile else 0) | (BUILD_MATRIX if matrix else 0), 0)
+    opts = BuildOpts(l2_bits, sample_rate, (BUILD_PROFILE if profile else 0) | (BUILD_MATRIX if matrix else 0)
+                     | (BUILD_WIDE if wide else 0), 0)
     h = ctypes.c_void_p(0)
     _check(lib().wt_build(ctypes.c_void_p(sym.data_ptr() if sym.numel() else 0), sym.numel(), dts[sym.dtype], sigma,
                           ctypes.byref(opts), ctypes.c_void_p(_stream_handle(stream)), ctypes.byref(h)))

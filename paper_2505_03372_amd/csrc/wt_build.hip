@@ -186,6 +186,46 @@ __global__ __launch_bounds__(kBT) void k_wm_starts(const uint64_t* __restrict__ 
     wstart[c] = rs[rev_low((uint32_t)c, L)];
 }
 
+// ---------------------------------------------------------------- nodes by position (narrow codes)
+
+// flag[h] = 1 for a non-empty node (heap entry h), flag[nheap] = 0.
+__global__ __launch_bounds__(kBT) void k_ns_flag(const NodeB* __restrict__ ntb, uint64_t nheap, uint64_t* __restrict__ flag) {
+  const uint64_t h = (uint64_t)blockIdx.x * kBT + threadIdx.x;
+  if (h < nheap) flag[h] = (ntb[h].start != kNoNode && ntb[h].end > ntb[h].start) ? 1ull : 0ull;
+  else if (h == nheap) flag[h] = 0;
+}
+
+// The non-empty nodes in heap order (= position order within a level), at the exclusive scan of the flags.
+__global__ __launch_bounds__(kBT) void k_ns_scatter(const NodeB* __restrict__ ntb, uint64_t nheap,
+                                                    const uint64_t* __restrict__ idx, NodeS* __restrict__ ns) {
+  const uint64_t h = (uint64_t)blockIdx.x * kBT + threadIdx.x;
+  if (h >= nheap || idx[h + 1] == idx[h]) return;
+  const uint32_t l = 63u - (uint32_t)__clzll(h + 1);
+  NodeS e;
+  e.start = ntb[h].start;
+  e.pfx = (uint32_t)(h + 1 - (1ull << l));
+  e.pad = 0;
+  ns[idx[h]] = e;
+}
+
+// Per tile of level l (2^tshift elements): the node holding its first element, as an index from the
+// level's first entry of the position list (the last entry starting at or before the tile).
+__global__ __launch_bounds__(kBT) void k_tile_first(const LevelMeta* __restrict__ meta, uint32_t l, uint32_t tshift,
+                                                    const NodeS* __restrict__ ns, const uint64_t* __restrict__ idx,
+                                                    uint32_t* __restrict__ tfirst) {
+  const uint64_t t = (uint64_t)blockIdx.x * kBT + threadIdx.x;
+  const uint64_t x = t << tshift;
+  if (x >= meta[l].n) return;
+  const uint64_t lo = idx[(1ull << l) - 1], hi = idx[(2ull << l) - 1];
+  uint64_t a = lo, b = hi - 1;
+  while (a < b) {
+    const uint64_t mid = (a + b + 1) >> 1;
+    if (ns[mid].start <= x) a = mid;
+    else b = mid - 1;
+  }
+  tfirst[t] = (uint32_t)(a - lo);
+}
+
 // ---------------------------------------------------------------- host orchestration
 
 namespace {
@@ -281,13 +321,27 @@ hipError_t launch_hist(const void* d_sym, uint64_t n, uint32_t sigma, uint32_t L
   return hipGetLastError();
 }
 
-template <typename E>
+template <typename E, typename EO = E, bool kPos = false>
 hipError_t launch_level(const LevelArgs& a, uint64_t n, hipStream_t st) {
   using TL = Tile<E>;
   const uint64_t nt = ceil_div(n, TL::T);
   if (nt == 0) return hipSuccess;
-  hipLaunchKernelGGL((k_level<E, false>), dim3((uint32_t)nt), dim3(kBT), 0, st, a, ForestGrid{});
+  hipLaunchKernelGGL((k_level<E, false, EO, kPos>), dim3((uint32_t)nt), dim3(kBT), 0, st, a, ForestGrid{});
   return hipGetLastError();
+}
+
+// Level pass for input width wi, output width wo (bytes) and the node lookup of the level.
+hipError_t launch_level_w(const LevelArgs& a, uint64_t n, uint32_t wi, uint32_t wo, hipStream_t st) {
+  if (a.pos_node) {
+    if (wi == 1) return launch_level<uint8_t, uint8_t, true>(a, n, st);
+    if (wi == 2) return wo == 1 ? launch_level<uint16_t, uint8_t, true>(a, n, st)
+                                : launch_level<uint16_t, uint16_t, true>(a, n, st);
+    return wo == 1 ? launch_level<uint32_t, uint8_t, true>(a, n, st) : launch_level<uint32_t, uint16_t, true>(a, n, st);
+  }
+  if (wi == 1) return launch_level<uint8_t>(a, n, st);
+  if (wi == 2) return wo == 1 ? launch_level<uint16_t, uint8_t>(a, n, st) : launch_level<uint16_t>(a, n, st);
+  return wo == 1 ? launch_level<uint32_t, uint8_t>(a, n, st)
+                 : wo == 2 ? launch_level<uint32_t, uint16_t>(a, n, st) : launch_level<uint32_t>(a, n, st);
 }
 
 }  // namespace
@@ -303,8 +357,9 @@ TreePlan plan_tree(uint64_t n, uint32_t w, uint64_t sigma, uint32_t L, uint32_t 
   p.srate = srate;
   p.tile = tile_elems(w);
   // capacity: whole tiles plus one L2 block of slack (queries read the whole L2 block at i = n_l),
-  // rounded to 128-byte lines so every level starts on a line
-  const uint64_t cap_bits = round_up(round_up(std::max<uint64_t>(n, 1), p.tile) + 2048, 1024);
+  // rounded to 128-byte lines so every level starts on a line. A level pass writes every bit word of
+  // its last tile, and a level of narrowed 1-byte codes has the longest tiles (kTileBytes elements).
+  const uint64_t cap_bits = round_up(round_up(std::max<uint64_t>(n, 1), tile_elems(1)) + 2048, 1024);
   p.words_per_level = cap_bits / 64;
   p.l1_per_level = round_up(ceil_div(n, kL1Bits) + 1, 16);
   // + one group of slack: a select reads up to 40 entries from the vector of its first candidate
@@ -441,6 +496,8 @@ wt_status wt::build_tree(const void* d_sym, uint64_t n, uint32_t sym_bytes, uint
   const size_t o_z = take((P.nheap + 1) * 8);
   const size_t o_zs = take((P.nheap + 1) * 8);
   const size_t o_wones = take(WT_MAX_LEVELS * 8);
+  const size_t o_ns = take(std::max<uint64_t>(P.nheap, 1) * sizeof(NodeS));
+  const size_t o_tfirst = take(ntiles * 4);
   const uint64_t gcnt_n = hist_gcnt_entries(n, sym_bytes, sigma);
   const size_t o_part = take(std::max<uint64_t>(part_n, ceil_div(gcnt_n, kScanChunk) + 1) * 8);
   const size_t o_gcnt = take(gcnt_n * 8);
@@ -461,6 +518,32 @@ wt_status wt::build_tree(const void* d_sym, uint64_t n, uint32_t sym_bytes, uint
   uint64_t* part = (uint64_t*)(sb + o_part);
   uint32_t* err = (uint32_t*)(sb + o_err);
   uint64_t* wones = (uint64_t*)(sb + o_wones);
+  NodeS* ns = (NodeS*)(sb + o_ns);
+  uint32_t* tfirst = (uint32_t*)(sb + o_tfirst);
+
+  // Carried code width per level: level l + 1 needs only the code bits below level l (L - 1 - l of
+  // them), so the sequence narrows to 2 and then 1 byte as levels consume bits. Once a level writes
+  // codes without their prefix bits (fewer than L bits), nodes are found by position from that level on.
+  const bool narrow = (flags & WT_BUILD_WIDE) == 0;
+  uint32_t wl[WT_MAX_LEVELS + 1];
+  bool posm[WT_MAX_LEVELS] = {};
+  bool any_pos = false;
+  wl[0] = sym_bytes;
+  {
+    bool lost = false;
+    for (uint32_t l = 0; l < L; ++l) {
+      uint32_t wo = wl[l];
+      if (narrow && l + 1 < L) {
+        const uint32_t need = L - 1 - l;
+        wo = std::min<uint32_t>(wo, need <= 8 ? 1u : need <= 16 ? 2u : 4u);
+      }
+      wl[l + 1] = wo;
+      const bool drops = 8 * wo < L;
+      posm[l] = !matrix && l > 0 && (lost || drops);
+      any_pos = any_pos || posm[l];
+      lost = lost || drops;
+    }
+  }
 
   Prof prof;
   prof.on = (flags & WT_BUILD_PROFILE) != 0;
@@ -539,24 +622,36 @@ wt_status wt::build_tree(const void* d_sym, uint64_t n, uint32_t sym_bytes, uint
     hipLaunchKernelGGL(k_node_final, dim3(nb), dim3(kBT), 0, st, P.nheap, (const uint64_t*)zs, ntb, t->dev.nodes,
                        t->dev.meta);
     WT_STEP(hipGetLastError());
+    if (any_pos) {
+      // the non-empty nodes of every level in position order (z, zs are free again)
+      const uint32_t nbf = (uint32_t)ceil_div(P.nheap + 1, kBT);
+      hipLaunchKernelGGL(k_ns_flag, dim3(nbf), dim3(kBT), 0, st, (const NodeB*)ntb, P.nheap, z);
+      WT_STEP(hipGetLastError());
+      WT_STEP(exclusive_scan_u64(z, P.nheap + 1, zs, part, st));
+      hipLaunchKernelGGL(k_ns_scatter, dim3(nb), dim3(kBT), 0, st, (const NodeB*)ntb, P.nheap, (const uint64_t*)zs, ns);
+      WT_STEP(hipGetLastError());
+    }
     WT_STEP(prof.end());
   }
 
   uint32_t l2shift = 0, sshift = 0;
   while ((1u << l2shift) < l2_bits) ++l2shift;
   while ((1u << sshift) < srate) ++sshift;
-  uint32_t tshift = 0;
-  while ((1u << tshift) < T) ++tshift;
 
   for (uint32_t l = 0; l < L; ++l) {
     uint64_t* cnt_l = tcnt + (size_t)l * cstride;
     uint64_t* chunk_l = cnt_l + ntiles + 1;
     uint64_t* pre_l = tpre + (size_t)l * (ntiles + 1);
+    uint32_t tshift = 0;  // tiles of level l: kTileBytes of its element width
+    while ((1u << tshift) < tile_elems(wl[l])) ++tshift;
     WT_STEP(prof.begin("tile_scan", (int)l));
     hipLaunchKernelGGL(k_tile_reduce, dim3((uint32_t)nchunks), dim3(kBT), 0, st, (const LevelMeta*)t->dev.meta, l,
                        tshift, (const uint64_t*)cnt_l, chunk_l);
     hipLaunchKernelGGL(k_tile_scan, dim3((uint32_t)(nchunks + 1)), dim3(kBT), 0, st, t->dev.meta, l, tshift,
                        (const uint64_t*)cnt_l, (const uint64_t*)chunk_l, pre_l, t->dev.L1, t->dev.L2);
+    if (posm[l])
+      hipLaunchKernelGGL(k_tile_first, dim3((uint32_t)ceil_div(ceil_div(n, 1ull << tshift), kBT)), dim3(kBT), 0, st,
+                         (const LevelMeta*)t->dev.meta, l, tshift, (const NodeS*)ns, (const uint64_t*)zs, tfirst);
     WT_STEP(hipGetLastError());
     WT_STEP(prof.end());
     LevelArgs a{};
@@ -580,10 +675,12 @@ wt_status wt::build_tree(const void* d_sym, uint64_t n, uint32_t sym_bytes, uint
     a.in_vec = (l == 0) ? 0u : 1u;
     a.in_aligned = (l == 0) ? (((uintptr_t)d_sym & 15u) == 0) : 1u;
     a.matrix = matrix ? 1u : 0u;
+    a.pos_node = posm[l] ? 1u : 0u;
+    a.ns = ns;
+    a.ns_idx = zs;
+    a.tfirst = tfirst;
     WT_STEP(prof.begin("level", (int)l));
-    if (sym_bytes == 1) WT_STEP(launch_level<uint8_t>(a, n, st));
-    else if (sym_bytes == 2) WT_STEP(launch_level<uint16_t>(a, n, st));
-    else WT_STEP(launch_level<uint32_t>(a, n, st));
+    WT_STEP(launch_level_w(a, n, wl[l], wl[l + 1], st));
     WT_STEP(prof.end());
   }
 

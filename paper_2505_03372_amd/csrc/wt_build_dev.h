@@ -813,6 +813,36 @@ __device__ __forceinline__ void tile_scan_body(LevelMeta* __restrict__ meta, uin
 
 // ---------------------------------------------------------------- level pass
 
+// A non-empty node of a level, for finding nodes by position (narrow codes).
+struct NodeS {
+  uint64_t start;
+  uint32_t pfx;  // code prefix (index in the level's node table)
+  uint32_t pad;
+};
+
+// Index of the last entry of list[0, n) whose start is <= q (list[0] <= q).
+__device__ __forceinline__ uint32_t lst_find(const uint32_t* __restrict__ list, uint32_t n, uint32_t q) {
+  uint32_t lo = 0, hi = n - 1;
+  while (lo < hi) {
+    const uint32_t mid = (lo + hi + 1) >> 1;
+    if (list[mid] <= q) lo = mid;
+    else hi = mid - 1;
+  }
+  return lo;
+}
+
+// Code prefix of the node holding level position x: the last of ns[lo, hi) whose start is <= x.
+template <typename P>
+__device__ __forceinline__ uint64_t ns_find(P ns, uint64_t lo, uint64_t hi, uint64_t x) {
+  hi -= 1;
+  while (lo < hi) {
+    const uint64_t mid = (lo + hi + 1) >> 1;
+    if (ns[mid].start <= x) lo = mid;
+    else hi = mid - 1;
+  }
+  return ns[lo].pfx;
+}
+
 struct LevelArgs {
   const void* in;  // level-l sequence (codes; symbols at level 0)
   void* out;       // level-(l+1) sequence
@@ -830,6 +860,13 @@ struct LevelArgs {
   uint32_t in_vec;      // the input may be read with 16-byte vectors everywhere (padded and aligned)
   uint32_t in_aligned;  // the input base is 16-byte aligned (vectors only inside the sequence)
   uint32_t matrix;      // wavelet matrix: the whole level is one node (ntb[0]: zeros then ones)
+  // Narrow codes: once a level has written codes without their prefix bits, later levels find an
+  // element's node by its position: the non-empty nodes of every level, in position order (ns, level l
+  // at [ns_idx[2^l - 1], ns_idx[2^(l+1) - 1])), and the node holding each tile's first element.
+  uint32_t pos_node;
+  const NodeS* ns;
+  const uint64_t* ns_idx;
+  const uint32_t* tfirst;
 };
 
 // The level pass's view of LevelArgs, with its pointers in the global address space.
@@ -847,6 +884,10 @@ struct LevelArgsG {
   uint32_t l, L, sigma, pow2;
   uint32_t l2shift, sshift;
   uint32_t encode, in_vec, in_aligned, matrix;
+  uint32_t pos_node;
+  const WT_GLOBAL NodeS* ns;
+  const WT_GLOBAL uint64_t* ns_idx;
+  const WT_GLOBAL uint32_t* tfirst;
 };
 
 __device__ __forceinline__ LevelArgsG to_global(const LevelArgs& a) {
@@ -871,6 +912,10 @@ __device__ __forceinline__ LevelArgsG to_global(const LevelArgs& a) {
   g.in_vec = a.in_vec;
   g.in_aligned = a.in_aligned;
   g.matrix = a.matrix;
+  g.pos_node = a.pos_node;
+  g.ns = (const WT_GLOBAL NodeS*)a.ns;
+  g.ns_idx = (const WT_GLOBAL uint64_t*)a.ns_idx;
+  g.tfirst = (const WT_GLOBAL uint32_t*)a.tfirst;
   return g;
 }
 
@@ -1041,19 +1086,26 @@ __device__ __forceinline__ LevelArgs forest_level_args(const TreeB& b, uint32_t 
   a.in_vec = l == 0 ? 0u : 1u;
   a.in_aligned = l == 0 ? b.aligned : 1u;
   a.matrix = 0;
+  a.pos_node = 0;
+  a.ns = nullptr;
+  a.ns_idx = nullptr;
+  a.tfirst = nullptr;
   return a;
 }
 
 // The body stays in the kernel (as a device function it needs far more registers).
 // Waves per SIMD the level pass is compiled for (a register budget): six where the body fits in
 // 80 registers without spilling, else five.
-template <typename E, bool kForest>
+template <typename E, bool kForest, bool kPos = false>
 constexpr int level_waves() {
-  return (sizeof(E) == 1 && !kForest) || (sizeof(E) == 2 && kForest) ? 6 : 5;
+  return (sizeof(E) == 1 && !kForest && !kPos) || (sizeof(E) == 2 && kForest) ? 6 : 5;
 }
 
-template <typename E, bool kForest>
-__global__ __launch_bounds__(kBT, (level_waves<E, kForest>())) void k_level(LevelArgs a_one, ForestGrid fg) {
+// E: element type of level l; EO: of level l + 1 (narrower when the codes need fewer bits below the
+// level: the prefix bits are dropped and later levels find nodes by position).
+// kPos: nodes by position (levels after the codes lost their prefix bits).
+template <typename E, bool kForest, typename EO = E, bool kPos = false>
+__global__ __launch_bounds__(kBT, (level_waves<E, kForest, kPos>())) void k_level(LevelArgs a_one, ForestGrid fg) {
   LevelArgsG a;
   uint64_t t;
   if constexpr (kForest) {
@@ -1065,8 +1117,10 @@ __global__ __launch_bounds__(kBT, (level_waves<E, kForest>())) void k_level(Leve
     t = blockIdx.x;
   }
   using TL = Tile<E>;
+  using TO = Tile<EO>;
+  static_assert(sizeof(EO) <= sizeof(E) && (!kForest || sizeof(EO) == sizeof(E)), "codes only narrow");
   constexpr int T = TL::T, W = TL::W, EV = TL::EV, G = TL::G, NCH = TL::NCH;
-  __shared__ __align__(16) E s_stage[T + 16 / sizeof(E) + 4];  // + slack for the 20-byte chunk reads
+  __shared__ __align__(16) EO s_stage[T + 16 / sizeof(EO) + 4];  // + slack for the 20-byte chunk reads
   __shared__ uint64_t s_words[W + 1];  // entry W: 0, so ranks are defined at x = T
   __shared__ uint32_t s_wpre[W + 1];   // entry W: ones of the tile
   __shared__ uint32_t s_w[kBT / 64];
@@ -1077,6 +1131,10 @@ __global__ __launch_bounds__(kBT, (level_waves<E, kForest>())) void k_level(Leve
   __shared__ uint64_t s_dst[2];   // single-node tile: destinations of its first zero and first one
   __shared__ uint32_t s_nc[4];    // single-node tile: next-level ones per (run, destination tile)
   __shared__ uint2 s_enc[32];     // level 0 of a reduced alphabet: (high code bits, shift) by h
+  __shared__ uint32_t s_lst[kSegMax];  // nodes by position: the tile's nodes (tile-relative starts)
+  __shared__ uint32_t s_lpf[kSegMax];  //   and their code prefixes
+  __shared__ uint32_t s_nlst;          //   count (kSegMax + 1: more nodes than the list holds)
+  __shared__ uint64_t s_i0;            //   the first node's entry in the level's position list
 
   const uint32_t tid = threadIdx.x, lane = tid & 63u;
   const uint32_t l = a.l, L = a.L;
@@ -1143,12 +1201,44 @@ __global__ __launch_bounds__(kBT, (level_waves<E, kForest>())) void k_level(Leve
     if (q0 < cnt && q0 + EV > cnt - 1) {
       const uint32_t cx = elem128<E>(((uint64_t)vx[k].y << 32) | vx[k].x, ((uint64_t)vx[k].w << 32) | vx[k].z,
                                      cnt - 1 - q0);
-      s_node[1] = (l && !a.matrix) ? ((uint64_t)cx >> (L - l)) & ((1ull << l) - 1ull) : 0ull;
+      if (!kPos) s_node[1] = (l && !a.matrix) ? ((uint64_t)cx >> (L - l)) & ((1ull << l) - 1ull) : 0ull;
     }
-    if (q0 == 0)
+    if (q0 == 0 && !kPos)
       s_node[0] = (l && !a.matrix) ? ((uint64_t)vec_elem<E>(vx[k], 0) >> (L - l)) & ((1ull << l) - 1ull) : 0ull;
   }
   if (tid < 4) s_nc[tid] = 0;
+  if (kPos && tid < 64) {
+    // the tile's nodes: entries from the one holding t0 on, while they start inside the tile (starts
+    // increase, so those entries are a prefix of each round of 64)
+    const uint64_t lo = a.ns_idx[(1ull << l) - 1], hi = a.ns_idx[(2ull << l) - 1];
+    const uint64_t i0 = lo + a.tfirst[t];
+    const uint64_t tend = t0 + cnt;
+    uint32_t total = 0;
+    bool more = true;
+    for (uint32_t r = 0; r <= (uint32_t)kSegMax / 64 && more; ++r) {
+      const uint64_t j = (uint64_t)r * 64 + lane;
+      bool in = false;
+      NodeS e{};
+      if (i0 + j < hi) {
+        e.start = a.ns[i0 + j].start;
+        e.pfx = a.ns[i0 + j].pfx;
+        in = j == 0 || e.start < tend;
+      }
+      const uint32_t c = (uint32_t)__popcll(__ballot(in));
+      if (in && j < (uint64_t)kSegMax) {
+        s_lst[j] = j ? (uint32_t)(e.start - t0) : 0u;
+        s_lpf[j] = e.pfx;
+      }
+      total += c;
+      more = c == 64;
+    }
+    if (lane == 0) {
+      s_nlst = min(total, (uint32_t)kSegMax + 1u);
+      s_i0 = i0;
+      s_node[0] = s_lpf[0];
+      s_node[1] = total == 1 ? s_lpf[0] : ~0ull;
+    }
+  }
   __syncthreads();
   // a tile inside one node (the rule at shallow levels) takes the fast path: two runs, no segments
   const bool single = s_node[0] == s_node[1];
@@ -1220,6 +1310,13 @@ __global__ __launch_bounds__(kBT, (level_waves<E, kForest>())) void k_level(Leve
   // 4a. staging
   const uint32_t nbsh = L - 2 - l;
   const uint64_t pmask = (1ull << l) - 1ull;
+  // code prefix of the node holding tile position q (nodes by position)
+  const uint32_t nlst = kPos ? s_nlst : 0u;
+  auto pfx_at = [&](uint32_t q) -> uint64_t {
+    if (nlst <= (uint32_t)kSegMax) return s_lpf[lst_find(s_lst, nlst, q)];
+    const uint64_t hi = a.ns_idx[(2ull << l) - 1];
+    return ns_find(a.ns, s_i0, min(hi, s_i0 + cnt), t0 + q);
+  };
   if (single) {
     // zeros fill slots [0, Z), ones [Z, cnt); each lane walks its vectors with running slots
     const uint32_t Z = cnt - tile_ones;
@@ -1234,7 +1331,7 @@ __global__ __launch_bounds__(kBT, (level_waves<E, kForest>())) void k_level(Leve
 #pragma unroll
           for (int e = 0; e < EV; ++e) {
             const uint32_t b = (m >> e) & 1u;
-            s_stage[b ? p1 : p0] = (E)vec_elem<E>(vx[k], e);
+            s_stage[b ? p1 : p0] = (EO)vec_elem<E>(vx[k], e);
             p1 += b;
             p0 += b ^ 1u;
           }
@@ -1243,7 +1340,7 @@ __global__ __launch_bounds__(kBT, (level_waves<E, kForest>())) void k_level(Leve
           const uint64_t lo = ((uint64_t)vx[k].y << 32) | vx[k].x, hi = ((uint64_t)vx[k].w << 32) | vx[k].z;
           for (uint32_t e = 0; e < cnt - q0; ++e) {
             const uint32_t b = (m >> e) & 1u;
-            s_stage[b ? p1 : p0] = (E)elem128<E>(lo, hi, e);
+            s_stage[b ? p1 : p0] = (EO)elem128<E>(lo, hi, e);
             p1 += b;
             p0 += b ^ 1u;
           }
@@ -1260,8 +1357,8 @@ __global__ __launch_bounds__(kBT, (level_waves<E, kForest>())) void k_level(Leve
     const uint32_t len1 = d1 < n_next ? (uint32_t)min<uint64_t>(cnt - Z, n_next - d1) : 0u;
     // Offsets relative to each run's first 16-byte destination chunk (32-bit): the run covers bytes
     // [a_r, e_r) from that chunk's base g_r; tb_r is the base's offset inside its destination tile.
-    constexpr uint32_t w = (uint32_t)sizeof(E);
-    constexpr uint32_t kTileB = (uint32_t)T * w;  // bytes of a destination tile
+    constexpr uint32_t w = (uint32_t)sizeof(EO);
+    constexpr uint32_t kTileB = (uint32_t)TO::T * w;  // bytes of a destination tile
     const uint64_t g0 = (d0 * w) & ~15ull, g1 = (d1 * w) & ~15ull;
     const uint32_t a0 = (uint32_t)(d0 * w) & 15u, a1 = (uint32_t)(d1 * w) & 15u;
     const uint32_t e0 = a0 + len0 * w, e1 = a1 + len1 * w;
@@ -1285,12 +1382,12 @@ __global__ __launch_bounds__(kBT, (level_waves<E, kForest>())) void k_level(Leve
         y.z = __builtin_amdgcn_alignbyte(x3, x2, sh);
         y.w = __builtin_amdgcn_alignbyte(x4, x3, sh);
         st16(cp, y);
-        nb = vec_count_bit<E>(y, nbsh);  // next-level ones of the 16 / w elements
+        nb = vec_count_bit<EO>(y, nbsh);  // next-level ones of the 16 / w elements
       } else {
         // run edge: element stores
-        WT_GLOBAL E* oe = pcast<E>(cp);
+        WT_GLOBAL EO* oe = pcast<EO>(cp);
         for (uint32_t x = blo; x < bhi; x += w) {
-          const E v = s_stage[(src + x - blo) / w];
+          const EO v = s_stage[(src + x - blo) / w];
           oe[(x - rb) / w] = v;
           nb += ((uint32_t)v >> nbsh) & 1u;
         }
@@ -1316,7 +1413,7 @@ __global__ __launch_bounds__(kBT, (level_waves<E, kForest>())) void k_level(Leve
       const uint32_t c = s_nc[tid];
       const uint64_t d = (tid < 2) ? d0 : d1;
       if (c && d < n_next)
-        atomic_add_u64(a.cnt_next + (d >> TL::TSHIFT) + (tid & 1u), c);
+        atomic_add_u64(a.cnt_next + (d >> TO::TSHIFT) + (tid & 1u), c);
     }
     return;
   }
@@ -1331,8 +1428,8 @@ __global__ __launch_bounds__(kBT, (level_waves<E, kForest>())) void k_level(Leve
         const uint32_t nv = min((uint32_t)EV, cnt - q0);
         const uint64_t lo = ((uint64_t)vx[k].y << 32) | vx[k].x, hi = ((uint64_t)vx[k].w << 32) | vx[k].z;
         const uint32_t cf = vec_elem<E>(vx[k], 0), cl = elem128<E>(lo, hi, nv - 1);
-        const uint64_t Nf = l ? ((uint64_t)cf >> (L - l)) & pmask : 0ull;
-        const uint64_t Nl = l ? ((uint64_t)cl >> (L - l)) & pmask : 0ull;
+        const uint64_t Nf = kPos ? pfx_at(q0) : l ? ((uint64_t)cf >> (L - l)) & pmask : 0ull;
+        const uint64_t Nl = kPos ? pfx_at(q0 + nv - 1) : l ? ((uint64_t)cl >> (L - l)) & pmask : 0ull;
         if (Nf == Nl) {
           // the whole vector lies in one node
           if (Nf != curN) enter_node(ld_node(a.ntb + Nf), q0, t0, cnt, G0, G1, s_words, s_wpre, s_seg, &s_nseg, sa, zs, R1a), curN = Nf;
@@ -1343,14 +1440,14 @@ __global__ __launch_bounds__(kBT, (level_waves<E, kForest>())) void k_level(Leve
 #pragma unroll
             for (int e = 0; e < EV; ++e) {
               const uint32_t b = (m >> e) & 1u;
-              s_stage[min(b ? p1 : p0, (uint32_t)T - 1u)] = (E)vec_elem<E>(vx[k], e);
+              s_stage[min(b ? p1 : p0, (uint32_t)T - 1u)] = (EO)vec_elem<E>(vx[k], e);
               p1 += b;
               p0 += b ^ 1u;
             }
           } else {
             for (uint32_t e = 0; e < nv; ++e) {
               const uint32_t b = (m >> e) & 1u;
-              s_stage[min(b ? p1 : p0, (uint32_t)T - 1u)] = (E)elem128<E>(lo, hi, e);
+              s_stage[min(b ? p1 : p0, (uint32_t)T - 1u)] = (EO)elem128<E>(lo, hi, e);
               p1 += b;
               p0 += b ^ 1u;
             }
@@ -1360,10 +1457,10 @@ __global__ __launch_bounds__(kBT, (level_waves<E, kForest>())) void k_level(Leve
             const uint32_t code = elem128<E>(lo, hi, e);
             const uint32_t b = (code >> bsh) & 1u;
             const uint32_t q = q0 + e;
-            const uint64_t N = l ? ((uint64_t)code >> (L - l)) & pmask : 0ull;
+            const uint64_t N = kPos ? pfx_at(q) : l ? ((uint64_t)code >> (L - l)) & pmask : 0ull;
             if (N != curN) enter_node(ld_node(a.ntb + N), q, t0, cnt, G0, G1, s_words, s_wpre, s_seg, &s_nseg, sa, zs, R1a), curN = N;
             const uint32_t slot = b ? sa + zs + (r1 - R1a) : sa + ((q - r1) - (sa - R1a));
-            s_stage[min(slot, (uint32_t)T - 1u)] = (E)code;
+            s_stage[min(slot, (uint32_t)T - 1u)] = (EO)code;
             r1 += b;
           }
         }
@@ -1386,7 +1483,7 @@ __global__ __launch_bounds__(kBT, (level_waves<E, kForest>())) void k_level(Leve
         const uint32_t bb = r & 1u;
         const uint64_t d = bb ? g.d1 : g.d0;
         const uint32_t len = d < n_next ? (uint32_t)min<uint64_t>(bb ? g.z - g.a - g.zs : g.zs, n_next - d) : 0u;
-        if (len) nch = (uint32_t)(((d + len - 1) * sizeof(E) >> 4) - ((d * sizeof(E)) >> 4) + 1);
+        if (len) nch = (uint32_t)(((d + len - 1) * sizeof(EO) >> 4) - ((d * sizeof(EO)) >> 4) + 1);
       }
       uint32_t total;
       const uint32_t ex = block_excl_scan_u32(nch, s_w, total);
@@ -1415,11 +1512,11 @@ __global__ __launch_bounds__(kBT, (level_waves<E, kForest>())) void k_level(Leve
         const uint64_t d = bb ? g.d1 : g.d0;
         const uint32_t len = (uint32_t)min<uint64_t>(bb ? g.z - g.a - g.zs : g.zs, n_next - d);
         const uint32_t slot0 = bb ? g.a + g.zs : g.a;
-        const uint64_t db = d * sizeof(E), de = (d + len) * sizeof(E);
+        const uint64_t db = d * sizeof(EO), de = (d + len) * sizeof(EO);
         chunk = (db >> 4) + (c - s_cp[lo]);
         const uint64_t cb = chunk << 4;
         const uint64_t blo = max(db, cb), bhi = min(de, cb + 16);
-        const uint32_t src = slot0 * (uint32_t)sizeof(E) + (uint32_t)(blo - db);  // LDS byte of blo
+        const uint32_t src = slot0 * (uint32_t)sizeof(EO) + (uint32_t)(blo - db);  // LDS byte of blo
         if (blo == cb && bhi == cb + 16) {
           const uint32_t dw = src >> 2, sh = src & 3u;
           const uint32_t x0 = st32[dw], x1 = st32[dw + 1], x2 = st32[dw + 2], x3 = st32[dw + 3],
@@ -1430,19 +1527,19 @@ __global__ __launch_bounds__(kBT, (level_waves<E, kForest>())) void k_level(Leve
           y.z = __builtin_amdgcn_alignbyte(x3, x2, sh);
           y.w = __builtin_amdgcn_alignbyte(x4, x3, sh);
           st16(outb + cb, y);
-          nb1 = vec_count_bit<E>(y, nbsh);
+          nb1 = vec_count_bit<EO>(y, nbsh);
         } else {
-          const uint32_t s0 = src / (uint32_t)sizeof(E);
-          WT_GLOBAL E* oe = pcast<E>(outb);
-          const uint64_t e0 = blo / sizeof(E), e1 = bhi / sizeof(E);
+          const uint32_t s0 = src / (uint32_t)sizeof(EO);
+          WT_GLOBAL EO* oe = pcast<EO>(outb);
+          const uint64_t e0 = blo / sizeof(EO), e1 = bhi / sizeof(EO);
           for (uint64_t e = e0; e < e1; ++e) {
-            const E v = s_stage[s0 + (uint32_t)(e - e0)];
+            const EO v = s_stage[s0 + (uint32_t)(e - e0)];
             oe[e] = v;
             nb1 += ((uint32_t)v >> nbsh) & 1u;
           }
         }
       }
-      const uint64_t dt = (chunk << 4) / ((uint64_t)T * sizeof(E));
+      const uint64_t dt = (chunk << 4) / ((uint64_t)TO::T * sizeof(EO));
       count_next(__ballot(active), dt, 0u, lane, cur_tile, cur_c, a.cnt_next, nb1);
     }
   } else {
@@ -1459,7 +1556,7 @@ __global__ __launch_bounds__(kBT, (level_waves<E, kForest>())) void k_level(Leve
       uint32_t nbit = 0;
       if (j < cnt) {
         const uint32_t code = (uint32_t)s_stage[j];
-        const uint64_t N = l ? ((uint64_t)code >> (L - l)) & pmask : 0ull;
+        const uint64_t N = kPos ? pfx_at(j) : l ? ((uint64_t)code >> (L - l)) & pmask : 0ull;
         if (N != curN) {
           const NodeB nb = ld_node(a.ntb + N);
           sa = (uint32_t)(nb.start > t0 ? min(nb.start - t0, (uint64_t)cnt) : 0ull);
@@ -1473,11 +1570,11 @@ __global__ __launch_bounds__(kBT, (level_waves<E, kForest>())) void k_level(Leve
         dest = (j < sa + zs) ? D0 + (j - sa) : D1 + (j - sa - zs);
         cont = dest < n_next;
         if (cont) {
-          pcast<E>(outb)[dest] = (E)code;
+          pcast<EO>(outb)[dest] = (EO)code;
           nbit = (code >> nbsh) & 1u;
         }
       }
-      count_next(__ballot(cont), dest >> TL::TSHIFT, nbit, lane, cur_tile, cur_c, a.cnt_next, 0u);
+      count_next(__ballot(cont), dest >> TO::TSHIFT, nbit, lane, cur_tile, cur_c, a.cnt_next, 0u);
     }
   }
   if (lane == 0 && cur_c) atomic_add_u64(a.cnt_next + cur_tile, cur_c);

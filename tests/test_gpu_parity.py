@@ -280,3 +280,38 @@ def test_binned_batches_equal_unbinned(order):
     idx = np.arange(0, q, 61)
     G._assert_eq("select vs oracle", got[idx], oracle.select(S, sigma, sc[idx], sk[idx]), sk[idx])
     t.free()
+
+
+# (width, sigma, n, kind): trees whose level sequence narrows (u32 -> u16 -> u8, u16 -> u8) and whose
+# later levels find nodes by position, including tiles with more nodes than the per-tile list holds
+NARROW_CASES = [
+    (4, 1 << 20, (1 << 21) + 333, "zipf12"),
+    (4, 1 << 17, 1 << 20, "uniform"),
+    (4, 70001, 500000, "zipf"),
+    (4, 300, 100000, "uniform"),
+    (2, 65536, (1 << 20) + 5, "uniform"),
+    (2, 40000, 300000, "zipf"),
+    (2, 1000, 1 << 20, "runs"),
+    (2, 60001, 100000, "sparse"),
+    (4, 1 << 20, 300000, "sparse"),
+]
+
+
+@pytest.mark.parametrize("width,sigma,n,kind", NARROW_CASES)
+def test_narrow_codes_build_the_same_tree(width, sigma, n, kind):
+    """The default build (narrowing codes, nodes by position after the prefix is dropped) equals the
+    full-width build part by part, and both equal the oracle."""
+    import paper_2505_03372_amd as wt
+    G.log("narrow vs wide: width=%d sigma=%d n=%d %s" % (width, sigma, n, kind))
+    S = make_seq(kind, n, sigma, width, 0x7A00 + sigma + n)
+    tn = G.gpu_build(S, sigma)
+    tw = G.gpu_build(S, sigma, wide=True)
+    try:
+        G.compare_structure(tn, oracle.OracleTree(S, sigma))
+        for l in range(tn.info["levels"]):
+            for part in (wt.PART_BITS, wt.PART_L1, wt.PART_L2, wt.PART_SAMPLES1, wt.PART_SAMPLES0):
+                np.testing.assert_array_equal(tn.export(part, l), tw.export(part, l))
+        G.compare_queries(tn, S, sigma, *G.random_queries(S, sigma, 4096, 0x7A01 + n))
+    finally:
+        tn.free()
+        tw.free()
