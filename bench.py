@@ -648,12 +648,13 @@ def run_tree(args, torch, wt, workloads, dev, name, steps, warmup, learned, kind
 
     def step(record, matrix=False):
         # the build is timed by one event pair around the whole wt_build call on its stream (it includes
-        # the library's allocations, launch gaps and the final read-back of the level sizes), beside the
-        # sum of the per-kernel events the library records and the host wall time of the call
+        # the library's allocations, launch gaps and the final read-back of the level sizes) and by the
+        # host wall time of the call; the per-kernel times come from separate builds with the library's
+        # per-kernel events (each event pair leaves a gap of about 10 us on the stream)
         eb0, eb1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         eb0.record(stream)
         h0 = time.perf_counter()
-        t = wt.build(S, sigma, l2_bits=args.l2_bits, sample_rate=args.sample_rate, profile=True, matrix=matrix)
+        t = wt.build(S, sigma, l2_bits=args.l2_bits, sample_rate=args.sample_rate, matrix=matrix)
         h1 = time.perf_counter()
         eb1.record(stream)
         evs = {}
@@ -677,8 +678,18 @@ def run_tree(args, torch, wt, workloads, dev, name, steps, warmup, learned, kind
                 evs[kind if variant == "plain" else "select_learned"] = (e0, e1)
         qprof = wt.query_profile()  # per-kernel durations of this step's query calls (waits for them)
         if record is not None:
-            record.append((t.profile(), evs, t.info, linfo, qprof, (eb0, eb1), (h1 - h0) * 1e3))
+            record.append((None, evs, t.info, linfo, qprof, (eb0, eb1), (h1 - h0) * 1e3))
         t.free()
+
+    def kernel_profiles(k, matrix=False):
+        # per-kernel durations of k builds made with the library's events (outside the timed steps)
+        out = []
+        for _ in range(k):
+            t = wt.build(S, sigma, l2_bits=args.l2_bits, sample_rate=args.sample_rate, profile=True, matrix=matrix)
+            torch.cuda.synchronize()
+            out.append(t.profile())
+            t.free()
+        return out
 
     for _ in range(warmup):
         step(None)
@@ -713,6 +724,7 @@ def run_tree(args, torch, wt, workloads, dev, name, steps, warmup, learned, kind
         unbinned["learned_vs_plain_speedup"] = unbinned["plain_ms"] / unbinned["learned_ms"]
         t.free()
     ms_per_step = (t1 - t0) * 1e3 / steps
+    profs = kernel_profiles(max(3, steps))
     hostq = None
     if hostq_sizes:
         t = wt.build(S, sigma, l2_bits=args.l2_bits, sample_rate=args.sample_rate)
@@ -730,9 +742,10 @@ def run_tree(args, torch, wt, workloads, dev, name, steps, warmup, learned, kind
         torch.cuda.synchronize()
         m1 = time.perf_counter()
         wt.query_profiling(False)
+        mprofs = kernel_profiles(matrix_steps, matrix=True)
         mat = {"steps": matrix_steps, "ms_per_step": (m1 - m0) * 1e3 / matrix_steps,
                "build_ms_median": float(np.median([r[5][0].elapsed_time(r[5][1]) for r in mrecs])),
-               "build_kernel_sum_ms_median": float(np.median([sum(p["ms"] for p in r[0]) for r in mrecs]))}
+               "build_kernel_sum_ms_median": float(np.median([sum(p["ms"] for p in pr) for pr in mprofs]))}
         mat["build_symbols_per_s"] = n / (mat["build_ms_median"] * 1e-3)
         mk = {}
         for r in mrecs:
@@ -750,11 +763,12 @@ def run_tree(args, torch, wt, workloads, dev, name, steps, warmup, learned, kind
     level_ms, build_ms, build_ev_ms, build_wall_ms, learn_ms = [], [], [], [], []
     qms = {}
     kms = {}
-    for prof, evs, _, linfo, qprof, (eb0, eb1), wall in recs:
-        for e in qprof:
-            kms.setdefault(e["kernel"], []).append(e["ms"])
+    for prof in profs:
         level_ms += [p["ms"] for p in prof if p["kernel"] == "level"]
         build_ms.append(sum(p["ms"] for p in prof))
+    for _, evs, _, linfo, qprof, (eb0, eb1), wall in recs:
+        for e in qprof:
+            kms.setdefault(e["kernel"], []).append(e["ms"])
         build_ev_ms.append(eb0.elapsed_time(eb1))
         build_wall_ms.append(wall)
         if linfo is not None:

@@ -23,6 +23,7 @@
 
 #include <algorithm>
 #include <cstring>
+#include <vector>
 
 #include "wt_build_dev.h"
 #include "wt_host.h"
@@ -372,7 +373,8 @@ TreePlan plan_tree(uint64_t n, uint32_t w, uint64_t sigma, uint32_t L, uint32_t 
     off = round_up(off + bytes, 256);
     return o;
   };
-  p.off_meta = take(sizeof(LevelMeta) * WT_MAX_LEVELS);
+  // level metadata, then one more entry holding the build's symbol-range flag (read back with them)
+  p.off_meta = take(sizeof(LevelMeta) * (WT_MAX_LEVELS + 1));
   p.off_cum = take((sigma + 1) * sizeof(uint64_t));
   p.off_nodes = take(matrix ? sizeof(NodeQ) : std::max<uint64_t>(p.nheap, 1) * sizeof(NodeQ));
   p.off_wstart = take(matrix ? std::max<uint64_t>(sigma, 1) * sizeof(uint64_t) : 0);
@@ -516,7 +518,8 @@ wt_status wt::build_tree(const void* d_sym, uint64_t n, uint32_t sym_bytes, uint
   uint64_t* z = (uint64_t*)(sb + o_z);
   uint64_t* zs = (uint64_t*)(sb + o_zs);
   uint64_t* part = (uint64_t*)(sb + o_part);
-  uint32_t* err = (uint32_t*)(sb + o_err);
+  uint32_t* err = (uint32_t*)(t->dev.meta + WT_MAX_LEVELS);
+  (void)o_err;
   uint64_t* wones = (uint64_t*)(sb + o_wones);
   NodeS* ns = (NodeS*)(sb + o_ns);
   uint32_t* tfirst = (uint32_t*)(sb + o_tfirst);
@@ -684,18 +687,15 @@ wt_status wt::build_tree(const void* d_sym, uint64_t n, uint32_t sym_bytes, uint
     WT_STEP(prof.end());
   }
 
-  // read back level sizes and the range flag
-  struct Readback {
-    LevelMeta meta[WT_MAX_LEVELS];
-    uint32_t err;
-  };
-  Readback rb{};
-  if (L) WT_STEP(hipMemcpyAsync(rb.meta, t->dev.meta, sizeof(LevelMeta) * L, hipMemcpyDeviceToHost, st));
-  WT_STEP(hipMemcpyAsync(&rb.err, err, sizeof(uint32_t), hipMemcpyDeviceToHost, st));
+  // read back level sizes and the range flag (one copy: the flag sits after the level entries)
+  std::vector<LevelMeta> rb(WT_MAX_LEVELS + 1);
+  WT_STEP(hipMemcpyAsync(rb.data(), t->dev.meta, sizeof(LevelMeta) * (WT_MAX_LEVELS + 1), hipMemcpyDeviceToHost, st));
   WT_STEP(hipStreamSynchronize(st));
 #undef WT_STEP
-  if (rb.err) return bail(fail(WT_ERR_SYMBOL_RANGE, "wt_build: a symbol is >= sigma (%llu)", (unsigned long long)sigma));
-  for (uint32_t l = 0; l < L; ++l) t->hmeta[l] = rb.meta[l];
+  uint32_t rb_err = 0;
+  std::memcpy(&rb_err, &rb[WT_MAX_LEVELS], sizeof(rb_err));
+  if (rb_err) return bail(fail(WT_ERR_SYMBOL_RANGE, "wt_build: a symbol is >= sigma (%llu)", (unsigned long long)sigma));
+  for (uint32_t l = 0; l < L; ++l) t->hmeta[l] = rb[l];
   if (prof.on) prof.collect(t->prof);
   *out = t;
   return WT_OK;
