@@ -465,14 +465,19 @@ wt_status wt_query_host_release(void);
  * budget has left (the budget is carved once from device memory at creation). An admitted request
  * copies its queries to the device, runs wt_query_mixed's kernels and copies the answers back, all on
  * its slot's stream, so requests that arrive while others are on the GPU overlap with them.
+ * Small requests are coalesced: when a slot frees up, the oldest waiting request and the waiting
+ * requests after it, in arrival order, are admitted together while their total stays within
+ * coalesce_q queries; they are copied side by side into one device batch, answered by one run of the
+ * mixed kernels and copied back each to its own answer array, and complete together; such a batch
+ * goes through page-locked staging buffers of its slot (one copy up, one copy down).
  * Latency = completion (observed by the server) - arrival. A request's answers do not depend on what
  * else is in flight. A request larger than the whole budget is rejected (status WT_ERR_OOM).
  */
 typedef struct wt_server wt_server;
 
 typedef struct {
-  uint32_t slots;          /* requests in flight at once; 0 = 8, at most 64 */
-  uint32_t reserved;
+  uint32_t slots;          /* batches in flight at once (a stream each); 0 = 8, at most 64 */
+  uint32_t coalesce_q;     /* largest total of a coalesced batch of requests; 0 = 16384, 1 = no coalescing */
   uint64_t mem_budget;     /* device bytes for in-flight requests; 0 = 4 GiB */
   double sim_ns_per_query; /* > 0: no GPU; a request occupies its slot for q * this many ns (scheduler tests) */
 } wt_server_opts;
@@ -494,7 +499,8 @@ typedef struct {
 } wt_completion;
 
 typedef struct {
-  uint32_t requests, rejected, peak_in_flight, reserved;
+  uint32_t requests, rejected, peak_in_flight; /* peak_in_flight counts requests */
+  uint32_t batches;        /* device batches run (one per admitted group of coalesced requests) */
   uint64_t queries;        /* answered */
   uint64_t peak_bytes;     /* most device bytes held by admitted requests at once */
   double makespan_s;       /* first arrival to last completion */

@@ -133,7 +133,7 @@ class ForestInfo(ctypes.Structure):
 
 
 class ServerOpts(ctypes.Structure):
-    _fields_ = [("slots", ctypes.c_uint32), ("reserved", ctypes.c_uint32), ("mem_budget", ctypes.c_uint64),
+    _fields_ = [("slots", ctypes.c_uint32), ("coalesce_q", ctypes.c_uint32), ("mem_budget", ctypes.c_uint64),
                 ("sim_ns_per_query", ctypes.c_double)]
 
 
@@ -150,7 +150,7 @@ class Completion(ctypes.Structure):
 
 class ServeStats(ctypes.Structure):
     _fields_ = [("requests", ctypes.c_uint32), ("rejected", ctypes.c_uint32), ("peak_in_flight", ctypes.c_uint32),
-                ("reserved", ctypes.c_uint32), ("queries", ctypes.c_uint64), ("peak_bytes", ctypes.c_uint64),
+                ("batches", ctypes.c_uint32), ("queries", ctypes.c_uint64), ("peak_bytes", ctypes.c_uint64),
                 ("makespan_s", ctypes.c_double), ("qps", ctypes.c_double), ("lat_p50_s", ctypes.c_double),
                 ("lat_p99_s", ctypes.c_double), ("lat_mean_s", ctypes.c_double), ("lat_max_s", ctypes.c_double)]
 
@@ -624,8 +624,10 @@ def _host_ptr(a) -> int:
 class Server:
     """Continuous-batching server over a resident forest (or a simulated executor when sim_ns_per_query > 0)."""
 
-    def __init__(self, forest=None, slots: int = 8, mem_budget: int = 0, sim_ns_per_query: float = 0.0):
-        opts = ServerOpts(slots, 0, mem_budget, sim_ns_per_query)
+    def __init__(self, forest=None, slots: int = 0, mem_budget: int = 0, sim_ns_per_query: float = 0.0,
+                 coalesce: int = 0):
+        """slots: batches in flight (0: 8); coalesce: largest total of coalesced requests (0: 16384, 1: none)."""
+        opts = ServerOpts(slots, coalesce, mem_budget, sim_ns_per_query)
         h = ctypes.c_void_p(0)
         _check(lib().wt_server_create(forest._h if forest is not None else None, ctypes.byref(opts), ctypes.byref(h)))
         self._h = h

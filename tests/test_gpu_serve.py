@@ -72,7 +72,7 @@ def _pinned(a: np.ndarray):
     return t
 
 
-def _run(f, reqs, slots, budget=0, learned=False):
+def _run(f, reqs, slots, budget=0, learned=False, coalesce=0):
     import paper_2505_03372_amd as wt
     rq = []
     for r in reqs:
@@ -81,7 +81,7 @@ def _run(f, reqs, slots, budget=0, learned=False):
             op[op == 2] = 3
         rq.append(dict(arrival_s=r["arrival_s"], tree=_pinned(r["tree"]), op=_pinned(op), sym=_pinned(r["sym"]),
                        arg=_pinned(r["arg"]), out=_pinned(np.zeros_like(r["out"]))))
-    s = wt.Server(f, slots=slots, mem_budget=budget)
+    s = wt.Server(f, slots=slots, mem_budget=budget, coalesce=coalesce)
     comps, st = s.run(rq)
     s.close()
     assert all(c["status"] == wt.WT_OK for c in comps)
@@ -109,10 +109,10 @@ def test_results_alone_equal_results_in_the_mix(served):
     ov = _overlapping_pairs(comps_mix)
     G.log("  overlapping request pairs: %d" % ov)
     assert ov > 0, "no two requests were in flight at the same time"
-    G.log("serving: alone (1 slot, spaced arrivals)")
+    G.log("serving: alone (1 slot, one request per batch)")
     alone_reqs = [dict(r, arrival_s=0.0) for r in reqs]
-    alone, _, st_alone = _run(f, alone_reqs, 1)
-    assert st_alone["peak_in_flight"] == 1
+    alone, _, st_alone = _run(f, alone_reqs, 1, coalesce=1)
+    assert st_alone["peak_in_flight"] == 1 and st_alone["batches"] == len(reqs)
     for i, r in enumerate(reqs):
         ref = G.host(f.query_mixed(G.dev(r["tree"]), G.dev(r["op"]), G.dev(r["sym"]), G.dev(r["arg"])))
         np.testing.assert_array_equal(mix[i], ref, err_msg="request %d in the mix" % i)
@@ -147,6 +147,33 @@ def test_memory_budget_bounds_in_flight_bytes(served):
     for i, r in enumerate(reqs):
         ref = G.host(f.query_mixed(G.dev(r["tree"]), G.dev(r["op"]), G.dev(r["sym"]), G.dev(r["arg"])))
         np.testing.assert_array_equal(out[i], ref)
+
+
+def test_coalesced_small_requests(served):
+    """Small requests waiting together are answered as coalesced batches (fewer batches than requests)
+    with the answers of one wt_query_mixed call per request, including requests of one query and
+    all-access requests without symbols."""
+    f, seqs = served
+    reqs = _trace(seqs, 200, 1 << 12, 0x7A, 0.0)
+    for r in reqs[::9]:  # all-access requests, passed without symbols
+        r["op"][:] = 0
+    G.log("serving: coalesced small requests")
+    import paper_2505_03372_amd as wt
+    rq = []
+    for i, r in enumerate(reqs):
+        acc = i % 9 == 0
+        rq.append(dict(arrival_s=0.0, tree=_pinned(r["tree"]), op=_pinned(r["op"]),
+                       sym=None if acc else _pinned(r["sym"]), arg=_pinned(r["arg"]),
+                       out=_pinned(np.zeros_like(r["out"]))))
+    s = wt.Server(f, slots=2, coalesce=16384)
+    comps, st = s.run(rq)
+    s.close()
+    G.log("  %s" % st)
+    assert all(c["status"] == wt.WT_OK for c in comps)
+    assert st["batches"] < len(reqs) // 4
+    for i, r in enumerate(reqs):
+        ref = G.host(f.query_mixed(G.dev(r["tree"]), G.dev(r["op"]), G.dev(r["sym"]), G.dev(r["arg"])))
+        np.testing.assert_array_equal(rq[i]["out"].numpy(), ref, err_msg="request %d" % i)
 
 
 @pytest.mark.skip(reason="learned selects inside mixed batches are switched off: that traversal (tree arguments per "
