@@ -55,6 +55,15 @@ def lib():
         L.oracle_level_bits.restype = ctypes.c_int
         L.oracle_level_bits.argtypes = [ctypes.c_void_p, ctypes.c_uint64, ctypes.c_int, ctypes.c_uint64,
                                         ctypes.c_uint64, _u64p, _u64p]
+        L.oracle_level_bits_codes.restype = ctypes.c_int
+        L.oracle_level_bits_codes.argtypes = [ctypes.c_void_p, ctypes.c_uint64, ctypes.c_int, ctypes.c_uint64,
+                                              ctypes.c_int, _u64p, _u32p, ctypes.c_uint64, _u64p, _u64p]
+        L.oracle_nodes_codes.argtypes = [ctypes.c_void_p, ctypes.c_uint64, ctypes.c_int, ctypes.c_uint64,
+                                         ctypes.c_int, _u64p, _u32p, ctypes.c_int, _u64p, _u64p, _u64p]
+        L.oracle_huffman_lengths.restype = ctypes.c_int
+        L.oracle_huffman_lengths.argtypes = [_u64p, ctypes.c_uint64, ctypes.c_int, _u32p]
+        L.oracle_huffman_codes.restype = ctypes.c_int
+        L.oracle_huffman_codes.argtypes = [_u32p, ctypes.c_uint64, _u64p, _u32p]
         L.oracle_directory.argtypes = [_u64p, ctypes.c_uint64, ctypes.c_uint64, _u64p, _u16p]
         L.oracle_samples.argtypes = [_u64p, ctypes.c_uint64, ctypes.c_uint64, _u64p, _u64p, _u64p, _u64p]
         L.oracle_nodes.argtypes = [ctypes.c_void_p, ctypes.c_uint64, ctypes.c_int, ctypes.c_uint64, ctypes.c_int,
@@ -114,6 +123,34 @@ def codes(sigma: int):
     return code[:sigma], ln[:sigma]
 
 
+def huffman_limit(m: int) -> int:
+    """Longest code a Huffman-shaped tree of m >= 2 occurring symbols may use: ceil(lg m) + 8, at most
+    24 (the most levels a tree has)."""
+    return min(24, max(1, (m - 1).bit_length()) + 8)
+
+
+def huffman_lengths(h: np.ndarray, limit: int | None = None) -> np.ndarray:
+    """Optimal code lengths, none above `limit`, for the counts h (package-merge; wt_oracle.c)."""
+    h = np.ascontiguousarray(h, dtype=np.uint64)
+    m = int(np.count_nonzero(h))
+    if limit is None:
+        limit = huffman_limit(max(m, 2))
+    ln = np.zeros(max(h.size, 1), dtype=np.uint32)
+    rc = lib().oracle_huffman_lengths(_p(h, _u64p), h.size, limit, _p(ln, _u32p))
+    if rc < 0:
+        raise ValueError("2^limit is below the number of symbols")
+    return ln[: h.size]
+
+
+def huffman_codes(lens: np.ndarray):
+    """Canonical codes for the lengths: (left-aligned codes, ranks in code order, L)."""
+    lens = np.ascontiguousarray(lens, dtype=np.uint32)
+    code = np.zeros(max(lens.size, 1), dtype=np.uint64)
+    rk = np.zeros(max(lens.size, 1), dtype=np.uint32)
+    L = lib().oracle_huffman_codes(_p(lens, _u32p), lens.size, _p(code, _u64p), _p(rk, _u32p))
+    return code[: lens.size], rk[: lens.size], int(L)
+
+
 def hist(S: np.ndarray, sigma: int) -> np.ndarray:
     S = _seq(S)
     h = np.zeros(max(sigma, 1), dtype=np.uint64)
@@ -135,22 +172,34 @@ class OracleTree:
     """Every part of the tree, computed from its definition (see wt_oracle.c)."""
 
     def __init__(self, S: np.ndarray, sigma: int, l2_bits: int = 512, sample_rate: int = 4096,
-                 with_nodes: bool = True):
+                 with_nodes: bool = True, huffman: bool = False):
         S = _seq(S)
         self.n = int(S.size)
         self.sigma = int(sigma)
         self.l2_bits = l2_bits
         self.sample_rate = sample_rate
-        self.L = num_levels(sigma)
+        self.huffman = huffman
         self.hist = hist(S, sigma)
         self.cum_hist = np.zeros(sigma + 1, dtype=np.uint64)
         self.cum_hist[1:] = np.cumsum(self.hist, dtype=np.uint64)
+        if huffman:
+            # Huffman-shaped: canonical codes of the optimal length-limited code for these counts
+            self.lens = huffman_lengths(self.hist)
+            self.codes, self.rank, self.L = huffman_codes(self.lens)
+        else:
+            self.codes, self.lens = codes(sigma)
+            self.L = num_levels(sigma)
         L = self.L
         stride = max(1, (self.n + 63) // 64)
         bits = np.zeros((max(L, 1), stride), dtype=np.uint64)
         level_n = np.zeros(max(L, 1), dtype=np.uint64)
-        rc = lib().oracle_level_bits(ctypes.c_void_p(S.ctypes.data), self.n, S.dtype.itemsize, sigma, stride,
-                                     _p(bits, _u64p), _p(level_n, _u64p))
+        if huffman:
+            rc = lib().oracle_level_bits_codes(ctypes.c_void_p(S.ctypes.data), self.n, S.dtype.itemsize, sigma, L,
+                                               _p(self.codes, _u64p), _p(self.lens, _u32p), stride,
+                                               _p(bits, _u64p), _p(level_n, _u64p))
+        else:
+            rc = lib().oracle_level_bits(ctypes.c_void_p(S.ctypes.data), self.n, S.dtype.itemsize, sigma, stride,
+                                         _p(bits, _u64p), _p(level_n, _u64p))
         if rc != 0:
             raise ValueError("symbol out of range")
         self.level_n = [int(x) for x in level_n[:L]]
@@ -179,8 +228,13 @@ class OracleTree:
             if with_nodes:
                 st = np.zeros(1 << l, dtype=np.uint64)
                 r0 = np.zeros(1 << l, dtype=np.uint64)
-                lib().oracle_nodes(ctypes.c_void_p(S.ctypes.data), self.n, S.dtype.itemsize, sigma, l,
-                                   _p(rowp, _u64p), _p(st, _u64p), _p(r0, _u64p))
+                if huffman:
+                    lib().oracle_nodes_codes(ctypes.c_void_p(S.ctypes.data), self.n, S.dtype.itemsize, sigma, L,
+                                             _p(self.codes, _u64p), _p(self.lens, _u32p), l, _p(rowp, _u64p),
+                                             _p(st, _u64p), _p(r0, _u64p))
+                else:
+                    lib().oracle_nodes(ctypes.c_void_p(S.ctypes.data), self.n, S.dtype.itemsize, sigma, l,
+                                       _p(rowp, _u64p), _p(st, _u64p), _p(r0, _u64p))
                 self.node_start.append(st)
                 self.node_r0.append(r0)
 

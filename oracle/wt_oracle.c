@@ -30,6 +30,14 @@
  *    p at level l starts at the number of level-l elements with a smaller prefix;
  *    its precomputed rank is rank0 of level l at that start.
  *
+ *  - Huffman-shaped tree (Conclusion, named as a further variant; the Huffman-shaped
+ *    wavelet tree of Navarro's survey): the same levels, but the codes are an optimal
+ *    prefix code for the symbol frequencies of S with no code longer than a limit
+ *    (package-merge). Canonical form: the occurring symbols ordered by (code length
+ *    descending, symbol ascending) receive consecutive left-aligned code values, so at
+ *    every depth the internal nodes are the leftmost prefixes and a node's elements are
+ *    preceded in its level by exactly the elements of the symbols ordered before it.
+ *
  * Query answers outside the domains of the definitions are sentinels:
  *   access(i >= n) = 0xFFFFFFFF; rank(c, i > n) = UINT64_MAX; rank(c >= sigma, i) = 0;
  *   select(c, 0) = UINT64_MAX; select(c, k > count(c)) = n; select(c >= sigma, k) = n.
@@ -88,21 +96,18 @@ int oracle_hist(const void* S, uint64_t n, int w, uint64_t sigma, uint64_t* hist
 }
 
 /*
- * Level bits of every level. bits is L rows of `stride` words each (zero padded);
- * level_n[l] receives n_l. The sequence of level l is obtained from S by a stable
- * counting sort on the key code >> (L - l) (the top l code bits); elements whose
- * code length is <= l are left out. Returns -1 if a symbol is >= sigma.
+ * Level bits of every level for the given codes (left-aligned to L bits) and code
+ * lengths. bits is L rows of `stride` words each (zero padded); level_n[l] receives
+ * n_l. The sequence of level l is obtained from S by a stable counting sort on the
+ * key code >> (L - l) (the top l code bits); elements whose code length is <= l are
+ * left out. Returns -1 if a symbol is >= sigma.
  */
-int oracle_level_bits(const void* S, uint64_t n, int w, uint64_t sigma, uint64_t stride,
-                      uint64_t* bits, uint64_t* level_n) {
-  int L = oracle_num_levels(sigma);
+int oracle_level_bits_codes(const void* S, uint64_t n, int w, uint64_t sigma, int L, const uint64_t* code,
+                            const uint32_t* len, uint64_t stride, uint64_t* bits, uint64_t* level_n) {
   if (L == 0) return 0;
-  uint64_t* code = (uint64_t*)malloc(sigma * sizeof(uint64_t));
-  uint32_t* len = (uint32_t*)malloc(sigma * sizeof(uint32_t));
   uint64_t* order = (uint64_t*)malloc((n ? n : 1) * sizeof(uint64_t));
-  oracle_codes(sigma, code, len);
   for (uint64_t i = 0; i < n; ++i)
-    if (sym_at(S, w, i) >= sigma) { free(code); free(len); free(order); return -1; }
+    if (sym_at(S, w, i) >= sigma) { free(order); return -1; }
   memset(bits, 0, (size_t)L * stride * sizeof(uint64_t));
   for (int l = 0; l < L; ++l) {
     /* stable counting sort of positions by the top-l code bits */
@@ -130,8 +135,21 @@ int oracle_level_bits(const void* S, uint64_t n, int w, uint64_t sigma, uint64_t
     }
     level_n[l] = m;
   }
-  free(code); free(len); free(order);
+  free(order);
   return 0;
+}
+
+/* The levels of the reduced tree (codes of oracle_codes, L = ceil(lg sigma)). */
+int oracle_level_bits(const void* S, uint64_t n, int w, uint64_t sigma, uint64_t stride,
+                      uint64_t* bits, uint64_t* level_n) {
+  int L = oracle_num_levels(sigma);
+  if (L == 0) return 0;
+  uint64_t* code = (uint64_t*)malloc(sigma * sizeof(uint64_t));
+  uint32_t* len = (uint32_t*)malloc(sigma * sizeof(uint32_t));
+  oracle_codes(sigma, code, len);
+  int rc = oracle_level_bits_codes(S, n, w, sigma, L, code, len, stride, bits, level_n);
+  free(code); free(len);
+  return rc;
 }
 
 static int bit_at(const uint64_t* row, uint64_t j) { return (int)((row[j / 64] >> (j % 64)) & 1); }
@@ -174,17 +192,14 @@ void oracle_samples(const uint64_t* row, uint64_t nl, uint64_t s, uint64_t* s1, 
 }
 
 /*
- * Node starts and precomputed ranks at level l for every code prefix p in [0, 2^l).
+ * Node starts and precomputed ranks at level l for every code prefix p in [0, 2^l), for the given
+ * codes (left-aligned to L bits) and lengths.
  * A prefix names a node when some symbol whose code is longer than l carries it;
  * otherwise both outputs are UINT64_MAX.
  */
-void oracle_nodes(const void* S, uint64_t n, int w, uint64_t sigma, int l, const uint64_t* row,
-                  uint64_t* start, uint64_t* r0) {
-  int L = oracle_num_levels(sigma);
+void oracle_nodes_codes(const void* S, uint64_t n, int w, uint64_t sigma, int L, const uint64_t* code,
+                        const uint32_t* len, int l, const uint64_t* row, uint64_t* start, uint64_t* r0) {
   uint64_t np = 1ull << l;
-  uint64_t* code = (uint64_t*)malloc(sigma * sizeof(uint64_t));
-  uint32_t* len = (uint32_t*)malloc(sigma * sizeof(uint32_t));
-  oracle_codes(sigma, code, len);
   char* exists = (char*)calloc(np, 1);
   uint64_t* count = (uint64_t*)calloc(np, sizeof(uint64_t));
   for (uint64_t c = 0; c < sigma; ++c)
@@ -210,7 +225,119 @@ void oracle_nodes(const void* S, uint64_t n, int w, uint64_t sigma, int l, const
     }
     before += count[p];
   }
-  free(zeros_before); free(code); free(len); free(exists); free(count);
+  free(zeros_before); free(exists); free(count);
+}
+
+/* Node starts of the reduced tree (codes of oracle_codes). */
+void oracle_nodes(const void* S, uint64_t n, int w, uint64_t sigma, int l, const uint64_t* row,
+                  uint64_t* start, uint64_t* r0) {
+  int L = oracle_num_levels(sigma);
+  uint64_t* code = (uint64_t*)malloc(sigma * sizeof(uint64_t));
+  uint32_t* len = (uint32_t*)malloc(sigma * sizeof(uint32_t));
+  oracle_codes(sigma, code, len);
+  oracle_nodes_codes(S, n, w, sigma, L, code, len, l, row, start, r0);
+  free(code); free(len);
+}
+
+/*
+ * Huffman-shaped tree: code lengths. For the symbols that occur (hist[c] > 0), lengths of an
+ * optimal prefix code (least sum of hist[c] * len[c]) among those with no length above `limit`,
+ * by the package-merge method of Larmore and Hirschberg: the list of depth `limit` is the
+ * occurring symbols ordered by (count, symbol); the list of depth d < limit merges those symbols
+ * with the packages of the list of depth d + 1 (its items paired in order, first with second,
+ * third with fourth, ..., an odd last item dropped; a package weighs the sum of its pair), by
+ * weight, a symbol before a package of equal weight. The first 2m - 2 items of the depth-1 list
+ * are taken (m occurring symbols), and the packages taken at depth d take their two items at
+ * depth d + 1; a symbol's length is the number of depths at which it is taken. Symbols that do not
+ * occur get length 0, and so does a lone occurring symbol (a tree of no level). Returns the
+ * largest length, or -1 if 2^limit < m.
+ */
+typedef struct {
+  uint64_t weight;
+  uint64_t sym;
+} HLeaf;
+
+static int hleaf_cmp(const void* a, const void* b) {
+  const HLeaf* x = (const HLeaf*)a;
+  const HLeaf* y = (const HLeaf*)b;
+  if (x->weight != y->weight) return x->weight < y->weight ? -1 : 1;
+  return x->sym < y->sym ? -1 : (x->sym > y->sym);
+}
+
+int oracle_huffman_lengths(const uint64_t* hist, uint64_t sigma, int limit, uint32_t* len) {
+  memset(len, 0, sigma * sizeof(uint32_t));
+  uint64_t m = 0;
+  for (uint64_t c = 0; c < sigma; ++c) m += hist[c] > 0;
+  if (m <= 1) return 0;
+  if (limit < 1 || (limit < 63 && (1ull << limit) < m)) return -1;
+  HLeaf* leaf = (HLeaf*)malloc(m * sizeof(HLeaf));
+  uint64_t j = 0;
+  for (uint64_t c = 0; c < sigma; ++c)
+    if (hist[c] > 0) { leaf[j].weight = hist[c]; leaf[j].sym = c; ++j; }
+  qsort(leaf, m, sizeof(HLeaf), hleaf_cmp);
+  /* is_leaf[d][x]: item x of the list of depth d (1..limit) is a symbol (1) or a package (0) */
+  uint64_t cap = 2 * m;
+  char* is_leaf = (char*)calloc((size_t)(limit + 1) * cap, 1);
+  uint64_t* items = (uint64_t*)calloc((size_t)(limit + 1), sizeof(uint64_t));
+  uint64_t* wprev = (uint64_t*)malloc(cap * sizeof(uint64_t));
+  uint64_t* wcur = (uint64_t*)malloc(cap * sizeof(uint64_t));
+  uint64_t nprev = 0;
+  for (int d = limit; d >= 1; --d) {
+    char* fl = is_leaf + (size_t)d * cap;
+    uint64_t npk = d == limit ? 0 : nprev / 2, a = 0, k = 0, x = 0;
+    while (a < m || k < npk) {
+      uint64_t pw = k < npk ? wprev[2 * k] + wprev[2 * k + 1] : 0;
+      if (a < m && (k >= npk || leaf[a].weight <= pw)) {
+        wcur[x] = leaf[a].weight;
+        fl[x] = 1;
+        ++a;
+      } else {
+        wcur[x] = pw;
+        fl[x] = 0;
+        ++k;
+      }
+      ++x;
+    }
+    items[d] = x;
+    nprev = x;
+    uint64_t* tmp = wprev; wprev = wcur; wcur = tmp;
+  }
+  uint64_t take = 2 * m - 2;
+  int maxlen = 0;
+  for (int d = 1; d <= limit && take > 0; ++d) {
+    const char* fl = is_leaf + (size_t)d * cap;
+    uint64_t leaves = 0;
+    for (uint64_t x = 0; x < take && x < items[d]; ++x) leaves += (uint64_t)fl[x];
+    for (uint64_t a = 0; a < leaves; ++a) {
+      len[leaf[a].sym] += 1;
+      if ((int)len[leaf[a].sym] > maxlen) maxlen = (int)len[leaf[a].sym];
+    }
+    take = 2 * (take - leaves);
+  }
+  free(leaf); free(is_leaf); free(items); free(wprev); free(wcur);
+  return maxlen;
+}
+
+/*
+ * Huffman-shaped tree: canonical codes for the lengths len[] (0 = no code). The symbols with a
+ * code, ordered by (length descending, symbol ascending), get ranks 0, 1, ... and left-aligned
+ * code values (L = the largest length) V_0 = 0, V_{r+1} = V_r + 2^(L - len_r); rank[c] =
+ * UINT32_MAX for a symbol without a code. Returns L.
+ */
+int oracle_huffman_codes(const uint32_t* len, uint64_t sigma, uint64_t* code, uint32_t* rank) {
+  int L = 0;
+  for (uint64_t c = 0; c < sigma; ++c) if ((int)len[c] > L) L = (int)len[c];
+  uint64_t v = 0;
+  uint32_t r = 0;
+  for (uint64_t c = 0; c < sigma; ++c) { code[c] = 0; rank[c] = UINT32_MAX; }
+  for (int ell = L; ell >= 1; --ell)
+    for (uint64_t c = 0; c < sigma; ++c)
+      if ((int)len[c] == ell) {
+        code[c] = v;
+        rank[c] = r++;
+        v += 1ull << (L - ell);
+      }
+  return L;
 }
 
 /*
