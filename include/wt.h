@@ -52,7 +52,8 @@ typedef struct {
   uint32_t sample_rate; /* select sample interval s (Section 4.2): power of two in [512, 2^20]; default 4096 */
   uint32_t flags;       /* WT_BUILD_PROFILE: time every build kernel with HIP events (wt_build_profile);
                            WT_BUILD_MATRIX: build the wavelet matrix instead of the level-wise tree;
-                           WT_BUILD_WIDE: keep full-width codes at every level */
+                           WT_BUILD_WIDE: keep full-width codes at every level;
+                           WT_BUILD_HUFFMAN: Huffman-shaped tree */
   uint32_t reserved;
 } wt_build_opts;
 
@@ -72,6 +73,28 @@ typedef struct {
    element) as soon as the code bits the remaining levels need fit, and the levels after the code's
    prefix bits are dropped find each element's node by its position; the tree is the same either way. */
 #define WT_BUILD_WIDE 4u
+/* Huffman-shaped tree (the Huffman variant the thesis's Conclusion names as a next step; the
+   Huffman-shaped wavelet tree of Navarro's survey, which Section 2 cites): the same level-wise layout,
+   rank directory, select samples and queries, but the codes are an optimal prefix code for the
+   symbol counts of d_sym, so a symbol's elements take as many levels as its code has bits and the
+   levels hold sum_c count(c) len(c) bits in all (the zero-order entropy plus less than one bit per
+   symbol) instead of n ceil(lg sigma).
+   * Lengths: optimal among the prefix codes of the symbols that occur with no code longer than
+     min(WT_MAX_LEVELS, ceil(lg m) + 8) bits (m = number of distinct symbols), by package-merge
+     (Larmore and Hirschberg): the list of the deepest length is the occurring symbols ordered by
+     (count, symbol); every shorter list merges them with the consecutive pairs of the next deeper
+     list (an odd last item dropped), by weight, a symbol before a pair of equal weight; the first
+     2m - 2 items of the length-1 list are taken, and every pair taken takes its two items one length
+     deeper; a symbol's length is the number of lists in which it is taken. A lone symbol gets no code
+     (a tree of no level); symbols that do not occur get none either (rank 0, select n).
+   * Codes (canonical): the occurring symbols ordered by (length descending, symbol ascending) take
+     consecutive left-aligned code values from 0 (each adds 2^(L - length), L = the longest length),
+     so at every level the nodes of the longer codes come first and a node starts at the count of
+     the symbols ordered before it.
+   The code lengths are computed on the host from the histogram (one extra pass over d_sym and one
+   copy of sigma counts to the host); WT_PART_HUFF_CODES exports the codes. Not combinable with
+   WT_BUILD_MATRIX; forests and the learned index refuse Huffman-shaped trees (WT_ERR_ARG). */
+#define WT_BUILD_HUFFMAN 8u
 
 /* Largest declared alphabet: the node tables are indexed by code prefix (2^L entries). */
 #define WT_MAX_SIGMA (1ull << 24)
@@ -157,6 +180,8 @@ typedef struct {
   uint32_t alphabet_extracted; /* 1: built with sigma = 0 (queries map values to codes and back) */
   uint32_t matrix;             /* 1: a wavelet matrix (WT_BUILD_MATRIX); level_n[l] = n at every level */
   uint64_t max_symbol;         /* largest symbol value of the alphabet */
+  uint32_t huffman;            /* 1: a Huffman-shaped tree (WT_BUILD_HUFFMAN) */
+  uint32_t reserved1;
 } wt_info_t;
 
 wt_status wt_info(const wt_tree* t, wt_info_t* out);
@@ -175,6 +200,8 @@ wt_status wt_info(const wt_tree* t, wt_info_t* out);
  *   WT_PART_WM_STARTS  u64[sigma]             wavelet matrix only (level ignored): first position of every
  *                                             code's run in the order below the last level (the elements
  *                                             sorted stably by their codes read bit-reversed)
+ *   WT_PART_HUFF_CODES u64[sigma]             Huffman-shaped tree only (level ignored): len(c) << 32 |
+ *                                             code(c), the code right-aligned (0: c has no code)
  * A wavelet matrix has no node parts (WT_PART_NODE_START / WT_PART_NODE_R0 give WT_ERR_ARG).
  */
 enum {
@@ -187,7 +214,8 @@ enum {
   WT_PART_NODE_R0 = 6,
   WT_PART_CUM_HIST = 7,
   WT_PART_ALPHABET = 8,
-  WT_PART_WM_STARTS = 9
+  WT_PART_WM_STARTS = 9,
+  WT_PART_HUFF_CODES = 10
 };
 
 /* Copy one part to host memory h_dst of cap bytes; *needed receives the byte size of the part

@@ -24,10 +24,11 @@ LIB_PATH = os.path.join(_HERE, "libwt.so")
 
 WT_OK, WT_ERR_ARG, WT_ERR_SYMBOL_RANGE, WT_ERR_OOM, WT_ERR_HIP, WT_ERR_STATE = range(6)
 PART_BITS, PART_L1, PART_L2, PART_SAMPLES1, PART_SAMPLES0, PART_NODE_START, PART_NODE_R0, PART_CUM_HIST, \
-    PART_ALPHABET, PART_WM_STARTS = range(10)
+    PART_ALPHABET, PART_WM_STARTS, PART_HUFF_CODES = range(11)
 BUILD_PROFILE = 1
 BUILD_MATRIX = 2
 BUILD_WIDE = 4
+BUILD_HUFFMAN = 8
 MAX_LEVELS = 24
 MAX_SIGMA = 1 << 24
 ACCESS_INVALID = 0xFFFFFFFF
@@ -78,7 +79,8 @@ class Info(ctypes.Structure):
                 ("level_n", ctypes.c_uint64 * MAX_LEVELS), ("level_ones", ctypes.c_uint64 * MAX_LEVELS),
                 ("bytes_bits", ctypes.c_uint64), ("bytes_l1", ctypes.c_uint64), ("bytes_l2", ctypes.c_uint64),
                 ("bytes_samples", ctypes.c_uint64), ("bytes_nodes", ctypes.c_uint64), ("bytes_total", ctypes.c_uint64),
-                ("alphabet_extracted", ctypes.c_uint32), ("matrix", ctypes.c_uint32), ("max_symbol", ctypes.c_uint64)]
+                ("alphabet_extracted", ctypes.c_uint32), ("matrix", ctypes.c_uint32), ("max_symbol", ctypes.c_uint64),
+                ("huffman", ctypes.c_uint32), ("reserved1", ctypes.c_uint32)]
 
 
 class LearnOpts(ctypes.Structure):
@@ -308,7 +310,8 @@ class Tree:
                     sample_rate=inf.sample_rate, level_n=list(inf.level_n[:L]), level_ones=list(inf.level_ones[:L]),
                     bytes_bits=inf.bytes_bits, bytes_l1=inf.bytes_l1, bytes_l2=inf.bytes_l2,
                     bytes_samples=inf.bytes_samples, bytes_nodes=inf.bytes_nodes, bytes_total=inf.bytes_total,
-                    alphabet_extracted=bool(inf.alphabet_extracted), matrix=bool(inf.matrix), max_symbol=inf.max_symbol)
+                    alphabet_extracted=bool(inf.alphabet_extracted), matrix=bool(inf.matrix), max_symbol=inf.max_symbol,
+                    huffman=bool(inf.huffman))
 
     @property
     def n(self) -> int:
@@ -452,17 +455,18 @@ def build_bitvector(words, n_bits: int, l2_bits: int = 512, sample_rate: int = 4
 
 
 def build(sym, sigma: int, l2_bits: int = 512, sample_rate: int = 4096, profile: bool = False, stream=None,
-          matrix: bool = False, wide: bool = False) -> Tree:
+          matrix: bool = False, wide: bool = False, huffman: bool = False) -> Tree:
     """Build the wavelet tree of a contiguous device tensor of uint8/uint16/uint32 symbols. sigma: declared
     alphabet size (symbols in [0, sigma)), or 0 to extract the alphabet (the distinct values). matrix: build
-    the wavelet matrix instead (same queries). wide: keep full-width codes at every level (same tree)."""
+    the wavelet matrix instead (same queries). wide: keep full-width codes at every level (same tree).
+    huffman: Huffman-shaped tree (codes of an optimal length-limited prefix code of the counts)."""
     dts = _sym_dtypes()
     if sym.dtype not in dts:
         raise TypeError("symbols must be uint8, uint16 or uint32 (got %s)" % sym.dtype)
     if not sym.is_cuda or not sym.is_contiguous():
         raise ValueError("symbols must be a contiguous device tensor")
     opts = BuildOpts(l2_bits, sample_rate, (BUILD_PROFILE if profile else 0) | (BUILD_MATRIX if matrix else 0)
-                     | (BUILD_WIDE if wide else 0), 0)
+                     | (BUILD_WIDE if wide else 0) | (BUILD_HUFFMAN if huffman else 0), 0)
     h = ctypes.c_void_p(0)
     _check(lib().wt_build(ctypes.c_void_p(sym.data_ptr() if sym.numel() else 0), sym.numel(), dts[sym.dtype], sigma,
                           ctypes.byref(opts), ctypes.c_void_p(_stream_handle(stream)), ctypes.byref(h)))

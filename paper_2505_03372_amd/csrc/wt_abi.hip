@@ -120,6 +120,7 @@ extern "C" wt_status wt_info(const wt_tree* t, wt_info_t* out) {
   out->bytes_total = t->block_bytes;
   out->alphabet_extracted = t->amap ? 1u : 0u;
   out->matrix = t->matrix;
+  out->huffman = t->huff;
   out->max_symbol = t->amap ? t->max_symbol : (t->sigma ? t->sigma - 1 : 0);
   return WT_OK;
 }
@@ -148,6 +149,22 @@ extern "C" wt_status wt_export(const wt_tree* t, int level, int part, void* h_ds
     if (cap < bytes) return fail(WT_ERR_ARG, "wt_export: capacity %zu < %zu bytes", cap, bytes);
     WT_HIP(hipDeviceSynchronize());
     WT_HIP(hipMemcpy(h_dst, t->dev.wstart, bytes, hipMemcpyDeviceToHost));
+    return WT_OK;
+  }
+  if (part == WT_PART_HUFF_CODES) {
+    if (!t->huff) return fail(WT_ERR_ARG, "wt_export: WT_PART_HUFF_CODES needs a Huffman-shaped tree");
+    const size_t bytes = (size_t)t->sigma * 8;
+    if (needed) *needed = bytes;
+    if (!h_dst) return WT_OK;
+    if (cap < bytes) return fail(WT_ERR_ARG, "wt_export: capacity %zu < %zu bytes", cap, bytes);
+    WT_HIP(hipDeviceSynchronize());
+    uint64_t* o = (uint64_t*)h_dst;
+    WT_HIP(hipMemcpy(o, t->dev.hcode, bytes, hipMemcpyDeviceToHost));
+    // stored left-aligned to L bits; exported right-aligned
+    for (uint64_t c = 0; c < t->sigma; ++c) {
+      const uint32_t len = (uint32_t)(o[c] >> 32);
+      o[c] = len ? ((uint64_t)len << 32) | ((uint32_t)o[c] >> (t->L - len)) : 0ull;
+    }
     return WT_OK;
   }
   if (t->matrix && (part == WT_PART_NODE_START || part == WT_PART_NODE_R0))

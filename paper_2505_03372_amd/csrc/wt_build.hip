@@ -27,6 +27,7 @@
 
 #include "wt_build_dev.h"
 #include "wt_host.h"
+#include "wt_huff.h"
 #include "wt_internal.h"
 
 namespace wt {
@@ -322,6 +323,53 @@ hipError_t launch_hist(const void* d_sym, uint64_t n, uint32_t sigma, uint32_t L
   return hipGetLastError();
 }
 
+// Histogram of d_sym on its own, copied to the host, with the symbol-range check: the first step of a
+// Huffman-shaped build, whose levels depend on the counts. Scratch of its own.
+wt_status huff_prepass(const void* d_sym, uint64_t n, uint32_t w, uint64_t sigma, hipStream_t st,
+                       std::vector<uint64_t>& hist) {
+  hist.assign(sigma, 0ull);
+  if (n == 0) return WT_OK;
+  const uint64_t ntiles = ceil_div(n, tile_elems(w));
+  const uint64_t gcnt_n = hist_gcnt_entries(n, w, sigma);
+  size_t so = 0;
+  auto take = [&](size_t bytes) {
+    const size_t o = so;
+    so = round_up(so + bytes, 256);
+    return o;
+  };
+  const size_t o_hist = take((sigma + 1) * 8);
+  const size_t o_cnt = take((ntiles + 1) * 8);
+  const size_t o_err = take(64);
+  const size_t o_gcnt = take(gcnt_n * 8);
+  const size_t o_goff = take(gcnt_n * 8);
+  const size_t o_part = take((ceil_div(std::max<uint64_t>(gcnt_n, 1), kScanChunk) + 1) * 8);
+  const size_t o_seq = take(gcnt_n ? n * w : 0);
+  Scratch S;
+  S.st = st;
+  S.block = dev_alloc(so, st);
+  if (!S.block) return fail(WT_ERR_OOM, "wt_build: scratch allocation of %zu bytes failed", so);
+  char* sb = (char*)S.block;
+  uint64_t* h = (uint64_t*)(sb + o_hist);
+  uint64_t* cnt0 = (uint64_t*)(sb + o_cnt);
+  uint32_t* err = (uint32_t*)(sb + o_err);
+  hipLaunchKernelGGL(k_fill_u64, dim3(64), dim3(kBT), 0, st, h, sigma + 1, 0ull);
+  hipLaunchKernelGGL(k_fill_u64, dim3(64), dim3(kBT), 0, st, cnt0, ntiles + 1, 0ull);
+  hipLaunchKernelGGL(k_fill_u64, dim3(1), dim3(64), 0, st, (uint64_t*)err, 8ull, 0ull);
+  WT_HIP(hipGetLastError());
+  // the level-0 tile counts it also makes (bit 0 of the symbols) are not used
+  const HistBufs hb{h, cnt0, err, (uint64_t*)(sb + o_gcnt), (uint64_t*)(sb + o_goff), (uint64_t*)(sb + o_part),
+                    sb + o_seq};
+  if (w == 1) WT_HIP(launch_hist<uint8_t>(d_sym, n, (uint32_t)sigma, 1, hb, st));
+  else if (w == 2) WT_HIP(launch_hist<uint16_t>(d_sym, n, (uint32_t)sigma, 1, hb, st));
+  else WT_HIP(launch_hist<uint32_t>(d_sym, n, (uint32_t)sigma, 1, hb, st));
+  uint32_t bad = 0;
+  WT_HIP(hipMemcpyAsync(hist.data(), h, sigma * 8, hipMemcpyDeviceToHost, st));
+  WT_HIP(hipMemcpyAsync(&bad, err, 4, hipMemcpyDeviceToHost, st));
+  WT_HIP(hipStreamSynchronize(st));
+  if (bad) return fail(WT_ERR_SYMBOL_RANGE, "wt_build: a symbol is >= sigma (%llu)", (unsigned long long)sigma);
+  return WT_OK;
+}
+
 template <typename E, typename EO = E, bool kPos = false>
 hipError_t launch_level(const LevelArgs& a, uint64_t n, hipStream_t st) {
   using TL = Tile<E>;
@@ -348,7 +396,7 @@ hipError_t launch_level_w(const LevelArgs& a, uint64_t n, uint32_t wi, uint32_t 
 }  // namespace
 
 TreePlan plan_tree(uint64_t n, uint32_t w, uint64_t sigma, uint32_t L, uint32_t l2_bits, uint32_t srate,
-                   bool matrix) {
+                   bool matrix, bool huff) {
   TreePlan p{};
   p.n = n;
   p.sigma = sigma;
@@ -378,6 +426,7 @@ TreePlan plan_tree(uint64_t n, uint32_t w, uint64_t sigma, uint32_t L, uint32_t 
   p.off_cum = take((sigma + 1) * sizeof(uint64_t));
   p.off_nodes = take(matrix ? sizeof(NodeQ) : std::max<uint64_t>(p.nheap, 1) * sizeof(NodeQ));
   p.off_wstart = take(matrix ? std::max<uint64_t>(sigma, 1) * sizeof(uint64_t) : 0);
+  p.off_huff = take(huff ? huff_table_bytes(sigma) : 0);
   p.off_bits = take((size_t)L * p.words_per_level * sizeof(uint64_t));
   p.off_l1 = take((size_t)L * p.l1_per_level * sizeof(uint64_t));
   p.off_l2 = take((size_t)L * p.l2_per_level * sizeof(uint16_t));
@@ -432,9 +481,24 @@ wt_status wt::build_tree(const void* d_sym, uint64_t n, uint32_t sym_bytes, uint
   uint32_t L = 0;
   while ((1ull << L) < sigma) ++L;
   const bool matrix = (flags & WT_BUILD_MATRIX) != 0;
-  // a wavelet matrix uses the plain L-bit symbols as codes, whatever sigma
-  const uint32_t pow2 = matrix || (sigma & (sigma - 1)) == 0;
-  const TreePlan P = plan_tree(n, sym_bytes, sigma, L, l2_bits, srate, matrix);
+  const bool huff = (flags & WT_BUILD_HUFFMAN) != 0;
+  if (huff && matrix) return fail(WT_ERR_ARG, "wt_build: WT_BUILD_HUFFMAN and WT_BUILD_MATRIX do not combine");
+  // Huffman-shaped: the counts fix the codes and so the levels; the first level pass then reads the
+  // symbols rewritten as codes of wc bytes
+  HuffCode hc;
+  std::vector<uint64_t> hh;
+  uint32_t wc = sym_bytes;
+  if (huff) {
+    const wt_status hr = huff_prepass(d_sym, n, sym_bytes, sigma, st, hh);
+    if (hr != WT_OK) return hr;
+    huff_code(hh.data(), sigma, hc);
+    L = hc.L;
+    wc = L <= 8 ? 1u : L <= 16 ? 2u : 4u;
+  }
+  // a wavelet matrix uses the plain L-bit symbols as codes, whatever sigma; a Huffman-shaped tree its
+  // canonical codes (no reduced-code step)
+  const uint32_t pow2 = matrix || huff || (sigma & (sigma - 1)) == 0;
+  const TreePlan P = plan_tree(n, wc, sigma, L, l2_bits, srate, matrix, huff);
 
   wt_tree* t = new wt_tree();
   t->n = n;
@@ -445,6 +509,7 @@ wt_status wt::build_tree(const void* d_sym, uint64_t n, uint32_t sym_bytes, uint
   t->srate = srate;
   t->pow2 = pow2;
   t->matrix = matrix ? 1u : 0u;
+  t->huff = huff ? 1u : 0u;
   t->device = dev;
   t->block_bytes = P.total;
   t->block = dev_alloc(P.total, st);
@@ -461,6 +526,11 @@ wt_status wt::build_tree(const void* d_sym, uint64_t n, uint32_t sym_bytes, uint
   t->dev.L2 = (uint16_t*)(base + P.off_l2);
   t->dev.smp = (uint64_t*)(base + P.off_smp);
   t->dev.wstart = matrix ? (uint64_t*)(base + P.off_wstart) : nullptr;
+  if (huff) {
+    t->dev.hcode = (const uint64_t*)(base + P.off_huff);
+    t->dev.hsym = (const uint32_t*)(base + P.off_huff + huff_hsym_off(sigma));
+    t->dev.hdepth = (const uint64_t*)(base + P.off_huff + huff_hdepth_off(sigma));
+  }
   t->bytes_bits = (size_t)L * P.words_per_level * 8;
   t->bytes_l1 = (size_t)L * P.l1_per_level * 8;
   t->bytes_l2 = (size_t)L * P.l2_per_level * 2;
@@ -486,8 +556,11 @@ wt_status wt::build_tree(const void* d_sym, uint64_t n, uint32_t sym_bytes, uint
     so = round_up(so + bytes, 256);
     return o;
   };
-  const size_t o_seq0 = take(L > 1 ? seq_elems * sym_bytes : 0);
-  const size_t o_seq1 = take(L > 2 ? seq_elems * sym_bytes : 0);
+  const size_t o_seq0 = take(L > 1 ? seq_elems * wc : 0);
+  const size_t o_seq1 = take(L > 2 ? seq_elems * wc : 0);
+  const size_t o_enc = take(huff && L > 0 ? seq_elems * wc : 0);  // Huffman: the symbols as codes
+  const size_t o_code_r = take(huff ? hc.m * 4 : 0);
+  const size_t o_cumr = take(huff ? (hc.m + 1) * 8 : 0);
   const size_t o_hist = take(hist_n * 8);
   const uint64_t nchunks = ceil_div(ntiles, kChunkTiles);
   const uint64_t cstride = (ntiles + 1) + (nchunks + 1);  // per level: tile counts, then chunk counts
@@ -500,7 +573,7 @@ wt_status wt::build_tree(const void* d_sym, uint64_t n, uint32_t sym_bytes, uint
   const size_t o_wones = take(WT_MAX_LEVELS * 8);
   const size_t o_ns = take(std::max<uint64_t>(P.nheap, 1) * sizeof(NodeS));
   const size_t o_tfirst = take(ntiles * 4);
-  const uint64_t gcnt_n = hist_gcnt_entries(n, sym_bytes, sigma);
+  const uint64_t gcnt_n = huff ? 0 : hist_gcnt_entries(n, sym_bytes, sigma);
   const size_t o_part = take(std::max<uint64_t>(part_n, ceil_div(gcnt_n, kScanChunk) + 1) * 8);
   const size_t o_gcnt = take(gcnt_n * 8);
   const size_t o_goff = take(gcnt_n * 8);
@@ -531,7 +604,7 @@ wt_status wt::build_tree(const void* d_sym, uint64_t n, uint32_t sym_bytes, uint
   uint32_t wl[WT_MAX_LEVELS + 1];
   bool posm[WT_MAX_LEVELS] = {};
   bool any_pos = false;
-  wl[0] = sym_bytes;
+  wl[0] = wc;
   {
     bool lost = false;
     for (uint32_t l = 0; l < L; ++l) {
@@ -584,10 +657,24 @@ wt_status wt::build_tree(const void* d_sym, uint64_t n, uint32_t sym_bytes, uint
   WT_STEP(prof.end());
 
   WT_STEP(prof.begin("hist", -1));
-  const HistBufs hb{hist, tcnt, err, (uint64_t*)(sb + o_gcnt), (uint64_t*)(sb + o_goff), part, seq[0]};
-  if (sym_bytes == 1) WT_STEP(launch_hist<uint8_t>(d_sym, n, (uint32_t)sigma, L, hb, st));
-  else if (sym_bytes == 2) WT_STEP(launch_hist<uint16_t>(d_sym, n, (uint32_t)sigma, L, hb, st));
-  else WT_STEP(launch_hist<uint32_t>(d_sym, n, (uint32_t)sigma, L, hb, st));
+  if (huff) {
+    // the histogram is known; the code tables go with the tree, the codes in rank order and their
+    // counts to the node walk (host vectors live until the build's final synchronisation)
+    if (sigma) WT_STEP(hipMemcpyAsync(hist, hh.data(), sigma * 8, hipMemcpyHostToDevice, st));
+    WT_STEP(hipMemcpyAsync((void*)t->dev.hcode, hc.hcode.data(), sigma * 8, hipMemcpyHostToDevice, st));
+    if (hc.m) WT_STEP(hipMemcpyAsync((void*)t->dev.hsym, hc.sym.data(), hc.m * 4, hipMemcpyHostToDevice, st));
+    if (!hc.depth.empty())
+      WT_STEP(hipMemcpyAsync((void*)t->dev.hdepth, hc.depth.data(), hc.depth.size() * 8, hipMemcpyHostToDevice, st));
+    if (hc.m > 1) {
+      WT_STEP(hipMemcpyAsync(sb + o_code_r, hc.code_r.data(), hc.m * 4, hipMemcpyHostToDevice, st));
+      WT_STEP(hipMemcpyAsync(sb + o_cumr, hc.cumr.data(), (hc.m + 1) * 8, hipMemcpyHostToDevice, st));
+    }
+  } else {
+    const HistBufs hb{hist, tcnt, err, (uint64_t*)(sb + o_gcnt), (uint64_t*)(sb + o_goff), part, seq[0]};
+    if (sym_bytes == 1) WT_STEP(launch_hist<uint8_t>(d_sym, n, (uint32_t)sigma, L, hb, st));
+    else if (sym_bytes == 2) WT_STEP(launch_hist<uint16_t>(d_sym, n, (uint32_t)sigma, L, hb, st));
+    else WT_STEP(launch_hist<uint32_t>(d_sym, n, (uint32_t)sigma, L, hb, st));
+  }
   WT_STEP(prof.end());
 
   WT_STEP(prof.begin("cum_hist", -1));
@@ -617,8 +704,12 @@ wt_status wt::build_tree(const void* d_sym, uint64_t n, uint32_t sym_bytes, uint
   } else if (L > 0) {
     WT_STEP(prof.begin("nodes", -1));
     const uint32_t nb = (uint32_t)ceil_div(P.nheap, kBT);
-    hipLaunchKernelGGL(k_node_walk, dim3(nb), dim3(kBT), 0, st, (uint32_t)sigma, P.nheap,
-                       (const uint64_t*)t->dev.cum, ntb, z);
+    if (huff)
+      WT_STEP(huff_node_walk(L, hc.m, P.nheap, (const uint32_t*)(sb + o_code_r), (const uint64_t*)(sb + o_cumr), ntb,
+                             z, st));
+    else
+      hipLaunchKernelGGL(k_node_walk, dim3(nb), dim3(kBT), 0, st, (uint32_t)sigma, P.nheap,
+                         (const uint64_t*)t->dev.cum, ntb, z);
     hipLaunchKernelGGL(k_fill_u64, dim3(1), dim3(64), 0, st, z + P.nheap, 1ull, 0ull);
     WT_STEP(hipGetLastError());
     WT_STEP(exclusive_scan_u64(z, P.nheap + 1, zs, part, st));
@@ -634,6 +725,13 @@ wt_status wt::build_tree(const void* d_sym, uint64_t n, uint32_t sym_bytes, uint
       hipLaunchKernelGGL(k_ns_scatter, dim3(nb), dim3(kBT), 0, st, (const NodeB*)ntb, P.nheap, (const uint64_t*)zs, ns);
       WT_STEP(hipGetLastError());
     }
+    WT_STEP(prof.end());
+  }
+
+  if (huff && L > 0) {
+    // symbols -> codes, and the ones per tile of level 0 (code bit L - 1)
+    WT_STEP(prof.begin("encode", -1));
+    WT_STEP(huff_encode(d_sym, sym_bytes, n, (uint32_t)sigma, t->dev.hcode, L, sb + o_enc, wc, tcnt, st));
     WT_STEP(prof.end());
   }
 
@@ -658,7 +756,7 @@ wt_status wt::build_tree(const void* d_sym, uint64_t n, uint32_t sym_bytes, uint
     WT_STEP(hipGetLastError());
     WT_STEP(prof.end());
     LevelArgs a{};
-    a.in = l == 0 ? d_sym : seq[(l - 1) & 1];
+    a.in = l == 0 ? (huff ? (const void*)(sb + o_enc) : d_sym) : seq[(l - 1) & 1];
     a.out = (l + 1 < L) ? seq[l & 1] : nullptr;
     a.bits = t->dev.bits;
     a.L1 = t->dev.L1;
@@ -675,8 +773,8 @@ wt_status wt::build_tree(const void* d_sym, uint64_t n, uint32_t sym_bytes, uint
     a.l2shift = l2shift;
     a.sshift = sshift;
     a.encode = (l == 0 && !pow2) ? 1u : 0u;
-    a.in_vec = (l == 0) ? 0u : 1u;
-    a.in_aligned = (l == 0) ? (((uintptr_t)d_sym & 15u) == 0) : 1u;
+    a.in_vec = (l == 0 && !huff) ? 0u : 1u;
+    a.in_aligned = (l == 0 && !huff) ? (((uintptr_t)d_sym & 15u) == 0) : 1u;
     a.matrix = matrix ? 1u : 0u;
     a.pos_node = posm[l] ? 1u : 0u;
     a.ns = ns;

@@ -18,6 +18,7 @@ struct wt_tree {
   uint64_t n = 0, sigma = 0;
   uint32_t L = 0, w = 0, l2_bits = 512, srate = 4096, pow2 = 1;
   uint32_t matrix = 0;  // 1: wavelet matrix (no node table; dev.wstart holds the symbols' bottom starts)
+  uint32_t huff = 0;    // 1: Huffman-shaped tree (dev.hcode / hsym / hdepth hold its code tables)
   int device = 0;
   void* block = nullptr;  // one allocation holding every device part of the tree
   bool borrowed = false;  // the parts live in a forest's allocation (freed with the forest)
@@ -78,15 +79,20 @@ struct TreePlan {
   uint64_t words_per_level;  // bit words per level (padded to whole tiles + one L2 block, 128 B aligned)
   uint64_t l1_per_level, l2_per_level, smp_per_level;
   uint64_t nheap;  // node table entries: 2^L - 1
-  size_t off_meta, off_cum, off_nodes, off_bits, off_l1, off_l2, off_smp, off_wstart, total;
+  size_t off_meta, off_cum, off_nodes, off_bits, off_l1, off_l2, off_smp, off_wstart, off_huff, total;
 };
 
 // Bytes of one training record of the learned index (the query forms follow the records).
 size_t learn_model_bytes();
 
 // matrix: the parts of a wavelet matrix (no node table; sigma bottom starts instead).
+// huff: room for the code tables of a Huffman-shaped tree (huff_table_bytes(sigma) bytes at off_huff).
 TreePlan plan_tree(uint64_t n, uint32_t w, uint64_t sigma, uint32_t L, uint32_t l2_bits, uint32_t srate,
-                   bool matrix = false);
+                   bool matrix = false, bool huff = false);
+// Code tables of a Huffman-shaped tree: hcode (sigma u64), hsym (sigma u32), hdepth (WT_MAX_LEVELS + 1 u64).
+inline size_t huff_hsym_off(uint64_t sigma) { return ((sigma * 8 + 255) / 256) * 256; }
+inline size_t huff_hdepth_off(uint64_t sigma) { return huff_hsym_off(sigma) + ((sigma * 4 + 255) / 256) * 256; }
+inline size_t huff_table_bytes(uint64_t sigma) { return huff_hdepth_off(sigma) + (WT_MAX_LEVELS + 1) * 8; }
 
 // Bytes of the level sequence one level-kernel block handles; a tile holds kTileBytes / w elements.
 constexpr uint32_t kTileBytes = 16384;

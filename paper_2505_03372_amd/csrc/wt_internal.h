@@ -54,6 +54,12 @@ struct TreeDev {
   uint64_t* cum;  // sigma + 1
   LevelMeta* meta;
   uint64_t* wstart;  // wavelet matrix: first position of every symbol's run below the last level; tree: NULL
+  // Huffman-shaped tree (NULL otherwise): per symbol len << 32 | left-aligned code; the symbol of
+  // every rank; per depth d, F_d << 32 | I_d (the internal nodes of depth d are the prefixes [0, I_d),
+  // the leaf with prefix p >= I_d is rank F_d + p - I_d)
+  const uint64_t* hcode;
+  const uint32_t* hsym;
+  const uint64_t* hdepth;
 };
 
 // ---- small device helpers ----

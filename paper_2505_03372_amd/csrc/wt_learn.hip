@@ -453,6 +453,7 @@ extern "C" wt_status wt_learn_select(wt_tree* t, const wt_learn_opts* opts, wt_s
   clear_error();
   if (!t) return fail(WT_ERR_ARG, "wt_learn_select: tree is NULL");
   if (t->matrix) return fail(WT_ERR_ARG, "wt_learn_select: the learned index needs the tree's node table (not a wavelet matrix)");
+  if (t->huff) return fail(WT_ERR_ARG, "wt_learn_select: the learned index is built for balanced and reduced trees, not Huffman-shaped ones");
   uint32_t epochs = 500, pmax = kPMax;
   float lr = 3e-3f;
   if (opts) {

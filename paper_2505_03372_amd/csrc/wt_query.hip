@@ -24,9 +24,31 @@
 
 namespace wt {
 
+// One traversal of the tree's shape SH: 0 level-wise tree, 1 wavelet matrix, 2 Huffman-shaped tree.
+template <int L2S, int SH>
+__device__ __forceinline__ uint32_t access_sh(const QArgs& a, const LevelMeta* m, uint64_t x) {
+  if constexpr (SH == 1) return wm_access_one<L2S>(a, m, x);
+  else if constexpr (SH == 2) return huff_access_one<L2S>(a, m, x);
+  else return access_one<L2S>(a, m, x);
+}
+
+template <int L2S, int SH>
+__device__ __forceinline__ uint64_t rank_sh(const QArgs& a, const LevelMeta* m, uint32_t c, uint64_t x) {
+  if constexpr (SH == 1) return wm_rank_one<L2S>(a, m, c, x);
+  else if constexpr (SH == 2) return huff_rank_one<L2S>(a, m, c, x);
+  else return rank_one<L2S>(a, m, c, x);
+}
+
+template <int L2S, int SH>
+__device__ __forceinline__ uint64_t select_sh(const QArgs& a, const LevelMeta* m, uint32_t c, uint64_t k) {
+  if constexpr (SH == 1) return wm_select_one<L2S>(a, m, c, k);
+  else if constexpr (SH == 2) return huff_select_one<L2S>(a, m, c, k);
+  else return select_one<L2S>(a, m, c, k);
+}
+
 // sq: NULL, or the queries in binned order: slot j runs query sq[j].id with the arguments stored in sq[j] (its
 // answer written at that index).
-template <int L2S, uint32_t QB, bool WM = false>
+template <int L2S, uint32_t QB, int SH = 0>
 __global__ __launch_bounds__(QB, 8) void k_access(QArgs a, const uint64_t* __restrict__ pos, uint64_t q,
                                                 uint32_t* __restrict__ out, const SQ* __restrict__ sq,
                                                 uint32_t subshift) {
@@ -38,15 +60,15 @@ __global__ __launch_bounds__(QB, 8) void k_access(QArgs a, const uint64_t* __res
       uint32_t jj, c;
       uint64_t x;
       if (local_order<0, QB>(a, sq, q, j0 + threadIdx.x, subshift, s_ord, jj, c, x))
-        out[jj] = WM ? wm_access_one<L2S>(a, s_meta, x) : access_one<L2S>(a, s_meta, x);
+        out[jj] = access_sh<L2S, SH>(a, s_meta, x);
     }
     return;
   }
   for (uint64_t j = xcd_block() * QB + threadIdx.x; j < q; j += (uint64_t)gridDim.x * QB)
-    out[j] = WM ? wm_access_one<L2S>(a, s_meta, pos[j]) : access_one<L2S>(a, s_meta, pos[j]);
+    out[j] = access_sh<L2S, SH>(a, s_meta, pos[j]);
 }
 
-template <int L2S, uint32_t QB, bool WM = false>
+template <int L2S, uint32_t QB, int SH = 0>
 __global__ __launch_bounds__(QB, 8) void k_rank(QArgs a, const uint32_t* __restrict__ sym,
                                               const uint64_t* __restrict__ pos, uint64_t q,
                                               uint64_t* __restrict__ out, const SQ* __restrict__ sq,
@@ -59,15 +81,15 @@ __global__ __launch_bounds__(QB, 8) void k_rank(QArgs a, const uint32_t* __restr
       uint32_t jj, c;
       uint64_t x;
       if (local_order<1, QB>(a, sq, q, j0 + threadIdx.x, subshift, s_ord, jj, c, x))
-        out[jj] = WM ? wm_rank_one<L2S>(a, s_meta, c, x) : rank_one<L2S>(a, s_meta, c, x);
+        out[jj] = rank_sh<L2S, SH>(a, s_meta, c, x);
     }
     return;
   }
   for (uint64_t j = xcd_block() * QB + threadIdx.x; j < q; j += (uint64_t)gridDim.x * QB)
-    out[j] = WM ? wm_rank_one<L2S>(a, s_meta, sym[j], pos[j]) : rank_one<L2S>(a, s_meta, sym[j], pos[j]);
+    out[j] = rank_sh<L2S, SH>(a, s_meta, sym[j], pos[j]);
 }
 
-template <int L2S, uint32_t QB, bool WM = false>
+template <int L2S, uint32_t QB, int SH = 0>
 __global__ __launch_bounds__(QB, 8) void k_select(QArgs a, const uint32_t* __restrict__ sym,
                                                 const uint64_t* __restrict__ kin, uint64_t q,
                                                 uint64_t* __restrict__ out, const SQ* __restrict__ sq,
@@ -80,12 +102,12 @@ __global__ __launch_bounds__(QB, 8) void k_select(QArgs a, const uint32_t* __res
       uint32_t jj, c;
       uint64_t x;
       if (local_order<2, QB>(a, sq, q, j0 + threadIdx.x, subshift, s_ord, jj, c, x))
-        out[jj] = WM ? wm_select_one<L2S>(a, s_meta, c, x) : select_one<L2S>(a, s_meta, c, x);
+        out[jj] = select_sh<L2S, SH>(a, s_meta, c, x);
     }
     return;
   }
   for (uint64_t j = xcd_block() * QB + threadIdx.x; j < q; j += (uint64_t)gridDim.x * QB)
-    out[j] = WM ? wm_select_one<L2S>(a, s_meta, sym[j], kin[j]) : select_one<L2S>(a, s_meta, sym[j], kin[j]);
+    out[j] = select_sh<L2S, SH>(a, s_meta, sym[j], kin[j]);
 }
 
 // ---------------------------------------------------------------- per-kernel timing
@@ -397,22 +419,29 @@ wt_status query_run(const wt_tree* t, int kind, const uint32_t* d_sym, const uin
   const uint32_t grid = query_grid(q, binned ? kQB : kQT);
   uint32_t* o32 = (uint32_t*)d_out;
   uint64_t* o64 = (uint64_t*)d_out;
-#define WT_RUN(QB)                                                                                          \
-  do {                                                                                                      \
-    if (kind == 0) {                                                                                        \
-      if (t->matrix) { WT_DISPATCH_L2_WM(t->l2_bits, QB, true, k_access, a, d_arg, q, o32, sq, sub); }     \
-      else { WT_DISPATCH_L2(t->l2_bits, QB, k_access, a, d_arg, q, o32, sq, sub); }                         \
-    } else if (kind == 1) {                                                                                 \
-      if (t->matrix) { WT_DISPATCH_L2_WM(t->l2_bits, QB, true, k_rank, a, sym, d_arg, q, o64, sq, sub); }  \
-      else { WT_DISPATCH_L2(t->l2_bits, QB, k_rank, a, sym, d_arg, q, o64, sq, sub); }                      \
-    } else {                                                                                                \
-      if (t->matrix) { WT_DISPATCH_L2_WM(t->l2_bits, QB, true, k_select, a, sym, d_arg, q, o64, sq, sub); } \
-      else { WT_DISPATCH_L2(t->l2_bits, QB, k_select, a, sym, d_arg, q, o64, sq, sub); }                    \
-    }                                                                                                       \
+#define WT_RUN_SH(QB, SH)                                                                               \
+  do {                                                                                                  \
+    if (kind == 0) { WT_DISPATCH_L2_SH(t->l2_bits, QB, SH, k_access, a, d_arg, q, o32, sq, sub); }        \
+    else if (kind == 1) { WT_DISPATCH_L2_SH(t->l2_bits, QB, SH, k_rank, a, sym, d_arg, q, o64, sq, sub); } \
+    else { WT_DISPATCH_L2_SH(t->l2_bits, QB, SH, k_select, a, sym, d_arg, q, o64, sq, sub); }             \
+  } while (0)
+#define WT_DISPATCH_SH0(QB)                                                                    \
+  do {                                                                                         \
+    if (kind == 0) { WT_DISPATCH_L2(t->l2_bits, QB, k_access, a, d_arg, q, o32, sq, sub); }      \
+    else if (kind == 1) { WT_DISPATCH_L2(t->l2_bits, QB, k_rank, a, sym, d_arg, q, o64, sq, sub); } \
+    else { WT_DISPATCH_L2(t->l2_bits, QB, k_select, a, sym, d_arg, q, o64, sq, sub); }           \
+  } while (0)
+#define WT_RUN(QB)                       \
+  do {                                   \
+    if (t->matrix) WT_RUN_SH(QB, 1);     \
+    else if (t->huff) WT_RUN_SH(QB, 2);  \
+    else WT_DISPATCH_SH0(QB);            \
   } while (0)
   if (binned) WT_RUN(kQB);
   else WT_RUN(kQT);
 #undef WT_RUN
+#undef WT_RUN_SH
+#undef WT_DISPATCH_SH0
   if (!pre) qprof_end(st);
   if (sb.block) dev_free(sb.block, st);
   if (mapped) dev_free(mapped, st);

@@ -311,6 +311,84 @@ __device__ __forceinline__ uint64_t select_one(const QArgs& a, const LevelMeta* 
   return r - 1;
 }
 
+// ---- Huffman-shaped tree: the same levels and node table, over canonical prefix codes of different
+// lengths (longer codes on the left). A code's bits pick the children; the traversal of an element
+// ends where its prefix becomes a leaf: at depth d the internal nodes are the prefixes [0, I_d), and
+// the leaf with prefix p >= I_d is the symbol of rank F_d + p - I_d (both per depth in hdepth).
+
+// access: top-down until the prefix read so far is a leaf; where both children of the node are
+// leaves the bit alone decides (no rank).
+template <int L2S>
+__device__ __forceinline__ uint32_t huff_access_one(const QArgs& a, const LevelMeta* meta, uint64_t i) {
+  if (i >= a.n) return 0xFFFFFFFFu;
+  if (a.L == 0) return a.d.hsym[0];
+  uint64_t p = 0, x = i;
+  NodeQ nd = node_at(a.d.nodes, 0);
+  for (uint32_t l = 0; l < a.L; ++l) {
+    const LevelMeta& m = meta[l];
+    const uint64_t dep = a.d.hdepth[l + 1];
+    const uint64_t I = (uint32_t)dep, F = dep >> 32;
+    const uint64_t y = nd.start + x;
+    uint32_t bit;
+    if (2 * p >= I) {  // both children are leaves
+      bit = (uint32_t)(a.d.bits[m.bits + (y >> 6)] >> (y & 63)) & 1u;
+      p = 2 * p + bit;
+      return a.d.hsym[F + p - I];
+    }
+    const uint64_t r0 = y - rank1_at<L2S>(a.d, m, y, bit);
+    p = 2 * p + bit;
+    if (p >= I) return a.d.hsym[F + p - I];
+    x = bit ? x - (r0 - nd.r0) : r0 - nd.r0;
+    nd = node_at(a.d.nodes, (2ull << l) - 1 + p);
+  }
+  return 0xFFFFFFFFu;  // not reached: every code ends by level L
+}
+
+// rank: top-down along the symbol's code (as rank_one, the code bits instead of the split rule).
+template <int L2S>
+__device__ __forceinline__ uint64_t huff_rank_one(const QArgs& a, const LevelMeta* meta, uint32_t c, uint64_t i) {
+  if (i > a.n) return ~0ull;
+  if (c >= a.sigma) return 0;
+  const uint64_t hc = a.d.hcode[c];
+  const uint32_t len = (uint32_t)(hc >> 32), code = (uint32_t)hc;
+  if (len == 0) return a.d.cum[c + 1] > a.d.cum[c] ? i : 0;  // the lone symbol of the tree, or absent
+  uint64_t p = 0, x = i;
+  NodeQ nd = node_at(a.d.nodes, 0);
+  for (uint32_t l = 0; l < len; ++l) {
+    if (x == 0) break;
+    const uint32_t b = (code >> (a.L - 1 - l)) & 1u;
+    const uint64_t y = nd.start + x;
+    NodeQ nx = nd;
+    if (l + 1 < len) nx = a.d.nodes[(2ull << l) - 1 + 2 * p + b];
+    uint32_t bit;
+    const uint64_t r0 = y - rank1_at<L2S, true>(a.d, meta[l], y, bit);
+    x = b ? x - (r0 - nd.r0) : r0 - nd.r0;
+    p = 2 * p + b;
+    nd = nx;
+  }
+  return x;
+}
+
+// select: bottom-up from the symbol's leaf (as select_one, the code and its length from the table).
+template <int L2S>
+__device__ __forceinline__ uint64_t huff_select_one(const QArgs& a, const LevelMeta* meta, uint32_t c, uint64_t k) {
+  if (k == 0) return ~0ull;
+  if (c >= a.sigma) return a.n;
+  if (k > a.d.cum[c + 1] - a.d.cum[c]) return a.n;
+  const uint64_t hc = a.d.hcode[c];
+  const uint32_t len = (uint32_t)(hc >> 32), code = (uint32_t)hc;
+  uint64_t r = k;
+  for (int l = (int)len - 1; l >= 0; --l) {
+    const uint64_t p = l ? (uint64_t)(code >> (a.L - l)) : 0ull;
+    const uint32_t b = (code >> (a.L - 1 - l)) & 1u;
+    const NodeQ nd = node_at(a.d.nodes, (1ull << l) - 1 + p);
+    const uint64_t target = b ? (nd.start - nd.r0) + r : nd.r0 + r;
+    const uint64_t at = select_at<L2S>(a.d, meta[l], b, target, a.sshift);
+    r = at - nd.start + 1;
+  }
+  return r - 1;
+}
+
 // ---- wavelet matrix: every level holds all n elements; an element at position p of level l with bit b
 // is at rank0_l(p) (b = 0) or zeros_l + rank1_l(p) (b = 1) in level l + 1, and its bit at level l is
 // bit L-1-l of its symbol. One binary rank or select per level, no node table.
@@ -516,12 +594,12 @@ inline uint32_t query_grid(uint64_t q, uint32_t qb) {
 }
 
 // Launch of KERNEL<L2S, QB, WM> for the tree's |L2| (WM: the wavelet-matrix traversal).
-#define WT_DISPATCH_L2_WM(bits, QB, WM, KERNEL, ...)                                                              \
+#define WT_DISPATCH_L2_SH(bits, QB, SH, KERNEL, ...)                                                              \
   switch (bits) {                                                                                                 \
-    case 256: hipLaunchKernelGGL((KERNEL<8, QB, WM>), dim3(grid), dim3(QB), 0, st, __VA_ARGS__); break;          \
-    case 512: hipLaunchKernelGGL((KERNEL<9, QB, WM>), dim3(grid), dim3(QB), 0, st, __VA_ARGS__); break;          \
-    case 1024: hipLaunchKernelGGL((KERNEL<10, QB, WM>), dim3(grid), dim3(QB), 0, st, __VA_ARGS__); break;        \
-    default: hipLaunchKernelGGL((KERNEL<11, QB, WM>), dim3(grid), dim3(QB), 0, st, __VA_ARGS__); break;          \
+    case 256: hipLaunchKernelGGL((KERNEL<8, QB, SH>), dim3(grid), dim3(QB), 0, st, __VA_ARGS__); break;          \
+    case 512: hipLaunchKernelGGL((KERNEL<9, QB, SH>), dim3(grid), dim3(QB), 0, st, __VA_ARGS__); break;          \
+    case 1024: hipLaunchKernelGGL((KERNEL<10, QB, SH>), dim3(grid), dim3(QB), 0, st, __VA_ARGS__); break;        \
+    default: hipLaunchKernelGGL((KERNEL<11, QB, SH>), dim3(grid), dim3(QB), 0, st, __VA_ARGS__); break;          \
   }
 
 #define WT_DISPATCH_L2(bits, QB, KERNEL, ...)                                                          \
