@@ -27,12 +27,12 @@ in [1, 2^20] (70 % select, 20 % rank, 10 % access) from page-locked host memory,
 saturation and at Poisson arrivals of 0.5, 0.8 and 0.95 of the saturation rate; p50/p99 latency and
 queries/s. (Selects inside mixed batches use the plain sampled search.)
 
-The default run also measures, outside its timed steps, the wavelet matrix of the same sequence
-answering the same queries (key `matrix`), queries from host memory (wt_query_host, 10^5..10^7 of
-each kind, page-locked and pageable arrays; key `host_queries`), the large-alphabet configuration (2^28 u32
-symbols, sigma 2^20; key `large_alpha`) and the rank/select benchmark of plain bit arrays (2^32 bits,
-fill 10/50/90 %, uniform and adversarial placement, |L2| 512, s 16384, 10^8 queries of each of
-rank0/rank1/select0/select1; key `bitvec`).
+The default run also measures, outside its timed steps, the wavelet matrix and the Huffman-shaped tree
+of the same sequence answering the same queries (keys `matrix`, `huffman`), queries from host memory
+(wt_query_host, 10^5..10^7 of each kind, page-locked and pageable arrays; key `host_queries`), the
+large-alphabet configuration (2^28 u32 symbols, sigma 2^20; key `large_alpha`) and the rank/select
+benchmark of plain bit arrays (2^32 bits, fill 10/50/90 %, uniform and adversarial placement, |L2| 512,
+s 16384, 10^8 queries of each of rank0/rank1/select0/select1; key `bitvec`).
 """
 from __future__ import annotations
 
@@ -602,6 +602,8 @@ def main():
     }
     if res["matrix"] is not None:
         line["matrix"] = res["matrix"]
+    if res["huffman"] is not None:
+        line["huffman"] = res["huffman"]
     if res["hostq"] is not None:
         line["host_queries"] = res["hostq"]
     if args.workload == "text_zipf" and not args.no_extra:
@@ -661,7 +663,7 @@ def run_tree(args, torch, wt, workloads, dev, name, steps, warmup, learned, kind
     wt.query_profiling(True)
     use_learned = learned and "select" in kinds
 
-    def step(record, matrix=False):
+    def step(record, shape="tree"):
         # the build is timed by one event pair around the whole wt_build call on its stream (it includes
         # the library's allocations, launch gaps and the final read-back of the level sizes) and by the
         # host wall time of the call; the per-kernel times come from separate builds with the library's
@@ -669,12 +671,13 @@ def run_tree(args, torch, wt, workloads, dev, name, steps, warmup, learned, kind
         eb0, eb1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         eb0.record(stream)
         h0 = time.perf_counter()
-        t = wt.build(S, sigma, l2_bits=args.l2_bits, sample_rate=args.sample_rate, matrix=matrix)
+        t = wt.build(S, sigma, l2_bits=args.l2_bits, sample_rate=args.sample_rate, matrix=shape == "matrix",
+                     huffman=shape == "huffman")
         h1 = time.perf_counter()
         eb1.record(stream)
         evs = {}
         linfo = None
-        if use_learned and not matrix:
+        if use_learned and shape == "tree":
             linfo = t.learn_select()
         for kind, a in kinds.items():
             for variant in (("plain", "learned") if kind == "select" and linfo is not None else ("plain",)):
@@ -696,11 +699,12 @@ def run_tree(args, torch, wt, workloads, dev, name, steps, warmup, learned, kind
             record.append((None, evs, t.info, linfo, qprof, (eb0, eb1), (h1 - h0) * 1e3))
         t.free()
 
-    def kernel_profiles(k, matrix=False):
+    def kernel_profiles(k, shape="tree"):
         # per-kernel durations of k builds made with the library's events (outside the timed steps)
         out = []
         for _ in range(k):
-            t = wt.build(S, sigma, l2_bits=args.l2_bits, sample_rate=args.sample_rate, profile=True, matrix=matrix)
+            t = wt.build(S, sigma, l2_bits=args.l2_bits, sample_rate=args.sample_rate, profile=True,
+                         matrix=shape == "matrix", huffman=shape == "huffman")
             torch.cuda.synchronize()
             out.append(t.profile())
             t.free()
@@ -745,34 +749,44 @@ def run_tree(args, torch, wt, workloads, dev, name, steps, warmup, learned, kind
         t = wt.build(S, sigma, l2_bits=args.l2_bits, sample_rate=args.sample_rate)
         hostq = run_hostq(torch, wt, t, kinds, hostq_sizes)
         t.free()
-    mat = None
-    if matrix_steps:
-        # the wavelet matrix of the same sequence answering the same queries (outside the timed steps)
+    def shape_leg(shape, k_steps):
+        # another shape of the same sequence answering the same queries (outside the timed steps)
         wt.query_profiling(True)
-        step(None, matrix=True)
+        step(None, shape)
         mrecs = []
         m0 = time.perf_counter()
-        for _ in range(matrix_steps):
-            step(mrecs, matrix=True)
+        for _ in range(k_steps):
+            step(mrecs, shape)
         torch.cuda.synchronize()
         m1 = time.perf_counter()
         wt.query_profiling(False)
-        mprofs = kernel_profiles(matrix_steps, matrix=True)
-        mat = {"steps": matrix_steps, "ms_per_step": (m1 - m0) * 1e3 / matrix_steps,
+        mprofs = kernel_profiles(k_steps, shape)
+        res = {"steps": k_steps, "ms_per_step": (m1 - m0) * 1e3 / k_steps,
                "build_ms_median": float(np.median([r[5][0].elapsed_time(r[5][1]) for r in mrecs])),
                "build_kernel_sum_ms_median": float(np.median([sum(p["ms"] for p in pr) for pr in mprofs]))}
-        mat["build_symbols_per_s"] = n / (mat["build_ms_median"] * 1e-3)
+        res["build_symbols_per_s"] = n / (res["build_ms_median"] * 1e-3)
+        inf = mrecs[0][2]
+        res["levels"] = inf["levels"]
+        res["level_bits_total"] = int(sum(inf["level_n"]))
+        res["level_bits_per_symbol"] = res["level_bits_total"] / max(n, 1)
         mk = {}
         for r in mrecs:
             for k, (e0, e1) in r[1].items():
-                mat.setdefault(k + "_ms_median", []).append(e0.elapsed_time(e1))
+                res.setdefault(k + "_ms_median", []).append(e0.elapsed_time(e1))
             for e in r[4]:
                 mk.setdefault(e["kernel"], []).append(e["ms"])
-        for k in [k for k in mat if k.endswith("_ms_median") and isinstance(mat[k], list)]:
-            mat[k] = float(np.median(mat[k]))
-            mat[k.replace("_ms_median", "_queries_per_s")] = q / (mat[k] * 1e-3)
+        for k in [k for k in res if k.endswith("_ms_median") and isinstance(res[k], list)]:
+            res[k] = float(np.median(res[k]))
+            res[k.replace("_ms_median", "_queries_per_s")] = q / (res[k] * 1e-3)
         for k, v in mk.items():
-            mat["kernel_%s_ms_per_step" % k] = float(np.sum(v)) / matrix_steps
+            res["kernel_%s_ms_per_step" % k] = float(np.sum(v)) / k_steps
+        level = [p["ms"] for pr in mprofs for p in pr if p["kernel"] == "level"]
+        res["build_level_kernel_ms_sum_median"] = float(np.median([sum(p["ms"] for p in pr if p["kernel"] == "level")
+                                                                  for pr in mprofs])) if level else 0.0
+        return res
+
+    mat = shape_leg("matrix", matrix_steps) if matrix_steps else None
+    huff = shape_leg("huffman", matrix_steps) if matrix_steps else None
 
     info = recs[0][2]
     level_ms, build_ms, build_ev_ms, build_wall_ms, learn_ms = [], [], [], [], []
@@ -856,7 +870,8 @@ def run_tree(args, torch, wt, workloads, dev, name, steps, warmup, learned, kind
     torch.cuda.empty_cache()
     return {"n": n, "width": width, "sigma": sigma, "q": q, "kinds": list(qms.keys()), "info": info,
             "items": items, "ms_per_step": ms_per_step, "rates": rates, "roofline": roof,
-            "roofline_build": build_roof, "roofline_build_total": build_total, "matrix": mat, "hostq": hostq}
+            "roofline_build": build_roof, "roofline_build_total": build_total, "matrix": mat, "huffman": huff,
+            "hostq": hostq}
 
 
 if __name__ == "__main__":
