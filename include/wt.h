@@ -132,6 +132,41 @@ wt_status wt_set_allocator(wt_alloc_fn alloc_fn, wt_free_fn free_fn, void* ctx);
 wt_status wt_build(const void* d_sym, uint64_t n, uint32_t sym_bytes, uint64_t sigma, const wt_build_opts* opts,
                    wt_stream_t stream, wt_tree** out);
 
+/*
+ * Build from host memory in chunks (the chunked construction the thesis's Conclusion names as its next
+ * step: the copy to the device overlaps the building, and the device never holds the whole sequence, so
+ * sequences larger than what a device-resident build can take are built without unified memory).
+ * The result is the tree wt_build makes from a device copy of the same symbols: every part identical.
+ *   h_sym     host array (page-locked or pageable) of n symbols of sym_bytes bytes (1, 2 or 4).
+ *   sigma     declared alphabet, 1 <= sigma <= WT_MAX_SIGMA (sigma = 0 is not supported here).
+ *   opts      as wt_build (l2_bits, sample_rate, WT_BUILD_WIDE); WT_BUILD_MATRIX and WT_BUILD_HUFFMAN
+ *             are refused.
+ *   chunk     symbols per chunk (0: 2^27), at least 2^16.
+ *   stats     may be NULL.
+ * Two passes over h_sym, each copying chunk i + 1 while chunk i is processed:
+ *   1. counts: the histogram of every chunk is added up (node starts depend on the whole sequence),
+ *      then the node tables and level sizes of the tree;
+ *   2. per chunk: the chunk's own tree, whose every node segment at every level is copied (as a bit run)
+ *      to its place in the tree's level: the node's start plus the node's elements in earlier chunks
+ *      (the level-wise order keeps sequence order inside a node, so a node's elements are its chunks'
+ *      segments one after the other);
+ * then the rank directory and select samples of every level from its bits. Device memory: the tree,
+ * node tables, and a working set of about (12 + 4 sym_bytes) chunk bytes; pageable arrays are staged
+ * through two page-locked buffers of chunk sym_bytes bytes, filled by host threads.
+ * The call waits for the build. Errors: those of wt_build.
+ */
+typedef struct {
+  uint32_t chunks;     /* chunks per pass */
+  uint32_t pinned;     /* 1: h_sym was page-locked (no staging) */
+  float ms_counts;     /* pass 1 (copies and histograms), host clock */
+  float ms_build;      /* pass 2 and the directories, host clock */
+  float ms_total;      /* the whole call */
+  uint64_t work_bytes; /* device memory beside the tree */
+} wt_build_host_stats;
+
+wt_status wt_build_host(const void* h_sym, uint64_t n, uint32_t sym_bytes, uint64_t sigma, const wt_build_opts* opts,
+                        uint64_t chunk, wt_build_host_stats* stats, wt_stream_t stream, wt_tree** out);
+
 /* Release a tree (waits for the device to be idle first). NULL is accepted. */
 wt_status wt_free(wt_tree* t);
 

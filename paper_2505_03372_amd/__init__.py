@@ -40,7 +40,8 @@ ABI_FUNCTIONS = ("wt_set_allocator", "wt_build", "wt_free", "wt_access", "wt_ran
                  "wt_select_learned", "wt_learned_info", "wt_learned_model", "wt_mlp_loss_grad",
                  "wt_build_forest", "wt_forest_tree", "wt_forest_info", "wt_forest_free", "wt_query_mixed",
                  "wt_autotune", "wt_server_create", "wt_server_run", "wt_server_destroy", "wt_query_profiling",
-                 "wt_query_profile", "wt_bv_build", "wt_select_noalloc", "wt_query_host", "wt_query_host_release")
+                 "wt_query_profile", "wt_bv_build", "wt_select_noalloc", "wt_query_host", "wt_query_host_release",
+                 "wt_build_host")
 OP_ACCESS, OP_RANK, OP_SELECT, OP_SELECT_LEARNED = 0, 1, 2, 3
 TUNE_NB, TUNE_SB = 21, 7
 MLP_PARAMS = 49
@@ -157,6 +158,11 @@ class ServeStats(ctypes.Structure):
                 ("lat_p99_s", ctypes.c_double), ("lat_mean_s", ctypes.c_double), ("lat_max_s", ctypes.c_double)]
 
 
+class BuildHostStats(ctypes.Structure):
+    _fields_ = [("chunks", ctypes.c_uint32), ("pinned", ctypes.c_uint32), ("ms_counts", ctypes.c_float),
+                ("ms_build", ctypes.c_float), ("ms_total", ctypes.c_float), ("work_bytes", ctypes.c_uint64)]
+
+
 class ProfEntry(ctypes.Structure):
     _fields_ = [("kernel", ctypes.c_char * 32), ("level", ctypes.c_int32), ("ms", ctypes.c_float)]
 
@@ -175,6 +181,9 @@ def lib():
     vp, u64, u32 = ctypes.c_void_p, ctypes.c_uint64, ctypes.c_uint32
     L.wt_build.restype = ctypes.c_int
     L.wt_build.argtypes = [vp, u64, u32, u64, ctypes.POINTER(BuildOpts), vp, ctypes.POINTER(vp)]
+    L.wt_build_host.restype = ctypes.c_int
+    L.wt_build_host.argtypes = [vp, u64, u32, u64, ctypes.POINTER(BuildOpts), u64, ctypes.POINTER(BuildHostStats), vp,
+                                ctypes.POINTER(vp)]
     L.wt_bv_build.restype = ctypes.c_int
     L.wt_bv_build.argtypes = [vp, u64, ctypes.POINTER(BuildOpts), vp, ctypes.POINTER(vp)]
     L.wt_free.restype = ctypes.c_int
@@ -452,6 +461,22 @@ def build_bitvector(words, n_bits: int, l2_bits: int = 512, sample_rate: int = 4
     _check(lib().wt_bv_build(ctypes.c_void_p(words.data_ptr() if n_bits else 0), n_bits, ctypes.byref(opts),
                              ctypes.c_void_p(_stream_handle(stream)), ctypes.byref(h)))
     return Tree(h.value)
+
+
+def build_host(sym: np.ndarray, sigma: int, chunk: int = 0, l2_bits: int = 512, sample_rate: int = 4096,
+               wide: bool = False, stream=None):
+    """Build the tree of a host array (numpy uint8/uint16/uint32, page-locked or pageable) in chunks of
+    `chunk` symbols (0: 2^27); the same tree as build() of a device copy. Returns (tree, stats)."""
+    widths = {np.dtype(np.uint8): 1, np.dtype(np.uint16): 2, np.dtype(np.uint32): 4}
+    if sym.dtype not in widths or not sym.flags["C_CONTIGUOUS"]:
+        raise TypeError("symbols must be a contiguous uint8, uint16 or uint32 array")
+    opts = BuildOpts(l2_bits, sample_rate, BUILD_WIDE if wide else 0, 0)
+    st = BuildHostStats()
+    h = ctypes.c_void_p(0)
+    _check(lib().wt_build_host(ctypes.c_void_p(sym.ctypes.data if sym.size else 0), sym.size, widths[sym.dtype], sigma,
+                               ctypes.byref(opts), chunk, ctypes.byref(st), ctypes.c_void_p(_stream_handle(stream)),
+                               ctypes.byref(h)))
+    return Tree(h.value), {f: getattr(st, f) for f, _ in BuildHostStats._fields_}
 
 
 def build(sym, sigma: int, l2_bits: int = 512, sample_rate: int = 4096, profile: bool = False, stream=None,

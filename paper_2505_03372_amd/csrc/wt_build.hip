@@ -329,39 +329,20 @@ wt_status huff_prepass(const void* d_sym, uint64_t n, uint32_t w, uint64_t sigma
                        std::vector<uint64_t>& hist) {
   hist.assign(sigma, 0ull);
   if (n == 0) return WT_OK;
-  const uint64_t ntiles = ceil_div(n, tile_elems(w));
-  const uint64_t gcnt_n = hist_gcnt_entries(n, w, sigma);
-  size_t so = 0;
-  auto take = [&](size_t bytes) {
-    const size_t o = so;
-    so = round_up(so + bytes, 256);
-    return o;
-  };
-  const size_t o_hist = take((sigma + 1) * 8);
-  const size_t o_cnt = take((ntiles + 1) * 8);
-  const size_t o_err = take(64);
-  const size_t o_gcnt = take(gcnt_n * 8);
-  const size_t o_goff = take(gcnt_n * 8);
-  const size_t o_part = take((ceil_div(std::max<uint64_t>(gcnt_n, 1), kScanChunk) + 1) * 8);
-  const size_t o_seq = take(gcnt_n ? n * w : 0);
+  const size_t o_err = round_up((sigma + 1) * 8, 256);
+  const size_t o_hs = o_err + 256;
+  const size_t so = o_hs + hist_add_scratch_bytes(n, w, sigma);
   Scratch S;
   S.st = st;
   S.block = dev_alloc(so, st);
   if (!S.block) return fail(WT_ERR_OOM, "wt_build: scratch allocation of %zu bytes failed", so);
   char* sb = (char*)S.block;
-  uint64_t* h = (uint64_t*)(sb + o_hist);
-  uint64_t* cnt0 = (uint64_t*)(sb + o_cnt);
+  uint64_t* h = (uint64_t*)sb;
   uint32_t* err = (uint32_t*)(sb + o_err);
   hipLaunchKernelGGL(k_fill_u64, dim3(64), dim3(kBT), 0, st, h, sigma + 1, 0ull);
-  hipLaunchKernelGGL(k_fill_u64, dim3(64), dim3(kBT), 0, st, cnt0, ntiles + 1, 0ull);
   hipLaunchKernelGGL(k_fill_u64, dim3(1), dim3(64), 0, st, (uint64_t*)err, 8ull, 0ull);
   WT_HIP(hipGetLastError());
-  // the level-0 tile counts it also makes (bit 0 of the symbols) are not used
-  const HistBufs hb{h, cnt0, err, (uint64_t*)(sb + o_gcnt), (uint64_t*)(sb + o_goff), (uint64_t*)(sb + o_part),
-                    sb + o_seq};
-  if (w == 1) WT_HIP(launch_hist<uint8_t>(d_sym, n, (uint32_t)sigma, 1, hb, st));
-  else if (w == 2) WT_HIP(launch_hist<uint16_t>(d_sym, n, (uint32_t)sigma, 1, hb, st));
-  else WT_HIP(launch_hist<uint32_t>(d_sym, n, (uint32_t)sigma, 1, hb, st));
+  WT_HIP(hist_add(d_sym, n, w, sigma, h, err, sb + o_hs, st));
   uint32_t bad = 0;
   WT_HIP(hipMemcpyAsync(hist.data(), h, sigma * 8, hipMemcpyDeviceToHost, st));
   WT_HIP(hipMemcpyAsync(&bad, err, 4, hipMemcpyDeviceToHost, st));
@@ -435,6 +416,69 @@ TreePlan plan_tree(uint64_t n, uint32_t w, uint64_t sigma, uint32_t L, uint32_t 
   return p;
 }
 
+// Scratch of hist_add: tile counts it also makes (not used), and for alphabets above the dense
+// histogram the window counts, their scan and the symbols in window order.
+size_t hist_add_scratch_bytes(uint64_t n, uint32_t w, uint64_t sigma) {
+  const uint64_t ntiles = ceil_div(std::max<uint64_t>(n, 1), tile_elems(w));
+  const uint64_t gcnt_n = hist_gcnt_entries(n, w, sigma);
+  return round_up((ntiles + 1) * 8, 256) + 2 * round_up(gcnt_n * 8, 256) +
+         round_up((ceil_div(std::max<uint64_t>(gcnt_n, 1), kScanChunk) + 1) * 8, 256) +
+         round_up(gcnt_n ? n * w : 0, 256);
+}
+
+hipError_t hist_add(const void* d_sym, uint64_t n, uint32_t w, uint64_t sigma, uint64_t* hist, uint32_t* err,
+                    char* sb, hipStream_t st) {
+  if (n == 0) return hipSuccess;
+  const uint64_t ntiles = ceil_div(n, tile_elems(w));
+  const uint64_t gcnt_n = hist_gcnt_entries(n, w, sigma);
+  const size_t o_gcnt = round_up((ntiles + 1) * 8, 256);
+  const size_t o_goff = o_gcnt + round_up(gcnt_n * 8, 256);
+  const size_t o_part = o_goff + round_up(gcnt_n * 8, 256);
+  const size_t o_seq = o_part + round_up((ceil_div(std::max<uint64_t>(gcnt_n, 1), kScanChunk) + 1) * 8, 256);
+  // the level-0 tile counts the histogram kernels also make (bit 0 of the symbols) are not used
+  const HistBufs hb{hist, (uint64_t*)sb, err, (uint64_t*)(sb + o_gcnt), (uint64_t*)(sb + o_goff),
+                    (uint64_t*)(sb + o_part), sb + o_seq};
+  if (w == 1) return launch_hist<uint8_t>(d_sym, n, (uint32_t)sigma, 1, hb, st);
+  if (w == 2) return launch_hist<uint16_t>(d_sym, n, (uint32_t)sigma, 1, hb, st);
+  return launch_hist<uint32_t>(d_sym, n, (uint32_t)sigma, 1, hb, st);
+}
+
+hipError_t init_levels(const TreePlan& P, LevelMeta* d_meta, LevelMeta* h_meta, hipStream_t st) {
+  InitArgs ia{};
+  ia.L = P.L;
+  for (uint32_t l = 0; l < P.L; ++l) {
+    LevelMeta& mm = ia.meta[l];
+    mm.bits = (uint64_t)l * P.words_per_level;
+    mm.l1 = (uint64_t)l * P.l1_per_level;
+    mm.l2 = (uint64_t)l * P.l2_per_level;
+    mm.smp = (uint64_t)l * P.smp_per_level;
+    mm.smp_cap = P.smp_per_level;
+    h_meta[l] = mm;
+  }
+  hipLaunchKernelGGL(k_init_meta, dim3(1), dim3(64), 0, st, ia, d_meta);
+  return hipGetLastError();
+}
+
+hipError_t fill_u64(uint64_t* p, uint64_t n, uint64_t v, hipStream_t st) {
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_fill_u64, dim3((uint32_t)std::min<uint64_t>(ceil_div(n, kBT), 4096)), dim3(kBT), 0, st, p, n, v);
+  return hipGetLastError();
+}
+
+hipError_t node_tables(uint32_t sigma, uint64_t nheap, const uint64_t* cum, NodeB* ntb, uint64_t* z, uint64_t* zs,
+                       uint64_t* part, NodeQ* nodes, LevelMeta* meta, hipStream_t st) {
+  if (nheap == 0) return hipSuccess;
+  const uint32_t nb = (uint32_t)ceil_div(nheap, kBT);
+  hipLaunchKernelGGL(k_node_walk, dim3(nb), dim3(kBT), 0, st, sigma, nheap, cum, ntb, z);
+  hipLaunchKernelGGL(k_fill_u64, dim3(1), dim3(64), 0, st, z + nheap, 1ull, 0ull);
+  hipError_t he = hipGetLastError();
+  if (he != hipSuccess) return he;
+  he = exclusive_scan_u64(z, nheap + 1, zs, part, st);
+  if (he != hipSuccess) return he;
+  hipLaunchKernelGGL(k_node_final, dim3(nb), dim3(kBT), 0, st, nheap, (const uint64_t*)zs, ntb, nodes, meta);
+  return hipGetLastError();
+}
+
 }  // namespace wt
 
 using namespace wt;
@@ -452,7 +496,7 @@ wt_status wt::check_build_opts(const wt_build_opts* opts) {
 // The build of wt_build for a declared alphabet (sigma >= 1); wt_build (wt_alpha.hip) first extracts
 // the alphabet when sigma = 0.
 wt_status wt::build_tree(const void* d_sym, uint64_t n, uint32_t sym_bytes, uint64_t sigma, const wt_build_opts* opts,
-                         wt_stream_t stream, wt_tree** out) {
+                         wt_stream_t stream, wt_tree** out, NodeB* ntb_out) {
   if (!out) return fail(WT_ERR_ARG, "wt_build: out is NULL");
   *out = nullptr;
   if (sym_bytes != 1 && sym_bytes != 2 && sym_bytes != 4)
@@ -716,6 +760,7 @@ wt_status wt::build_tree(const void* d_sym, uint64_t n, uint32_t sym_bytes, uint
     hipLaunchKernelGGL(k_node_final, dim3(nb), dim3(kBT), 0, st, P.nheap, (const uint64_t*)zs, ntb, t->dev.nodes,
                        t->dev.meta);
     WT_STEP(hipGetLastError());
+    if (ntb_out) WT_STEP(hipMemcpyAsync(ntb_out, ntb, P.nheap * sizeof(NodeB), hipMemcpyDeviceToDevice, st));
     if (any_pos) {
       // the non-empty nodes of every level in position order (z, zs are free again)
       const uint32_t nbf = (uint32_t)ceil_div(P.nheap + 1, kBT);

@@ -134,6 +134,36 @@ __global__ void k_bv_meta(LevelMeta m, LevelMeta* __restrict__ meta) {
   if (threadIdx.x == 0) *meta = m;
 }
 
+// tile ones, their scan, scan partials, and the sigma = 2 histogram and node entry that k_bv_dir also
+// writes (not used for a level of a larger tree)
+size_t bv_directory_scratch_bytes(uint64_t n) {
+  const uint64_t ntiles = ceil_div(std::max<uint64_t>(n, 1), (uint64_t)kBvTileWords * 64);
+  return (2 * (ntiles + 1) + ceil_div(ntiles + 1, kScanChunk) + 1 + 8) * 8;
+}
+
+hipError_t bv_directory(uint64_t* bits, uint64_t* L1, uint16_t* L2, uint64_t* smp, LevelMeta* meta, uint64_t n,
+                        uint64_t smp_cap, uint32_t l2_bits, uint32_t srate, char* scratch, hipStream_t st) {
+  const uint64_t ntiles = ceil_div(n, (uint64_t)kBvTileWords * 64);
+  uint64_t* tile_ones = (uint64_t*)scratch;
+  uint64_t* pre = tile_ones + ntiles + 1;
+  uint64_t* part = pre + ntiles + 1;
+  uint64_t* dummy = part + ceil_div(ntiles + 1, kScanChunk) + 1;
+  uint32_t l2w_shift = 0, sshift = 0;
+  while ((64u << l2w_shift) < l2_bits) ++l2w_shift;
+  while ((1u << sshift) < srate) ++sshift;
+  BvArgs a{bits, L1, L2, smp, meta, dummy, (NodeQ*)(dummy + 3), pre, n, smp_cap, l2w_shift, sshift};
+  if (ntiles == 0) {
+    hipLaunchKernelGGL(k_bv_empty, dim3(1), dim3(64), 0, st, a);
+    return hipGetLastError();
+  }
+  // in place: clears the bits past n and counts the ones of every tile
+  hipLaunchKernelGGL(k_bv_copy, dim3((uint32_t)ntiles), dim3(kBT), 0, st, (const uint64_t*)bits, n, bits, tile_ones);
+  hipError_t he = exclusive_scan_u64(tile_ones, ntiles, pre, part, st);
+  if (he != hipSuccess) return he;
+  hipLaunchKernelGGL(k_bv_dir, dim3((uint32_t)ntiles), dim3(kBT), 0, st, a, ntiles);
+  return hipGetLastError();
+}
+
 }  // namespace wt
 
 using namespace wt;

@@ -47,8 +47,10 @@ wt_status fail(wt_status s, const char* fmt, ...);
 // Validation of the build options (|L2| and s), shared by both build paths (wt_build.hip).
 wt_status check_build_opts(const wt_build_opts* opts);
 // Build of a declared alphabet (wt_build.hip); wt_build itself also handles sigma = 0.
+// ntb_out: when given (2^L - 1 entries of device memory), receives the build node table (node
+// [start, end) per code prefix, heap order) of a level-wise tree.
 wt_status build_tree(const void* d_sym, uint64_t n, uint32_t sym_bytes, uint64_t sigma, const wt_build_opts* opts,
-                     wt_stream_t stream, wt_tree** out);
+                     wt_stream_t stream, wt_tree** out, NodeB* ntb_out = nullptr);
 // Extracted alphabets (wt_alpha.hip): query symbols as codes (*mapped = d_sym when the tree has a
 // declared alphabet; otherwise a q-entry buffer, returned in *scratch for the caller to free after the
 // traversal; with `buf` given, that q-entry buffer is used and nothing is allocated) and access answers
@@ -93,6 +95,30 @@ TreePlan plan_tree(uint64_t n, uint32_t w, uint64_t sigma, uint32_t L, uint32_t 
 inline size_t huff_hsym_off(uint64_t sigma) { return ((sigma * 8 + 255) / 256) * 256; }
 inline size_t huff_hdepth_off(uint64_t sigma) { return huff_hsym_off(sigma) + ((sigma * 4 + 255) / 256) * 256; }
 inline size_t huff_table_bytes(uint64_t sigma) { return huff_hdepth_off(sigma) + (WT_MAX_LEVELS + 1) * 8; }
+
+// Host memory: page-locked (hipHostMalloc or registered with HIP), and a memcpy split over a few
+// threads (a single thread does not reach the host's memory bandwidth). wt_hostq.hip.
+bool is_pinned(const void* p);
+void par_copy(void* dst, const void* src, size_t bytes);
+
+// Build steps shared by the device build and the build from host memory (wt_build.hip, wt_bv.hip).
+// hist[c] += count of c in d_sym[0, n), *err set when a symbol is >= sigma; scratch of
+// hist_add_scratch_bytes(n, w, sigma) bytes.
+size_t hist_add_scratch_bytes(uint64_t n, uint32_t w, uint64_t sigma);
+hipError_t hist_add(const void* d_sym, uint64_t n, uint32_t w, uint64_t sigma, uint64_t* hist, uint32_t* err,
+                    char* scratch, hipStream_t st);
+// Level metadata (offsets of every level's parts, counts cleared) on the device and the host.
+hipError_t init_levels(const TreePlan& P, LevelMeta* d_meta, LevelMeta* h_meta, hipStream_t st);
+hipError_t fill_u64(uint64_t* p, uint64_t n, uint64_t v, hipStream_t st);
+// Node tables of a level-wise tree from the cumulative histogram: build entries, query entries, and
+// the level sizes (meta[l].n). z, zs: nheap + 1 entries; part: scan partials.
+hipError_t node_tables(uint32_t sigma, uint64_t nheap, const uint64_t* cum, NodeB* ntb, uint64_t* z, uint64_t* zs,
+                       uint64_t* part, NodeQ* nodes, LevelMeta* meta, hipStream_t st);
+// Rank directory and select samples of one level from its bits (bits past n cleared); sets meta->n and
+// meta->ones. scratch: bv_directory_scratch_bytes(n) bytes.
+size_t bv_directory_scratch_bytes(uint64_t n);
+hipError_t bv_directory(uint64_t* bits, uint64_t* L1, uint16_t* L2, uint64_t* smp, LevelMeta* meta, uint64_t n,
+                        uint64_t smp_cap, uint32_t l2_bits, uint32_t srate, char* scratch, hipStream_t st);
 
 // Bytes of the level sequence one level-kernel block handles; a tile holds kTileBytes / w elements.
 constexpr uint32_t kTileBytes = 16384;

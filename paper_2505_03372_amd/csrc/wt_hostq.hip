@@ -29,9 +29,6 @@
 #include "wt_query_dev.h"
 
 namespace wt {
-namespace {
-
-constexpr uint64_t kDefaultChunk = 1ull << 22;
 
 bool is_pinned(const void* p) {
   if (!p) return true;
@@ -62,6 +59,10 @@ void par_copy(void* dst, const void* src, size_t bytes) {
   std::memcpy(dst, src, std::min(bytes, per));
   for (auto& x : th) x.join();
 }
+
+namespace {
+
+constexpr uint64_t kDefaultChunk = 1ull << 22;
 
 // Device buffers of one call: two slots and the shared scratch.
 struct Slots {

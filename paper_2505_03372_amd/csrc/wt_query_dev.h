@@ -111,7 +111,6 @@ __device__ __forceinline__ uint32_t block_select(const uint64_t* __restrict__ wp
 template <int L2S, bool kLine = true>
 __device__ __forceinline__ uint64_t select_at(const TreeDev& d, const LevelMeta& m, uint32_t b, uint64_t k,
                                               uint32_t sshift) {
-  constexpr int L2W = (1 << L2S) / 64;
   constexpr uint64_t kPer = kL1Bits >> L2S;  // L2 blocks per L1 block
   const uint64_t nl = m.n;
   const uint64_t cntb = b ? m.ones : nl - m.ones;
