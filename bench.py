@@ -30,6 +30,8 @@ queries/s. (Selects inside mixed batches use the plain sampled search.)
 The default run also measures, outside its timed steps, the wavelet matrix and the Huffman-shaped tree
 of the same sequence answering the same queries (keys `matrix`, `huffman`), queries from host memory
 (wt_query_host, 10^5..10^7 of each kind, page-locked and pageable arrays; key `host_queries`), the
+chunked build from host memory against copy-then-build (wt_build_host, 2^27-symbol chunks; key
+`host_build`), the
 large-alphabet configuration (2^28 u32 symbols, sigma 2^20; key `large_alpha`) and the rank/select
 benchmark of plain bit arrays (2^32 bits, fill 10/50/90 %, uniform and adversarial placement, |L2| 512,
 s 16384, 10^8 queries of each of rank0/rank1/select0/select1; key `bitvec`).
@@ -458,6 +460,57 @@ def run_bitvec(torch, wt, workloads, dev, n_bits: int, nq: int, reps: int = 3) -
                                  "note": "64 B (one L2 block of bits) per query, random lines"}}
 
 
+def run_host_build(torch, wt, S_host, sigma, dev, chunk: int = 1 << 27, reps: int = 3) -> dict:
+    """wt_build_host (the chunked build from host memory) from page-locked and pageable arrays, against
+    copying the whole sequence to the device and building there (median host-clock ms of `reps` calls
+    after one warm-up each)."""
+    n = int(S_host.size)
+    pin = torch.empty(n, dtype=getattr(torch, str(S_host.dtype)), pin_memory=True)
+    pin.numpy()[:] = S_host
+    res = {"n": n, "sym_bytes": int(S_host.dtype.itemsize), "chunk": chunk}
+    for name, arr, two in (("pinned", pin.numpy(), False), ("pageable", S_host, False),
+                           ("pinned_two_pass", pin.numpy(), True)):
+        ms, cnt, bld, work = [], [], [], 0
+        for r in range(reps + 1):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            t, st = wt.build_host(arr, sigma, chunk=chunk, two_pass=two)
+            t1 = time.perf_counter()
+            t.free()
+            if r:
+                ms.append((t1 - t0) * 1e3)
+                cnt.append(st["ms_counts"])
+                bld.append(st["ms_build"])
+                work = st["work_bytes"]
+                res["chunks"] = st["chunks"]
+                res[name + "_passes"] = st["passes"]
+        res[name + "_ms"] = float(np.median(ms))
+        res[name + "_counts_pass_ms"] = float(np.median(cnt))
+        res[name + "_build_pass_ms"] = float(np.median(bld))
+        res[name + "_symbols_per_s"] = n / (res[name + "_ms"] * 1e-3)
+        res[name + "_work_bytes"] = int(work)
+    cp, cb = [], []
+    for r in range(reps + 1):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        d = pin.to(dev, non_blocking=True)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        t = wt.build(d, sigma)
+        t2 = time.perf_counter()
+        t.free()
+        del d
+        if r:
+            cp.append((t1 - t0) * 1e3)
+            cb.append((t2 - t0) * 1e3)
+    res["copy_ms"] = float(np.median(cp))
+    res["copy_GB_per_s"] = n * res["sym_bytes"] / (res["copy_ms"] * 1e-3) / 1e9
+    res["copy_then_device_build_ms"] = float(np.median(cb))
+    res["pinned_vs_copy_then_build"] = res["copy_then_device_build_ms"] / res["pinned_ms"]
+    del pin
+    return res
+
+
 def run_hostq(torch, wt, t, kinds, sizes, reps: int = 3) -> dict:
     """Queries from host memory (wt_query_host): for every query kind and batch size, the end-to-end time
     of the call (copies in, kernels, copies out) with page-locked and with pageable host arrays, beside
@@ -576,7 +629,8 @@ def main():
     res = run_tree(args, torch, wt, workloads, dev, args.workload, args.steps, args.warmup,
                    learned=not args.no_learned, kinds_wanted=("access", "rank", "select"),
                    matrix_steps=0 if args.no_extra else 3,
-                   hostq_sizes=() if args.no_extra else tuple(10 ** e for e in range(5, args.hostq_max_log10 + 1)))
+                   hostq_sizes=() if args.no_extra else tuple(10 ** e for e in range(5, args.hostq_max_log10 + 1)),
+                   host_build=not args.no_extra)
     n, width, sigma, q = res["n"], res["width"], res["sigma"], res["q"]
     ms_per_step = res["ms_per_step"]
     line = {
@@ -606,6 +660,8 @@ def main():
         line["huffman"] = res["huffman"]
     if res["hostq"] is not None:
         line["host_queries"] = res["hostq"]
+    if res["host_build"] is not None:
+        line["host_build"] = res["host_build"]
     if args.workload == "text_zipf" and not args.no_extra:
         # the large-alphabet configuration (2^28 u32 symbols, sigma 2^20, 2^24 rank + 2^24 select), measured
         # in the same run after the main workload, outside its timed steps
@@ -637,7 +693,7 @@ def main():
 
 
 def run_tree(args, torch, wt, workloads, dev, name, steps, warmup, learned, kinds_wanted, matrix_steps=0,
-             hostq_sizes=()):
+             hostq_sizes=(), host_build=False):
     """Timed steps of one single-tree workload: build (+ learned-index training) + queries + free."""
     idx, n, width, sigma, q = workloads.CONFIGS[name]
     print("# generating workload %s: n=%d width=%d sigma=%d q=%d" % (name, n, width, sigma, q),
@@ -655,6 +711,7 @@ def run_tree(args, torch, wt, workloads, dev, name, steps, warmup, learned, kind
             "rank": torch.empty(q, dtype=torch.uint64, device=dev),
             "select": torch.empty(q, dtype=torch.uint64, device=dev),
             "select_learned": torch.empty(q, dtype=torch.uint64, device=dev)}
+    S_host = wl.S if host_build else None
     del wl
     torch.cuda.synchronize()
     print("# workload resident in HBM", file=sys.stderr, flush=True)
@@ -871,7 +928,7 @@ def run_tree(args, torch, wt, workloads, dev, name, steps, warmup, learned, kind
     return {"n": n, "width": width, "sigma": sigma, "q": q, "kinds": list(qms.keys()), "info": info,
             "items": items, "ms_per_step": ms_per_step, "rates": rates, "roofline": roof,
             "roofline_build": build_roof, "roofline_build_total": build_total, "matrix": mat, "huffman": huff,
-            "hostq": hostq}
+            "hostq": hostq, "host_build": run_host_build(torch, wt, S_host, sigma, dev) if host_build else None}
 
 
 if __name__ == "__main__":

@@ -139,29 +139,34 @@ wt_status wt_build(const void* d_sym, uint64_t n, uint32_t sym_bytes, uint64_t s
  * The result is the tree wt_build makes from a device copy of the same symbols: every part identical.
  *   h_sym     host array (page-locked or pageable) of n symbols of sym_bytes bytes (1, 2 or 4).
  *   sigma     declared alphabet, 1 <= sigma <= WT_MAX_SIGMA (sigma = 0 is not supported here).
- *   opts      as wt_build (l2_bits, sample_rate, WT_BUILD_WIDE); WT_BUILD_MATRIX and WT_BUILD_HUFFMAN
- *             are refused.
+ *   opts      as wt_build (l2_bits, sample_rate, WT_BUILD_WIDE, and WT_BUILD_HOST_TWO_PASS below);
+ *             WT_BUILD_MATRIX and WT_BUILD_HUFFMAN are refused.
  *   chunk     symbols per chunk (0: 2^27), at least 2^16.
  *   stats     may be NULL.
- * Two passes over h_sym, each copying chunk i + 1 while chunk i is processed:
- *   1. counts: the histogram of every chunk is added up (node starts depend on the whole sequence),
- *      then the node tables and level sizes of the tree;
- *   2. per chunk: the chunk's own tree, whose every node segment at every level is copied (as a bit run)
- *      to its place in the tree's level: the node's start plus the node's elements in earlier chunks
- *      (the level-wise order keeps sequence order inside a node, so a node's elements are its chunks'
- *      segments one after the other);
- * then the rank directory and select samples of every level from its bits. Device memory: the tree,
- * node tables, and a working set of about (12 + 4 sym_bytes) chunk bytes; pageable arrays are staged
- * through two page-locked buffers of chunk sym_bytes bytes, filled by host threads.
- * The call waits for the build. Errors: those of wt_build.
+ * Every chunk is copied to the device while the previous one is processed, and gets its own tree (the
+ * device build). The level-wise order keeps sequence order inside a node, so a node's elements at a
+ * level are its segments in the chunks' trees one after the other: each segment is copied, as a bit
+ * run, to the node's start (known from the whole sequence's histogram) plus the node's elements in the
+ * earlier chunks. Then the rank directory and select samples of every level are made from its bits.
+ *   One pass (default, when device memory allows): the chunks' trees (about the tree's size in all) are
+ *   kept until the last chunk has added its counts, then placed.
+ *   Two passes (WT_BUILD_HOST_TWO_PASS, or when the chunks' trees would not fit): a first pass over
+ *   h_sym adds up the counts; the second builds each chunk's tree and places it at once, so the device
+ *   holds the tree, its node tables and a working set of a few chunks only, at the price of copying
+ *   h_sym twice.
+ * Pageable arrays are staged through two page-locked buffers of chunk sym_bytes bytes, filled by host
+ * threads. The call waits for the build. Errors: those of wt_build.
  */
+#define WT_BUILD_HOST_TWO_PASS 16u
+
 typedef struct {
   uint32_t chunks;     /* chunks per pass */
   uint32_t pinned;     /* 1: h_sym was page-locked (no staging) */
-  float ms_counts;     /* pass 1 (copies and histograms), host clock */
-  float ms_build;      /* pass 2 and the directories, host clock */
+  uint32_t passes;     /* 1 or 2 (see above) */
+  float ms_counts;     /* until the counts of the whole sequence are known (the first pass), host clock */
+  float ms_build;      /* the rest: placement (and the second pass) and the directories, host clock */
   float ms_total;      /* the whole call */
-  uint64_t work_bytes; /* device memory beside the tree */
+  uint64_t work_bytes; /* device memory beside the tree, largest */
 } wt_build_host_stats;
 
 wt_status wt_build_host(const void* h_sym, uint64_t n, uint32_t sym_bytes, uint64_t sigma, const wt_build_opts* opts,

@@ -29,6 +29,7 @@ BUILD_PROFILE = 1
 BUILD_MATRIX = 2
 BUILD_WIDE = 4
 BUILD_HUFFMAN = 8
+BUILD_HOST_TWO_PASS = 16
 MAX_LEVELS = 24
 MAX_SIGMA = 1 << 24
 ACCESS_INVALID = 0xFFFFFFFF
@@ -159,8 +160,9 @@ class ServeStats(ctypes.Structure):
 
 
 class BuildHostStats(ctypes.Structure):
-    _fields_ = [("chunks", ctypes.c_uint32), ("pinned", ctypes.c_uint32), ("ms_counts", ctypes.c_float),
-                ("ms_build", ctypes.c_float), ("ms_total", ctypes.c_float), ("work_bytes", ctypes.c_uint64)]
+    _fields_ = [("chunks", ctypes.c_uint32), ("pinned", ctypes.c_uint32), ("passes", ctypes.c_uint32),
+                ("ms_counts", ctypes.c_float), ("ms_build", ctypes.c_float), ("ms_total", ctypes.c_float),
+                ("work_bytes", ctypes.c_uint64)]
 
 
 class ProfEntry(ctypes.Structure):
@@ -464,13 +466,14 @@ def build_bitvector(words, n_bits: int, l2_bits: int = 512, sample_rate: int = 4
 
 
 def build_host(sym: np.ndarray, sigma: int, chunk: int = 0, l2_bits: int = 512, sample_rate: int = 4096,
-               wide: bool = False, stream=None):
+               wide: bool = False, two_pass: bool = False, stream=None):
     """Build the tree of a host array (numpy uint8/uint16/uint32, page-locked or pageable) in chunks of
-    `chunk` symbols (0: 2^27); the same tree as build() of a device copy. Returns (tree, stats)."""
+    `chunk` symbols (0: 2^27); the same tree as build() of a device copy. two_pass: copy the array twice
+    and keep only a few chunks on the device. Returns (tree, stats)."""
     widths = {np.dtype(np.uint8): 1, np.dtype(np.uint16): 2, np.dtype(np.uint32): 4}
     if sym.dtype not in widths or not sym.flags["C_CONTIGUOUS"]:
         raise TypeError("symbols must be a contiguous uint8, uint16 or uint32 array")
-    opts = BuildOpts(l2_bits, sample_rate, BUILD_WIDE if wide else 0, 0)
+    opts = BuildOpts(l2_bits, sample_rate, (BUILD_WIDE if wide else 0) | (BUILD_HOST_TWO_PASS if two_pass else 0), 0)
     st = BuildHostStats()
     h = ctypes.c_void_p(0)
     _check(lib().wt_build_host(ctypes.c_void_p(sym.ctypes.data if sym.size else 0), sym.size, widths[sym.dtype], sigma,

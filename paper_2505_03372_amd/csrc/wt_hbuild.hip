@@ -6,15 +6,16 @@
 // stably sorted by the code bits above it), so the elements of node N at level l are the elements of
 // N in chunk 0, then those in chunk 1, and so on. A chunk's own tree holds, at level l, the segment
 // of every node N as one run of bits; in the tree of the whole sequence that run starts at the node's
-// start plus the elements of N in the earlier chunks. So:
-//   pass 1  per chunk: copy, histogram added up; then the cumulative histogram, node tables and level
-//           sizes of the whole tree (Section 5: node starts from the histogram alone);
-//   pass 2  per chunk: copy, the chunk's tree (the device build), every node segment of every level
-//           or-ed into place as a bit run (one wave per 4096 bits, 64 per lane, bit-unaligned on both
-//           sides), the node's running count advanced;
-//   then    per level, the rank directory and select samples from the bits (Sections 4.1, 4.2).
-// The next chunk's copy is in flight while a chunk is processed (two device slots; pageable arrays go
-// through two page-locked staging buffers filled by host threads).
+// start plus the elements of N in the earlier chunks. Node starts come from the histogram alone
+// (Section 5), so the counts of the whole sequence must be known before a segment is placed:
+//   one pass   per chunk: copy, the chunk's tree (the device build), its counts added up; then the
+//              node tables and level sizes of the whole tree, and every chunk's segments placed;
+//   two passes per chunk: copy, counts added up; node tables; then per chunk: copy, the chunk's tree,
+//              its segments placed at once (the device holds a few chunks only);
+// placement: or-ed in as bit runs, one wave per 4096 bits of a segment, 64 per lane, bit-unaligned on
+// both sides, the node's running count advanced; then per level the rank directory and select samples
+// from the bits (Sections 4.1, 4.2). The next chunk's copy is in flight while a chunk is processed (two
+// device slots; pageable arrays go through two page-locked staging buffers filled by host threads).
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -100,11 +101,19 @@ struct HostBuild {
   hipEvent_t copied[2] = {nullptr, nullptr}, freed[2] = {nullptr, nullptr};
   char* stage[2] = {nullptr, nullptr};
   void* work = nullptr;
+  void* pool = nullptr;  // one pass: every chunk's build node table
   hipStream_t st = nullptr;
   wt_tree* t = nullptr;  // the tree until it is handed out
+  std::vector<wt_tree*> cts;  // one pass: the chunks' trees until they are placed
   ~HostBuild() {
     if (cs) (void)hipStreamSynchronize(cs);
     if (st) (void)hipStreamSynchronize(st);
+    for (wt_tree* ct : cts) {
+      if (!ct) continue;
+      dev_free(ct->block, st);
+      delete ct;
+    }
+    if (pool) dev_free(pool, st);
     for (int k = 0; k < 2; ++k) {
       if (copied[k]) (void)hipEventDestroy(copied[k]);
       if (freed[k]) (void)hipEventDestroy(freed[k]);
@@ -265,7 +274,53 @@ extern "C" wt_status wt_build_host(const void* h_sym, uint64_t n, uint32_t sym_b
     return hipEventRecord(H.copied[k], H.cs);
   };
 
-  // ---- pass 1: counts
+  // One pass keeps every chunk's tree (and its build node table) until the counts are complete: chosen
+  // when that fits in what the device has free, with room for one chunk build's scratch.
+  wt_build_opts copts{};
+  copts.l2_bits = l2_bits;
+  copts.sample_rate = srate;
+  copts.flags = flags & WT_BUILD_WIDE;
+  const size_t pool_bytes = (size_t)nch * std::max<uint64_t>(nheap, 1) * sizeof(NodeB);
+  size_t keep_bytes = pool_bytes;
+  for (uint64_t c = 0; c < nch; ++c) keep_bytes += plan_tree(csize(c), sym_bytes, sigma, L, l2_bits, srate).total;
+  bool one_pass = !(flags & WT_BUILD_HOST_TWO_PASS) && L > 0;
+  if (one_pass) {
+    size_t fr = 0, tot = 0;
+    WT_HIP(hipMemGetInfo(&fr, &tot));
+    const size_t build_scratch = (size_t)chunk * sym_bytes * 4 + (size_t)nheap * 96 + (64u << 20);
+    one_pass = keep_bytes + build_scratch < fr;
+  }
+  if (one_pass) {
+    H.pool = dev_alloc(pool_bytes, st);
+    if (!H.pool) one_pass = false;
+  }
+  NodeB* pool = (NodeB*)H.pool;
+
+  // Places every node segment of the chunk tree ct (build node table ntb_c) into the tree's levels.
+  uint64_t chunk_tree_bytes = 0;
+  auto place = [&](const wt_tree* ct, const NodeB* ntb_c) -> hipError_t {
+    hipError_t he = hipSuccess;
+    for (uint32_t l = 0; l < L && he == hipSuccess; ++l) {
+      const uint64_t ncl = ct->hmeta[l].n;
+      if (ncl == 0) continue;
+      const uint64_t np = 1ull << l, hb = np - 1;
+      hipLaunchKernelGGL(k_place_plan, dim3((uint32_t)ceil_div(np + 1, kBT)), dim3(kBT), 0, st, ntb_c + hb,
+                         (const NodeB*)(ntb_g + hb), np, done + hb, psrc, plen, pdst, pcs);
+      he = hipGetLastError();
+      if (he == hipSuccess) he = exclusive_scan_u64(pcs, np + 1, poff, part, st);
+      if (he == hipSuccess) {
+        const uint64_t waves = std::min<uint64_t>(ceil_div(ncl, kPieceBits) + np, 1ull << 16);
+        hipLaunchKernelGGL(k_place, dim3((uint32_t)ceil_div(waves, kBT / 64)), dim3(kBT), 0, st,
+                           (const uint64_t*)(ct->dev.bits + ct->hmeta[l].bits), t->dev.bits + t->hmeta[l].bits,
+                           (const uint64_t*)poff, np, (const uint64_t*)psrc, (const uint64_t*)plen,
+                           (const uint64_t*)pdst);
+        he = hipGetLastError();
+      }
+    }
+    return he;
+  };
+
+  // ---- first pass: counts (and, in one pass, the chunks' trees)
   WT_HIP(fill_u64(hist, sigma + 1, 0ull, st));
   WT_HIP(fill_u64((uint64_t*)err, 8, 0ull, st));
   WT_HIP(fill_u64(done, nheap + 1, 0ull, st));
@@ -278,6 +333,13 @@ extern "C" wt_status wt_build_host(const void* h_sym, uint64_t n, uint32_t sym_b
     if (c + 1 < nch) WT_HIP(upload(c + 1, k ^ 1));
     WT_HIP(hipStreamWaitEvent(st, H.copied[k], 0));
     WT_HIP(hist_add(in[k], csize(c), sym_bytes, sigma, hist, err, wb + o_hs, st));
+    if (one_pass) {
+      wt_tree* ct = nullptr;
+      const wt_status brc = build_tree(in[k], csize(c), sym_bytes, sigma, &copts, st, &ct, pool + c * nheap);
+      if (brc != WT_OK) return brc;
+      H.cts.push_back(ct);
+      chunk_tree_bytes += ct->block_bytes;
+    }
     WT_HIP(hipEventRecord(H.freed[k], st));
   }
   uint32_t bad = 0;
@@ -291,14 +353,18 @@ extern "C" wt_status wt_build_host(const void* h_sym, uint64_t n, uint32_t sym_b
   WT_HIP(hipStreamSynchronize(st));
   const float ms_counts = ms_since(t_start);
 
-  // ---- pass 2: every chunk's tree, its node segments placed
+  // ---- placement (one pass: the kept trees; two passes: a second pass over the chunks)
   const auto t_build = std::chrono::steady_clock::now();
-  wt_build_opts copts{};
-  copts.l2_bits = l2_bits;
-  copts.sample_rate = srate;
-  copts.flags = flags & WT_BUILD_WIDE;
-  uint64_t chunk_tree_bytes = 0;
-  if (L > 0) {
+  if (one_pass) {
+    for (uint64_t c = 0; c < nch; ++c) {
+      const hipError_t he = place(H.cts[c], pool + c * nheap);
+      if (he != hipSuccess) return fail(WT_ERR_HIP, "wt_build_host: placement: %s", hipGetErrorString(he));
+      dev_free(H.cts[c]->block, st);
+      delete H.cts[c];
+      H.cts[c] = nullptr;
+    }
+    chunk_tree_bytes += pool_bytes;
+  } else if (L > 0) {
     WT_HIP(upload(0, 0));
     for (uint64_t c = 0; c < nch; ++c) {
       const int k = (int)(c & 1);
@@ -309,34 +375,17 @@ extern "C" wt_status wt_build_host(const void* h_sym, uint64_t n, uint32_t sym_b
       if (brc != WT_OK) return brc;
       WT_HIP(hipEventRecord(H.freed[k], st));
       chunk_tree_bytes = std::max<uint64_t>(chunk_tree_bytes, ct->block_bytes);
-      hipError_t he = hipSuccess;
-      for (uint32_t l = 0; l < L && he == hipSuccess; ++l) {
-        const uint64_t ncl = ct->hmeta[l].n;
-        if (ncl == 0) continue;
-        const uint64_t np = 1ull << l, hb = np - 1;
-        hipLaunchKernelGGL(k_place_plan, dim3((uint32_t)ceil_div(np + 1, kBT)), dim3(kBT), 0, st,
-                           (const NodeB*)(ntb_c + hb), (const NodeB*)(ntb_g + hb), np, done + hb, psrc, plen, pdst, pcs);
-        he = hipGetLastError();
-        if (he == hipSuccess) he = exclusive_scan_u64(pcs, np + 1, poff, part, st);
-        if (he == hipSuccess) {
-          const uint64_t waves = std::min<uint64_t>(ceil_div(ncl, kPieceBits) + np, 1ull << 16);
-          hipLaunchKernelGGL(k_place, dim3((uint32_t)ceil_div(waves, kBT / 64)), dim3(kBT), 0, st,
-                             (const uint64_t*)(ct->dev.bits + ct->hmeta[l].bits), t->dev.bits + t->hmeta[l].bits,
-                             (const uint64_t*)poff, np, (const uint64_t*)psrc, (const uint64_t*)plen,
-                             (const uint64_t*)pdst);
-          he = hipGetLastError();
-        }
-      }
+      const hipError_t he = place(ct, ntb_c);
       dev_free(ct->block, st);
       delete ct;
       if (he != hipSuccess) return fail(WT_ERR_HIP, "wt_build_host: placement: %s", hipGetErrorString(he));
     }
-    // ---- rank directory and select samples of every level
-    for (uint32_t l = 0; l < L; ++l) {
-      const LevelMeta& m = t->hmeta[l];
-      WT_HIP(bv_directory(t->dev.bits + m.bits, t->dev.L1 + m.l1, t->dev.L2 + m.l2, t->dev.smp + m.smp, t->dev.meta + l,
-                          rb[l].n, m.smp_cap, l2_bits, srate, wb + o_dir, st));
-    }
+  }
+  // ---- rank directory and select samples of every level
+  for (uint32_t l = 0; l < L; ++l) {
+    const LevelMeta& m = t->hmeta[l];
+    WT_HIP(bv_directory(t->dev.bits + m.bits, t->dev.L1 + m.l1, t->dev.L2 + m.l2, t->dev.smp + m.smp, t->dev.meta + l,
+                        rb[l].n, m.smp_cap, l2_bits, srate, wb + o_dir, st));
   }
   WT_HIP(hipMemcpyAsync(rb.data(), t->dev.meta, sizeof(LevelMeta) * WT_MAX_LEVELS, hipMemcpyDeviceToHost, st));
   WT_HIP(hipStreamSynchronize(st));
@@ -344,6 +393,7 @@ extern "C" wt_status wt_build_host(const void* h_sym, uint64_t n, uint32_t sym_b
   if (stats) {
     stats->chunks = (uint32_t)nch;
     stats->pinned = pinned ? 1u : 0u;
+    stats->passes = one_pass ? 1u : 2u;
     stats->ms_counts = ms_counts;
     stats->ms_build = ms_since(t_build);
     stats->ms_total = ms_since(t_start);

@@ -1,9 +1,9 @@
 """GPU tests of the build from host memory in chunks (wt_build_host; the chunked construction of the
 thesis's Conclusion): the tree equals the one wt_build makes from a device copy, part by part (level
 sizes and ones, bits, L1/L2, samples, node tables, cumulative histogram), and the oracle's tree; its
-answers equal the oracle's. Page-locked and pageable arrays; one chunk, many chunks with a ragged last
-one, chunks smaller than a tile of the level pass; reduced codes, 2- and 4-byte symbols, an alphabet
-above the dense histogram, full-width codes, sigma = 1, and a level of more than 1024 tiles.
+answers equal the oracle's. One pass and two passes; page-locked and pageable arrays; one chunk, many
+chunks with a ragged last one; reduced codes, 2- and 4-byte symbols, an alphabet above the dense
+histogram, full-width codes, sigma = 1, and a level of more than 1024 tiles.
 """
 import numpy as np
 import pytest
@@ -47,37 +47,42 @@ def same_tree(th, td):
                 raise AssertionError("part %d level %d differs at %d places, first %d" % (part, l, bad.size, bad[0]))
 
 
-# (width, sigma, n, kind, chunk, pinned, oracle_check)
+# (width, sigma, n, kind, chunk, pinned, two_pass)
 CASES = [
+    (1, 256, (1 << 21) + 777, "zipf", 1 << 16, True, False),
+    (1, 256, (1 << 21) + 777, "zipf", 1 << 16, False, False),
     (1, 256, (1 << 21) + 777, "zipf", 1 << 16, True, True),
     (1, 256, (1 << 21) + 777, "zipf", 1 << 16, False, True),
+    (1, 5, 300001, "zipf", 65537, True, False),
     (1, 5, 300001, "zipf", 65537, True, True),
-    (1, 200, 250000, "runs", 1 << 20, False, True),        # one chunk
+    (1, 200, 250000, "runs", 1 << 20, False, False),       # one chunk
     (1, 7, 40000, "uniform", 1 << 16, True, True),         # fewer symbols than one chunk
-    (2, 1000, 1 << 20, "zipf", 100003, True, True),
+    (2, 1000, 1 << 20, "zipf", 100003, True, False),
     (2, 65536, 400000, "uniform", 1 << 17, False, True),
-    (4, 1 << 20, 1 << 21, "zipf12", 1 << 19, True, True),  # alphabet above the dense histogram
-    (4, 12345, 300000, "sparse", 70000, False, True),
-    (1, 1, 100000, "equal", 1 << 16, True, True),          # sigma = 1: no level
+    (4, 1 << 20, 1 << 21, "zipf12", 1 << 19, True, False),  # alphabet above the dense histogram
+    (4, 1 << 20, 1 << 21, "zipf12", 1 << 19, True, True),
+    (4, 12345, 300000, "sparse", 70000, False, False),
+    (1, 1, 100000, "equal", 1 << 16, True, False),         # sigma = 1: no level
 ]
 
 
-@pytest.mark.parametrize("width,sigma,n,kind,chunk,pinned,check", CASES)
-def test_host_build_equals_device_build(width, sigma, n, kind, chunk, pinned, check):
+@pytest.mark.parametrize("width,sigma,n,kind,chunk,pinned,two_pass", CASES)
+def test_host_build_equals_device_build(width, sigma, n, kind, chunk, pinned, two_pass):
     import paper_2505_03372_amd as wt
-    G.log("host build: width=%d sigma=%d n=%d %s chunk=%d pinned=%s" % (width, sigma, n, kind, chunk, pinned))
+    G.log("host build: width=%d sigma=%d n=%d %s chunk=%d pinned=%s two_pass=%s"
+          % (width, sigma, n, kind, chunk, pinned, two_pass))
     S = make_seq(kind, n, sigma, width, 0x4B10 + n + sigma)
     keep = None
     Sh = S
     if pinned:
         Sh, keep = _pinned(S)
-    th, st = wt.build_host(Sh, sigma, chunk=chunk)
+    th, st = wt.build_host(Sh, sigma, chunk=chunk, two_pass=two_pass)
     td = G.gpu_build(S, sigma)
     try:
         assert st["chunks"] == -(-n // min(chunk, n)) and st["pinned"] == int(pinned)
+        assert st["passes"] == (2 if two_pass or sigma == 1 else 1)
         same_tree(th, td)
-        if check:
-            G.compare_structure(th, oracle.OracleTree(S, sigma))
+        G.compare_structure(th, oracle.OracleTree(S, sigma))
         G.compare_queries(th, S, sigma, *G.edge_queries(S, sigma))
         G.compare_queries(th, S, sigma, *G.random_queries(S, sigma, 4096, 0x4B11 + n))
     finally:
@@ -109,9 +114,11 @@ def test_host_build_more_than_1024_tiles():
     S = make_seq("zipf", n, sigma, 1, 0x4B13)
     Sh, keep = _pinned(S)
     th, st = wt.build_host(Sh, sigma, chunk=1 << 22)
+    t2, st2 = wt.build_host(Sh, sigma, chunk=1 << 22, two_pass=True)
     td = G.gpu_build(S, sigma)
     try:
-        assert st["chunks"] == 5
+        assert st["chunks"] == 5 and st["passes"] == 1 and st2["passes"] == 2
+        same_tree(t2, td)
         same_tree(th, td)
         pos, rc, ri, sc, sk = G.random_queries(S, sigma, 1 << 17, 0x4B14)
         smp = workloads.uniform(0x4B15, 4096, 1 << 17).astype(np.int64)
@@ -121,6 +128,7 @@ def test_host_build_more_than_1024_tiles():
                                       oracle.rank(S, sigma, rc[smp], ri[smp]))
     finally:
         th.free()
+        t2.free()
         td.free()
     del keep
 
