@@ -111,6 +111,134 @@ def load_query_traffic(kernel: str, q: int):
     return k["traffic_bytes"] if k else None
 
 
+def _short_kernel(name: str) -> str:
+    """'void wt::k_select<9, 1024u, 0>(...)' -> 'k_select<9, 1024u>' (the shape argument 0, the tree,
+    dropped: the names the bench line uses); other shapes and kernels keep their arguments."""
+    k = name.split("(")[0].replace("void ", "").replace("wt::", "").strip()
+    return k[:-4] + ">" if k.endswith(", 0>") else k
+
+
+def profile_summary(d: str) -> None:
+    """Writes the summaries under profiles/ from the rocprofv3 runs of PROFILE_COMMANDS kept in `d`
+    (trace/, fetch/, write/, l2/ with their CSV files, and the bench JSON lines trace.json and
+    fetch.json): the kernel statistics of the default text_zipf run against the bench line of the same
+    run, and the HBM traffic and L2 hit rate of the level kernel and the binned query kernels. The
+    counters are read per dispatch (FETCH_SIZE and WRITE_SIZE in KiB) and scaled by what they read for
+    the run's 1 GiB device copy."""
+    import csv
+
+    def rows(sub, name):
+        with open(os.path.join(d, sub, name)) as f:
+            return list(csv.DictReader(f))
+
+    def bench_line(name):
+        with open(os.path.join(d, name)) as f:
+            return json.loads(f.read().strip().splitlines()[-1])
+
+    out_dir = os.path.join(ROOT, "profiles")
+    cmd = PROFILE_COMMANDS
+    # kernel statistics
+    stats = rows("trace", "run_kernel_stats.csv")
+    tl = bench_line("trace.json")
+    tot = sum(float(r["TotalDurationNs"]) for r in stats)
+    lines = ["# all kernels of the default bench, text_zipf (2^30 u8, 2^26 queries per kind): rocprofv3 kernel trace",
+             "", "Command (repository root on the GPU box, `TMPDIR=/tmp`):", "", "    " + cmd["trace"], "",
+             "Kernel statistics (`run_kernel_stats.csv`, top entries):", "",
+             "| kernel | calls | avg µs | total ms | % |", "|---|---|---|---|---|"]
+    by = {}
+    for r in sorted(stats, key=lambda r: -float(r["TotalDurationNs"]))[:16]:
+        k = _short_kernel(r["Name"])
+        by[k] = r
+        lines.append("| %s | %s | %.1f | %.1f | %.2f |" % (k, r["Calls"], float(r["AverageNs"]) / 1e3,
+                                                        float(r["TotalDurationNs"]) / 1e6,
+                                                        100.0 * float(r["TotalDurationNs"]) / tot))
+    for key, what in (("roofline", "Kernel with the most time per step"), ("roofline_build", "Build kernel")):
+        rf = tl[key]
+        match = [r for r in stats if _short_kernel(r["Name"]).replace("uint8_t", "unsigned char")
+                 .startswith(rf["kernel"].replace("uint8_t", "unsigned char").rstrip(">"))]
+        if match:
+            r = match[0]
+            lines += ["", "%s `%s`: rocprofv3 average %.1f µs over %s launches; the bench line of the same run "
+                      "(`%s`) reports avg_launch_ms = %.4f (HIP events around each launch), achieved %.0f GB/s = "
+                      "%.3f of %.0f GB/s." % (what, _short_kernel(r["Name"]), float(r["AverageNs"]) / 1e3, r["Calls"],
+                                               key, rf["avg_launch_ms"], rf["achieved"], rf["frac"], rf["peak"])]
+    with open(os.path.join(out_dir, "kernels_text_zipf_trace.md"), "w") as f:
+        f.write("\n".join(lines) + "\n")
+
+    # counters
+    fl = bench_line("fetch.json")
+    fetch, write, l2 = rows("fetch", "run_counter_collection.csv"), rows("write", "run_counter_collection.csv"), \
+        rows("l2", "run_counter_collection.csv")
+
+    def vals(rs, counter, pred):
+        return [float(r["Counter_Value"]) for r in rs if r["Counter_Name"] == counter and pred(r["Kernel_Name"])]
+
+    def copy_scale(rs, counter):
+        v = vals(rs, counter, lambda k: "copyBuffer" in k)
+        return float(fl["calibration_copy_bytes"]) / (max(v) * 1024.0)
+
+    fs, ws = copy_scale(fetch, "FETCH_SIZE"), copy_scale(write, "WRITE_SIZE")
+
+    def traffic(pred):
+        fv, wv = vals(fetch, "FETCH_SIZE", pred), vals(write, "WRITE_SIZE", pred)
+        h, m = sum(vals(l2, "TCC_HIT_sum", pred)), sum(vals(l2, "TCC_MISS_sum", pred))
+        return (len(fv), float(np.mean(fv)) * 1024 * fs, float(np.mean(wv)) * 1024 * ws,
+                h / (h + m) if h + m else None)
+
+    lvl = lambda k: _short_kernel(k).startswith("k_level<unsigned char, false")
+    n_l, f_l, w_l, hit_l = traffic(lvl)
+    alg_l = fl["roofline_build"]["bytes_per_launch"]
+    lj = {"kernel": "k_level<unsigned char, false>", "workload": "level_kernel_text_zipf",
+          "source_sha256_16": source_hash(LEVEL_SRCS), "launches": n_l, "fetch_scale": fs, "write_scale": ws,
+          "fetch_bytes_per_launch": f_l, "write_bytes_per_launch": w_l, "traffic_bytes_per_launch": f_l + w_l,
+          "algorithmic_bytes_per_launch": alg_l, "l2_hit_rate": hit_l, "commands": [cmd["fetch"], cmd["write"], cmd["l2"]]}
+    with open(os.path.join(out_dir, "level_kernel_text_zipf_pmc.json"), "w") as f:
+        json.dump(lj, f, indent=1)
+    q = fl["config"]["queries_per_kind"]
+    qj = {"source_sha256_16": source_hash(QUERY_SRCS), "queries_per_launch": q, "kernels": {},
+          "commands": [cmd["fetch"], cmd["write"], cmd["l2"]]}
+    for name in ("k_access<9, 1024u>", "k_rank<9, 1024u>", "k_select<9, 1024u>", "k_select_learned<9, 1024u>"):
+        nk, fq, wq, hq = traffic(lambda k, name=name: _short_kernel(k) == name)
+        alg = 64.0 * (int(fl["config"]["sigma"]) - 1).bit_length() * q  # levels of the tree: ceil(lg sigma)
+        qj["kernels"][name] = {"launches": nk, "fetch_bytes": fq, "write_bytes": wq, "traffic_bytes": fq + wq,
+                               "algorithmic_bytes": alg, "l2_hit_rate": hq}
+    with open(os.path.join(out_dir, "query_kernels_text_zipf_pmc.json"), "w") as f:
+        json.dump(qj, f, indent=1)
+    md = ["# level and query kernels, text_zipf (2^30 u8, 2^26 queries per kind): HBM traffic and L2 hits", "",
+          "Commands (repository root on the GPU box, `TMPDIR=/tmp`; one counter set per run):", ""]
+    md += ["    " + cmd[k] for k in ("fetch", "write", "l2")]
+    md += ["", "FETCH_SIZE and WRITE_SIZE are KiB per dispatch; scaled by what they read for the run's 1 GiB device "
+           "copy (FETCH x %.3f, WRITE x %.3f). Algorithmic bytes: the level pass's stream (bench.py "
+           "`level_launch_bytes`); a query kernel's 64 B (one L2 block of bits) per level per query." % (fs, ws), "",
+           "| kernel | launches | FETCH (GB) | WRITE (GB) | traffic / algorithmic | L2 hit rate |",
+           "|---|---|---|---|---|---|",
+           "| k_level<unsigned char, false> (per launch) | %d | %.3f | %.3f | %.3f | %.3f |"
+           % (n_l, f_l / 1e9, w_l / 1e9, (f_l + w_l) / alg_l, hit_l or 0.0)]
+    for name, k in qj["kernels"].items():
+        md.append("| %s | %d | %.3f | %.3f | %.2f | %.3f |" % (name, k["launches"], k["fetch_bytes"] / 1e9,
+                                                             k["write_bytes"] / 1e9,
+                                                             k["traffic_bytes"] / k["algorithmic_bytes"],
+                                                             k["l2_hit_rate"] or 0.0))
+    md += ["", "Source hashes (sha256/16): level kernel %s, query kernels %s." % (lj["source_sha256_16"],
+                                                                               qj["source_sha256_16"])]
+    with open(os.path.join(out_dir, "kernel_traffic_text_zipf_pmc.md"), "w") as f:
+        f.write("\n".join(md) + "\n")
+    print("profiles written from", d)
+
+
+# the rocprofv3 runs profile_summary reads (from the repository root; <out> is the directory it is given)
+PROFILE_COMMANDS = {
+    "trace": "rocprofv3 --kernel-trace --stats -f csv -d <out>/trace -o run -- python3 bench.py --no-cpu-baseline "
+             "--no-extra > <out>/trace.json",
+    "fetch": "rocprofv3 --pmc FETCH_SIZE -f csv -d <out>/fetch -o run -- python3 bench.py --steps 1 --warmup 0 "
+             "--no-cpu-baseline --no-extra --calibrate-copy > <out>/fetch.json",
+    "write": "rocprofv3 --pmc WRITE_SIZE -f csv -d <out>/write -o run -- python3 bench.py --steps 1 --warmup 0 "
+             "--no-cpu-baseline --no-extra --calibrate-copy",
+    "l2": "rocprofv3 --pmc TCC_HIT_sum TCC_MISS_sum -f csv -d <out>/l2 -o run -- python3 bench.py --steps 1 "
+          "--warmup 0 --no-cpu-baseline --no-extra",
+}
+
+
 def cpu_model() -> str:
     try:
         with open("/proc/cpuinfo") as f:
@@ -595,9 +723,14 @@ def main():
                     help="largest host-sourced batch of the default run, 10^k queries (5..8)")
     ap.add_argument("--cpu-sample-log2", type=int, default=25)
     ap.add_argument("--cpu-queries-log2", type=int, default=20)
+    ap.add_argument("--profile-summary", metavar="DIR",
+                    help="write the summaries under profiles/ from the rocprofv3 runs kept in DIR, then exit")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run a plain 1 GiB device copy (reference kernel for HBM counter scaling)")
     args = ap.parse_args()
+    if args.profile_summary:
+        profile_summary(args.profile_summary)
+        return
     if args.gpus != 1:
         print("bench.py measures one GPU: the wavelet-tree build and queries here run on a single MI355X "
               "(--gpus %d is not supported)" % args.gpus, file=sys.stderr)

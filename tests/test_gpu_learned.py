@@ -93,6 +93,37 @@ def test_training_reduces_prediction_error():
     t.free()
 
 
+def test_learned_search_window_against_sampled_select():
+    """What the model saves over the plain select, on the same tree: the plain select searches the L2
+    blocks between the two samples around its target (every level and side, weighted by the targets an
+    interval holds); the learned select starts at the model's prediction and searches around it. The
+    trained models' mean error is well below the plain search range (both in L2 blocks)."""
+    import paper_2505_03372_amd as wt
+    S, sigma = workloads.make_text("text_zipf", n=1 << 24)
+    G.log("learned window vs sampled range on text_zipf prefix 2^24")
+    t = G.gpu_build(S, sigma)
+    try:
+        info = t.learn_select()
+        inf = t.info
+        s, l2 = inf["sample_rate"], inf["l2_bits"]
+        spans, weights = [], []
+        for l in range(inf["levels"]):
+            nl, ones = inf["level_n"][l], inf["level_ones"][l]
+            for part, cnt in ((wt.PART_SAMPLES1, ones), (wt.PART_SAMPLES0, nl - ones)):
+                smp = t.export(part, l).astype(np.int64)
+                bounds = np.concatenate([[0], smp, [max(nl - 1, 0)]])
+                spans.append((bounds[1:] // l2) - (bounds[:-1] // l2) + 1)
+                w = np.full(smp.size + 1, s, dtype=np.float64)
+                w[-1] = cnt - s * smp.size
+                weights.append(w)
+        plain = float(np.average(np.concatenate(spans), weights=np.concatenate(weights)))
+        G.log("  plain search range %.2f L2 blocks, learned mean error %.2f blocks (training %.2f ms)"
+              % (plain, info["mean_err_blocks"], info["train_ms"]))
+        assert 2.0 * info["mean_err_blocks"] < plain
+    finally:
+        t.free()
+
+
 def test_compiled_models_equal_networks_and_slots():
     sigma, n = 77, 300001
     S = make_seq("zipf", n, sigma, 1, 0xC0DE)
