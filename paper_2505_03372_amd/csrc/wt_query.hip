@@ -145,7 +145,13 @@ void qprof_end(hipStream_t st) {
 // counts its chunk in an LDS histogram (128 KB: one 1024-thread block per CU), a pass gives every
 // (bucket, block) its offset, and the scatter places the chunk with LDS cursors (all atomics in LDS).
 // The buckets are fine enough that the 64 queries of a wave fall within a few lines of every array.
-constexpr uint32_t kBins = 32768;
+// kBins is the largest bucket count (the LDS arrays); a batch uses nb = 2^nbl <= kBins buckets. Access
+// batches take 2^14 (measured on 2^26 queries over 2^30 symbols: the scatter's 2^15 buckets cost more
+// than the finer order saves the traversal, 6.1 against 6.7 ms); rank and select take 2^15.
+constexpr uint32_t kBinsLog = 15;
+constexpr uint32_t kBins = 1u << kBinsLog;
+constexpr uint32_t kAccessBinsLog = 14;
+static_assert((1u << kAccessBinsLog) >= 1024, "bucket count: at least one per thread of the scan block");
 constexpr uint32_t kBinT = 1024;                // threads of the counting and scatter blocks
 constexpr uint32_t kBinChunk = kBinT * 256;     // queries per block
 constexpr uint64_t kSortMinQ = 1ull << 16;
@@ -158,8 +164,9 @@ constexpr uint32_t kBinNone = 0xFFFFFFFFu;  // slot past the batch
 
 template <int KIND>
 __device__ __forceinline__ void bin_round(const QArgs& a, const uint32_t* __restrict__ sym,
-                                          const uint64_t* __restrict__ arg, uint64_t q, uint32_t shift, uint64_t j0,
-                                          uint32_t (&bin)[kBinU], uint64_t (&x)[kBinU], uint32_t (&c)[kBinU]) {
+                                          const uint64_t* __restrict__ arg, uint64_t q, uint32_t shift, uint32_t nb,
+                                          uint64_t j0, uint32_t (&bin)[kBinU], uint64_t (&x)[kBinU],
+                                          uint32_t (&c)[kBinU]) {
 #pragma unroll
   for (uint32_t u = 0; u < kBinU; ++u) {
     const uint64_t j = j0 + (uint64_t)u * kBinT;
@@ -169,59 +176,60 @@ __device__ __forceinline__ void bin_round(const QArgs& a, const uint32_t* __rest
 #pragma unroll
   for (uint32_t u = 0; u < kBinU; ++u) {
     const uint64_t j = j0 + (uint64_t)u * kBinT;
-    bin[u] = j < q ? (uint32_t)min<uint64_t>(sort_key(a, KIND, c[u], x[u]) >> shift, kBins - 1) : kBinNone;
+    bin[u] = j < q ? (uint32_t)min<uint64_t>(sort_key(a, KIND, c[u], x[u]) >> shift, nb - 1) : kBinNone;
   }
 }
 
 template <int KIND>
 __global__ __launch_bounds__(kBinT) void k_bin_count(QArgs a, const uint32_t* __restrict__ sym,
                                                    const uint64_t* __restrict__ arg, uint64_t q, uint32_t shift,
-                                                   uint32_t* __restrict__ bhist) {
+                                                   uint32_t nb, uint32_t* __restrict__ bhist) {
   __shared__ uint32_t h[kBins];
-  for (uint32_t b = threadIdx.x; b < kBins; b += kBinT) h[b] = 0;
+  for (uint32_t b = threadIdx.x; b < nb; b += kBinT) h[b] = 0;
   __syncthreads();
   const uint64_t c0 = (uint64_t)blockIdx.x * kBinChunk;
   for (uint32_t i = threadIdx.x; i < kBinChunk; i += kBinT * kBinU) {
     uint32_t bin[kBinU], c[kBinU];
     uint64_t x[kBinU];
-    bin_round<KIND>(a, sym, arg, q, shift, c0 + i, bin, x, c);
+    bin_round<KIND>(a, sym, arg, q, shift, nb, c0 + i, bin, x, c);
 #pragma unroll
     for (uint32_t u = 0; u < kBinU; ++u)
       if (bin[u] != kBinNone) atomicAdd(&h[bin[u]], 1u);
   }
   __syncthreads();
-  for (uint32_t b = threadIdx.x; b < kBins; b += kBinT) bhist[(uint64_t)blockIdx.x * kBins + b] = h[b];
+  for (uint32_t b = threadIdx.x; b < nb; b += kBinT) bhist[(uint64_t)blockIdx.x * nb + b] = h[b];
 }
 
 // Per bucket: exclusive prefix over the blocks (in place) and the bucket total. The column is read
 // 16 entries at a time (loads issued together) before they are rewritten.
-__global__ __launch_bounds__(kQT) void k_bin_offsets(uint32_t* __restrict__ bhist, uint32_t nblk,
+__global__ __launch_bounds__(kQT) void k_bin_offsets(uint32_t* __restrict__ bhist, uint32_t nblk, uint32_t nb,
                                                      uint32_t* __restrict__ tot) {
   constexpr uint32_t R = 16;
   const uint32_t b = blockIdx.x * kQT + threadIdx.x;
-  if (b >= kBins) return;
+  if (b >= nb) return;
   uint32_t run = 0;
   for (uint32_t k0 = 0; k0 < nblk; k0 += R) {
     uint32_t v[R];
 #pragma unroll
-    for (uint32_t r = 0; r < R; ++r) v[r] = k0 + r < nblk ? bhist[(uint64_t)(k0 + r) * kBins + b] : 0u;
+    for (uint32_t r = 0; r < R; ++r) v[r] = k0 + r < nblk ? bhist[(uint64_t)(k0 + r) * nb + b] : 0u;
 #pragma unroll
     for (uint32_t r = 0; r < R; ++r) {
-      if (k0 + r < nblk) bhist[(uint64_t)(k0 + r) * kBins + b] = run;
+      if (k0 + r < nblk) bhist[(uint64_t)(k0 + r) * nb + b] = run;
       run += v[r];
     }
   }
   tot[b] = run;
 }
 
-// In place exclusive scan of the bucket totals (one block of 1024 threads, kBins / 1024 per thread).
-__global__ __launch_bounds__(1024) void k_bin_scan(uint32_t* __restrict__ tot) {
+// In place exclusive scan of the nb bucket totals (one block of 1024 threads, nb / 1024 per thread).
+__global__ __launch_bounds__(1024) void k_bin_scan(uint32_t* __restrict__ tot, uint32_t nb) {
   __shared__ uint32_t s_w[16];
   constexpr uint32_t kPer = kBins / 1024;
+  const uint32_t per = nb / 1024;
   uint32_t v[kPer], sum = 0;
 #pragma unroll
   for (uint32_t i = 0; i < kPer; ++i) {
-    v[i] = tot[threadIdx.x * kPer + i];
+    v[i] = i < per ? tot[threadIdx.x * per + i] : 0u;
     sum += v[i];
   }
   const uint32_t lane = threadIdx.x & 63u, wv = threadIdx.x >> 6;
@@ -238,7 +246,7 @@ __global__ __launch_bounds__(1024) void k_bin_scan(uint32_t* __restrict__ tot) {
   uint32_t run = pre + inc - sum;
 #pragma unroll
   for (uint32_t i = 0; i < kPer; ++i) {
-    tot[threadIdx.x * kPer + i] = run;
+    if (i < per) tot[threadIdx.x * per + i] = run;
     run += v[i];
   }
 }
@@ -247,16 +255,16 @@ __global__ __launch_bounds__(1024) void k_bin_scan(uint32_t* __restrict__ tot) {
 template <int KIND>
 __global__ __launch_bounds__(kBinT) void k_bin_scatter(QArgs a, const uint32_t* __restrict__ sym,
                                                      const uint64_t* __restrict__ arg, uint64_t q, uint32_t shift,
-                                                     const uint32_t* __restrict__ bhist,
+                                                     uint32_t nb, const uint32_t* __restrict__ bhist,
                                                      const uint32_t* __restrict__ base, SQ* __restrict__ sq) {
   __shared__ uint32_t cur[kBins];
-  for (uint32_t b = threadIdx.x; b < kBins; b += kBinT) cur[b] = base[b] + bhist[(uint64_t)blockIdx.x * kBins + b];
+  for (uint32_t b = threadIdx.x; b < nb; b += kBinT) cur[b] = base[b] + bhist[(uint64_t)blockIdx.x * nb + b];
   __syncthreads();
   const uint64_t c0 = (uint64_t)blockIdx.x * kBinChunk;
   for (uint32_t i = threadIdx.x; i < kBinChunk; i += kBinT * kBinU) {
     uint32_t bin[kBinU], c[kBinU];
     uint64_t x[kBinU];
-    bin_round<KIND>(a, sym, arg, q, shift, c0 + i, bin, x, c);
+    bin_round<KIND>(a, sym, arg, q, shift, nb, c0 + i, bin, x, c);
 #pragma unroll
     for (uint32_t u = 0; u < kBinU; ++u)
       if (bin[u] != kBinNone) {
@@ -322,8 +330,8 @@ void sort_ids_enqueue(const uint16_t* ids, uint64_t q, char* scratch, uint32_t* 
   const uint32_t nblk = (uint32_t)ceil_div(q, kBinChunk);
   uint32_t* bhist = (uint32_t*)scratch;
   hipLaunchKernelGGL(k_bin_count_ids, dim3(nblk), dim3(kBinT), 0, st, ids, q, bhist);
-  hipLaunchKernelGGL(k_bin_offsets, dim3(kBins / kQT), dim3(kQT), 0, st, bhist, nblk, tot);
-  hipLaunchKernelGGL(k_bin_scan, dim3(1), dim3(1024), 0, st, tot);
+  hipLaunchKernelGGL(k_bin_offsets, dim3(kBins / kQT), dim3(kQT), 0, st, bhist, nblk, kBins, tot);
+  hipLaunchKernelGGL(k_bin_scan, dim3(1), dim3(1024), 0, st, tot, kBins);
   hipLaunchKernelGGL(k_bin_scatter_ids, dim3(nblk), dim3(kBinT), 0, st, ids, q, (const uint32_t*)bhist,
                      (const uint32_t*)tot, perm);
 }
@@ -355,27 +363,29 @@ wt_status sort_batch(const wt_tree* t, const QArgs& a, int kind, const uint32_t*
   sb.sq = (SQ*)(blk + o_p);
   uint32_t bits = 0;
   while ((1ull << bits) < a.n + 1) ++bits;
-  const uint32_t shift = bits > 15 ? bits - 15 : 0;
+  const uint32_t nbl = kind == 0 ? kAccessBinsLog : kBinsLog, nb = 1u << nbl;
+  const uint32_t shift = bits > nbl ? bits - nbl : 0;
   sb.subshift = shift > qb_bits(kQB) ? shift - qb_bits(kQB) : 0;
   if (!pre) qprof_begin("sort_count", st);
-  if (kind == 0) hipLaunchKernelGGL(k_bin_count<0>, dim3(nblk), dim3(kBinT), 0, st, a, sym, arg, q, shift, bhist);
-  else if (kind == 1) hipLaunchKernelGGL(k_bin_count<1>, dim3(nblk), dim3(kBinT), 0, st, a, sym, arg, q, shift, bhist);
-  else hipLaunchKernelGGL(k_bin_count<2>, dim3(nblk), dim3(kBinT), 0, st, a, sym, arg, q, shift, bhist);
+  if (kind == 0) hipLaunchKernelGGL(k_bin_count<0>, dim3(nblk), dim3(kBinT), 0, st, a, sym, arg, q, shift, nb, bhist);
+  else if (kind == 1)
+    hipLaunchKernelGGL(k_bin_count<1>, dim3(nblk), dim3(kBinT), 0, st, a, sym, arg, q, shift, nb, bhist);
+  else hipLaunchKernelGGL(k_bin_count<2>, dim3(nblk), dim3(kBinT), 0, st, a, sym, arg, q, shift, nb, bhist);
   if (!pre) qprof_end(st);
   if (!pre) qprof_begin("sort_scan", st);
-  hipLaunchKernelGGL(k_bin_offsets, dim3(kBins / kQT), dim3(kQT), 0, st, bhist, nblk, tot);
-  hipLaunchKernelGGL(k_bin_scan, dim3(1), dim3(1024), 0, st, tot);
+  hipLaunchKernelGGL(k_bin_offsets, dim3(nb / kQT), dim3(kQT), 0, st, bhist, nblk, nb, tot);
+  hipLaunchKernelGGL(k_bin_scan, dim3(1), dim3(1024), 0, st, tot, nb);
   if (!pre) qprof_end(st);
   if (!pre) qprof_begin("sort_scatter", st);
   if (kind == 0)
-    hipLaunchKernelGGL(k_bin_scatter<0>, dim3(nblk), dim3(kBinT), 0, st, a, sym, arg, q, shift, (const uint32_t*)bhist,
-                       (const uint32_t*)tot, sb.sq);
+    hipLaunchKernelGGL(k_bin_scatter<0>, dim3(nblk), dim3(kBinT), 0, st, a, sym, arg, q, shift, nb,
+                       (const uint32_t*)bhist, (const uint32_t*)tot, sb.sq);
   else if (kind == 1)
-    hipLaunchKernelGGL(k_bin_scatter<1>, dim3(nblk), dim3(kBinT), 0, st, a, sym, arg, q, shift, (const uint32_t*)bhist,
-                       (const uint32_t*)tot, sb.sq);
+    hipLaunchKernelGGL(k_bin_scatter<1>, dim3(nblk), dim3(kBinT), 0, st, a, sym, arg, q, shift, nb,
+                       (const uint32_t*)bhist, (const uint32_t*)tot, sb.sq);
   else
-    hipLaunchKernelGGL(k_bin_scatter<2>, dim3(nblk), dim3(kBinT), 0, st, a, sym, arg, q, shift, (const uint32_t*)bhist,
-                       (const uint32_t*)tot, sb.sq);
+    hipLaunchKernelGGL(k_bin_scatter<2>, dim3(nblk), dim3(kBinT), 0, st, a, sym, arg, q, shift, nb,
+                       (const uint32_t*)bhist, (const uint32_t*)tot, sb.sq);
   if (!pre) qprof_end(st);
   WT_HIP(hipGetLastError());
   binned = true;
