@@ -52,7 +52,7 @@ typedef struct {
   uint32_t sample_rate; /* select sample interval s (Section 4.2): power of two in [512, 2^20]; default 4096 */
   uint32_t flags;       /* WT_BUILD_PROFILE: time every build kernel with HIP events (wt_build_profile);
                            WT_BUILD_MATRIX: build the wavelet matrix instead of the level-wise tree;
-                           WT_BUILD_WIDE: keep full-width codes at every level;
+                           WT_BUILD_WIDE / WT_BUILD_NARROW: carried code width (below);
                            WT_BUILD_HUFFMAN: Huffman-shaped tree */
   uint32_t reserved;
 } wt_build_opts;
@@ -69,10 +69,17 @@ typedef struct {
    export of bits / L1 / L2 / samples / WT_PART_WM_STARTS, wt_select_noalloc, wt_free) work on it; the
    learned index, forests and the node-table parts do not (WT_ERR_ARG). */
 #define WT_BUILD_MATRIX 2u
-/* Carry full-width codes at every level. By default the level sequence narrows (4 -> 2 -> 1 bytes per
-   element) as soon as the code bits the remaining levels need fit, and the levels after the code's
-   prefix bits are dropped find each element's node by its position; the tree is the same either way. */
+/* Carried code width. Narrowing: the level sequence narrows (4 -> 2 -> 1 bytes per element) as soon
+   as the code bits the remaining levels need fit, and the levels after the code's prefix bits are
+   dropped find each element's node by its position (a node list built from the node table). It saves
+   bytes per level but costs launches and node-list passes per build (measured: slower up to 2^24
+   symbols, faster from 2^26 on, for 2-byte symbols over 2^16 and 4-byte ones over 2^20), so by
+   default it is used from WT_NARROW_MIN_N symbols on. WT_BUILD_WIDE keeps full-width codes at every
+   level, WT_BUILD_NARROW narrows at any size (WIDE wins if both are given). The tree is the same
+   either way. */
 #define WT_BUILD_WIDE 4u
+#define WT_BUILD_NARROW 32u
+#define WT_NARROW_MIN_N (1ull << 25)
 /* Huffman-shaped tree (the Huffman variant the thesis's Conclusion names as a next step; the
    Huffman-shaped wavelet tree of Navarro's survey, which Section 2 cites): the same level-wise layout,
    rank directory, select samples and queries, but the codes are an optimal prefix code for the
@@ -139,7 +146,8 @@ wt_status wt_build(const void* d_sym, uint64_t n, uint32_t sym_bytes, uint64_t s
  * The result is the tree wt_build makes from a device copy of the same symbols: every part identical.
  *   h_sym     host array (page-locked or pageable) of n symbols of sym_bytes bytes (1, 2 or 4).
  *   sigma     declared alphabet, 1 <= sigma <= WT_MAX_SIGMA (sigma = 0 is not supported here).
- *   opts      as wt_build (l2_bits, sample_rate, WT_BUILD_WIDE, and WT_BUILD_HOST_TWO_PASS below);
+ *   opts      as wt_build (l2_bits, sample_rate, WT_BUILD_WIDE / WT_BUILD_NARROW for the chunks' trees, and
+ *             WT_BUILD_HOST_TWO_PASS below);
  *             WT_BUILD_MATRIX and WT_BUILD_HUFFMAN are refused.
  *   chunk     symbols per chunk (0: 2^27), at least 2^16.
  *   stats     may be NULL.

@@ -29,6 +29,7 @@ BUILD_PROFILE = 1
 BUILD_MATRIX = 2
 BUILD_WIDE = 4
 BUILD_HUFFMAN = 8
+BUILD_NARROW = 32
 BUILD_HOST_TWO_PASS = 16
 MAX_LEVELS = 24
 MAX_SIGMA = 1 << 24
@@ -466,14 +467,15 @@ def build_bitvector(words, n_bits: int, l2_bits: int = 512, sample_rate: int = 4
 
 
 def build_host(sym: np.ndarray, sigma: int, chunk: int = 0, l2_bits: int = 512, sample_rate: int = 4096,
-               wide: bool = False, two_pass: bool = False, stream=None):
+               wide: bool = False, two_pass: bool = False, narrow: bool = False, stream=None):
     """Build the tree of a host array (numpy uint8/uint16/uint32, page-locked or pageable) in chunks of
     `chunk` symbols (0: 2^27); the same tree as build() of a device copy. two_pass: copy the array twice
     and keep only a few chunks on the device. Returns (tree, stats)."""
     widths = {np.dtype(np.uint8): 1, np.dtype(np.uint16): 2, np.dtype(np.uint32): 4}
     if sym.dtype not in widths or not sym.flags["C_CONTIGUOUS"]:
         raise TypeError("symbols must be a contiguous uint8, uint16 or uint32 array")
-    opts = BuildOpts(l2_bits, sample_rate, (BUILD_WIDE if wide else 0) | (BUILD_HOST_TWO_PASS if two_pass else 0), 0)
+    opts = BuildOpts(l2_bits, sample_rate, (BUILD_WIDE if wide else 0) | (BUILD_HOST_TWO_PASS if two_pass else 0)
+                     | (BUILD_NARROW if narrow else 0), 0)
     st = BuildHostStats()
     h = ctypes.c_void_p(0)
     _check(lib().wt_build_host(ctypes.c_void_p(sym.ctypes.data if sym.size else 0), sym.size, widths[sym.dtype], sigma,
@@ -483,10 +485,11 @@ def build_host(sym: np.ndarray, sigma: int, chunk: int = 0, l2_bits: int = 512, 
 
 
 def build(sym, sigma: int, l2_bits: int = 512, sample_rate: int = 4096, profile: bool = False, stream=None,
-          matrix: bool = False, wide: bool = False, huffman: bool = False) -> Tree:
+          matrix: bool = False, wide: bool = False, huffman: bool = False, narrow: bool = False) -> Tree:
     """Build the wavelet tree of a contiguous device tensor of uint8/uint16/uint32 symbols. sigma: declared
     alphabet size (symbols in [0, sigma)), or 0 to extract the alphabet (the distinct values). matrix: build
-    the wavelet matrix instead (same queries). wide: keep full-width codes at every level (same tree).
+    the wavelet matrix instead (same queries). wide / narrow: keep full-width codes at every level, or
+    narrow them at any size (default: narrow from 2^24 symbols on; the same tree either way).
     huffman: Huffman-shaped tree (codes of an optimal length-limited prefix code of the counts)."""
     dts = _sym_dtypes()
     if sym.dtype not in dts:
@@ -494,7 +497,8 @@ def build(sym, sigma: int, l2_bits: int = 512, sample_rate: int = 4096, profile:
     if not sym.is_cuda or not sym.is_contiguous():
         raise ValueError("symbols must be a contiguous device tensor")
     opts = BuildOpts(l2_bits, sample_rate, (BUILD_PROFILE if profile else 0) | (BUILD_MATRIX if matrix else 0)
-                     | (BUILD_WIDE if wide else 0) | (BUILD_HUFFMAN if huffman else 0), 0)
+                     | (BUILD_WIDE if wide else 0) | (BUILD_HUFFMAN if huffman else 0)
+                     | (BUILD_NARROW if narrow else 0), 0)
     h = ctypes.c_void_p(0)
     _check(lib().wt_build(ctypes.c_void_p(sym.data_ptr() if sym.numel() else 0), sym.numel(), dts[sym.dtype], sigma,
                           ctypes.byref(opts), ctypes.c_void_p(_stream_handle(stream)), ctypes.byref(h)))

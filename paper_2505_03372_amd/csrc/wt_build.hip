@@ -644,7 +644,7 @@ wt_status wt::build_tree(const void* d_sym, uint64_t n, uint32_t sym_bytes, uint
   // Carried code width per level: level l + 1 needs only the code bits below level l (L - 1 - l of
   // them), so the sequence narrows to 2 and then 1 byte as levels consume bits. Once a level writes
   // codes without their prefix bits (fewer than L bits), nodes are found by position from that level on.
-  const bool narrow = (flags & WT_BUILD_WIDE) == 0;
+  const bool narrow = (flags & WT_BUILD_WIDE) == 0 && ((flags & WT_BUILD_NARROW) != 0 || n >= WT_NARROW_MIN_N);
   uint32_t wl[WT_MAX_LEVELS + 1];
   bool posm[WT_MAX_LEVELS] = {};
   bool any_pos = false;

@@ -279,7 +279,7 @@ extern "C" wt_status wt_build_host(const void* h_sym, uint64_t n, uint32_t sym_b
   wt_build_opts copts{};
   copts.l2_bits = l2_bits;
   copts.sample_rate = srate;
-  copts.flags = flags & WT_BUILD_WIDE;
+  copts.flags = flags & (WT_BUILD_WIDE | WT_BUILD_NARROW);
   const size_t pool_bytes = (size_t)nch * std::max<uint64_t>(nheap, 1) * sizeof(NodeB);
   size_t keep_bytes = pool_bytes;
   for (uint64_t c = 0; c < nch; ++c) keep_bytes += plan_tree(csize(c), sym_bytes, sigma, L, l2_bits, srate).total;

@@ -140,7 +140,7 @@ def test_huffman_binned_and_narrow_equal_wide(width, sigma, n, kind):
     import paper_2505_03372_amd as wt
     G.log("huffman binned / narrow vs wide: width=%d sigma=%d n=%d %s" % (width, sigma, n, kind))
     S = _seq(kind, n, sigma, width, 0x4A15 + sigma)
-    th = G.gpu_build(S, sigma, huffman=True)
+    th = G.gpu_build(S, sigma, huffman=True, narrow=True)
     tw = G.gpu_build(S, sigma, huffman=True, wide=True)
     tt = G.gpu_build(S, sigma)
     try:

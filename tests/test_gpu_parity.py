@@ -299,12 +299,12 @@ NARROW_CASES = [
 
 @pytest.mark.parametrize("width,sigma,n,kind", NARROW_CASES)
 def test_narrow_codes_build_the_same_tree(width, sigma, n, kind):
-    """The default build (narrowing codes, nodes by position after the prefix is dropped) equals the
-    full-width build part by part, and both equal the oracle."""
+    """The narrowing build (forced at these sizes: nodes by position after the prefix is dropped) equals
+    the full-width build part by part, and both equal the oracle."""
     import paper_2505_03372_amd as wt
     G.log("narrow vs wide: width=%d sigma=%d n=%d %s" % (width, sigma, n, kind))
     S = make_seq(kind, n, sigma, width, 0x7A00 + sigma + n)
-    tn = G.gpu_build(S, sigma)
+    tn = G.gpu_build(S, sigma, narrow=True)
     tw = G.gpu_build(S, sigma, wide=True)
     try:
         G.compare_structure(tn, oracle.OracleTree(S, sigma))
