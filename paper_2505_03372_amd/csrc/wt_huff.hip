@@ -111,22 +111,61 @@ void huff_code(const uint64_t* hist, uint64_t sigma, HuffCode& hc) {
 // ---------------------------------------------------------------- device
 
 // Symbols -> left-aligned codes of the first level (one block per tile of EC elements), and the ones
-// of code bit L - 1 of every tile (the tile counts of level 0).
+// of code bit L - 1 of every tile (the tile counts of level 0). 16-byte loads of the symbols when the
+// array is aligned; the code table is staged in LDS for alphabets up to kEncLds symbols.
+constexpr uint32_t kEncLds = 8192;
+
 template <typename E, typename EC>
 __global__ __launch_bounds__(kBT) void k_huff_encode(const E* __restrict__ in, uint64_t n, uint32_t sigma,
-                                                     const uint64_t* __restrict__ hcode, uint32_t L,
+                                                     const uint64_t* __restrict__ hcode, uint32_t L, uint32_t aligned,
                                                      EC* __restrict__ out, uint64_t* __restrict__ cnt0) {
   __shared__ uint32_t s_w[kBT / 64];
+  __shared__ uint32_t s_code[kEncLds];
   constexpr uint32_t T = kTileBytes / sizeof(EC);
+  constexpr uint32_t V = 16 / sizeof(E);  // symbols per 16-byte load
+  const bool lds = sigma <= kEncLds;
+  if (lds) {
+    for (uint32_t c = threadIdx.x; c < sigma; c += kBT) s_code[c] = (uint32_t)hcode[c];
+    __syncthreads();
+  }
+  auto code_of = [&](uint32_t s) -> uint32_t {
+    if (s >= sigma) s = 0;  // out of range: the build has already failed; keep the index valid
+    return lds ? s_code[s] : (uint32_t)hcode[s];
+  };
   const uint64_t t0 = (uint64_t)blockIdx.x * T;
   const uint32_t cnt = (uint32_t)min<uint64_t>((uint64_t)T, n - t0);
   uint32_t ones = 0;
-  for (uint32_t j = threadIdx.x; j < cnt; j += kBT) {
-    uint32_t s = (uint32_t)in[t0 + j];
-    if (s >= sigma) s = 0;  // out of range: the build has already failed; keep the index valid
-    const uint32_t code = (uint32_t)hcode[s];
-    out[t0 + j] = (EC)code;
-    ones += (code >> (L - 1)) & 1u;
+  if (aligned) {
+    for (uint32_t j = threadIdx.x * V; j < cnt; j += kBT * V) {
+      E v[V];
+      if (j + V <= cnt) {
+        const uint4 x = *reinterpret_cast<const uint4*>(in + t0 + j);
+        __builtin_memcpy(v, &x, 16);
+      } else {
+#pragma unroll
+        for (uint32_t e = 0; e < V; ++e) v[e] = j + e < cnt ? in[t0 + j + e] : (E)0;
+      }
+      EC o[V];
+#pragma unroll
+      for (uint32_t e = 0; e < V; ++e) {
+        const uint32_t code = code_of((uint32_t)v[e]);
+        o[e] = (EC)code;
+        ones += (j + e < cnt) ? ((code >> (L - 1)) & 1u) : 0u;
+      }
+      if (j + V <= cnt) {
+        __builtin_memcpy(out + t0 + j, o, sizeof(o));
+      } else {
+#pragma unroll
+        for (uint32_t e = 0; e < V; ++e)
+          if (j + e < cnt) out[t0 + j + e] = o[e];
+      }
+    }
+  } else {
+    for (uint32_t j = threadIdx.x; j < cnt; j += kBT) {
+      const uint32_t code = code_of((uint32_t)in[t0 + j]);
+      out[t0 + j] = (EC)code;
+      ones += (code >> (L - 1)) & 1u;
+    }
   }
 #pragma unroll
   for (int off = 32; off > 0; off >>= 1) ones += __shfl_xor(ones, off, 64);
@@ -187,8 +226,9 @@ static hipError_t launch_encode(const void* in, uint64_t n, uint32_t sigma, cons
                                 void* out, uint64_t* cnt0, hipStream_t st) {
   const uint64_t nt = ceil_div(n, kTileBytes / sizeof(EC));
   if (nt == 0) return hipSuccess;
+  const uint32_t aligned = ((uintptr_t)in & 15u) == 0;
   hipLaunchKernelGGL((k_huff_encode<E, EC>), dim3((uint32_t)nt), dim3(kBT), 0, st, (const E*)in, n, sigma, hcode, L,
-                     (EC*)out, cnt0);
+                     aligned, (EC*)out, cnt0);
   return hipGetLastError();
 }
 
