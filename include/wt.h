@@ -134,7 +134,9 @@ wt_status wt_set_allocator(wt_alloc_fn alloc_fn, wt_free_fn free_fn, void* ctx);
  * The call enqueues the build on `stream` and waits for it to finish (it must read back the
  * level sizes and the symbol-range flag). d_sym is not retained.
  * Errors: WT_ERR_ARG (bad arguments, more than WT_MAX_SIGMA distinct values), WT_ERR_SYMBOL_RANGE
- * (a symbol >= sigma), WT_ERR_OOM, WT_ERR_HIP.
+ * (a symbol >= sigma), WT_ERR_OOM, WT_ERR_HIP, WT_ERR_STATE (internal error: a level pass found an
+ * element whose staging slot lies outside its tile; the write is kept inside the tile and the tree is
+ * refused, since the tables it would hold are inconsistent).
  */
 wt_status wt_build(const void* d_sym, uint64_t n, uint32_t sym_bytes, uint64_t sigma, const wt_build_opts* opts,
                    wt_stream_t stream, wt_tree** out);

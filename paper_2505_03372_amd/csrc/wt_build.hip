@@ -825,6 +825,7 @@ wt_status wt::build_tree(const void* d_sym, uint64_t n, uint32_t sym_bytes, uint
     a.ns = ns;
     a.ns_idx = zs;
     a.tfirst = tfirst;
+    a.err = err;
     WT_STEP(prof.begin("level", (int)l));
     WT_STEP(launch_level_w(a, n, wl[l], wl[l + 1], st));
     WT_STEP(prof.end());
@@ -837,7 +838,10 @@ wt_status wt::build_tree(const void* d_sym, uint64_t n, uint32_t sym_bytes, uint
 #undef WT_STEP
   uint32_t rb_err = 0;
   std::memcpy(&rb_err, &rb[WT_MAX_LEVELS], sizeof(rb_err));
-  if (rb_err) return bail(fail(WT_ERR_SYMBOL_RANGE, "wt_build: a symbol is >= sigma (%llu)", (unsigned long long)sigma));
+  if (rb_err & 1u)
+    return bail(fail(WT_ERR_SYMBOL_RANGE, "wt_build: a symbol is >= sigma (%llu)", (unsigned long long)sigma));
+  if (rb_err & 2u)
+    return bail(fail(WT_ERR_STATE, "wt_build: internal error: the level pass placed an element outside its tile"));
   for (uint32_t l = 0; l < L; ++l) t->hmeta[l] = rb[l];
   if (prof.on) prof.collect(t->prof);
   *out = t;

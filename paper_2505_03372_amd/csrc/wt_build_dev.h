@@ -867,6 +867,9 @@ struct LevelArgs {
   const NodeS* ns;
   const uint64_t* ns_idx;
   const uint32_t* tfirst;
+  // Build error word (bit 1: an element fell outside its tile's staging slots, an internal error the
+  // host reports), or NULL.
+  uint32_t* err;
 };
 
 // The level pass's view of LevelArgs, with its pointers in the global address space.
@@ -888,6 +891,7 @@ struct LevelArgsG {
   const WT_GLOBAL NodeS* ns;
   const WT_GLOBAL uint64_t* ns_idx;
   const WT_GLOBAL uint32_t* tfirst;
+  WT_GLOBAL uint32_t* err;
 };
 
 __device__ __forceinline__ LevelArgsG to_global(const LevelArgs& a) {
@@ -916,6 +920,7 @@ __device__ __forceinline__ LevelArgsG to_global(const LevelArgs& a) {
   g.ns = (const WT_GLOBAL NodeS*)a.ns;
   g.ns_idx = (const WT_GLOBAL uint64_t*)a.ns_idx;
   g.tfirst = (const WT_GLOBAL uint32_t*)a.tfirst;
+  g.err = (WT_GLOBAL uint32_t*)a.err;
   return g;
 }
 
@@ -1090,6 +1095,7 @@ __device__ __forceinline__ LevelArgs forest_level_args(const TreeB& b, uint32_t 
   a.ns = nullptr;
   a.ns_idx = nullptr;
   a.tfirst = nullptr;
+  a.err = b.err;
   return a;
 }
 
@@ -1417,6 +1423,7 @@ __global__ __launch_bounds__(kBT, (level_waves<E, kForest, kPos>())) void k_leve
     }
     return;
   }
+  bool bad = false;  // a staging slot fell outside the tile
   {
     uint64_t curN = ~0ull;
     uint32_t sa = 0, zs = 0, R1a = 0;
@@ -1440,6 +1447,7 @@ __global__ __launch_bounds__(kBT, (level_waves<E, kForest, kPos>())) void k_leve
 #pragma unroll
             for (int e = 0; e < EV; ++e) {
               const uint32_t b = (m >> e) & 1u;
+              bad = bad || (b ? p1 : p0) >= (uint32_t)T;
               s_stage[min(b ? p1 : p0, (uint32_t)T - 1u)] = (EO)vec_elem<E>(vx[k], e);
               p1 += b;
               p0 += b ^ 1u;
@@ -1447,6 +1455,7 @@ __global__ __launch_bounds__(kBT, (level_waves<E, kForest, kPos>())) void k_leve
           } else {
             for (uint32_t e = 0; e < nv; ++e) {
               const uint32_t b = (m >> e) & 1u;
+              bad = bad || (b ? p1 : p0) >= (uint32_t)T;
               s_stage[min(b ? p1 : p0, (uint32_t)T - 1u)] = (EO)elem128<E>(lo, hi, e);
               p1 += b;
               p0 += b ^ 1u;
@@ -1460,6 +1469,7 @@ __global__ __launch_bounds__(kBT, (level_waves<E, kForest, kPos>())) void k_leve
             const uint64_t N = kPos ? pfx_at(q) : l ? ((uint64_t)code >> (L - l)) & pmask : 0ull;
             if (N != curN) enter_node(ld_node(a.ntb + N), q, t0, cnt, G0, G1, s_words, s_wpre, s_seg, &s_nseg, sa, zs, R1a), curN = N;
             const uint32_t slot = b ? sa + zs + (r1 - R1a) : sa + ((q - r1) - (sa - R1a));
+            bad = bad || slot >= (uint32_t)T;
             s_stage[min(slot, (uint32_t)T - 1u)] = (EO)code;
             r1 += b;
           }
@@ -1578,5 +1588,8 @@ __global__ __launch_bounds__(kBT, (level_waves<E, kForest, kPos>())) void k_leve
     }
   }
   if (lane == 0 && cur_c) atomic_add_u64(a.cnt_next + cur_tile, cur_c);
+  // a slot outside the tile (clamped above so LDS stays intact) is an internal error: reported, not hidden
+  if (__ballot(bad) != 0 && lane == 0 && a.err)
+    (void)__hip_atomic_fetch_or(a.err, 2u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 }  // namespace wt

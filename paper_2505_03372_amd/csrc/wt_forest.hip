@@ -765,9 +765,12 @@ extern "C" wt_status wt_build_forest(const wt_seq_desc* h_descs, uint32_t count,
   if (he != hipSuccess) return bail(fail(WT_ERR_HIP, "wt_build_forest: graph launch: %s", hipGetErrorString(he)));
 
   for (uint32_t j = 0; j < count; ++j) {
-    if (ho[j].err)
+    if (ho[j].err & 1u)
       return bail(fail(WT_ERR_SYMBOL_RANGE, "wt_build_forest: sequence %u has a symbol >= sigma (%llu)", j,
                        (unsigned long long)sh[j].sigma));
+    if (ho[j].err & 2u)
+      return bail(fail(WT_ERR_STATE, "wt_build_forest: internal error: a level pass placed an element of sequence "
+                       "%u outside its tile", j));
   }
   uint64_t symbols = 0;
   for (uint32_t j = 0; j < count; ++j) {
