@@ -439,7 +439,9 @@ wt_status wt_autotune(const wt_seq_desc* h_descs, uint32_t count, uint32_t sym_b
 
 typedef struct {
   const wt_tune_table* tune; /* may be NULL */
-  uint32_t flags;            /* reserved */
+  uint32_t flags;            /* WT_BUILD_WIDE: every level carries full-width codes. Default: each tree's
+                                carried codes narrow as its levels consume bits (the single-tree rule of
+                                WT_BUILD_NARROW, for every tree whatever its length); the trees are the same. */
   uint32_t reserved;
 } wt_forest_opts;
 

@@ -633,11 +633,13 @@ def load_tune(path: str) -> TuneTable:
     return make_tune_table({tuple(int(x) for x in k.split(",")): tuple(v) for k, v in d.items()})
 
 
-def build_forest(seqs, sigmas, l2_bits=None, sample_rates=None, tune: TuneTable = None, stream=None) -> Forest:
+def build_forest(seqs, sigmas, l2_bits=None, sample_rates=None, tune: TuneTable = None, stream=None,
+                 wide: bool = False) -> Forest:
     """Build one tree per device tensor of `seqs` (all uint8, all uint16 or all uint32; views of one buffer
-    are fine) in one captured graph launch. l2_bits / sample_rates: per-sequence lists (0 = tuned/default)."""
+    are fine) in one captured graph launch. l2_bits / sample_rates: per-sequence lists (0 = tuned/default);
+    wide: carry full-width codes through every level (same trees)."""
     descs, w = _descs(seqs, sigmas, l2_bits, sample_rates)
-    opts = ForestOpts(ctypes.pointer(tune) if tune is not None else None, 0, 0)
+    opts = ForestOpts(ctypes.pointer(tune) if tune is not None else None, BUILD_WIDE if wide else 0, 0)
     h = ctypes.c_void_p(0)
     _check(lib().wt_build_forest(descs, len(seqs), w, ctypes.byref(opts), ctypes.c_void_p(_stream_handle(stream)),
                                  ctypes.byref(h)))

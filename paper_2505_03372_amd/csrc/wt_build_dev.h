@@ -820,29 +820,6 @@ struct NodeS {
   uint32_t pad;
 };
 
-// Index of the last entry of list[0, n) whose start is <= q (list[0] <= q).
-__device__ __forceinline__ uint32_t lst_find(const uint32_t* __restrict__ list, uint32_t n, uint32_t q) {
-  uint32_t lo = 0, hi = n - 1;
-  while (lo < hi) {
-    const uint32_t mid = (lo + hi + 1) >> 1;
-    if (list[mid] <= q) lo = mid;
-    else hi = mid - 1;
-  }
-  return lo;
-}
-
-// Code prefix of the node holding level position x: the last of ns[lo, hi) whose start is <= x.
-template <typename P>
-__device__ __forceinline__ uint64_t ns_find(P ns, uint64_t lo, uint64_t hi, uint64_t x) {
-  hi -= 1;
-  while (lo < hi) {
-    const uint64_t mid = (lo + hi + 1) >> 1;
-    if (ns[mid].start <= x) lo = mid;
-    else hi = mid - 1;
-  }
-  return ns[lo].pfx;
-}
-
 struct LevelArgs {
   const void* in;  // level-l sequence (codes; symbols at level 0)
   void* out;       // level-(l+1) sequence
@@ -1057,15 +1034,26 @@ struct TreeB {
   uint64_t* part;
   uint32_t* err;
   uint64_t ntiles, nchunks, cstride, nheap;
+  // Carried code width of every level (2 bits per level l = 0 .. L: log2 of its element bytes; level 0
+  // holds the symbols) and the levels whose nodes are found by position (bit l), with the tree's
+  // non-empty nodes in position order for them (indexed through zs, as in the single-tree build).
+  uint64_t wlog;
+  uint32_t posmask, pad1;
+  NodeS* ns;
 };
 
-// Blocks of a forest launch: block g belongs to tree bmap[g] and is block g - boff[tree] of it.
+__device__ __forceinline__ uint32_t forest_wlog(const TreeB& b, uint32_t l) {
+  return (uint32_t)(b.wlog >> (2 * l)) & 3u;
+}
+
+// Blocks of a forest launch: block g = base + blockIdx.x of the map belongs to tree bmap[g] and is
+// block g - boff[tree] of it (a launch may cover a range of the map's trees).
 struct ForestGrid {
   const TreeB* tb;
   const uint32_t* bmap;
   const uint32_t* boff;
   uint32_t l;
-  uint32_t pad;
+  uint32_t base;
 };
 
 // Arguments of the level-l pass of a tree of a forest build (as the single-tree build sets them).
@@ -1091,12 +1079,29 @@ __device__ __forceinline__ LevelArgs forest_level_args(const TreeB& b, uint32_t 
   a.in_vec = l == 0 ? 0u : 1u;
   a.in_aligned = l == 0 ? b.aligned : 1u;
   a.matrix = 0;
-  a.pos_node = 0;
-  a.ns = nullptr;
-  a.ns_idx = nullptr;
-  a.tfirst = nullptr;
+  a.pos_node = (b.posmask >> l) & 1u;
+  a.ns = b.ns;
+  a.ns_idx = b.zs;
+  a.tfirst = nullptr;  // each tile finds its first node itself
   a.err = b.err;
   return a;
+}
+
+// Index of the last entry of ns[lo, hi) whose start is <= x, given ns[lo].start <= x and increasing
+// starts: a 64-way search by one whole wave (three rounds of one load per lane for 2^17 entries).
+template <typename P>
+__device__ __forceinline__ uint64_t wave_find_start(P ns, uint64_t lo, uint64_t hi, uint64_t x, uint32_t lane) {
+  while (hi - lo > 1) {
+    const uint64_t step = (hi - lo + 63) / 64;
+    const uint64_t i = lo + (uint64_t)lane * step;
+    const bool le = i < hi && ns[i].start <= x;
+    // the lanes with le are 0 .. c - 1 (lane 0 tests lo), so the answer is in [lo + (c-1) step, lo + c step)
+    const uint32_t c = (uint32_t)__popcll(__ballot(le));
+    const uint64_t nlo = lo + (uint64_t)(c - 1) * step;
+    hi = min(hi, nlo + step);
+    lo = nlo;
+  }
+  return lo;
 }
 
 // The body stays in the kernel (as a device function it needs far more registers).
@@ -1104,7 +1109,7 @@ __device__ __forceinline__ LevelArgs forest_level_args(const TreeB& b, uint32_t 
 // 80 registers without spilling, else five.
 template <typename E, bool kForest, bool kPos = false>
 constexpr int level_waves() {
-  return (sizeof(E) == 1 && !kForest && !kPos) || (sizeof(E) == 2 && kForest) ? 6 : 5;
+  return !kPos && ((sizeof(E) == 1 && !kForest) || (sizeof(E) == 2 && kForest)) ? 6 : 5;
 }
 
 // E: element type of level l; EO: of level l + 1 (narrower when the codes need fewer bits below the
@@ -1115,8 +1120,9 @@ __global__ __launch_bounds__(kBT, (level_waves<E, kForest, kPos>())) void k_leve
   LevelArgsG a;
   uint64_t t;
   if constexpr (kForest) {
-    const uint32_t j = fg.bmap[blockIdx.x];
-    t = blockIdx.x - fg.boff[j];
+    const uint32_t g = blockIdx.x + fg.base;
+    const uint32_t j = fg.bmap[g];
+    t = g - fg.boff[j];
     a = to_global(forest_level_args(fg.tb[j], fg.l));
   } else {
     a = to_global(a_one);
@@ -1124,7 +1130,7 @@ __global__ __launch_bounds__(kBT, (level_waves<E, kForest, kPos>())) void k_leve
   }
   using TL = Tile<E>;
   using TO = Tile<EO>;
-  static_assert(sizeof(EO) <= sizeof(E) && (!kForest || sizeof(EO) == sizeof(E)), "codes only narrow");
+  static_assert(sizeof(EO) <= sizeof(E), "codes only narrow");
   constexpr int T = TL::T, W = TL::W, EV = TL::EV, G = TL::G, NCH = TL::NCH;
   __shared__ __align__(16) EO s_stage[T + 16 / sizeof(EO) + 4];  // + slack for the 20-byte chunk reads
   __shared__ uint64_t s_words[W + 1];  // entry W: 0, so ranks are defined at x = T
@@ -1137,10 +1143,15 @@ __global__ __launch_bounds__(kBT, (level_waves<E, kForest, kPos>())) void k_leve
   __shared__ uint64_t s_dst[2];   // single-node tile: destinations of its first zero and first one
   __shared__ uint32_t s_nc[4];    // single-node tile: next-level ones per (run, destination tile)
   __shared__ uint2 s_enc[32];     // level 0 of a reduced alphabet: (high code bits, shift) by h
-  __shared__ uint32_t s_lst[kSegMax];  // nodes by position: the tile's nodes (tile-relative starts)
-  __shared__ uint32_t s_lpf[kSegMax];  //   and their code prefixes
-  __shared__ uint32_t s_nlst;          //   count (kSegMax + 1: more nodes than the list holds)
-  __shared__ uint64_t s_i0;            //   the first node's entry in the level's position list
+  // nodes by position: bit q of s_nb is set where a node starts at tile position q > 0, s_nbp counts
+  // the starts before each word, so the node of position q is the tile's node number (starts in
+  // (0, q]); s_lpf holds the code prefixes of the first kSegMax nodes, s_i0 the first node's entry in
+  // the level's position list and s_nn the tile's node count
+  __shared__ uint64_t s_nb[kPos ? W + 1 : 1];
+  __shared__ uint32_t s_nbp[kPos ? W + 1 : 1];
+  __shared__ uint32_t s_lpf[kSegMax];
+  __shared__ uint64_t s_i0;
+  __shared__ uint32_t s_nn;
 
   const uint32_t tid = threadIdx.x, lane = tid & 63u;
   const uint32_t l = a.l, L = a.L;
@@ -1213,39 +1224,38 @@ __global__ __launch_bounds__(kBT, (level_waves<E, kForest, kPos>())) void k_leve
       s_node[0] = (l && !a.matrix) ? ((uint64_t)vec_elem<E>(vx[k], 0) >> (L - l)) & ((1ull << l) - 1ull) : 0ull;
   }
   if (tid < 4) s_nc[tid] = 0;
-  if (kPos && tid < 64) {
-    // the tile's nodes: entries from the one holding t0 on, while they start inside the tile (starts
-    // increase, so those entries are a prefix of each round of 64)
-    const uint64_t lo = a.ns_idx[(1ull << l) - 1], hi = a.ns_idx[(2ull << l) - 1];
-    const uint64_t i0 = lo + a.tfirst[t];
-    const uint64_t tend = t0 + cnt;
-    uint32_t total = 0;
-    bool more = true;
-    for (uint32_t r = 0; r <= (uint32_t)kSegMax / 64 && more; ++r) {
-      const uint64_t j = (uint64_t)r * 64 + lane;
-      bool in = false;
-      NodeS e{};
-      if (i0 + j < hi) {
-        e.start = a.ns[i0 + j].start;
-        e.pfx = a.ns[i0 + j].pfx;
-        in = j == 0 || e.start < tend;
+  if constexpr (kPos) {
+    if (tid <= (uint32_t)W) s_nb[tid] = 0;
+    if (tid < 64) {
+      // the tile's nodes: entries i0 (the one holding t0) .. i1 (the last starting inside the tile);
+      // at most cnt nodes start inside the tile
+      const uint64_t lo = a.ns_idx[(1ull << l) - 1], hi = a.ns_idx[(2ull << l) - 1];
+      const uint64_t i0 = a.tfirst ? lo + a.tfirst[t] : wave_find_start(a.ns, lo, hi, t0, lane);
+      const uint64_t i1 = wave_find_start(a.ns, i0, min(hi, i0 + cnt), t0 + cnt - 1, lane);
+      if (lane == 0) {
+        const uint32_t p0 = a.ns[i0].pfx;
+        s_i0 = i0;
+        s_nn = (uint32_t)(i1 - i0 + 1);
+        s_lpf[0] = p0;
+        s_node[0] = p0;
+        s_node[1] = i1 == i0 ? (uint64_t)p0 : ~0ull;
       }
-      const uint32_t c = (uint32_t)__popcll(__ballot(in));
-      if (in && j < (uint64_t)kSegMax) {
-        s_lst[j] = j ? (uint32_t)(e.start - t0) : 0u;
-        s_lpf[j] = e.pfx;
-      }
-      total += c;
-      more = c == 64;
-    }
-    if (lane == 0) {
-      s_nlst = min(total, (uint32_t)kSegMax + 1u);
-      s_i0 = i0;
-      s_node[0] = s_lpf[0];
-      s_node[1] = total == 1 ? s_lpf[0] : ~0ull;
     }
   }
   __syncthreads();
+  if constexpr (kPos) {
+    const uint32_t nn = s_nn;
+    if (nn > 1) {
+      // node starts inside the tile into the bitmap, and the first prefixes into the list
+      const uint64_t i0 = s_i0;
+      for (uint32_t j = 1 + tid; j < nn; j += kBT) {
+        const uint32_t x = (uint32_t)(a.ns[i0 + j].start - t0);  // in [1, cnt)
+        atomicOr((unsigned long long*)&s_nb[x >> 6], 1ull << (x & 63u));
+        if (j < (uint32_t)kSegMax) s_lpf[j] = a.ns[i0 + j].pfx;
+      }
+      __syncthreads();
+    }
+  }
   // a tile inside one node (the rule at shallow levels) takes the fast path: two runs, no segments
   const bool single = s_node[0] == s_node[1];
   if (single && !last && tid == 0) {
@@ -1254,12 +1264,18 @@ __global__ __launch_bounds__(kBT, (level_waves<E, kForest, kPos>())) void k_leve
     s_dst[1] = nb.off1 + G1;
   }
 
-  // 2. tile-local rank1 at every word
+  // 2. tile-local rank1 at every word (and, for nodes by position, the node starts before every word:
+  // both counts are at most T < 2^16, so one scan carries them in the two halves of a word)
   uint32_t tile_ones;
   {
-    const uint32_t pc = (tid < (uint32_t)W) ? popc64(s_words[tid]) : 0u;
+    uint32_t pc = (tid < (uint32_t)W) ? popc64(s_words[tid]) : 0u;
+    if constexpr (kPos) pc |= (tid < (uint32_t)W) ? popc64(s_nb[tid]) << 16 : 0u;
     const uint32_t ex = block_excl_scan_u32(pc, s_w, tile_ones);
-    if (tid < (uint32_t)W) s_wpre[tid] = ex;
+    if constexpr (kPos) {
+      if (tid < (uint32_t)W) s_nbp[tid] = ex >> 16;
+      tile_ones &= 0xFFFFu;
+    }
+    if (tid < (uint32_t)W) s_wpre[tid] = ex & (kPos ? 0xFFFFu : 0xFFFFFFFFu);
     if (tid == 0) {
       s_wpre[W] = tile_ones;
       s_words[W] = 0;
@@ -1317,11 +1333,10 @@ __global__ __launch_bounds__(kBT, (level_waves<E, kForest, kPos>())) void k_leve
   const uint32_t nbsh = L - 2 - l;
   const uint64_t pmask = (1ull << l) - 1ull;
   // code prefix of the node holding tile position q (nodes by position)
-  const uint32_t nlst = kPos ? s_nlst : 0u;
   auto pfx_at = [&](uint32_t q) -> uint64_t {
-    if (nlst <= (uint32_t)kSegMax) return s_lpf[lst_find(s_lst, nlst, q)];
-    const uint64_t hi = a.ns_idx[(2ull << l) - 1];
-    return ns_find(a.ns, s_i0, min(hi, s_i0 + cnt), t0 + q);
+    const uint32_t w = q >> 6;
+    const uint32_t k = s_nbp[w] + popc64(s_nb[w] & ((2ull << (q & 63u)) - 1ull));  // starts in (0, q]
+    return k < (uint32_t)kSegMax ? (uint64_t)s_lpf[k] : (uint64_t)a.ns[s_i0 + k].pfx;
   };
   if (single) {
     // zeros fill slots [0, Z), ones [Z, cnt); each lane walks its vectors with running slots

@@ -29,9 +29,10 @@ struct FB {
 };
 
 __device__ __forceinline__ FB forest_block(const ForestGrid& fg) {
-  const uint32_t j = fg.bmap[blockIdx.x];
+  const uint32_t g = blockIdx.x + fg.base;
+  const uint32_t j = fg.bmap[g];
   const uint32_t b0 = fg.boff[j];
-  return FB{j, (uint64_t)(blockIdx.x - b0), (uint64_t)(fg.boff[j + 1] - b0)};
+  return FB{j, (uint64_t)(g - b0), (uint64_t)(fg.boff[j + 1] - b0)};
 }
 
 // Level metadata of every tree and cleared counters (histogram, tile counts, range flag).
@@ -129,12 +130,17 @@ __global__ __launch_bounds__(kBT) void kf_node_final(ForestGrid fg) {
   node_final_body(b.nheap, b.zs, b.ntb, b.nodes, b.meta, f.bid * kBT + threadIdx.x);
 }
 
+// Tiles of level l hold kTileBytes of its carried codes (b.tshift: the symbols' tile at level 0).
+__device__ __forceinline__ uint32_t forest_tshift(const TreeB& b, uint32_t l) {
+  return b.tshift + forest_wlog(b, 0) - forest_wlog(b, l);
+}
+
 __global__ __launch_bounds__(kBT) void kf_tile_reduce(ForestGrid fg) {
   const FB f = forest_block(fg);
   const TreeB& b = fg.tb[f.j];
   const uint32_t l = fg.l;
   const uint64_t* cnt = b.tcnt + (uint64_t)l * b.cstride;
-  tile_reduce_body(b.meta, l, b.tshift, cnt, b.tcnt + (uint64_t)l * b.cstride + b.ntiles + 1, f.bid);
+  tile_reduce_body(b.meta, l, forest_tshift(b, l), cnt, b.tcnt + (uint64_t)l * b.cstride + b.ntiles + 1, f.bid);
 }
 
 __global__ __launch_bounds__(kBT) void kf_tile_scan(ForestGrid fg) {
@@ -142,8 +148,32 @@ __global__ __launch_bounds__(kBT) void kf_tile_scan(ForestGrid fg) {
   const TreeB& b = fg.tb[f.j];
   const uint32_t l = fg.l;
   const uint64_t* cnt = b.tcnt + (uint64_t)l * b.cstride;
-  tile_scan_body(b.meta, l, b.tshift, cnt, cnt + b.ntiles + 1, b.tpre + (uint64_t)l * (b.ntiles + 1), b.L1, b.L2,
-                 f.bid);
+  tile_scan_body(b.meta, l, forest_tshift(b, l), cnt, cnt + b.ntiles + 1, b.tpre + (uint64_t)l * (b.ntiles + 1),
+                 b.L1, b.L2, f.bid);
+}
+
+// Non-empty nodes in position order for trees with levels whose nodes are found by position: flags of
+// the heap entries into z (z[nheap] stays 0 from kf_init), then, after the scan of z into zs, every
+// non-empty entry at its rank.
+__global__ __launch_bounds__(kBT) void kf_ns_flag(ForestGrid fg) {
+  const FB f = forest_block(fg);
+  const TreeB& b = fg.tb[f.j];
+  const uint64_t h = f.bid * kBT + threadIdx.x;
+  if (!b.posmask || h >= b.nheap) return;
+  b.z[h] = (b.ntb[h].start != kNoNode && b.ntb[h].end > b.ntb[h].start) ? 1ull : 0ull;
+}
+
+__global__ __launch_bounds__(kBT) void kf_ns_scatter(ForestGrid fg) {
+  const FB f = forest_block(fg);
+  const TreeB& b = fg.tb[f.j];
+  const uint64_t h = f.bid * kBT + threadIdx.x;
+  if (!b.posmask || h >= b.nheap || b.zs[h + 1] == b.zs[h]) return;
+  const uint32_t l = 63u - (uint32_t)__clzll(h + 1);
+  NodeS e;
+  e.start = b.ntb[h].start;
+  e.pfx = (uint32_t)(h + 1 - (1ull << l));
+  e.pad = 0;
+  b.ns[b.zs[h]] = e;
 }
 
 // Level sizes and range flag of every tree into one buffer (one block per tree, caller order).
@@ -488,6 +518,36 @@ extern "C" wt_status wt_build_forest(const wt_seq_desc* h_descs, uint32_t count,
     while ((1ull << s.L) < s.sigma) ++s.L;
     s.pow2 = (s.sigma & (s.sigma - 1)) == 0;
   }
+  // Carried code width per tree and level, as the single-tree build narrows them: level l + 1 needs the
+  // L - 1 - l code bits below level l only, so the codes narrow as levels consume bits; once a level
+  // has dropped prefix bits, the levels after it find nodes by position. WT_BUILD_WIDE keeps the width.
+  const bool narrow = !(opts && (opts->flags & WT_BUILD_WIDE));
+  struct Sched {
+    uint64_t wlog;     // 2 bits per level: log2 of its element bytes
+    uint32_t posmask;  // levels whose nodes are found by position
+  };
+  std::vector<Sched> sched(count);
+  for (uint32_t j = 0; j < count; ++j) {
+    const uint32_t L = sh[j].L;
+    uint32_t w = sym_bytes;
+    uint64_t wlog = log2_floor(w);
+    uint32_t posmask = 0;
+    bool lost = false;
+    for (uint32_t l = 0; l < L; ++l) {
+      uint32_t wo = w;
+      if (narrow && l + 1 < L) {
+        const uint32_t need = L - 1 - l;
+        wo = std::min<uint32_t>(wo, need <= 8 ? 1u : need <= 16 ? 2u : 4u);
+      }
+      const bool drops = 8 * wo < L;
+      if (l > 0 && (lost || drops)) posmask |= 1u << l;
+      lost = lost || drops;
+      wlog |= (uint64_t)log2_floor(wo) << (2 * (l + 1));
+      w = wo;
+    }
+    sched[j] = Sched{wlog, posmask};
+  }
+
   // build order: level count descending (stable)
   std::vector<uint32_t> order(count);
   std::iota(order.begin(), order.end(), 0u);
@@ -532,7 +592,7 @@ extern "C" wt_status wt_build_forest(const wt_seq_desc* h_descs, uint32_t count,
   }
   // scratch of every tree
   struct SOff {
-    size_t seq0, seq1, clear, tpre, ntb, z, zs, part;
+    size_t seq0, seq1, clear, tpre, ntb, z, zs, part, ns;
     uint64_t hist_n, clear_n, ntiles, nchunks, cstride, part_n;
   };
   std::vector<SOff> so(count);
@@ -562,6 +622,7 @@ extern "C" wt_status wt_build_forest(const wt_seq_desc* h_descs, uint32_t count,
     o.z = take((P.nheap + 1) * 8);
     o.zs = take((P.nheap + 1) * 8);
     o.part = take(o.part_n * 8);
+    o.ns = take(sched[j].posmask ? P.nheap * sizeof(NodeS) : 0);
   }
 
   wt_forest* f = new wt_forest();
@@ -591,7 +652,9 @@ extern "C" wt_status wt_build_forest(const wt_seq_desc* h_descs, uint32_t count,
 
   // per-tree state (build order) and block maps
   std::vector<TreeB> tb(count);
-  MapBuilder m_init, m_hist_small, m_hist_big, m_hist_hash, m_scan_c, m_scan_z, m_node, m_tile, m_level;
+  MapBuilder m_init, m_hist_small, m_hist_big, m_hist_hash, m_scan_c, m_scan_z, m_node, m_tile;
+  MapBuilder m_level[3];  // level passes over 1-, 2- and 4-byte codes: tiles of kTileBytes per tree
+  bool any_pos = false;
   uint64_t all_tiles = 0;
   for (uint32_t j = 0; j < count; ++j) all_tiles += sh[j].n ? ceil_div(sh[j].n, T) : 0;
   // histogram blocks of a quarter of the single-tree size: most of a forest's trees get one block,
@@ -642,6 +705,10 @@ extern "C" wt_status wt_build_forest(const wt_seq_desc* h_descs, uint32_t count,
     b.nchunks = o.nchunks;
     b.cstride = o.cstride;
     b.nheap = P.nheap;
+    b.wlog = sched[j].wlog;
+    b.posmask = sched[j].posmask;
+    b.ns = sched[j].posmask ? (NodeS*)(sb + o.ns) : nullptr;
+    any_pos = any_pos || sched[j].posmask != 0;
     for (uint32_t l = 0; l < b.L; ++l) active[l] = s + 1;
 
     const uint64_t ntiles_n = b.n ? ceil_div(b.n, T) : 0;
@@ -657,9 +724,11 @@ extern "C" wt_status wt_build_forest(const wt_seq_desc* h_descs, uint32_t count,
     m_scan_z.add(s, b.L ? ceil_div(P.nheap + 1, kScanChunk) : 0);
     m_node.add(s, b.L ? ceil_div(P.nheap, kBT) : 0);
     m_tile.add(s, b.L ? o.nchunks + 1 : 0);
-    m_level.add(s, b.L ? ntiles_n : 0);
+    for (uint32_t k = 0; k < 3; ++k)
+      m_level[k].add(s, b.L && (1u << k) <= sym_bytes ? ceil_div(b.n, tile_elems(1u << k)) : 0);
   }
-  for (MapBuilder* m : {&m_init, &m_hist_small, &m_hist_big, &m_hist_hash, &m_scan_c, &m_scan_z, &m_node, &m_tile, &m_level})
+  for (MapBuilder* m : {&m_init, &m_hist_small, &m_hist_big, &m_hist_hash, &m_scan_c, &m_scan_z, &m_node, &m_tile,
+                        &m_level[0], &m_level[1], &m_level[2]})
     m->close();
 
   // one upload: tree states, build order, every map
@@ -679,7 +748,8 @@ extern "C" wt_status wt_build_forest(const wt_seq_desc* h_descs, uint32_t count,
   const MapOff u_init = put_map(m_init), u_hs = put_map(m_hist_small), u_hb = put_map(m_hist_big),
                u_hh = put_map(m_hist_hash),
                u_sc = put_map(m_scan_c), u_sz = put_map(m_scan_z), u_node = put_map(m_node),
-               u_tile = put_map(m_tile), u_level = put_map(m_level);
+               u_tile = put_map(m_tile);
+  const MapOff u_level[3] = {put_map(m_level[0]), put_map(m_level[1]), put_map(m_level[2])};
   const size_t u_out = round_up(hbuf.size(), 256);
   const size_t plan_bytes = u_out + (size_t)count * sizeof(ForestOut);
   void* dplan = dev_alloc(plan_bytes, st);
@@ -688,13 +758,13 @@ extern "C" wt_status wt_build_forest(const wt_seq_desc* h_descs, uint32_t count,
   char* dp = (char*)dplan;
   WT_HIP(hipMemcpyAsync(dp, hbuf.data(), hbuf.size(), hipMemcpyHostToDevice, st));
   const TreeB* d_tb = (const TreeB*)(dp + u_tb);
-  auto grid_of = [&](const MapOff& u, uint32_t l = 0) {
+  auto grid_of = [&](const MapOff& u, uint32_t l = 0, uint32_t base = 0) {
     ForestGrid g;
     g.tb = d_tb;
     g.bmap = (const uint32_t*)(dp + u.bmap);
     g.boff = (const uint32_t*)(dp + u.boff);
     g.l = l;
-    g.pad = 0;
+    g.base = base;
     return g;
   };
   ForestOut* d_out = (ForestOut*)(dp + u_out);
@@ -728,14 +798,49 @@ extern "C" wt_status wt_build_forest(const wt_seq_desc* h_descs, uint32_t count,
   launch(kf_scan_partials, active.empty() ? 0 : (Lmax ? active[0] : 0), 1024, 0, d_tb, 1u);
   launch(kf_scan_down, m_scan_z.bmap.size(), kBT, 0, grid_of(u_sz), 1u);
   launch(kf_node_final, m_node.bmap.size(), kBT, 0, grid_of(u_node));
+  if (any_pos) {
+    // non-empty nodes in position order (z and zs are free again)
+    launch(kf_ns_flag, m_node.bmap.size(), kBT, 0, grid_of(u_node));
+    launch(kf_scan_reduce, m_scan_z.bmap.size(), kBT, 0, grid_of(u_sz), 1u);
+    launch(kf_scan_partials, active.empty() ? 0 : (Lmax ? active[0] : 0), 1024, 0, d_tb, 1u);
+    launch(kf_scan_down, m_scan_z.bmap.size(), kBT, 0, grid_of(u_sz), 1u);
+    launch(kf_ns_scatter, m_node.bmap.size(), kBT, 0, grid_of(u_node));
+  }
+  // one level-pass launch per run of trees (in build order) with the same code widths and node lookup
+  auto launch_level = [&](uint32_t wi, uint32_t wo, bool pos, uint64_t nb, const ForestGrid& g) {
+#define WT_LV(E, EO)                                                      \
+  do {                                                                    \
+    if (pos) launch(k_level<E, true, EO, true>, nb, kBT, 0, LevelArgs{}, g);  \
+    else launch(k_level<E, true, EO, false>, nb, kBT, 0, LevelArgs{}, g);     \
+  } while (0)
+    if (wi == 0) WT_LV(uint8_t, uint8_t);
+    else if (wi == 1) {
+      if (wo == 0) WT_LV(uint16_t, uint8_t);
+      else WT_LV(uint16_t, uint16_t);
+    } else {
+      if (wo == 0) WT_LV(uint32_t, uint8_t);
+      else if (wo == 1) WT_LV(uint32_t, uint16_t);
+      else WT_LV(uint32_t, uint32_t);
+    }
+#undef WT_LV
+  };
+  auto level_class = [&](uint32_t s, uint32_t l) {
+    const TreeB& b = tb[s];
+    return (uint32_t)((b.wlog >> (2 * l)) & 15u) | (((b.posmask >> l) & 1u) << 4);  // input, output width, lookup
+  };
   for (uint32_t l = 0; l < Lmax; ++l) {
     const uint32_t A = active[l];
     launch(kf_tile_reduce, m_tile.boff[A], kBT, 0, grid_of(u_tile, l));
     launch(kf_tile_scan, m_tile.boff[A], kBT, 0, grid_of(u_tile, l));
-    const uint64_t nb = m_level.boff[A];
-    if (sym_bytes == 1) launch(k_level<uint8_t, true>, nb, kBT, 0, LevelArgs{}, grid_of(u_level, l));
-    else if (sym_bytes == 2) launch(k_level<uint16_t, true>, nb, kBT, 0, LevelArgs{}, grid_of(u_level, l));
-    else launch(k_level<uint32_t, true>, nb, kBT, 0, LevelArgs{}, grid_of(u_level, l));
+    for (uint32_t s0 = 0; s0 < A;) {
+      const uint32_t c = level_class(s0, l);
+      uint32_t s1 = s0 + 1;
+      while (s1 < A && level_class(s1, l) == c) ++s1;
+      const uint32_t wi = c & 3u, wo = (c >> 2) & 3u;
+      const MapBuilder& m = m_level[wi];
+      launch_level(wi, wo, (c >> 4) != 0, (uint64_t)m.boff[s1] - m.boff[s0], grid_of(u_level[wi], l, m.boff[s0]));
+      s0 = s1;
+    }
   }
   launch(kf_gather, count, 64, 0, d_tb, (const uint32_t*)(dp + u_order), d_out);
   hipError_t he = hipGetLastError();

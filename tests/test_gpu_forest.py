@@ -104,6 +104,67 @@ def test_forest_trees_equal_single_builds(small_forest):
         t1.free()
 
 
+def _same_forests(fa, fb, count):
+    import paper_2505_03372_amd as wt
+    parts = [wt.PART_BITS, wt.PART_L1, wt.PART_L2, wt.PART_SAMPLES1, wt.PART_SAMPLES0, wt.PART_NODE_START,
+             wt.PART_NODE_R0]
+    for j in range(count):
+        ta, tb = fa[j], fb[j]
+        assert ta.info["level_n"] == tb.info["level_n"] and ta.info["level_ones"] == tb.info["level_ones"], j
+        for l in range(ta.info["levels"]):
+            for part in parts:
+                a, b = ta.export(part, l), tb.export(part, l)
+                assert a.shape == b.shape and np.array_equal(a, b), (j, l, part)
+
+
+def test_forest_narrow_codes_equal_wide(small_forest):
+    """The default forest carries codes that narrow level by level (nodes by position once prefix bits are
+    dropped); the same forest with full-width codes is identical part by part."""
+    import paper_2505_03372_amd as wt
+    f, seqs = small_forest
+    G.log("forest: full-width codes against the default")
+    fw = wt.build_forest([G.dev(S) for S in seqs], [s[1] for s in SHAPES], l2_bits=[s[3] for s in SHAPES],
+                         sample_rates=[s[4] for s in SHAPES], wide=True)
+    try:
+        assert fw.info["graph_kernels"] < f.info["graph_kernels"]  # one level launch per level when wide
+        _same_forests(f, fw, len(SHAPES))
+    finally:
+        fw.free()
+
+
+# u32 sequences: codes narrow from 4 to 2 to 1 byte (alphabets up to 2^20, 20 levels)
+SHAPES32 = [
+    (300001, 1 << 20, "zipf12"),
+    (100000, 70000, "uniform"),
+    (65537, 1000003, "sparse"),
+    (200000, 300, "zipf"),
+    (9000, 1 << 17, "uniform"),
+    (50000, 2, "alternate"),
+    (1, 5, "uniform"),
+    (0, 9, "uniform"),
+]
+
+
+def test_forest_u32_narrow_codes():
+    import paper_2505_03372_amd as wt
+    seqs = [make_seq(kind, n, sigma, 4, 0x3A0 + i) for i, (n, sigma, kind) in enumerate(SHAPES32)]
+    sig = [s[1] for s in SHAPES32]
+    G.log("u32 forest of %d shapes, narrow and wide codes" % len(seqs))
+    dev = [G.dev(S) for S in seqs]
+    fn = wt.build_forest(dev, sig)
+    fw = wt.build_forest(dev, sig, wide=True)
+    try:
+        _same_forests(fn, fw, len(seqs))
+        for j, (S, sigma) in enumerate(zip(seqs, sig)):
+            if S.size == 0:
+                continue
+            G.compare_structure(fn[j], oracle.OracleTree(S, sigma))
+            G.compare_queries(fn[j], S, sigma, *G.random_queries(S, sigma, 2048, 0x3B0 + j))
+    finally:
+        fn.free()
+        fw.free()
+
+
 def _mixed_reference(f, seqs, tree, op, sym, arg):
     """Per-tree query calls for every query (grouped by tree and op)."""
     out = np.full(tree.size, np.iinfo(np.uint64).max, dtype=np.uint64)
