@@ -223,7 +223,59 @@ def profile_summary(d: str) -> None:
                                                                                qj["source_sha256_16"])]
     with open(os.path.join(out_dir, "kernel_traffic_text_zipf_pmc.md"), "w") as f:
         f.write("\n".join(md) + "\n")
+    if os.path.isdir(os.path.join(d, "forest")):
+        forest_summary(d, out_dir)
     print("profiles written from", d)
+
+
+def forest_summary(d: str, out_dir: str) -> None:
+    """profiles/forest_build_graph_trace.md from the kernel trace of PROFILE_COMMANDS["forest"]: kernel
+    totals per build, and the level passes of the last build by level and launch (the forest launches a
+    level once per run of trees with the same code widths and node lookup)."""
+    import csv
+    with open(os.path.join(d, "forest", "run_kernel_trace.csv")) as f:
+        rows = sorted(csv.DictReader(f), key=lambda r: int(r["Start_Timestamp"]))
+    starts = [i for i, r in enumerate(rows) if _short_kernel(r["Kernel_Name"]) == "kf_init"]
+    builds = []
+    for b, i0 in enumerate(starts):
+        i1 = starts[b + 1] if b + 1 < len(starts) else len(rows)
+        seg = rows[i0:i1]
+        g = [i for i, r in enumerate(seg) if _short_kernel(r["Kernel_Name"]) == "kf_gather"]
+        builds.append(seg[:g[0] + 1] if g else seg)
+    nb = len(builds)
+    tot = {}
+    for seg in builds:
+        for r in seg:
+            k = _short_kernel(r["Kernel_Name"])
+            k = k if k.startswith("k_level") else k.split("<")[0]
+            tot[k] = tot.get(k, 0.0) + (int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e3
+    last = builds[-1]
+    span = (int(last[-1]["End_Timestamp"]) - int(last[0]["Start_Timestamp"])) / 1e3
+    lines = ["# forest build graph (1024 u16 sequences, Σ n = 1.75·10^9): rocprofv3 kernel trace", "",
+             "Command (repository root on the GPU box, `TMPDIR=/tmp`):", "", "    " + PROFILE_COMMANDS["forest"], "",
+             "The run builds the forest %d times (warm-up included); every kernel node of the captured graph is its "
+             "own dispatch. Last build: %d kernels, %.1f µs from the first kernel's start to the last one's end."
+             % (nb, len(last), span), "", "Kernels of the graph, per build (mean over the run):", "",
+             "| kernel | µs per build | % |", "|---|---|---|"]
+    s_all = sum(tot.values())
+    for k, v in sorted(tot.items(), key=lambda x: -x[1]):
+        lines.append("| %s | %.1f | %.1f |" % (k, v / nb, 100.0 * v / s_all))
+    lines += ["", "Level passes of the last build, µs per launch (E: element type of the level, EO: of the next "
+              "level, kPos: nodes by position):", "", "| level | launch | blocks | µs |", "|---|---|---|---|"]
+    lvl, per = -1, {}
+    for r in last:
+        k = _short_kernel(r["Kernel_Name"])
+        if k == "kf_tile_reduce":
+            lvl += 1
+        if k.startswith("k_level"):
+            us = (int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e3
+            per[lvl] = per.get(lvl, 0.0) + us
+            lines.append("| %d | %s | %d | %.1f |" % (lvl, k, int(r["Grid_Size_X"]) // int(r["Workgroup_Size_X"]), us))
+    lines += ["", "Per level (all launches): " + ", ".join("%d: %.0f" % (l, v) for l, v in sorted(per.items())) +
+              " µs; level passes %.1f µs in total." % sum(per.values()),
+              "", "Source hash of the level kernel (sha256/16): %s." % source_hash(LEVEL_SRCS)]
+    with open(os.path.join(out_dir, "forest_build_graph_trace.md"), "w") as f:
+        f.write("\n".join(lines) + "\n")
 
 
 # the rocprofv3 runs profile_summary reads (from the repository root; <out> is the directory it is given)
@@ -236,6 +288,8 @@ PROFILE_COMMANDS = {
              "--no-cpu-baseline --no-extra --calibrate-copy",
     "l2": "rocprofv3 --pmc TCC_HIT_sum TCC_MISS_sum -f csv -d <out>/l2 -o run -- python3 bench.py --steps 1 "
           "--warmup 0 --no-cpu-baseline --no-extra",
+    "forest": "rocprofv3 --kernel-trace --stats -f csv -d <out>/forest -o run -- python3 bench.py --workload forest "
+              "--steps 2 --warmup 1",
 }
 
 
