@@ -1145,13 +1145,13 @@ __global__ __launch_bounds__(kBT, (level_waves<E, kForest, kPos>())) void k_leve
   __shared__ uint2 s_enc[32];     // level 0 of a reduced alphabet: (high code bits, shift) by h
   // nodes by position: bit q of s_nb is set where a node starts at tile position q > 0, s_nbp counts
   // the starts before each word, so the node of position q is the tile's node number (starts in
-  // (0, q]); s_lpf holds the code prefixes of the first kSegMax nodes, s_i0 the first node's entry in
-  // the level's position list and s_nn the tile's node count
+  // (0, q]); s_lpf holds the code prefixes of the first kSegMax nodes, s_i0 and s_i1 the entries of
+  // the tile's first and last node in the level's position list
   __shared__ uint64_t s_nb[kPos ? W + 1 : 1];
   __shared__ uint32_t s_nbp[kPos ? W + 1 : 1];
   __shared__ uint32_t s_lpf[kSegMax];
   __shared__ uint64_t s_i0;
-  __shared__ uint32_t s_nn;
+  __shared__ uint64_t s_i1;
 
   const uint32_t tid = threadIdx.x, lane = tid & 63u;
   const uint32_t l = a.l, L = a.L;
@@ -1226,25 +1226,29 @@ __global__ __launch_bounds__(kBT, (level_waves<E, kForest, kPos>())) void k_leve
   if (tid < 4) s_nc[tid] = 0;
   if constexpr (kPos) {
     if (tid <= (uint32_t)W) s_nb[tid] = 0;
-    if (tid < 64) {
-      // the tile's nodes: entries i0 (the one holding t0) .. i1 (the last starting inside the tile);
-      // at most cnt nodes start inside the tile
+    if (tid < 128) {
+      // the tile's nodes: entries i0 (the one holding t0, found by wave 0) .. i1 (the last starting
+      // inside the tile, found by wave 1 at the same time)
       const uint64_t lo = a.ns_idx[(1ull << l) - 1], hi = a.ns_idx[(2ull << l) - 1];
-      const uint64_t i0 = a.tfirst ? lo + a.tfirst[t] : wave_find_start(a.ns, lo, hi, t0, lane);
-      const uint64_t i1 = wave_find_start(a.ns, i0, min(hi, i0 + cnt), t0 + cnt - 1, lane);
-      if (lane == 0) {
-        const uint32_t p0 = a.ns[i0].pfx;
-        s_i0 = i0;
-        s_nn = (uint32_t)(i1 - i0 + 1);
-        s_lpf[0] = p0;
-        s_node[0] = p0;
-        s_node[1] = i1 == i0 ? (uint64_t)p0 : ~0ull;
+      if (tid < 64) {
+        const uint64_t i0 = a.tfirst ? lo + a.tfirst[t] : wave_find_start(a.ns, lo, hi, t0, lane);
+        if (lane == 0) {
+          const uint32_t p0 = a.ns[i0].pfx;
+          s_i0 = i0;
+          s_lpf[0] = p0;
+          s_node[0] = p0;
+        }
+      } else {
+        const uint64_t i1 = wave_find_start(a.ns, lo, hi, t0 + cnt - 1, lane);
+        if (lane == 0) s_i1 = i1;
       }
     }
   }
   __syncthreads();
+  bool single = false;  // a tile inside one node (the rule at shallow levels) takes the fast path
   if constexpr (kPos) {
-    const uint32_t nn = s_nn;
+    const uint32_t nn = (uint32_t)(s_i1 - s_i0 + 1);
+    single = nn == 1;
     if (nn > 1) {
       // node starts inside the tile into the bitmap, and the first prefixes into the list
       const uint64_t i0 = s_i0;
@@ -1256,8 +1260,8 @@ __global__ __launch_bounds__(kBT, (level_waves<E, kForest, kPos>())) void k_leve
       __syncthreads();
     }
   }
-  // a tile inside one node (the rule at shallow levels) takes the fast path: two runs, no segments
-  const bool single = s_node[0] == s_node[1];
+  // a tile inside one node: two runs, no segments
+  if constexpr (!kPos) single = s_node[0] == s_node[1];
   if (single && !last && tid == 0) {
     const NodeB nb = ld_node(a.ntb + s_node[0]);
     s_dst[0] = nb.off0 + (t0 - G1);
@@ -1332,11 +1336,14 @@ __global__ __launch_bounds__(kBT, (level_waves<E, kForest, kPos>())) void k_leve
   // 4a. staging
   const uint32_t nbsh = L - 2 - l;
   const uint64_t pmask = (1ull << l) - 1ull;
-  // code prefix of the node holding tile position q (nodes by position)
-  auto pfx_at = [&](uint32_t q) -> uint64_t {
+  // Nodes by position: the tile's node number of position q (node starts in (0, q]) identifies the
+  // node inside the tile; its code prefix is looked up when a lane enters the node.
+  auto knum = [&](uint32_t q) -> uint64_t {
     const uint32_t w = q >> 6;
-    const uint32_t k = s_nbp[w] + popc64(s_nb[w] & ((2ull << (q & 63u)) - 1ull));  // starts in (0, q]
-    return k < (uint32_t)kSegMax ? (uint64_t)s_lpf[k] : (uint64_t)a.ns[s_i0 + k].pfx;
+    return s_nbp[w] + popc64(s_nb[w] & ((2ull << (q & 63u)) - 1ull));
+  };
+  auto kpfx = [&](uint64_t k) -> uint64_t {
+    return k < (uint64_t)kSegMax ? (uint64_t)s_lpf[k] : (uint64_t)a.ns[s_i0 + k].pfx;
   };
   if (single) {
     // zeros fill slots [0, Z), ones [Z, cnt); each lane walks its vectors with running slots
@@ -1449,12 +1456,24 @@ __global__ __launch_bounds__(kBT, (level_waves<E, kForest, kPos>())) void k_leve
         uint32_t r1 = r1loc(s_words, s_wpre, q0);
         const uint32_t nv = min((uint32_t)EV, cnt - q0);
         const uint64_t lo = ((uint64_t)vx[k].y << 32) | vx[k].x, hi = ((uint64_t)vx[k].w << 32) | vx[k].z;
-        const uint32_t cf = vec_elem<E>(vx[k], 0), cl = elem128<E>(lo, hi, nv - 1);
-        const uint64_t Nf = kPos ? pfx_at(q0) : l ? ((uint64_t)cf >> (L - l)) & pmask : 0ull;
-        const uint64_t Nl = kPos ? pfx_at(q0 + nv - 1) : l ? ((uint64_t)cl >> (L - l)) & pmask : 0ull;
+        // node of the first and the last element (nodes by position: tile node numbers, and the
+        // node starts at the vector's other elements, bits 1 .. nv-1 of sbits; EV divides 64)
+        uint64_t Nf, Nl;
+        uint32_t sbits = 0;
+        if constexpr (kPos) {
+          const uint32_t w = q0 >> 6;
+          const uint64_t wb = s_nb[w];
+          Nf = s_nbp[w] + popc64(wb & ((2ull << (q0 & 63u)) - 1ull));
+          sbits = (uint32_t)(wb >> (q0 & 63u)) & ((2u << (nv - 1)) - 2u);
+          Nl = Nf + (uint32_t)__popc(sbits);
+        } else {
+          const uint32_t cf = vec_elem<E>(vx[k], 0), cl = elem128<E>(lo, hi, nv - 1);
+          Nf = l ? ((uint64_t)cf >> (L - l)) & pmask : 0ull;
+          Nl = l ? ((uint64_t)cl >> (L - l)) & pmask : 0ull;
+        }
         if (Nf == Nl) {
           // the whole vector lies in one node
-          if (Nf != curN) enter_node(ld_node(a.ntb + Nf), q0, t0, cnt, G0, G1, s_words, s_wpre, s_seg, &s_nseg, sa, zs, R1a), curN = Nf;
+          if (Nf != curN) enter_node(ld_node(a.ntb + (kPos ? kpfx(Nf) : Nf)), q0, t0, cnt, G0, G1, s_words, s_wpre, s_seg, &s_nseg, sa, zs, R1a), curN = Nf;
           // slot = R1a + rank0 or sa + zs - R1a + rank1 (tile-local ranks), as running slots
           uint32_t p1 = sa + zs - R1a + r1, p0 = R1a + q0 - r1;
           const uint32_t m = vmask[k];
@@ -1477,12 +1496,14 @@ __global__ __launch_bounds__(kBT, (level_waves<E, kForest, kPos>())) void k_leve
             }
           }
         } else {
+          uint64_t Nk = Nf;  // nodes by position: the running node number
           for (uint32_t e = 0; e < nv; ++e) {
             const uint32_t code = elem128<E>(lo, hi, e);
             const uint32_t b = (code >> bsh) & 1u;
             const uint32_t q = q0 + e;
-            const uint64_t N = kPos ? pfx_at(q) : l ? ((uint64_t)code >> (L - l)) & pmask : 0ull;
-            if (N != curN) enter_node(ld_node(a.ntb + N), q, t0, cnt, G0, G1, s_words, s_wpre, s_seg, &s_nseg, sa, zs, R1a), curN = N;
+            if constexpr (kPos) Nk += (sbits >> e) & 1u;
+            const uint64_t N = kPos ? Nk : l ? ((uint64_t)code >> (L - l)) & pmask : 0ull;
+            if (N != curN) enter_node(ld_node(a.ntb + (kPos ? kpfx(N) : N)), q, t0, cnt, G0, G1, s_words, s_wpre, s_seg, &s_nseg, sa, zs, R1a), curN = N;
             const uint32_t slot = b ? sa + zs + (r1 - R1a) : sa + ((q - r1) - (sa - R1a));
             bad = bad || slot >= (uint32_t)T;
             s_stage[min(slot, (uint32_t)T - 1u)] = (EO)code;
@@ -1581,9 +1602,9 @@ __global__ __launch_bounds__(kBT, (level_waves<E, kForest, kPos>())) void k_leve
       uint32_t nbit = 0;
       if (j < cnt) {
         const uint32_t code = (uint32_t)s_stage[j];
-        const uint64_t N = kPos ? pfx_at(j) : l ? ((uint64_t)code >> (L - l)) & pmask : 0ull;
+        const uint64_t N = kPos ? knum(j) : l ? ((uint64_t)code >> (L - l)) & pmask : 0ull;
         if (N != curN) {
-          const NodeB nb = ld_node(a.ntb + N);
+          const NodeB nb = ld_node(a.ntb + (kPos ? kpfx(N) : N));
           sa = (uint32_t)(nb.start > t0 ? min(nb.start - t0, (uint64_t)cnt) : 0ull);
           const uint32_t sz = (uint32_t)(nb.end > t0 ? min(nb.end - t0, (uint64_t)cnt) : 0ull);
           const uint32_t R1a = r1loc(s_words, s_wpre, sa);
