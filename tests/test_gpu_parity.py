@@ -282,6 +282,43 @@ def test_binned_batches_equal_unbinned(order):
     t.free()
 
 
+@pytest.mark.parametrize("order", ["random", "one_position", "two_values"])
+def test_two_pass_binning_equals_one_pass(order):
+    """Batches of 2^24 queries and more are binned in two passes (coarse bucket groups, then buckets);
+    their answers equal those of the same queries asked in batches binned in one pass, and the oracle's
+    on a sample. one_position / two_values put the whole batch into one or two buckets."""
+    n, sigma = 3_000_017, 300
+    S = make_seq("zipf", n, sigma, 2, 0x5152)
+    t = G.gpu_build(S, sigma)
+    q = (1 << 24) + 77
+    pos, rc, ri, sc, sk = G.random_queries(S, sigma, q, 0x78)
+    if order == "one_position":
+        pos[:] = n // 3; ri[:] = n // 3; sc[:] = sc[0]; sk[:] = 2
+    elif order == "two_values":
+        pos[::2] = 5; ri[::2] = n; sk[1::2] = 1
+    pos[::97] = n + 5; ri[::89] = n + 1; rc[::83] = sigma + 3; sk[::79] = 0; sc[::73] = sigma
+    G.log("two-pass binning, order %s, q=%d" % (order, q))
+
+    def pieces(fn, *arrs):
+        step = 1 << 22
+        return np.concatenate([G.host(fn(*[G.dev(np.ascontiguousarray(a[i:i + step])) for a in arrs]))
+                               for i in range(0, q, step)])
+    got = G.host(t.access(G.dev(pos)))
+    G._assert_eq("access two-pass", got, pieces(t.access, pos), pos)
+    idx = np.arange(0, q, 4099)
+    G._assert_eq("access vs oracle", got[idx], oracle.access(S, pos[idx]), pos[idx])
+    got = G.host(t.rank(G.dev(rc), G.dev(ri)))
+    G._assert_eq("rank two-pass", got, pieces(t.rank, rc, ri), ri)
+    G._assert_eq("rank vs oracle", got[idx], oracle.rank(S, sigma, rc[idx], ri[idx]), ri[idx])
+    got = G.host(t.select(G.dev(sc), G.dev(sk)))
+    G._assert_eq("select two-pass", got, pieces(t.select, sc, sk), sk)
+    G._assert_eq("select vs oracle", got[idx], oracle.select(S, sigma, sc[idx], sk[idx]), sk[idx])
+    t.learn_select()
+    got = G.host(t.select_learned(G.dev(sc), G.dev(sk)))
+    G._assert_eq("learned select two-pass", got, pieces(t.select, sc, sk), sk)
+    t.free()
+
+
 # (width, sigma, n, kind): trees whose level sequence narrows (u32 -> u16 -> u8, u16 -> u8) and whose
 # later levels find nodes by position, including tiles with more nodes than the per-tile list holds
 NARROW_CASES = [
