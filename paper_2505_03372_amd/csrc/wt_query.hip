@@ -284,8 +284,8 @@ __global__ __launch_bounds__(kBinT) void k_bin_scatter(QArgs a, const uint32_t* 
 // consecutive groups of buckets), a round of kRound queries at a time, staged in LDS in coarse order;
 // the second gives each coarse bucket one block, which places its queries into the buckets the same
 // way. Both read and write every record once more than the scatter, all of it in runs. Measured on
-// 2^26 queries over 2^30 symbols: 1.7 -> 1.3 ms for 2^15 buckets; access batches keep the one-pass
-// scatter into their 2^14 buckets (1.2 ms, against 1.4 ms in two passes).
+// 2^26 queries over 2^30 symbols: 1.7 -> 1.05 ms for 2^15 buckets (rank, select), 1.18 -> 0.92 ms
+// for 2^14 (access).
 constexpr uint32_t kCoarseLog = 8;
 constexpr uint32_t kCoarse = 1u << kCoarseLog;
 constexpr uint32_t kRound = kBinT * kBinU;          // queries per round of a block
@@ -382,30 +382,65 @@ __global__ __launch_bounds__(kBinT) void k_bin_coarse(QArgs a, const uint32_t* _
   }
 }
 
-// Second pass: block g places coarse bucket g of tmp (slots start[g fb] .. start[(g+1) fb], or q for
-// the last) into its buckets in sq.
+// Second pass: coarse bucket g is placed by kFineParts blocks; part p takes the records that the
+// first pass's blocks [b0, b1) wrote (a contiguous slice of the bucket), whose first slot in every
+// bucket follows from the same per-(block, bucket) offsets. Rounds of kRound2 records keep the LDS at
+// two blocks per CU.
+constexpr uint32_t kFineParts = 4;
+constexpr uint32_t kRound2 = kBinT * 4;
 template <int KIND>
-__global__ __launch_bounds__(kBinT) void k_bin_fine(QArgs a, uint64_t q, uint32_t shift, uint32_t nb,
+__global__ __launch_bounds__(kBinT) void k_bin_fine(QArgs a, uint64_t q, uint32_t shift, uint32_t nb, uint32_t nblk,
+                                                  const uint32_t* __restrict__ bhist,
                                                   const uint32_t* __restrict__ start, const SQ* __restrict__ tmp,
                                                   SQ* __restrict__ sq) {
-  __shared__ SQ s_rec[kRound];
-  __shared__ uint8_t s_grp[kRound];
+  constexpr uint32_t U = kRound2 / kBinT;
+  __shared__ SQ s_rec[kRound2];
+  __shared__ uint8_t s_grp[kRound2];
   __shared__ uint32_t s_cur[kCoarse], s_cnt[kCoarse], s_off[kCoarse], s_base[kCoarse];
-  __shared__ uint32_t s_nr;
+  __shared__ uint32_t s_nr, s_lo, s_len;
   const uint32_t tid = threadIdx.x, lane = tid & 63u;
-  const uint32_t fb = nb >> kCoarseLog, g = blockIdx.x;
-  const uint64_t lo = start[(uint64_t)g * fb], hi = g + 1 < kCoarse ? start[(uint64_t)(g + 1) * fb] : q;
-  if (tid < fb) s_cur[tid] = start[(uint64_t)g * fb + tid];
-  for (uint64_t r0 = lo; r0 < hi; r0 += kRound) {
-    SQ rec[kBinU];
-    uint32_t f[kBinU], r[kBinU];
+  const uint32_t fb = nb >> kCoarseLog, g = blockIdx.x / kFineParts, p = blockIdx.x % kFineParts;
+  const uint32_t b0 = (uint32_t)((uint64_t)p * nblk / kFineParts), b1 = (uint32_t)((uint64_t)(p + 1) * nblk / kFineParts);
+  if (b0 == b1) return;
+  // per bucket of the group: the part's first slot, and the part's records before it (s_cnt)
+  if (tid < fb) {
+    const uint32_t bin = g * fb + tid;
+    const uint32_t o0 = bhist[(uint64_t)b0 * nb + bin];
+    const uint32_t o1 = b1 < nblk ? bhist[(uint64_t)b1 * nb + bin]
+                                  : (uint32_t)((bin + 1 < nb ? (uint64_t)start[bin + 1] : q) - start[bin]);
+    s_cur[tid] = start[bin] + o0;
+    s_cnt[tid] = o0;
+    s_off[tid] = o1 - o0;
+  }
+  __syncthreads();
+  if (tid < 64) {
+    uint32_t before = 0, len = 0;
+    for (uint32_t f = lane; f < fb; f += 64) {
+      before += s_cnt[f];
+      len += s_off[f];
+    }
 #pragma unroll
-    for (uint32_t u = 0; u < kBinU; ++u) {
+    for (uint32_t d = 32; d > 0; d >>= 1) {
+      before += __shfl_xor(before, d, 64);
+      len += __shfl_xor(len, d, 64);
+    }
+    if (lane == 0) {
+      s_lo = start[g * fb] + before;
+      s_len = len;
+    }
+  }
+  __syncthreads();
+  const uint64_t lo = s_lo, hi = lo + s_len;
+  for (uint64_t r0 = lo; r0 < hi; r0 += kRound2) {
+    SQ rec[U];
+    uint32_t f[U], r[U];
+#pragma unroll
+    for (uint32_t u = 0; u < U; ++u) {
       const uint64_t j = r0 + tid + (uint64_t)u * kBinT;
       if (j < hi) rec[u] = tmp[j];
     }
 #pragma unroll
-    for (uint32_t u = 0; u < kBinU; ++u) {
+    for (uint32_t u = 0; u < U; ++u) {
       const uint64_t j = r0 + tid + (uint64_t)u * kBinT;
       f[u] = j < hi ? (uint32_t)min<uint64_t>(sort_key(a, KIND, rec[u].sym, rec[u].arg) >> shift, nb - 1) & (fb - 1)
                     : kBinNone;
@@ -413,12 +448,12 @@ __global__ __launch_bounds__(kBinT) void k_bin_fine(QArgs a, uint64_t q, uint32_
     if (tid < kCoarse) s_cnt[tid] = 0;
     __syncthreads();
 #pragma unroll
-    for (uint32_t u = 0; u < kBinU; ++u) r[u] = f[u] != kBinNone ? atomicAdd(&s_cnt[f[u]], 1u) : 0u;
+    for (uint32_t u = 0; u < U; ++u) r[u] = f[u] != kBinNone ? atomicAdd(&s_cnt[f[u]], 1u) : 0u;
     __syncthreads();
     if (tid < 64) round_offsets(s_cnt, fb, s_off, s_base, s_cur, &s_nr, lane);
     __syncthreads();
 #pragma unroll
-    for (uint32_t u = 0; u < kBinU; ++u)
+    for (uint32_t u = 0; u < U; ++u)
       if (f[u] != kBinNone) {
         const uint32_t sl = s_off[f[u]] + r[u];
         s_rec[sl] = rec[u];
@@ -509,7 +544,7 @@ wt_status sort_batch(const wt_tree* t, const QArgs& a, int kind, const uint32_t*
   const size_t o_t = round_up((size_t)nblk * kBins * 4, 256), o_p = o_t + round_up(4 * kBins, 256);
   char* blk = pre;
   const uint32_t nbl = kind == 0 ? kAccessBinsLog : kBinsLog, nb = 1u << nbl;
-  const bool two = !pre && q >= kTwoPassMinQ && nb == kBins;  // two passes need a second record array
+  const bool two = !pre && q >= kTwoPassMinQ;  // two passes need a second record array
   SQ* tmp = nullptr;
   if (!blk) {
     const size_t bytes = sort_batch_bytes(q), all = bytes + (two ? round_up(sizeof(SQ) * q, 256) : 0);
@@ -542,8 +577,8 @@ wt_status sort_batch(const wt_tree* t, const QArgs& a, int kind, const uint32_t*
   do {                                                                                                     \
     hipLaunchKernelGGL(k_bin_coarse<K>, dim3(nblk), dim3(kBinT), 0, st, a, sym, arg, q, shift, nb,          \
                        (const uint32_t*)bhist, (const uint32_t*)tot, tmp);                                  \
-    hipLaunchKernelGGL(k_bin_fine<K>, dim3(kCoarse), dim3(kBinT), 0, st, a, q, shift, nb, (const uint32_t*)tot, \
-                       (const SQ*)tmp, sb.sq);                                                             \
+    hipLaunchKernelGGL(k_bin_fine<K>, dim3(kCoarse * kFineParts), dim3(kBinT), 0, st, a, q, shift, nb, nblk,   \
+                       (const uint32_t*)bhist, (const uint32_t*)tot, (const SQ*)tmp, sb.sq);                \
   } while (0)
     if (kind == 0) WT_TWO(0);
     else if (kind == 1) WT_TWO(1);
