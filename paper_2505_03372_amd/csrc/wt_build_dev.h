@@ -430,6 +430,18 @@ __device__ __forceinline__ void hist_dense_body(PS sym, uint64_t n, uint32_t sig
         const uint64_t t0 = t << TL::TSHIFT;
         const uint32_t cnt = (uint32_t)min<uint64_t>(TL::T, n - t0);
         uint32_t ones = 0;
+        // a whole vector of a whole tile: no bounds, and the level-0 ones by a dot product (a symbol
+        // >= sigma fails the build, so counting its bit changes nothing that is kept)
+        auto count_vec_full = [&](const uint4& x) {
+#pragma unroll
+          for (int e = 0; e < EV; ++e) {
+            const uint32_t s = vec_elem<E>(x, e);
+            const uint32_t r = s - w0;
+            if (r < wn) atomicAdd(&my_h[r], 1u);
+            if (first) bad |= s >= sigma ? 1u : 0u;
+          }
+          if (first) ones += vec_count_bit<E>(x, lsh);
+        };
         auto count_vec = [&](const uint4& x, uint32_t q0) {
 #pragma unroll
           for (int e = 0; e < EV; ++e) {
@@ -467,7 +479,7 @@ __device__ __forceinline__ void hist_dense_body(PS sym, uint64_t n, uint32_t sig
           for (int k = 0; k < NCH; ++k) {
             uint4 x;
             __builtin_memcpy(&x, &vx[k], 16);
-            count_vec(x, (uint32_t)(k * kBT + gt) * EV);
+            count_vec_full(x);
           }
         } else if (sizeof(E) < 4 && !aligned && cnt == (uint32_t)TL::T && ((uintptr_t)(sym + t0) & 15u) != 0) {
           // whole tile of a u8/u16 sequence that starts off a 16-byte boundary (forest trees at
@@ -493,7 +505,7 @@ __device__ __forceinline__ void hist_dense_body(PS sym, uint64_t n, uint32_t sig
               for (int e = 0; e < EV; ++e) atomicAdd(&my_h[vec_elem<E>(x, e)], 1u);
               ones += vec_count_bit<E>(x, lsh);
             } else {
-              count_vec(x, (uint32_t)(k * kBT + gt) * EV);
+              count_vec_full(x);
             }
           }
         } else {
