@@ -144,11 +144,14 @@ constexpr int kScanChunk = kBT * kScanPer;  // elements per block
 __device__ __forceinline__ void scan_reduce_body(const uint64_t* __restrict__ in, uint64_t n,
                                                  uint64_t* __restrict__ part, uint64_t bid) {
   __shared__ uint64_t s_w[kBT / 64];
-  const uint64_t b0 = bid * kScanChunk + (uint64_t)threadIdx.x * kScanPer;
+  // only the chunk's sum is needed, so the loads go in the coalesced order
+  const uint64_t b0 = bid * kScanChunk + threadIdx.x;
   uint64_t s = 0;
 #pragma unroll
-  for (int i = 0; i < kScanPer; ++i)
-    if (b0 + i < n) s += in[b0 + i];
+  for (int i = 0; i < kScanPer; ++i) {
+    const uint64_t j = b0 + (uint64_t)i * kBT;
+    if (j < n) s += in[j];
+  }
   uint64_t tot;
   block_excl_scan_u64(s, s_w, tot);
   if (threadIdx.x == 0) part[bid] = tot;
@@ -168,24 +171,41 @@ __device__ __forceinline__ void scan_partials_body(uint64_t* __restrict__ part, 
   }
 }
 
+// The chunk goes through LDS (each thread's run of kScanPer padded by one slot against bank
+// conflicts), so the global loads and stores are coalesced while every thread scans its own run.
 __device__ __forceinline__ void scan_down_body(const uint64_t* __restrict__ in, uint64_t n,
                                                const uint64_t* __restrict__ part, uint64_t* __restrict__ out,
                                                uint64_t bid) {
+  constexpr uint32_t R = kScanPer + 1;
   __shared__ uint64_t s_w[kBT / 64];
-  const uint64_t b0 = bid * kScanChunk + (uint64_t)threadIdx.x * kScanPer;
+  __shared__ uint64_t s_v[kBT * R];
+  const uint32_t tid = threadIdx.x;
+  const uint64_t c0 = bid * kScanChunk;
+#pragma unroll
+  for (int i = 0; i < kScanPer; ++i) {
+    const uint32_t j = (uint32_t)i * kBT + tid;
+    s_v[(j / kScanPer) * R + j % kScanPer] = c0 + j < n ? in[c0 + j] : 0ull;
+  }
+  __syncthreads();
   uint64_t v[kScanPer];
   uint64_t s = 0;
 #pragma unroll
   for (int i = 0; i < kScanPer; ++i) {
-    v[i] = (b0 + i < n) ? in[b0 + i] : 0;
+    v[i] = s_v[tid * R + i];
     s += v[i];
   }
   uint64_t tot;
   uint64_t run = block_excl_scan_u64(s, s_w, tot) + part[bid];
 #pragma unroll
   for (int i = 0; i < kScanPer; ++i) {
-    if (b0 + i < n) out[b0 + i] = run;
+    s_v[tid * R + i] = run;
     run += v[i];
+  }
+  __syncthreads();
+#pragma unroll
+  for (int i = 0; i < kScanPer; ++i) {
+    const uint32_t j = (uint32_t)i * kBT + tid;
+    if (c0 + j < n) out[c0 + j] = s_v[(j / kScanPer) * R + j % kScanPer];
   }
 }
 
