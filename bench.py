@@ -32,7 +32,9 @@ of the same sequence answering the same queries (keys `matrix`, `huffman`), quer
 (wt_query_host, 10^5..10^7 of each kind, page-locked and pageable arrays; key `host_queries`), the
 chunked build from host memory against copy-then-build (wt_build_host, 2^27-symbol chunks; key
 `host_build`), the
-large-alphabet configuration (2^28 u32 symbols, sigma 2^20; key `large_alpha`) and the rank/select
+large-alphabet configuration (2^28 u32 symbols, sigma 2^20; key `large_alpha`), the batched forest
+build and its mixed queries (three builds of the forest workload below, without the one-tree-at-a-time
+comparison; key `forest`) and the rank/select
 benchmark of plain bit arrays (2^32 bits, fill 10/50/90 %, uniform and adversarial placement, |L2| 512,
 s 16384, 10^8 queries of each of rank0/rank1/select0/select1; key `bitvec`).
 """
@@ -352,6 +354,12 @@ def forest_level_bytes(f, w: int) -> float:
 
 
 def main_forest(args, torch, wt, workloads, dev):
+    print(json.dumps(forest_leg(args, torch, wt, workloads, dev, args.steps, args.warmup, plain=True)), flush=True)
+
+
+def forest_leg(args, torch, wt, workloads, dev, steps, warmup, plain):
+    """The batched forest workload: `steps` timed forest builds plus mixed queries (after `warmup`), and
+    with `plain` the same trees built and queried one at a time for comparison. Returns the JSON line."""
     cfg = workloads.FOREST
     print("# generating the batched workload (%d u16 sequences, %d mixed queries)" % (cfg["trees"], cfg["queries"]),
           file=sys.stderr, flush=True)
@@ -369,7 +377,7 @@ def main_forest(args, torch, wt, workloads, dev):
     order = np.lexsort((fw.op, fw.tree))
     keys = fw.tree[order].astype(np.int64) * 4 + fw.op[order]
     bounds = np.searchsorted(keys, np.arange(fw.trees * 4 + 1))
-    for j in range(fw.trees):
+    for j in range(fw.trees if plain else 0):
         g = []
         for o in range(3):
             idx = order[bounds[4 * j + o]:bounds[4 * j + o + 1]]
@@ -416,16 +424,14 @@ def main_forest(args, torch, wt, workloads, dev):
             t.free()
         return t1 - t0, t2 - t1, t2 - t0
 
-    for _ in range(args.warmup):
+    for _ in range(warmup):
         forest_step(None)
     recs = []
     t0 = time.perf_counter()
-    for _ in range(args.steps):
+    for _ in range(steps):
         forest_step(recs)
     t1 = time.perf_counter()
-    ms_per_step = (t1 - t0) * 1e3 / args.steps
-    plain = [plain_step() for _ in range(max(1, min(args.steps, 3)))]
-    pb, pq, pt = (float(np.median([p[i] for p in plain])) for i in range(3))
+    ms_per_step = (t1 - t0) * 1e3 / steps
     fb = float(np.median([r["build_s"] for r in recs]))
     fq = float(np.median([r["query_ms"] for r in recs])) * 1e-3
     gms = float(np.median([r["info"]["graph_ms"] for r in recs]))
@@ -434,7 +440,7 @@ def main_forest(args, torch, wt, workloads, dev):
     line = {
         "metric": "batched build symbols/s + mixed queries/s (forest vs one tree at a time)",
         "value": (n_total + q) / (ms_per_step * 1e-3), "unit": "(symbols+queries)/s", "n_gpus": 1,
-        "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_per_step, "higher_is_better": True,
+        "steps": steps, "warmup": warmup, "ms_per_step": ms_per_step, "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "u16", "data": "synthetic",
         "config": {"workload": "forest", "trees": len(views), "symbols": n_total, "sym_bytes": 2,
                    "mixed_queries": q, "tuned_buckets": trep["buckets"]},
@@ -443,18 +449,21 @@ def main_forest(args, torch, wt, workloads, dev):
                   "forest_capture_ms": float(np.median([r["info"]["capture_ms"] for r in recs])),
                   "forest_library_ms": float(np.median([r["info"]["total_ms"] for r in recs])),
                   "forest_graph_kernels": recs[0]["info"]["graph_kernels"],
-                  "mixed_queries_per_s": q / fq, "mixed_ms": fq * 1e3,
-                  "plain_build_symbols_per_s": n_total / pb, "plain_build_ms": pb * 1e3,
-                  "plain_queries_per_s": q / pq, "plain_queries_ms": pq * 1e3,
-                  "forest_vs_plain_build_speedup": pb / fb, "forest_vs_plain_query_speedup": pq / fq,
-                  "forest_vs_plain_total_speedup": pt / (fb + fq)},
+                  "mixed_queries_per_s": q / fq, "mixed_ms": fq * 1e3},
         "roofline": {"kernel": "forest build graph (every level pass of every tree)", "bound": "hbm",
                      "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": ach / HBM_PEAK_GBS,
                      "traffic": None, "bytes_per_launch": lb, "avg_launch_ms": gms, "launches": len(recs),
                      "note": "level-pass algorithmic bytes of all trees / graph duration (includes histograms, "
                              "scans and node tables)"},
     }
-    print(json.dumps(line), flush=True)
+    if plain:
+        runs = [plain_step() for _ in range(max(1, min(steps, 3)))]
+        pb, pq, pt = (float(np.median([p[i] for p in runs])) for i in range(3))
+        line["rates"].update({"plain_build_symbols_per_s": n_total / pb, "plain_build_ms": pb * 1e3,
+                              "plain_queries_per_s": q / pq, "plain_queries_ms": pq * 1e3,
+                              "forest_vs_plain_build_speedup": pb / fb, "forest_vs_plain_query_speedup": pq / fq,
+                              "forest_vs_plain_total_speedup": pt / (fb + fq)})
+    return line
 
 
 def main_serve(args, torch, wt, workloads, dev):
@@ -771,7 +780,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="text_zipf")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-extra", action="store_true", help="skip the large-alphabet and bit-array legs of the default run")
+    ap.add_argument("--no-extra", action="store_true",
+                    help="skip the extra legs of the default run (matrix, Huffman, host memory, large alphabet, "
+                         "forest, bit arrays)")
     ap.add_argument("--no-learned", action="store_true", help="skip the learned select index (training + queries)")
     ap.add_argument("--l2-bits", type=int, default=0, help="bits per L2 block (256..2048; 0: library default)")
     ap.add_argument("--sample-rate", type=int, default=0, help="select sample rate s (0: library default)")
@@ -865,6 +876,12 @@ def main():
             "ms_per_step": la["ms_per_step"], "value": la["items"] / (la["ms_per_step"] * 1e-3),
             "unit": "(symbols+queries)/s", "rates": la["rates"], "roofline": la["roofline"],
             "roofline_build": la["roofline_build"], "roofline_build_total": la["roofline_build_total"]}
+    if args.workload == "text_zipf" and not args.no_extra:
+        # the batched forest build (1024 u16 sequences) and its mixed queries, outside the timed steps
+        print("# forest leg", file=sys.stderr, flush=True)
+        fl = forest_leg(args, torch, wt, workloads, dev, 3, 1, plain=False)
+        line["forest"] = {k: fl[k] for k in ("config", "ms_per_step", "value", "unit", "rates", "roofline")}
+        torch.cuda.empty_cache()
     if args.workload == "text_zipf" and not args.no_extra:
         # the rank/select benchmark of plain bit arrays, outside the timed steps
         print("# bit-array leg", file=sys.stderr, flush=True)
